@@ -1,0 +1,377 @@
+/*
+ * ct_oracle.c -- plain, slow CPU oracle for the linear-layer hot path of
+ * CompactTag (arXiv 2311.04406): two parties of SPDZ2k-style MPC over the
+ * value ring Z_{2^k}, k = 64, with shares and tags in Z_{2^{k+s}} = Z_{2^128}
+ * (s = 64) and key shares in Z_{2^s}.
+ *
+ * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the CPU
+ * baseline of the benchmark may load this file.  It shares no code with the
+ * GPU library and must never be used as a fallback for it.
+ *
+ * Everything is naive loops over `unsigned __int128`, whose arithmetic wraps
+ * modulo 2^128 exactly as the ring Z_{2^{k+s}} does.  Each step follows the
+ * paper in order:
+ *   - authenticated sharing, Sec. 2.4 and Eq. (1);
+ *   - the preprocessing functionalities F_Rand and F_MAC, Appendix A;
+ *   - Pi_BatchRec (Fig. 1): open and tag check;
+ *   - Pi_MatMul (Fig. 2, Eqs. (2)-(3)): the SPDZ2k baseline;
+ *   - Pi_Compress (Fig. "proccomp"), Pi_OptMAC (Fig. "expand"), the compact
+ *     tag of Eq. (7) and Pi_CompactMatMul (Fig. 6) at f = 0.
+ * Readings where the paper is ambiguous (integer key sum, the party that adds
+ * public value terms, D opened mod 2^{k+s}, E*U inside the compact tag, check
+ * modulus 2^{k+s}) are the ones listed in the design notes and in the file
+ * comments below.
+ */
+#include "ct_oracle.h"
+
+#include <stdlib.h>
+#include <string.h>
+
+typedef unsigned __int128 u128;
+
+/* Ring multiplications performed so far; the tag accounting of Sec. 3.4 is
+ * read off this counter around the tag computations. */
+static uint64_t g_mults;
+
+/* ------------------------------------------------------------------ */
+/* (lo, hi) limb storage                                                */
+
+static inline u128 ld(const uint64_t *p, int64_t i) {
+    return (u128)p[2 * i] | ((u128)p[2 * i + 1] << 64);
+}
+static inline void st(uint64_t *p, int64_t i, u128 v) {
+    p[2 * i] = (uint64_t)v;
+    p[2 * i + 1] = (uint64_t)(v >> 64);
+}
+static uint64_t *alloc128(int64_t n) {
+    uint64_t *p = (uint64_t *)calloc((size_t)(n > 0 ? n : 1) * 2, sizeof(uint64_t));
+    if (!p) abort();
+    return p;
+}
+
+/* ------------------------------------------------------------------ */
+/* F_Rand / F_MAC stand-in: counter-based SplitMix64                    */
+/* (Steele, Lea and Flood, "Fast splittable pseudorandom number         */
+/*  generators", OOPSLA 2014).  The i-th draw (0-based) of a stream is   */
+/*  the (i+1)-th output of SplitMix64 started at the stream key.         */
+
+#define OR_GAMMA 0x9E3779B97F4A7C15ULL
+
+uint64_t or_mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+uint64_t or_stream_key(uint64_t seed, uint64_t stream) { return or_mix64(seed ^ or_mix64(stream)); }
+
+uint64_t or_draw(uint64_t seed, uint64_t stream, uint64_t i) {
+    return or_mix64(or_stream_key(seed, stream) + (i + 1) * OR_GAMMA);
+}
+
+void or_draw_many(uint64_t seed, uint64_t stream, uint64_t first, int64_t n, uint64_t *out) {
+    for (int64_t i = 0; i < n; i++) out[i] = or_draw(seed, stream, first + (uint64_t)i);
+}
+
+static uint64_t stream_of(uint64_t layer_id, uint64_t purpose) { return (layer_id << 16) | purpose; }
+
+/* element e of a 128-bit stream is draw(2e) + 2^64 * draw(2e+1) */
+static u128 draw128(uint64_t seed, uint64_t stream, uint64_t e) {
+    return (u128)or_draw(seed, stream, 2 * e) | ((u128)or_draw(seed, stream, 2 * e + 1) << 64);
+}
+
+/* F_MAC Initialize: key shares [Delta]_p uniform in Z_{2^s}. */
+void or_key_shares(uint64_t key_seed, uint64_t delta[2]) {
+    for (int p = 0; p < 2; p++)
+        delta[p] = or_draw(key_seed, stream_of(OR_GLOBAL_LAYER, OR_P_KEY + (uint64_t)p), 0);
+}
+
+/* The key used in every tag relation is the integer sum [Delta]_0 + [Delta]_1
+ * (< 2^65), taken mod 2^{k+s}; see the reading of Sec. 2.4 in the design notes. */
+static u128 key_sum(const uint64_t delta[2]) { return (u128)delta[0] + (u128)delta[1]; }
+
+/* ------------------------------------------------------------------ */
+/* building blocks                                                      */
+
+/* out = P * Q mod 2^128 for P (M x K), Q (K x N); a plain triple loop. */
+void or_matmul(int64_t M, int64_t K, int64_t N, const uint64_t *P, const uint64_t *Q, uint64_t *out) {
+    u128 *acc = (u128 *)calloc((size_t)(N > 0 ? N : 1), sizeof(u128));
+    if (!acc) abort();
+    for (int64_t i = 0; i < M; i++) {
+        memset(acc, 0, (size_t)N * sizeof(u128));
+        for (int64_t k = 0; k < K; k++) {
+            u128 a = ld(P, i * K + k);
+            for (int64_t j = 0; j < N; j++) acc[j] += a * ld(Q, k * N + j);
+            g_mults += (uint64_t)N;
+        }
+        for (int64_t j = 0; j < N; j++) st(out, i * N + j, acc[j]);
+    }
+    free(acc);
+}
+
+/* Pi_Compress (Fig. "proccomp", step 1): M^c = M * chi, chi in Z_{2^s}^{N x 1}. */
+void or_compress(int64_t rows, int64_t N, const uint64_t *Mx, const uint64_t *chi, uint64_t *out) {
+    for (int64_t i = 0; i < rows; i++) {
+        u128 s = 0;
+        for (int64_t j = 0; j < N; j++) s += ld(Mx, i * N + j) * (u128)chi[j];
+        g_mults += (uint64_t)N;
+        st(out, i, s);
+    }
+}
+
+/* Pi_BatchRec tag check (Fig. 1, tag-check steps 2-3), one party's share:
+ *   [CS] = [tag W] (.) chi - [Delta]_p * (W (.) chi),  cs_p = sum of all entries of [CS],
+ * everything mod 2^{k+s}. */
+void or_batchrec_cs(int64_t n, const uint64_t *W, const uint64_t *tW, const uint64_t *chi,
+                    uint64_t delta_p, uint64_t out[2]) {
+    u128 cs = 0;
+    for (int64_t e = 0; e < n; e++) {
+        u128 CS = ld(tW, e) * (u128)chi[e] - (u128)delta_p * (ld(W, e) * (u128)chi[e]);
+        cs += CS;
+    }
+    st(out, 0, cs);
+}
+
+/* Pi_CompactMatMul verification, steps 3-5 (Fig. 6), one party's share:
+ *   [CS] = [Delta]_p * D^c;  [CS] = [CS] (.) chihat - [tag D^c] (.) chihat;  cs_p = sum_i [CS]_i.
+ * Reduced mod 2^{k+s} (reading of the k+2s modulus in the design notes). */
+void or_compact_cs(int64_t rows, const uint64_t *Dc, const uint64_t *tDc, const uint64_t *chihat,
+                   uint64_t delta_p, uint64_t out[2]) {
+    u128 cs = 0;
+    for (int64_t i = 0; i < rows; i++) {
+        u128 CS = (u128)delta_p * ld(Dc, i);
+        CS = CS * (u128)chihat[i] - ld(tDc, i) * (u128)chihat[i];
+        cs += CS;
+    }
+    st(out, 0, cs);
+}
+
+/* ------------------------------------------------------------------ */
+/* preprocessing: a trusted dealer in place of F_MAC Auth               */
+
+/* Authenticated 2-party sharing of one lifted value (Sec. 2.4): party 0's value
+ * and tag shares are fresh draws, party 1's complete the sums
+ *   [v]_0 + [v]_1 = v~,   [t]_0 + [t]_1 = Delta~ * v~   (mod 2^{k+s}). */
+static void auth_share(u128 lift, u128 dsum, uint64_t seed, uint64_t layer_id, int obj, uint64_t e,
+                       uint64_t *v0, uint64_t *v1, uint64_t *t0, uint64_t *t1, int64_t at) {
+    u128 s0 = draw128(seed, stream_of(layer_id, OR_P_VSH + (uint64_t)obj), e);
+    u128 tag = dsum * lift;
+    u128 ts0 = draw128(seed, stream_of(layer_id, OR_P_TSH + (uint64_t)obj), e);
+    st(v0, at, s0);
+    st(v1, at, lift - s0);
+    st(t0, at, ts0);
+    st(t1, at, tag - ts0);
+}
+
+enum { OBJ_X = 1, OBJ_Y = 2, OBJ_A = 3, OBJ_B = 4, OBJ_C = 5, OBJ_R = 6 };
+
+/* Preprocessing of Fig. 6 (Beaver matrix triple A, B, C = A*B and the mask R),
+ * plus, when with_inputs is set, authenticated shares of the inputs X and Y.
+ * Inputs are values of Z_{2^k} lifted with zero upper bits; A, B, R are
+ * uniform in Z_{2^{k+s}}; C~ = A~ * B~ mod 2^{k+s}. */
+void or_deal(const or_desc *d, const uint64_t delta[2], int with_inputs, or_bufs *b) {
+    const int64_t M = d->M, K = d->K, N = d->N, r0 = d->r0, rows = d->r1 - d->r0;
+    const uint64_t seed = d->seed, lid = d->layer_id;
+    const u128 dsum = key_sum(delta);
+    (void)M;
+
+    uint64_t *At = alloc128(rows * K), *Bt = alloc128(K * N), *Ct = alloc128(rows * N);
+    for (int64_t i = 0; i < rows; i++)
+        for (int64_t k = 0; k < K; k++)
+            st(At, i * K + k, draw128(seed, stream_of(lid, OR_P_LIFT_A), (uint64_t)((r0 + i) * K + k)));
+    for (int64_t e = 0; e < K * N; e++) st(Bt, e, draw128(seed, stream_of(lid, OR_P_LIFT_B), (uint64_t)e));
+    or_matmul(rows, K, N, At, Bt, Ct);
+
+    for (int64_t i = 0; i < rows; i++)
+        for (int64_t k = 0; k < K; k++) {
+            int64_t at = i * K + k;
+            uint64_t e = (uint64_t)((r0 + i) * K + k);
+            if (with_inputs) {
+                u128 x = (u128)or_draw(seed, stream_of(lid, OR_P_LIFT_X), e);
+                auth_share(x, dsum, seed, lid, OBJ_X, e, b->X[0], b->X[1], b->tX[0], b->tX[1], at);
+            }
+            auth_share(ld(At, at), dsum, seed, lid, OBJ_A, e, b->A[0], b->A[1], b->tA[0], b->tA[1], at);
+        }
+    for (int64_t e = 0; e < K * N; e++) {
+        if (with_inputs) {
+            u128 y = (u128)or_draw(seed, stream_of(lid, OR_P_LIFT_Y), (uint64_t)e);
+            auth_share(y, dsum, seed, lid, OBJ_Y, (uint64_t)e, b->Y[0], b->Y[1], b->tY[0], b->tY[1], e);
+        }
+        auth_share(ld(Bt, e), dsum, seed, lid, OBJ_B, (uint64_t)e, b->B[0], b->B[1], b->tB[0], b->tB[1], e);
+    }
+    for (int64_t i = 0; i < rows; i++)
+        for (int64_t j = 0; j < N; j++) {
+            int64_t at = i * N + j;
+            uint64_t e = (uint64_t)((r0 + i) * N + j);
+            u128 r = draw128(seed, stream_of(lid, OR_P_LIFT_R), e);
+            auth_share(ld(Ct, at), dsum, seed, lid, OBJ_C, e, b->C[0], b->C[1], b->tC[0], b->tC[1], at);
+            auth_share(r, dsum, seed, lid, OBJ_R, e, b->R[0], b->R[1], b->tR[0], b->tR[1], at);
+        }
+    free(At);
+    free(Bt);
+    free(Ct);
+}
+
+/* ------------------------------------------------------------------ */
+/* online phase (what the GPU library calls tag_linear)                 */
+
+/* Pi_BatchRec open (Fig. 1, steps 1-3) of W = P - Q for authenticated P, Q:
+ * each party's share [W]_p = [P]_p - [Q]_p is broadcast and W = sum_p [W]_p
+ * mod 2^{k+s}.  The zero mask of Fig. 1 is omitted: Q is a uniform Beaver mask. */
+static void open_diff(int64_t n, uint64_t *const P[2], uint64_t *const Q[2], uint64_t *W) {
+    for (int64_t e = 0; e < n; e++) {
+        u128 w0 = ld(P[0], e) - ld(Q[0], e);
+        u128 w1 = ld(P[1], e) - ld(Q[1], e);
+        st(W, e, w0 + w1);
+    }
+}
+
+static void add_into(int64_t n, uint64_t *acc, const uint64_t *x) {
+    for (int64_t e = 0; e < n; e++) st(acc, e, ld(acc, e) + ld(x, e));
+}
+
+void or_online(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) {
+    const int64_t K = d->K, N = d->N, rows = d->r1 - d->r0;
+    const uint64_t seed = d->seed, lid = d->layer_id;
+
+    /* Fig. 6 online step 1: open E = X - A and U = Y - B. */
+    open_diff(rows * K, b->X, b->A, b->E);
+    open_diff(K * N, b->Y, b->B, b->U);
+
+    /* Fig. 6 online step 2 and Eq. (2):
+     *   [Z]_p = [C]_p + E*[B]_p + [A]_p*U, and the public term E*U is added by
+     *   party 0 only (Fig. 2 step 3 / Fig. 6 step 4).  E*U is formed before D
+     *   is opened (reading of Eq. (7) and the cost count of Sec. 3.4). */
+    uint64_t *EU = alloc128(rows * N), *tmp = alloc128(rows * N);
+    uint64_t m_eu = g_mults;
+    or_matmul(rows, K, N, b->E, b->U, EU);
+    const uint64_t eu_mults = g_mults - m_eu;
+    for (int p = 0; p < 2; p++) {
+        memcpy(b->Z[p], b->C[p], (size_t)(rows * N) * 16);
+        or_matmul(rows, K, N, b->E, b->B[p], tmp);
+        add_into(rows * N, b->Z[p], tmp);
+        or_matmul(rows, K, N, b->A[p], b->U, tmp);
+        add_into(rows * N, b->Z[p], tmp);
+    }
+    add_into(rows * N, b->Z[0], EU);
+
+    /* Open D = R - Z (Pi_OptMAC step 2 in COMPACT mode; Pi_Truncation step 1 in
+     * SPDZ2k mode), kept as the full lift D~ mod 2^{k+s}. */
+    open_diff(rows * N, b->R, b->Z, b->D);
+
+    if (mode == OR_MODE_SPDZ2K) {
+        /* Eq. (3): [tZ]_p = [tC]_p + E*[tB]_p + [tA]_p*U + [Delta]_p * (E*U);
+         * the key term is added by every party (it is a share of Delta~ * EU).
+         * Every party forms E*U itself, so its cost is charged to each. */
+        for (int p = 0; p < 2; p++) {
+            uint64_t m0 = g_mults;
+            memcpy(b->tZ[p], b->tC[p], (size_t)(rows * N) * 16);
+            or_matmul(rows, K, N, b->E, b->tB[p], tmp);
+            add_into(rows * N, b->tZ[p], tmp);
+            or_matmul(rows, K, N, b->tA[p], b->U, tmp);
+            add_into(rows * N, b->tZ[p], tmp);
+            for (int64_t e = 0; e < rows * N; e++) {
+                st(b->tZ[p], e, ld(b->tZ[p], e) + (u128)delta[p] * ld(EU, e));
+                g_mults++;
+            }
+            b->tag_mults[p] = g_mults - m0 + eu_mults;
+        }
+    } else {
+        /* Pi_OptMAC step 3: [tZ]_p = [tR]_p - [Delta]_p * D~. */
+        uint64_t opt[2];
+        for (int p = 0; p < 2; p++) {
+            uint64_t m0 = g_mults;
+            for (int64_t e = 0; e < rows * N; e++) {
+                st(b->tZ[p], e, ld(b->tR[p], e) - (u128)delta[p] * ld(b->D, e));
+                g_mults++;
+            }
+            opt[p] = g_mults - m0;
+        }
+
+        /* Fig. 6 steps 5-6: public combiners chi in Z_{2^s}^{N x 1}, compress
+         * tag(B), tag(C), U, tag(R) and D~ along N.  The public vectors U^c,
+         * D~^c and E*U^c are formed by every party, so their cost is charged
+         * to each. */
+        uint64_t *chi = (uint64_t *)malloc((size_t)(N > 0 ? N : 1) * 8);
+        if (!chi) abort();
+        or_draw_many(seed, stream_of(lid, OR_P_CHI), 0, N, chi);
+        uint64_t m_pub = g_mults;
+        or_compress(K, N, b->U, chi, b->Uc);
+        or_compress(rows, N, b->D, chi, b->Dc);
+        /* Eq. (7) / Fig. 6 step 7, with the key on the public term:
+         *   [tZ^c]_p = [tC^c]_p + E*[tB^c]_p + [tA]_p*U^c + [Delta]_p * (E*U^c)
+         *   [tD^c]_p = [tR^c]_p - [tZ^c]_p */
+        or_matmul(rows, K, 1, b->E, b->Uc, b->EUc);
+        const uint64_t pub_mults = g_mults - m_pub;
+        uint64_t *v = alloc128(rows);
+        for (int p = 0; p < 2; p++) {
+            uint64_t m0 = g_mults;
+            or_compress(K, N, b->tB[p], chi, b->tBc[p]);
+            or_compress(rows, N, b->tC[p], chi, b->tCc[p]);
+            or_compress(rows, N, b->tR[p], chi, b->tRc[p]);
+            memcpy(b->tZc[p], b->tCc[p], (size_t)rows * 16);
+            or_matmul(rows, K, 1, b->E, b->tBc[p], v);
+            add_into(rows, b->tZc[p], v);
+            or_matmul(rows, K, 1, b->tA[p], b->Uc, v);
+            add_into(rows, b->tZc[p], v);
+            for (int64_t i = 0; i < rows; i++) {
+                st(b->tZc[p], i, ld(b->tZc[p], i) + (u128)delta[p] * ld(b->EUc, i));
+                g_mults++;
+                st(b->tDc[p], i, ld(b->tRc[p], i) - ld(b->tZc[p], i));
+            }
+            b->tag_mults[p] = g_mults - m0 + pub_mults + opt[p];
+        }
+        free(chi);
+        free(v);
+    }
+    free(EU);
+    free(tmp);
+}
+
+/* ------------------------------------------------------------------ */
+/* verification (what the GPU library calls mac_check)                  */
+
+/* per-party tag shares of W = P - Q by linearity: [tW]_p = [tP]_p - [tQ]_p */
+static void tag_diff(int64_t n, const uint64_t *tP, const uint64_t *tQ, uint64_t *out) {
+    for (int64_t e = 0; e < n; e++) st(out, e, ld(tP, e) - ld(tQ, e));
+}
+
+void or_check(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) {
+    const int64_t M = d->M, K = d->K, N = d->N, r0 = d->r0, rows = d->r1 - d->r0;
+    const uint64_t seed = d->seed, lid = d->layer_id;
+    int64_t big = rows * K > K * N ? rows * K : K * N;
+    if (rows * N > big) big = rows * N;
+    uint64_t *tW = alloc128(big);
+    uint64_t *chi = (uint64_t *)malloc((size_t)(big > M ? big : M) * 8);
+    if (!chi) abort();
+    (void)M;
+
+    /* Fig. 6 verification step 1: Pi_BatchRec tag check of E and of U, one
+     * public combiner per element (Fig. 1 tag-check step 1). */
+    or_draw_many(seed, stream_of(lid, OR_P_CHI_E), (uint64_t)(r0 * K), rows * K, chi);
+    for (int p = 0; p < 2; p++) {
+        tag_diff(rows * K, b->tX[p], b->tA[p], tW);
+        or_batchrec_cs(rows * K, b->E, tW, chi, delta[p], b->cs[0][p]);
+    }
+    or_draw_many(seed, stream_of(lid, OR_P_CHI_U), 0, K * N, chi);
+    for (int p = 0; p < 2; p++) {
+        tag_diff(K * N, b->tY[p], b->tB[p], tW);
+        or_batchrec_cs(K * N, b->U, tW, chi, delta[p], b->cs[1][p]);
+    }
+
+    if (mode == OR_MODE_SPDZ2K) {
+        /* Pi_Truncation verification: Pi_BatchRec tag check of D = R - Z,
+         * [tD]_p = [tR]_p - [tZ]_p. */
+        or_draw_many(seed, stream_of(lid, OR_P_CHI_D), (uint64_t)(r0 * N), rows * N, chi);
+        for (int p = 0; p < 2; p++) {
+            tag_diff(rows * N, b->tR[p], b->tZ[p], tW);
+            or_batchrec_cs(rows * N, b->D, tW, chi, delta[p], b->cs[2][p]);
+        }
+    } else {
+        /* Fig. 6 verification steps 2-5: chihat in Z_{2^s}^{M x 1}. */
+        or_draw_many(seed, stream_of(lid, OR_P_CHIHAT), (uint64_t)r0, rows, chi);
+        for (int p = 0; p < 2; p++) or_compact_cs(rows, b->Dc, b->tDc[p], chi, delta[p], b->cs[2][p]);
+    }
+    free(tW);
+    free(chi);
+}

@@ -1,0 +1,79 @@
+/*
+ * ct_oracle.h -- interface of the CPU oracle (test infrastructure only).
+ *
+ * This header belongs to oracle/ and to nothing else: the GPU library has its
+ * own header and shares no code, constant or helper with this one.  Only the
+ * test suite, the smoke check and the CPU-baseline leg of the benchmark load
+ * the oracle.
+ *
+ * Ring elements of Z_{2^128} are stored as two little-endian uint64 limbs
+ * (lo, hi).  Matrices are row-major.  A "rows" range [r0, r1) restricts every
+ * M-indexed quantity to those rows of the M dimension; with r0 = 0 and r1 = M
+ * the oracle runs the whole procedure.  K x N quantities are always complete.
+ */
+#ifndef CT_ORACLE_H
+#define CT_ORACLE_H
+#include <stdint.h>
+
+#define OR_MODE_SPDZ2K 0
+#define OR_MODE_COMPACT 1
+
+/* Purposes of the counter-based generator streams; stream = (layer_id << 16) | purpose. */
+#define OR_P_LIFT_X 0x01
+#define OR_P_LIFT_Y 0x02
+#define OR_P_LIFT_A 0x03
+#define OR_P_LIFT_B 0x04
+#define OR_P_LIFT_R 0x05
+#define OR_P_VSH 0x10 /* + object index 1..6 (X, Y, A, B, C, R) */
+#define OR_P_TSH 0x20 /* + object index 1..6 */
+#define OR_P_CHI 0x30
+#define OR_P_CHIHAT 0x31
+#define OR_P_CHI_E 0x32
+#define OR_P_CHI_U 0x33
+#define OR_P_CHI_D 0x34
+#define OR_P_KEY 0x40 /* + party, on the global layer id 0xFFFF */
+#define OR_GLOBAL_LAYER 0xFFFFULL
+
+typedef struct {
+    int64_t M, K, N;          /* X is M x K, Y is K x N, Z is M x N */
+    uint64_t seed, layer_id;  /* per-layer randomness */
+    int64_t r0, r1;           /* rows of the M dimension that are computed */
+} or_desc;
+
+/* Every pointer is a caller-owned array of (lo, hi) uint64 pairs. */
+typedef struct {
+    /* rows x K */
+    uint64_t *X[2], *tX[2], *A[2], *tA[2], *E;
+    /* K x N */
+    uint64_t *Y[2], *tY[2], *B[2], *tB[2], *U;
+    /* rows x N */
+    uint64_t *C[2], *tC[2], *R[2], *tR[2], *Z[2], *tZ[2], *D;
+    /* compact-tag vectors: K entries */
+    uint64_t *Uc, *tBc[2];
+    /* compact-tag vectors: rows entries */
+    uint64_t *Dc, *EUc, *tCc[2], *tRc[2], *tZc[2], *tDc[2];
+    /* check-value shares cs[W][party][limb], W in (E, U, D) */
+    uint64_t cs[3][2][2];
+    /* local multiplications spent on tags, per party */
+    uint64_t tag_mults[2];
+} or_bufs;
+
+uint64_t or_mix64(uint64_t z);
+uint64_t or_stream_key(uint64_t seed, uint64_t stream);
+uint64_t or_draw(uint64_t seed, uint64_t stream, uint64_t i);
+void or_draw_many(uint64_t seed, uint64_t stream, uint64_t first, int64_t n, uint64_t *out);
+
+void or_key_shares(uint64_t key_seed, uint64_t delta[2]);
+void or_deal(const or_desc *d, const uint64_t delta[2], int with_inputs, or_bufs *b);
+void or_online(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b);
+void or_check(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b);
+
+/* building blocks, exposed so tests can feed chosen combiners */
+void or_matmul(int64_t M, int64_t K, int64_t N, const uint64_t *P, const uint64_t *Q, uint64_t *out);
+void or_compress(int64_t rows, int64_t N, const uint64_t *Mx, const uint64_t *chi, uint64_t *out);
+void or_batchrec_cs(int64_t n, const uint64_t *W, const uint64_t *tW, const uint64_t *chi,
+                    uint64_t delta_p, uint64_t out[2]);
+void or_compact_cs(int64_t rows, const uint64_t *Dc, const uint64_t *tDc, const uint64_t *chihat,
+                   uint64_t delta_p, uint64_t out[2]);
+
+#endif

@@ -1,0 +1,348 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a published
+generator output, a plain definition (the product of the lifted inputs, the
+tag relation of Eq. (1)), an identity between the two protocols, the
+soundness of the MAC check, a special case that reduces to the single-value
+check of Sec. 2.5, the closed-form costs of Sec. 3.4, or brute force with
+Python integers on tiny shapes.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import ref
+
+R = 1 << 128
+M64 = (1 << 64) - 1
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+SHAPES = [(1, 1, 1), (2, 3, 4), (4, 5, 3), (3, 1, 2), (5, 7, 1), (1, 6, 5), (6, 4, 9)]
+
+
+def ints(a):
+    return O.to_ints(a)
+
+
+def lift(L, name):
+    """sum of the two parties' shares, mod 2^128"""
+    return (ints(L[name][0]) + ints(L[name][1])) % R
+
+
+def dsum(L):
+    return int(L.delta[0]) + int(L.delta[1])
+
+
+def lifts_from_prng(L):
+    """The dealt lifts recomputed directly from the generator definition."""
+    M, K, N, seed, lid = L.M, L.K, L.N, L.seed, L.layer_id
+    r0, r1 = L.r0, L.r1
+
+    def d64(purpose, e):
+        return ref.draw(seed, ref.stream(lid, purpose), e)
+
+    def d128(purpose, e):
+        return d64(purpose, 2 * e) | (d64(purpose, 2 * e + 1) << 64)
+
+    X = np.array([[d64(1, i * K + k) for k in range(K)] for i in range(r0, r1)], dtype=object)
+    Y = np.array([[d64(2, k * N + j) for j in range(N)] for k in range(K)], dtype=object)
+    A = np.array([[d128(3, i * K + k) for k in range(K)] for i in range(r0, r1)], dtype=object)
+    B = np.array([[d128(4, k * N + j) for j in range(N)] for k in range(K)], dtype=object)
+    Rm = np.array([[d128(5, i * N + j) for j in range(N)] for i in range(r0, r1)], dtype=object)
+    return X.reshape(r1 - r0, K), Y.reshape(K, N), A.reshape(r1 - r0, K), B.reshape(K, N), Rm.reshape(r1 - r0, N)
+
+
+def omatmul(P, Q):
+    return np.array([[sum(int(P[i, k]) * int(Q[k, j]) for k in range(P.shape[1])) % R
+                      for j in range(Q.shape[1])] for i in range(P.shape[0])], dtype=object).reshape(
+        P.shape[0], Q.shape[1])
+
+
+@pytest.fixture(scope="module")
+def built():
+    O.build()
+
+
+# ---------------------------------------------------------------- generator
+
+def test_splitmix64_published_outputs(built):
+    vals = [int(l, 16) for l in open(os.path.join(GOLDEN, "splitmix64_state0.txt")) if l.startswith("0x")]
+    gamma = 0x9E3779B97F4A7C15
+    got = [O.mix64((n * gamma) & M64) for n in range(1, len(vals) + 1)]
+    assert got == vals
+
+
+def test_stream_draws_are_splitmix_outputs(built):
+    # the i-th draw of a stream is output i+1 of SplitMix64 started at the stream key
+    for seed, stream in [(0, 0), (1000, 0x10001), (2 ** 63 + 5, (7 << 16) | 0x32)]:
+        key = O.lib().or_stream_key(seed, stream)
+        state = key
+        for i in range(5):
+            state = (state + 0x9E3779B97F4A7C15) & M64
+            assert O.draw(seed, stream, i) == O.mix64(state)
+        assert key == O.mix64(seed ^ O.mix64(stream))
+
+
+def test_python_generator_matches_c(built):
+    for i in range(10):
+        assert ref.draw(1001, (3 << 16) | 4, i) == O.draw(1001, (3 << 16) | 4, i)
+
+
+# ---------------------------------------------------------------- dealer
+
+@pytest.mark.parametrize("shape", SHAPES[:5])
+def test_dealer_sharing_and_tags(built, shape):
+    M, K, N = shape
+    L = O.OracleLayer(M, K, N, seed=11, layer_id=3, key_seed=99).deal()
+    X, Y, A, B, Rm = lifts_from_prng(L)
+    key = dsum(L)
+    assert int(L.delta[0]) < 2 ** 64 and int(L.delta[1]) < 2 ** 64
+    C = omatmul(A, B)  # the triple: C~ = A~ B~ mod 2^{k+s}
+    for name, v in [("X", X), ("Y", Y), ("A", A), ("B", B), ("C", C), ("R", Rm)]:
+        assert (lift(L, name) == v).all(), name
+        # Eq. (1): the tag shares sum to Delta~ * v~ mod 2^{k+s}
+        assert (lift(L, "t" + name) == (key * v) % R).all(), name
+    assert (X < 2 ** 64).all() and (Y < 2 ** 64).all()
+
+
+def test_key_shares_one_zero_give_tags_equal_to_lifts(built):
+    L = O.OracleLayer(3, 4, 2, seed=5, layer_id=1, key_seed=1)
+    L.delta = np.array([1, 0], dtype=np.uint64)
+    L.deal()
+    for name in "XYABCR":
+        assert (lift(L, "t" + name) == lift(L, name)).all()
+
+
+# ---------------------------------------------------------------- online phase
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("mode", [O.MODE_SPDZ2K, O.MODE_COMPACT])
+def test_plain_definitions(built, shape, mode):
+    M, K, N = shape
+    L = O.run_layer(mode, M, K, N, seed=20 + M, layer_id=2, key_seed=77)
+    X, Y, A, B, Rm = lifts_from_prng(L)
+    XY = omatmul(X, Y)
+    # Beaver correctness: the output shares reconstruct X~ Y~ mod 2^{k+s}
+    Zt = lift(L, "Z")
+    assert (Zt == XY).all()
+    # and the value is the plain Z_{2^64} product
+    Z64 = (np.array(Zt.reshape(-1) % 2 ** 64, dtype=np.uint64)).reshape(M, N)
+    Xu = np.array(X.reshape(-1), dtype=np.uint64).reshape(M, K)
+    Yu = np.array(Y.reshape(-1), dtype=np.uint64).reshape(K, N)
+    with np.errstate(over="ignore"):
+        assert (np.matmul(Xu, Yu) == Z64).all()
+    # opened values
+    assert (ints(L["E"]) == (X - A) % R).all()
+    assert (ints(L["U"]) == (Y - B) % R).all()
+    assert (ints(L["D"]) == (Rm - XY) % R).all()
+    # tag relation on the output, both protocols
+    assert (lift(L, "tZ") == (dsum(L) * XY) % R).all()
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_cross_mode_identities(built, shape):
+    """CompactTag reaches the same authenticated output as SPDZ2k: identical value
+    shares and opened matrices, equal tag sums, and per party the compact tag
+    equals the SPDZ2k tag compressed by the same combiners."""
+    M, K, N = shape
+    S = O.run_layer(O.MODE_SPDZ2K, M, K, N, seed=31, layer_id=5, key_seed=4)
+    C = O.run_layer(O.MODE_COMPACT, M, K, N, seed=31, layer_id=5, key_seed=4)
+    for n in ("Z", "E", "U", "D"):
+        assert (S[n] == C[n]).all(), n
+    assert (lift(S, "tZ") == lift(C, "tZ")).all()
+    chi = np.array([ref.draw(31, ref.stream(5, 0x30), j) for j in range(N)], dtype=object)
+    for p in range(2):
+        tZs = ints(S["tZ"][p]).reshape(M, N)
+        expect = np.array([sum(int(tZs[i, j]) * int(chi[j]) for j in range(N)) % R for i in range(M)], dtype=object)
+        assert (ints(C["tZc"][p]) == expect).all()
+        # compact tag of D: [tD^c]_p = [tR]_p chi - [tZ]_p chi
+        tRs = ints(C["tR"][p]).reshape(M, N)
+        expD = np.array([sum((int(tRs[i, j]) - int(tZs[i, j])) * int(chi[j]) for j in range(N)) % R
+                         for i in range(M)], dtype=object)
+        assert (ints(C["tDc"][p]) == expD).all()
+    # the compressed public matrices
+    Dm = ints(C["D"]).reshape(M, N)
+    assert (ints(C["Dc"]) == np.array([sum(int(Dm[i, j]) * int(chi[j]) for j in range(N)) % R
+                                       for i in range(M)], dtype=object)).all()
+
+
+@pytest.mark.parametrize("shape", SHAPES[:6])
+@pytest.mark.parametrize("compact", [False, True])
+def test_bruteforce_python_reference(built, shape, compact):
+    M, K, N = shape
+    mode = O.MODE_COMPACT if compact else O.MODE_SPDZ2K
+    L = O.run_layer(mode, M, K, N, seed=41, layer_id=9, key_seed=8)
+    S = {n: [ints(L[n][p]).reshape(L[n][p].shape[:-1]).tolist() for p in range(2)]
+         for n in ("X", "tX", "A", "tA", "Y", "tY", "B", "tB", "C", "tC", "R", "tR")}
+    delta = [int(L.delta[0]), int(L.delta[1])]
+    out = ref.online_and_check(compact, M, K, N, 41, 9, delta, S)
+    assert ints(L["E"]).reshape(M, K).tolist() == out["E"]
+    assert ints(L["U"]).reshape(K, N).tolist() == out["U"]
+    assert ints(L["D"]).reshape(M, N).tolist() == out["D"]
+    for p in range(2):
+        assert ints(L["Z"][p]).reshape(M, N).tolist() == out["Z"][p]
+        assert ints(L["tZ"][p]).reshape(M, N).tolist() == out["tZ"][p]
+        if compact:
+            assert ints(L["tZc"][p]).tolist() == out["tZc"][p]
+            assert ints(L["tDc"][p]).tolist() == out["tDc"][p]
+    for w in range(3):
+        for p in range(2):
+            assert O.u128(L.cs[w, p]) == out["cs"][w][p], (w, p)
+
+
+# ---------------------------------------------------------------- verification
+
+@pytest.mark.parametrize("mode", [O.MODE_SPDZ2K, O.MODE_COMPACT])
+def test_honest_runs_accept(built, mode):
+    for seed in range(12):
+        M, K, N = SHAPES[seed % len(SHAPES)]
+        L = O.run_layer(mode, M, K, N, seed=100 + seed, layer_id=seed, key_seed=1000 + seed)
+        assert L.cs_sums() == [0, 0, 0]
+        assert L.accept()
+
+
+TAMPER_TARGETS = [("X", 0), ("tX", 0), ("A", 2), ("tA", 2), ("Y", 1), ("tY", 1), ("B", 1), ("tB", 1),
+                  ("C", 2), ("tC", 2), ("R", 2), ("tR", 2)]
+
+
+@pytest.mark.parametrize("mode", [O.MODE_SPDZ2K, O.MODE_COMPACT])
+@pytest.mark.parametrize("target", TAMPER_TARGETS)
+@pytest.mark.parametrize("bit", [0, 31, 63])
+def test_single_flipped_share_bit_aborts(built, mode, target, bit):
+    """Flipping one bit below 2^k in one party's value or tag share makes the
+    check that covers it fail (failure probability <= 2^{-s+log(s+1)}, Fig. 1
+    and Theorem 1)."""
+    name, w = target
+    M, K, N = 3, 4, 5
+    for party in (0, 1):
+        L = O.OracleLayer(M, K, N, seed=7, layer_id=4, key_seed=3).deal()
+        arr = L[name][party]
+        flat = arr.reshape(-1, 2)
+        idx = (5 * bit + 3) % flat.shape[0]
+        flat[idx, 0] ^= np.uint64(1 << bit)
+        L.online(mode).check(mode)
+        sums = L.cs_sums()
+        assert sums[w] != 0, (name, party, bit, sums)
+        assert not L.accept()
+
+
+def test_compact_check_with_unit_combiners_is_single_value_check(built):
+    """With chi = e_j and chihat = e_i the compact check of D reduces to the
+    single-value check of D_ij (Sec. 2.5): cs_p = -([tag D_ij]_p - D_ij [Delta]_p)."""
+    M, K, N = 3, 4, 5
+    L = O.run_layer(O.MODE_COMPACT, M, K, N, seed=3, layer_id=1, key_seed=2)
+    D = L["D"]
+    for i in range(M):
+        for j in range(N):
+            chi = np.zeros(N, dtype=np.uint64)
+            chi[j] = 1
+            chih = np.zeros(M, dtype=np.uint64)
+            chih[i] = 1
+            Dc = O.compress(D, chi)
+            total = 0
+            for p in range(2):
+                tD = ((ints(L["tR"][p]) - ints(L["tZ"][p])) % R)
+                tDc = O.compress(O.from_ints(tD), chi)
+                cs = O.compact_cs(Dc, tDc, chih, int(L.delta[p]))
+                single = (int(tD[i, j]) - O.u128(D[i, j]) * int(L.delta[p])) % R
+                assert cs == (-single) % R
+                total += cs
+            assert total % R == 0
+
+
+def test_batchrec_with_unit_combiner_is_single_value_check(built):
+    M, K, N = 2, 3, 2
+    L = O.run_layer(O.MODE_SPDZ2K, M, K, N, seed=9, layer_id=2, key_seed=5)
+    E = L["E"]
+    for e in range(M * K):
+        chi = np.zeros(M * K, dtype=np.uint64)
+        chi[e] = 1
+        for p in range(2):
+            tE = (ints(L["tX"][p]) - ints(L["tA"][p])) % R
+            cs = O.batchrec_cs(E, O.from_ints(tE), chi, int(L.delta[p]))
+            i, k = divmod(e, K)
+            assert cs == (int(tE[i, k]) - O.u128(E[i, k]) * int(L.delta[p])) % R
+
+
+def test_rows_ranges_compose(built):
+    """Running rows [r0, r1) pieces reproduces the full run and the check-value
+    shares add up (this is how full-size layers are sampled)."""
+    M, K, N = 7, 5, 4
+    for mode in (O.MODE_SPDZ2K, O.MODE_COMPACT):
+        full = O.run_layer(mode, M, K, N, seed=13, layer_id=6, key_seed=21)
+        cuts = [0, 2, 3, 7]
+        cs = [[0, 0], [0, 0], [0, 0]]
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            part = O.run_layer(mode, M, K, N, seed=13, layer_id=6, key_seed=21, r0=a, r1=b)
+            for n in ("E", "tX"):
+                sl = full[n][a:b] if n == "E" else full[n][:, a:b]
+                assert (part[n] == sl).all()
+            for n in ("Z", "tZ"):
+                assert (part[n] == full[n][:, a:b]).all()
+            assert (part["D"] == full["D"][a:b]).all()
+            if mode == O.MODE_COMPACT:
+                assert (part["tDc"] == full["tDc"][:, a:b]).all()
+            for w in (0, 2):
+                for p in range(2):
+                    cs[w][p] += O.u128(part.cs[w, p])
+            assert (part["U"] == full["U"]).all()
+        for w in (0, 2):
+            for p in range(2):
+                assert cs[w][p] % R == O.u128(full.cs[w, p])
+
+
+# ---------------------------------------------------------------- readings
+
+def test_literal_k_plus_2s_check_rejects_honest_runs(built):
+    """Documents the reading of Fig. 6 verification steps 4-6: evaluated mod
+    2^{k+2s} on the 128-bit shares, the honest compact check fails most of the
+    time, while mod 2^{k+s} it always passes."""
+    R192 = 1 << 192
+    fails = 0
+    trials = 40
+    for t in range(trials):
+        L = O.run_layer(O.MODE_COMPACT, 3, 2, 2, seed=500 + t, layer_id=1, key_seed=600 + t)
+        assert L.accept()
+        chih = [ref.draw(500 + t, ref.stream(1, 0x31), i) for i in range(3)]
+        s = 0
+        for p in range(2):
+            Dc = ints(L["Dc"])
+            tDc = ints(L["tDc"][p])
+            for i in range(3):
+                cs_i = ((int(L.delta[p]) * int(Dc[i])) % R) * chih[i] - int(tDc[i]) * chih[i]
+                s += cs_i
+        fails += (s % R192) != 0
+    assert fails > trials // 2
+
+
+def test_party1_only_key_term_breaks_tag_relation(built):
+    """Documents the reading of Fig. 2 step 3: if only one party adds its key
+    share times E*U, the tag shares no longer sum to Delta~ * Z~."""
+    M, K, N = 3, 4, 2
+    L = O.run_layer(O.MODE_SPDZ2K, M, K, N, seed=17, layer_id=2, key_seed=19)
+    EU = omatmul(ints(L["E"]).reshape(M, K), ints(L["U"]).reshape(K, N))
+    literal = (ints(L["tZ"][0]) + ints(L["tZ"][1]) - int(L.delta[1]) * EU) % R
+    assert not (literal == (dsum(L) * lift(L, "Z")) % R).any()
+
+
+# ---------------------------------------------------------------- costs
+
+@pytest.mark.parametrize("shape", SHAPES + [(8, 16, 32), (33, 7, 2)])
+def test_tag_multiplication_counts_match_closed_forms(built, shape):
+    M, K, N = shape
+    S = O.run_layer(O.MODE_SPDZ2K, M, K, N, seed=1, layer_id=1, key_seed=1)
+    C = O.run_layer(O.MODE_COMPACT, M, K, N, seed=1, layer_id=1, key_seed=1)
+    for p in range(2):
+        assert int(S.tag_mults[p]) == O.spdz2k_tag_mults(M, K, N)
+        assert int(C.tag_mults[p]) == O.compact_tag_mults(M, K, N)
+
+
+def test_paper_384x_example():
+    kv = dict(l.strip().split("=") for l in open(os.path.join(GOLDEN, "paper_op_counts.txt"))
+              if "=" in l and not l.startswith("#"))
+    T1, T2, T3 = int(kv["T1"]), int(kv["T2"]), int(kv["T3"])
+    ratio = O.spdz2k_tag_mults(T1, T2, T3) / O.compact_tag_mults(T1, T2, T3)
+    assert round(ratio) == int(kv["printed_ratio"])
+    assert abs(ratio - 384.08) < 0.01
