@@ -1,0 +1,147 @@
+/*
+ * compacttag.h -- C ABI of libcompacttag, the MI355X (gfx950) library for the
+ * linear-layer hot path of actively secure two-party MPC over Z_{2^64}
+ * (CompactTag, arXiv 2311.04406).
+ *
+ * Setting (Sec. 2.4 of the paper): values live in Z_{2^k}, k = 64; value and
+ * tag shares live in Z_{2^{k+s}} = Z_{2^128}, s = 64; the MAC key shares
+ * [Delta]_p live in Z_{2^s}.  Two parties p = 0, 1 are simulated in one
+ * process on one GPU; every "broadcast and reconstruct" of the paper is an
+ * on-device sum of the two parties' shares.
+ *
+ * Conventions shared by every entry point
+ *   - Ring elements of Z_{2^128} are ct_u128 {lo, hi}: value = lo + 2^64 * hi.
+ *   - Every matrix is row-major and contiguous; X is M x K, Y is K x N,
+ *     Z = X * Y is M x N (the paper's T1 x T2, T2 x T3 and T1 x T3).
+ *   - Every ct_u128 pointer in ct_layer_bufs is a DEVICE pointer, 16-byte
+ *     aligned, allocated and owned by the caller; the library never frees
+ *     caller memory and never allocates on the hot path (ct_tag_linear,
+ *     ct_mac_check_device).  Buffers of different layers must not overlap.
+ *   - Work is enqueued on the stream given in ct_params (NULL = the null
+ *     stream) and is asynchronous unless stated otherwise.  A context is
+ *     single-stream and not thread-safe; several contexts may coexist.
+ *   - Errors are returned as ct_status; nothing is thrown across the ABI.
+ *     CT_EINVAL: a null or misaligned pointer, M, K or N < 1, k or s not 64,
+ *     f != 0, n < 1 or more layers than the context was sized for.
+ *     CT_EDEVICE: a HIP error (text in ct_last_error).  CT_ABORT is not a
+ *     library error: it is the protocol's abort when a MAC check fails.
+ */
+#ifndef COMPACTTAG_H
+#define COMPACTTAG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    uint64_t lo, hi;
+} ct_u128;
+
+typedef enum { CT_OK = 0, CT_EINVAL = 1, CT_ENOMEM = 2, CT_EDEVICE = 3, CT_ABORT = 4 } ct_status;
+
+/* CT_MODE_SPDZ2K: per-element tags of Eq. (3) (Pi_MatMul, Fig. 2), with D = R - Z
+ *                 opened and batch-checked as in Pi_Truncation (Fig. 3).
+ * CT_MODE_COMPACT: optimistic tag (Pi_OptMAC) verified through the compact tag
+ *                 of Eq. (7) (Pi_CompactMatMul, Fig. 6). */
+typedef enum { CT_MODE_SPDZ2K = 0, CT_MODE_COMPACT = 1 } ct_mode;
+
+typedef struct ct_ctx ct_ctx;
+
+typedef struct {
+    int device;           /* HIP device ordinal */
+    uint64_t key_seed;    /* seeds the key shares [Delta]_0, [Delta]_1 */
+    int k_bits, s_bits;   /* must both be 64 */
+    void *hip_stream;     /* hipStream_t the context enqueues on; NULL = null stream */
+    int max_layers;       /* largest n accepted by one call; <= 0 means 256 */
+} ct_params;
+
+typedef struct {
+    int64_t M, K, N;      /* X: M x K, Y: K x N */
+    int32_t f;            /* fractional bits truncated after the product; must be 0 */
+    int32_t reserved;
+    uint64_t seed;        /* per-layer seed of the dealer and of the public combiners */
+    uint64_t layer_id;    /* < 2^48; names the layer's generator streams */
+} ct_layer_desc;
+
+/* Per-layer device buffers.  [v]_p / [t v]_p are party p's value / tag share. */
+typedef struct {
+    ct_u128 *X[2], *tX[2], *A[2], *tA[2];                   /* M x K */
+    ct_u128 *Y[2], *tY[2], *B[2], *tB[2];                   /* K x N */
+    ct_u128 *C[2], *tC[2], *R[2], *tR[2], *Z[2], *tZ[2];    /* M x N; Z, tZ are outputs */
+    ct_u128 *E, *U, *D;  /* opened public values E = X - A (M x K), U = Y - B (K x N),
+                            D = R - Z (M x N); outputs of ct_tag_linear */
+    ct_u128 *cvec;       /* compact-tag vectors, CT_CVEC_LEN(M, K) elements, layout below;
+                            written by ct_tag_linear in CT_MODE_COMPACT, unused otherwise */
+} ct_layer_bufs;
+
+/* cvec layout (element offsets): U^c [K] | tB^c_0 [K] | tB^c_1 [K] | D^c [M] | (E U^c) [M] |
+ * tC^c_0 [M] | tC^c_1 [M] | tR^c_0 [M] | tR^c_1 [M] | tZ^c_0 [M] | tZ^c_1 [M] | tD^c_0 [M] | tD^c_1 [M] */
+#define CT_CVEC_LEN(M, K) (3 * (K) + 10 * (M))
+
+/* Check-value shares of one layer: cs[W][p] for W = 0 (E), 1 (U), 2 (D).
+ * accept = 1 iff cs[W][0] + cs[W][1] = 0 mod 2^128 for all three W. */
+typedef struct {
+    ct_u128 cs[3][2];
+    int32_t accept;
+    int32_t reserved;
+} ct_check_result;
+
+/* Creates a context on params->device: samples the key shares
+ * [Delta]_p = draw(key_seed, stream (0xFFFF << 16) | (0x40 + p), 0) (F_MAC
+ * Initialize, Appendix A) and keeps them resident, and allocates the
+ * context's own fixed-size device scratch (descriptor tables, check
+ * accumulators).  *out receives the context; free it with ct_destroy. */
+ct_status ct_create(ct_ctx **out, const ct_params *params);
+
+/* Releases the context and its scratch after synchronizing its stream. */
+ct_status ct_destroy(ct_ctx *ctx);
+
+/* Copies the two key shares to host memory out[0], out[1]. */
+ct_status ct_key_shares(const ct_ctx *ctx, uint64_t out[2]);
+
+/* Dealer (preprocessing of Fig. 6 and F_MAC Auth, Appendix A), for n layers:
+ * Beaver matrix triple A (M x K), B (K x N), C = A*B mod 2^128 (M x N) and the
+ * mask R (M x N), all uniform in Z_{2^128}, and, if with_inputs != 0, inputs
+ * X (M x K) and Y (K x N) uniform in Z_{2^64} (upper limb zero).  Every object
+ * is authenticated: [v]_0 and [tv]_0 are fresh draws, [v]_1 = v~ - [v]_0 and
+ * [tv]_1 = Delta~ * v~ - [tv]_0 with Delta~ = [Delta]_0 + [Delta]_1 taken as an
+ * integer.  Writes X, tX, Y, tY (if with_inputs), A, tA, B, tB, C, tC, R, tR
+ * of both parties.  Asynchronous. */
+ct_status ct_gen_triple_tags(ct_ctx *ctx, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
+                             int with_inputs);
+
+/* Online phase of n linear layers (Fig. 6 online steps 1-7 at f = 0 for
+ * CT_MODE_COMPACT; Fig. 2 with Eqs. (2)-(3) plus the opening of D for
+ * CT_MODE_SPDZ2K).  Reads X, tX, A, tA, Y, tY, B, tB, C, tC, R, tR; writes
+ * E, U, D, Z, tZ (and cvec in CT_MODE_COMPACT).  Party 0 adds the public term
+ * E*U to its value share; every party adds its key share times a public term
+ * to its tag share.  Asynchronous; allocates nothing. */
+ct_status ct_tag_linear(ct_ctx *ctx, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n);
+
+/* Verification of n layers, results left in device memory: writes n
+ * ct_check_result records to the device array out_dev (the accept field is
+ * computed on the device).  Pi_BatchRec tag check (Fig. 1) of E and U in both
+ * modes and of D = R - Z in CT_MODE_SPDZ2K (Pi_Truncation, Fig. 3); the
+ * compact check of D (Fig. 6 verification steps 2-6) in CT_MODE_COMPACT.  All
+ * check values are reduced mod 2^128.  The public combiners are drawn from the
+ * layer's generator streams, so a layer's results do not depend on the other
+ * layers in the call.  Asynchronous; allocates nothing; graph-capturable. */
+ct_status ct_mac_check_device(ct_ctx *ctx, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B,
+                              int n, ct_check_result *out_dev);
+
+/* As ct_mac_check_device, then waits for the stream and copies the n results
+ * to host memory out.  Returns CT_ABORT if any layer fails its check (out is
+ * still filled, so the caller can see which check value failed). */
+ct_status ct_mac_check(ct_ctx *ctx, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
+                       ct_check_result *out);
+
+/* Text of the last error on this context ("" if none). */
+const char *ct_last_error(const ct_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COMPACTTAG_H */

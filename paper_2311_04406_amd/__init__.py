@@ -1,0 +1,9 @@
+"""MI355X-native hot path of CompactTag (arXiv 2311.04406).
+
+Two-party SPDZ2k-style linear layers over Z_{2^64} with 128-bit shares and
+tags: output-share products on the int8 matrix cores, CompactTag's optimistic
+and compact tags, and batch MAC verification, behind the C ABI of
+``include/compacttag.h``.  ``binding`` is the thin ctypes layer over it.
+"""
+from .binding import (CT_ABORT, CT_OK, MODE_COMPACT, MODE_SPDZ2K, CheckResult, Context, CtError, Layer,  # noqa
+                      load)

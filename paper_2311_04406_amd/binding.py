@@ -1,0 +1,223 @@
+"""ctypes binding of libcompacttag (argument marshalling only).
+
+Every step of the hot path runs in the HIP library; this module only builds
+the C structures of ``include/compacttag.h`` from torch tensors and forwards
+the calls.  Device memory and the stream come from PyTorch (ROCm build): each
+ring matrix is a ``torch.int64`` tensor of shape ``[rows, cols, 2]`` holding
+the (lo, hi) limbs of Z_{2^128} elements.
+
+There is no CPU fallback: if the library is not built or no GPU is visible,
+``load()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libcompacttag.so")
+
+MODE_SPDZ2K = 0
+MODE_COMPACT = 1
+CT_OK, CT_EINVAL, CT_ENOMEM, CT_EDEVICE, CT_ABORT = 0, 1, 2, 3, 4
+STATUS = {0: "CT_OK", 1: "CT_EINVAL", 2: "CT_ENOMEM", 3: "CT_EDEVICE", 4: "CT_ABORT"}
+MASK64 = (1 << 64) - 1
+
+
+class CtParams(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("key_seed", ctypes.c_uint64), ("k_bits", ctypes.c_int),
+                ("s_bits", ctypes.c_int), ("hip_stream", ctypes.c_void_p), ("max_layers", ctypes.c_int)]
+
+
+class CtLayerDesc(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int64), ("K", ctypes.c_int64), ("N", ctypes.c_int64), ("f", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64), ("layer_id", ctypes.c_uint64)]
+
+
+_P2 = ctypes.c_void_p * 2
+BUF_PAIRS = ["X", "tX", "A", "tA", "Y", "tY", "B", "tB", "C", "tC", "R", "tR", "Z", "tZ"]
+BUF_SINGLE = ["E", "U", "D", "cvec"]
+
+
+class CtLayerBufs(ctypes.Structure):
+    _fields_ = [(n, _P2) for n in BUF_PAIRS] + [(n, ctypes.c_void_p) for n in BUF_SINGLE]
+
+
+class CtCheckResult(ctypes.Structure):
+    _fields_ = [("cs", ctypes.c_uint64 * 12), ("accept", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Loads the built HIP library; raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2311_04406_amd.build` "
+                           "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i = ctypes.c_void_p, ctypes.c_int
+    L.ct_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(CtParams)]
+    L.ct_destroy.argtypes = [vp]
+    L.ct_key_shares.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
+    L.ct_gen_triple_tags.argtypes = [vp, ctypes.POINTER(CtLayerDesc), ctypes.POINTER(CtLayerBufs), i, i]
+    L.ct_tag_linear.argtypes = [vp, i, ctypes.POINTER(CtLayerDesc), ctypes.POINTER(CtLayerBufs), i]
+    L.ct_mac_check_device.argtypes = [vp, i, ctypes.POINTER(CtLayerDesc), ctypes.POINTER(CtLayerBufs), i, vp]
+    L.ct_mac_check.argtypes = [vp, i, ctypes.POINTER(CtLayerDesc), ctypes.POINTER(CtLayerBufs), i,
+                               ctypes.POINTER(CtCheckResult)]
+    L.ct_last_error.argtypes = [vp]
+    L.ct_last_error.restype = ctypes.c_char_p
+    for f in ("ct_create", "ct_destroy", "ct_key_shares", "ct_gen_triple_tags", "ct_tag_linear",
+              "ct_mac_check_device", "ct_mac_check"):
+        getattr(L, f).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+class CtError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+@dataclass
+class CheckResult:
+    cs: list            # cs[W][p] as Python ints, W in (E, U, D)
+    accept: bool
+
+    def sums(self):
+        return [(self.cs[w][0] + self.cs[w][1]) % (1 << 128) for w in range(3)]
+
+
+def _result(r: CtCheckResult) -> CheckResult:
+    v = list(r.cs)
+    cs = [[v[4 * w + 2 * p] | (v[4 * w + 2 * p + 1] << 64) for p in range(2)] for w in range(3)]
+    return CheckResult(cs=cs, accept=bool(r.accept))
+
+
+class Layer:
+    """Device buffers of one linear layer (both parties), as torch tensors."""
+
+    def __init__(self, M: int, K: int, N: int, seed: int, layer_id: int, device="cuda:0", f: int = 0):
+        self.M, self.K, self.N, self.seed, self.layer_id, self.f = M, K, N, seed, layer_id, f
+        self.t = {}
+        dims = {"MK": (M, K), "KN": (K, N), "MN": (M, N)}
+        groups = {"MK": ["X", "tX", "A", "tA"], "KN": ["Y", "tY", "B", "tB"],
+                  "MN": ["C", "tC", "R", "tR", "Z", "tZ"]}
+        for g, names in groups.items():
+            for n in names:
+                self.t[n] = [torch.zeros(dims[g] + (2,), dtype=torch.int64, device=device) for _ in range(2)]
+        self.t["E"] = torch.zeros((M, K, 2), dtype=torch.int64, device=device)
+        self.t["U"] = torch.zeros((K, N, 2), dtype=torch.int64, device=device)
+        self.t["D"] = torch.zeros((M, N, 2), dtype=torch.int64, device=device)
+        self.t["cvec"] = torch.zeros((3 * K + 10 * M, 2), dtype=torch.int64, device=device)
+
+    @staticmethod
+    def footprint_bytes(M: int, K: int, N: int) -> int:
+        return 16 * (9 * M * K + 9 * K * N + 13 * M * N + 3 * K + 10 * M)
+
+    def __getitem__(self, name):
+        return self.t[name]
+
+    def desc(self) -> CtLayerDesc:
+        return CtLayerDesc(self.M, self.K, self.N, self.f, 0, self.seed & MASK64, self.layer_id & MASK64)
+
+    def bufs(self) -> CtLayerBufs:
+        b = CtLayerBufs()
+        for n in BUF_PAIRS:
+            setattr(b, n, _P2(self.t[n][0].data_ptr(), self.t[n][1].data_ptr()))
+        for n in BUF_SINGLE:
+            setattr(b, n, self.t[n].data_ptr())
+        return b
+
+    # cvec views (element offsets of compacttag.h)
+    def cvec_parts(self):
+        M, K, c = self.M, self.K, self.t["cvec"]
+        o = {"Uc": (0, K), "tBc0": (K, K), "tBc1": (2 * K, K), "Dc": (3 * K, M), "EUc": (3 * K + M, M)}
+        base = 3 * K + 2 * M
+        for i, n in enumerate(["tCc0", "tCc1", "tRc0", "tRc1", "tZc0", "tZc1", "tDc0", "tDc1"]):
+            o[n] = (base + i * M, M)
+        return {n: c[a:a + l] for n, (a, l) in o.items()}
+
+
+def _arrays(layers):
+    n = len(layers)
+    D = (CtLayerDesc * n)(*[l.desc() for l in layers])
+    B = (CtLayerBufs * n)(*[l.bufs() for l in layers])
+    return n, D, B
+
+
+class Context:
+    """A libcompacttag context bound to one device and one HIP stream."""
+
+    def __init__(self, device: int = 0, key_seed: int = 0, stream=None, max_layers: int = 256):
+        self.lib = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: libcompacttag needs an MI355X (there is no CPU fallback)")
+        self.device = device
+        self.torch_device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.torch_device)
+        self.stream = stream
+        handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        p = CtParams(device, key_seed & MASK64, 64, 64, handle, max_layers)
+        h = ctypes.c_void_p()
+        s = self.lib.ct_create(ctypes.byref(h), ctypes.byref(p))
+        if s != CT_OK:
+            raise CtError(s, "ct_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ct_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, s: int, allow_abort: bool = False):
+        if s == CT_OK or (allow_abort and s == CT_ABORT):
+            return s
+        raise CtError(s, self.lib.ct_last_error(self.h).decode())
+
+    def key_shares(self):
+        out = (ctypes.c_uint64 * 2)()
+        self._check(self.lib.ct_key_shares(self.h, out))
+        return [int(out[0]), int(out[1])]
+
+    def gen_triple_tags(self, layers, with_inputs: bool = True):
+        n, D, B = _arrays(layers)
+        self._check(self.lib.ct_gen_triple_tags(self.h, D, B, n, int(with_inputs)))
+
+    def tag_linear(self, mode: int, layers):
+        n, D, B = _arrays(layers)
+        self._check(self.lib.ct_tag_linear(self.h, mode, D, B, n))
+
+    def mac_check_device(self, mode: int, layers, out: torch.Tensor):
+        """out: int64 device tensor of n * 14 entries (n ct_check_result records)."""
+        n, D, B = _arrays(layers)
+        assert out.numel() * 8 >= n * ctypes.sizeof(CtCheckResult)
+        self._check(self.lib.ct_mac_check_device(self.h, mode, D, B, n, ctypes.c_void_p(out.data_ptr())))
+
+    def mac_check(self, mode: int, layers):
+        n, D, B = _arrays(layers)
+        res = (CtCheckResult * n)()
+        s = self._check(self.lib.ct_mac_check(self.h, mode, D, B, n, res), allow_abort=True)
+        out = [_result(r) for r in res]
+        return s, out
+
+    @staticmethod
+    def decode_results(t: torch.Tensor, n: int):
+        """Decodes ct_check_result records copied back from mac_check_device."""
+        raw = t.detach().cpu().contiguous().numpy().tobytes()
+        arr = (CtCheckResult * n).from_buffer_copy(raw[: n * ctypes.sizeof(CtCheckResult)])
+        return [_result(r) for r in arr]

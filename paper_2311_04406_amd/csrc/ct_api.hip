@@ -1,0 +1,422 @@
+// ct_api.hip -- host side of the libcompacttag C ABI (see compacttag.h).
+//
+// A call validates its layers, writes one LayerDev record per layer (sizes,
+// key shares, generator stream keys, buffer pointers) and the GEMM problem
+// list into pinned staging memory, uploads them with one asynchronous copy on
+// the context stream, and enqueues the kernels of the requested phase.  The
+// staging area is reused only after the previous upload has completed (an
+// event), so a call never allocates.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "compacttag.h"
+#include "ct_internal.h"
+
+using namespace ct;
+
+struct ct_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint64_t delta[2] = {0, 0};
+    int max_layers = 0, max_probs = 0;
+    int num_cus = 256;
+    LayerDev *layers_dev = nullptr, *layers_host = nullptr;
+    GemmProb *gemm_dev = nullptr, *gemm_host = nullptr;
+    u128 *acc_dev = nullptr;
+    ct_check_result *res_dev = nullptr, *res_host = nullptr;
+    hipEvent_t upload_done = nullptr;
+    std::string err;
+};
+
+namespace {
+
+// ---- SplitMix64 (Steele, Lea, Flood 2014), host side ----
+uint64_t hmix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+uint64_t hkey(uint64_t seed, uint64_t layer_id, uint64_t purpose) {
+    return hmix(seed ^ hmix((layer_id << 16) | purpose));
+}
+uint64_t hdraw(uint64_t key, uint64_t i) { return hmix(key + (i + 1) * 0x9E3779B97F4A7C15ull); }
+
+ct_status fail(ct_ctx *c, ct_status s, const std::string &msg) {
+    if (c) c->err = msg;
+    return s;
+}
+ct_status hip_fail(ct_ctx *c, hipError_t e, const char *where) {
+    return fail(c, CT_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+#define HIPCHK(ctx, expr)                                          \
+    do {                                                           \
+        hipError_t e_ = (expr);                                    \
+        if (e_ != hipSuccess) return hip_fail((ctx), e_, #expr);   \
+    } while (0)
+
+bool aligned16(const void *p) { return p != nullptr && (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+enum Need : unsigned {
+    NEED_INPUTS = 1,   // X, tX, Y, tY
+    NEED_TRIPLE = 2,   // A, tA, B, tB, C, tC, R, tR
+    NEED_OUT = 4,      // Z, tZ, E, U, D
+    NEED_CVEC = 8,
+};
+
+ct_status validate(ct_ctx *c, const ct_layer_desc *L, const ct_layer_bufs *B, int n, unsigned need) {
+    if (!c) return CT_EINVAL;
+    if (!L || !B) return fail(c, CT_EINVAL, "null layer or buffer array");
+    if (n < 1 || n > c->max_layers)
+        return fail(c, CT_EINVAL, "n must be in [1, max_layers] (" + std::to_string(c->max_layers) + ")");
+    for (int l = 0; l < n; l++) {
+        const ct_layer_desc &d = L[l];
+        const std::string at = "layer " + std::to_string(l) + ": ";
+        if (d.M < 1 || d.K < 1 || d.N < 1) return fail(c, CT_EINVAL, at + "M, K, N must be >= 1");
+        if (d.M >= (1LL << 31) || d.K >= (1LL << 31) || d.N >= (1LL << 31))
+            return fail(c, CT_EINVAL, at + "M, K, N must be < 2^31");
+        if (d.f != 0) return fail(c, CT_EINVAL, at + "f must be 0 (truncation is not on this path)");
+        if (d.layer_id >= (1ULL << 48)) return fail(c, CT_EINVAL, at + "layer_id must be < 2^48");
+        const ct_layer_bufs &b = B[l];
+        auto chk = [&](const ct_u128 *p, const char *name) -> bool {
+            if (!aligned16(p)) {
+                c->err = at + "buffer " + name + " is null or not 16-byte aligned";
+                return false;
+            }
+            return true;
+        };
+        for (int p = 0; p < 2; p++) {
+            if (need & NEED_INPUTS)
+                if (!chk(b.X[p], "X") || !chk(b.tX[p], "tX") || !chk(b.Y[p], "Y") || !chk(b.tY[p], "tY"))
+                    return CT_EINVAL;
+            if (need & NEED_TRIPLE)
+                if (!chk(b.A[p], "A") || !chk(b.tA[p], "tA") || !chk(b.B[p], "B") || !chk(b.tB[p], "tB") ||
+                    !chk(b.C[p], "C") || !chk(b.tC[p], "tC") || !chk(b.R[p], "R") || !chk(b.tR[p], "tR"))
+                    return CT_EINVAL;
+            if (need & NEED_OUT)
+                if (!chk(b.Z[p], "Z") || !chk(b.tZ[p], "tZ")) return CT_EINVAL;
+        }
+        if (need & NEED_OUT)
+            if (!chk(b.E, "E") || !chk(b.U, "U") || !chk(b.D, "D")) return CT_EINVAL;
+        if (need & NEED_CVEC)
+            if (!chk(b.cvec, "cvec")) return CT_EINVAL;
+    }
+    return CT_OK;
+}
+
+void fill_layer(const ct_ctx *c, const ct_layer_desc &d, const ct_layer_bufs &b, int l, LayerDev &o) {
+    std::memset(&o, 0, sizeof(o));
+    o.M = d.M;
+    o.K = d.K;
+    o.N = d.N;
+    o.delta[0] = c->delta[0];
+    o.delta[1] = c->delta[1];
+    const uint64_t s = d.seed, id = d.layer_id;
+    o.key[K_LIFT_X] = hkey(s, id, P_LIFT_X);
+    o.key[K_LIFT_Y] = hkey(s, id, P_LIFT_Y);
+    o.key[K_LIFT_A] = hkey(s, id, P_LIFT_A);
+    o.key[K_LIFT_B] = hkey(s, id, P_LIFT_B);
+    o.key[K_LIFT_R] = hkey(s, id, P_LIFT_R);
+    for (int obj = 1; obj <= 6; obj++) {
+        o.key[K_VSH_X + obj - 1] = hkey(s, id, P_VSH + obj);
+        o.key[K_TSH_X + obj - 1] = hkey(s, id, P_TSH + obj);
+    }
+    o.key[K_CHI] = hkey(s, id, P_CHI);
+    o.key[K_CHIHAT] = hkey(s, id, P_CHIHAT);
+    o.key[K_CHI_E] = hkey(s, id, P_CHI_E);
+    o.key[K_CHI_U] = hkey(s, id, P_CHI_U);
+    o.key[K_CHI_D] = hkey(s, id, P_CHI_D);
+    auto cp = [](u128 *dst[2], ct_u128 *const src[2]) {
+        dst[0] = reinterpret_cast<u128 *>(src[0]);
+        dst[1] = reinterpret_cast<u128 *>(src[1]);
+    };
+    cp(o.X, b.X); cp(o.tX, b.tX); cp(o.A, b.A); cp(o.tA, b.tA);
+    cp(o.Y, b.Y); cp(o.tY, b.tY); cp(o.B, b.B); cp(o.tB, b.tB);
+    cp(o.C, b.C); cp(o.tC, b.tC); cp(o.R, b.R); cp(o.tR, b.tR);
+    cp(o.Z, b.Z); cp(o.tZ, b.tZ);
+    o.E = reinterpret_cast<u128 *>(b.E);
+    o.U = reinterpret_cast<u128 *>(b.U);
+    o.D = reinterpret_cast<u128 *>(b.D);
+    o.cvec = reinterpret_cast<u128 *>(b.cvec);
+    o.acc = c->acc_dev + (size_t)l * ACC_PER_LAYER;
+}
+
+struct Sizes {
+    int64_t mk = 0, kn = 0, mn = 0, m = 0, k = 0, kn_segs = 0, mn_segs = 0, cvec = 0;
+};
+
+Sizes max_sizes(const ct_layer_desc *L, int n) {
+    Sizes s;
+    const int64_t SEG = 1024;
+    for (int l = 0; l < n; l++) {
+        const ct_layer_desc &d = L[l];
+        s.mk = std::max(s.mk, d.M * d.K);
+        s.kn = std::max(s.kn, d.K * d.N);
+        s.mn = std::max(s.mn, d.M * d.N);
+        s.m = std::max(s.m, d.M);
+        s.k = std::max(s.k, d.K);
+        s.kn_segs = std::max(s.kn_segs, d.K * ((d.N + SEG - 1) / SEG));
+        s.mn_segs = std::max(s.mn_segs, d.M * ((d.N + SEG - 1) / SEG));
+        s.cvec = std::max(s.cvec, (int64_t)CT_CVEC_LEN(d.M, d.K));
+    }
+    return s;
+}
+
+// Waits for the previous upload, then stages layers (and GEMM problems).
+ct_status stage_layers(ct_ctx *c, const ct_layer_desc *L, const ct_layer_bufs *B, int n) {
+    HIPCHK(c, hipEventSynchronize(c->upload_done));
+    for (int l = 0; l < n; l++) fill_layer(c, L[l], B[l], l, c->layers_host[l]);
+    return CT_OK;
+}
+
+ct_status upload(ct_ctx *c, int n, int nprobs) {
+    HIPCHK(c, hipMemcpyAsync(c->layers_dev, c->layers_host, sizeof(LayerDev) * n, hipMemcpyHostToDevice,
+                             c->stream));
+    if (nprobs > 0)
+        HIPCHK(c, hipMemcpyAsync(c->gemm_dev, c->gemm_host, sizeof(GemmProb) * nprobs, hipMemcpyHostToDevice,
+                                 c->stream));
+    HIPCHK(c, hipEventRecord(c->upload_done, c->stream));
+    return CT_OK;
+}
+
+GemmProb make_prob(const u128 *L1, const u128 *L2, const u128 *R1, const u128 *R1b, uint64_t s, const u128 *R2,
+                   const u128 *base, u128 *out, const ct_layer_desc &d) {
+    GemmProb p;
+    std::memset(&p, 0, sizeof(p));
+    p.L1 = L1; p.L2 = L2; p.R1 = R1; p.R1b = (s != 0) ? R1b : nullptr; p.R2 = R2;
+    p.s = s; p.base = base; p.out = out;
+    p.M = (int32_t)d.M; p.N = (int32_t)d.N; p.K = (int32_t)d.K;
+    return p;
+}
+
+// Orders MFMA problems first, then skinny ones; assigns tiles and K splits.
+// Returns the number of MFMA problems; *total_tiles receives their tile count.
+constexpr int MAX_STEPS_PER_SPLIT = 255;  // keeps every int32 diagonal exact
+
+int plan_gemms(std::vector<GemmProb> &probs, int num_cus, int *total_tiles, bool *any_accum) {
+    std::stable_partition(probs.begin(), probs.end(), [](const GemmProb &p) { return p.N > SKINNY_MAX_N; });
+    int nm = 0;
+    int64_t base_tiles = 0;
+    for (auto &p : probs) {
+        if (p.N <= SKINNY_MAX_N) break;
+        nm++;
+        p.tiles_m = (p.M + 63) / 64;
+        p.tiles_n = (p.N + 63) / 64;
+        p.ksteps_seg = (p.K + 31) / 32;
+        p.nsteps = p.ksteps_seg * (p.L2 ? 2 : 1);
+        base_tiles += (int64_t)p.tiles_m * p.tiles_n;
+    }
+    int64_t want = base_tiles > 0 ? (num_cus + base_tiles - 1) / base_tiles : 1;
+    if (want < 1) want = 1;
+    int tile = 0;
+    *any_accum = false;
+    for (int i = 0; i < nm; i++) {
+        GemmProb &p = probs[i];
+        int64_t splits = std::min<int64_t>(want, std::max(1, p.nsteps / 8));
+        if (splits < 1) splits = 1;
+        int sps = (int)((p.nsteps + splits - 1) / splits);
+        if (sps > MAX_STEPS_PER_SPLIT) sps = MAX_STEPS_PER_SPLIT;
+        p.steps_per_split = sps;
+        p.splits = (p.nsteps + sps - 1) / sps;
+        p.accumulate = p.splits > 1 ? 1 : 0;
+        if (p.accumulate) *any_accum = true;
+        p.tile_begin = tile;
+        p.tiles = p.tiles_m * p.tiles_n * p.splits;
+        tile += p.tiles;
+    }
+    *total_tiles = tile;
+    return nm;
+}
+
+ct_status run_gemms(ct_ctx *c, int nprobs, int nm, int total_tiles) {
+    if (nm > 0) {
+        int grid = total_tiles;
+        HIPCHK(c, launch_gemm(c->gemm_dev, nm, total_tiles, grid, c->stream));
+    }
+    if (nprobs > nm) {
+        int max_rows = 0;
+        for (int i = nm; i < nprobs; i++) max_rows = std::max(max_rows, c->gemm_host[i].M);
+        HIPCHK(c, launch_skinny(c->gemm_dev + nm, nprobs - nm, max_rows, c->stream));
+    }
+    return CT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ct_status ct_create(ct_ctx **out, const ct_params *p) {
+    if (!out || !p) return CT_EINVAL;
+    *out = nullptr;
+    if (p->k_bits != 64 || p->s_bits != 64) return CT_EINVAL;
+    ct_ctx *c = new ct_ctx();
+    c->device = p->device;
+    c->stream = reinterpret_cast<hipStream_t>(p->hip_stream);
+    c->max_layers = p->max_layers > 0 ? p->max_layers : 256;
+    c->max_probs = 4 * c->max_layers;
+    for (int q = 0; q < 2; q++) c->delta[q] = hdraw(hkey(p->key_seed, GLOBAL_LAYER, P_KEY + q), 0);
+    auto bail = [&](hipError_t e, const char *what) {
+        std::fprintf(stderr, "ct_create: %s: %s\n", what, hipGetErrorString(e));
+        ct_destroy(c);
+        return CT_EDEVICE;
+    };
+    hipError_t e;
+    if ((e = hipSetDevice(c->device)) != hipSuccess) return bail(e, "hipSetDevice");
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cus > 0)
+        c->num_cus = cus;
+    if ((e = hipMalloc(&c->layers_dev, sizeof(LayerDev) * c->max_layers)) != hipSuccess) return bail(e, "hipMalloc");
+    if ((e = hipMalloc(&c->gemm_dev, sizeof(GemmProb) * c->max_probs)) != hipSuccess) return bail(e, "hipMalloc");
+    if ((e = hipMalloc(&c->acc_dev, sizeof(u128) * ACC_PER_LAYER * c->max_layers)) != hipSuccess)
+        return bail(e, "hipMalloc");
+    if ((e = hipMalloc(&c->res_dev, sizeof(ct_check_result) * c->max_layers)) != hipSuccess)
+        return bail(e, "hipMalloc");
+    if ((e = hipHostMalloc(&c->layers_host, sizeof(LayerDev) * c->max_layers, hipHostMallocDefault)) != hipSuccess)
+        return bail(e, "hipHostMalloc");
+    if ((e = hipHostMalloc(&c->gemm_host, sizeof(GemmProb) * c->max_probs, hipHostMallocDefault)) != hipSuccess)
+        return bail(e, "hipHostMalloc");
+    if ((e = hipHostMalloc(&c->res_host, sizeof(ct_check_result) * c->max_layers, hipHostMallocDefault)) !=
+        hipSuccess)
+        return bail(e, "hipHostMalloc");
+    if ((e = hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming)) != hipSuccess)
+        return bail(e, "hipEventCreate");
+    if ((e = hipEventRecord(c->upload_done, c->stream)) != hipSuccess) return bail(e, "hipEventRecord");
+    *out = c;
+    return CT_OK;
+}
+
+ct_status ct_destroy(ct_ctx *c) {
+    if (!c) return CT_EINVAL;
+    if (c->stream || c->layers_dev) hipStreamSynchronize(c->stream);
+    if (c->upload_done) hipEventDestroy(c->upload_done);
+    if (c->layers_dev) hipFree(c->layers_dev);
+    if (c->gemm_dev) hipFree(c->gemm_dev);
+    if (c->acc_dev) hipFree(c->acc_dev);
+    if (c->res_dev) hipFree(c->res_dev);
+    if (c->layers_host) hipHostFree(c->layers_host);
+    if (c->gemm_host) hipHostFree(c->gemm_host);
+    if (c->res_host) hipHostFree(c->res_host);
+    delete c;
+    return CT_OK;
+}
+
+ct_status ct_key_shares(const ct_ctx *c, uint64_t out[2]) {
+    if (!c || !out) return CT_EINVAL;
+    out[0] = c->delta[0];
+    out[1] = c->delta[1];
+    return CT_OK;
+}
+
+const char *ct_last_error(const ct_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+ct_status ct_gen_triple_tags(ct_ctx *c, const ct_layer_desc *L, const ct_layer_bufs *B, int n, int with_inputs) {
+    ct_status s = validate(c, L, B, n, NEED_TRIPLE | (with_inputs ? NEED_INPUTS : 0));
+    if (s != CT_OK) return s;
+    HIPCHK(c, hipSetDevice(c->device));
+    if ((s = stage_layers(c, L, B, n)) != CT_OK) return s;
+    std::vector<GemmProb> probs;
+    probs.reserve(n);
+    for (int l = 0; l < n; l++) {
+        const LayerDev &o = c->layers_host[l];
+        probs.push_back(make_prob(o.A[1], nullptr, o.B[1], nullptr, 0, nullptr, nullptr, o.C[1], L[l]));
+    }
+    int total_tiles = 0;
+    bool any_accum = false;
+    const int nm = plan_gemms(probs, c->num_cus, &total_tiles, &any_accum);
+    std::copy(probs.begin(), probs.end(), c->gemm_host);
+    if ((s = upload(c, n, (int)probs.size())) != CT_OK) return s;
+    const Sizes sz = max_sizes(L, n);
+    HIPCHK(c, launch_deal_lift(c->layers_dev, n, std::max(sz.mk, sz.kn), c->stream));
+    for (int i = 0; i < nm; i++)
+        if (probs[i].accumulate)
+            HIPCHK(c, launch_fill_zero(probs[i].out, (int64_t)probs[i].M * probs[i].N, c->stream));
+    if ((s = run_gemms(c, (int)probs.size(), nm, total_tiles)) != CT_OK) return s;
+    const int mask = (with_inputs ? ((1 << OBJ_X) | (1 << OBJ_Y)) : 0) | (1 << OBJ_A) | (1 << OBJ_B) |
+                     (1 << OBJ_C) | (1 << OBJ_R);
+    HIPCHK(c, launch_deal_auth(c->layers_dev, n, mask, std::max({sz.mk, sz.kn, sz.mn}), c->stream));
+    return CT_OK;
+}
+
+ct_status ct_tag_linear(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n) {
+    if (mode != CT_MODE_SPDZ2K && mode != CT_MODE_COMPACT) return fail(c, CT_EINVAL, "unknown mode");
+    const bool compact = mode == CT_MODE_COMPACT;
+    ct_status s = validate(c, L, B, n, NEED_INPUTS | NEED_TRIPLE | NEED_OUT | (compact ? NEED_CVEC : 0));
+    if (s != CT_OK) return s;
+    HIPCHK(c, hipSetDevice(c->device));
+    if ((s = stage_layers(c, L, B, n)) != CT_OK) return s;
+
+    // Output-share products of Eq. (2), both parties, folded into two-segment
+    // products:  [Z]_0 = [C]_0 + E ([B]_0 + U) + [A]_0 U,  [Z]_1 = [C]_1 + E [B]_1 + [A]_1 U.
+    // SPDZ2k tags of Eq. (3):  [tZ]_p = [tC]_p + E ([tB]_p + [Delta]_p U) + [tA]_p U.
+    std::vector<GemmProb> probs;
+    probs.reserve(4 * n);
+    for (int l = 0; l < n; l++) {
+        const LayerDev &o = c->layers_host[l];
+        probs.push_back(make_prob(o.E, o.A[0], o.B[0], o.U, 1, o.U, o.C[0], o.Z[0], L[l]));
+        probs.push_back(make_prob(o.E, o.A[1], o.B[1], nullptr, 0, o.U, o.C[1], o.Z[1], L[l]));
+        if (!compact) {
+            probs.push_back(make_prob(o.E, o.tA[0], o.tB[0], o.U, c->delta[0], o.U, o.tC[0], o.tZ[0], L[l]));
+            probs.push_back(make_prob(o.E, o.tA[1], o.tB[1], o.U, c->delta[1], o.U, o.tC[1], o.tZ[1], L[l]));
+        }
+    }
+    int total_tiles = 0;
+    bool any_accum = false;
+    const int nm = plan_gemms(probs, c->num_cus, &total_tiles, &any_accum);
+    std::copy(probs.begin(), probs.end(), c->gemm_host);
+    if ((s = upload(c, n, (int)probs.size())) != CT_OK) return s;
+
+    const Sizes sz = max_sizes(L, n);
+    if (compact) HIPCHK(c, launch_zero_acc(c->layers_dev, n, 1, sz.cvec, c->stream));
+    HIPCHK(c, launch_open(c->layers_dev, n, std::max(sz.mk, sz.kn), c->stream));
+    if (compact) HIPCHK(c, launch_compress_kn(c->layers_dev, n, sz.k, sz.kn_segs, c->stream));
+    if (any_accum) HIPCHK(c, launch_copy_base(c->layers_dev, n, mode, sz.mn, c->stream));
+    if ((s = run_gemms(c, (int)probs.size(), nm, total_tiles)) != CT_OK) return s;
+    if (compact) {
+        HIPCHK(c, launch_post_compact(c->layers_dev, n, sz.m, sz.mn_segs, c->stream));
+        HIPCHK(c, launch_compact_tag(c->layers_dev, n, sz.m, c->stream));
+    } else {
+        HIPCHK(c, launch_open_d(c->layers_dev, n, sz.mn, c->stream));
+    }
+    return CT_OK;
+}
+
+ct_status ct_mac_check_device(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
+                              ct_check_result *out_dev) {
+    if (mode != CT_MODE_SPDZ2K && mode != CT_MODE_COMPACT) return fail(c, CT_EINVAL, "unknown mode");
+    const bool compact = mode == CT_MODE_COMPACT;
+    ct_status s = validate(c, L, B, n, NEED_INPUTS | NEED_TRIPLE | NEED_OUT | (compact ? NEED_CVEC : 0));
+    if (s != CT_OK) return s;
+    if (!aligned16(out_dev)) return fail(c, CT_EINVAL, "out_dev is null or misaligned");
+    HIPCHK(c, hipSetDevice(c->device));
+    if ((s = stage_layers(c, L, B, n)) != CT_OK) return s;
+    if ((s = upload(c, n, 0)) != CT_OK) return s;
+    const Sizes sz = max_sizes(L, n);
+    HIPCHK(c, launch_zero_acc(c->layers_dev, n, 2, 0, c->stream));
+    const int mask = compact ? 0x3 : 0x7;
+    HIPCHK(c, launch_check_batch(c->layers_dev, n, mask, std::max({sz.mk, sz.kn, sz.mn}), c->stream));
+    if (compact) HIPCHK(c, launch_check_compact(c->layers_dev, n, c->stream));
+    HIPCHK(c, launch_finalize(c->layers_dev, n, mode, out_dev, c->stream));
+    return CT_OK;
+}
+
+ct_status ct_mac_check(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
+                       ct_check_result *out) {
+    if (!c) return CT_EINVAL;
+    if (!out) return fail(c, CT_EINVAL, "null result array");
+    ct_status s = ct_mac_check_device(c, mode, L, B, n, c->res_dev);
+    if (s != CT_OK) return s;
+    HIPCHK(c, hipMemcpyAsync(c->res_host, c->res_dev, sizeof(ct_check_result) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    bool ok = true;
+    for (int l = 0; l < n; l++) {
+        out[l] = c->res_host[l];
+        ok = ok && c->res_host[l].accept;
+    }
+    return ok ? CT_OK : CT_ABORT;
+}
+
+}  // extern "C"

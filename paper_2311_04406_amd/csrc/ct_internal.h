@@ -1,0 +1,99 @@
+// ct_internal.h -- library-internal types shared by the host side of
+// libcompacttag and its HIP kernels.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "compacttag.h"
+
+namespace ct {
+
+// Element of Z_{2^128}: value = lo + 2^64 hi (same layout as ct_u128).
+struct u128 {
+    uint64_t lo, hi;
+};
+
+// Generator stream purposes; stream = (layer_id << 16) | purpose.
+enum Purpose : uint32_t {
+    P_LIFT_X = 0x01, P_LIFT_Y = 0x02, P_LIFT_A = 0x03, P_LIFT_B = 0x04, P_LIFT_R = 0x05,
+    P_VSH = 0x10,  // + object 1..6
+    P_TSH = 0x20,  // + object 1..6
+    P_CHI = 0x30, P_CHIHAT = 0x31, P_CHI_E = 0x32, P_CHI_U = 0x33, P_CHI_D = 0x34,
+    P_KEY = 0x40,  // + party, on the global layer id 0xFFFF
+};
+enum Obj : int { OBJ_X = 1, OBJ_Y = 2, OBJ_A = 3, OBJ_B = 4, OBJ_C = 5, OBJ_R = 6 };
+constexpr uint64_t GLOBAL_LAYER = 0xFFFF;
+
+// Index of each generator key in LayerDev::key.
+enum KeyIdx : int {
+    K_LIFT_X = 0, K_LIFT_Y, K_LIFT_A, K_LIFT_B, K_LIFT_R,
+    K_VSH_X, K_VSH_Y, K_VSH_A, K_VSH_B, K_VSH_C, K_VSH_R,
+    K_TSH_X, K_TSH_Y, K_TSH_A, K_TSH_B, K_TSH_C, K_TSH_R,
+    K_CHI, K_CHIHAT, K_CHI_E, K_CHI_U, K_CHI_D,
+    K_COUNT
+};
+
+// Per-layer descriptor as the kernels see it (device memory).
+struct LayerDev {
+    int64_t M, K, N;
+    uint64_t delta[2];          // key shares
+    uint64_t key[K_COUNT];      // SplitMix64 stream keys
+    u128 *X[2], *tX[2], *A[2], *tA[2];
+    u128 *Y[2], *tY[2], *B[2], *tB[2];
+    u128 *C[2], *tC[2], *R[2], *tR[2], *Z[2], *tZ[2];
+    u128 *E, *U, *D, *cvec;
+    u128 *acc;                  // check accumulators, ACC_PER_LAYER entries (context scratch)
+};
+
+// Check accumulators per layer: for W in (E, U, D): [sum chi*tW_0, sum chi*tW_1, sum chi*W].
+constexpr int ACC_PER_LAYER = 9;
+
+// cvec offsets (elements), see compacttag.h
+struct CvecOff {
+    int64_t Uc, tBc0, tBc1, Dc, EUc, tCc0, tCc1, tRc0, tRc1, tZc0, tZc1, tDc0, tDc1;
+};
+__host__ __device__ inline CvecOff cvec_off(int64_t M, int64_t K) {
+    CvecOff o;
+    o.Uc = 0; o.tBc0 = K; o.tBc1 = 2 * K; o.Dc = 3 * K; o.EUc = 3 * K + M;
+    o.tCc0 = 3 * K + 2 * M; o.tCc1 = 3 * K + 3 * M; o.tRc0 = 3 * K + 4 * M; o.tRc1 = 3 * K + 5 * M;
+    o.tZc0 = 3 * K + 6 * M; o.tZc1 = 3 * K + 7 * M; o.tDc0 = 3 * K + 8 * M; o.tDc1 = 3 * K + 9 * M;
+    return o;
+}
+
+// One ring GEMM problem:
+//   out (+)= base + L1 * (R1 + s * R1b) + L2 * R2     (all mod 2^128)
+// L1, L2: M x K (row-major, ld K); R1, R1b, R2: K x N (ld N); out, base: M x N.
+// L2 == nullptr: single segment.  R1b == nullptr or s == 0: no fold term.
+// accumulate != 0: out already holds base and partial sums are added atomically.
+struct GemmProb {
+    const u128 *L1, *L2, *R1, *R1b, *R2, *base;
+    u128 *out;
+    uint64_t s;
+    int32_t M, N, K, accumulate;
+    int32_t tiles_m, tiles_n, splits, steps_per_split;  // steps are 32-wide K slices
+    int32_t ksteps_seg, nsteps, tile_begin, tiles;
+};
+
+// Skinny problem for N <= SKINNY_MAX_N: same algebra, VALU kernel, one wave per row.
+constexpr int SKINNY_MAX_N = 8;
+
+// ---- launchers (defined in the .hip files) ----
+hipError_t launch_gemm(const GemmProb *probs_dev, int nprobs, int total_tiles, int grid, hipStream_t st);
+hipError_t launch_skinny(const GemmProb *probs_dev, int nprobs, int max_rows, hipStream_t st);
+
+hipError_t launch_fill_zero(u128 *p, int64_t n, hipStream_t st);
+hipError_t launch_deal_lift(const LayerDev *L, int n, int64_t max_elems, hipStream_t st);
+hipError_t launch_deal_auth(const LayerDev *L, int n, int obj, int64_t max_elems, hipStream_t st);
+hipError_t launch_open(const LayerDev *L, int n, int64_t max_elems, hipStream_t st);
+hipError_t launch_copy_base(const LayerDev *L, int n, int mode, int64_t max_elems, hipStream_t st);
+hipError_t launch_compress_kn(const LayerDev *L, int n, int64_t max_rows, int64_t max_segs, hipStream_t st);
+hipError_t launch_post_compact(const LayerDev *L, int n, int64_t max_rows, int64_t max_segs, hipStream_t st);
+hipError_t launch_open_d(const LayerDev *L, int n, int64_t max_elems, hipStream_t st);
+hipError_t launch_compact_tag(const LayerDev *L, int n, int64_t max_rows, hipStream_t st);
+hipError_t launch_zero_acc(const LayerDev *L, int n, int mode, int64_t max_rows, hipStream_t st);
+hipError_t launch_check_batch(const LayerDev *L, int n, int which, int64_t max_elems, hipStream_t st);
+hipError_t launch_check_compact(const LayerDev *L, int n, hipStream_t st);
+hipError_t launch_finalize(const LayerDev *L, int n, int mode, ct_check_result *out, hipStream_t st);
+
+}  // namespace ct

@@ -1,0 +1,85 @@
+"""Helpers of the GPU parity tests: run layers through the C ABI and compare
+them element by element with the oracle (both sides start from the same
+seeds; no value crosses from the GPU path into the oracle)."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import torch
+
+import oracle as O
+
+DEALT = ["X", "tX", "A", "tA", "Y", "tY", "B", "tB", "C", "tC", "R", "tR"]
+MK = {"X", "tX", "A", "tA", "E"}
+KN = {"Y", "tY", "B", "tB", "U"}
+MN = {"C", "tC", "R", "tR", "Z", "tZ", "D"}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def to_np(t: torch.Tensor) -> np.ndarray:
+    return t.detach().contiguous().cpu().numpy().view(np.uint64)
+
+
+def gpu_layers(ctx, specs, device="cuda:0"):
+    from paper_2311_04406_amd import Layer
+    return [Layer(s.M, s.K, s.N, s.seed, s.layer_id, device=device) for s in specs]
+
+
+def oracle_run(mode, spec, key_seed, r0=0, r1=None):
+    return O.run_layer(mode, spec.M, spec.K, spec.N, spec.seed, spec.layer_id, key_seed, r0, r1)
+
+
+def _rows(name, arr, r0, r1):
+    if name in MK or name in MN:
+        return arr[r0:r1]
+    return arr
+
+
+def compare_layer(gl, ol, mode, r0=0, r1=None, dealt=True, what=""):
+    """Bit-exact comparison of every array of one layer (rows [r0, r1) of the
+    M-indexed ones)."""
+    if r1 is None:
+        r1 = gl.M
+    names = (DEALT if dealt else []) + ["Z", "tZ"]
+    for n in names:
+        for p in range(2):
+            g = to_np(_rows(n, gl[n][p], r0, r1))
+            o = ol[n][p]
+            assert g.shape == o.shape, (what, n, g.shape, o.shape)
+            if not np.array_equal(g, o):
+                bad = np.argwhere((g != o).any(axis=-1))
+                raise AssertionError(f"{what}: {n}[{p}] differs at {len(bad)} places, first {bad[:3].tolist()}")
+    for n in ("E", "U", "D"):
+        g = to_np(_rows(n, gl[n], r0, r1))
+        if not np.array_equal(g, ol[n]):
+            bad = np.argwhere((g != ol[n]).any(axis=-1))
+            raise AssertionError(f"{what}: {n} differs at {len(bad)} places, first {bad[:3].tolist()}")
+    if mode == O.MODE_COMPACT:
+        parts = {k: to_np(v) for k, v in gl.cvec_parts().items()}
+        pairs = [("Uc", ol["Uc"]), ("tBc0", ol["tBc"][0]), ("tBc1", ol["tBc"][1])]
+        for n, on in [("Dc", "Dc"), ("EUc", "EUc")]:
+            pairs.append((n, ol[on]))
+        for base in ("tCc", "tRc", "tZc", "tDc"):
+            for p in range(2):
+                pairs.append((f"{base}{p}", ol[base][p]))
+        for n, o in pairs:
+            g = parts[n]
+            if n not in ("Uc", "tBc0", "tBc1"):
+                g = g[r0:r1]
+            assert np.array_equal(g, o), (what, n)
+
+
+def compare_cs(gres, ol, which=(0, 1, 2), what=""):
+    for w in which:
+        for p in range(2):
+            assert gres.cs[w][p] == O.u128(ol.cs[w, p]), (what, w, p)
+
+
+def free():
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()

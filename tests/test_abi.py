@@ -1,0 +1,103 @@
+"""Host-side checks of the C ABI (no GPU needed): the library builds for gfx950,
+loads, exports every entry point the header declares, the ctypes mirror of
+each structure matches the header's layout, and argument validation that
+happens before any device call rejects bad input."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "compacttag.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2311_04406_amd import binding, build
+    if not os.path.exists(binding.LIB_PATH):
+        build.build()
+    return binding.load()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:ct_status|const char \*)\s*(ct_\w+)\s*\(", src, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for f in ("ct_create", "ct_destroy", "ct_gen_triple_tags", "ct_tag_linear", "ct_mac_check",
+              "ct_mac_check_device", "ct_key_shares", "ct_last_error"):
+        assert f in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2311_04406_amd import binding
+    out = subprocess.run(["nm", "-D", "--defined-only", binding.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\sT\s(ct_\w+)$", out, re.M))
+    for f in declared_functions():
+        assert f in exported, f
+        assert hasattr(lib, f)
+
+
+def test_library_is_built_for_gfx950():
+    from paper_2311_04406_amd import binding
+    data = open(binding.LIB_PATH, "rb").read()
+    assert b"gfx950" in data
+
+
+def test_struct_layouts_match_header():
+    from paper_2311_04406_amd import binding as b
+    prog = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "compacttag.h"
+int main(void) {
+  printf("%zu %zu %zu %zu\n", sizeof(ct_params), sizeof(ct_layer_desc), sizeof(ct_layer_bufs), sizeof(ct_check_result));
+  printf("%zu %zu %zu %zu\n", offsetof(ct_params, hip_stream), offsetof(ct_params, max_layers),
+         offsetof(ct_layer_desc, seed), offsetof(ct_layer_desc, layer_id));
+  printf("%zu %zu %zu\n", offsetof(ct_layer_bufs, E), offsetof(ct_layer_bufs, cvec), offsetof(ct_check_result, accept));
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "l.c")
+        open(c, "w").write(prog)
+        exe = os.path.join(d, "l")
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        vals = [int(x) for x in subprocess.check_output([exe]).split()]
+    got = [ctypes.sizeof(b.CtParams), ctypes.sizeof(b.CtLayerDesc), ctypes.sizeof(b.CtLayerBufs),
+           ctypes.sizeof(b.CtCheckResult),
+           b.CtParams.hip_stream.offset, b.CtParams.max_layers.offset, b.CtLayerDesc.seed.offset,
+           b.CtLayerDesc.layer_id.offset, b.CtLayerBufs.E.offset, b.CtLayerBufs.cvec.offset,
+           b.CtCheckResult.accept.offset]
+    assert got == vals
+
+
+def test_validation_before_device_calls(lib):
+    from paper_2311_04406_amd import binding as b
+    h = ctypes.c_void_p()
+    # k, s other than 64 are rejected before the device is touched
+    p = b.CtParams(0, 1, 32, 32, None, 4)
+    assert lib.ct_create(ctypes.byref(h), ctypes.byref(p)) == b.CT_EINVAL
+    assert lib.ct_create(None, ctypes.byref(p)) == b.CT_EINVAL
+    assert lib.ct_destroy(None) == b.CT_EINVAL
+    assert lib.ct_key_shares(None, None) == b.CT_EINVAL
+    assert lib.ct_tag_linear(None, 1, None, None, 1) == b.CT_EINVAL
+    assert lib.ct_mac_check(None, 1, None, None, 1, None) == b.CT_EINVAL
+    assert lib.ct_gen_triple_tags(None, None, None, 1, 1) == b.CT_EINVAL
+    assert lib.ct_last_error(None) == b"null context"
+
+
+def test_product_path_has_no_oracle_dependency():
+    """The package never imports or links the oracle (no CPU fallback)."""
+    pkg = os.path.join(ROOT, "paper_2311_04406_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in src and "from oracle" not in src, f
+                assert "ct_oracle" not in src, f

@@ -1,0 +1,117 @@
+"""GPU parity: the HIP path, called through the C ABI, against the CPU oracle,
+bit-exact (everything is integer arithmetic mod 2^128)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from gpu_util import compare_cs, compare_layer, free, gpu_layers, oracle_run, say, to_np
+
+pytestmark = pytest.mark.gpu
+
+KEY = 7
+MODES = [O.MODE_SPDZ2K, O.MODE_COMPACT]
+
+
+class Spec:
+    def __init__(self, M, K, N, seed=1, layer_id=1, name=""):
+        self.M, self.K, self.N, self.seed, self.layer_id, self.name = M, K, N, seed, layer_id, name or f"{M}x{K}x{N}"
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    O.build()
+    from paper_2311_04406_amd import Context
+    c = Context(device=0, key_seed=KEY)
+    yield c
+    c.close()
+
+
+def run_all(ctx, mode, specs):
+    layers = gpu_layers(ctx, specs)
+    ctx.gen_triple_tags(layers)
+    ctx.tag_linear(mode, layers)
+    status, res = ctx.mac_check(mode, layers)
+    torch.cuda.synchronize()
+    return layers, status, res
+
+
+# shapes that span several tiles, ragged edges in every dimension, the
+# skinny path (N <= 8), K not a multiple of 32 and K long enough to be split
+SMALL = [Spec(1, 1, 1), Spec(3, 5, 7, 2, 2), Spec(64, 128, 32, 1000, 1, "fc64x128x32"), Spec(70, 100, 130, 3, 3),
+         Spec(130, 33, 65, 4, 4), Spec(5, 300, 9, 5, 5), Spec(17, 40, 8, 6, 6), Spec(33, 70, 1, 7, 7),
+         Spec(96, 600, 200, 8, 8), Spec(40, 2100, 70, 9, 9), Spec(65, 4500, 66, 10, 10)]
+
+
+def test_key_shares(ctx):
+    assert ctx.key_shares() == [int(x) for x in O.key_shares(KEY)]
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("spec", SMALL, ids=lambda s: s.name)
+def test_small_layers_bit_exact(ctx, mode, spec):
+    say(f"[parity] mode={mode} shape={spec.name}")
+    layers, status, res = run_all(ctx, mode, [spec])
+    ol = oracle_run(mode, spec, KEY)
+    compare_layer(layers[0], ol, mode, what=spec.name)
+    compare_cs(res[0], ol, what=spec.name)
+    assert status == 0 and res[0].accept and ol.accept()
+    free()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_several_layers_in_one_call(ctx, mode):
+    specs = [SMALL[3], SMALL[5], SMALL[7], Spec(64, 128, 32, 11, 12)]
+    say(f"[parity] multi-layer mode={mode}")
+    layers, status, res = run_all(ctx, mode, specs)
+    for s, gl, r in zip(specs, layers, res):
+        ol = oracle_run(mode, s, KEY)
+        compare_layer(gl, ol, mode, what=s.name)
+        compare_cs(r, ol, what=s.name)
+    assert status == 0
+    free()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_repeat_runs_identical(ctx, mode):
+    """Determinism across launches (cross-workgroup sums are exact)."""
+    s = Spec(96, 600, 200, 8, 8)
+    layers, _, r1 = run_all(ctx, mode, [s])
+    z1 = [to_np(layers[0]["Z"][p]) for p in range(2)] + [to_np(layers[0]["tZ"][p]) for p in range(2)]
+    ctx.tag_linear(mode, layers)
+    _, r2 = ctx.mac_check(mode, layers)
+    z2 = [to_np(layers[0]["Z"][p]) for p in range(2)] + [to_np(layers[0]["tZ"][p]) for p in range(2)]
+    assert all(np.array_equal(a, b) for a, b in zip(z1, z2))
+    assert r1[0].cs == r2[0].cs
+    free()
+
+
+TAMPER = [("X", 1, 5, 0), ("tA", 0, 63, 0), ("B", 0, 31, 1), ("tY", 1, 0, 1), ("C", 1, 17, 2), ("tR", 0, 40, 2)]
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("target", TAMPER, ids=lambda t: f"{t[0]}{t[1]}b{t[2]}")
+def test_flipped_share_bit_aborts(ctx, mode, target):
+    """One flipped bit in one party's share makes ct_mac_check return CT_ABORT,
+    with the same check values as the oracle given the same flip."""
+    from paper_2311_04406_amd import CT_ABORT
+    name, party, bit, w = target
+    s = Spec(40, 70, 50, 21, 3)
+    say(f"[tamper] mode={mode} {name}[{party}] bit {bit}")
+    layers = gpu_layers(ctx, [s])
+    ctx.gen_triple_tags(layers)
+    t = layers[0][name][party]
+    flat = t.view(-1, 2)
+    idx = 37 % flat.shape[0]
+    limb = 0 if bit < 64 else 1
+    flat[idx, limb] ^= (1 << (bit % 64)) if bit % 64 < 63 else -(1 << 63)
+    ctx.tag_linear(mode, layers)
+    status, res = ctx.mac_check(mode, layers)
+    assert status == CT_ABORT and not res[0].accept
+    assert res[0].sums()[w] != 0
+    ol = O.OracleLayer(s.M, s.K, s.N, s.seed, s.layer_id, KEY).deal()
+    ol[name][party].reshape(-1, 2)[idx, limb] ^= np.uint64(1 << (bit % 64))
+    ol.online(mode).check(mode)
+    compare_layer(layers[0], ol, mode, what="tampered")
+    compare_cs(res[0], ol, what="tampered")
+    free()
