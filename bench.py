@@ -1,0 +1,275 @@
+#!/usr/bin/env python3
+"""Benchmark of the linear-layer hot path on one MI355X.
+
+A step is one pass of the whole hot path over one batch of layers: the online
+phase (ct_tag_linear: open E and U, output-share products, tags) and the
+verification (ct_mac_check_device: batch tag checks of E and U, check of D),
+for every layer of the workload in one call.  The dealer runs once before the
+timed region and is not timed.  Inputs are synthetic (uniform ring elements
+from the dealer's seeded generator) and resident in HBM.
+
+Prints one JSON line.  Default workload: the CNN layer set (four VGG-style 3x3
+convolutions as im2col products and the 25088 -> 4096 classifier layer at
+batch 1), CompactTag protocol, with the SPDZ2k protocol and per-layer
+launches measured beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "tagged ring-MACs/sec (Z_2^64 GEMM Gops) + p50/p99 tag latency, 1 MI355X"
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+INT8_PEAK_TOPS = 5000.0      # MI355X dense int8 MFMA, 5.0 POP/s
+DIGIT_PAIRS = 136            # int8 digit products per 128-bit ring multiply-accumulate
+
+
+def stage_work(stage: str, specs, mode: str):
+    """Algorithmic work of one launch of a kernel stage over the layer batch:
+    ("hbm", bytes) or ("mfma", int8 ops).  Per-element figures (16 B per
+    Z_2^128 element):
+      open 80 B per element of MK + KN (4 share reads, 1 write)
+      compress_kn 48 B per KN element (U, tB_0, tB_1)
+      copy_base 32 B per MN element per array (2 arrays, 4 in SPDZ2k)
+      ring_gemm 2 * 136 int8 ops per ring MAC (4 MKN ring MACs per layer,
+        8 in SPDZ2k), layers with N > 8
+      skinny 16 B per element of the distinct M x K operands (E, A_0, A_1,
+        and tA_0, tA_1 in SPDZ2k), layers with N <= 8
+      post_compact 176 B per MN element (8 reads, 3 writes)
+      compact_tag 48 B per MK element (E, tA_0, tA_1)
+      open_d 80 B per MN element
+      check_batch 80 B per element of MK + KN (+ MN in SPDZ2k)."""
+    spdz = mode == "spdz2k"
+    tot = 0
+    for s in specs:
+        M, K, N = s.M, s.K, s.N
+        mk, kn, mn = M * K, K * N, M * N
+        if stage == "open":
+            tot += 80 * (mk + kn)
+        elif stage == "compress_kn":
+            tot += 48 * kn
+        elif stage == "copy_base":
+            tot += 32 * mn * (4 if spdz else 2)
+        elif stage == "ring_gemm":
+            if N > 8:
+                tot += 2 * DIGIT_PAIRS * (8 if spdz else 4) * M * K * N
+        elif stage == "skinny":
+            if N <= 8:
+                tot += 16 * mk * (5 if spdz else 3)
+        elif stage == "post_compact":
+            tot += 176 * mn
+        elif stage == "compact_tag":
+            tot += 48 * mk
+        elif stage == "open_d":
+            tot += 80 * mn
+        elif stage == "check_batch":
+            tot += 80 * (mk + kn + (mn if spdz else 0))
+        else:
+            return None
+    return ("mfma" if stage == "ring_gemm" else "hbm", tot)
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2311_04406_amd", "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        e = d.get(workload, {}).get(kernel)
+        if e and e.get("source_digest") == source_digest():
+            return e["bytes_per_launch"]
+    except Exception:
+        return None
+    return None
+
+
+def pct(v, q):
+    v = sorted(v)
+    if not v:
+        return None
+    i = min(len(v) - 1, max(0, int(round(q / 100.0 * (len(v) - 1)))))
+    return v[i]
+
+
+def run_steps(ctx, mode_id, layer_groups, out_dev, steps, warmup, torch, timing=False):
+    """Runs warmup + steps; each step enqueues every group (one call per group).
+    Returns (total seconds, per-step ms list)."""
+    def step():
+        for g in layer_groups:
+            ctx.tag_linear(mode_id, g)
+            ctx.mac_check_device(mode_id, g, out_dev)
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    if timing:
+        ctx.set_timing(True)
+        ctx.stage_times()  # reset
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        evs[i][0].record()
+        step()
+        evs[i][1].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    per = [a.elapsed_time(b) for a, b in evs]
+    stages = None
+    if timing:
+        stages = ctx.stage_times()
+        ctx.set_timing(False)
+    return t1 - t0, per, stages
+
+
+def cpu_baseline(specs):
+    """The oracle (single-threaded C, -O2) on a bounded sample of the workload:
+    every layer with M * K * N below 2^28 in full, and the first 2048 rows of
+    any larger one; online phase + verification in the CompactTag protocol
+    (the dealer is untimed)."""
+    import oracle as O
+    from paper_2311_04406_amd.workloads import KEY_SEED
+    O.build()
+    parts = []
+    for s in specs:
+        if s.mkn < (1 << 28):
+            parts.append((s, 0, None))
+        else:
+            parts.append((s, 0, min(s.M, 2048)))
+        if len(parts) >= 6:
+            break
+    t_tot, macs = 0.0, 0
+    for s, r0, r1 in parts:
+        L = O.OracleLayer(s.M, s.K, s.N, s.seed, s.layer_id, KEY_SEED, r0, r1).deal()
+        t0 = time.perf_counter()
+        L.online(O.MODE_COMPACT).check(O.MODE_COMPACT)
+        t_tot += time.perf_counter() - t0
+        rows = (r1 if r1 is not None else s.M) - r0
+        macs += rows * s.K * s.N
+        if r1 is None:
+            assert L.accept()
+    desc = " + ".join(f"{s.name} rows [{r0},{r1 if r1 is not None else s.M})" for s, r0, r1 in parts)
+    return {"value": macs / t_tot / 1e9, "unit": "G ring-MAC/s", "cores": 1, "kind": "oracle",
+            "sample": f"{desc}; CompactTag online phase + verification, single-threaded C oracle; {t_tot:.1f} s",
+            "seconds": t_tot, "ring_macs": macs}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="cnn", choices=["cnn", "transformer", "batched", "fc_small"])
+    ap.add_argument("--mode", default="compact", choices=["compact", "spdz2k"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the SPDZ2k and per-layer comparison runs")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the layers shard across GPUs by layer or by output columns, which is not built here",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2311_04406_amd import MODE_COMPACT, MODE_SPDZ2K, Context, Layer, workloads
+
+    specs = workloads.CONFIGS[args.config]()
+    mode_id = MODE_COMPACT if args.mode == "compact" else MODE_SPDZ2K
+    ctx = Context(device=0, key_seed=workloads.KEY_SEED, max_layers=max(256, len(specs)))
+    layers = [Layer(s.M, s.K, s.N, s.seed, s.layer_id, device="cuda:0") for s in specs]
+    print(f"[bench] config {args.config}: {len(specs)} layers, dealer ...", file=sys.stderr, flush=True)
+    ctx.gen_triple_tags(layers)
+    torch.cuda.synchronize()
+    out_dev = torch.zeros(len(layers) * 14, dtype=torch.int64, device="cuda:0")
+    mkn = sum(s.mkn for s in specs)
+
+    print(f"[bench] timed {args.mode}: {args.warmup} warmup + {args.steps} steps", file=sys.stderr, flush=True)
+    T, per, stages = run_steps(ctx, mode_id, [layers], out_dev, args.steps, args.warmup, torch, timing=True)
+    res = Context.decode_results(out_dev, len(layers))
+    if not all(r.accept for r in res):
+        print("[bench] ERROR: an honest run was rejected", file=sys.stderr)
+        sys.exit(1)
+    ms = T / args.steps * 1e3
+    value = mkn * args.steps / T / 1e9
+
+    # per-stage figures and the dominant kernel's roofline
+    stage_rows = {}
+    for name, (tot_ms, n) in stages.items():
+        avg = tot_ms / max(n, 1)
+        w = stage_work(name, specs, args.mode)
+        row = {"ms_per_launch": round(avg, 5), "launches": n, "share_of_step": round(tot_ms / args.steps / ms, 4)}
+        if w is not None and w[1] > 0:
+            bound, units = w
+            if bound == "hbm":
+                row.update(bound="hbm", achieved_GBps=round(units / (avg * 1e-3) / 1e9, 1),
+                           frac=round(units / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), algorithmic_bytes=units)
+            else:
+                row.update(bound="mfma", achieved_TOPS=round(units / (avg * 1e-3) / 1e12, 1),
+                           frac=round(units / (avg * 1e-3) / 1e12 / INT8_PEAK_TOPS, 4), int8_ops=units)
+        stage_rows[name] = row
+    ranked = sorted(((k, v) for k, v in stage_rows.items() if "bound" in v),
+                    key=lambda kv: -kv[1]["ms_per_launch"] * kv[1]["launches"])
+    roofline = None
+    if ranked:
+        k, v = ranked[0]
+        if v["bound"] == "hbm":
+            roofline = {"kernel": k, "bound": "hbm", "achieved": v["achieved_GBps"], "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": v["frac"]}
+        else:
+            roofline = {"kernel": k, "bound": "mfma", "achieved": v["achieved_TOPS"], "peak": INT8_PEAK_TOPS,
+                        "unit": "TOPS (int8)", "frac": v["frac"]}
+        roofline["traffic"] = measured_traffic(k, f"{args.config}/{args.mode}")
+        roofline["share_of_step"] = v["share_of_step"]
+
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "G ring-MAC/s (Z_2^64 GEMM Gops, 1 op = 1 MAC)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "p50_ms": round(pct(per, 50), 4), "p99_ms": round(pct(per, 99), 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u128",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: " + ", ".join(f"{s.name} ({s.M}x{s.K}x{s.N})" for s in specs)
+                   if len(specs) <= 8 else f"{args.config}: {len(specs)} layers, sum MKN {mkn}",
+                   "protocol": args.mode, "parties": 2, "ring": "values Z_2^64, shares and tags Z_2^128",
+                   "layers_per_call": len(specs), "sum_MKN": mkn},
+        "roofline": roofline,
+        "stages": stage_rows,
+    }
+
+    if not args.no_compare:
+        other = MODE_SPDZ2K if mode_id == MODE_COMPACT else MODE_COMPACT
+        oname = "spdz2k" if other == MODE_SPDZ2K else "compact"
+        T2, per2, _ = run_steps(ctx, other, [layers], out_dev, args.steps, args.warmup, torch)
+        out[oname] = {"value": round(mkn * args.steps / T2 / 1e9, 3), "ms_per_step": round(T2 / args.steps * 1e3, 4),
+                      "p50_ms": round(pct(per2, 50), 4), "p99_ms": round(pct(per2, 99), 4)}
+        T3, per3, _ = run_steps(ctx, mode_id, [[l] for l in layers], out_dev, args.steps, args.warmup, torch)
+        out["per_layer_launch"] = {"value": round(mkn * args.steps / T3 / 1e9, 3),
+                                   "ms_per_step": round(T3 / args.steps * 1e3, 4),
+                                   "p50_ms": round(pct(per3, 50), 4), "p99_ms": round(pct(per3, 99), 4)}
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        cb = cpu_baseline(specs)
+        out["cpu_baseline"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in cb.items()}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -138,6 +138,24 @@ ct_status ct_mac_check_device(ct_ctx *ctx, ct_mode mode, const ct_layer_desc *L,
 ct_status ct_mac_check(ct_ctx *ctx, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
                        ct_check_result *out);
 
+/* Optional per-kernel timing, for profiling: while enabled, every kernel the
+ * context launches is bracketed by a pair of HIP events recorded on the
+ * context stream.  The first enable creates the context's event pool (2048
+ * pairs); when the pool is full the stream is synchronized and the pairs are
+ * folded into per-stage totals.  Not for use under graph capture. */
+ct_status ct_set_timing(ct_ctx *ctx, int enable);
+
+typedef struct {
+    char name[24];        /* kernel stage, e.g. "ring_gemm", "check_batch" */
+    double total_ms;      /* summed event-measured duration */
+    int64_t launches;     /* number of launches summed */
+} ct_stage_time;
+
+/* Synchronizes the stream and returns, per kernel stage launched since the
+ * previous call, the summed duration and launch count (at most max records;
+ * *count receives the number of stages), then resets the totals. */
+ct_status ct_stage_times(ct_ctx *ctx, ct_stage_time *out, int max, int *count);
+
 /* Text of the last error on this context ("" if none). */
 const char *ct_last_error(const ct_ctx *ctx);
 

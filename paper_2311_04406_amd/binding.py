@@ -46,6 +46,10 @@ class CtLayerBufs(ctypes.Structure):
     _fields_ = [(n, _P2) for n in BUF_PAIRS] + [(n, ctypes.c_void_p) for n in BUF_SINGLE]
 
 
+class CtStageTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("total_ms", ctypes.c_double), ("launches", ctypes.c_int64)]
+
+
 class CtCheckResult(ctypes.Structure):
     _fields_ = [("cs", ctypes.c_uint64 * 12), ("accept", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
@@ -71,10 +75,12 @@ def load() -> ctypes.CDLL:
     L.ct_mac_check_device.argtypes = [vp, i, ctypes.POINTER(CtLayerDesc), ctypes.POINTER(CtLayerBufs), i, vp]
     L.ct_mac_check.argtypes = [vp, i, ctypes.POINTER(CtLayerDesc), ctypes.POINTER(CtLayerBufs), i,
                                ctypes.POINTER(CtCheckResult)]
+    L.ct_set_timing.argtypes = [vp, i]
+    L.ct_stage_times.argtypes = [vp, ctypes.POINTER(CtStageTime), i, ctypes.POINTER(ctypes.c_int)]
     L.ct_last_error.argtypes = [vp]
     L.ct_last_error.restype = ctypes.c_char_p
     for f in ("ct_create", "ct_destroy", "ct_key_shares", "ct_gen_triple_tags", "ct_tag_linear",
-              "ct_mac_check_device", "ct_mac_check"):
+              "ct_mac_check_device", "ct_mac_check", "ct_set_timing", "ct_stage_times"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -214,6 +220,16 @@ class Context:
         s = self._check(self.lib.ct_mac_check(self.h, mode, D, B, n, res), allow_abort=True)
         out = [_result(r) for r in res]
         return s, out
+
+    def set_timing(self, enable: bool):
+        self._check(self.lib.ct_set_timing(self.h, int(enable)))
+
+    def stage_times(self):
+        """{stage: (total_ms, launches)} since the previous call (synchronizes)."""
+        buf = (CtStageTime * 32)()
+        cnt = ctypes.c_int()
+        self._check(self.lib.ct_stage_times(self.h, buf, 32, ctypes.byref(cnt)))
+        return {buf[i].name.decode(): (buf[i].total_ms, int(buf[i].launches)) for i in range(min(cnt.value, 32))}
 
     @staticmethod
     def decode_results(t: torch.Tensor, n: int):

@@ -19,6 +19,17 @@
 
 using namespace ct;
 
+// Kernel stages, for the optional per-launch timing (ct_set_timing).
+enum Stage : int {
+    ST_DEAL_LIFT, ST_FILL_ZERO, ST_DEAL_AUTH, ST_ZERO_CVEC, ST_OPEN, ST_COMPRESS_KN, ST_COPY_BASE, ST_RING_GEMM,
+    ST_SKINNY, ST_POST_COMPACT, ST_COMPACT_TAG, ST_OPEN_D, ST_ZERO_ACC, ST_CHECK_BATCH, ST_CHECK_COMPACT,
+    ST_FINALIZE, ST_COUNT
+};
+static const char *kStageNames[ST_COUNT] = {
+    "deal_lift", "fill_zero", "deal_auth", "zero_cvec", "open", "compress_kn", "copy_base", "ring_gemm",
+    "skinny", "post_compact", "compact_tag", "open_d", "zero_acc", "check_batch", "check_compact", "finalize"};
+constexpr int EV_POOL = 2048;
+
 struct ct_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -31,6 +42,13 @@ struct ct_ctx {
     ct_check_result *res_dev = nullptr, *res_host = nullptr;
     hipEvent_t upload_done = nullptr;
     std::string err;
+    // per-launch timing: event pairs recorded around each kernel on `stream`
+    bool timing = false;
+    std::vector<hipEvent_t> ev_start, ev_end;
+    std::vector<int> ev_stage;
+    int ev_used = 0;
+    double stage_ms[ST_COUNT] = {};
+    int64_t stage_n[ST_COUNT] = {};
 };
 
 namespace {
@@ -57,6 +75,36 @@ ct_status hip_fail(ct_ctx *c, hipError_t e, const char *where) {
     do {                                                           \
         hipError_t e_ = (expr);                                    \
         if (e_ != hipSuccess) return hip_fail((ctx), e_, #expr);   \
+    } while (0)
+
+// Folds the recorded event pairs into the per-stage totals (synchronizes).
+hipError_t fold_timing(ct_ctx *c) {
+    if (c->ev_used == 0) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return e;
+    for (int i = 0; i < c->ev_used; i++) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, c->ev_start[i], c->ev_end[i]);
+        if (e != hipSuccess) return e;
+        c->stage_ms[c->ev_stage[i]] += ms;
+        c->stage_n[c->ev_stage[i]] += 1;
+    }
+    c->ev_used = 0;
+    return hipSuccess;
+}
+
+// Runs a launcher; with timing on, brackets it with an event pair on the stream.
+#define LAUNCH(ctx, stage, expr)                                                         \
+    do {                                                                                 \
+        if ((ctx)->timing) {                                                             \
+            if ((ctx)->ev_used == EV_POOL) HIPCHK(ctx, fold_timing(ctx));                \
+            HIPCHK(ctx, hipEventRecord((ctx)->ev_start[(ctx)->ev_used], (ctx)->stream)); \
+        }                                                                                \
+        HIPCHK(ctx, expr);                                                               \
+        if ((ctx)->timing) {                                                             \
+            HIPCHK(ctx, hipEventRecord((ctx)->ev_end[(ctx)->ev_used], (ctx)->stream));   \
+            (ctx)->ev_stage[(ctx)->ev_used++] = (stage);                                 \
+        }                                                                                \
     } while (0)
 
 bool aligned16(const void *p) { return p != nullptr && (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
@@ -235,12 +283,12 @@ int plan_gemms(std::vector<GemmProb> &probs, int num_cus, int *total_tiles, bool
 ct_status run_gemms(ct_ctx *c, int nprobs, int nm, int total_tiles) {
     if (nm > 0) {
         int grid = total_tiles;
-        HIPCHK(c, launch_gemm(c->gemm_dev, nm, total_tiles, grid, c->stream));
+        LAUNCH(c, ST_RING_GEMM, launch_gemm(c->gemm_dev, nm, total_tiles, grid, c->stream));
     }
     if (nprobs > nm) {
         int max_rows = 0;
         for (int i = nm; i < nprobs; i++) max_rows = std::max(max_rows, c->gemm_host[i].M);
-        HIPCHK(c, launch_skinny(c->gemm_dev + nm, nprobs - nm, max_rows, c->stream));
+        LAUNCH(c, ST_SKINNY, launch_skinny(c->gemm_dev + nm, nprobs - nm, max_rows, c->stream));
     }
     return CT_OK;
 }
@@ -293,6 +341,8 @@ ct_status ct_destroy(ct_ctx *c) {
     if (!c) return CT_EINVAL;
     if (c->stream || c->layers_dev) hipStreamSynchronize(c->stream);
     if (c->upload_done) hipEventDestroy(c->upload_done);
+    for (auto e : c->ev_start) hipEventDestroy(e);
+    for (auto e : c->ev_end) hipEventDestroy(e);
     if (c->layers_dev) hipFree(c->layers_dev);
     if (c->gemm_dev) hipFree(c->gemm_dev);
     if (c->acc_dev) hipFree(c->acc_dev);
@@ -330,14 +380,14 @@ ct_status ct_gen_triple_tags(ct_ctx *c, const ct_layer_desc *L, const ct_layer_b
     std::copy(probs.begin(), probs.end(), c->gemm_host);
     if ((s = upload(c, n, (int)probs.size())) != CT_OK) return s;
     const Sizes sz = max_sizes(L, n);
-    HIPCHK(c, launch_deal_lift(c->layers_dev, n, std::max(sz.mk, sz.kn), c->stream));
+    LAUNCH(c, ST_DEAL_LIFT, launch_deal_lift(c->layers_dev, n, std::max(sz.mk, sz.kn), c->stream));
     for (int i = 0; i < nm; i++)
         if (probs[i].accumulate)
-            HIPCHK(c, launch_fill_zero(probs[i].out, (int64_t)probs[i].M * probs[i].N, c->stream));
+            LAUNCH(c, ST_FILL_ZERO, launch_fill_zero(probs[i].out, (int64_t)probs[i].M * probs[i].N, c->stream));
     if ((s = run_gemms(c, (int)probs.size(), nm, total_tiles)) != CT_OK) return s;
     const int mask = (with_inputs ? ((1 << OBJ_X) | (1 << OBJ_Y)) : 0) | (1 << OBJ_A) | (1 << OBJ_B) |
                      (1 << OBJ_C) | (1 << OBJ_R);
-    HIPCHK(c, launch_deal_auth(c->layers_dev, n, mask, std::max({sz.mk, sz.kn, sz.mn}), c->stream));
+    LAUNCH(c, ST_DEAL_AUTH, launch_deal_auth(c->layers_dev, n, mask, std::max({sz.mk, sz.kn, sz.mn}), c->stream));
     return CT_OK;
 }
 
@@ -370,16 +420,16 @@ ct_status ct_tag_linear(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const c
     if ((s = upload(c, n, (int)probs.size())) != CT_OK) return s;
 
     const Sizes sz = max_sizes(L, n);
-    if (compact) HIPCHK(c, launch_zero_acc(c->layers_dev, n, 1, sz.cvec, c->stream));
-    HIPCHK(c, launch_open(c->layers_dev, n, std::max(sz.mk, sz.kn), c->stream));
-    if (compact) HIPCHK(c, launch_compress_kn(c->layers_dev, n, sz.k, sz.kn_segs, c->stream));
-    if (any_accum) HIPCHK(c, launch_copy_base(c->layers_dev, n, mode, sz.mn, c->stream));
+    if (compact) LAUNCH(c, ST_ZERO_CVEC, launch_zero_acc(c->layers_dev, n, 1, sz.cvec, c->stream));
+    LAUNCH(c, ST_OPEN, launch_open(c->layers_dev, n, std::max(sz.mk, sz.kn), c->stream));
+    if (compact) LAUNCH(c, ST_COMPRESS_KN, launch_compress_kn(c->layers_dev, n, sz.k, sz.kn_segs, c->stream));
+    if (any_accum) LAUNCH(c, ST_COPY_BASE, launch_copy_base(c->layers_dev, n, mode, sz.mn, c->stream));
     if ((s = run_gemms(c, (int)probs.size(), nm, total_tiles)) != CT_OK) return s;
     if (compact) {
-        HIPCHK(c, launch_post_compact(c->layers_dev, n, sz.m, sz.mn_segs, c->stream));
-        HIPCHK(c, launch_compact_tag(c->layers_dev, n, sz.m, c->stream));
+        LAUNCH(c, ST_POST_COMPACT, launch_post_compact(c->layers_dev, n, sz.m, sz.mn_segs, c->stream));
+        LAUNCH(c, ST_COMPACT_TAG, launch_compact_tag(c->layers_dev, n, sz.m, c->stream));
     } else {
-        HIPCHK(c, launch_open_d(c->layers_dev, n, sz.mn, c->stream));
+        LAUNCH(c, ST_OPEN_D, launch_open_d(c->layers_dev, n, sz.mn, c->stream));
     }
     return CT_OK;
 }
@@ -395,11 +445,11 @@ ct_status ct_mac_check_device(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, c
     if ((s = stage_layers(c, L, B, n)) != CT_OK) return s;
     if ((s = upload(c, n, 0)) != CT_OK) return s;
     const Sizes sz = max_sizes(L, n);
-    HIPCHK(c, launch_zero_acc(c->layers_dev, n, 2, 0, c->stream));
+    LAUNCH(c, ST_ZERO_ACC, launch_zero_acc(c->layers_dev, n, 2, 0, c->stream));
     const int mask = compact ? 0x3 : 0x7;
-    HIPCHK(c, launch_check_batch(c->layers_dev, n, mask, std::max({sz.mk, sz.kn, sz.mn}), c->stream));
-    if (compact) HIPCHK(c, launch_check_compact(c->layers_dev, n, c->stream));
-    HIPCHK(c, launch_finalize(c->layers_dev, n, mode, out_dev, c->stream));
+    LAUNCH(c, ST_CHECK_BATCH, launch_check_batch(c->layers_dev, n, mask, std::max({sz.mk, sz.kn, sz.mn}), c->stream));
+    if (compact) LAUNCH(c, ST_CHECK_COMPACT, launch_check_compact(c->layers_dev, n, c->stream));
+    LAUNCH(c, ST_FINALIZE, launch_finalize(c->layers_dev, n, mode, out_dev, c->stream));
     return CT_OK;
 }
 
@@ -417,6 +467,43 @@ ct_status ct_mac_check(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct
         ok = ok && c->res_host[l].accept;
     }
     return ok ? CT_OK : CT_ABORT;
+}
+
+ct_status ct_set_timing(ct_ctx *c, int enable) {
+    if (!c) return CT_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    if (enable && c->ev_start.empty()) {
+        c->ev_start.resize(EV_POOL);
+        c->ev_end.resize(EV_POOL);
+        c->ev_stage.resize(EV_POOL);
+        for (int i = 0; i < EV_POOL; i++) {
+            HIPCHK(c, hipEventCreate(&c->ev_start[i]));
+            HIPCHK(c, hipEventCreate(&c->ev_end[i]));
+        }
+    }
+    if (!enable) HIPCHK(c, fold_timing(c));
+    c->timing = enable != 0;
+    return CT_OK;
+}
+
+ct_status ct_stage_times(ct_ctx *c, ct_stage_time *out, int max, int *count) {
+    if (!c || !count || (max > 0 && !out)) return CT_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, fold_timing(c));
+    int k = 0;
+    for (int st = 0; st < ST_COUNT; st++) {
+        if (c->stage_n[st] == 0) continue;
+        if (k < max) {
+            std::snprintf(out[k].name, sizeof(out[k].name), "%s", kStageNames[st]);
+            out[k].total_ms = c->stage_ms[st];
+            out[k].launches = c->stage_n[st];
+        }
+        k++;
+        c->stage_ms[st] = 0;
+        c->stage_n[st] = 0;
+    }
+    *count = k;
+    return CT_OK;
 }
 
 }  // extern "C"
