@@ -35,44 +35,34 @@ DIGIT_PAIRS = 136            # int8 digit products per 128-bit ring multiply-acc
 
 def stage_work(stage: str, specs, mode: str):
     """Algorithmic work of one launch of a kernel stage over the layer batch:
-    ("hbm", bytes) or ("mfma", int8 ops).  Per-element figures (16 B per
-    Z_2^128 element):
-      open 80 B per element of MK + KN (4 share reads, 1 write)
-      compress_kn 48 B per KN element (U, tB_0, tB_1)
-      copy_base 32 B per MN element per array (2 arrays, 4 in SPDZ2k)
-      ring_gemm 2 * 136 int8 ops per ring MAC (4 MKN ring MACs per layer,
-        8 in SPDZ2k), layers with N > 8
-      skinny 16 B per element of the distinct M x K operands (E, A_0, A_1,
-        and tA_0, tA_1 in SPDZ2k), layers with N <= 8
-      post_compact 176 B per MN element (8 reads, 3 writes)
-      compact_tag 48 B per MK element (E, tA_0, tA_1)
-      open_d 80 B per MN element
-      check_batch 80 B per element of MK + KN (+ MN in SPDZ2k)."""
+    ("hbm", bytes) or ("mfma", int8 ops), for the fused step
+    (ct_tag_linear_check).  16 B per Z_2^128 element; per element:
+      open_u     K x N: reads Y_p, B_p, tY_p, tB_p (8), writes U: 144 B
+      row_pass   M x K: reads X_p, A_p, tX_p, tA_p (8), writes E: 144 B,
+                 plus the folded operands written for matrix-core layers
+                 (A_0 + E; SPDZ2k also tA_p + Delta_p E): 16 / 48 B
+      copy_base  M x N: 32 B per array (2 arrays, 4 in SPDZ2k), N > 8 layers
+      ring_gemm  2 * 136 int8 ops per ring MAC; 4 M K N ring MACs per
+                 layer (8 in SPDZ2k), layers with N > 8
+      post       M x N: CompactTag reads R_p, Z_p, tR_p, tC_p (8), writes D,
+                 tZ_p (3): 176 B; SPDZ2k reads R_p, Z_p, tR_p, tZ_p (8),
+                 writes D: 144 B."""
     spdz = mode == "spdz2k"
     tot = 0
     for s in specs:
         M, K, N = s.M, s.K, s.N
         mk, kn, mn = M * K, K * N, M * N
-        if stage == "open":
-            tot += 80 * (mk + kn)
-        elif stage == "compress_kn":
-            tot += 48 * kn
+        wide = N > 8
+        if stage == "open_u":
+            tot += 144 * kn
+        elif stage == "row_pass":
+            tot += 144 * mk + ((48 if spdz else 16) * mk if wide else 0)
         elif stage == "copy_base":
-            tot += 32 * mn * (4 if spdz else 2)
+            tot += (32 * mn * (4 if spdz else 2)) if wide else 0
         elif stage == "ring_gemm":
-            if N > 8:
-                tot += 2 * DIGIT_PAIRS * (8 if spdz else 4) * M * K * N
-        elif stage == "skinny":
-            if N <= 8:
-                tot += 16 * mk * (5 if spdz else 3)
-        elif stage == "post_compact":
-            tot += 176 * mn
-        elif stage == "compact_tag":
-            tot += 48 * mk
-        elif stage == "open_d":
-            tot += 80 * mn
-        elif stage == "check_batch":
-            tot += 80 * (mk + kn + (mn if spdz else 0))
+            tot += 2 * DIGIT_PAIRS * (8 if spdz else 4) * M * K * N if wide else 0
+        elif stage == "post":
+            tot += (144 if spdz else 176) * mn
         else:
             return None
     return ("mfma" if stage == "ring_gemm" else "hbm", tot)
@@ -109,13 +99,17 @@ def pct(v, q):
     return v[i]
 
 
-def run_steps(ctx, mode_id, layer_groups, out_dev, steps, warmup, torch, timing=False):
-    """Runs warmup + steps; each step enqueues every group (one call per group).
-    Returns (total seconds, per-step ms list)."""
+def run_steps(ctx, mode_id, layer_groups, out_dev, steps, warmup, torch, timing=False, fused=True):
+    """Runs warmup + steps; each step enqueues every group (one call per group):
+    ct_tag_linear_check (fused) or ct_tag_linear + ct_mac_check_device.
+    Returns (total seconds, per-step ms list, stage times)."""
     def step():
         for g in layer_groups:
-            ctx.tag_linear(mode_id, g)
-            ctx.mac_check_device(mode_id, g, out_dev)
+            if fused:
+                ctx.tag_linear_check(mode_id, g, out_dev)
+            else:
+                ctx.tag_linear(mode_id, g)
+                ctx.mac_check_device(mode_id, g, out_dev)
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
@@ -263,6 +257,10 @@ def main():
         out["per_layer_launch"] = {"value": round(mkn * args.steps / T3 / 1e9, 3),
                                    "ms_per_step": round(T3 / args.steps * 1e3, 4),
                                    "p50_ms": round(pct(per3, 50), 4), "p99_ms": round(pct(per3, 99), 4)}
+        T4, per4, _ = run_steps(ctx, mode_id, [layers], out_dev, args.steps, args.warmup, torch, fused=False)
+        out["separate_check"] = {"value": round(mkn * args.steps / T4 / 1e9, 3),
+                                 "ms_per_step": round(T4 / args.steps * 1e3, 4),
+                                 "p50_ms": round(pct(per4, 50), 4), "p99_ms": round(pct(per4, 99), 4)}
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         cb = cpu_baseline(specs)

@@ -75,7 +75,17 @@ typedef struct {
                             D = R - Z (M x N); outputs of ct_tag_linear */
     ct_u128 *cvec;       /* compact-tag vectors, CT_CVEC_LEN(M, K) elements, layout below;
                             written by ct_tag_linear in CT_MODE_COMPACT, unused otherwise */
+    ct_u128 *work;       /* caller-owned workspace of CT_WORK_LEN(M, K, N) elements (NULL allowed
+                            when that is 0); contents are undefined after a call */
 } ct_layer_bufs;
+
+/* Layers with N <= CT_SKINNY_N form their output products in the pass that
+ * opens E (bandwidth-bound, no workspace); wider layers use the matrix cores
+ * and a workspace holding the folded left operands A_0 + E and, in SPDZ2k
+ * mode, [tA]_p + [Delta]_p E (three M x K arrays).  The matrix-core path
+ * needs K < 2^21 and N < 2^22. */
+#define CT_SKINNY_N 8
+#define CT_WORK_LEN(M, K, N) ((N) > CT_SKINNY_N ? 3 * (M) * (K) : 0)
 
 /* cvec layout (element offsets): U^c [K] | tB^c_0 [K] | tB^c_1 [K] | D^c [M] | (E U^c) [M] |
  * tC^c_0 [M] | tC^c_1 [M] | tR^c_0 [M] | tR^c_1 [M] | tZ^c_0 [M] | tZ^c_1 [M] | tD^c_0 [M] | tD^c_1 [M] */
@@ -128,9 +138,20 @@ ct_status ct_tag_linear(ct_ctx *ctx, ct_mode mode, const ct_layer_desc *L, const
  * compact check of D (Fig. 6 verification steps 2-6) in CT_MODE_COMPACT.  All
  * check values are reduced mod 2^128.  The public combiners are drawn from the
  * layer's generator streams, so a layer's results do not depend on the other
- * layers in the call.  Asynchronous; allocates nothing; graph-capturable. */
+ * layers in the call.  Asynchronous; allocates nothing.  Reads the arrays
+ * again, independently of how ct_tag_linear produced them. */
 ct_status ct_mac_check_device(ct_ctx *ctx, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B,
                               int n, ct_check_result *out_dev);
+
+/* The online phase and the verification of n layers in one pass over the
+ * data: the same outputs as ct_tag_linear followed by ct_mac_check_device and
+ * the same n check records in out_dev, but each check sum is accumulated by
+ * the kernel that opens the checked value (E and U from the input shares, D
+ * after the products), so no share array is read twice.  This is the
+ * amortised verification of many products in one shot.  Asynchronous;
+ * allocates nothing. */
+ct_status ct_tag_linear_check(ct_ctx *ctx, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
+                              ct_check_result *out_dev);
 
 /* As ct_mac_check_device, then waits for the stream and copies the n results
  * to host memory out.  Returns CT_ABORT if any layer fails its check (out is

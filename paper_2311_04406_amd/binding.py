@@ -39,7 +39,8 @@ class CtLayerDesc(ctypes.Structure):
 
 _P2 = ctypes.c_void_p * 2
 BUF_PAIRS = ["X", "tX", "A", "tA", "Y", "tY", "B", "tB", "C", "tC", "R", "tR", "Z", "tZ"]
-BUF_SINGLE = ["E", "U", "D", "cvec"]
+BUF_SINGLE = ["E", "U", "D", "cvec", "work"]
+SKINNY_N = 8
 
 
 class CtLayerBufs(ctypes.Structure):
@@ -73,6 +74,7 @@ def load() -> ctypes.CDLL:
     L.ct_gen_triple_tags.argtypes = [vp, ctypes.POINTER(CtLayerDesc), ctypes.POINTER(CtLayerBufs), i, i]
     L.ct_tag_linear.argtypes = [vp, i, ctypes.POINTER(CtLayerDesc), ctypes.POINTER(CtLayerBufs), i]
     L.ct_mac_check_device.argtypes = [vp, i, ctypes.POINTER(CtLayerDesc), ctypes.POINTER(CtLayerBufs), i, vp]
+    L.ct_tag_linear_check.argtypes = [vp, i, ctypes.POINTER(CtLayerDesc), ctypes.POINTER(CtLayerBufs), i, vp]
     L.ct_mac_check.argtypes = [vp, i, ctypes.POINTER(CtLayerDesc), ctypes.POINTER(CtLayerBufs), i,
                                ctypes.POINTER(CtCheckResult)]
     L.ct_set_timing.argtypes = [vp, i]
@@ -80,7 +82,7 @@ def load() -> ctypes.CDLL:
     L.ct_last_error.argtypes = [vp]
     L.ct_last_error.restype = ctypes.c_char_p
     for f in ("ct_create", "ct_destroy", "ct_key_shares", "ct_gen_triple_tags", "ct_tag_linear",
-              "ct_mac_check_device", "ct_mac_check", "ct_set_timing", "ct_stage_times"):
+              "ct_mac_check_device", "ct_mac_check", "ct_set_timing", "ct_stage_times", "ct_tag_linear_check"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -123,10 +125,12 @@ class Layer:
         self.t["U"] = torch.zeros((K, N, 2), dtype=torch.int64, device=device)
         self.t["D"] = torch.zeros((M, N, 2), dtype=torch.int64, device=device)
         self.t["cvec"] = torch.zeros((3 * K + 10 * M, 2), dtype=torch.int64, device=device)
+        wl = 3 * M * K if N > SKINNY_N else 1
+        self.t["work"] = torch.zeros((wl, 2), dtype=torch.int64, device=device)
 
     @staticmethod
     def footprint_bytes(M: int, K: int, N: int) -> int:
-        return 16 * (9 * M * K + 9 * K * N + 13 * M * N + 3 * K + 10 * M)
+        return 16 * (9 * M * K + 9 * K * N + 13 * M * N + 3 * K + 10 * M + (3 * M * K if N > SKINNY_N else 0))
 
     def __getitem__(self, name):
         return self.t[name]
@@ -213,6 +217,12 @@ class Context:
         n, D, B = _arrays(layers)
         assert out.numel() * 8 >= n * ctypes.sizeof(CtCheckResult)
         self._check(self.lib.ct_mac_check_device(self.h, mode, D, B, n, ctypes.c_void_p(out.data_ptr())))
+
+    def tag_linear_check(self, mode: int, layers, out: torch.Tensor):
+        """Online phase with the verification fused in; n check records to `out` (device)."""
+        n, D, B = _arrays(layers)
+        assert out.numel() * 8 >= n * ctypes.sizeof(CtCheckResult)
+        self._check(self.lib.ct_tag_linear_check(self.h, mode, D, B, n, ctypes.c_void_p(out.data_ptr())))
 
     def mac_check(self, mode: int, layers):
         n, D, B = _arrays(layers)

@@ -21,13 +21,12 @@ using namespace ct;
 
 // Kernel stages, for the optional per-launch timing (ct_set_timing).
 enum Stage : int {
-    ST_DEAL_LIFT, ST_FILL_ZERO, ST_DEAL_AUTH, ST_ZERO_CVEC, ST_OPEN, ST_COMPRESS_KN, ST_COPY_BASE, ST_RING_GEMM,
-    ST_SKINNY, ST_POST_COMPACT, ST_COMPACT_TAG, ST_OPEN_D, ST_ZERO_ACC, ST_CHECK_BATCH, ST_CHECK_COMPACT,
-    ST_FINALIZE, ST_COUNT
+    ST_DEAL_LIFT, ST_FILL_ZERO, ST_DEAL_AUTH, ST_DEAL_SKINNY, ST_ZERO_ACC, ST_OPEN_U, ST_ROW_PASS, ST_COPY_BASE,
+    ST_RING_GEMM, ST_POST, ST_COMPACT_FINAL, ST_CHECK_BATCH, ST_CHECK_COMPACT, ST_FINALIZE, ST_COUNT
 };
 static const char *kStageNames[ST_COUNT] = {
-    "deal_lift", "fill_zero", "deal_auth", "zero_cvec", "open", "compress_kn", "copy_base", "ring_gemm",
-    "skinny", "post_compact", "compact_tag", "open_d", "zero_acc", "check_batch", "check_compact", "finalize"};
+    "deal_lift", "fill_zero", "deal_auth", "deal_skinny", "zero_acc", "open_u", "row_pass", "copy_base",
+    "ring_gemm", "post", "compact_final", "check_batch", "check_compact", "finalize"};
 constexpr int EV_POOL = 2048;
 
 struct ct_ctx {
@@ -114,6 +113,7 @@ enum Need : unsigned {
     NEED_TRIPLE = 2,   // A, tA, B, tB, C, tC, R, tR
     NEED_OUT = 4,      // Z, tZ, E, U, D
     NEED_CVEC = 8,
+    NEED_WORK = 16,    // workspace of layers with N > SKINNY_MAX_N
 };
 
 ct_status validate(ct_ctx *c, const ct_layer_desc *L, const ct_layer_bufs *B, int n, unsigned need) {
@@ -152,6 +152,11 @@ ct_status validate(ct_ctx *c, const ct_layer_desc *L, const ct_layer_bufs *B, in
             if (!chk(b.E, "E") || !chk(b.U, "U") || !chk(b.D, "D")) return CT_EINVAL;
         if (need & NEED_CVEC)
             if (!chk(b.cvec, "cvec")) return CT_EINVAL;
+        if ((need & NEED_WORK) && d.N > SKINNY_MAX_N) {
+            if (!chk(b.work, "work")) return CT_EINVAL;
+            if (d.K >= (1LL << 21) || d.N >= (1LL << 22))
+                return fail(c, CT_EINVAL, at + "matrix-core path needs K < 2^21 and N < 2^22");
+        }
     }
     return CT_OK;
 }
@@ -190,16 +195,16 @@ void fill_layer(const ct_ctx *c, const ct_layer_desc &d, const ct_layer_bufs &b,
     o.U = reinterpret_cast<u128 *>(b.U);
     o.D = reinterpret_cast<u128 *>(b.D);
     o.cvec = reinterpret_cast<u128 *>(b.cvec);
+    o.work = reinterpret_cast<u128 *>(b.work);
     o.acc = c->acc_dev + (size_t)l * ACC_PER_LAYER;
 }
 
 struct Sizes {
-    int64_t mk = 0, kn = 0, mn = 0, m = 0, k = 0, kn_segs = 0, mn_segs = 0, cvec = 0;
+    int64_t mk = 0, kn = 0, mn = 0, m = 0, k = 0, cvec = 0, kn_items = 0, mn_items = 0;
 };
 
 Sizes max_sizes(const ct_layer_desc *L, int n) {
     Sizes s;
-    const int64_t SEG = 1024;
     for (int l = 0; l < n; l++) {
         const ct_layer_desc &d = L[l];
         s.mk = std::max(s.mk, d.M * d.K);
@@ -207,9 +212,9 @@ Sizes max_sizes(const ct_layer_desc *L, int n) {
         s.mn = std::max(s.mn, d.M * d.N);
         s.m = std::max(s.m, d.M);
         s.k = std::max(s.k, d.K);
-        s.kn_segs = std::max(s.kn_segs, d.K * ((d.N + SEG - 1) / SEG));
-        s.mn_segs = std::max(s.mn_segs, d.M * ((d.N + SEG - 1) / SEG));
         s.cvec = std::max(s.cvec, (int64_t)CT_CVEC_LEN(d.M, d.K));
+        s.kn_items = std::max(s.kn_items, sweep_items(d.K, d.N));
+        s.mn_items = std::max(s.mn_items, sweep_items(d.M, d.N));
     }
     return s;
 }
@@ -231,12 +236,11 @@ ct_status upload(ct_ctx *c, int n, int nprobs) {
     return CT_OK;
 }
 
-GemmProb make_prob(const u128 *L1, const u128 *L2, const u128 *R1, const u128 *R1b, uint64_t s, const u128 *R2,
-                   const u128 *base, u128 *out, const ct_layer_desc &d) {
+GemmProb make_prob(const u128 *L1, const u128 *L2, const u128 *R1, const u128 *R2, const u128 *base, u128 *out,
+                   const ct_layer_desc &d) {
     GemmProb p;
     std::memset(&p, 0, sizeof(p));
-    p.L1 = L1; p.L2 = L2; p.R1 = R1; p.R1b = (s != 0) ? R1b : nullptr; p.R2 = R2;
-    p.s = s; p.base = base; p.out = out;
+    p.L1 = L1; p.L2 = L2; p.R1 = R1; p.R2 = R2; p.base = base; p.out = out;
     p.M = (int32_t)d.M; p.N = (int32_t)d.N; p.K = (int32_t)d.K;
     return p;
 }
@@ -248,7 +252,7 @@ constexpr int MAX_STEPS_PER_SPLIT = 255;  // keeps every int32 diagonal exact
 int plan_gemms(std::vector<GemmProb> &probs, int num_cus, int *total_tiles, bool *any_accum) {
     std::stable_partition(probs.begin(), probs.end(), [](const GemmProb &p) { return p.N > SKINNY_MAX_N; });
     int nm = 0;
-    int64_t base_tiles = 0;
+    int64_t total_steps = 0;
     for (auto &p : probs) {
         if (p.N <= SKINNY_MAX_N) break;
         nm++;
@@ -256,20 +260,21 @@ int plan_gemms(std::vector<GemmProb> &probs, int num_cus, int *total_tiles, bool
         p.tiles_n = (p.N + 63) / 64;
         p.ksteps_seg = (p.K + 31) / 32;
         p.nsteps = p.ksteps_seg * (p.L2 ? 2 : 1);
-        base_tiles += (int64_t)p.tiles_m * p.tiles_n;
+        total_steps += (int64_t)p.tiles_m * p.tiles_n * p.nsteps;
     }
-    int64_t want = base_tiles > 0 ? (num_cus + base_tiles - 1) / base_tiles : 1;
-    if (want < 1) want = 1;
+    // K slices per tile: enough tiles for two rounds over the compute units,
+    // equal-length tiles across problems, at least 8 slices per tile (the
+    // split partials cost atomics), at most MAX_STEPS_PER_SPLIT (exactness).
+    int64_t target = (total_steps + 2LL * num_cus - 1) / (2LL * num_cus);
+    if (target < 8) target = 8;
+    if (target > MAX_STEPS_PER_SPLIT) target = MAX_STEPS_PER_SPLIT;
     int tile = 0;
     *any_accum = false;
     for (int i = 0; i < nm; i++) {
         GemmProb &p = probs[i];
-        int64_t splits = std::min<int64_t>(want, std::max(1, p.nsteps / 8));
-        if (splits < 1) splits = 1;
-        int sps = (int)((p.nsteps + splits - 1) / splits);
-        if (sps > MAX_STEPS_PER_SPLIT) sps = MAX_STEPS_PER_SPLIT;
-        p.steps_per_split = sps;
-        p.splits = (p.nsteps + sps - 1) / sps;
+        const int64_t splits = std::max<int64_t>(1, (p.nsteps + target - 1) / target);
+        p.steps_per_split = (int)((p.nsteps + splits - 1) / splits);
+        p.splits = (p.nsteps + p.steps_per_split - 1) / p.steps_per_split;
         p.accumulate = p.splits > 1 ? 1 : 0;
         if (p.accumulate) *any_accum = true;
         p.tile_begin = tile;
@@ -288,7 +293,7 @@ ct_status run_gemms(ct_ctx *c, int nprobs, int nm, int total_tiles) {
     if (nprobs > nm) {
         int max_rows = 0;
         for (int i = nm; i < nprobs; i++) max_rows = std::max(max_rows, c->gemm_host[i].M);
-        LAUNCH(c, ST_SKINNY, launch_skinny(c->gemm_dev + nm, nprobs - nm, max_rows, c->stream));
+        LAUNCH(c, ST_DEAL_SKINNY, launch_skinny(c->gemm_dev + nm, nprobs - nm, max_rows, c->stream));
     }
     return CT_OK;
 }
@@ -372,7 +377,7 @@ ct_status ct_gen_triple_tags(ct_ctx *c, const ct_layer_desc *L, const ct_layer_b
     probs.reserve(n);
     for (int l = 0; l < n; l++) {
         const LayerDev &o = c->layers_host[l];
-        probs.push_back(make_prob(o.A[1], nullptr, o.B[1], nullptr, 0, nullptr, nullptr, o.C[1], L[l]));
+        probs.push_back(make_prob(o.A[1], nullptr, o.B[1], nullptr, nullptr, o.C[1], L[l]));
     }
     int total_tiles = 0;
     bool any_accum = false;
@@ -391,26 +396,39 @@ ct_status ct_gen_triple_tags(ct_ctx *c, const ct_layer_desc *L, const ct_layer_b
     return CT_OK;
 }
 
-ct_status ct_tag_linear(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n) {
+}  // extern "C"
+
+namespace {
+
+// The online phase, optionally with the verification fused into its passes
+// (out_dev != nullptr).
+ct_status online(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
+                 ct_check_result *out_dev) {
+    if (!c) return CT_EINVAL;
     if (mode != CT_MODE_SPDZ2K && mode != CT_MODE_COMPACT) return fail(c, CT_EINVAL, "unknown mode");
     const bool compact = mode == CT_MODE_COMPACT;
-    ct_status s = validate(c, L, B, n, NEED_INPUTS | NEED_TRIPLE | NEED_OUT | (compact ? NEED_CVEC : 0));
+    const bool check = out_dev != nullptr;
+    ct_status s = validate(c, L, B, n, NEED_INPUTS | NEED_TRIPLE | NEED_OUT | NEED_WORK | (compact ? NEED_CVEC : 0));
     if (s != CT_OK) return s;
+    if (check && !aligned16(out_dev)) return fail(c, CT_EINVAL, "out_dev is null or misaligned");
     HIPCHK(c, hipSetDevice(c->device));
     if ((s = stage_layers(c, L, B, n)) != CT_OK) return s;
 
-    // Output-share products of Eq. (2), both parties, folded into two-segment
-    // products:  [Z]_0 = [C]_0 + E ([B]_0 + U) + [A]_0 U,  [Z]_1 = [C]_1 + E [B]_1 + [A]_1 U.
-    // SPDZ2k tags of Eq. (3):  [tZ]_p = [tC]_p + E ([tB]_p + [Delta]_p U) + [tA]_p U.
+    // Matrix-core products (layers with N > SKINNY_MAX_N), both parties,
+    // Eq. (2) with E U folded into party 0's left operand by the row pass:
+    //   [Z]_0 = [C]_0 + E [B]_0 + (A_0 + E) U,   [Z]_1 = [C]_1 + E [B]_1 + [A]_1 U;
+    // SPDZ2k tags of Eq. (3):  [tZ]_p = [tC]_p + E [tB]_p + ([tA]_p + [Delta]_p E) U.
     std::vector<GemmProb> probs;
     probs.reserve(4 * n);
     for (int l = 0; l < n; l++) {
+        if (L[l].N <= SKINNY_MAX_N) continue;
         const LayerDev &o = c->layers_host[l];
-        probs.push_back(make_prob(o.E, o.A[0], o.B[0], o.U, 1, o.U, o.C[0], o.Z[0], L[l]));
-        probs.push_back(make_prob(o.E, o.A[1], o.B[1], nullptr, 0, o.U, o.C[1], o.Z[1], L[l]));
+        const int64_t mk = L[l].M * L[l].K;
+        probs.push_back(make_prob(o.E, o.work, o.B[0], o.U, o.C[0], o.Z[0], L[l]));
+        probs.push_back(make_prob(o.E, o.A[1], o.B[1], o.U, o.C[1], o.Z[1], L[l]));
         if (!compact) {
-            probs.push_back(make_prob(o.E, o.tA[0], o.tB[0], o.U, c->delta[0], o.U, o.tC[0], o.tZ[0], L[l]));
-            probs.push_back(make_prob(o.E, o.tA[1], o.tB[1], o.U, c->delta[1], o.U, o.tC[1], o.tZ[1], L[l]));
+            probs.push_back(make_prob(o.E, o.work + mk, o.tB[0], o.U, o.tC[0], o.tZ[0], L[l]));
+            probs.push_back(make_prob(o.E, o.work + 2 * mk, o.tB[1], o.U, o.tC[1], o.tZ[1], L[l]));
         }
     }
     int total_tiles = 0;
@@ -420,22 +438,36 @@ ct_status ct_tag_linear(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const c
     if ((s = upload(c, n, (int)probs.size())) != CT_OK) return s;
 
     const Sizes sz = max_sizes(L, n);
-    if (compact) LAUNCH(c, ST_ZERO_CVEC, launch_zero_acc(c->layers_dev, n, 1, sz.cvec, c->stream));
-    LAUNCH(c, ST_OPEN, launch_open(c->layers_dev, n, std::max(sz.mk, sz.kn), c->stream));
-    if (compact) LAUNCH(c, ST_COMPRESS_KN, launch_compress_kn(c->layers_dev, n, sz.k, sz.kn_segs, c->stream));
+    const int flags = (check ? F_CHECK : 0) | (compact ? F_COMPACT : F_SPDZ);
+    const int zero_what = (compact ? 1 : 0) | (check ? 2 : 0);
+    if (zero_what) LAUNCH(c, ST_ZERO_ACC, launch_zero_acc(c->layers_dev, n, zero_what, sz.cvec, c->stream));
+    LAUNCH(c, ST_OPEN_U, launch_open_u(c->layers_dev, n, flags, sz.kn_items, c->stream));
+    LAUNCH(c, ST_ROW_PASS, launch_row_pass(c->layers_dev, n, flags, sz.m, c->stream));
     if (any_accum) LAUNCH(c, ST_COPY_BASE, launch_copy_base(c->layers_dev, n, mode, sz.mn, c->stream));
     if ((s = run_gemms(c, (int)probs.size(), nm, total_tiles)) != CT_OK) return s;
-    if (compact) {
-        LAUNCH(c, ST_POST_COMPACT, launch_post_compact(c->layers_dev, n, sz.m, sz.mn_segs, c->stream));
-        LAUNCH(c, ST_COMPACT_TAG, launch_compact_tag(c->layers_dev, n, sz.m, c->stream));
-    } else {
-        LAUNCH(c, ST_OPEN_D, launch_open_d(c->layers_dev, n, sz.mn, c->stream));
-    }
+    LAUNCH(c, ST_POST, launch_post(c->layers_dev, n, flags, sz.mn_items, c->stream));
+    if (compact) LAUNCH(c, ST_COMPACT_FINAL, launch_compact_final(c->layers_dev, n, flags, c->stream));
+    if (check) LAUNCH(c, ST_FINALIZE, launch_finalize(c->layers_dev, n, out_dev, c->stream));
     return CT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ct_status ct_tag_linear(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n) {
+    return online(c, mode, L, B, n, nullptr);
+}
+
+ct_status ct_tag_linear_check(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
+                              ct_check_result *out_dev) {
+    if (c && !out_dev) return fail(c, CT_EINVAL, "null result array");
+    return online(c, mode, L, B, n, out_dev);
 }
 
 ct_status ct_mac_check_device(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
                               ct_check_result *out_dev) {
+    if (!c) return CT_EINVAL;
     if (mode != CT_MODE_SPDZ2K && mode != CT_MODE_COMPACT) return fail(c, CT_EINVAL, "unknown mode");
     const bool compact = mode == CT_MODE_COMPACT;
     ct_status s = validate(c, L, B, n, NEED_INPUTS | NEED_TRIPLE | NEED_OUT | (compact ? NEED_CVEC : 0));
@@ -449,7 +481,7 @@ ct_status ct_mac_check_device(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, c
     const int mask = compact ? 0x3 : 0x7;
     LAUNCH(c, ST_CHECK_BATCH, launch_check_batch(c->layers_dev, n, mask, std::max({sz.mk, sz.kn, sz.mn}), c->stream));
     if (compact) LAUNCH(c, ST_CHECK_COMPACT, launch_check_compact(c->layers_dev, n, c->stream));
-    LAUNCH(c, ST_FINALIZE, launch_finalize(c->layers_dev, n, mode, out_dev, c->stream));
+    LAUNCH(c, ST_FINALIZE, launch_finalize(c->layers_dev, n, out_dev, c->stream));
     return CT_OK;
 }
 

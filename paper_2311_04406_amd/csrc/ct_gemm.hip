@@ -120,39 +120,48 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &P, int tm, int tn, int
 #pragma unroll
     for (int t = 0; t < 16; t++) acc[t] = v16i{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 
-    u128 ra[8], rb[8];
+    // Branch-free operand loads: buffer loads whose out-of-range offset returns
+    // zero.  Descriptors are based at the tile's first row (A) and at the K
+    // slice's first row (B), so 32-bit offsets suffice for any matrix size.
+    constexpr uint32_t OOB = 0x80000000u;
+    auto rsrc = [](const u128 *base, int64_t bytes) {
+        const int32_t nrec = bytes > 0x7FFFFFF0LL ? 0x7FFFFFF0 : (int32_t)bytes;
+        return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, nrec, 0x00020000);
+    };
+    const bool arow_ok = m0 + ar < M;
+    const bool bcol_ok = n0 + bc < N;
+    v4i ra[8], rb[8];
     auto gload = [&](int step) {
         const int seg = step >= P.ksteps_seg ? 1 : 0;
         const int kb = (step - seg * P.ksteps_seg) * BK;
         const u128 *Ls = seg ? P.L2 : P.L1;
         const u128 *Rs = seg ? P.R2 : P.R1;
-        const u128 *Rb = seg ? nullptr : P.R1b;
-        const int m = m0 + ar;
+        const auto ra_rs = rsrc(Ls + (int64_t)m0 * K, (int64_t)(M - m0) * K * 16);
+        const auto rb_rs = rsrc(Rs + (int64_t)kb * N, (int64_t)(K - kb) * N * 16);
 #pragma unroll
         for (int j = 0; j < 8; j++) {
             const int k = kb + akk + j;
-            ra[j] = (m < M && k < K) ? ld(Ls, (int64_t)m * K + k) : zero128();
+            const uint32_t off = (arow_ok && k < K) ? (uint32_t)(ar * K + k) * 16u : OOB;
+            ra[j] = __builtin_amdgcn_raw_buffer_load_b128(ra_rs, off, 0, 0);
         }
-        const int n = n0 + bc;
 #pragma unroll
         for (int j = 0; j < 8; j++) {
-            const int k = kb + bkk + j;
-            u128 v = zero128();
-            if (k < K && n < N) {
-                const int64_t idx = (int64_t)k * N + n;
-                v = ld(Rs, idx);
-                if (Rb != nullptr) v = add(v, mul64(ld(Rb, idx), P.s));
-            }
-            rb[j] = v;
+            const int kk = bkk + j;
+            const uint32_t off = (bcol_ok && kb + kk < K) ? (uint32_t)(kk * N + n0 + bc) * 16u : OOB;
+            rb[j] = __builtin_amdgcn_raw_buffer_load_b128(rb_rs, off, 0, 0);
         }
+    };
+    auto as128 = [](v4i v) {
+        return u128{(uint64_t)(uint32_t)v[0] | ((uint64_t)(uint32_t)v[1] << 32),
+                    (uint64_t)(uint32_t)v[2] | ((uint64_t)(uint32_t)v[3] << 32)};
     };
     auto lstore = [&](uint8_t *stage) {
         uint32_t w[8][4];
 #pragma unroll
-        for (int j = 0; j < 8; j++) to_digits(ra[j], w[j]);
+        for (int j = 0; j < 8; j++) to_digits(as128(ra[j]), w[j]);
         write_planes(stage, a_off, w);
 #pragma unroll
-        for (int j = 0; j < 8; j++) to_digits(rb[j], w[j]);
+        for (int j = 0; j < 8; j++) to_digits(as128(rb[j]), w[j]);
         write_planes(stage + OPBYTES, b_off, w);
     };
 
@@ -178,12 +187,15 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &P, int tm, int tn, int
         v4i b[16];
 #pragma unroll
         for (int j = 0; j < 16; j++) b[j] = *reinterpret_cast<const v4i *>(cur + OPBYTES + j * PLANE + b_frag);
+        v4i a = *reinterpret_cast<const v4i *>(cur + a_frag);
 #pragma unroll
         for (int i = 0; i < 16; i++) {
-            const v4i a = *reinterpret_cast<const v4i *>(cur + i * PLANE + a_frag);
+            // prefetch the next A digit plane while this one's products issue
+            const v4i an = *reinterpret_cast<const v4i *>(cur + ((i + 1) & 15) * PLANE + a_frag);
 #pragma unroll
             for (int j = 0; j < 16 - i; j++)
                 acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b[j], acc[i + j], 0, 0, 0);
+            a = an;
         }
 
         if (more) lstore(nxt);
@@ -236,10 +248,12 @@ hipError_t launch_gemm(const GemmProb *probs_dev, int nprobs, int total_tiles, i
 }
 
 // ---------------------------------------------------------------- skinny
-// Products with few output columns (N <= SKINNY_MAX_N, e.g. a fully connected
-// layer at batch 1) are bandwidth-bound row-times-matrix products: one
-// wavefront per output row, lanes striding over K with coalesced 16-byte
-// loads, 128-bit VALU multiply-adds, a wavefront reduction per column.
+// The dealer's triple product C~ = A~ B~ for layers with few output columns
+// (N <= SKINNY_MAX_N, e.g. a classifier layer at batch 1) is a bandwidth-bound
+// row-times-matrix product: one wavefront per output row, lanes striding over
+// K with coalesced 16-byte loads, 128-bit VALU multiply-adds, a wavefront
+// reduction per column.  (The online phase forms these products inside its
+// pass over E.)
 __global__ __launch_bounds__(256) void k_skinny(const GemmProb *__restrict__ probs, int nprobs) {
     const GemmProb P = probs[blockIdx.y];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -251,17 +265,13 @@ __global__ __launch_bounds__(256) void k_skinny(const GemmProb *__restrict__ pro
         for (int seg = 0; seg < (P.L2 ? 2 : 1); seg++) {
             const u128 *Ls = seg ? P.L2 : P.L1;
             const u128 *Rs = seg ? P.R2 : P.R1;
-            const u128 *Rb = seg ? nullptr : P.R1b;
             const u128 *row = Ls + (int64_t)m * K;
             for (int k = lane; k < K; k += 64) {
                 const u128 a = ld(row, k);
 #pragma unroll
                 for (int n = 0; n < SKINNY_MAX_N; n++) {
                     if (n < N) {
-                        const int64_t idx = (int64_t)k * N + n;
-                        u128 r = ld(Rs, idx);
-                        if (Rb != nullptr) r = add(r, mul64(ld(Rb, idx), P.s));
-                        acc[n] = mad(acc[n], a, r);
+                        acc[n] = mad(acc[n], a, ld(Rs, (int64_t)k * N + n));
                     }
                 }
             }

@@ -43,7 +43,19 @@ struct LayerDev {
     u128 *Y[2], *tY[2], *B[2], *tB[2];
     u128 *C[2], *tC[2], *R[2], *tR[2], *Z[2], *tZ[2];
     u128 *E, *U, *D, *cvec;
+    u128 *work;                 // caller workspace: A_0 + E | tA_0 + Delta_0 E | tA_1 + Delta_1 E (M x K each)
     u128 *acc;                  // check accumulators, ACC_PER_LAYER entries (context scratch)
+};
+
+// Layers with N <= SKINNY_MAX_N take their output products on the VALU inside
+// the pass that opens E (no MFMA tiles, no workspace).
+constexpr int SKINNY_MAX_N = 8;
+
+// Flags of the fused passes.
+enum PassFlags : int {
+    F_CHECK = 1,    // accumulate the MAC-check sums of the values the pass opens
+    F_COMPACT = 2,  // CompactTag protocol (compression, compact tag)
+    F_SPDZ = 4,     // SPDZ2k protocol (per-element tags by products)
 };
 
 // Check accumulators per layer: for W in (E, U, D): [sum chi*tW_0, sum chi*tW_1, sum chi*W].
@@ -62,21 +74,18 @@ __host__ __device__ inline CvecOff cvec_off(int64_t M, int64_t K) {
 }
 
 // One ring GEMM problem:
-//   out (+)= base + L1 * (R1 + s * R1b) + L2 * R2     (all mod 2^128)
-// L1, L2: M x K (row-major, ld K); R1, R1b, R2: K x N (ld N); out, base: M x N.
-// L2 == nullptr: single segment.  R1b == nullptr or s == 0: no fold term.
-// accumulate != 0: out already holds base and partial sums are added atomically.
+//   out (+)= base + L1 * R1 + L2 * R2     (all mod 2^128)
+// L1, L2: M x K (row-major, ld K); R1, R2: K x N (ld N); out, base: M x N.
+// L2 == nullptr: single segment.  accumulate != 0: out already holds base and
+// partial sums of K splits are added atomically.
 struct GemmProb {
-    const u128 *L1, *L2, *R1, *R1b, *R2, *base;
+    const u128 *L1, *L2, *R1, *R2, *base;
     u128 *out;
-    uint64_t s;
     int32_t M, N, K, accumulate;
     int32_t tiles_m, tiles_n, splits, steps_per_split;  // steps are 32-wide K slices
     int32_t ksteps_seg, nsteps, tile_begin, tiles;
 };
 
-// Skinny problem for N <= SKINNY_MAX_N: same algebra, VALU kernel, one wave per row.
-constexpr int SKINNY_MAX_N = 8;
 
 // ---- launchers (defined in the .hip files) ----
 hipError_t launch_gemm(const GemmProb *probs_dev, int nprobs, int total_tiles, int grid, hipStream_t st);
@@ -85,15 +94,26 @@ hipError_t launch_skinny(const GemmProb *probs_dev, int nprobs, int max_rows, hi
 hipError_t launch_fill_zero(u128 *p, int64_t n, hipStream_t st);
 hipError_t launch_deal_lift(const LayerDev *L, int n, int64_t max_elems, hipStream_t st);
 hipError_t launch_deal_auth(const LayerDev *L, int n, int obj, int64_t max_elems, hipStream_t st);
-hipError_t launch_open(const LayerDev *L, int n, int64_t max_elems, hipStream_t st);
+hipError_t launch_zero_acc(const LayerDev *L, int n, int what, int64_t max_cvec, hipStream_t st);
 hipError_t launch_copy_base(const LayerDev *L, int n, int mode, int64_t max_elems, hipStream_t st);
-hipError_t launch_compress_kn(const LayerDev *L, int n, int64_t max_rows, int64_t max_segs, hipStream_t st);
-hipError_t launch_post_compact(const LayerDev *L, int n, int64_t max_rows, int64_t max_segs, hipStream_t st);
-hipError_t launch_open_d(const LayerDev *L, int n, int64_t max_elems, hipStream_t st);
-hipError_t launch_compact_tag(const LayerDev *L, int n, int64_t max_rows, hipStream_t st);
-hipError_t launch_zero_acc(const LayerDev *L, int n, int mode, int64_t max_rows, hipStream_t st);
+hipError_t launch_open_u(const LayerDev *L, int n, int flags, int64_t max_items, hipStream_t st);
+hipError_t launch_row_pass(const LayerDev *L, int n, int flags, int64_t max_rows, hipStream_t st);
+hipError_t launch_post(const LayerDev *L, int n, int flags, int64_t max_items, hipStream_t st);
+hipError_t launch_compact_final(const LayerDev *L, int n, int flags, hipStream_t st);
 hipError_t launch_check_batch(const LayerDev *L, int n, int which, int64_t max_elems, hipStream_t st);
 hipError_t launch_check_compact(const LayerDev *L, int n, hipStream_t st);
-hipError_t launch_finalize(const LayerDev *L, int n, int mode, ct_check_result *out, hipStream_t st);
+hipError_t launch_finalize(const LayerDev *L, int n, ct_check_result *out, hipStream_t st);
+
+// Number of wavefront work items of a row sweep over an R x N matrix (the
+// grid of the sweeping kernels is sized from it).
+inline int64_t sweep_items(int64_t rows, int64_t N) {
+    if (N <= 64) {
+        int64_t g = 1;
+        while (g < N) g <<= 1;
+        const int64_t rpw = 64 / g;
+        return (rows + rpw - 1) / rpw;
+    }
+    return rows * ((N + 511) / 512);
+}
 
 }  // namespace ct

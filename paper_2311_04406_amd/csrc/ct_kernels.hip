@@ -1,28 +1,108 @@
-// ct_kernels.hip -- the bandwidth-bound steps of the linear-layer hot path:
-// dealer fills, the openings of E, U and D, the optimistic tag, compression
-// along N, the compact tag and the batch MAC checks.
+// ct_kernels.hip -- the bandwidth-bound steps of the linear-layer hot path.
 //
-// Every kernel takes the layer table and handles all layers of a call: grid
-// dimension y indexes (layer, sub-object) and dimension x strides over the
-// elements (or rows) of that layer.  Reductions go wavefront -> workgroup in
-// registers and LDS, then one exact 128-bit atomic addition per workgroup.
+// The online phase touches every share array once, in three fused passes:
+//   k_open_u   over K x N: opens U = Y - B (Fig. 6 online step 1), compresses
+//              U and the tag shares of B along N (Fig. 6 step 6), and can
+//              accumulate the batch tag check of U (Fig. 1);
+//   k_row_pass over M x K, one wavefront per row: opens E = X - A, forms the
+//              compact-tag products E U^c, E [tB^c]_p, [tA]_p U^c (Eq. (7)),
+//              the folded operands A_0 + E and [tA]_p + [Delta]_p E of the
+//              matrix-core products, or -- for layers with N <= 8 -- the whole
+//              output (and SPDZ2k tag) products on the VALU, and can
+//              accumulate the batch tag check of E;
+//   k_post     over M x N, after the products: opens D = R - Z, writes the
+//              optimistic tag (Pi_OptMAC) and compresses D, tag(R), tag(C)
+//              along N (CompactTag), or accumulates the batch check of D
+//              (SPDZ2k);
+// then k_compact_final finishes Eq. (7) per row and can accumulate the compact
+// check of D (Fig. 6 verification).  With F_CHECK the verification sums are
+// formed by the passes that read the data anyway; without it ct_mac_check
+// recomputes them with k_check_batch / k_check_compact.
+//
+// Every kernel serves all layers of a call: grid dimension y indexes layers
+// (and sub-objects), dimension x strides over that layer's work.  Cross-
+// workgroup sums use exact 128-bit atomics into zeroed accumulators.
 #include "ct_device.h"
 
 namespace ct {
 
 constexpr int TPB = 256;
 constexpr int WAVES = TPB / 64;
+constexpr int SEGW = 512;  // elements per wavefront item of a long row
 
 __device__ __forceinline__ u128 key_sum(const LayerDev &L) {
     const uint64_t lo = L.delta[0] + L.delta[1];
     return u128{lo, lo < L.delta[0] ? 1ull : 0ull};
 }
 
+__device__ __forceinline__ bool nz(u128 v) { return (v.lo | v.hi) != 0; }
+
 static inline int grid_for(int64_t n) {
     int64_t g = (n + TPB - 1) / TPB;
     if (g > 8192) g = 8192;
     if (g < 1) g = 1;
     return (int)g;
+}
+static inline int grid_items(int64_t items) {  // one wavefront per item
+    int64_t g = (items + WAVES - 1) / WAVES;
+    if (g > 16384) g = 16384;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+// Adds each workgroup's NV sums (block-reduced) atomically into dst[0..NV).
+template <int NV>
+__device__ __forceinline__ void block_accumulate(u128 (&v)[NV], u128 *sh, u128 *dst) {
+    block_sum<NV, WAVES>(v, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; i++)
+            if (nz(v[i])) atomic_add128(dst + i, v[i]);
+    }
+}
+
+// Row sweep over an R x N matrix.  Rows of N <= 64 elements are reduced by
+// groups of G = pow2ceil(N) lanes (64 / G rows per wavefront); longer rows
+// are cut into items of SEGW elements, one wavefront each.  elem(r, c, v)
+// accumulates into the NV row sums v; row_done(r, v) receives each item's sums
+// (in the group leader lane) and must add them atomically.
+template <int NV, typename Elem, typename RowDone>
+__device__ __forceinline__ void row_sweep(int64_t rows, int64_t N, Elem elem, RowDone row_done) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave_id = (blockIdx.x * (int64_t)TPB + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * TPB) >> 6;
+    if (N <= 64) {
+        int G = 1;
+        while (G < N) G <<= 1;
+        const int rpw = 64 / G;
+        const int64_t items = (rows + rpw - 1) / rpw;
+        for (int64_t it = wave_id; it < items; it += nwaves) {
+            const int64_t r = it * rpw + lane / G;
+            const int c = lane % G;
+            u128 v[NV];
+#pragma unroll
+            for (int i = 0; i < NV; i++) v[i] = zero128();
+            if (r < rows && c < N) elem(r, (int64_t)c, v);
+            for (int m = G >> 1; m >= 1; m >>= 1) {
+#pragma unroll
+                for (int i = 0; i < NV; i++) v[i] = add(v[i], shfl_xor128(v[i], m));
+            }
+            if (c == 0 && r < rows) row_done(r, v);
+        }
+    } else {
+        const int64_t segs = (N + SEGW - 1) / SEGW, items = rows * segs;
+        for (int64_t it = wave_id; it < items; it += nwaves) {
+            const int64_t r = it / segs, c0 = (it % segs) * SEGW;
+            const int64_t c1 = c0 + SEGW < N ? c0 + SEGW : N;
+            u128 v[NV];
+#pragma unroll
+            for (int i = 0; i < NV; i++) v[i] = zero128();
+            for (int64_t c = c0 + lane; c < c1; c += 64) elem(r, c, v);
+#pragma unroll
+            for (int i = 0; i < NV; i++) v[i] = wave_sum(v[i]);
+            if (lane == 0) row_done(r, v);
+        }
+    }
 }
 
 // ---------------------------------------------------------------- fill
@@ -64,14 +144,15 @@ __global__ void k_deal_auth(const LayerDev *__restrict__ Ls, int obj_mask) {
     const int obj = blockIdx.y % 6 + 1;
     if (!((obj_mask >> obj) & 1)) return;
     int64_t n;
-    u128 **v, **t;
+    u128 *const *v;
+    u128 *const *t;
     switch (obj) {
-        case OBJ_X: n = L.M * L.K; v = (u128 **)L.X; t = (u128 **)L.tX; break;
-        case OBJ_Y: n = L.K * L.N; v = (u128 **)L.Y; t = (u128 **)L.tY; break;
-        case OBJ_A: n = L.M * L.K; v = (u128 **)L.A; t = (u128 **)L.tA; break;
-        case OBJ_B: n = L.K * L.N; v = (u128 **)L.B; t = (u128 **)L.tB; break;
-        case OBJ_C: n = L.M * L.N; v = (u128 **)L.C; t = (u128 **)L.tC; break;
-        default: n = L.M * L.N; v = (u128 **)L.R; t = (u128 **)L.tR; break;
+        case OBJ_X: n = L.M * L.K; v = L.X; t = L.tX; break;
+        case OBJ_Y: n = L.K * L.N; v = L.Y; t = L.tY; break;
+        case OBJ_A: n = L.M * L.K; v = L.A; t = L.tA; break;
+        case OBJ_B: n = L.K * L.N; v = L.B; t = L.tB; break;
+        case OBJ_C: n = L.M * L.N; v = L.C; t = L.tC; break;
+        default: n = L.M * L.N; v = L.R; t = L.tR; break;
     }
     u128 *v0 = v[0], *v1 = v[1], *t0 = t[0], *t1 = t[1];
     const uint64_t kv = L.key[K_VSH_X + obj - 1], kt = L.key[K_TSH_X + obj - 1];
@@ -97,35 +178,30 @@ hipError_t launch_deal_auth(const LayerDev *L, int n, int obj_mask, int64_t max_
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- open E, U
-// Fig. 6 online step 1 (Pi_BatchRec open): [W]_p = [P]_p - [Q]_p is each
-// party's broadcast share and W = [W]_0 + [W]_1.
-
-__global__ void k_open(const LayerDev *__restrict__ Ls) {
-    const LayerDev &L = Ls[blockIdx.y >> 1];
-    const int which = blockIdx.y & 1;  // 0: E = X - A, 1: U = Y - B
-    const int64_t n = which ? L.K * L.N : L.M * L.K;
-    const u128 *P0 = which ? L.Y[0] : L.X[0], *P1 = which ? L.Y[1] : L.X[1];
-    const u128 *Q0 = which ? L.B[0] : L.A[0], *Q1 = which ? L.B[1] : L.A[1];
-    u128 *W = which ? L.U : L.E;
-    for (int64_t e = blockIdx.x * (int64_t)TPB + threadIdx.x; e < n; e += (int64_t)gridDim.x * TPB) {
-        const u128 w0 = sub(ld(P0, e), ld(Q0, e));
-        const u128 w1 = sub(ld(P1, e), ld(Q1, e));
-        st(W, e, add(w0, w1));
+// ---------------------------------------------------------------- zeroing
+// what bit 0: the compressed vectors (cvec); bit 1: the check accumulators.
+__global__ void k_zero_acc(const LayerDev *__restrict__ Ls, int what) {
+    const LayerDev &L = Ls[blockIdx.y];
+    if (what & 1) {
+        const int64_t n = 3 * L.K + 10 * L.M;
+        for (int64_t e = blockIdx.x * (int64_t)TPB + threadIdx.x; e < n; e += (int64_t)gridDim.x * TPB)
+            st(L.cvec, e, zero128());
     }
+    if ((what & 2) && blockIdx.x == 0 && threadIdx.x < ACC_PER_LAYER) st(L.acc, threadIdx.x, zero128());
 }
 
-hipError_t launch_open(const LayerDev *L, int n, int64_t max_elems, hipStream_t st) {
-    hipLaunchKernelGGL(k_open, dim3(grid_for(max_elems), 2 * n), dim3(TPB), 0, st, L);
+hipError_t launch_zero_acc(const LayerDev *L, int n, int what, int64_t max_cvec, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_acc, dim3((what & 1) ? grid_for(max_cvec) : 1, n), dim3(TPB), 0, st, L, what);
     return hipGetLastError();
 }
 
 // Output arrays that receive split-K partial products start from their
-// constant term: [Z]_p = [C]_p, and in SPDZ2k mode [tZ]_p = [tC]_p.
+// constant term: [Z]_p = [C]_p, and in SPDZ2k mode [tZ]_p = [tC]_p.  Layers
+// whose products are formed in the row pass (N <= SKINNY_MAX_N) are skipped.
 __global__ void k_copy_base(const LayerDev *__restrict__ Ls, int spdz) {
     const LayerDev &L = Ls[blockIdx.y >> 2];
     const int which = blockIdx.y & 3;  // 0,1: Z_p ; 2,3: tZ_p
-    if (which >= 2 && !spdz) return;
+    if ((which >= 2 && !spdz) || L.N <= SKINNY_MAX_N) return;
     const int p = which & 1;
     const u128 *src = which >= 2 ? L.tC[p] : L.C[p];
     u128 *dst = which >= 2 ? L.tZ[p] : L.Z[p];
@@ -140,224 +216,286 @@ hipError_t launch_copy_base(const LayerDev *L, int n, int mode, int64_t max_elem
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- row reductions
-// Rows of an R x N matrix are reduced against chi (Pi_Compress).  Rows with
-// N <= SMALL_N are handled one per thread; longer rows are cut into segments
-// of SEG elements, one workgroup per segment, combined by 128-bit atomics into
-// the (pre-zeroed) destination.
-constexpr int SMALL_N = 64;
-constexpr int SEG = 4 * TPB;
-
-__device__ __forceinline__ int64_t segs_per_row(int64_t N) { return (N + SEG - 1) / SEG; }
-
-// Compress along N of the K x N matrices: U^c = U chi and [tB^c]_p = [tB]_p chi.
-__global__ void k_compress_kn(const LayerDev *__restrict__ Ls) {
+// ---------------------------------------------------------------- pass over K x N
+// [U]_p = [Y]_p - [B]_p is party p's broadcast share and U = [U]_0 + [U]_1
+// (Pi_BatchRec open).  CompactTag: U^c = U chi and [tB^c]_p = [tB]_p chi with
+// chi_j drawn per column (Pi_Compress).  F_CHECK: the batch check sums of U,
+// sum chi'_e ([tY]_p - [tB]_p) and sum chi'_e U_e.
+__global__ __launch_bounds__(TPB) void k_open_u(const LayerDev *__restrict__ Ls, int flags) {
     __shared__ u128 sh[3 * WAVES];
     const LayerDev &L = Ls[blockIdx.y];
     const int64_t K = L.K, N = L.N;
+    const bool check = flags & F_CHECK, compact = flags & F_COMPACT;
     const CvecOff o = cvec_off(L.M, K);
-    u128 *Uc = L.cvec + o.Uc, *tBc0 = L.cvec + o.tBc0, *tBc1 = L.cvec + o.tBc1;
-    const uint64_t kchi = L.key[K_CHI];
-    if (N <= SMALL_N) {
-        for (int64_t r = blockIdx.x * (int64_t)TPB + threadIdx.x; r < K; r += (int64_t)gridDim.x * TPB) {
-            u128 a = zero128(), b0 = zero128(), b1 = zero128();
-            for (int64_t j = 0; j < N; j++) {
-                const uint64_t c = sdraw(kchi, (uint64_t)j);
-                const int64_t e = r * N + j;
-                a = mad64(a, ld(L.U, e), c);
-                b0 = mad64(b0, ld(L.tB[0], e), c);
-                b1 = mad64(b1, ld(L.tB[1], e), c);
-            }
-            st(Uc, r, a);
-            st(tBc0, r, b0);
-            st(tBc1, r, b1);
+    u128 chk[3] = {zero128(), zero128(), zero128()};
+    const uint64_t kchi = L.key[K_CHI], kcu = L.key[K_CHI_U];
+    auto elem = [&](int64_t r, int64_t c, u128 (&v)[3]) {
+        const int64_t e = r * N + c;
+        const u128 tb0 = ld(L.tB[0], e), tb1 = ld(L.tB[1], e);
+        const u128 u = add(sub(ld(L.Y[0], e), ld(L.B[0], e)), sub(ld(L.Y[1], e), ld(L.B[1], e)));
+        st(L.U, e, u);
+        if (compact) {
+            const uint64_t x = sdraw(kchi, (uint64_t)c);
+            v[0] = mad64(v[0], u, x);
+            v[1] = mad64(v[1], tb0, x);
+            v[2] = mad64(v[2], tb1, x);
         }
-        return;
-    }
-    const int64_t spr = segs_per_row(N), nseg = K * spr;
-    for (int64_t sgi = blockIdx.x; sgi < nseg; sgi += gridDim.x) {
-        const int64_t r = sgi / spr, j0 = (sgi % spr) * SEG;
-        u128 v[3] = {zero128(), zero128(), zero128()};
-        for (int64_t j = j0 + threadIdx.x; j < j0 + SEG && j < N; j += TPB) {
-            const uint64_t c = sdraw(kchi, (uint64_t)j);
-            const int64_t e = r * N + j;
-            v[0] = mad64(v[0], ld(L.U, e), c);
-            v[1] = mad64(v[1], ld(L.tB[0], e), c);
-            v[2] = mad64(v[2], ld(L.tB[1], e), c);
+        if (check) {
+            const uint64_t x = sdraw(kcu, (uint64_t)e);
+            chk[0] = mad64(chk[0], sub(ld(L.tY[0], e), tb0), x);
+            chk[1] = mad64(chk[1], sub(ld(L.tY[1], e), tb1), x);
+            chk[2] = mad64(chk[2], u, x);
         }
-        block_sum<3, WAVES>(v, sh);
-        if (threadIdx.x == 0) {
-            atomic_add128(Uc + r, v[0]);
-            atomic_add128(tBc0 + r, v[1]);
-            atomic_add128(tBc1 + r, v[2]);
+    };
+    auto row_done = [&](int64_t r, u128 (&v)[3]) {
+        if (compact) {
+            atomic_add128(L.cvec + o.Uc + r, v[0]);
+            atomic_add128(L.cvec + o.tBc0 + r, v[1]);
+            atomic_add128(L.cvec + o.tBc1 + r, v[2]);
         }
-    }
+    };
+    row_sweep<3>(K, N, elem, row_done);
+    if (check) block_accumulate<3>(chk, sh, L.acc + 3);
 }
 
-static int row_grid(int64_t rows, int64_t max_segs) {
-    int64_t g = max_segs;
-    const int64_t gr = (rows + TPB - 1) / TPB;
-    if (gr > g) g = gr;
-    if (g > 16384) g = 16384;
-    if (g < 1) g = 1;
-    return (int)g;
-}
-
-hipError_t launch_compress_kn(const LayerDev *L, int n, int64_t max_rows, int64_t max_segs, hipStream_t st) {
-    hipLaunchKernelGGL(k_compress_kn, dim3(row_grid(max_rows, max_segs), n), dim3(TPB), 0, st, L);
+hipError_t launch_open_u(const LayerDev *L, int n, int flags, int64_t max_items, hipStream_t st) {
+    hipLaunchKernelGGL(k_open_u, dim3(grid_items(max_items), n), dim3(TPB), 0, st, L, flags);
     return hipGetLastError();
 }
 
-// COMPACT mode after the output GEMMs, per element of M x N:
-//   D~ = ([R]_0 - [Z]_0) + ([R]_1 - [Z]_1)          (Pi_OptMAC steps 1-2)
-//   [tZ]_p = [tR]_p - [Delta]_p D~                   (Pi_OptMAC step 3)
-// and the compressions D~^c, [tR^c]_p, [tC^c]_p (Fig. 6 step 6) of the rows.
-__device__ __forceinline__ u128 optmac_elem(const LayerDev &L, int64_t e) {
-    const u128 d0 = sub(ld(L.R[0], e), ld(L.Z[0], e));
-    const u128 d1 = sub(ld(L.R[1], e), ld(L.Z[1], e));
-    const u128 D = add(d0, d1);
-    st(L.D, e, D);
-    return D;
+// ---------------------------------------------------------------- pass over M x K
+// One wavefront per row m of E; lanes stride over k with coalesced loads.
+template <int NS>
+__device__ __forceinline__ void row_pass_body(const LayerDev &L, int flags, u128 (&chk)[3]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t M = L.M, K = L.K, N = L.N;
+    const bool check = flags & F_CHECK, compact = flags & F_COMPACT, spdz = flags & F_SPDZ;
+    const bool skinny = NS > 0;
+    const CvecOff o = cvec_off(M, K);
+    const u128 *Uc = L.cvec + o.Uc, *tBc0 = L.cvec + o.tBc0, *tBc1 = L.cvec + o.tBc1;
+    const uint64_t kce = L.key[K_CHI_E];
+    const uint64_t d0 = L.delta[0], d1 = L.delta[1];
+    u128 *AE0 = L.work, *tAE0 = L.work + M * K, *tAE1 = L.work + 2 * M * K;
+    for (int64_t m = blockIdx.x * (int64_t)WAVES + wave; m < M; m += (int64_t)gridDim.x * WAVES) {
+        // compact: E U^c, E tB^c_0, E tB^c_1, tA_0 U^c, tA_1 U^c
+        u128 cp[5] = {zero128(), zero128(), zero128(), zero128(), zero128()};
+        // skinny: Z_0, Z_1 (and SPDZ2k tZ_0, tZ_1) row products per column
+        u128 z0[NS > 0 ? NS : 1], z1[NS > 0 ? NS : 1], t0[NS > 0 ? NS : 1], t1[NS > 0 ? NS : 1];
+#pragma unroll
+        for (int j = 0; j < (NS > 0 ? NS : 1); j++) z0[j] = z1[j] = t0[j] = t1[j] = zero128();
+        const int64_t rb = m * K;
+        for (int64_t k = lane; k < K; k += 64) {
+            const int64_t e = rb + k;
+            const u128 a0 = ld(L.A[0], e), a1 = ld(L.A[1], e);
+            const u128 E = add(sub(ld(L.X[0], e), a0), sub(ld(L.X[1], e), a1));
+            st(L.E, e, E);
+            const bool need_ta = check || compact || (spdz && !skinny) || (spdz && skinny);
+            u128 ta0 = zero128(), ta1 = zero128();
+            if (need_ta) {
+                ta0 = ld(L.tA[0], e);
+                ta1 = ld(L.tA[1], e);
+            }
+            if (check) {
+                const uint64_t x = sdraw(kce, (uint64_t)e);
+                chk[0] = mad64(chk[0], sub(ld(L.tX[0], e), ta0), x);
+                chk[1] = mad64(chk[1], sub(ld(L.tX[1], e), ta1), x);
+                chk[2] = mad64(chk[2], E, x);
+            }
+            if (compact) {
+                const u128 uc = ld(Uc, k);
+                cp[0] = mad(cp[0], E, uc);
+                cp[1] = mad(cp[1], E, ld(tBc0, k));
+                cp[2] = mad(cp[2], E, ld(tBc1, k));
+                cp[3] = mad(cp[3], ta0, uc);
+                cp[4] = mad(cp[4], ta1, uc);
+            }
+            if constexpr (!skinny) {
+                // folded left operands of the matrix-core products:
+                //   [Z]_0 = [C]_0 + E [B]_0 + (A_0 + E) U,
+                //   [tZ]_p = [tC]_p + E [tB]_p + ([tA]_p + [Delta]_p E) U
+                st(AE0, e, add(a0, E));
+                if (spdz) {
+                    st(tAE0, e, add(ta0, mul64(E, d0)));
+                    st(tAE1, e, add(ta1, mul64(E, d1)));
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < NS; j++) {
+                    if (j < N) {
+                        const int64_t kn = k * N + j;
+                        const u128 u = ld(L.U, kn);
+                        z0[j] = mad(mad(z0[j], E, add(ld(L.B[0], kn), u)), a0, u);
+                        z1[j] = mad(mad(z1[j], E, ld(L.B[1], kn)), a1, u);
+                        if (spdz) {
+                            t0[j] = mad(mad(t0[j], E, add(ld(L.tB[0], kn), mul64(u, d0))), ta0, u);
+                            t1[j] = mad(mad(t1[j], E, add(ld(L.tB[1], kn), mul64(u, d1))), ta1, u);
+                        }
+                    }
+                }
+            }
+        }
+        if (compact) {
+#pragma unroll
+            for (int i = 0; i < 5; i++) cp[i] = wave_sum(cp[i]);
+            if (lane == 0) {
+                st(L.cvec + o.EUc, m, cp[0]);
+                // partial compact tags; k_compact_final adds [tC^c]_p and [Delta]_p (E U^c)
+                st(L.cvec + o.tZc0, m, add(cp[1], cp[3]));
+                st(L.cvec + o.tZc1, m, add(cp[2], cp[4]));
+            }
+        }
+        if constexpr (skinny) {
+#pragma unroll
+            for (int j = 0; j < NS; j++) {
+                if (j < N) {
+                    z0[j] = wave_sum(z0[j]);
+                    z1[j] = wave_sum(z1[j]);
+                    if (spdz) {
+                        t0[j] = wave_sum(t0[j]);
+                        t1[j] = wave_sum(t1[j]);
+                    }
+                    if (lane == 0) {
+                        const int64_t mn = m * N + j;
+                        st(L.Z[0], mn, add(ld(L.C[0], mn), z0[j]));
+                        st(L.Z[1], mn, add(ld(L.C[1], mn), z1[j]));
+                        if (spdz) {
+                            st(L.tZ[0], mn, add(ld(L.tC[0], mn), t0[j]));
+                            st(L.tZ[1], mn, add(ld(L.tC[1], mn), t1[j]));
+                        }
+                    }
+                }
+            }
+        }
+    }
 }
 
-__global__ void k_post_compact(const LayerDev *__restrict__ Ls) {
-    __shared__ u128 sh[5 * WAVES];
+__global__ __launch_bounds__(TPB) void k_row_pass(const LayerDev *__restrict__ Ls, int flags) {
+    __shared__ u128 sh[3 * WAVES];
+    const LayerDev &L = Ls[blockIdx.y];
+    u128 chk[3] = {zero128(), zero128(), zero128()};
+    if (L.N <= 1) row_pass_body<1>(L, flags, chk);
+    else if (L.N <= 2) row_pass_body<2>(L, flags, chk);
+    else if (L.N <= 4) row_pass_body<4>(L, flags, chk);
+    else if (L.N <= SKINNY_MAX_N) row_pass_body<SKINNY_MAX_N>(L, flags, chk);
+    else row_pass_body<0>(L, flags, chk);
+    if (flags & F_CHECK) block_accumulate<3>(chk, sh, L.acc + 0);
+}
+
+hipError_t launch_row_pass(const LayerDev *L, int n, int flags, int64_t max_rows, hipStream_t st) {
+    hipLaunchKernelGGL(k_row_pass, dim3(grid_items(max_rows), n), dim3(TPB), 0, st, L, flags);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- pass over M x N
+// D~ = ([R]_0 - [Z]_0) + ([R]_1 - [Z]_1) (Pi_OptMAC steps 1-2 / Pi_Truncation
+// step 1).  CompactTag: [tZ]_p = [tR]_p - [Delta]_p D~ (Pi_OptMAC step 3) and
+// the compressions D~^c, [tR^c]_p, [tC^c]_p (Fig. 6 step 6).  SPDZ2k with
+// F_CHECK: the batch check sums of D with [tD]_p = [tR]_p - [tZ]_p.
+__global__ __launch_bounds__(TPB) void k_post(const LayerDev *__restrict__ Ls, int flags) {
+    __shared__ u128 sh[3 * WAVES];
     const LayerDev &L = Ls[blockIdx.y];
     const int64_t M = L.M, N = L.N;
+    const bool check = flags & F_CHECK, compact = flags & F_COMPACT;
     const CvecOff o = cvec_off(M, L.K);
-    u128 *Dc = L.cvec + o.Dc, *tRc0 = L.cvec + o.tRc0, *tRc1 = L.cvec + o.tRc1;
-    u128 *tCc0 = L.cvec + o.tCc0, *tCc1 = L.cvec + o.tCc1;
-    const uint64_t kchi = L.key[K_CHI];
-    auto elem = [&](int64_t e, uint64_t c, u128 (&v)[5]) {
-        const u128 D = optmac_elem(L, e);
-        const u128 tr0 = ld(L.tR[0], e), tr1 = ld(L.tR[1], e);
-        st(L.tZ[0], e, sub(tr0, mul64(D, L.delta[0])));
-        st(L.tZ[1], e, sub(tr1, mul64(D, L.delta[1])));
-        v[0] = mad64(v[0], D, c);
-        v[1] = mad64(v[1], tr0, c);
-        v[2] = mad64(v[2], tr1, c);
-        v[3] = mad64(v[3], ld(L.tC[0], e), c);
-        v[4] = mad64(v[4], ld(L.tC[1], e), c);
-    };
-    if (N <= SMALL_N) {
-        for (int64_t r = blockIdx.x * (int64_t)TPB + threadIdx.x; r < M; r += (int64_t)gridDim.x * TPB) {
-            u128 v[5] = {zero128(), zero128(), zero128(), zero128(), zero128()};
-            for (int64_t j = 0; j < N; j++) elem(r * N + j, sdraw(kchi, (uint64_t)j), v);
-            st(Dc, r, v[0]);
-            st(tRc0, r, v[1]);
-            st(tRc1, r, v[2]);
-            st(tCc0, r, v[3]);
-            st(tCc1, r, v[4]);
+    const uint64_t kchi = L.key[K_CHI], kcd = L.key[K_CHI_D];
+    u128 chk[3] = {zero128(), zero128(), zero128()};
+    if (compact) {
+        auto elem = [&](int64_t r, int64_t c, u128 (&v)[5]) {
+            const int64_t e = r * N + c;
+            const u128 D = add(sub(ld(L.R[0], e), ld(L.Z[0], e)), sub(ld(L.R[1], e), ld(L.Z[1], e)));
+            st(L.D, e, D);
+            const u128 tr0 = ld(L.tR[0], e), tr1 = ld(L.tR[1], e);
+            st(L.tZ[0], e, sub(tr0, mul64(D, L.delta[0])));
+            st(L.tZ[1], e, sub(tr1, mul64(D, L.delta[1])));
+            const uint64_t x = sdraw(kchi, (uint64_t)c);
+            v[0] = mad64(v[0], D, x);
+            v[1] = mad64(v[1], tr0, x);
+            v[2] = mad64(v[2], tr1, x);
+            v[3] = mad64(v[3], ld(L.tC[0], e), x);
+            v[4] = mad64(v[4], ld(L.tC[1], e), x);
+        };
+        auto row_done = [&](int64_t r, u128 (&v)[5]) {
+            atomic_add128(L.cvec + o.Dc + r, v[0]);
+            atomic_add128(L.cvec + o.tRc0 + r, v[1]);
+            atomic_add128(L.cvec + o.tRc1 + r, v[2]);
+            atomic_add128(L.cvec + o.tCc0 + r, v[3]);
+            atomic_add128(L.cvec + o.tCc1 + r, v[4]);
+        };
+        row_sweep<5>(M, N, elem, row_done);
+    } else {
+        const int64_t n = M * N;
+        for (int64_t e = blockIdx.x * (int64_t)TPB + threadIdx.x; e < n; e += (int64_t)gridDim.x * TPB) {
+            const u128 z0 = ld(L.Z[0], e), z1 = ld(L.Z[1], e);
+            const u128 D = add(sub(ld(L.R[0], e), z0), sub(ld(L.R[1], e), z1));
+            st(L.D, e, D);
+            if (check) {
+                const uint64_t x = sdraw(kcd, (uint64_t)e);
+                chk[0] = mad64(chk[0], sub(ld(L.tR[0], e), ld(L.tZ[0], e)), x);
+                chk[1] = mad64(chk[1], sub(ld(L.tR[1], e), ld(L.tZ[1], e)), x);
+                chk[2] = mad64(chk[2], D, x);
+            }
         }
-        return;
-    }
-    const int64_t spr = segs_per_row(N), nseg = M * spr;
-    for (int64_t sgi = blockIdx.x; sgi < nseg; sgi += gridDim.x) {
-        const int64_t r = sgi / spr, j0 = (sgi % spr) * SEG;
-        u128 v[5] = {zero128(), zero128(), zero128(), zero128(), zero128()};
-        for (int64_t j = j0 + threadIdx.x; j < j0 + SEG && j < N; j += TPB)
-            elem(r * N + j, sdraw(kchi, (uint64_t)j), v);
-        block_sum<5, WAVES>(v, sh);
-        if (threadIdx.x == 0) {
-            atomic_add128(Dc + r, v[0]);
-            atomic_add128(tRc0 + r, v[1]);
-            atomic_add128(tRc1 + r, v[2]);
-            atomic_add128(tCc0 + r, v[3]);
-            atomic_add128(tCc1 + r, v[4]);
-        }
+        if (check) block_accumulate<3>(chk, sh, L.acc + 6);
     }
 }
 
-hipError_t launch_post_compact(const LayerDev *L, int n, int64_t max_rows, int64_t max_segs, hipStream_t st) {
-    hipLaunchKernelGGL(k_post_compact, dim3(row_grid(max_rows, max_segs), n), dim3(TPB), 0, st, L);
-    return hipGetLastError();
-}
-
-// SPDZ2k mode: open D~ = sum_p ([R]_p - [Z]_p) (Pi_Truncation step 1).
-__global__ void k_open_d(const LayerDev *__restrict__ Ls) {
-    const LayerDev &L = Ls[blockIdx.y];
-    const int64_t n = L.M * L.N;
-    for (int64_t e = blockIdx.x * (int64_t)TPB + threadIdx.x; e < n; e += (int64_t)gridDim.x * TPB)
-        optmac_elem(L, e);
-}
-
-hipError_t launch_open_d(const LayerDev *L, int n, int64_t max_elems, hipStream_t st) {
-    hipLaunchKernelGGL(k_open_d, dim3(grid_for(max_elems), n), dim3(TPB), 0, st, L);
+hipError_t launch_post(const LayerDev *L, int n, int flags, int64_t max_items, hipStream_t st) {
+    hipLaunchKernelGGL(k_post, dim3(grid_items(max_items), n), dim3(TPB), 0, st, L, flags);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- compact tag
-// Eq. (7) with the key on the public term, one wavefront per row of E:
-//   (E U^c)_m, [tZ^c]_p = [tC^c]_p + E [tB^c]_p + [tA]_p U^c + [Delta]_p (E U^c),
+// Eq. (7) with the key on the public term, per row m:
+//   [tZ^c]_p = [tC^c]_p + (E [tB^c]_p + [tA]_p U^c) + [Delta]_p (E U^c),
 //   [tD^c]_p = [tR^c]_p - [tZ^c]_p.
-__global__ void k_compact_tag(const LayerDev *__restrict__ Ls) {
+// F_CHECK: the compact check of D (Fig. 6 verification steps 2-5) in the
+// accumulator form of the batch checks,
+//   acc6 = -sum chihat_i [tD^c]_{0,i}, acc7 = -sum chihat_i [tD^c]_{1,i},
+//   acc8 = -sum chihat_i D^c_i,  so cs_p = acc_{6+p} - [Delta]_p acc8
+//        = sum_i chihat_i ([Delta]_p D^c_i - [tD^c]_{p,i})   (mod 2^128).
+__global__ __launch_bounds__(TPB) void k_compact_final(const LayerDev *__restrict__ Ls, int flags) {
+    __shared__ u128 sh[3 * WAVES];
     const LayerDev &L = Ls[blockIdx.y];
-    const int64_t M = L.M, K = L.K;
-    const CvecOff o = cvec_off(M, K);
-    const u128 *Uc = L.cvec + o.Uc, *tBc0 = L.cvec + o.tBc0, *tBc1 = L.cvec + o.tBc1;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int64_t m = blockIdx.x * (int64_t)WAVES + wave; m < M; m += (int64_t)gridDim.x * WAVES) {
-        u128 eu = zero128(), eb0 = zero128(), eb1 = zero128(), au0 = zero128(), au1 = zero128();
-        const u128 *Er = L.E + m * K, *A0 = L.tA[0] + m * K, *A1 = L.tA[1] + m * K;
-        for (int64_t k = lane; k < K; k += 64) {
-            const u128 e = ld(Er, k), uc = ld(Uc, k);
-            eu = mad(eu, e, uc);
-            eb0 = mad(eb0, e, ld(tBc0, k));
-            eb1 = mad(eb1, e, ld(tBc1, k));
-            au0 = mad(au0, ld(A0, k), uc);
-            au1 = mad(au1, ld(A1, k), uc);
+    const int64_t M = L.M;
+    const CvecOff o = cvec_off(M, L.K);
+    u128 *c = L.cvec;
+    u128 v[3] = {zero128(), zero128(), zero128()};
+    for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < M; i += (int64_t)gridDim.x * TPB) {
+        const u128 eu = ld(c + o.EUc, i);
+        const u128 z0 = add(add(ld(c + o.tCc0, i), ld(c + o.tZc0, i)), mul64(eu, L.delta[0]));
+        const u128 z1 = add(add(ld(c + o.tCc1, i), ld(c + o.tZc1, i)), mul64(eu, L.delta[1]));
+        const u128 dd0 = sub(ld(c + o.tRc0, i), z0), dd1 = sub(ld(c + o.tRc1, i), z1);
+        st(c + o.tZc0, i, z0);
+        st(c + o.tZc1, i, z1);
+        st(c + o.tDc0, i, dd0);
+        st(c + o.tDc1, i, dd1);
+        if (flags & F_CHECK) {
+            const uint64_t x = sdraw(L.key[K_CHIHAT], (uint64_t)i);
+            v[0] = mad64(v[0], dd0, x);
+            v[1] = mad64(v[1], dd1, x);
+            v[2] = mad64(v[2], ld(c + o.Dc, i), x);
         }
-        eu = wave_sum(eu);
-        eb0 = wave_sum(eb0);
-        eb1 = wave_sum(eb1);
-        au0 = wave_sum(au0);
-        au1 = wave_sum(au1);
-        if (lane == 0) {
-            st(L.cvec + o.EUc, m, eu);
-            u128 z0 = add(add(add(ld(L.cvec + o.tCc0, m), eb0), au0), mul64(eu, L.delta[0]));
-            u128 z1 = add(add(add(ld(L.cvec + o.tCc1, m), eb1), au1), mul64(eu, L.delta[1]));
-            st(L.cvec + o.tZc0, m, z0);
-            st(L.cvec + o.tZc1, m, z1);
-            st(L.cvec + o.tDc0, m, sub(ld(L.cvec + o.tRc0, m), z0));
-            st(L.cvec + o.tDc1, m, sub(ld(L.cvec + o.tRc1, m), z1));
-        }
+    }
+    if (flags & F_CHECK) {
+#pragma unroll
+        for (int i = 0; i < 3; i++) v[i] = sub(zero128(), v[i]);
+        block_accumulate<3>(v, sh, L.acc + 6);
     }
 }
 
-hipError_t launch_compact_tag(const LayerDev *L, int n, int64_t max_rows, hipStream_t st) {
-    int64_t g = (max_rows + WAVES - 1) / WAVES;
-    if (g > 8192) g = 8192;
-    if (g < 1) g = 1;
-    hipLaunchKernelGGL(k_compact_tag, dim3((int)g, n), dim3(TPB), 0, st, L);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------- zeroing
-// what = 1: the compressed vectors accumulated by atomics; what = 2: the
-// check accumulators.
-__global__ void k_zero_acc(const LayerDev *__restrict__ Ls, int what) {
-    const LayerDev &L = Ls[blockIdx.y];
-    if (what == 1) {
-        const int64_t n = 3 * L.K + 10 * L.M;
-        for (int64_t e = blockIdx.x * (int64_t)TPB + threadIdx.x; e < n; e += (int64_t)gridDim.x * TPB)
-            st(L.cvec, e, zero128());
-    } else if (blockIdx.x == 0 && threadIdx.x < ACC_PER_LAYER) {
-        st(L.acc, threadIdx.x, zero128());
-    }
-}
-
-hipError_t launch_zero_acc(const LayerDev *L, int n, int what, int64_t max_rows, hipStream_t st) {
-    hipLaunchKernelGGL(k_zero_acc, dim3(what == 1 ? grid_for(max_rows) : 1, n), dim3(TPB), 0, st, L, what);
+hipError_t launch_compact_final(const LayerDev *L, int n, int flags, hipStream_t st) {
+    hipLaunchKernelGGL(k_compact_final, dim3(4, n), dim3(TPB), 0, st, L, flags);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- MAC checks
-// Pi_BatchRec tag check (Fig. 1) of an opened W = P - Q with one public
-// combiner chi'_e per element (drawn from the layer's stream; never stored):
+// Standalone verification (ct_mac_check): Pi_BatchRec tag check (Fig. 1) of
+// an opened W = P - Q with one public combiner chi'_e per element (drawn from
+// the layer's stream; never stored):
 //   acc0 = sum chi' ([tP]_0 - [tQ]_0),  acc1 = sum chi' ([tP]_1 - [tQ]_1),
 //   accW = sum chi' W;   cs_p = acc_p - [Delta]_p accW   (mod 2^128).
 // y = layer * 3 + which; which = 0: E (X, A), 1: U (Y, B), 2: D (R, Z).
-__global__ void k_check_batch(const LayerDev *__restrict__ Ls, int which_mask) {
+__global__ __launch_bounds__(TPB) void k_check_batch(const LayerDev *__restrict__ Ls, int which_mask) {
     __shared__ u128 sh[3 * WAVES];
     const LayerDev &L = Ls[blockIdx.y / 3];
     const int which = blockIdx.y % 3;
@@ -372,6 +510,7 @@ __global__ void k_check_batch(const LayerDev *__restrict__ Ls, int which_mask) {
     } else {
         n = L.M * L.N; tP0 = L.tR[0]; tP1 = L.tR[1]; tQ0 = L.tZ[0]; tQ1 = L.tZ[1]; W = L.D; key = L.key[K_CHI_D];
     }
+    if (blockIdx.x * (int64_t)TPB >= n) return;  // no elements for this workgroup
     u128 v[3] = {zero128(), zero128(), zero128()};
     for (int64_t e = blockIdx.x * (int64_t)TPB + threadIdx.x; e < n; e += (int64_t)gridDim.x * TPB) {
         const uint64_t c = sdraw(key, (uint64_t)e);
@@ -379,13 +518,7 @@ __global__ void k_check_batch(const LayerDev *__restrict__ Ls, int which_mask) {
         v[1] = mad64(v[1], sub(ld(tP1, e), ld(tQ1, e)), c);
         v[2] = mad64(v[2], ld(W, e), c);
     }
-    block_sum<3, WAVES>(v, sh);
-    if (threadIdx.x == 0) {
-        u128 *acc = L.acc + 3 * which;
-        atomic_add128(acc + 0, v[0]);
-        atomic_add128(acc + 1, v[1]);
-        atomic_add128(acc + 2, v[2]);
-    }
+    block_accumulate<3>(v, sh, L.acc + 3 * which);
 }
 
 hipError_t launch_check_batch(const LayerDev *L, int n, int which_mask, int64_t max_elems, hipStream_t st) {
@@ -395,12 +528,9 @@ hipError_t launch_check_batch(const LayerDev *L, int n, int which_mask, int64_t 
     return hipGetLastError();
 }
 
-// Compact check of D (Fig. 6 verification steps 2-5), kept in the same
-// accumulator form as the batch checks:
-//   acc6 = -sum chihat_i [tD^c]_{0,i},  acc7 = -sum chihat_i [tD^c]_{1,i},
-//   acc8 = -sum chihat_i D^c_i,   so  cs_p = acc_{6+p} - [Delta]_p acc8
-//        = sum_i chihat_i ([Delta]_p D^c_i - [tD^c]_{p,i})   (mod 2^128).
-__global__ void k_check_compact(const LayerDev *__restrict__ Ls) {
+// Standalone compact check of D from the stored compact vectors (same
+// accumulator form as in k_compact_final).
+__global__ __launch_bounds__(TPB) void k_check_compact(const LayerDev *__restrict__ Ls) {
     __shared__ u128 sh[3 * WAVES];
     const LayerDev &L = Ls[blockIdx.y];
     const int64_t M = L.M;
@@ -448,8 +578,7 @@ __global__ void k_finalize(const LayerDev *__restrict__ Ls, int n, ct_check_resu
     out[l] = r;
 }
 
-hipError_t launch_finalize(const LayerDev *L, int n, int mode, ct_check_result *out, hipStream_t st) {
-    (void)mode;
+hipError_t launch_finalize(const LayerDev *L, int n, ct_check_result *out, hipStream_t st) {
     hipLaunchKernelGGL(k_finalize, dim3((n + TPB - 1) / TPB), dim3(TPB), 0, st, L, n, out);
     return hipGetLastError();
 }

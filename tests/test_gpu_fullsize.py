@@ -26,11 +26,17 @@ def ctx():
 
 
 def run_config(ctx, mode, specs):
+    """All layers in one fused call (the benchmark's launch configuration),
+    then the standalone verification, which must agree record by record."""
+    from paper_2311_04406_amd import Context
     layers = gpu_layers(ctx, specs)
     ctx.gen_triple_tags(layers)
-    ctx.tag_linear(mode, layers)
+    out = torch.zeros(14 * len(specs), dtype=torch.int64, device="cuda:0")
+    ctx.tag_linear_check(mode, layers, out)
+    fused = Context.decode_results(out, len(specs))
     status, res = ctx.mac_check(mode, layers)
     torch.cuda.synchronize()
+    assert [f.cs for f in fused] == [r.cs for r in res]
     return layers, status, res
 
 

@@ -86,6 +86,28 @@ def test_repeat_runs_identical(ctx, mode):
     free()
 
 
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("spec", SMALL, ids=lambda s: s.name)
+def test_fused_verification_matches(ctx, mode, spec):
+    """ct_tag_linear_check gives the same outputs and check records as
+    ct_tag_linear followed by ct_mac_check, and as the oracle."""
+    from paper_2311_04406_amd import Context
+    say(f"[fused] mode={mode} shape={spec.name}")
+    layers = gpu_layers(ctx, [spec])
+    ctx.gen_triple_tags(layers)
+    out = torch.zeros(14, dtype=torch.int64, device="cuda:0")
+    ctx.tag_linear_check(mode, layers, out)
+    torch.cuda.synchronize()
+    fused = Context.decode_results(out, 1)[0]
+    ol = oracle_run(mode, spec, KEY)
+    compare_layer(layers[0], ol, mode, what=spec.name)
+    compare_cs(fused, ol, what=spec.name)
+    assert fused.accept
+    status, sep = ctx.mac_check(mode, layers)
+    assert status == 0 and sep[0].cs == fused.cs
+    free()
+
+
 TAMPER = [("X", 1, 5, 0), ("tA", 0, 63, 0), ("B", 0, 31, 1), ("tY", 1, 0, 1), ("C", 1, 17, 2), ("tR", 0, 40, 2)]
 
 
@@ -105,10 +127,14 @@ def test_flipped_share_bit_aborts(ctx, mode, target):
     idx = 37 % flat.shape[0]
     limb = 0 if bit < 64 else 1
     flat[idx, limb] ^= (1 << (bit % 64)) if bit % 64 < 63 else -(1 << 63)
-    ctx.tag_linear(mode, layers)
+    out = torch.zeros(14, dtype=torch.int64, device="cuda:0")
+    ctx.tag_linear_check(mode, layers, out)
+    from paper_2311_04406_amd import Context
+    fused = Context.decode_results(out, 1)[0]
     status, res = ctx.mac_check(mode, layers)
-    assert status == CT_ABORT and not res[0].accept
+    assert status == CT_ABORT and not res[0].accept and not fused.accept
     assert res[0].sums()[w] != 0
+    assert fused.cs == res[0].cs
     ol = O.OracleLayer(s.M, s.K, s.N, s.seed, s.layer_id, KEY).deal()
     ol[name][party].reshape(-1, 2)[idx, limb] ^= np.uint64(1 << (bit % 64))
     ol.online(mode).check(mode)
