@@ -174,6 +174,7 @@ def main():
     ap.add_argument("--mode", default="compact", choices=["compact", "spdz2k"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the SPDZ2k and per-layer comparison runs")
+    ap.add_argument("--no-autotune", action="store_true", help="use the default matrix-core launch configuration")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -195,6 +196,10 @@ def main():
     out_dev = torch.zeros(len(layers) * 14, dtype=torch.int64, device="cuda:0")
     mkn = sum(s.mkn for s in specs)
 
+    tuning = None
+    if not args.no_autotune:
+        print("[bench] autotuning the matrix-core launch configuration ...", file=sys.stderr, flush=True)
+        tuning = ctx.autotune(mode_id, layers)
     print(f"[bench] timed {args.mode}: {args.warmup} warmup + {args.steps} steps", file=sys.stderr, flush=True)
     T, per, stages = run_steps(ctx, mode_id, [layers], out_dev, args.steps, args.warmup, torch, timing=True)
     res = Context.decode_results(out_dev, len(layers))
@@ -245,11 +250,16 @@ def main():
                    "layers_per_call": len(specs), "sum_MKN": mkn},
         "roofline": roofline,
         "stages": stage_rows,
+        "tuning": tuning,
     }
 
     if not args.no_compare:
         other = MODE_SPDZ2K if mode_id == MODE_COMPACT else MODE_COMPACT
         oname = "spdz2k" if other == MODE_SPDZ2K else "compact"
+        if not args.no_autotune:
+            ctx.autotune(other, layers)
+            for l in layers:
+                ctx.autotune(mode_id, [l])
         T2, per2, _ = run_steps(ctx, other, [layers], out_dev, args.steps, args.warmup, torch)
         out[oname] = {"value": round(mkn * args.steps / T2 / 1e9, 3), "ms_per_step": round(T2 / args.steps * 1e3, 4),
                       "p50_ms": round(pct(per2, 50), 4), "p99_ms": round(pct(per2, 99), 4)}

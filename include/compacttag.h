@@ -82,10 +82,14 @@ typedef struct {
 /* Layers with N <= CT_SKINNY_N form their output products in the pass that
  * opens E (bandwidth-bound, no workspace); wider layers use the matrix cores
  * and a workspace holding the folded left operands A_0 + E and, in SPDZ2k
- * mode, [tA]_p + [Delta]_p E (three M x K arrays).  The matrix-core path
- * needs K < 2^21 and N < 2^22. */
+ * mode, [tA]_p + [Delta]_p E (three M x K arrays), then the operands of the
+ * products converted to 8-bit digit tiles (five left operands of
+ * 64 x 32-element tiles over M x K and five right ones over N x K, 2048
+ * elements per tile).  The matrix-core path needs K < 2^21 and N < 2^22. */
 #define CT_SKINNY_N 8
-#define CT_WORK_LEN(M, K, N) ((N) > CT_SKINNY_N ? 3 * (M) * (K) : 0)
+#define CT_TILES_(D, K) ((((D) + 63) / 64) * (((K) + 31) / 32))
+#define CT_WORK_LEN(M, K, N) \
+    ((N) > CT_SKINNY_N ? 3 * (M) * (K) + 5 * 2048 * (CT_TILES_(M, K) + CT_TILES_(N, K)) : 0)
 
 /* cvec layout (element offsets): U^c [K] | tB^c_0 [K] | tB^c_1 [K] | D^c [M] | (E U^c) [M] |
  * tC^c_0 [M] | tC^c_1 [M] | tR^c_0 [M] | tR^c_1 [M] | tZ^c_0 [M] | tZ^c_1 [M] | tD^c_0 [M] | tD^c_1 [M] */
@@ -176,6 +180,34 @@ typedef struct {
  * previous call, the summed duration and launch count (at most max records;
  * *count receives the number of stages), then resets the totals. */
 ct_status ct_stage_times(ct_ctx *ctx, ct_stage_time *out, int max, int *count);
+
+/* Launch configuration of the matrix-core products. */
+typedef struct {
+    int32_t group_m;       /* output row tiles per group of the tile order (>= 1) */
+    int32_t xcd_remap;     /* 1: each XCD gets a contiguous range of the tile list */
+    int32_t split_target;  /* K slices of 32 per tile; 0 = as many tiles as fill the GPU twice */
+    int32_t reserved;
+    double gemm_ms;        /* ct_autotune: measured duration of the products per call */
+} ct_tuning;
+
+/* Autotuner: runs the online phase of this batch of layers (outputs written
+ * as by ct_tag_linear) once per candidate launch configuration (group_m in
+ * 1, 2, 4, 8, 16; XCD remap off and on; split_target 0, 16, 32, 64, 128),
+ * times the matrix-core products with HIP events (reps timed runs after one
+ * warm-up each), and keeps the fastest for this shape class -- the protocol
+ * and the rounded-up binary logarithms of M, K, N of every matrix-core
+ * layer.  Later calls of the same class use it.  Synchronizes; allocates the
+ * timing event pool if timing was never enabled.  best (may be NULL)
+ * receives the choice. */
+ct_status ct_autotune(ct_ctx *ctx, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n, int reps,
+                      ct_tuning *best);
+
+/* The configuration a call with these layers would use (gemm_ms = -1). */
+ct_status ct_get_tuning(const ct_ctx *ctx, ct_mode mode, const ct_layer_desc *L, int n, ct_tuning *out);
+
+/* Sets the configuration of shape classes never tuned and forgets all tuned
+ * ones. */
+ct_status ct_set_tuning(ct_ctx *ctx, const ct_tuning *t);
 
 /* Text of the last error on this context ("" if none). */
 const char *ct_last_error(const ct_ctx *ctx);

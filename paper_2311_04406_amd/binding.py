@@ -25,6 +25,15 @@ MODE_COMPACT = 1
 CT_OK, CT_EINVAL, CT_ENOMEM, CT_EDEVICE, CT_ABORT = 0, 1, 2, 3, 4
 STATUS = {0: "CT_OK", 1: "CT_EINVAL", 2: "CT_ENOMEM", 3: "CT_EDEVICE", 4: "CT_ABORT"}
 MASK64 = (1 << 64) - 1
+SKINNY_N = 8
+
+
+def work_len(M: int, K: int, N: int) -> int:
+    """CT_WORK_LEN of compacttag.h: workspace elements of one layer."""
+    if N <= SKINNY_N:
+        return 0
+    tiles = lambda d: ((d + 63) // 64) * ((K + 31) // 32)
+    return 3 * M * K + 5 * 2048 * (tiles(M) + tiles(N))
 
 
 class CtParams(ctypes.Structure):
@@ -40,7 +49,6 @@ class CtLayerDesc(ctypes.Structure):
 _P2 = ctypes.c_void_p * 2
 BUF_PAIRS = ["X", "tX", "A", "tA", "Y", "tY", "B", "tB", "C", "tC", "R", "tR", "Z", "tZ"]
 BUF_SINGLE = ["E", "U", "D", "cvec", "work"]
-SKINNY_N = 8
 
 
 class CtLayerBufs(ctypes.Structure):
@@ -49,6 +57,11 @@ class CtLayerBufs(ctypes.Structure):
 
 class CtStageTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 24), ("total_ms", ctypes.c_double), ("launches", ctypes.c_int64)]
+
+
+class CtTuning(ctypes.Structure):
+    _fields_ = [("group_m", ctypes.c_int32), ("xcd_remap", ctypes.c_int32), ("split_target", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("gemm_ms", ctypes.c_double)]
 
 
 class CtCheckResult(ctypes.Structure):
@@ -79,10 +92,15 @@ def load() -> ctypes.CDLL:
                                ctypes.POINTER(CtCheckResult)]
     L.ct_set_timing.argtypes = [vp, i]
     L.ct_stage_times.argtypes = [vp, ctypes.POINTER(CtStageTime), i, ctypes.POINTER(ctypes.c_int)]
+    L.ct_autotune.argtypes = [vp, i, ctypes.POINTER(CtLayerDesc), ctypes.POINTER(CtLayerBufs), i, i,
+                              ctypes.POINTER(CtTuning)]
+    L.ct_get_tuning.argtypes = [vp, i, ctypes.POINTER(CtLayerDesc), i, ctypes.POINTER(CtTuning)]
+    L.ct_set_tuning.argtypes = [vp, ctypes.POINTER(CtTuning)]
     L.ct_last_error.argtypes = [vp]
     L.ct_last_error.restype = ctypes.c_char_p
     for f in ("ct_create", "ct_destroy", "ct_key_shares", "ct_gen_triple_tags", "ct_tag_linear",
-              "ct_mac_check_device", "ct_mac_check", "ct_set_timing", "ct_stage_times", "ct_tag_linear_check"):
+              "ct_mac_check_device", "ct_mac_check", "ct_set_timing", "ct_stage_times", "ct_tag_linear_check", "ct_autotune", "ct_get_tuning",
+              "ct_set_tuning"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -125,12 +143,11 @@ class Layer:
         self.t["U"] = torch.zeros((K, N, 2), dtype=torch.int64, device=device)
         self.t["D"] = torch.zeros((M, N, 2), dtype=torch.int64, device=device)
         self.t["cvec"] = torch.zeros((3 * K + 10 * M, 2), dtype=torch.int64, device=device)
-        wl = 3 * M * K if N > SKINNY_N else 1
-        self.t["work"] = torch.zeros((wl, 2), dtype=torch.int64, device=device)
+        self.t["work"] = torch.zeros((max(1, work_len(M, K, N)), 2), dtype=torch.int64, device=device)
 
     @staticmethod
     def footprint_bytes(M: int, K: int, N: int) -> int:
-        return 16 * (9 * M * K + 9 * K * N + 13 * M * N + 3 * K + 10 * M + (3 * M * K if N > SKINNY_N else 0))
+        return 16 * (9 * M * K + 9 * K * N + 13 * M * N + 3 * K + 10 * M + work_len(M, K, N))
 
     def __getitem__(self, name):
         return self.t[name]
@@ -230,6 +247,25 @@ class Context:
         s = self._check(self.lib.ct_mac_check(self.h, mode, D, B, n, res), allow_abort=True)
         out = [_result(r) for r in res]
         return s, out
+
+    def autotune(self, mode: int, layers, reps: int = 2) -> dict:
+        """Chooses the matrix-core launch configuration for this layer batch's
+        shape class (runs the online phase once per candidate)."""
+        n, D, B = _arrays(layers)
+        t = CtTuning()
+        self._check(self.lib.ct_autotune(self.h, mode, D, B, n, reps, ctypes.byref(t)))
+        return {"group_m": t.group_m, "xcd_remap": t.xcd_remap, "split_target": t.split_target,
+                "gemm_ms": t.gemm_ms}
+
+    def get_tuning(self, mode: int, layers) -> dict:
+        n, D, B = _arrays(layers)
+        t = CtTuning()
+        self._check(self.lib.ct_get_tuning(self.h, mode, D, n, ctypes.byref(t)))
+        return {"group_m": t.group_m, "xcd_remap": t.xcd_remap, "split_target": t.split_target}
+
+    def set_tuning(self, group_m: int = 1, xcd_remap: int = 0, split_target: int = 0):
+        t = CtTuning(group_m, xcd_remap, split_target, 0, 0.0)
+        self._check(self.lib.ct_set_tuning(self.h, ctypes.byref(t)))
 
     def set_timing(self, enable: bool):
         self._check(self.lib.ct_set_timing(self.h, int(enable)))

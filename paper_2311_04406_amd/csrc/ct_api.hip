@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "compacttag.h"
@@ -21,12 +22,12 @@ using namespace ct;
 
 // Kernel stages, for the optional per-launch timing (ct_set_timing).
 enum Stage : int {
-    ST_DEAL_LIFT, ST_FILL_ZERO, ST_DEAL_AUTH, ST_DEAL_SKINNY, ST_ZERO_ACC, ST_OPEN_U, ST_ROW_PASS, ST_COPY_BASE,
-    ST_RING_GEMM, ST_POST, ST_COMPACT_FINAL, ST_CHECK_BATCH, ST_CHECK_COMPACT, ST_FINALIZE, ST_COUNT
+    ST_DEAL_LIFT, ST_FILL_ZERO, ST_DEAL_AUTH, ST_DEAL_SKINNY, ST_ZERO_ACC, ST_OPEN_U, ST_ROW_PASS, ST_PACK,
+    ST_COPY_BASE, ST_RING_GEMM, ST_POST, ST_COMPACT_FINAL, ST_CHECK_BATCH, ST_CHECK_COMPACT, ST_FINALIZE, ST_COUNT
 };
 static const char *kStageNames[ST_COUNT] = {
-    "deal_lift", "fill_zero", "deal_auth", "deal_skinny", "zero_acc", "open_u", "row_pass", "copy_base",
-    "ring_gemm", "post", "compact_final", "check_batch", "check_compact", "finalize"};
+    "deal_lift", "fill_zero", "deal_auth", "deal_skinny", "zero_acc", "open_u", "row_pass", "pack",
+    "copy_base", "ring_gemm", "post", "compact_final", "check_batch", "check_compact", "finalize"};
 constexpr int EV_POOL = 2048;
 
 struct ct_ctx {
@@ -37,6 +38,9 @@ struct ct_ctx {
     int num_cus = 256;
     LayerDev *layers_dev = nullptr, *layers_host = nullptr;
     GemmProb *gemm_dev = nullptr, *gemm_host = nullptr;
+    PackJob *pack_dev = nullptr, *pack_host = nullptr;
+    SkinnyProb *skinny_dev = nullptr, *skinny_host = nullptr;
+    int max_jobs = 0;
     u128 *acc_dev = nullptr;
     ct_check_result *res_dev = nullptr, *res_host = nullptr;
     hipEvent_t upload_done = nullptr;
@@ -48,6 +52,11 @@ struct ct_ctx {
     int ev_used = 0;
     double stage_ms[ST_COUNT] = {};
     int64_t stage_n[ST_COUNT] = {};
+    // launch configuration of the matrix-core products per shape class
+    std::unordered_map<uint64_t, GemmTuning> tuned;
+    GemmTuning fallback = {1, 0, 0};
+    bool forcing = false;
+    GemmTuning forced = {1, 0, 0};
 };
 
 namespace {
@@ -226,52 +235,94 @@ ct_status stage_layers(ct_ctx *c, const ct_layer_desc *L, const ct_layer_bufs *B
     return CT_OK;
 }
 
-ct_status upload(ct_ctx *c, int n, int nprobs) {
+ct_status upload(ct_ctx *c, int n, int nprobs, int njobs = 0, int nskinny = 0) {
     HIPCHK(c, hipMemcpyAsync(c->layers_dev, c->layers_host, sizeof(LayerDev) * n, hipMemcpyHostToDevice,
                              c->stream));
     if (nprobs > 0)
         HIPCHK(c, hipMemcpyAsync(c->gemm_dev, c->gemm_host, sizeof(GemmProb) * nprobs, hipMemcpyHostToDevice,
                                  c->stream));
+    if (njobs > 0)
+        HIPCHK(c, hipMemcpyAsync(c->pack_dev, c->pack_host, sizeof(PackJob) * njobs, hipMemcpyHostToDevice,
+                                 c->stream));
+    if (nskinny > 0)
+        HIPCHK(c, hipMemcpyAsync(c->skinny_dev, c->skinny_host, sizeof(SkinnyProb) * nskinny,
+                                 hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipEventRecord(c->upload_done, c->stream));
     return CT_OK;
 }
 
-GemmProb make_prob(const u128 *L1, const u128 *L2, const u128 *R1, const u128 *R2, const u128 *base, u128 *out,
+GemmProb make_prob(const u128 *Lp1, const u128 *Lp2, const u128 *Rp1, const u128 *Rp2, const u128 *base, u128 *out,
                    const ct_layer_desc &d) {
     GemmProb p;
     std::memset(&p, 0, sizeof(p));
-    p.L1 = L1; p.L2 = L2; p.R1 = R1; p.R2 = R2; p.base = base; p.out = out;
+    p.Lp1 = Lp1; p.Lp2 = Lp2; p.Rp1 = Rp1; p.Rp2 = Rp2; p.base = base; p.out = out;
     p.M = (int32_t)d.M; p.N = (int32_t)d.N; p.K = (int32_t)d.K;
     return p;
+}
+
+PackJob make_job(const u128 *src, u128 *dst, int64_t rows, int64_t cols, int side) {
+    PackJob j;
+    std::memset(&j, 0, sizeof(j));
+    j.src = src; j.dst = dst; j.rows = (int32_t)rows; j.cols = (int32_t)cols; j.side = side;
+    const int64_t major = side == 0 ? rows : cols, K = side == 0 ? cols : rows;
+    j.majt = (int32_t)((major + 63) / 64);
+    j.kt = (int32_t)((K + 31) / 32);
+    j.tiles = j.majt * j.kt;
+    return j;
+}
+
+// Assigns tile ranges to packing jobs; returns the total tile count.
+int plan_jobs(PackJob *jobs, int njobs) {
+    int t = 0;
+    for (int i = 0; i < njobs; i++) {
+        jobs[i].tile_begin = t;
+        t += jobs[i].tiles;
+    }
+    return t;
 }
 
 // Orders MFMA problems first, then skinny ones; assigns tiles and K splits.
 // Returns the number of MFMA problems; *total_tiles receives their tile count.
 constexpr int MAX_STEPS_PER_SPLIT = 255;  // keeps every int32 diagonal exact
 
-int plan_gemms(std::vector<GemmProb> &probs, int num_cus, int *total_tiles, bool *any_accum) {
-    std::stable_partition(probs.begin(), probs.end(), [](const GemmProb &p) { return p.N > SKINNY_MAX_N; });
-    int nm = 0;
+// Shape class of a call: the protocol and, per matrix-core layer, the
+// rounded-up binary logarithms of M, K and N (FNV-1a hash).
+uint64_t shape_class(int mode, const ct_layer_desc *L, int n) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) { h = (h ^ v) * 1099511628211ull; };
+    auto lg = [](int64_t v) { int r = 0; while ((1LL << r) < v) r++; return (uint64_t)r; };
+    mix((uint64_t)mode);
+    for (int l = 0; l < n; l++)
+        if (L[l].N > SKINNY_MAX_N) mix((lg(L[l].M) << 16) | (lg(L[l].K) << 8) | lg(L[l].N));
+    return h;
+}
+
+GemmTuning tuning_for(const ct_ctx *c, uint64_t key) {
+    if (c->forcing) return c->forced;
+    auto it = c->tuned.find(key);
+    return it == c->tuned.end() ? c->fallback : it->second;
+}
+
+int plan_gemms(std::vector<GemmProb> &probs, int num_cus, const GemmTuning &tu, int *total_tiles, bool *any_accum) {
     int64_t total_steps = 0;
     for (auto &p : probs) {
-        if (p.N <= SKINNY_MAX_N) break;
-        nm++;
         p.tiles_m = (p.M + 63) / 64;
         p.tiles_n = (p.N + 63) / 64;
-        p.ksteps_seg = (p.K + 31) / 32;
-        p.nsteps = p.ksteps_seg * (p.L2 ? 2 : 1);
+        p.kt = (p.K + 31) / 32;
+        p.nsteps = p.kt * (p.Lp2 ? 2 : 1);
+        p.group_m = std::max(1, std::min(tu.group_m, p.tiles_m));
         total_steps += (int64_t)p.tiles_m * p.tiles_n * p.nsteps;
     }
-    // K slices per tile: enough tiles for two rounds over the compute units,
-    // equal-length tiles across problems, at least 8 slices per tile (the
-    // split partials cost atomics), at most MAX_STEPS_PER_SPLIT (exactness).
-    int64_t target = (total_steps + 2LL * num_cus - 1) / (2LL * num_cus);
+    // K slices per tile: by default enough tiles for two rounds over the
+    // compute units, equal-length tiles across problems; at least 8 slices
+    // per tile (split partials cost atomics), at most MAX_STEPS_PER_SPLIT
+    // (exactness of the int32 diagonals).
+    int64_t target = tu.split_target > 0 ? tu.split_target : (total_steps + 2LL * num_cus - 1) / (2LL * num_cus);
     if (target < 8) target = 8;
     if (target > MAX_STEPS_PER_SPLIT) target = MAX_STEPS_PER_SPLIT;
     int tile = 0;
     *any_accum = false;
-    for (int i = 0; i < nm; i++) {
-        GemmProb &p = probs[i];
+    for (auto &p : probs) {
         const int64_t splits = std::max<int64_t>(1, (p.nsteps + target - 1) / target);
         p.steps_per_split = (int)((p.nsteps + splits - 1) / splits);
         p.splits = (p.nsteps + p.steps_per_split - 1) / p.steps_per_split;
@@ -282,19 +333,11 @@ int plan_gemms(std::vector<GemmProb> &probs, int num_cus, int *total_tiles, bool
         tile += p.tiles;
     }
     *total_tiles = tile;
-    return nm;
+    return (int)probs.size();
 }
 
-ct_status run_gemms(ct_ctx *c, int nprobs, int nm, int total_tiles) {
-    if (nm > 0) {
-        int grid = total_tiles;
-        LAUNCH(c, ST_RING_GEMM, launch_gemm(c->gemm_dev, nm, total_tiles, grid, c->stream));
-    }
-    if (nprobs > nm) {
-        int max_rows = 0;
-        for (int i = nm; i < nprobs; i++) max_rows = std::max(max_rows, c->gemm_host[i].M);
-        LAUNCH(c, ST_DEAL_SKINNY, launch_skinny(c->gemm_dev + nm, nprobs - nm, max_rows, c->stream));
-    }
+ct_status run_gemms(ct_ctx *c, int nprobs, int total_tiles, const GemmTuning &tu) {
+    if (nprobs > 0) LAUNCH(c, ST_RING_GEMM, launch_gemm(c->gemm_dev, nprobs, total_tiles, tu.xcd_remap, c->stream));
     return CT_OK;
 }
 
@@ -311,6 +354,7 @@ ct_status ct_create(ct_ctx **out, const ct_params *p) {
     c->stream = reinterpret_cast<hipStream_t>(p->hip_stream);
     c->max_layers = p->max_layers > 0 ? p->max_layers : 256;
     c->max_probs = 4 * c->max_layers;
+    c->max_jobs = 10 * c->max_layers;
     for (int q = 0; q < 2; q++) c->delta[q] = hdraw(hkey(p->key_seed, GLOBAL_LAYER, P_KEY + q), 0);
     auto bail = [&](hipError_t e, const char *what) {
         std::fprintf(stderr, "ct_create: %s: %s\n", what, hipGetErrorString(e));
@@ -324,6 +368,14 @@ ct_status ct_create(ct_ctx **out, const ct_params *p) {
         c->num_cus = cus;
     if ((e = hipMalloc(&c->layers_dev, sizeof(LayerDev) * c->max_layers)) != hipSuccess) return bail(e, "hipMalloc");
     if ((e = hipMalloc(&c->gemm_dev, sizeof(GemmProb) * c->max_probs)) != hipSuccess) return bail(e, "hipMalloc");
+    if ((e = hipMalloc(&c->pack_dev, sizeof(PackJob) * c->max_jobs)) != hipSuccess) return bail(e, "hipMalloc");
+    if ((e = hipMalloc(&c->skinny_dev, sizeof(SkinnyProb) * c->max_layers)) != hipSuccess)
+        return bail(e, "hipMalloc");
+    if ((e = hipHostMalloc(&c->pack_host, sizeof(PackJob) * c->max_jobs, hipHostMallocDefault)) != hipSuccess)
+        return bail(e, "hipHostMalloc");
+    if ((e = hipHostMalloc(&c->skinny_host, sizeof(SkinnyProb) * c->max_layers, hipHostMallocDefault)) !=
+        hipSuccess)
+        return bail(e, "hipHostMalloc");
     if ((e = hipMalloc(&c->acc_dev, sizeof(u128) * ACC_PER_LAYER * c->max_layers)) != hipSuccess)
         return bail(e, "hipMalloc");
     if ((e = hipMalloc(&c->res_dev, sizeof(ct_check_result) * c->max_layers)) != hipSuccess)
@@ -351,6 +403,10 @@ ct_status ct_destroy(ct_ctx *c) {
     if (c->layers_dev) hipFree(c->layers_dev);
     if (c->gemm_dev) hipFree(c->gemm_dev);
     if (c->acc_dev) hipFree(c->acc_dev);
+    if (c->pack_dev) hipFree(c->pack_dev);
+    if (c->skinny_dev) hipFree(c->skinny_dev);
+    if (c->pack_host) hipHostFree(c->pack_host);
+    if (c->skinny_host) hipHostFree(c->skinny_host);
     if (c->res_dev) hipFree(c->res_dev);
     if (c->layers_host) hipHostFree(c->layers_host);
     if (c->gemm_host) hipHostFree(c->gemm_host);
@@ -369,27 +425,50 @@ ct_status ct_key_shares(const ct_ctx *c, uint64_t out[2]) {
 const char *ct_last_error(const ct_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
 ct_status ct_gen_triple_tags(ct_ctx *c, const ct_layer_desc *L, const ct_layer_bufs *B, int n, int with_inputs) {
-    ct_status s = validate(c, L, B, n, NEED_TRIPLE | (with_inputs ? NEED_INPUTS : 0));
+    ct_status s = validate(c, L, B, n, NEED_TRIPLE | NEED_WORK | (with_inputs ? NEED_INPUTS : 0));
     if (s != CT_OK) return s;
     HIPCHK(c, hipSetDevice(c->device));
     if ((s = stage_layers(c, L, B, n)) != CT_OK) return s;
+    // C~ = A~ B~ with the lifts left in party 1's buffers: packed matrix-core
+    // product for wide layers (operand tiles in the workspace), VALU rows for
+    // layers with N <= SKINNY_MAX_N.
     std::vector<GemmProb> probs;
-    probs.reserve(n);
+    int njobs = 0, nskinny = 0;
     for (int l = 0; l < n; l++) {
         const LayerDev &o = c->layers_host[l];
-        probs.push_back(make_prob(o.A[1], nullptr, o.B[1], nullptr, nullptr, o.C[1], L[l]));
+        const ct_layer_desc &d = L[l];
+        if (d.N <= SKINNY_MAX_N) {
+            SkinnyProb sp;
+            std::memset(&sp, 0, sizeof(sp));
+            sp.L = o.A[1]; sp.R = o.B[1]; sp.out = o.C[1];
+            sp.M = (int32_t)d.M; sp.N = (int32_t)d.N; sp.K = (int32_t)d.K;
+            c->skinny_host[nskinny++] = sp;
+            continue;
+        }
+        const WorkOff w = work_off(d.M, d.K, d.N);
+        c->pack_host[njobs++] = make_job(o.A[1], o.work + w.Ep, d.M, d.K, 0);
+        c->pack_host[njobs++] = make_job(o.B[1], o.work + w.B0p, d.K, d.N, 1);
+        probs.push_back(make_prob(o.work + w.Ep, nullptr, o.work + w.B0p, nullptr, nullptr, o.C[1], d));
     }
+    const int pack_tiles = plan_jobs(c->pack_host, njobs);
     int total_tiles = 0;
     bool any_accum = false;
-    const int nm = plan_gemms(probs, c->num_cus, &total_tiles, &any_accum);
+    const GemmTuning tu = c->fallback;
+    const int nm = plan_gemms(probs, c->num_cus, tu, &total_tiles, &any_accum);
     std::copy(probs.begin(), probs.end(), c->gemm_host);
-    if ((s = upload(c, n, (int)probs.size())) != CT_OK) return s;
+    if ((s = upload(c, n, nm, njobs, nskinny)) != CT_OK) return s;
     const Sizes sz = max_sizes(L, n);
     LAUNCH(c, ST_DEAL_LIFT, launch_deal_lift(c->layers_dev, n, std::max(sz.mk, sz.kn), c->stream));
+    LAUNCH(c, ST_PACK, launch_pack(c->pack_dev, njobs, pack_tiles, c->stream));
     for (int i = 0; i < nm; i++)
         if (probs[i].accumulate)
             LAUNCH(c, ST_FILL_ZERO, launch_fill_zero(probs[i].out, (int64_t)probs[i].M * probs[i].N, c->stream));
-    if ((s = run_gemms(c, (int)probs.size(), nm, total_tiles)) != CT_OK) return s;
+    if ((s = run_gemms(c, nm, total_tiles, tu)) != CT_OK) return s;
+    if (nskinny > 0) {
+        int max_rows = 0;
+        for (int i = 0; i < nskinny; i++) max_rows = std::max(max_rows, c->skinny_host[i].M);
+        LAUNCH(c, ST_DEAL_SKINNY, launch_skinny(c->skinny_dev, nskinny, max_rows, c->stream));
+    }
     const int mask = (with_inputs ? ((1 << OBJ_X) | (1 << OBJ_Y)) : 0) | (1 << OBJ_A) | (1 << OBJ_B) |
                      (1 << OBJ_C) | (1 << OBJ_R);
     LAUNCH(c, ST_DEAL_AUTH, launch_deal_auth(c->layers_dev, n, mask, std::max({sz.mk, sz.kn, sz.mn}), c->stream));
@@ -418,33 +497,56 @@ ct_status online(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_layer
     // Eq. (2) with E U folded into party 0's left operand by the row pass:
     //   [Z]_0 = [C]_0 + E [B]_0 + (A_0 + E) U,   [Z]_1 = [C]_1 + E [B]_1 + [A]_1 U;
     // SPDZ2k tags of Eq. (3):  [tZ]_p = [tC]_p + E [tB]_p + ([tA]_p + [Delta]_p E) U.
+    // Every operand is converted once into digit tiles in the workspace.
     std::vector<GemmProb> probs;
     probs.reserve(4 * n);
+    int njobs = 0;
     for (int l = 0; l < n; l++) {
-        if (L[l].N <= SKINNY_MAX_N) continue;
+        const ct_layer_desc &d = L[l];
+        if (d.N <= SKINNY_MAX_N) continue;
         const LayerDev &o = c->layers_host[l];
-        const int64_t mk = L[l].M * L[l].K;
-        probs.push_back(make_prob(o.E, o.work, o.B[0], o.U, o.C[0], o.Z[0], L[l]));
-        probs.push_back(make_prob(o.E, o.A[1], o.B[1], o.U, o.C[1], o.Z[1], L[l]));
+        const WorkOff w = work_off(d.M, d.K, d.N);
+        u128 *W = o.work;
+        PackJob *J = c->pack_host;
+        J[njobs++] = make_job(o.E, W + w.Ep, d.M, d.K, 0);
+        J[njobs++] = make_job(W + w.AE0, W + w.AE0p, d.M, d.K, 0);
+        J[njobs++] = make_job(o.A[1], W + w.A1p, d.M, d.K, 0);
+        J[njobs++] = make_job(o.B[0], W + w.B0p, d.K, d.N, 1);
+        J[njobs++] = make_job(o.B[1], W + w.B1p, d.K, d.N, 1);
+        J[njobs++] = make_job(o.U, W + w.Up, d.K, d.N, 1);
+        probs.push_back(make_prob(W + w.Ep, W + w.AE0p, W + w.B0p, W + w.Up, o.C[0], o.Z[0], d));
+        probs.push_back(make_prob(W + w.Ep, W + w.A1p, W + w.B1p, W + w.Up, o.C[1], o.Z[1], d));
         if (!compact) {
-            probs.push_back(make_prob(o.E, o.work + mk, o.tB[0], o.U, o.tC[0], o.tZ[0], L[l]));
-            probs.push_back(make_prob(o.E, o.work + 2 * mk, o.tB[1], o.U, o.tC[1], o.tZ[1], L[l]));
+            J[njobs++] = make_job(W + w.tAE0, W + w.tAE0p, d.M, d.K, 0);
+            J[njobs++] = make_job(W + w.tAE1, W + w.tAE1p, d.M, d.K, 0);
+            J[njobs++] = make_job(o.tB[0], W + w.tB0p, d.K, d.N, 1);
+            J[njobs++] = make_job(o.tB[1], W + w.tB1p, d.K, d.N, 1);
+            probs.push_back(make_prob(W + w.Ep, W + w.tAE0p, W + w.tB0p, W + w.Up, o.tC[0], o.tZ[0], d));
+            probs.push_back(make_prob(W + w.Ep, W + w.tAE1p, W + w.tB1p, W + w.Up, o.tC[1], o.tZ[1], d));
         }
     }
+    const int pack_tiles = plan_jobs(c->pack_host, njobs);
     int total_tiles = 0;
     bool any_accum = false;
-    const int nm = plan_gemms(probs, c->num_cus, &total_tiles, &any_accum);
+    const GemmTuning tu = tuning_for(c, shape_class(mode, L, n));
+    const int nm = plan_gemms(probs, c->num_cus, tu, &total_tiles, &any_accum);
     std::copy(probs.begin(), probs.end(), c->gemm_host);
-    if ((s = upload(c, n, (int)probs.size())) != CT_OK) return s;
+    if ((s = upload(c, n, nm, njobs)) != CT_OK) return s;
 
     const Sizes sz = max_sizes(L, n);
     const int flags = (check ? F_CHECK : 0) | (compact ? F_COMPACT : F_SPDZ);
     const int zero_what = (compact ? 1 : 0) | (check ? 2 : 0);
     if (zero_what) LAUNCH(c, ST_ZERO_ACC, launch_zero_acc(c->layers_dev, n, zero_what, sz.cvec, c->stream));
     LAUNCH(c, ST_OPEN_U, launch_open_u(c->layers_dev, n, flags, sz.kn_items, c->stream));
-    LAUNCH(c, ST_ROW_PASS, launch_row_pass(c->layers_dev, n, flags, sz.m, c->stream));
+    int variants = 0;
+    for (int l = 0; l < n; l++) {
+        const int64_t N = L[l].N;
+        variants |= 1 << (N > SKINNY_MAX_N ? 0 : (N <= 1 ? 1 : (N <= 2 ? 2 : (N <= 4 ? 4 : SKINNY_MAX_N))));
+    }
+    LAUNCH(c, ST_ROW_PASS, launch_row_pass(c->layers_dev, n, flags, sz.m, variants, c->stream));
+    if (njobs > 0) LAUNCH(c, ST_PACK, launch_pack(c->pack_dev, njobs, pack_tiles, c->stream));
     if (any_accum) LAUNCH(c, ST_COPY_BASE, launch_copy_base(c->layers_dev, n, mode, sz.mn, c->stream));
-    if ((s = run_gemms(c, (int)probs.size(), nm, total_tiles)) != CT_OK) return s;
+    if ((s = run_gemms(c, nm, total_tiles, tu)) != CT_OK) return s;
     LAUNCH(c, ST_POST, launch_post(c->layers_dev, n, flags, sz.mn_items, c->stream));
     if (compact) LAUNCH(c, ST_COMPACT_FINAL, launch_compact_final(c->layers_dev, n, flags, c->stream));
     if (check) LAUNCH(c, ST_FINALIZE, launch_finalize(c->layers_dev, n, out_dev, c->stream));
@@ -515,6 +617,77 @@ ct_status ct_set_timing(ct_ctx *c, int enable) {
     }
     if (!enable) HIPCHK(c, fold_timing(c));
     c->timing = enable != 0;
+    return CT_OK;
+}
+
+ct_status ct_set_tuning(ct_ctx *c, const ct_tuning *t) {
+    if (!c || !t) return CT_EINVAL;
+    if (t->group_m < 1 || t->split_target < 0 || t->split_target > MAX_STEPS_PER_SPLIT)
+        return fail(c, CT_EINVAL, "invalid tuning");
+    c->fallback = GemmTuning{t->group_m, t->xcd_remap ? 1 : 0, t->split_target};
+    c->tuned.clear();
+    return CT_OK;
+}
+
+ct_status ct_get_tuning(const ct_ctx *c, ct_mode mode, const ct_layer_desc *L, int n, ct_tuning *out) {
+    if (!c || !L || !out || n < 1) return CT_EINVAL;
+    const GemmTuning t = tuning_for(c, shape_class(mode, L, n));
+    out->group_m = t.group_m;
+    out->xcd_remap = t.xcd_remap;
+    out->split_target = t.split_target;
+    out->gemm_ms = -1.0;
+    return CT_OK;
+}
+
+ct_status ct_autotune(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n, int reps,
+                      ct_tuning *best_out) {
+    if (!c) return CT_EINVAL;
+    if (reps < 1) reps = 1;
+    const bool was_timing = c->timing;
+    ct_status s = ct_set_timing(c, 1);
+    if (s != CT_OK) return s;
+    HIPCHK(c, fold_timing(c));
+    const double saved_ms = c->stage_ms[ST_RING_GEMM];
+    const int64_t saved_n = c->stage_n[ST_RING_GEMM];
+    static const int groups[] = {1, 2, 4, 8, 16};
+    static const int splits[] = {0, 16, 32, 64, 128};
+    GemmTuning best = c->fallback;
+    double best_ms = 1e30;
+    for (int xcd = 0; xcd < 2; xcd++)
+        for (int g : groups)
+            for (int sp : splits) {
+                c->forcing = true;
+                c->forced = GemmTuning{g, xcd, sp};
+                s = online(c, mode, L, B, n, nullptr);  // warm-up
+                if (s == CT_OK) {
+                    HIPCHK(c, fold_timing(c));
+                    c->stage_ms[ST_RING_GEMM] = 0;
+                    c->stage_n[ST_RING_GEMM] = 0;
+                    for (int r = 0; r < reps && s == CT_OK; r++) s = online(c, mode, L, B, n, nullptr);
+                }
+                if (s == CT_OK) {
+                    HIPCHK(c, fold_timing(c));
+                    const double ms = c->stage_ms[ST_RING_GEMM] / reps;
+                    if (c->stage_n[ST_RING_GEMM] > 0 && ms < best_ms) {
+                        best_ms = ms;
+                        best = c->forced;
+                    }
+                }
+                c->forcing = false;
+                if (s != CT_OK) return s;
+            }
+    c->stage_ms[ST_RING_GEMM] = saved_ms;
+    c->stage_n[ST_RING_GEMM] = saved_n;
+    if (!was_timing) {
+        c->timing = false;
+    }
+    c->tuned[shape_class(mode, L, n)] = best;
+    if (best_out) {
+        best_out->group_m = best.group_m;
+        best_out->xcd_remap = best.xcd_remap;
+        best_out->split_target = best.split_target;
+        best_out->gemm_ms = best_ms < 1e29 ? best_ms : -1.0;
+    }
     return CT_OK;
 }
 

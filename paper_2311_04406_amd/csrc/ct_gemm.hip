@@ -1,6 +1,6 @@
 // ct_gemm.hip -- exact matrix products over Z_{2^128} for gfx950.
 //
-// The local products of Eqs. (2)-(3) (E*[B]_p, [A]_p*U, E*U and their tag
+// The local products of Eqs. (2)-(3) (E [B]_p, [A]_p U, E U and their tag
 // counterparts) are dense contractions of 128-bit ring elements.  They run on
 // the int8 matrix cores (v_mfma_i32_32x32x32_i8) through an exact digit
 // decomposition:
@@ -19,13 +19,15 @@
 // xored with 0x80 and read as int8: adding 128 to every digit of the balanced
 // form gives a digit string in [0, 255], i.e. the ordinary bytes of x + K.
 //
-// Tile: 64 x 64 outputs per workgroup of 4 wavefronts (2 x 2), 32 x 32 per
-// wavefront, K sliced by 32.  The operands of a slice are converted to digits
-// by the loading threads and written to LDS as 16 digit planes per operand
-// (plane d holds digit d of a 64 x 32 tile, 32 bytes per row or column, the
-// two 16-byte halves swapped on every other group of 4 rows to spread LDS
-// banks); two slices are double-buffered (128 KB).  A wavefront keeps the 16
-// B digit fragments of its slice in registers and streams the A digits.
+// Data flow.  k_pack converts every operand once into digit tiles (64 major
+// indices x 32 k, 16 planes, 32 KB; layout in ct_internal.h) through an LDS
+// transpose.  k_ring_gemm then only copies tiles: a workgroup of 4
+// wavefronts owns a 64 x 64 output tile (32 x 32 per wavefront), streams one
+// 32-wide K slice at a time (A and B tiles, 64 KB) global -> LDS with
+// global_load_lds_dwordx4 into one of two statically distinct LDS stages
+// while the matrix cores work on the other, and reads 16-byte digit fragments
+// in a triangular order (fragment pair t unlocks 2t+1 or 2(16-t) products) so
+// the first products issue after a single fragment pair.
 #include "ct_device.h"
 
 namespace ct {
@@ -35,8 +37,9 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int BM = 64, BN = 64, BK = 32;
 constexpr int PLANE = BM * BK;       // bytes per digit plane of a 64 x 32 tile
-constexpr int OPBYTES = 16 * PLANE;  // 16 digit planes: 32 KB
-constexpr int STAGE = 2 * OPBYTES;   // A and B: 64 KB
+constexpr int OPBYTES = 16 * PLANE;  // 16 digit planes: 32 KB (= TILE_ELEMS * 16)
+constexpr int STAGE = 2 * OPBYTES;   // A and B tiles of one K slice: 64 KB
+static_assert(OPBYTES == TILE_ELEMS * 16, "tile size");
 
 __device__ __forceinline__ void to_digits(u128 x, uint32_t (&w)[4]) {
     const uint64_t K = 0x8080808080808080ull;
@@ -48,14 +51,16 @@ __device__ __forceinline__ void to_digits(u128 x, uint32_t (&w)[4]) {
     w[3] = (uint32_t)((hi ^ K) >> 32);
 }
 
-// byte offset of (row, k) inside one digit plane (k multiple of 8 or 16)
-__device__ __forceinline__ int plane_off(int row, int k) {
+// byte offset of (major j, k) inside one digit plane (k a multiple of 8);
+// the two 16-byte halves of a row swap on every other group of 4 rows, which
+// spreads the 16-byte fragment reads of 8 consecutive lanes over all banks.
+__device__ __forceinline__ int plane_off(int j, int k) {
     const int chunk = k >> 4;
-    return row * BK + (((chunk ^ (row >> 2)) & 1) << 4) + (k & 15);
+    return j * BK + (((chunk ^ (j >> 2)) & 1) << 4) + (k & 15);
 }
 
-// Transposes digits of 8 consecutive-k elements into 16 planes of 8 bytes and
-// writes them at base + d * PLANE + off.
+// Transposes the digits of 8 consecutive-k elements into 16 planes of 8 bytes
+// and writes them at base + d * PLANE + off.
 __device__ __forceinline__ void write_planes(uint8_t *base, int off, const uint32_t (&w)[8][4]) {
 #pragma unroll
     for (int q = 0; q < 4; q++) {  // dword q holds digits 4q .. 4q+3
@@ -81,6 +86,58 @@ __device__ __forceinline__ void write_planes(uint8_t *base, int off, const uint3
     }
 }
 
+// ---------------------------------------------------------------- packing
+// One workgroup per digit tile: 256 threads load 8 consecutive-k elements
+// each (a row segment of a left operand, a column segment of a right one),
+// write their digit planes to LDS, and the tile is stored with 16-byte
+// coalesced writes.
+__global__ __launch_bounds__(256) void k_pack(const PackJob *__restrict__ jobs, int njobs, int total_tiles) {
+    __shared__ __attribute__((aligned(16))) uint8_t tile[OPBYTES];
+    const int tid = threadIdx.x;
+    for (int t = blockIdx.x; t < total_tiles; t += gridDim.x) {
+        int lo = 0, hi = njobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+        }
+        const PackJob J = jobs[lo];
+        const int local = t - J.tile_begin;
+        const int tm = local / J.kt, ks = local % J.kt;
+        int j, kk;
+        if (J.side == 0) { j = tid >> 2; kk = (tid & 3) * 8; }
+        else { j = tid & 63; kk = (tid >> 6) * 8; }
+        const int major = tm * 64 + j;
+        uint32_t w[8][4];
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const int k = ks * 32 + kk + i;
+            u128 v = zero128();
+            if (J.side == 0) {
+                if (major < J.rows && k < J.cols) v = ld(J.src, (int64_t)major * J.cols + k);
+            } else {
+                if (k < J.rows && major < J.cols) v = ld(J.src, (int64_t)k * J.cols + major);
+            }
+            to_digits(v, w[i]);
+        }
+        write_planes(tile, plane_off(j, kk), w);
+        __syncthreads();
+        uint4 *dst = reinterpret_cast<uint4 *>(J.dst + ((int64_t)tm * J.kt + ks) * TILE_ELEMS);
+#pragma unroll
+        for (int i = 0; i < OPBYTES / 16 / 256; i++)
+            dst[i * 256 + tid] = reinterpret_cast<const uint4 *>(tile)[i * 256 + tid];
+        __syncthreads();
+    }
+}
+
+hipError_t launch_pack(const PackJob *jobs_dev, int njobs, int total_tiles, hipStream_t st) {
+    if (njobs <= 0 || total_tiles <= 0) return hipSuccess;
+    int grid = total_tiles < 65536 ? total_tiles : 65536;
+    hipLaunchKernelGGL(k_pack, dim3(grid), dim3(256), 0, st, jobs_dev, njobs, total_tiles);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- products
+
 // 2^sh * s (s a signed 32-bit diagonal sum) as an element of Z_{2^128}
 template <int SH>
 __device__ __forceinline__ u128 shifted(int32_t s) {
@@ -102,103 +159,80 @@ __device__ __forceinline__ void combine(const v16i (&acc)[16], int r, u128 &v) {
     }
 }
 
-__device__ __forceinline__ void gemm_tile(const GemmProb &P, int tm, int tn, int split, uint8_t *smem) {
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Copies the A and B digit tiles of one K slice into an LDS stage: 64 chunks
+// of 1 KB, 16 per wavefront, each a single global_load_lds_dwordx4 (lane l
+// moves bytes [16 l, 16 l + 16) of its chunk).
+__device__ __forceinline__ void issue_slice(const uint8_t *a_tile, const uint8_t *b_tile, uint8_t *stage) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+        const int c = wave * 16 + i;  // chunk 0..63: A 0..31, B 32..63
+        const uint8_t *src = (c < 32 ? a_tile + c * 1024 : b_tile + (c - 32) * 1024) + lane * 16;
+        __builtin_amdgcn_global_load_lds((const void *)src, (lds_void *)(stage + c * 1024), 16, 0, 0);
+    }
+}
+
+// The 136 digit products of one K slice from an LDS stage, fragments read in
+// triangular order.
+__device__ __forceinline__ void slice_products(const uint8_t *stage, int a_frag, int b_frag, v16i (&acc)[16]) {
+    v4i a[16], b[16];
+#pragma unroll
+    for (int t = 0; t < 16; t++) {
+        a[t] = *reinterpret_cast<const v4i *>(stage + t * PLANE + a_frag);
+        b[t] = *reinterpret_cast<const v4i *>(stage + OPBYTES + t * PLANE + b_frag);
+        // pairs (t, j) and (i, t) with i, j <= t and i + j <= 15 become available
+#pragma unroll
+        for (int j = 0; j <= t && t + j <= 15; j++)
+            acc[t + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[t], b[j], acc[t + j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < t && i + t <= 15; i++)
+            acc[i + t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[t], acc[i + t], 0, 0, 0);
+    }
+}
+
+// vmcnt(0), expcnt and lgkmcnt left unconstrained (gfx9 s_waitcnt encoding)
+#define WAIT_VMEM() __builtin_amdgcn_s_waitcnt(0x0F70)
+
+__device__ __forceinline__ void gemm_tile(const GemmProb &P, int tm, int tn, int split, uint8_t *lds) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    const int M = P.M, N = P.N, K = P.K;
+    const int M = P.M, N = P.N;
     const int m0 = tm * BM, n0 = tn * BN;
     const int s_begin = split * P.steps_per_split;
     const int s_end = min(s_begin + P.steps_per_split, P.nsteps);
-
-    // loader coordinates: A thread -> (row, 8 consecutive k); B thread -> (col, 8 consecutive k)
-    const int ar = tid >> 2, akk = (tid & 3) * 8;
-    const int bc = tid & 63, bkk = (tid >> 6) * 8;
-    const int a_off = plane_off(ar, akk);
-    const int b_off = plane_off(bc, bkk);
 
     v16i acc[16];
 #pragma unroll
     for (int t = 0; t < 16; t++) acc[t] = v16i{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 
-    // Branch-free operand loads: buffer loads whose out-of-range offset returns
-    // zero.  Descriptors are based at the tile's first row (A) and at the K
-    // slice's first row (B), so 32-bit offsets suffice for any matrix size.
-    constexpr uint32_t OOB = 0x80000000u;
-    auto rsrc = [](const u128 *base, int64_t bytes) {
-        const int32_t nrec = bytes > 0x7FFFFFF0LL ? 0x7FFFFFF0 : (int32_t)bytes;
-        return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, nrec, 0x00020000);
+    auto a_tile = [&](int step) {
+        const int seg = step >= P.kt ? 1 : 0;
+        const u128 *Lp = seg ? P.Lp2 : P.Lp1;
+        return reinterpret_cast<const uint8_t *>(Lp + ((int64_t)tm * P.kt + (step - seg * P.kt)) * TILE_ELEMS);
     };
-    const bool arow_ok = m0 + ar < M;
-    const bool bcol_ok = n0 + bc < N;
-    v4i ra[8], rb[8];
-    auto gload = [&](int step) {
-        const int seg = step >= P.ksteps_seg ? 1 : 0;
-        const int kb = (step - seg * P.ksteps_seg) * BK;
-        const u128 *Ls = seg ? P.L2 : P.L1;
-        const u128 *Rs = seg ? P.R2 : P.R1;
-        const auto ra_rs = rsrc(Ls + (int64_t)m0 * K, (int64_t)(M - m0) * K * 16);
-        const auto rb_rs = rsrc(Rs + (int64_t)kb * N, (int64_t)(K - kb) * N * 16);
-#pragma unroll
-        for (int j = 0; j < 8; j++) {
-            const int k = kb + akk + j;
-            const uint32_t off = (arow_ok && k < K) ? (uint32_t)(ar * K + k) * 16u : OOB;
-            ra[j] = __builtin_amdgcn_raw_buffer_load_b128(ra_rs, off, 0, 0);
-        }
-#pragma unroll
-        for (int j = 0; j < 8; j++) {
-            const int kk = bkk + j;
-            const uint32_t off = (bcol_ok && kb + kk < K) ? (uint32_t)(kk * N + n0 + bc) * 16u : OOB;
-            rb[j] = __builtin_amdgcn_raw_buffer_load_b128(rb_rs, off, 0, 0);
-        }
-    };
-    auto as128 = [](v4i v) {
-        return u128{(uint64_t)(uint32_t)v[0] | ((uint64_t)(uint32_t)v[1] << 32),
-                    (uint64_t)(uint32_t)v[2] | ((uint64_t)(uint32_t)v[3] << 32)};
-    };
-    auto lstore = [&](uint8_t *stage) {
-        uint32_t w[8][4];
-#pragma unroll
-        for (int j = 0; j < 8; j++) to_digits(as128(ra[j]), w[j]);
-        write_planes(stage, a_off, w);
-#pragma unroll
-        for (int j = 0; j < 8; j++) to_digits(as128(rb[j]), w[j]);
-        write_planes(stage + OPBYTES, b_off, w);
+    auto b_tile = [&](int step) {
+        const int seg = step >= P.kt ? 1 : 0;
+        const u128 *Rp = seg ? P.Rp2 : P.Rp1;
+        return reinterpret_cast<const uint8_t *>(Rp + ((int64_t)tn * P.kt + (step - seg * P.kt)) * TILE_ELEMS);
     };
 
-    // MFMA-side fragment offsets (lane -> row/col lane%32, k half lane/32)
+    // MFMA-side fragment offsets: lane -> row/column lane % 32, k half lane / 32
     const int chunk = lane >> 5;
     const int arow = wm * 32 + (lane & 31);
     const int brow = wn * 32 + (lane & 31);
     const int a_frag = arow * BK + (((chunk ^ (arow >> 2)) & 1) << 4);
     const int b_frag = brow * BK + (((chunk ^ (brow >> 2)) & 1) << 4);
 
-    if (s_begin < s_end) {
-        gload(s_begin);
-        lstore(smem);
-    }
+    if (s_begin < s_end) issue_slice(a_tile(s_begin), b_tile(s_begin), lds);
+    WAIT_VMEM();
     __syncthreads();
     for (int s = s_begin; s < s_end; s++) {
         const int buf = (s - s_begin) & 1;
-        const uint8_t *cur = smem + buf * STAGE;
-        uint8_t *nxt = smem + (buf ^ 1) * STAGE;
-        const bool more = s + 1 < s_end;
-        if (more) gload(s + 1);
-
-        v4i b[16];
-#pragma unroll
-        for (int j = 0; j < 16; j++) b[j] = *reinterpret_cast<const v4i *>(cur + OPBYTES + j * PLANE + b_frag);
-        v4i a = *reinterpret_cast<const v4i *>(cur + a_frag);
-#pragma unroll
-        for (int i = 0; i < 16; i++) {
-            // prefetch the next A digit plane while this one's products issue
-            const v4i an = *reinterpret_cast<const v4i *>(cur + ((i + 1) & 15) * PLANE + a_frag);
-#pragma unroll
-            for (int j = 0; j < 16 - i; j++)
-                acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b[j], acc[i + j], 0, 0, 0);
-            a = an;
-        }
-
-        if (more) lstore(nxt);
+        if (s + 1 < s_end) issue_slice(a_tile(s + 1), b_tile(s + 1), lds + (buf ^ 1) * STAGE);
+        slice_products(lds + buf * STAGE, a_frag, b_frag, acc);
+        WAIT_VMEM();
         __syncthreads();
     }
 
@@ -222,28 +256,47 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &P, int tm, int tn, int
     }
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2): block b runs on XCD b % 8.  With xcd_remap the tile list is cut into
+// 8 contiguous ranges, one per XCD, so the workgroups resident on an XCD at a
+// time work on neighbouring tiles.  Within a problem, tiles are numbered by K
+// split, then in column sweeps over groups of group_m row tiles: a run of
+// consecutive tiles covers a group_m x w block of the output and reads
+// group_m left and w right operand tiles per K slice.
+__device__ __forceinline__ int xcd_tile(int b, int total) {
+    const int q = total >> 3, r = total & 7;
+    const int x = b & 7, i = b >> 3;
+    return x * q + (x < r ? x : r) + i;
+}
+
 __global__ __launch_bounds__(256, 1) void k_ring_gemm(const GemmProb *__restrict__ probs, int nprobs,
-                                                      int total_tiles) {
-    __shared__ __attribute__((aligned(16))) uint8_t smem[2 * STAGE];
-    for (int t = blockIdx.x; t < total_tiles; t += gridDim.x) {
+                                                      int total_tiles, int xcd_remap) {
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[2 * STAGE];
+    for (int b = blockIdx.x; b < total_tiles; b += gridDim.x) {
+        const int t = xcd_remap ? xcd_tile(b, total_tiles) : b;
         int lo = 0, hi = nprobs - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (probs[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
         }
         const GemmProb P = probs[lo];
-        int local = t - P.tile_begin;
-        const int split = local % P.splits;
-        local /= P.splits;
-        const int tn = local % P.tiles_n, tm = local / P.tiles_n;
-        gemm_tile(P, tm, tn, split, smem);
-        __syncthreads();
+        const int local = t - P.tile_begin;
+        const int per_split = P.tiles_m * P.tiles_n;
+        const int split = local / per_split;
+        const int g = local % per_split;
+        const int gm = P.group_m;
+        const int group = g / (gm * P.tiles_n);
+        const int tm0 = group * gm;
+        const int gme = min(gm, P.tiles_m - tm0);
+        const int r = g - group * gm * P.tiles_n;
+        const int tn = r / gme, tm = tm0 + r % gme;
+        gemm_tile(P, tm, tn, split, lds);
     }
 }
 
-hipError_t launch_gemm(const GemmProb *probs_dev, int nprobs, int total_tiles, int grid, hipStream_t st) {
+hipError_t launch_gemm(const GemmProb *probs_dev, int nprobs, int total_tiles, int xcd_remap, hipStream_t st) {
     if (nprobs <= 0 || total_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ring_gemm, dim3(grid), dim3(256), 0, st, probs_dev, nprobs, total_tiles);
+    hipLaunchKernelGGL(k_ring_gemm, dim3(total_tiles), dim3(256), 0, st, probs_dev, nprobs, total_tiles, xcd_remap);
     return hipGetLastError();
 }
 
@@ -254,47 +307,32 @@ hipError_t launch_gemm(const GemmProb *probs_dev, int nprobs, int total_tiles, i
 // K with coalesced 16-byte loads, 128-bit VALU multiply-adds, a wavefront
 // reduction per column.  (The online phase forms these products inside its
 // pass over E.)
-__global__ __launch_bounds__(256) void k_skinny(const GemmProb *__restrict__ probs, int nprobs) {
-    const GemmProb P = probs[blockIdx.y];
+__global__ __launch_bounds__(256) void k_skinny(const SkinnyProb *__restrict__ probs, int nprobs) {
+    const SkinnyProb P = probs[blockIdx.y];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int N = P.N, K = P.K;
     for (int m = blockIdx.x * 4 + wave; m < P.M; m += gridDim.x * 4) {
         u128 acc[SKINNY_MAX_N];
 #pragma unroll
         for (int n = 0; n < SKINNY_MAX_N; n++) acc[n] = zero128();
-        for (int seg = 0; seg < (P.L2 ? 2 : 1); seg++) {
-            const u128 *Ls = seg ? P.L2 : P.L1;
-            const u128 *Rs = seg ? P.R2 : P.R1;
-            const u128 *row = Ls + (int64_t)m * K;
-            for (int k = lane; k < K; k += 64) {
-                const u128 a = ld(row, k);
+        const u128 *row = P.L + (int64_t)m * K;
+        for (int k = lane; k < K; k += 64) {
+            const u128 a = ld(row, k);
 #pragma unroll
-                for (int n = 0; n < SKINNY_MAX_N; n++) {
-                    if (n < N) {
-                        acc[n] = mad(acc[n], a, ld(Rs, (int64_t)k * N + n));
-                    }
-                }
-            }
+            for (int n = 0; n < SKINNY_MAX_N; n++)
+                if (n < N) acc[n] = mad(acc[n], a, ld(P.R, (int64_t)k * N + n));
         }
 #pragma unroll
         for (int n = 0; n < SKINNY_MAX_N; n++) {
             if (n < N) {
-                u128 v = wave_sum(acc[n]);
-                if (lane == 0) {
-                    const int64_t idx = (int64_t)m * N + n;
-                    if (P.accumulate) {
-                        atomic_add128(P.out + idx, v);
-                    } else {
-                        if (P.base) v = add(v, ld(P.base, idx));
-                        st(P.out, idx, v);
-                    }
-                }
+                const u128 v = wave_sum(acc[n]);
+                if (lane == 0) st(P.out, (int64_t)m * N + n, v);
             }
         }
     }
 }
 
-hipError_t launch_skinny(const GemmProb *probs_dev, int nprobs, int max_rows, hipStream_t st) {
+hipError_t launch_skinny(const SkinnyProb *probs_dev, int nprobs, int max_rows, hipStream_t st) {
     if (nprobs <= 0) return hipSuccess;
     int gx = (max_rows + 3) / 4;
     if (gx > 4096) gx = 4096;

@@ -73,23 +73,79 @@ __host__ __device__ inline CvecOff cvec_off(int64_t M, int64_t K) {
     return o;
 }
 
-// One ring GEMM problem:
+// Operands of the matrix-core products are converted once into "digit
+// tiles": for an operand with major dimension D (rows of a left operand,
+// columns of a right operand) and contraction length K, tile (t, ks) covers
+// major indices [64 t, 64 t + 64) and k in [32 ks, 32 ks + 32); it occupies
+// TILE_ELEMS elements (32 KB) at ((t * KT) + ks) * TILE_ELEMS and holds 16
+// planes of signed 8-bit digits (plane d = digit d) of 64 x 32 bytes, in the
+// byte order of the GEMM's LDS stage.  Out-of-range entries are zero.
+constexpr int TILE_ELEMS = 2048;
+inline int64_t packed_elems(int64_t major, int64_t K) { return ((major + 63) / 64) * ((K + 31) / 32) * TILE_ELEMS; }
+
+// Workspace of a layer with N > SKINNY_MAX_N (element offsets): the folded
+// left operands written by the row pass, then the digit tiles of every
+// operand of the matrix-core products.
+struct WorkOff {
+    int64_t AE0, tAE0, tAE1;                  // u128, M x K each
+    int64_t Ep, AE0p, A1p, tAE0p, tAE1p;      // packed left operands
+    int64_t B0p, B1p, Up, tB0p, tB1p;         // packed right operands
+    int64_t total;
+};
+inline WorkOff work_off(int64_t M, int64_t K, int64_t N) {
+    WorkOff o;
+    const int64_t mk = M * K, pl = packed_elems(M, K), pr = packed_elems(N, K);
+    o.AE0 = 0; o.tAE0 = mk; o.tAE1 = 2 * mk;
+    o.Ep = 3 * mk; o.AE0p = o.Ep + pl; o.A1p = o.Ep + 2 * pl; o.tAE0p = o.Ep + 3 * pl; o.tAE1p = o.Ep + 4 * pl;
+    o.B0p = o.Ep + 5 * pl; o.B1p = o.B0p + pr; o.Up = o.B0p + 2 * pr; o.tB0p = o.B0p + 3 * pr;
+    o.tB1p = o.B0p + 4 * pr;
+    o.total = o.B0p + 5 * pr;
+    return o;
+}
+
+// One packing job: src (row-major rows x cols) -> dst digit tiles.
+// side 0: left operand (major = row, k = column); side 1: right operand
+// (major = column, k = row).
+struct PackJob {
+    const u128 *src;
+    u128 *dst;
+    int32_t rows, cols, side, majt, kt, tile_begin, tiles, pad;
+};
+
+// One ring GEMM problem over packed operands:
 //   out (+)= base + L1 * R1 + L2 * R2     (all mod 2^128)
-// L1, L2: M x K (row-major, ld K); R1, R2: K x N (ld N); out, base: M x N.
-// L2 == nullptr: single segment.  accumulate != 0: out already holds base and
-// partial sums of K splits are added atomically.
+// Lp1, Lp2: packed M x K left operands; Rp1, Rp2: packed K x N right
+// operands; out, base: M x N row-major.  Lp2 == nullptr: single segment.
+// accumulate != 0: out already holds base and partial sums of K splits are
+// added atomically.
 struct GemmProb {
-    const u128 *L1, *L2, *R1, *R2, *base;
+    const u128 *Lp1, *Lp2, *Rp1, *Rp2, *base;
     u128 *out;
     int32_t M, N, K, accumulate;
     int32_t tiles_m, tiles_n, splits, steps_per_split;  // steps are 32-wide K slices
-    int32_t ksteps_seg, nsteps, tile_begin, tiles;
+    int32_t kt, nsteps, tile_begin, tiles;
+    int32_t group_m, pad0, pad1, pad2;  // tile order: column sweeps over groups of group_m row tiles
 };
 
+// Launch configuration of the matrix-core products (chosen by ct_autotune).
+struct GemmTuning {
+    int32_t group_m;       // row tiles per group of the tile order (1 = row-major order)
+    int32_t xcd_remap;     // give each XCD a contiguous range of the tile list
+    int32_t split_target;  // K slices per tile; 0 = enough tiles for two rounds over the CUs
+};
+
+// Unpacked product for the dealer's layers with N <= SKINNY_MAX_N:
+// out = L * R (L: M x K, R: K x N, row-major).
+struct SkinnyProb {
+    const u128 *L, *R;
+    u128 *out;
+    int32_t M, N, K, pad;
+};
 
 // ---- launchers (defined in the .hip files) ----
-hipError_t launch_gemm(const GemmProb *probs_dev, int nprobs, int total_tiles, int grid, hipStream_t st);
-hipError_t launch_skinny(const GemmProb *probs_dev, int nprobs, int max_rows, hipStream_t st);
+hipError_t launch_pack(const PackJob *jobs_dev, int njobs, int total_tiles, hipStream_t st);
+hipError_t launch_gemm(const GemmProb *probs_dev, int nprobs, int total_tiles, int xcd_remap, hipStream_t st);
+hipError_t launch_skinny(const SkinnyProb *probs_dev, int nprobs, int max_rows, hipStream_t st);
 
 hipError_t launch_fill_zero(u128 *p, int64_t n, hipStream_t st);
 hipError_t launch_deal_lift(const LayerDev *L, int n, int64_t max_elems, hipStream_t st);
@@ -97,7 +153,8 @@ hipError_t launch_deal_auth(const LayerDev *L, int n, int obj, int64_t max_elems
 hipError_t launch_zero_acc(const LayerDev *L, int n, int what, int64_t max_cvec, hipStream_t st);
 hipError_t launch_copy_base(const LayerDev *L, int n, int mode, int64_t max_elems, hipStream_t st);
 hipError_t launch_open_u(const LayerDev *L, int n, int flags, int64_t max_items, hipStream_t st);
-hipError_t launch_row_pass(const LayerDev *L, int n, int flags, int64_t max_rows, hipStream_t st);
+// variants: bit v set if some layer takes row-pass variant v (0, 1, 2, 4, 8)
+hipError_t launch_row_pass(const LayerDev *L, int n, int flags, int64_t max_rows, int variants, hipStream_t st);
 hipError_t launch_post(const LayerDev *L, int n, int flags, int64_t max_items, hipStream_t st);
 hipError_t launch_compact_final(const LayerDev *L, int n, int flags, hipStream_t st);
 hipError_t launch_check_batch(const LayerDev *L, int n, int which, int64_t max_elems, hipStream_t st);

@@ -369,20 +369,30 @@ __device__ __forceinline__ void row_pass_body(const LayerDev &L, int flags, u128
     }
 }
 
+// Variant of the row pass a layer takes: 0 for matrix-core layers, else the
+// smallest of 1, 2, 4, 8 that holds N.  Each variant is its own kernel so the
+// register budget (and occupancy) of one does not limit the others.
+__host__ __device__ inline int row_variant(int64_t N) {
+    return N > SKINNY_MAX_N ? 0 : (N <= 1 ? 1 : (N <= 2 ? 2 : (N <= 4 ? 4 : SKINNY_MAX_N)));
+}
+
+template <int NS>
 __global__ __launch_bounds__(TPB) void k_row_pass(const LayerDev *__restrict__ Ls, int flags) {
     __shared__ u128 sh[3 * WAVES];
     const LayerDev &L = Ls[blockIdx.y];
+    if (row_variant(L.N) != NS) return;
     u128 chk[3] = {zero128(), zero128(), zero128()};
-    if (L.N <= 1) row_pass_body<1>(L, flags, chk);
-    else if (L.N <= 2) row_pass_body<2>(L, flags, chk);
-    else if (L.N <= 4) row_pass_body<4>(L, flags, chk);
-    else if (L.N <= SKINNY_MAX_N) row_pass_body<SKINNY_MAX_N>(L, flags, chk);
-    else row_pass_body<0>(L, flags, chk);
+    row_pass_body<NS>(L, flags, chk);
     if (flags & F_CHECK) block_accumulate<3>(chk, sh, L.acc + 0);
 }
 
-hipError_t launch_row_pass(const LayerDev *L, int n, int flags, int64_t max_rows, hipStream_t st) {
-    hipLaunchKernelGGL(k_row_pass, dim3(grid_items(max_rows), n), dim3(TPB), 0, st, L, flags);
+hipError_t launch_row_pass(const LayerDev *L, int n, int flags, int64_t max_rows, int variants, hipStream_t st) {
+    const dim3 g(grid_items(max_rows), n), b(TPB);
+    if (variants & (1 << 0)) hipLaunchKernelGGL(k_row_pass<0>, g, b, 0, st, L, flags);
+    if (variants & (1 << 1)) hipLaunchKernelGGL(k_row_pass<1>, g, b, 0, st, L, flags);
+    if (variants & (1 << 2)) hipLaunchKernelGGL(k_row_pass<2>, g, b, 0, st, L, flags);
+    if (variants & (1 << 4)) hipLaunchKernelGGL(k_row_pass<4>, g, b, 0, st, L, flags);
+    if (variants & (1 << 8)) hipLaunchKernelGGL(k_row_pass<SKINNY_MAX_N>, g, b, 0, st, L, flags);
     return hipGetLastError();
 }
 

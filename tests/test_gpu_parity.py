@@ -108,6 +108,37 @@ def test_fused_verification_matches(ctx, mode, spec):
     free()
 
 
+@pytest.mark.parametrize("mode", MODES)
+def test_launch_configurations_give_identical_results(ctx, mode):
+    """The tile order, XCD remap and K-split length change only the schedule:
+    outputs and check records are bit-identical, and equal the oracle's."""
+    from paper_2311_04406_amd import Context
+    specs = [Spec(200, 700, 300, 31, 5), Spec(70, 100, 130, 3, 3), Spec(33, 70, 1, 7, 7)]
+    layers = gpu_layers(ctx, specs)
+    ctx.gen_triple_tags(layers)
+    out = torch.zeros(14 * len(specs), dtype=torch.int64, device="cuda:0")
+    ref = None
+    for g, x, sp in [(1, 0, 0), (4, 1, 8), (16, 0, 32), (2, 1, 128), (8, 1, 0)]:
+        say(f"[tuning] mode={mode} group_m={g} xcd={x} split={sp}")
+        ctx.set_tuning(g, x, sp)
+        ctx.tag_linear_check(mode, layers, out)
+        res = [r.cs for r in Context.decode_results(out, len(specs))]
+        got = [to_np(l[n][p]) for l in layers for n in ("Z", "tZ") for p in range(2)]
+        if ref is None:
+            ref = (res, got)
+            for s, gl, r in zip(specs, layers, Context.decode_results(out, len(specs))):
+                ol = oracle_run(mode, s, KEY)
+                compare_layer(gl, ol, mode, what=s.name)
+                compare_cs(r, ol, what=s.name)
+        else:
+            assert res == ref[0]
+            assert all(np.array_equal(a, b) for a, b in zip(got, ref[1]))
+    best = ctx.autotune(mode, layers)
+    assert best["group_m"] >= 1 and best["gemm_ms"] > 0
+    ctx.set_tuning(1, 0, 0)
+    free()
+
+
 TAMPER = [("X", 1, 5, 0), ("tA", 0, 63, 0), ("B", 0, 31, 1), ("tY", 1, 0, 1), ("C", 1, 17, 2), ("tR", 0, 40, 2)]
 
 
