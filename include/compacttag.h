@@ -45,7 +45,7 @@ typedef enum { CT_OK = 0, CT_EINVAL = 1, CT_ENOMEM = 2, CT_EDEVICE = 3, CT_ABORT
 /* CT_MODE_SPDZ2K: per-element tags of Eq. (3) (Pi_MatMul, Fig. 2), with D = R - Z
  *                 opened and batch-checked as in Pi_Truncation (Fig. 3).
  * CT_MODE_COMPACT: optimistic tag (Pi_OptMAC) verified through the compact tag
- *                 of Eq. (7) (Pi_CompactMatMul, Fig. 6). */
+ *                 of Eq. (5) (Pi_CompactMatMul, Fig. 7). */
 typedef enum { CT_MODE_SPDZ2K = 0, CT_MODE_COMPACT = 1 } ct_mode;
 
 typedef struct ct_ctx ct_ctx;
@@ -116,7 +116,7 @@ ct_status ct_destroy(ct_ctx *ctx);
 /* Copies the two key shares to host memory out[0], out[1]. */
 ct_status ct_key_shares(const ct_ctx *ctx, uint64_t out[2]);
 
-/* Dealer (preprocessing of Fig. 6 and F_MAC Auth, Appendix A), for n layers:
+/* Dealer (preprocessing of Fig. 7 and F_MAC Auth, Appendix A), for n layers:
  * Beaver matrix triple A (M x K), B (K x N), C = A*B mod 2^128 (M x N) and the
  * mask R (M x N), all uniform in Z_{2^128}, and, if with_inputs != 0, inputs
  * X (M x K) and Y (K x N) uniform in Z_{2^64} (upper limb zero).  Every object
@@ -127,7 +127,7 @@ ct_status ct_key_shares(const ct_ctx *ctx, uint64_t out[2]);
 ct_status ct_gen_triple_tags(ct_ctx *ctx, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
                              int with_inputs);
 
-/* Online phase of n linear layers (Fig. 6 online steps 1-7 at f = 0 for
+/* Online phase of n linear layers (Fig. 7 online steps 1-7 at f = 0 for
  * CT_MODE_COMPACT; Fig. 2 with Eqs. (2)-(3) plus the opening of D for
  * CT_MODE_SPDZ2K).  Reads X, tX, A, tA, Y, tY, B, tB, C, tC, R, tR; writes
  * E, U, D, Z, tZ (and cvec in CT_MODE_COMPACT).  Party 0 adds the public term
@@ -139,7 +139,7 @@ ct_status ct_tag_linear(ct_ctx *ctx, ct_mode mode, const ct_layer_desc *L, const
  * ct_check_result records to the device array out_dev (the accept field is
  * computed on the device).  Pi_BatchRec tag check (Fig. 1) of E and U in both
  * modes and of D = R - Z in CT_MODE_SPDZ2K (Pi_Truncation, Fig. 3); the
- * compact check of D (Fig. 6 verification steps 2-6) in CT_MODE_COMPACT.  All
+ * compact check of D (Fig. 7 verification steps 2-6) in CT_MODE_COMPACT.  All
  * check values are reduced mod 2^128.  The public combiners are drawn from the
  * layer's generator streams, so a layer's results do not depend on the other
  * layers in the call.  Asynchronous; allocates nothing.  Reads the arrays

@@ -7,7 +7,7 @@ GPU library never falls back to it.
 
 Ring elements of Z_{2^128} are numpy ``uint64`` arrays whose last axis holds
 the (lo, hi) limbs.  ``run_layer`` executes the whole two-party procedure of
-one linear layer -- the dealer (preprocessing of Fig. 6), the online phase and
+one linear layer -- the dealer (preprocessing of Fig. 7), the online phase and
 the verification -- optionally restricted to a range of rows of the M
 dimension, which is how full-size layers are sampled.
 """
@@ -268,7 +268,7 @@ def compact_cs(Dc: np.ndarray, tDc: np.ndarray, chihat: np.ndarray, delta_p: int
 
 
 # ---------------------------------------------------------------------------
-# closed-form operation counts of Sec. 3.4 (per party)
+# closed-form operation counts of Sec. 3.4.3 (per party)
 
 def spdz2k_tag_mults(M: int, K: int, N: int) -> int:
     return 3 * M * K * N + M * N

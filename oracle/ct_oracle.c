@@ -15,8 +15,8 @@
  *   - the preprocessing functionalities F_Rand and F_MAC, Appendix A;
  *   - Pi_BatchRec (Fig. 1): open and tag check;
  *   - Pi_MatMul (Fig. 2, Eqs. (2)-(3)): the SPDZ2k baseline;
- *   - Pi_Compress (Fig. "proccomp"), Pi_OptMAC (Fig. "expand"), the compact
- *     tag of Eq. (7) and Pi_CompactMatMul (Fig. 6) at f = 0.
+ *   - Pi_Compress (Fig. 4), Pi_OptMAC (Fig. 5), the compact tag of
+ *     Eq. (5) and Pi_CompactMatMul (Fig. 7) at f = 0.
  * Readings where the paper is ambiguous (integer key sum, the party that adds
  * public value terms, D opened mod 2^{k+s}, E*U inside the compact tag, check
  * modulus 2^{k+s}) are the ones listed in the design notes and in the file
@@ -29,7 +29,7 @@
 
 typedef unsigned __int128 u128;
 
-/* Ring multiplications performed so far; the tag accounting of Sec. 3.4 is
+/* Ring multiplications performed so far; the tag accounting of Sec. 3.4.3 is
  * read off this counter around the tag computations. */
 static uint64_t g_mults;
 
@@ -109,7 +109,7 @@ void or_matmul(int64_t M, int64_t K, int64_t N, const uint64_t *P, const uint64_
     free(acc);
 }
 
-/* Pi_Compress (Fig. "proccomp", step 1): M^c = M * chi, chi in Z_{2^s}^{N x 1}. */
+/* Pi_Compress (Fig. 4, step 1): M^c = M * chi, chi in Z_{2^s}^{N x 1}. */
 void or_compress(int64_t rows, int64_t N, const uint64_t *Mx, const uint64_t *chi, uint64_t *out) {
     for (int64_t i = 0; i < rows; i++) {
         u128 s = 0;
@@ -132,7 +132,7 @@ void or_batchrec_cs(int64_t n, const uint64_t *W, const uint64_t *tW, const uint
     st(out, 0, cs);
 }
 
-/* Pi_CompactMatMul verification, steps 3-5 (Fig. 6), one party's share:
+/* Pi_CompactMatMul verification, steps 3-5 (Fig. 7), one party's share:
  *   [CS] = [Delta]_p * D^c;  [CS] = [CS] (.) chihat - [tag D^c] (.) chihat;  cs_p = sum_i [CS]_i.
  * Reduced mod 2^{k+s} (reading of the k+2s modulus in the design notes). */
 void or_compact_cs(int64_t rows, const uint64_t *Dc, const uint64_t *tDc, const uint64_t *chihat,
@@ -165,7 +165,7 @@ static void auth_share(u128 lift, u128 dsum, uint64_t seed, uint64_t layer_id, i
 
 enum { OBJ_X = 1, OBJ_Y = 2, OBJ_A = 3, OBJ_B = 4, OBJ_C = 5, OBJ_R = 6 };
 
-/* Preprocessing of Fig. 6 (Beaver matrix triple A, B, C = A*B and the mask R),
+/* Preprocessing of Fig. 7 (Beaver matrix triple A, B, C = A*B and the mask R),
  * plus, when with_inputs is set, authenticated shares of the inputs X and Y.
  * Inputs are values of Z_{2^k} lifted with zero upper bits; A, B, R are
  * uniform in Z_{2^{k+s}}; C~ = A~ * B~ mod 2^{k+s}. */
@@ -234,14 +234,14 @@ void or_online(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) 
     const int64_t K = d->K, N = d->N, rows = d->r1 - d->r0;
     const uint64_t seed = d->seed, lid = d->layer_id;
 
-    /* Fig. 6 online step 1: open E = X - A and U = Y - B. */
+    /* Fig. 7 online step 1: open E = X - A and U = Y - B. */
     open_diff(rows * K, b->X, b->A, b->E);
     open_diff(K * N, b->Y, b->B, b->U);
 
-    /* Fig. 6 online step 2 and Eq. (2):
+    /* Fig. 7 online step 2 and Eq. (2):
      *   [Z]_p = [C]_p + E*[B]_p + [A]_p*U, and the public term E*U is added by
-     *   party 0 only (Fig. 2 step 3 / Fig. 6 step 4).  E*U is formed before D
-     *   is opened (reading of Eq. (7) and the cost count of Sec. 3.4). */
+     *   party 0 only (Fig. 2 step 3 / Fig. 7 step 4).  E*U is formed before D
+     *   is opened (reading of Eq. (5) and the cost count of Sec. 3.4.3). */
     uint64_t *EU = alloc128(rows * N), *tmp = alloc128(rows * N);
     uint64_t m_eu = g_mults;
     or_matmul(rows, K, N, b->E, b->U, EU);
@@ -288,7 +288,7 @@ void or_online(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) 
             opt[p] = g_mults - m0;
         }
 
-        /* Fig. 6 steps 5-6: public combiners chi in Z_{2^s}^{N x 1}, compress
+        /* Fig. 7 steps 5-6: public combiners chi in Z_{2^s}^{N x 1}, compress
          * tag(B), tag(C), U, tag(R) and D~ along N.  The public vectors U^c,
          * D~^c and E*U^c are formed by every party, so their cost is charged
          * to each. */
@@ -298,7 +298,7 @@ void or_online(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) 
         uint64_t m_pub = g_mults;
         or_compress(K, N, b->U, chi, b->Uc);
         or_compress(rows, N, b->D, chi, b->Dc);
-        /* Eq. (7) / Fig. 6 step 7, with the key on the public term:
+        /* Eq. (5) / Fig. 7 step 7, with the key on the public term:
          *   [tZ^c]_p = [tC^c]_p + E*[tB^c]_p + [tA]_p*U^c + [Delta]_p * (E*U^c)
          *   [tD^c]_p = [tR^c]_p - [tZ^c]_p */
         or_matmul(rows, K, 1, b->E, b->Uc, b->EUc);
@@ -346,7 +346,7 @@ void or_check(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) {
     if (!chi) abort();
     (void)M;
 
-    /* Fig. 6 verification step 1: Pi_BatchRec tag check of E and of U, one
+    /* Fig. 7 verification step 1: Pi_BatchRec tag check of E and of U, one
      * public combiner per element (Fig. 1 tag-check step 1). */
     or_draw_many(seed, stream_of(lid, OR_P_CHI_E), (uint64_t)(r0 * K), rows * K, chi);
     for (int p = 0; p < 2; p++) {
@@ -368,7 +368,7 @@ void or_check(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) {
             or_batchrec_cs(rows * N, b->D, tW, chi, delta[p], b->cs[2][p]);
         }
     } else {
-        /* Fig. 6 verification steps 2-5: chihat in Z_{2^s}^{M x 1}. */
+        /* Fig. 7 verification steps 2-5: chihat in Z_{2^s}^{M x 1}. */
         or_draw_many(seed, stream_of(lid, OR_P_CHIHAT), (uint64_t)r0, rows, chi);
         for (int p = 0; p < 2; p++) or_compact_cs(rows, b->Dc, b->tDc[p], chi, delta[p], b->cs[2][p]);
     }

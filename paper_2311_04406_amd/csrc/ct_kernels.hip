@@ -1,11 +1,11 @@
 // ct_kernels.hip -- the bandwidth-bound steps of the linear-layer hot path.
 //
 // The online phase touches every share array once, in three fused passes:
-//   k_open_u   over K x N: opens U = Y - B (Fig. 6 online step 1), compresses
-//              U and the tag shares of B along N (Fig. 6 step 6), and can
+//   k_open_u   over K x N: opens U = Y - B (Fig. 7 online step 1), compresses
+//              U and the tag shares of B along N (Fig. 7 step 6), and can
 //              accumulate the batch tag check of U (Fig. 1);
 //   k_row_pass over M x K, one wavefront per row: opens E = X - A, forms the
-//              compact-tag products E U^c, E [tB^c]_p, [tA]_p U^c (Eq. (7)),
+//              compact-tag products E U^c, E [tB^c]_p, [tA]_p U^c (Eq. (5)),
 //              the folded operands A_0 + E and [tA]_p + [Delta]_p E of the
 //              matrix-core products, or -- for layers with N <= 8 -- the whole
 //              output (and SPDZ2k tag) products on the VALU, and can
@@ -14,8 +14,8 @@
 //              optimistic tag (Pi_OptMAC) and compresses D, tag(R), tag(C)
 //              along N (CompactTag), or accumulates the batch check of D
 //              (SPDZ2k);
-// then k_compact_final finishes Eq. (7) per row and can accumulate the compact
-// check of D (Fig. 6 verification).  With F_CHECK the verification sums are
+// then k_compact_final finishes Eq. (5) per row and can accumulate the compact
+// check of D (Fig. 7 verification).  With F_CHECK the verification sums are
 // formed by the passes that read the data anyway; without it ct_mac_check
 // recomputes them with k_check_batch / k_check_compact.
 //
@@ -119,7 +119,7 @@ hipError_t launch_fill_zero(u128 *p, int64_t n, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------- dealer
-// Preprocessing of Fig. 6 / F_MAC Auth.  The lifts A~ and B~ are first written
+// Preprocessing of Fig. 7 / F_MAC Auth.  The lifts A~ and B~ are first written
 // into party 1's buffers, the triple product C~ = A~ B~ is formed there by the
 // ring GEMM, and k_deal_auth then splits every lift into value and tag shares.
 
@@ -399,7 +399,7 @@ hipError_t launch_row_pass(const LayerDev *L, int n, int flags, int64_t max_rows
 // ---------------------------------------------------------------- pass over M x N
 // D~ = ([R]_0 - [Z]_0) + ([R]_1 - [Z]_1) (Pi_OptMAC steps 1-2 / Pi_Truncation
 // step 1).  CompactTag: [tZ]_p = [tR]_p - [Delta]_p D~ (Pi_OptMAC step 3) and
-// the compressions D~^c, [tR^c]_p, [tC^c]_p (Fig. 6 step 6).  SPDZ2k with
+// the compressions D~^c, [tR^c]_p, [tC^c]_p (Fig. 7 step 6).  SPDZ2k with
 // F_CHECK: the batch check sums of D with [tD]_p = [tR]_p - [tZ]_p.
 __global__ __launch_bounds__(TPB) void k_post(const LayerDev *__restrict__ Ls, int flags) {
     __shared__ u128 sh[3 * WAVES];
@@ -455,10 +455,10 @@ hipError_t launch_post(const LayerDev *L, int n, int flags, int64_t max_items, h
 }
 
 // ---------------------------------------------------------------- compact tag
-// Eq. (7) with the key on the public term, per row m:
+// Eq. (5) with the key on the public term, per row m:
 //   [tZ^c]_p = [tC^c]_p + (E [tB^c]_p + [tA]_p U^c) + [Delta]_p (E U^c),
 //   [tD^c]_p = [tR^c]_p - [tZ^c]_p.
-// F_CHECK: the compact check of D (Fig. 6 verification steps 2-5) in the
+// F_CHECK: the compact check of D (Fig. 7 verification steps 2-5) in the
 // accumulator form of the batch checks,
 //   acc6 = -sum chihat_i [tD^c]_{0,i}, acc7 = -sum chihat_i [tD^c]_{1,i},
 //   acc8 = -sum chihat_i D^c_i,  so cs_p = acc_{6+p} - [Delta]_p acc8

@@ -4,7 +4,7 @@ Each test checks the oracle against something other than itself: a published
 generator output, a plain definition (the product of the lifted inputs, the
 tag relation of Eq. (1)), an identity between the two protocols, the
 soundness of the MAC check, a special case that reduces to the single-value
-check of Sec. 2.5, the closed-form costs of Sec. 3.4, or brute force with
+check of Sec. 2.5, the closed-form costs of Sec. 3.4.3, or brute force with
 Python integers on tiny shapes.
 """
 import os
@@ -296,7 +296,7 @@ def test_rows_ranges_compose(built):
 # ---------------------------------------------------------------- readings
 
 def test_literal_k_plus_2s_check_rejects_honest_runs(built):
-    """Documents the reading of Fig. 6 verification steps 4-6: evaluated mod
+    """Documents the reading of Fig. 7 verification steps 4-6: evaluated mod
     2^{k+2s} on the 128-bit shares, the honest compact check fails most of the
     time, while mod 2^{k+s} it always passes."""
     R192 = 1 << 192
