@@ -175,6 +175,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the SPDZ2k and per-layer comparison runs")
     ap.add_argument("--no-autotune", action="store_true", help="use the default matrix-core launch configuration")
+    ap.add_argument("--tuning", default=None, help="fixed launch configuration group_m,xcd_remap,split_target")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="copy this many MiB once with a plain device copy before the steps (calibrates "
+                         "hardware byte counters against a kernel of known traffic)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -196,8 +200,20 @@ def main():
     out_dev = torch.zeros(len(layers) * 14, dtype=torch.int64, device="cuda:0")
     mkn = sum(s.mkn for s in specs)
 
+    if args.copy_probe > 0:
+        n = args.copy_probe * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.int64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     tuning = None
-    if not args.no_autotune:
+    if args.tuning:
+        g, x, sp = (int(v) for v in args.tuning.split(","))
+        ctx.set_tuning(g, x, sp)
+        tuning = ctx.get_tuning(mode_id, layers)
+    elif not args.no_autotune:
         print("[bench] autotuning the matrix-core launch configuration ...", file=sys.stderr, flush=True)
         tuning = ctx.autotune(mode_id, layers)
     print(f"[bench] timed {args.mode}: {args.warmup} warmup + {args.steps} steps", file=sys.stderr, flush=True)

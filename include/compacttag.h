@@ -192,7 +192,7 @@ typedef struct {
 
 /* Autotuner: runs the online phase of this batch of layers (outputs written
  * as by ct_tag_linear) once per candidate launch configuration (group_m in
- * 1, 2, 4, 8, 16; XCD remap off and on; split_target 0, 16, 32, 64, 128),
+ * 1, 2, 4, 8, 16, 64; XCD remap off and on; split_target 0, 16, 32, 64, 128),
  * times the matrix-core products with HIP events (reps timed runs after one
  * warm-up each), and keeps the fastest for this shape class -- the protocol
  * and the rounded-up binary logarithms of M, K, N of every matrix-core

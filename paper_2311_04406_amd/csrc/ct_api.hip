@@ -257,6 +257,7 @@ GemmProb make_prob(const u128 *Lp1, const u128 *Lp2, const u128 *Rp1, const u128
     std::memset(&p, 0, sizeof(p));
     p.Lp1 = Lp1; p.Lp2 = Lp2; p.Rp1 = Rp1; p.Rp2 = Rp2; p.base = base; p.out = out;
     p.M = (int32_t)d.M; p.N = (int32_t)d.N; p.K = (int32_t)d.K;
+    p.gsize = 1;
     return p;
 }
 
@@ -303,6 +304,9 @@ GemmTuning tuning_for(const ct_ctx *c, uint64_t key) {
     return it == c->tuned.end() ? c->fallback : it->second;
 }
 
+// Plans the products: probs holds consecutive groups (the products of one
+// layer); gsize of each problem must be set.  Fills tiles, K splits and the
+// group tile ranges.
 int plan_gemms(std::vector<GemmProb> &probs, int num_cus, const GemmTuning &tu, int *total_tiles, bool *any_accum) {
     int64_t total_steps = 0;
     for (auto &p : probs) {
@@ -322,15 +326,25 @@ int plan_gemms(std::vector<GemmProb> &probs, int num_cus, const GemmTuning &tu, 
     if (target > MAX_STEPS_PER_SPLIT) target = MAX_STEPS_PER_SPLIT;
     int tile = 0;
     *any_accum = false;
-    for (auto &p : probs) {
-        const int64_t splits = std::max<int64_t>(1, (p.nsteps + target - 1) / target);
-        p.steps_per_split = (int)((p.nsteps + splits - 1) / splits);
-        p.splits = (p.nsteps + p.steps_per_split - 1) / p.steps_per_split;
-        p.accumulate = p.splits > 1 ? 1 : 0;
-        if (p.accumulate) *any_accum = true;
-        p.tile_begin = tile;
-        p.tiles = p.tiles_m * p.tiles_n * p.splits;
-        tile += p.tiles;
+    for (size_t i = 0; i < probs.size();) {
+        const int gs = probs[i].gsize;
+        GemmProb &p0 = probs[i];
+        const int64_t splits = std::max<int64_t>(1, (p0.nsteps + target - 1) / target);
+        const int sps = (int)((p0.nsteps + splits - 1) / splits);
+        const int nspl = (p0.nsteps + sps - 1) / sps;
+        const int gtiles = p0.tiles_m * p0.tiles_n * nspl * gs;
+        for (int j = 0; j < gs; j++) {
+            GemmProb &p = probs[i + j];
+            p.steps_per_split = sps;
+            p.splits = nspl;
+            p.accumulate = nspl > 1 ? 1 : 0;
+            p.tile_begin = tile;
+            p.tiles = gtiles;
+            p.gfirst = (int)i;
+        }
+        if (nspl > 1) *any_accum = true;
+        tile += gtiles;
+        i += gs;
     }
     *total_tiles = tile;
     return (int)probs.size();
@@ -514,6 +528,7 @@ ct_status online(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_layer
         J[njobs++] = make_job(o.B[0], W + w.B0p, d.K, d.N, 1);
         J[njobs++] = make_job(o.B[1], W + w.B1p, d.K, d.N, 1);
         J[njobs++] = make_job(o.U, W + w.Up, d.K, d.N, 1);
+        const size_t first = probs.size();
         probs.push_back(make_prob(W + w.Ep, W + w.AE0p, W + w.B0p, W + w.Up, o.C[0], o.Z[0], d));
         probs.push_back(make_prob(W + w.Ep, W + w.A1p, W + w.B1p, W + w.Up, o.C[1], o.Z[1], d));
         if (!compact) {
@@ -524,6 +539,7 @@ ct_status online(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_layer
             probs.push_back(make_prob(W + w.Ep, W + w.tAE0p, W + w.tB0p, W + w.Up, o.tC[0], o.tZ[0], d));
             probs.push_back(make_prob(W + w.Ep, W + w.tAE1p, W + w.tB1p, W + w.Up, o.tC[1], o.tZ[1], d));
         }
+        for (size_t j = first; j < probs.size(); j++) probs[j].gsize = (int32_t)(probs.size() - first);
     }
     const int pack_tiles = plan_jobs(c->pack_host, njobs);
     int total_tiles = 0;
@@ -649,7 +665,7 @@ ct_status ct_autotune(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_
     HIPCHK(c, fold_timing(c));
     const double saved_ms = c->stage_ms[ST_RING_GEMM];
     const int64_t saved_n = c->stage_n[ST_RING_GEMM];
-    static const int groups[] = {1, 2, 4, 8, 16};
+    static const int groups[] = {1, 2, 4, 8, 16, 64};
     static const int splits[] = {0, 16, 32, 64, 128};
     GemmTuning best = c->fallback;
     double best_ms = 1e30;

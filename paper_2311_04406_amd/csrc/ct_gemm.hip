@@ -51,12 +51,15 @@ __device__ __forceinline__ void to_digits(u128 x, uint32_t (&w)[4]) {
     w[3] = (uint32_t)((hi ^ K) >> 32);
 }
 
-// byte offset of (major j, k) inside one digit plane (k a multiple of 8);
-// the two 16-byte halves of a row swap on every other group of 4 rows, which
-// spreads the 16-byte fragment reads of 8 consecutive lanes over all banks.
+// byte offset of (major j, k) inside one digit plane (k a multiple of 8).
+// Rows are 32 bytes; the two 16-byte halves of row j swap when bit 2 xor
+// bit 3 of j is set, so the 16-byte fragment reads of 8 consecutive lanes
+// (rows j..j+7) cover 32 distinct banks and those of 16 consecutive lanes
+// cover 64.
+__device__ __forceinline__ int half_swap(int j) { return ((j >> 2) ^ (j >> 3)) & 1; }
 __device__ __forceinline__ int plane_off(int j, int k) {
     const int chunk = k >> 4;
-    return j * BK + (((chunk ^ (j >> 2)) & 1) << 4) + (k & 15);
+    return j * BK + ((chunk ^ half_swap(j)) << 4) + (k & 15);
 }
 
 // Transposes the digits of 8 consecutive-k elements into 16 planes of 8 bytes
@@ -222,8 +225,8 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &P, int tm, int tn, int
     const int chunk = lane >> 5;
     const int arow = wm * 32 + (lane & 31);
     const int brow = wn * 32 + (lane & 31);
-    const int a_frag = arow * BK + (((chunk ^ (arow >> 2)) & 1) << 4);
-    const int b_frag = brow * BK + (((chunk ^ (brow >> 2)) & 1) << 4);
+    const int a_frag = arow * BK + ((chunk ^ half_swap(arow)) << 4);
+    const int b_frag = brow * BK + ((chunk ^ half_swap(brow)) << 4);
 
     if (s_begin < s_end) issue_slice(a_tile(s_begin), b_tile(s_begin), lds);
     WAIT_VMEM();
@@ -259,10 +262,13 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &P, int tm, int tn, int
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 // L2): block b runs on XCD b % 8.  With xcd_remap the tile list is cut into
 // 8 contiguous ranges, one per XCD, so the workgroups resident on an XCD at a
-// time work on neighbouring tiles.  Within a problem, tiles are numbered by K
-// split, then in column sweeps over groups of group_m row tiles: a run of
-// consecutive tiles covers a group_m x w block of the output and reads
-// group_m left and w right operand tiles per K slice.
+// time work on neighbouring tiles.  The tiles of a layer's products (both
+// parties; four products in SPDZ2k mode) are numbered together, from slowest
+// to fastest: K split, group of group_m output row tiles, output column tile,
+// product, row tile within the group.  Neighbouring tiles therefore read the
+// same right-operand tile (all row tiles and both parties' products use U)
+// and the same left-operand tiles (E is shared by all products) in the same
+// K slice at about the same time.
 __device__ __forceinline__ int xcd_tile(int b, int total) {
     const int q = total >> 3, r = total & 7;
     const int x = b & 7, i = b >> 3;
@@ -279,17 +285,20 @@ __global__ __launch_bounds__(256, 1) void k_ring_gemm(const GemmProb *__restrict
             const int mid = (lo + hi + 1) >> 1;
             if (probs[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
         }
-        const GemmProb P = probs[lo];
-        const int local = t - P.tile_begin;
-        const int per_split = P.tiles_m * P.tiles_n;
+        const GemmProb &G = probs[lo];
+        const int tiles_m = G.tiles_m, tiles_n = G.tiles_n, gsize = G.gsize, gm = G.group_m;
+        const int local = t - G.tile_begin;
+        const int per_split = tiles_m * tiles_n * gsize;
         const int split = local / per_split;
-        const int g = local % per_split;
-        const int gm = P.group_m;
-        const int group = g / (gm * P.tiles_n);
-        const int tm0 = group * gm;
-        const int gme = min(gm, P.tiles_m - tm0);
-        const int r = g - group * gm * P.tiles_n;
-        const int tn = r / gme, tm = tm0 + r % gme;
+        const int rem = local - split * per_split;
+        const int tmg = rem / (gm * tiles_n * gsize);
+        const int gme = min(gm, tiles_m - tmg * gm);
+        const int r2 = rem - tmg * gm * tiles_n * gsize;
+        const int tn = r2 / (gme * gsize);
+        const int r3 = r2 - tn * gme * gsize;
+        const int pidx = r3 / gme;
+        const int tm = tmg * gm + (r3 - pidx * gme);
+        const GemmProb P = probs[G.gfirst + pidx];
         gemm_tile(P, tm, tn, split, lds);
     }
 }

@@ -112,7 +112,8 @@ struct PackJob {
     int32_t rows, cols, side, majt, kt, tile_begin, tiles, pad;
 };
 
-// One ring GEMM problem over packed operands:
+// One ring GEMM problem over packed operands (one party's product of a layer;
+// the products of a layer form a group whose tiles are interleaved):
 //   out (+)= base + L1 * R1 + L2 * R2     (all mod 2^128)
 // Lp1, Lp2: packed M x K left operands; Rp1, Rp2: packed K x N right
 // operands; out, base: M x N row-major.  Lp2 == nullptr: single segment.
@@ -123,8 +124,11 @@ struct GemmProb {
     u128 *out;
     int32_t M, N, K, accumulate;
     int32_t tiles_m, tiles_n, splits, steps_per_split;  // steps are 32-wide K slices
-    int32_t kt, nsteps, tile_begin, tiles;
-    int32_t group_m, pad0, pad1, pad2;  // tile order: column sweeps over groups of group_m row tiles
+    int32_t kt, nsteps, tile_begin, tiles;  // tile_begin, tiles: of the problem's layer group
+    int32_t group_m;  // tile order: column sweeps over groups of group_m row tiles
+    int32_t gfirst;   // index of the first problem of the layer group (problems of one layer
+    int32_t gsize;    //   share M, N, K and splits and are interleaved in the tile order)
+    int32_t pad;
 };
 
 // Launch configuration of the matrix-core products (chosen by ct_autotune).
