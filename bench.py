@@ -16,9 +16,9 @@ launches measured beside it.
 from __future__ import annotations
 
 import argparse
-import glob
 import hashlib
 import json
+import math
 import os
 import statistics
 import sys
@@ -68,10 +68,15 @@ def stage_work(stage: str, specs, mode: str):
     return ("mfma" if stage == "ring_gemm" else "hbm", tot)
 
 
+# Sources that determine what the device kernels do; the hardware counters in
+# profiles/traffic.json are valid only for the digest they were taken on.
+KERNEL_SOURCES = ("ct_device.h", "ct_internal.h", "ct_kernels.hip", "ct_gemm.hip")
+
+
 def source_digest() -> str:
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2311_04406_amd", "csrc", "*"))):
-        h.update(open(f, "rb").read())
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2311_04406_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -165,12 +170,73 @@ def cpu_baseline(specs):
             "seconds": t_tot, "ring_macs": macs}
 
 
+def serving_run(torch, ctx, mode_id, rate: float, count: int, arena_bytes: int, slots: int, max_batch: int,
+                seed: int = 5000, warm: float = 0.1):
+    """One open-loop serving run: `count` requests of a seeded Poisson stream
+    at `rate` req/s, each one layer of the CNN or encoder shape set, tag
+    generation or check with probability 1/2, submitted with their scheduled
+    arrival times to a fresh server.  The first `warm` fraction is excluded
+    from the statistics.  Latency = completion - scheduled arrival."""
+    from paper_2311_04406_amd import REQ_TAG, Server, workloads
+    shapes = workloads.serving_shapes()
+    arr = workloads.poisson_arrivals(rate, count, seed)
+    ch = workloads.request_choices(count, len(shapes), seed)
+    srv = Server(ctx, arena_bytes, slots=slots, max_batch=max_batch, mode=mode_id)
+    t0 = srv.now_us() + 5000.0
+    reqs = []
+    for i in range(count):
+        s = shapes[ch[i][1]]
+        reqs.append((i, ch[i][0], (s.M, s.K, s.N, 50000 + i, 10000 + i), t0 + arr[i] * 1e6))
+    srv.submit(reqs)
+    srv.drain(600)
+    comps = srv.poll(count + 16)
+    st = srv.stats()
+    srv.close()
+    torch.cuda.synchronize()
+    by_id = {r[0]: r for r in reqs}
+    nwarm = int(count * warm)
+    live = [c for c in comps if c["id"] >= nwarm]
+    bad = [c for c in comps if c["status"] != 0]
+    lat = sorted((c["done_us"] - c["arrival_us"]) / 1e3 for c in live)
+    lat_tag = sorted((c["done_us"] - c["arrival_us"]) / 1e3 for c in live if c["kind"] == REQ_TAG)
+    lat_chk = sorted((c["done_us"] - c["arrival_us"]) / 1e3 for c in live if c["kind"] != REQ_TAG)
+    t_first = min(c["arrival_us"] for c in live)
+    t_last = max(c["done_us"] for c in live)
+    span = (t_last - t_first) * 1e-6
+    macs = sum(by_id[c["id"]][2][0] * by_id[c["id"]][2][1] * by_id[c["id"]][2][2]
+               for c in live if c["kind"] == REQ_TAG)
+    return {"rate_rps": rate, "requests": count, "measured": len(live), "errors": len(bad),
+            "achieved_rps": round(len(live) / span, 1), "tag_gops": round(macs / span / 1e9, 3),
+            "p50_ms": round(pct(lat, 50), 3), "p99_ms": round(pct(lat, 99), 3),
+            "tag_p50_ms": round(pct(lat_tag, 50), 3) if lat_tag else None,
+            "tag_p99_ms": round(pct(lat_tag, 99), 3) if lat_tag else None,
+            "check_p50_ms": round(pct(lat_chk, 50), 3) if lat_chk else None,
+            "check_p99_ms": round(pct(lat_chk, 99), 3) if lat_chk else None,
+            "batches": st["batches"], "mean_batch": round(st["completed"] / max(st["batches"], 1), 2),
+            "max_batch": st["max_batch"], "converted_checks": st["converted"], "evictions": st["evictions"],
+            "arena_peak_GB": round(st["arena_peak"] / 1e9, 2)}
+
+
+SERVE_RATES = (100, 200, 500, 1000, 2000, 5000)
+SERVE_ARENA = 96 << 30
+SERVE_SLOTS = 3
+SERVE_BATCH = 32
+
+
+def serve_count(rate: float) -> int:
+    """At least 10 s of arrivals or at least 2000 requests."""
+    return int(min(2000, math.ceil(10 * rate)))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="cnn", choices=["cnn", "transformer", "batched", "fc_small"])
+    ap.add_argument("--config", default="cnn", choices=["cnn", "transformer", "batched", "fc_small", "serving"])
+    ap.add_argument("--serve-rate", type=float, default=1000.0,
+                    help="offered rate (req/s) of the serving leg of a layer-batch run")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--mode", default="compact", choices=["compact", "spdz2k"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the SPDZ2k and per-layer comparison runs")
@@ -190,6 +256,8 @@ def main():
     import torch
     from paper_2311_04406_amd import MODE_COMPACT, MODE_SPDZ2K, Context, Layer, workloads
 
+    if args.config == "serving":
+        return serving_main(args, torch)
     specs = workloads.CONFIGS[args.config]()
     mode_id = MODE_COMPACT if args.mode == "compact" else MODE_SPDZ2K
     ctx = Context(device=0, key_seed=workloads.KEY_SEED, max_layers=max(256, len(specs)))
@@ -217,7 +285,9 @@ def main():
         print("[bench] autotuning the matrix-core launch configuration ...", file=sys.stderr, flush=True)
         tuning = ctx.autotune(mode_id, layers)
     print(f"[bench] timed {args.mode}: {args.warmup} warmup + {args.steps} steps", file=sys.stderr, flush=True)
-    T, per, stages = run_steps(ctx, mode_id, [layers], out_dev, args.steps, args.warmup, torch, timing=True)
+    T, per, _ = run_steps(ctx, mode_id, [layers], out_dev, args.steps, args.warmup, torch)
+    # per-kernel durations: a second pass with an event pair around every launch
+    _, _, stages = run_steps(ctx, mode_id, [layers], out_dev, args.steps, 0, torch, timing=True)
     res = Context.decode_results(out_dev, len(layers))
     if not all(r.accept for r in res):
         print("[bench] ERROR: an honest run was rejected", file=sys.stderr)
@@ -287,11 +357,50 @@ def main():
         out["separate_check"] = {"value": round(mkn * args.steps / T4 / 1e9, 3),
                                  "ms_per_step": round(T4 / args.steps * 1e3, 4),
                                  "p50_ms": round(pct(per4, 50), 4), "p99_ms": round(pct(per4, 99), 4)}
+    if not args.no_serve:
+        print(f"[bench] serving leg at {args.serve_rate:g} req/s ...", file=sys.stderr, flush=True)
+        del layers
+        torch.cuda.empty_cache()
+        out["serving"] = serving_run(torch, ctx, mode_id, args.serve_rate, serve_count(args.serve_rate),
+                                     SERVE_ARENA, SERVE_SLOTS, SERVE_BATCH)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         cb = cpu_baseline(specs)
         out["cpu_baseline"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in cb.items()}
     ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def serving_main(args, torch):
+    """The serving configuration: an open-loop Poisson sweep over the offered
+    rates; `value` is the tagged ring-MAC throughput at the highest rate."""
+    from paper_2311_04406_amd import MODE_COMPACT, MODE_SPDZ2K, Context, workloads
+    mode_id = MODE_COMPACT if args.mode == "compact" else MODE_SPDZ2K
+    ctx = Context(device=0, key_seed=workloads.KEY_SEED)
+    rows = []
+    for rate in SERVE_RATES:
+        print(f"[bench] serving {rate} req/s ...", file=sys.stderr, flush=True)
+        rows.append(serving_run(torch, ctx, mode_id, rate, serve_count(rate), SERVE_ARENA, SERVE_SLOTS,
+                                SERVE_BATCH))
+        print(f"[bench]   {rows[-1]}", file=sys.stderr, flush=True)
+    ctx.close()
+    top = rows[-1]
+    ref = next((r for r in rows if r["rate_rps"] == args.serve_rate), rows[0])
+    shapes = workloads.serving_shapes()
+    out = {
+        "metric": METRIC, "value": top["tag_gops"], "unit": "G ring-MAC/s (Z_2^64 GEMM Gops, 1 op = 1 MAC)",
+        "n_gpus": 1, "steps": sum(r["requests"] for r in rows), "warmup": 0, "ms_per_step": None,
+        "p50_ms": ref["p50_ms"], "p99_ms": ref["p99_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u128", "data": "synthetic",
+        "config": {"workload": "serving: open-loop Poisson arrivals at " + ", ".join(str(r) for r in SERVE_RATES)
+                   + " req/s; each request one layer of " + ", ".join(f"{s.name} ({s.M}x{s.K}x{s.N})"
+                                                                       for s in shapes)
+                   + "; tag generation (dealer + online phase) or check, 1/2 each",
+                   "protocol": args.mode, "parties": 2, "ring": "values Z_2^64, shares and tags Z_2^128",
+                   "arena_GB": SERVE_ARENA / 2**30, "slots": SERVE_SLOTS, "max_batch": SERVE_BATCH,
+                   "latency_rate_rps": ref["rate_rps"]},
+        "serving": rows,
+    }
     print(json.dumps(out), flush=True)
 
 

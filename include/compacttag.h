@@ -209,6 +209,122 @@ ct_status ct_get_tuning(const ct_ctx *ctx, ct_mode mode, const ct_layer_desc *L,
  * ones. */
 ct_status ct_set_tuning(ct_ctx *ctx, const ct_tuning *t);
 
+/* ---- Captured plans: one graph launch per step (HIP graphs) ----
+ *
+ * A plan records the online phase of a fixed batch of layers (exactly as
+ * ct_tag_linear, or as ct_tag_linear_check when out_dev is not NULL) once
+ * into a HIP graph: its descriptor tables are uploaded into device memory the
+ * plan owns before the capture, so the graph holds kernel nodes only.  The
+ * layer buffers, out_dev and the launch configuration (ct_autotune's choice
+ * for the batch at creation time) are bound at creation; every launch
+ * recomputes all outputs from the current contents of the input buffers.
+ * Creating a plan allocates; launching one does not. */
+typedef struct ct_plan ct_plan;
+
+/* Validates as ct_tag_linear_check does (out_dev may be NULL: no
+ * verification), captures and instantiates the graph.  Synchronizes. */
+ct_status ct_plan_create(ct_ctx *ctx, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
+                         ct_check_result *out_dev, ct_plan **out);
+
+/* Launches the plan's graph on the context stream.  Asynchronous. */
+ct_status ct_plan_launch(ct_plan *plan);
+
+/* Waits for the plan's launches and frees it. */
+ct_status ct_plan_destroy(ct_plan *plan);
+
+/* ---- Request server: continuous batching over one device arena ----
+ *
+ * Serves a stream of tag-generation and verification requests of mixed
+ * layer shapes on one GPU.  A TAG request names a layer (shape, seed,
+ * layer_id): the server admits it when its footprint fits in the arena,
+ * draws its inputs and triple there with the dealer, and runs the online
+ * phase (as ct_gen_triple_tags with inputs, then ct_tag_linear, in the
+ * server's protocol).  The layer then stays resident -- shares, tags, key
+ * shares' products, public values -- for later checks.  A CHECK request
+ * names a shape: it runs the MAC checks (as ct_mac_check_device) on the most
+ * recent complete resident layer of that shape, and runs as a TAG if there
+ * is none.  Admission is first come, first served by scheduled arrival time;
+ * requests that have arrived while others are on the device form the next
+ * batch as soon as one of the server's slots (HIP streams) is free, so work
+ * of successive batches overlaps on the device.  Complete layers are
+ * evicted least recently used first when a TAG does not fit.  A layer's
+ * results do not depend on the other requests of its batch (the check
+ * combiners are keyed by the layer's seed and layer_id).
+ *
+ * The server runs a worker thread that owns the context from ct_server_create
+ * to ct_server_destroy: the context must not be used by any other call in
+ * that time.  The server allocates its slots' tables at creation and nothing
+ * afterwards; all layer memory comes from the caller's arena. */
+typedef struct ct_server ct_server;
+
+typedef enum { CT_REQ_TAG = 0, CT_REQ_CHECK = 1 } ct_req_kind;
+
+typedef struct {
+    void *arena;          /* device memory for resident layers and workspaces (caller-owned,
+                             256-byte aligned, not used by the caller while the server lives) */
+    size_t arena_bytes;
+    int32_t slots;        /* batches in flight at once, one HIP stream each: 1..8 */
+    int32_t max_batch;    /* most requests in one batch: 1..256 */
+    int32_t mode;         /* ct_mode of the TAG requests and of the checks */
+    int32_t reserved;
+} ct_server_params;
+
+typedef struct {
+    int64_t id;           /* the caller's request id (unique per server) */
+    int32_t kind;         /* ct_req_kind */
+    int32_t reserved;
+    ct_layer_desc layer;  /* TAG: the layer (f = 0); CHECK: only M, K, N are used */
+    double arrival_us;    /* scheduled arrival on the server clock (ct_server_now_us); the request is
+                             not admitted earlier, and its latency counts from this time */
+} ct_request;
+
+typedef struct {
+    int64_t id;
+    int32_t kind;         /* as executed */
+    int32_t status;       /* CT_OK; CT_ABORT: the check rejected; CT_ENOMEM: the layer does not fit in
+                             the arena at all; CT_EDEVICE: a HIP error (ct_server_last_error) */
+    int64_t layer;        /* id of the TAG request whose layer this request wrote or checked (-1 if none) */
+    double arrival_us, admit_us, done_us;  /* server clock; done_us: completion seen by the worker */
+    int32_t batch_size, slot;
+    ct_check_result result;  /* CHECK: the layer's check values */
+} ct_completion;
+
+typedef struct {
+    int64_t submitted, completed, rejected, converted, evictions, batches, max_batch, resident_layers;
+    uint64_t arena_bytes, arena_peak, arena_used;
+} ct_server_counts;
+
+/* Creates the server's slots and starts its worker thread. */
+ct_status ct_server_create(ct_ctx *ctx, const ct_server_params *params, ct_server **out);
+
+/* Microseconds since the server was created (the clock of arrival_us). */
+double ct_server_now_us(const ct_server *server);
+
+/* Queues n requests (validated first: on CT_EINVAL none is queued). */
+ct_status ct_server_submit(ct_server *server, const ct_request *reqs, int n);
+
+/* Moves up to max completions, in completion order, into out; *count
+ * receives their number.  Non-blocking. */
+ct_status ct_server_poll(ct_server *server, ct_completion *out, int max, int *count);
+
+/* Waits until every submitted request has completed (CT_EDEVICE after
+ * timeout_s seconds). */
+ct_status ct_server_drain(ct_server *server, double timeout_s);
+
+/* Descriptor and device buffers of the complete resident layer written by
+ * TAG request id (work = NULL).  The buffers stay valid until the server
+ * evicts the layer, which only an admission can do: read them while no
+ * request is pending. */
+ct_status ct_server_layer(ct_server *server, int64_t id, ct_layer_desc *desc, ct_layer_bufs *bufs);
+
+ct_status ct_server_stats(ct_server *server, ct_server_counts *out);
+
+/* Stops admitting, waits for the batches in flight, stops the worker and
+ * frees the slots (queued requests that were never admitted are dropped). */
+ct_status ct_server_destroy(ct_server *server);
+
+const char *ct_server_last_error(ct_server *server);
+
 /* Text of the last error on this context ("" if none). */
 const char *ct_last_error(const ct_ctx *ctx);
 

@@ -68,6 +68,32 @@ class CtCheckResult(ctypes.Structure):
     _fields_ = [("cs", ctypes.c_uint64 * 12), ("accept", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+REQ_TAG, REQ_CHECK = 0, 1
+
+
+class CtServerParams(ctypes.Structure):
+    _fields_ = [("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t), ("slots", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("mode", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class CtRequest(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("kind", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("layer", CtLayerDesc), ("arrival_us", ctypes.c_double)]
+
+
+class CtCompletion(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("kind", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("layer", ctypes.c_int64), ("arrival_us", ctypes.c_double), ("admit_us", ctypes.c_double),
+                ("done_us", ctypes.c_double), ("batch_size", ctypes.c_int32), ("slot", ctypes.c_int32),
+                ("result", CtCheckResult)]
+
+
+class CtServerCounts(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "rejected", "converted", "evictions",
+                                              "batches", "max_batch", "resident_layers")] + \
+               [(n, ctypes.c_uint64) for n in ("arena_bytes", "arena_peak", "arena_used")]
+
+
 _lib = None
 
 
@@ -96,11 +122,28 @@ def load() -> ctypes.CDLL:
                               ctypes.POINTER(CtTuning)]
     L.ct_get_tuning.argtypes = [vp, i, ctypes.POINTER(CtLayerDesc), i, ctypes.POINTER(CtTuning)]
     L.ct_set_tuning.argtypes = [vp, ctypes.POINTER(CtTuning)]
+    L.ct_plan_create.argtypes = [vp, i, ctypes.POINTER(CtLayerDesc), ctypes.POINTER(CtLayerBufs), i, vp,
+                                 ctypes.POINTER(vp)]
+    L.ct_plan_launch.argtypes = [vp]
+    L.ct_plan_destroy.argtypes = [vp]
+    L.ct_server_create.argtypes = [vp, ctypes.POINTER(CtServerParams), ctypes.POINTER(vp)]
+    L.ct_server_now_us.argtypes = [vp]
+    L.ct_server_now_us.restype = ctypes.c_double
+    L.ct_server_submit.argtypes = [vp, ctypes.POINTER(CtRequest), i]
+    L.ct_server_poll.argtypes = [vp, ctypes.POINTER(CtCompletion), i, ctypes.POINTER(ctypes.c_int)]
+    L.ct_server_drain.argtypes = [vp, ctypes.c_double]
+    L.ct_server_layer.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(CtLayerDesc), ctypes.POINTER(CtLayerBufs)]
+    L.ct_server_stats.argtypes = [vp, ctypes.POINTER(CtServerCounts)]
+    L.ct_server_destroy.argtypes = [vp]
+    L.ct_server_last_error.argtypes = [vp]
+    L.ct_server_last_error.restype = ctypes.c_char_p
     L.ct_last_error.argtypes = [vp]
     L.ct_last_error.restype = ctypes.c_char_p
     for f in ("ct_create", "ct_destroy", "ct_key_shares", "ct_gen_triple_tags", "ct_tag_linear",
-              "ct_mac_check_device", "ct_mac_check", "ct_set_timing", "ct_stage_times", "ct_tag_linear_check", "ct_autotune", "ct_get_tuning",
-              "ct_set_tuning"):
+              "ct_mac_check_device", "ct_mac_check", "ct_set_timing", "ct_stage_times", "ct_tag_linear_check",
+              "ct_autotune", "ct_get_tuning", "ct_set_tuning", "ct_plan_create", "ct_plan_launch",
+              "ct_plan_destroy", "ct_server_create", "ct_server_submit", "ct_server_poll", "ct_server_drain",
+              "ct_server_layer", "ct_server_stats", "ct_server_destroy"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -144,6 +187,14 @@ class Layer:
         self.t["D"] = torch.zeros((M, N, 2), dtype=torch.int64, device=device)
         self.t["cvec"] = torch.zeros((3 * K + 10 * M, 2), dtype=torch.int64, device=device)
         self.t["work"] = torch.zeros((max(1, work_len(M, K, N)), 2), dtype=torch.int64, device=device)
+
+    @classmethod
+    def wrap(cls, M: int, K: int, N: int, seed: int, layer_id: int, tensors: dict) -> "Layer":
+        """A Layer over existing device tensors (no allocation)."""
+        obj = cls.__new__(cls)
+        obj.M, obj.K, obj.N, obj.seed, obj.layer_id, obj.f = M, K, N, seed, layer_id, 0
+        obj.t = dict(tensors)
+        return obj
 
     @staticmethod
     def footprint_bytes(M: int, K: int, N: int) -> int:
@@ -277,9 +328,137 @@ class Context:
         self._check(self.lib.ct_stage_times(self.h, buf, 32, ctypes.byref(cnt)))
         return {buf[i].name.decode(): (buf[i].total_ms, int(buf[i].launches)) for i in range(min(cnt.value, 32))}
 
+    def plan(self, mode: int, layers, out: torch.Tensor | None = None) -> "Plan":
+        """Captures the online phase of this layer batch (with the fused
+        verification if `out` is given) into a HIP graph; see Plan."""
+        n, D, B = _arrays(layers)
+        if out is not None:
+            assert out.numel() * 8 >= n * ctypes.sizeof(CtCheckResult)
+        h = ctypes.c_void_p()
+        self._check(self.lib.ct_plan_create(self.h, mode, D, B, n,
+                                            ctypes.c_void_p(out.data_ptr()) if out is not None else None,
+                                            ctypes.byref(h)))
+        return Plan(self, h, layers, out)
+
     @staticmethod
     def decode_results(t: torch.Tensor, n: int):
         """Decodes ct_check_result records copied back from mac_check_device."""
         raw = t.detach().cpu().contiguous().numpy().tobytes()
         arr = (CtCheckResult * n).from_buffer_copy(raw[: n * ctypes.sizeof(CtCheckResult)])
         return [_result(r) for r in arr]
+
+
+class Plan:
+    """A captured online phase (ct_plan): launch() replays its HIP graph on
+    the context stream; the layers and result tensor stay bound to it."""
+
+    def __init__(self, ctx: Context, handle, layers, out):
+        self.ctx, self.h, self.layers, self.out = ctx, handle, list(layers), out
+
+    def launch(self):
+        self.ctx._check(self.ctx.lib.ct_plan_launch(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.ct_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _status_name(s: int) -> str:
+    return STATUS.get(s, str(s))
+
+
+class Server:
+    """The request server (ct_server_*): continuous batching of tag-generation
+    and check requests over one device arena, allocated here with PyTorch.
+    The server's worker thread owns `ctx` until close()."""
+
+    def __init__(self, ctx: Context, arena_bytes: int, slots: int = 2, max_batch: int = 32,
+                 mode: int = MODE_COMPACT):
+        self.ctx, self.lib = ctx, ctx.lib
+        self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=ctx.torch_device)
+        torch.cuda.synchronize(ctx.torch_device)
+        p = CtServerParams(self.arena.data_ptr(), arena_bytes, slots, max_batch, mode, 0)
+        h = ctypes.c_void_p()
+        s = self.lib.ct_server_create(ctx.h, ctypes.byref(p), ctypes.byref(h))
+        if s != CT_OK:
+            raise CtError(s, self.lib.ct_last_error(ctx.h).decode())
+        self.h = h
+
+    def _check(self, s: int):
+        if s != CT_OK:
+            raise CtError(s, self.lib.ct_server_last_error(self.h).decode())
+
+    def now_us(self) -> float:
+        return float(self.lib.ct_server_now_us(self.h))
+
+    def submit(self, reqs):
+        """reqs: iterable of (id, kind, (M, K, N, seed, layer_id), arrival_us)."""
+        reqs = list(reqs)
+        arr = (CtRequest * max(1, len(reqs)))()
+        for i, (rid, kind, (M, K, N, seed, lid), t) in enumerate(reqs):
+            arr[i] = CtRequest(rid, kind, 0, CtLayerDesc(M, K, N, 0, 0, seed & MASK64, lid & MASK64), t)
+        self._check(self.lib.ct_server_submit(self.h, arr, len(reqs)))
+
+    def poll(self, max_items: int = 4096):
+        buf = (CtCompletion * max_items)()
+        cnt = ctypes.c_int()
+        self._check(self.lib.ct_server_poll(self.h, buf, max_items, ctypes.byref(cnt)))
+        out = []
+        for i in range(cnt.value):
+            c = buf[i]
+            out.append({"id": c.id, "kind": c.kind, "status": c.status, "status_name": _status_name(c.status),
+                        "layer": c.layer, "arrival_us": c.arrival_us, "admit_us": c.admit_us,
+                        "done_us": c.done_us, "batch_size": c.batch_size, "slot": c.slot,
+                        "result": _result(c.result)})
+        return out
+
+    def drain(self, timeout_s: float = 120.0):
+        self._check(self.lib.ct_server_drain(self.h, timeout_s))
+
+    def layer(self, rid: int) -> Layer:
+        """The resident layer written by TAG request rid, as torch views into the arena."""
+        d, b = CtLayerDesc(), CtLayerBufs()
+        self._check(self.lib.ct_server_layer(self.h, rid, ctypes.byref(d), ctypes.byref(b)))
+        M, K, N = d.M, d.K, d.N
+        base = self.arena.data_ptr()
+
+        def view(ptr, rows, cols):
+            off = ptr - base
+            return self.arena[off: off + rows * cols * 16].view(torch.int64).view(rows, cols, 2)
+        dims = {"MK": (M, K), "KN": (K, N), "MN": (M, N)}
+        groups = {"MK": ["X", "tX", "A", "tA"], "KN": ["Y", "tY", "B", "tB"],
+                  "MN": ["C", "tC", "R", "tR", "Z", "tZ"]}
+        t = {}
+        for g, names in groups.items():
+            for n in names:
+                pair = getattr(b, n)
+                t[n] = [view(pair[q], *dims[g]) for q in range(2)]
+        t["E"] = view(b.E, M, K)
+        t["U"] = view(b.U, K, N)
+        t["D"] = view(b.D, M, N)
+        off = b.cvec - base
+        t["cvec"] = self.arena[off: off + (3 * K + 10 * M) * 16].view(torch.int64).view(3 * K + 10 * M, 2)
+        return Layer.wrap(M, K, N, d.seed, d.layer_id, t)
+
+    def stats(self) -> dict:
+        c = CtServerCounts()
+        self._check(self.lib.ct_server_stats(self.h, ctypes.byref(c)))
+        return {n: int(getattr(c, n)) for n, _ in CtServerCounts._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ct_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

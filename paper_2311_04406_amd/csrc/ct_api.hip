@@ -16,47 +16,21 @@
 #include <vector>
 
 #include "compacttag.h"
+#include "ct_host.h"
 #include "ct_internal.h"
 
 using namespace ct;
 
-// Kernel stages, for the optional per-launch timing (ct_set_timing).
-enum Stage : int {
-    ST_DEAL_LIFT, ST_FILL_ZERO, ST_DEAL_AUTH, ST_DEAL_SKINNY, ST_ZERO_ACC, ST_OPEN_U, ST_ROW_PASS, ST_PACK,
-    ST_COPY_BASE, ST_RING_GEMM, ST_POST, ST_COMPACT_FINAL, ST_CHECK_BATCH, ST_CHECK_COMPACT, ST_FINALIZE, ST_COUNT
-};
 static const char *kStageNames[ST_COUNT] = {
     "deal_lift", "fill_zero", "deal_auth", "deal_skinny", "zero_acc", "open_u", "row_pass", "pack",
     "copy_base", "ring_gemm", "post", "compact_final", "check_batch", "check_compact", "finalize"};
 constexpr int EV_POOL = 2048;
 
-struct ct_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    uint64_t delta[2] = {0, 0};
-    int max_layers = 0, max_probs = 0;
-    int num_cus = 256;
-    LayerDev *layers_dev = nullptr, *layers_host = nullptr;
-    GemmProb *gemm_dev = nullptr, *gemm_host = nullptr;
-    PackJob *pack_dev = nullptr, *pack_host = nullptr;
-    SkinnyProb *skinny_dev = nullptr, *skinny_host = nullptr;
-    int max_jobs = 0;
-    u128 *acc_dev = nullptr;
-    ct_check_result *res_dev = nullptr, *res_host = nullptr;
-    hipEvent_t upload_done = nullptr;
-    std::string err;
-    // per-launch timing: event pairs recorded around each kernel on `stream`
-    bool timing = false;
-    std::vector<hipEvent_t> ev_start, ev_end;
-    std::vector<int> ev_stage;
-    int ev_used = 0;
-    double stage_ms[ST_COUNT] = {};
-    int64_t stage_n[ST_COUNT] = {};
-    // launch configuration of the matrix-core products per shape class
-    std::unordered_map<uint64_t, GemmTuning> tuned;
-    GemmTuning fallback = {1, 0, 0};
-    bool forcing = false;
-    GemmTuning forced = {1, 0, 0};
+struct ct_plan {
+    ct_ctx *ctx = nullptr;
+    Lane lane;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -72,10 +46,6 @@ uint64_t hkey(uint64_t seed, uint64_t layer_id, uint64_t purpose) {
 }
 uint64_t hdraw(uint64_t key, uint64_t i) { return hmix(key + (i + 1) * 0x9E3779B97F4A7C15ull); }
 
-ct_status fail(ct_ctx *c, ct_status s, const std::string &msg) {
-    if (c) c->err = msg;
-    return s;
-}
 ct_status hip_fail(ct_ctx *c, hipError_t e, const char *where) {
     return fail(c, CT_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
@@ -88,7 +58,7 @@ ct_status hip_fail(ct_ctx *c, hipError_t e, const char *where) {
 // Folds the recorded event pairs into the per-stage totals (synchronizes).
 hipError_t fold_timing(ct_ctx *c) {
     if (c->ev_used == 0) return hipSuccess;
-    hipError_t e = hipStreamSynchronize(c->stream);
+    hipError_t e = hipStreamSynchronize(c->main.stream);
     if (e != hipSuccess) return e;
     for (int i = 0; i < c->ev_used; i++) {
         float ms = 0.f;
@@ -101,16 +71,18 @@ hipError_t fold_timing(ct_ctx *c) {
     return hipSuccess;
 }
 
-// Runs a launcher; with timing on, brackets it with an event pair on the stream.
-#define LAUNCH(ctx, stage, expr)                                                         \
+// Runs a launcher on lane ln; with timing on (main lane only), brackets it
+// with an event pair on the lane's stream.
+#define LAUNCH(ctx, ln, stage, expr)                                                     \
     do {                                                                                 \
-        if ((ctx)->timing) {                                                             \
+        const bool timed_ = (ctx)->timing && (ln).timed;                                 \
+        if (timed_) {                                                                    \
             if ((ctx)->ev_used == EV_POOL) HIPCHK(ctx, fold_timing(ctx));                \
-            HIPCHK(ctx, hipEventRecord((ctx)->ev_start[(ctx)->ev_used], (ctx)->stream)); \
+            HIPCHK(ctx, hipEventRecord((ctx)->ev_start[(ctx)->ev_used], (ln).stream));   \
         }                                                                                \
         HIPCHK(ctx, expr);                                                               \
-        if ((ctx)->timing) {                                                             \
-            HIPCHK(ctx, hipEventRecord((ctx)->ev_end[(ctx)->ev_used], (ctx)->stream));   \
+        if (timed_) {                                                                    \
+            HIPCHK(ctx, hipEventRecord((ctx)->ev_end[(ctx)->ev_used], (ln).stream));     \
             (ctx)->ev_stage[(ctx)->ev_used++] = (stage);                                 \
         }                                                                                \
     } while (0)
@@ -125,11 +97,11 @@ enum Need : unsigned {
     NEED_WORK = 16,    // workspace of layers with N > SKINNY_MAX_N
 };
 
-ct_status validate(ct_ctx *c, const ct_layer_desc *L, const ct_layer_bufs *B, int n, unsigned need) {
+ct_status validate(ct_ctx *c, int max_layers, const ct_layer_desc *L, const ct_layer_bufs *B, int n, unsigned need) {
     if (!c) return CT_EINVAL;
     if (!L || !B) return fail(c, CT_EINVAL, "null layer or buffer array");
-    if (n < 1 || n > c->max_layers)
-        return fail(c, CT_EINVAL, "n must be in [1, max_layers] (" + std::to_string(c->max_layers) + ")");
+    if (n < 1 || n > max_layers)
+        return fail(c, CT_EINVAL, "n must be in [1, max_layers] (" + std::to_string(max_layers) + ")");
     for (int l = 0; l < n; l++) {
         const ct_layer_desc &d = L[l];
         const std::string at = "layer " + std::to_string(l) + ": ";
@@ -170,7 +142,7 @@ ct_status validate(ct_ctx *c, const ct_layer_desc *L, const ct_layer_bufs *B, in
     return CT_OK;
 }
 
-void fill_layer(const ct_ctx *c, const ct_layer_desc &d, const ct_layer_bufs &b, int l, LayerDev &o) {
+void fill_layer(const ct_ctx *c, u128 *acc, const ct_layer_desc &d, const ct_layer_bufs &b, int l, LayerDev &o) {
     std::memset(&o, 0, sizeof(o));
     o.M = d.M;
     o.K = d.K;
@@ -205,11 +177,13 @@ void fill_layer(const ct_ctx *c, const ct_layer_desc &d, const ct_layer_bufs &b,
     o.D = reinterpret_cast<u128 *>(b.D);
     o.cvec = reinterpret_cast<u128 *>(b.cvec);
     o.work = reinterpret_cast<u128 *>(b.work);
-    o.acc = c->acc_dev + (size_t)l * ACC_PER_LAYER;
+    o.acc = acc + (size_t)l * ACC_PER_LAYER;
 }
 
 struct Sizes {
-    int64_t mk = 0, kn = 0, mn = 0, m = 0, k = 0, cvec = 0, kn_items = 0, mn_items = 0;
+    int64_t mk = 0, kn = 0, mn = 0, m = 0, k = 0, cvec = 0, kn_items = 0, mn_items = 0, row_items = 0,
+            skinny_mn = 0;
+    bool skinny = false;
 };
 
 Sizes max_sizes(const ct_layer_desc *L, int n) {
@@ -224,30 +198,34 @@ Sizes max_sizes(const ct_layer_desc *L, int n) {
         s.cvec = std::max(s.cvec, (int64_t)CT_CVEC_LEN(d.M, d.K));
         s.kn_items = std::max(s.kn_items, sweep_items(d.K, d.N));
         s.mn_items = std::max(s.mn_items, sweep_items(d.M, d.N));
+        s.row_items = std::max(s.row_items, row_items(d.M, d.K));
+        if (d.N <= SKINNY_MAX_N) {
+            s.skinny = true;
+            s.skinny_mn = std::max(s.skinny_mn, d.M * d.N);
+        }
     }
     return s;
 }
 
-// Waits for the previous upload, then stages layers (and GEMM problems).
-ct_status stage_layers(ct_ctx *c, const ct_layer_desc *L, const ct_layer_bufs *B, int n) {
-    HIPCHK(c, hipEventSynchronize(c->upload_done));
-    for (int l = 0; l < n; l++) fill_layer(c, L[l], B[l], l, c->layers_host[l]);
+// Waits for the lane's previous upload, then stages the layer records.
+ct_status stage_layers(ct_ctx *c, Lane &ln, const ct_layer_desc *L, const ct_layer_bufs *B, int n) {
+    HIPCHK(c, hipEventSynchronize(ln.upload_done));
+    for (int l = 0; l < n; l++) fill_layer(c, ln.acc_dev, L[l], B[l], l, ln.layers_host[l]);
     return CT_OK;
 }
 
-ct_status upload(ct_ctx *c, int n, int nprobs, int njobs = 0, int nskinny = 0) {
-    HIPCHK(c, hipMemcpyAsync(c->layers_dev, c->layers_host, sizeof(LayerDev) * n, hipMemcpyHostToDevice,
-                             c->stream));
+ct_status upload(ct_ctx *c, Lane &ln, int n, int nprobs, int njobs = 0, int nskinny = 0) {
+    HIPCHK(c, hipMemcpyAsync(ln.layers_dev, ln.layers_host, sizeof(LayerDev) * n, hipMemcpyHostToDevice, ln.stream));
     if (nprobs > 0)
-        HIPCHK(c, hipMemcpyAsync(c->gemm_dev, c->gemm_host, sizeof(GemmProb) * nprobs, hipMemcpyHostToDevice,
-                                 c->stream));
+        HIPCHK(c, hipMemcpyAsync(ln.gemm_dev, ln.gemm_host, sizeof(GemmProb) * nprobs, hipMemcpyHostToDevice,
+                                 ln.stream));
     if (njobs > 0)
-        HIPCHK(c, hipMemcpyAsync(c->pack_dev, c->pack_host, sizeof(PackJob) * njobs, hipMemcpyHostToDevice,
-                                 c->stream));
+        HIPCHK(c, hipMemcpyAsync(ln.pack_dev, ln.pack_host, sizeof(PackJob) * njobs, hipMemcpyHostToDevice,
+                                 ln.stream));
     if (nskinny > 0)
-        HIPCHK(c, hipMemcpyAsync(c->skinny_dev, c->skinny_host, sizeof(SkinnyProb) * nskinny,
-                                 hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipEventRecord(c->upload_done, c->stream));
+        HIPCHK(c, hipMemcpyAsync(ln.skinny_dev, ln.skinny_host, sizeof(SkinnyProb) * nskinny,
+                                 hipMemcpyHostToDevice, ln.stream));
+    HIPCHK(c, hipEventRecord(ln.upload_done, ln.stream));
     return CT_OK;
 }
 
@@ -350,12 +328,63 @@ int plan_gemms(std::vector<GemmProb> &probs, int num_cus, const GemmTuning &tu, 
     return (int)probs.size();
 }
 
-ct_status run_gemms(ct_ctx *c, int nprobs, int total_tiles, const GemmTuning &tu) {
-    if (nprobs > 0) LAUNCH(c, ST_RING_GEMM, launch_gemm(c->gemm_dev, nprobs, total_tiles, tu.xcd_remap, c->stream));
+ct_status run_gemms(ct_ctx *c, Lane &ln, int nprobs, int total_tiles, const GemmTuning &tu) {
+    if (nprobs > 0)
+        LAUNCH(c, ln, ST_RING_GEMM, launch_gemm(ln.gemm_dev, nprobs, total_tiles, tu.xcd_remap, ln.stream));
     return CT_OK;
 }
 
 }  // namespace
+
+namespace ct {
+
+ct_status fail(ct_ctx *c, ct_status s, const std::string &msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+hipError_t lane_init(Lane &ln, hipStream_t stream, int max_layers) {
+    ln.stream = stream;
+    ln.max_layers = max_layers;
+    ln.max_probs = 4 * max_layers;
+    ln.max_jobs = 10 * max_layers;
+    hipError_t e;
+#define LANE_TRY(expr) \
+    if ((e = (expr)) != hipSuccess) return e
+    LANE_TRY(hipMalloc(&ln.layers_dev, sizeof(LayerDev) * ln.max_layers));
+    LANE_TRY(hipMalloc(&ln.gemm_dev, sizeof(GemmProb) * ln.max_probs));
+    LANE_TRY(hipMalloc(&ln.pack_dev, sizeof(PackJob) * ln.max_jobs));
+    LANE_TRY(hipMalloc(&ln.skinny_dev, sizeof(SkinnyProb) * ln.max_layers));
+    LANE_TRY(hipMalloc(&ln.acc_dev, sizeof(u128) * ACC_PER_LAYER * ln.max_layers));
+    LANE_TRY(hipMalloc(&ln.res_dev, sizeof(ct_check_result) * ln.max_layers));
+    LANE_TRY(hipHostMalloc(&ln.layers_host, sizeof(LayerDev) * ln.max_layers, hipHostMallocDefault));
+    LANE_TRY(hipHostMalloc(&ln.gemm_host, sizeof(GemmProb) * ln.max_probs, hipHostMallocDefault));
+    LANE_TRY(hipHostMalloc(&ln.pack_host, sizeof(PackJob) * ln.max_jobs, hipHostMallocDefault));
+    LANE_TRY(hipHostMalloc(&ln.skinny_host, sizeof(SkinnyProb) * ln.max_layers, hipHostMallocDefault));
+    LANE_TRY(hipHostMalloc(&ln.res_host, sizeof(ct_check_result) * ln.max_layers, hipHostMallocDefault));
+    LANE_TRY(hipEventCreateWithFlags(&ln.upload_done, hipEventDisableTiming));
+    LANE_TRY(hipEventRecord(ln.upload_done, ln.stream));
+#undef LANE_TRY
+    return hipSuccess;
+}
+
+void lane_free(Lane &ln) {
+    if (ln.upload_done) (void)hipEventDestroy(ln.upload_done);
+    if (ln.layers_dev) (void)hipFree(ln.layers_dev);
+    if (ln.gemm_dev) (void)hipFree(ln.gemm_dev);
+    if (ln.pack_dev) (void)hipFree(ln.pack_dev);
+    if (ln.skinny_dev) (void)hipFree(ln.skinny_dev);
+    if (ln.acc_dev) (void)hipFree(ln.acc_dev);
+    if (ln.res_dev) (void)hipFree(ln.res_dev);
+    if (ln.layers_host) (void)hipHostFree(ln.layers_host);
+    if (ln.gemm_host) (void)hipHostFree(ln.gemm_host);
+    if (ln.pack_host) (void)hipHostFree(ln.pack_host);
+    if (ln.skinny_host) (void)hipHostFree(ln.skinny_host);
+    if (ln.res_host) (void)hipHostFree(ln.res_host);
+    ln = Lane();
+}
+
+}  // namespace ct
 
 extern "C" {
 
@@ -365,66 +394,30 @@ ct_status ct_create(ct_ctx **out, const ct_params *p) {
     if (p->k_bits != 64 || p->s_bits != 64) return CT_EINVAL;
     ct_ctx *c = new ct_ctx();
     c->device = p->device;
-    c->stream = reinterpret_cast<hipStream_t>(p->hip_stream);
-    c->max_layers = p->max_layers > 0 ? p->max_layers : 256;
-    c->max_probs = 4 * c->max_layers;
-    c->max_jobs = 10 * c->max_layers;
     for (int q = 0; q < 2; q++) c->delta[q] = hdraw(hkey(p->key_seed, GLOBAL_LAYER, P_KEY + q), 0);
-    auto bail = [&](hipError_t e, const char *what) {
-        std::fprintf(stderr, "ct_create: %s: %s\n", what, hipGetErrorString(e));
+    hipError_t e;
+    if ((e = hipSetDevice(c->device)) == hipSuccess) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cus > 0)
+            c->num_cus = cus;
+        e = lane_init(c->main, reinterpret_cast<hipStream_t>(p->hip_stream), p->max_layers > 0 ? p->max_layers : 256);
+    }
+    if (e != hipSuccess) {
+        std::fprintf(stderr, "ct_create: %s\n", hipGetErrorString(e));
         ct_destroy(c);
         return CT_EDEVICE;
-    };
-    hipError_t e;
-    if ((e = hipSetDevice(c->device)) != hipSuccess) return bail(e, "hipSetDevice");
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cus > 0)
-        c->num_cus = cus;
-    if ((e = hipMalloc(&c->layers_dev, sizeof(LayerDev) * c->max_layers)) != hipSuccess) return bail(e, "hipMalloc");
-    if ((e = hipMalloc(&c->gemm_dev, sizeof(GemmProb) * c->max_probs)) != hipSuccess) return bail(e, "hipMalloc");
-    if ((e = hipMalloc(&c->pack_dev, sizeof(PackJob) * c->max_jobs)) != hipSuccess) return bail(e, "hipMalloc");
-    if ((e = hipMalloc(&c->skinny_dev, sizeof(SkinnyProb) * c->max_layers)) != hipSuccess)
-        return bail(e, "hipMalloc");
-    if ((e = hipHostMalloc(&c->pack_host, sizeof(PackJob) * c->max_jobs, hipHostMallocDefault)) != hipSuccess)
-        return bail(e, "hipHostMalloc");
-    if ((e = hipHostMalloc(&c->skinny_host, sizeof(SkinnyProb) * c->max_layers, hipHostMallocDefault)) !=
-        hipSuccess)
-        return bail(e, "hipHostMalloc");
-    if ((e = hipMalloc(&c->acc_dev, sizeof(u128) * ACC_PER_LAYER * c->max_layers)) != hipSuccess)
-        return bail(e, "hipMalloc");
-    if ((e = hipMalloc(&c->res_dev, sizeof(ct_check_result) * c->max_layers)) != hipSuccess)
-        return bail(e, "hipMalloc");
-    if ((e = hipHostMalloc(&c->layers_host, sizeof(LayerDev) * c->max_layers, hipHostMallocDefault)) != hipSuccess)
-        return bail(e, "hipHostMalloc");
-    if ((e = hipHostMalloc(&c->gemm_host, sizeof(GemmProb) * c->max_probs, hipHostMallocDefault)) != hipSuccess)
-        return bail(e, "hipHostMalloc");
-    if ((e = hipHostMalloc(&c->res_host, sizeof(ct_check_result) * c->max_layers, hipHostMallocDefault)) !=
-        hipSuccess)
-        return bail(e, "hipHostMalloc");
-    if ((e = hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming)) != hipSuccess)
-        return bail(e, "hipEventCreate");
-    if ((e = hipEventRecord(c->upload_done, c->stream)) != hipSuccess) return bail(e, "hipEventRecord");
+    }
+    c->main.timed = true;
     *out = c;
     return CT_OK;
 }
 
 ct_status ct_destroy(ct_ctx *c) {
     if (!c) return CT_EINVAL;
-    if (c->stream || c->layers_dev) hipStreamSynchronize(c->stream);
-    if (c->upload_done) hipEventDestroy(c->upload_done);
-    for (auto e : c->ev_start) hipEventDestroy(e);
-    for (auto e : c->ev_end) hipEventDestroy(e);
-    if (c->layers_dev) hipFree(c->layers_dev);
-    if (c->gemm_dev) hipFree(c->gemm_dev);
-    if (c->acc_dev) hipFree(c->acc_dev);
-    if (c->pack_dev) hipFree(c->pack_dev);
-    if (c->skinny_dev) hipFree(c->skinny_dev);
-    if (c->pack_host) hipHostFree(c->pack_host);
-    if (c->skinny_host) hipHostFree(c->skinny_host);
-    if (c->res_dev) hipFree(c->res_dev);
-    if (c->layers_host) hipHostFree(c->layers_host);
-    if (c->gemm_host) hipHostFree(c->gemm_host);
-    if (c->res_host) hipHostFree(c->res_host);
+    if (c->main.layers_dev) (void)hipStreamSynchronize(c->main.stream);
+    for (auto e : c->ev_start) (void)hipEventDestroy(e);
+    for (auto e : c->ev_end) (void)hipEventDestroy(e);
+    lane_free(c->main);
     delete c;
     return CT_OK;
 }
@@ -438,74 +431,85 @@ ct_status ct_key_shares(const ct_ctx *c, uint64_t out[2]) {
 
 const char *ct_last_error(const ct_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
-ct_status ct_gen_triple_tags(ct_ctx *c, const ct_layer_desc *L, const ct_layer_bufs *B, int n, int with_inputs) {
-    ct_status s = validate(c, L, B, n, NEED_TRIPLE | NEED_WORK | (with_inputs ? NEED_INPUTS : 0));
+}  // extern "C"
+
+ct_status ct::run_deal(ct_ctx *c, Lane &ln, const ct_layer_desc *L, const ct_layer_bufs *B, int n, int with_inputs) {
+    ct_status s = validate(c, ln.max_layers, L, B, n, NEED_TRIPLE | NEED_WORK | (with_inputs ? NEED_INPUTS : 0));
     if (s != CT_OK) return s;
     HIPCHK(c, hipSetDevice(c->device));
-    if ((s = stage_layers(c, L, B, n)) != CT_OK) return s;
+    if ((s = stage_layers(c, ln, L, B, n)) != CT_OK) return s;
     // C~ = A~ B~ with the lifts left in party 1's buffers: packed matrix-core
     // product for wide layers (operand tiles in the workspace), VALU rows for
     // layers with N <= SKINNY_MAX_N.
     std::vector<GemmProb> probs;
     int njobs = 0, nskinny = 0;
     for (int l = 0; l < n; l++) {
-        const LayerDev &o = c->layers_host[l];
+        const LayerDev &o = ln.layers_host[l];
         const ct_layer_desc &d = L[l];
         if (d.N <= SKINNY_MAX_N) {
             SkinnyProb sp;
             std::memset(&sp, 0, sizeof(sp));
             sp.L = o.A[1]; sp.R = o.B[1]; sp.out = o.C[1];
             sp.M = (int32_t)d.M; sp.N = (int32_t)d.N; sp.K = (int32_t)d.K;
-            c->skinny_host[nskinny++] = sp;
+            ln.skinny_host[nskinny++] = sp;
             continue;
         }
         const WorkOff w = work_off(d.M, d.K, d.N);
-        c->pack_host[njobs++] = make_job(o.A[1], o.work + w.Ep, d.M, d.K, 0);
-        c->pack_host[njobs++] = make_job(o.B[1], o.work + w.B0p, d.K, d.N, 1);
+        ln.pack_host[njobs++] = make_job(o.A[1], o.work + w.Ep, d.M, d.K, 0);
+        ln.pack_host[njobs++] = make_job(o.B[1], o.work + w.B0p, d.K, d.N, 1);
         probs.push_back(make_prob(o.work + w.Ep, nullptr, o.work + w.B0p, nullptr, nullptr, o.C[1], d));
     }
-    const int pack_tiles = plan_jobs(c->pack_host, njobs);
+    const int pack_tiles = plan_jobs(ln.pack_host, njobs);
     int total_tiles = 0;
     bool any_accum = false;
     const GemmTuning tu = c->fallback;
     const int nm = plan_gemms(probs, c->num_cus, tu, &total_tiles, &any_accum);
-    std::copy(probs.begin(), probs.end(), c->gemm_host);
-    if ((s = upload(c, n, nm, njobs, nskinny)) != CT_OK) return s;
+    std::copy(probs.begin(), probs.end(), ln.gemm_host);
+    if ((s = upload(c, ln, n, nm, njobs, nskinny)) != CT_OK) return s;
     const Sizes sz = max_sizes(L, n);
-    LAUNCH(c, ST_DEAL_LIFT, launch_deal_lift(c->layers_dev, n, std::max(sz.mk, sz.kn), c->stream));
-    LAUNCH(c, ST_PACK, launch_pack(c->pack_dev, njobs, pack_tiles, c->stream));
+    LAUNCH(c, ln, ST_DEAL_LIFT, launch_deal_lift(ln.layers_dev, n, std::max(sz.mk, sz.kn), ln.stream));
+    LAUNCH(c, ln, ST_PACK, launch_pack(ln.pack_dev, njobs, pack_tiles, ln.stream));
     for (int i = 0; i < nm; i++)
         if (probs[i].accumulate)
-            LAUNCH(c, ST_FILL_ZERO, launch_fill_zero(probs[i].out, (int64_t)probs[i].M * probs[i].N, c->stream));
-    if ((s = run_gemms(c, nm, total_tiles, tu)) != CT_OK) return s;
+            LAUNCH(c, ln, ST_FILL_ZERO, launch_fill_zero(probs[i].out, (int64_t)probs[i].M * probs[i].N, ln.stream));
+    if ((s = run_gemms(c, ln, nm, total_tiles, tu)) != CT_OK) return s;
     if (nskinny > 0) {
         int max_rows = 0;
-        for (int i = 0; i < nskinny; i++) max_rows = std::max(max_rows, c->skinny_host[i].M);
-        LAUNCH(c, ST_DEAL_SKINNY, launch_skinny(c->skinny_dev, nskinny, max_rows, c->stream));
+        for (int i = 0; i < nskinny; i++) max_rows = std::max(max_rows, ln.skinny_host[i].M);
+        LAUNCH(c, ln, ST_DEAL_SKINNY, launch_skinny(ln.skinny_dev, nskinny, max_rows, ln.stream));
     }
     const int mask = (with_inputs ? ((1 << OBJ_X) | (1 << OBJ_Y)) : 0) | (1 << OBJ_A) | (1 << OBJ_B) |
                      (1 << OBJ_C) | (1 << OBJ_R);
-    LAUNCH(c, ST_DEAL_AUTH, launch_deal_auth(c->layers_dev, n, mask, std::max({sz.mk, sz.kn, sz.mn}), c->stream));
+    LAUNCH(c, ln, ST_DEAL_AUTH, launch_deal_auth(ln.layers_dev, n, mask, std::max({sz.mk, sz.kn, sz.mn}), ln.stream));
     return CT_OK;
+}
+
+
+extern "C" {
+
+ct_status ct_gen_triple_tags(ct_ctx *c, const ct_layer_desc *L, const ct_layer_bufs *B, int n, int with_inputs) {
+    if (!c) return CT_EINVAL;
+    return run_deal(c, c->main, L, B, n, with_inputs);
 }
 
 }  // extern "C"
 
-namespace {
+namespace ct {
 
 // The online phase, optionally with the verification fused into its passes
-// (out_dev != nullptr).
-ct_status online(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
-                 ct_check_result *out_dev) {
+// (out_dev != nullptr): validation, tables and their upload.
+ct_status prepare_online(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
+                         ct_check_result *out_dev, OnlineLaunch &P) {
     if (!c) return CT_EINVAL;
     if (mode != CT_MODE_SPDZ2K && mode != CT_MODE_COMPACT) return fail(c, CT_EINVAL, "unknown mode");
     const bool compact = mode == CT_MODE_COMPACT;
     const bool check = out_dev != nullptr;
-    ct_status s = validate(c, L, B, n, NEED_INPUTS | NEED_TRIPLE | NEED_OUT | NEED_WORK | (compact ? NEED_CVEC : 0));
+    ct_status s = validate(c, ln.max_layers, L, B, n,
+                           NEED_INPUTS | NEED_TRIPLE | NEED_OUT | NEED_WORK | (compact ? NEED_CVEC : 0));
     if (s != CT_OK) return s;
     if (check && !aligned16(out_dev)) return fail(c, CT_EINVAL, "out_dev is null or misaligned");
     HIPCHK(c, hipSetDevice(c->device));
-    if ((s = stage_layers(c, L, B, n)) != CT_OK) return s;
+    if ((s = stage_layers(c, ln, L, B, n)) != CT_OK) return s;
 
     // Matrix-core products (layers with N > SKINNY_MAX_N), both parties,
     // Eq. (2) with E U folded into party 0's left operand by the row pass:
@@ -518,10 +522,10 @@ ct_status online(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_layer
     for (int l = 0; l < n; l++) {
         const ct_layer_desc &d = L[l];
         if (d.N <= SKINNY_MAX_N) continue;
-        const LayerDev &o = c->layers_host[l];
+        const LayerDev &o = ln.layers_host[l];
         const WorkOff w = work_off(d.M, d.K, d.N);
         u128 *W = o.work;
-        PackJob *J = c->pack_host;
+        PackJob *J = ln.pack_host;
         J[njobs++] = make_job(o.E, W + w.Ep, d.M, d.K, 0);
         J[njobs++] = make_job(W + w.AE0, W + w.AE0p, d.M, d.K, 0);
         J[njobs++] = make_job(o.A[1], W + w.A1p, d.M, d.K, 0);
@@ -541,82 +545,179 @@ ct_status online(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_layer
         }
         for (size_t j = first; j < probs.size(); j++) probs[j].gsize = (int32_t)(probs.size() - first);
     }
-    const int pack_tiles = plan_jobs(c->pack_host, njobs);
-    int total_tiles = 0;
-    bool any_accum = false;
-    const GemmTuning tu = tuning_for(c, shape_class(mode, L, n));
-    const int nm = plan_gemms(probs, c->num_cus, tu, &total_tiles, &any_accum);
-    std::copy(probs.begin(), probs.end(), c->gemm_host);
-    if ((s = upload(c, n, nm, njobs)) != CT_OK) return s;
+    P = OnlineLaunch();
+    P.n = n;
+    P.mode = mode;
+    P.compact = compact;
+    P.check = check;
+    P.out_dev = out_dev;
+    P.njobs = njobs;
+    P.pack_tiles = plan_jobs(ln.pack_host, njobs);
+    P.tu = tuning_for(c, shape_class(mode, L, n));
+    P.nm = plan_gemms(probs, c->num_cus, P.tu, &P.total_tiles, &P.any_accum);
+    std::copy(probs.begin(), probs.end(), ln.gemm_host);
+    if ((s = upload(c, ln, n, P.nm, njobs)) != CT_OK) return s;
 
     const Sizes sz = max_sizes(L, n);
-    const int flags = (check ? F_CHECK : 0) | (compact ? F_COMPACT : F_SPDZ);
-    const int zero_what = (compact ? 1 : 0) | (check ? 2 : 0);
-    if (zero_what) LAUNCH(c, ST_ZERO_ACC, launch_zero_acc(c->layers_dev, n, zero_what, sz.cvec, c->stream));
-    LAUNCH(c, ST_OPEN_U, launch_open_u(c->layers_dev, n, flags, sz.kn_items, c->stream));
-    int variants = 0;
+    P.max_zero = std::max(compact ? sz.cvec : 0, sz.skinny_mn);
+    P.max_kn_items = sz.kn_items;
+    P.max_row_items = sz.row_items;
+    P.max_mn = sz.mn;
+    P.max_mn_items = sz.mn_items;
+    P.flags = (check ? F_CHECK : 0) | (compact ? F_COMPACT : F_SPDZ);
+    // cvec sums, check accumulators, and [Z]_p = [C]_p ([tZ]_p = [tC]_p) of
+    // skinny layers, all accumulated into atomically by the passes
+    P.zero_what = (compact ? 1 : 0) | (check ? 2 : 0) | (sz.skinny ? 4 : 0) | (sz.skinny && !compact ? 8 : 0);
     for (int l = 0; l < n; l++) {
         const int64_t N = L[l].N;
-        variants |= 1 << (N > SKINNY_MAX_N ? 0 : (N <= 1 ? 1 : (N <= 2 ? 2 : (N <= 4 ? 4 : SKINNY_MAX_N))));
+        P.variants |= 1 << (N > SKINNY_MAX_N ? 0 : (N <= 1 ? 1 : (N <= 2 ? 2 : (N <= 4 ? 4 : SKINNY_MAX_N))));
     }
-    LAUNCH(c, ST_ROW_PASS, launch_row_pass(c->layers_dev, n, flags, sz.m, variants, c->stream));
-    if (njobs > 0) LAUNCH(c, ST_PACK, launch_pack(c->pack_dev, njobs, pack_tiles, c->stream));
-    if (any_accum) LAUNCH(c, ST_COPY_BASE, launch_copy_base(c->layers_dev, n, mode, sz.mn, c->stream));
-    if ((s = run_gemms(c, nm, total_tiles, tu)) != CT_OK) return s;
-    LAUNCH(c, ST_POST, launch_post(c->layers_dev, n, flags, sz.mn_items, c->stream));
-    if (compact) LAUNCH(c, ST_COMPACT_FINAL, launch_compact_final(c->layers_dev, n, flags, c->stream));
-    if (check) LAUNCH(c, ST_FINALIZE, launch_finalize(c->layers_dev, n, out_dev, c->stream));
     return CT_OK;
 }
 
-}  // namespace
+// The kernels of the online phase, in order, on the lane's stream.
+ct_status enqueue_online(ct_ctx *c, Lane &ln, const OnlineLaunch &P) {
+    const int n = P.n;
+    if (P.zero_what)
+        LAUNCH(c, ln, ST_ZERO_ACC, launch_zero_acc(ln.layers_dev, n, P.zero_what, P.max_zero, ln.stream));
+    LAUNCH(c, ln, ST_OPEN_U, launch_open_u(ln.layers_dev, n, P.flags, P.max_kn_items, ln.stream));
+    LAUNCH(c, ln, ST_ROW_PASS, launch_row_pass(ln.layers_dev, n, P.flags, P.max_row_items, P.variants, ln.stream));
+    if (P.njobs > 0) LAUNCH(c, ln, ST_PACK, launch_pack(ln.pack_dev, P.njobs, P.pack_tiles, ln.stream));
+    if (P.any_accum)
+        LAUNCH(c, ln, ST_COPY_BASE, launch_copy_base(ln.layers_dev, n, P.mode, P.max_mn, ln.stream));
+    ct_status s = run_gemms(c, ln, P.nm, P.total_tiles, P.tu);
+    if (s != CT_OK) return s;
+    LAUNCH(c, ln, ST_POST, launch_post(ln.layers_dev, n, P.flags, P.max_mn_items, ln.stream));
+    if (P.compact) LAUNCH(c, ln, ST_COMPACT_FINAL, launch_compact_final(ln.layers_dev, n, P.flags, ln.stream));
+    if (P.check) LAUNCH(c, ln, ST_FINALIZE, launch_finalize(ln.layers_dev, n, P.out_dev, ln.stream));
+    return CT_OK;
+}
+
+ct_status run_online(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
+                     ct_check_result *out_dev) {
+    OnlineLaunch P;
+    ct_status s = prepare_online(c, ln, mode, L, B, n, out_dev, P);
+    return s != CT_OK ? s : enqueue_online(c, ln, P);
+}
+
+ct_status run_check(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
+                    ct_check_result *out_dev) {
+    if (!c) return CT_EINVAL;
+    if (mode != CT_MODE_SPDZ2K && mode != CT_MODE_COMPACT) return fail(c, CT_EINVAL, "unknown mode");
+    const bool compact = mode == CT_MODE_COMPACT;
+    ct_status s = validate(c, ln.max_layers, L, B, n, NEED_INPUTS | NEED_TRIPLE | NEED_OUT | (compact ? NEED_CVEC : 0));
+    if (s != CT_OK) return s;
+    if (!aligned16(out_dev)) return fail(c, CT_EINVAL, "out_dev is null or misaligned");
+    HIPCHK(c, hipSetDevice(c->device));
+    if ((s = stage_layers(c, ln, L, B, n)) != CT_OK) return s;
+    if ((s = upload(c, ln, n, 0)) != CT_OK) return s;
+    const Sizes sz = max_sizes(L, n);
+    LAUNCH(c, ln, ST_ZERO_ACC, launch_zero_acc(ln.layers_dev, n, 2, 0, ln.stream));
+    const int mask = compact ? 0x3 : 0x7;
+    LAUNCH(c, ln, ST_CHECK_BATCH,
+           launch_check_batch(ln.layers_dev, n, mask, std::max({sz.mk, sz.kn, sz.mn}), ln.stream));
+    if (compact) LAUNCH(c, ln, ST_CHECK_COMPACT, launch_check_compact(ln.layers_dev, n, ln.stream));
+    LAUNCH(c, ln, ST_FINALIZE, launch_finalize(ln.layers_dev, n, out_dev, ln.stream));
+    return CT_OK;
+}
+
+}  // namespace ct
 
 extern "C" {
 
 ct_status ct_tag_linear(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n) {
-    return online(c, mode, L, B, n, nullptr);
+    if (!c) return CT_EINVAL;
+    return run_online(c, c->main, mode, L, B, n, nullptr);
 }
 
 ct_status ct_tag_linear_check(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
                               ct_check_result *out_dev) {
-    if (c && !out_dev) return fail(c, CT_EINVAL, "null result array");
-    return online(c, mode, L, B, n, out_dev);
+    if (!c) return CT_EINVAL;
+    if (!out_dev) return fail(c, CT_EINVAL, "null result array");
+    return run_online(c, c->main, mode, L, B, n, out_dev);
 }
 
 ct_status ct_mac_check_device(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
                               ct_check_result *out_dev) {
     if (!c) return CT_EINVAL;
-    if (mode != CT_MODE_SPDZ2K && mode != CT_MODE_COMPACT) return fail(c, CT_EINVAL, "unknown mode");
-    const bool compact = mode == CT_MODE_COMPACT;
-    ct_status s = validate(c, L, B, n, NEED_INPUTS | NEED_TRIPLE | NEED_OUT | (compact ? NEED_CVEC : 0));
-    if (s != CT_OK) return s;
-    if (!aligned16(out_dev)) return fail(c, CT_EINVAL, "out_dev is null or misaligned");
-    HIPCHK(c, hipSetDevice(c->device));
-    if ((s = stage_layers(c, L, B, n)) != CT_OK) return s;
-    if ((s = upload(c, n, 0)) != CT_OK) return s;
-    const Sizes sz = max_sizes(L, n);
-    LAUNCH(c, ST_ZERO_ACC, launch_zero_acc(c->layers_dev, n, 2, 0, c->stream));
-    const int mask = compact ? 0x3 : 0x7;
-    LAUNCH(c, ST_CHECK_BATCH, launch_check_batch(c->layers_dev, n, mask, std::max({sz.mk, sz.kn, sz.mn}), c->stream));
-    if (compact) LAUNCH(c, ST_CHECK_COMPACT, launch_check_compact(c->layers_dev, n, c->stream));
-    LAUNCH(c, ST_FINALIZE, launch_finalize(c->layers_dev, n, out_dev, c->stream));
-    return CT_OK;
+    return run_check(c, c->main, mode, L, B, n, out_dev);
 }
 
 ct_status ct_mac_check(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
                        ct_check_result *out) {
     if (!c) return CT_EINVAL;
     if (!out) return fail(c, CT_EINVAL, "null result array");
-    ct_status s = ct_mac_check_device(c, mode, L, B, n, c->res_dev);
+    Lane &ln = c->main;
+    ct_status s = run_check(c, ln, mode, L, B, n, ln.res_dev);
     if (s != CT_OK) return s;
-    HIPCHK(c, hipMemcpyAsync(c->res_host, c->res_dev, sizeof(ct_check_result) * n, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpyAsync(ln.res_host, ln.res_dev, sizeof(ct_check_result) * n, hipMemcpyDeviceToHost, ln.stream));
+    HIPCHK(c, hipStreamSynchronize(ln.stream));
     bool ok = true;
     for (int l = 0; l < n; l++) {
-        out[l] = c->res_host[l];
-        ok = ok && c->res_host[l].accept;
+        out[l] = ln.res_host[l];
+        ok = ok && ln.res_host[l].accept;
     }
     return ok ? CT_OK : CT_ABORT;
+}
+
+ct_status ct_plan_create(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
+                         ct_check_result *out_dev, ct_plan **out) {
+    if (!c || !out) return CT_EINVAL;
+    *out = nullptr;
+    HIPCHK(c, hipSetDevice(c->device));
+    ct_plan *pl = new ct_plan();
+    pl->ctx = c;
+    hipStream_t st = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = lane_init(pl->lane, st, std::max(n, 1));
+    if (e != hipSuccess) {
+        ct_plan_destroy(pl);
+        return hip_fail(c, e, "ct_plan_create");
+    }
+    OnlineLaunch P;
+    ct_status s = prepare_online(c, pl->lane, mode, L, B, n, out_dev, P);
+    if (s == CT_OK) {
+        // the tables are uploaded before the capture starts, so the graph
+        // holds kernel nodes only
+        e = hipStreamSynchronize(st);
+        if (e == hipSuccess) e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            s = enqueue_online(c, pl->lane, P);
+            const hipError_t e2 = hipStreamEndCapture(st, &pl->graph);
+            if (s == CT_OK && e2 != hipSuccess) e = e2;
+        }
+        if (s == CT_OK && e == hipSuccess) e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
+        if (s == CT_OK && e != hipSuccess) s = hip_fail(c, e, "graph capture");
+    }
+    if (s != CT_OK) {
+        ct_plan_destroy(pl);
+        return s;
+    }
+    *out = pl;
+    return CT_OK;
+}
+
+ct_status ct_plan_launch(ct_plan *pl) {
+    if (!pl) return CT_EINVAL;
+    ct_ctx *c = pl->ctx;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipGraphLaunch(pl->exec, c->main.stream));
+    return CT_OK;
+}
+
+ct_status ct_plan_destroy(ct_plan *pl) {
+    if (!pl) return CT_EINVAL;
+    (void)hipSetDevice(pl->ctx->device);
+    if (pl->lane.stream) (void)hipStreamSynchronize(pl->lane.stream);
+    // a replay may still be running on the context stream
+    (void)hipStreamSynchronize(pl->ctx->main.stream);
+    if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+    if (pl->graph) (void)hipGraphDestroy(pl->graph);
+    hipStream_t st = pl->lane.stream;
+    lane_free(pl->lane);
+    if (st) (void)hipStreamDestroy(st);
+    delete pl;
+    return CT_OK;
 }
 
 ct_status ct_set_timing(ct_ctx *c, int enable) {
@@ -674,12 +775,12 @@ ct_status ct_autotune(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_
             for (int sp : splits) {
                 c->forcing = true;
                 c->forced = GemmTuning{g, xcd, sp};
-                s = online(c, mode, L, B, n, nullptr);  // warm-up
+                s = run_online(c, c->main, mode, L, B, n, nullptr);  // warm-up
                 if (s == CT_OK) {
                     HIPCHK(c, fold_timing(c));
                     c->stage_ms[ST_RING_GEMM] = 0;
                     c->stage_n[ST_RING_GEMM] = 0;
-                    for (int r = 0; r < reps && s == CT_OK; r++) s = online(c, mode, L, B, n, nullptr);
+                    for (int r = 0; r < reps && s == CT_OK; r++) s = run_online(c, c->main, mode, L, B, n, nullptr);
                 }
                 if (s == CT_OK) {
                     HIPCHK(c, fold_timing(c));

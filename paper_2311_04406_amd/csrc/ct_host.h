@@ -1,0 +1,96 @@
+// ct_host.h -- host-side internals shared by the C ABI (ct_api.hip), the
+// captured plans and the request server (ct_serve.hip).
+//
+// A Lane is everything one in-order execution of the path needs besides the
+// layer buffers: a HIP stream, device-resident tables (one LayerDev record
+// per layer, the matrix-core problem and packing-job lists), their pinned
+// host staging copies, the per-layer check accumulators and a result array.
+// The context owns one lane for its plain calls; a captured plan and every
+// slot of a server own one each, so their work can be in flight together.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "compacttag.h"
+#include "ct_internal.h"
+
+namespace ct {
+
+struct Lane {
+    hipStream_t stream = nullptr;
+    int max_layers = 0, max_probs = 0, max_jobs = 0;
+    LayerDev *layers_dev = nullptr, *layers_host = nullptr;
+    GemmProb *gemm_dev = nullptr, *gemm_host = nullptr;
+    PackJob *pack_dev = nullptr, *pack_host = nullptr;
+    SkinnyProb *skinny_dev = nullptr, *skinny_host = nullptr;
+    u128 *acc_dev = nullptr;
+    ct_check_result *res_dev = nullptr, *res_host = nullptr;
+    hipEvent_t upload_done = nullptr;  // the staging copies may be rewritten once this has completed
+    bool timed = false;                // per-launch event timing (the context's own lane only)
+};
+
+// Allocates the lane's tables for up to max_layers layers (the stream is the
+// caller's).  On failure the lane is left for lane_free.
+hipError_t lane_init(Lane &ln, hipStream_t stream, int max_layers);
+void lane_free(Lane &ln);
+
+}  // namespace ct
+
+// Kernel stages, for the optional per-launch timing (ct_set_timing).
+enum Stage : int {
+    ST_DEAL_LIFT, ST_FILL_ZERO, ST_DEAL_AUTH, ST_DEAL_SKINNY, ST_ZERO_ACC, ST_OPEN_U, ST_ROW_PASS, ST_PACK,
+    ST_COPY_BASE, ST_RING_GEMM, ST_POST, ST_COMPACT_FINAL, ST_CHECK_BATCH, ST_CHECK_COMPACT, ST_FINALIZE, ST_COUNT
+};
+
+struct ct_ctx {
+    int device = 0;
+    uint64_t delta[2] = {0, 0};
+    int num_cus = 256;
+    ct::Lane main;
+    std::string err;
+    // per-launch timing: event pairs recorded around each kernel of the main lane
+    bool timing = false;
+    std::vector<hipEvent_t> ev_start, ev_end;
+    std::vector<int> ev_stage;
+    int ev_used = 0;
+    double stage_ms[ST_COUNT] = {};
+    int64_t stage_n[ST_COUNT] = {};
+    // launch configuration of the matrix-core products per shape class
+    std::unordered_map<uint64_t, ct::GemmTuning> tuned;
+    ct::GemmTuning fallback = {1, 0, 0};
+    bool forcing = false;
+    ct::GemmTuning forced = {1, 0, 0};
+};
+
+namespace ct {
+
+// The phases of the path on a lane.  Each validates, stages and uploads its
+// tables on ln.stream, then enqueues its kernels there; nothing blocks except
+// the wait for the lane's previous upload.
+ct_status run_deal(ct_ctx *c, Lane &ln, const ct_layer_desc *L, const ct_layer_bufs *B, int n, int with_inputs);
+ct_status run_online(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
+                     ct_check_result *out_dev);
+ct_status run_check(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
+                    ct_check_result *out_dev);
+
+// Online phase split in two for capture: prepare validates and uploads the
+// tables (outside a capture), enqueue only launches kernels.
+struct OnlineLaunch {
+    int n = 0, nm = 0, njobs = 0, pack_tiles = 0, total_tiles = 0, variants = 0, flags = 0, zero_what = 0;
+    bool any_accum = false, compact = false, check = false;
+    ct_mode mode = CT_MODE_COMPACT;
+    GemmTuning tu;
+    int64_t max_zero = 0, max_kn_items = 0, max_row_items = 0, max_mn = 0, max_mn_items = 0;
+    ct_check_result *out_dev = nullptr;
+};
+ct_status prepare_online(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
+                         ct_check_result *out_dev, OnlineLaunch &P);
+ct_status enqueue_online(ct_ctx *c, Lane &ln, const OnlineLaunch &P);
+
+ct_status fail(ct_ctx *c, ct_status s, const std::string &msg);
+
+}  // namespace ct

@@ -51,6 +51,20 @@ struct LayerDev {
 // the pass that opens E (no MFMA tiles, no workspace).
 constexpr int SKINNY_MAX_N = 8;
 
+// Elements of one row of E per work item of the row pass (a multiple of 64,
+// at least 256): long rows are cut into several items, so that a layer with
+// few rows still spreads over the whole GPU; segments double while the layer
+// keeps at least 16384 items.
+__host__ __device__ inline int64_t row_seg(int64_t M, int64_t K) {
+    int64_t s = 256;
+    while (s < 4096 && M * ((K + 2 * s - 1) / (2 * s)) >= 16384) s *= 2;
+    return s;
+}
+__host__ __device__ inline int64_t row_items(int64_t M, int64_t K) {
+    const int64_t s = row_seg(M, K);
+    return M * ((K + s - 1) / s);
+}
+
 // Flags of the fused passes.
 enum PassFlags : int {
     F_CHECK = 1,    // accumulate the MAC-check sums of the values the pass opens
@@ -154,11 +168,11 @@ hipError_t launch_skinny(const SkinnyProb *probs_dev, int nprobs, int max_rows, 
 hipError_t launch_fill_zero(u128 *p, int64_t n, hipStream_t st);
 hipError_t launch_deal_lift(const LayerDev *L, int n, int64_t max_elems, hipStream_t st);
 hipError_t launch_deal_auth(const LayerDev *L, int n, int obj, int64_t max_elems, hipStream_t st);
-hipError_t launch_zero_acc(const LayerDev *L, int n, int what, int64_t max_cvec, hipStream_t st);
+hipError_t launch_zero_acc(const LayerDev *L, int n, int what, int64_t max_elems, hipStream_t st);
 hipError_t launch_copy_base(const LayerDev *L, int n, int mode, int64_t max_elems, hipStream_t st);
 hipError_t launch_open_u(const LayerDev *L, int n, int flags, int64_t max_items, hipStream_t st);
 // variants: bit v set if some layer takes row-pass variant v (0, 1, 2, 4, 8)
-hipError_t launch_row_pass(const LayerDev *L, int n, int flags, int64_t max_rows, int variants, hipStream_t st);
+hipError_t launch_row_pass(const LayerDev *L, int n, int flags, int64_t max_items, int variants, hipStream_t st);
 hipError_t launch_post(const LayerDev *L, int n, int flags, int64_t max_items, hipStream_t st);
 hipError_t launch_compact_final(const LayerDev *L, int n, int flags, hipStream_t st);
 hipError_t launch_check_batch(const LayerDev *L, int n, int which, int64_t max_elems, hipStream_t st);

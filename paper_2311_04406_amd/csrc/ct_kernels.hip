@@ -179,19 +179,32 @@ hipError_t launch_deal_auth(const LayerDev *L, int n, int obj_mask, int64_t max_
 }
 
 // ---------------------------------------------------------------- zeroing
-// what bit 0: the compressed vectors (cvec); bit 1: the check accumulators.
+// what bit 0: the compressed vectors (cvec); bit 1: the check accumulators;
+// bit 2: for layers with N <= SKINNY_MAX_N, [Z]_p = [C]_p (the row pass adds
+// the products of each row segment atomically); bit 3: also [tZ]_p = [tC]_p.
 __global__ void k_zero_acc(const LayerDev *__restrict__ Ls, int what) {
     const LayerDev &L = Ls[blockIdx.y];
+    const int64_t t0 = blockIdx.x * (int64_t)TPB + threadIdx.x, stride = (int64_t)gridDim.x * TPB;
     if (what & 1) {
         const int64_t n = 3 * L.K + 10 * L.M;
-        for (int64_t e = blockIdx.x * (int64_t)TPB + threadIdx.x; e < n; e += (int64_t)gridDim.x * TPB)
-            st(L.cvec, e, zero128());
+        for (int64_t e = t0; e < n; e += stride) st(L.cvec, e, zero128());
     }
     if ((what & 2) && blockIdx.x == 0 && threadIdx.x < ACC_PER_LAYER) st(L.acc, threadIdx.x, zero128());
+    if ((what & 4) && L.N <= SKINNY_MAX_N) {
+        const int64_t n = L.M * L.N;
+        for (int64_t e = t0; e < n; e += stride) {
+            st(L.Z[0], e, ld(L.C[0], e));
+            st(L.Z[1], e, ld(L.C[1], e));
+            if (what & 8) {
+                st(L.tZ[0], e, ld(L.tC[0], e));
+                st(L.tZ[1], e, ld(L.tC[1], e));
+            }
+        }
+    }
 }
 
-hipError_t launch_zero_acc(const LayerDev *L, int n, int what, int64_t max_cvec, hipStream_t st) {
-    hipLaunchKernelGGL(k_zero_acc, dim3((what & 1) ? grid_for(max_cvec) : 1, n), dim3(TPB), 0, st, L, what);
+hipError_t launch_zero_acc(const LayerDev *L, int n, int what, int64_t max_elems, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_acc, dim3((what & 5) ? grid_for(max_elems) : 1, n), dim3(TPB), 0, st, L, what);
     return hipGetLastError();
 }
 
@@ -264,10 +277,13 @@ hipError_t launch_open_u(const LayerDev *L, int n, int flags, int64_t max_items,
 }
 
 // ---------------------------------------------------------------- pass over M x K
-// One wavefront per row m of E; lanes stride over k with coalesced loads.
+// Work items are row segments of row_seg(M, K) elements, one wavefront each,
+// lanes striding over k with coalesced loads; each item adds its row sums
+// (compact-tag products, and the output products of skinny layers) to their
+// destinations with exact 128-bit atomics.
 template <int NS>
 __device__ __forceinline__ void row_pass_body(const LayerDev &L, int flags, u128 (&chk)[3]) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
     const int64_t M = L.M, K = L.K, N = L.N;
     const bool check = flags & F_CHECK, compact = flags & F_COMPACT, spdz = flags & F_SPDZ;
     const bool skinny = NS > 0;
@@ -276,7 +292,12 @@ __device__ __forceinline__ void row_pass_body(const LayerDev &L, int flags, u128
     const uint64_t kce = L.key[K_CHI_E];
     const uint64_t d0 = L.delta[0], d1 = L.delta[1];
     u128 *AE0 = L.work, *tAE0 = L.work + M * K, *tAE1 = L.work + 2 * M * K;
-    for (int64_t m = blockIdx.x * (int64_t)WAVES + wave; m < M; m += (int64_t)gridDim.x * WAVES) {
+    const int64_t seg = row_seg(M, K), segs = (K + seg - 1) / seg, items = M * segs;
+    const int64_t wave_id = (blockIdx.x * (int64_t)TPB + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * TPB) >> 6;
+    for (int64_t it = wave_id; it < items; it += nwaves) {
+        const int64_t m = it / segs, k0 = (it - m * segs) * seg;
+        const int64_t k1 = k0 + seg < K ? k0 + seg : K;
         // compact: E U^c, E tB^c_0, E tB^c_1, tA_0 U^c, tA_1 U^c
         u128 cp[5] = {zero128(), zero128(), zero128(), zero128(), zero128()};
         // skinny: Z_0, Z_1 (and SPDZ2k tZ_0, tZ_1) row products per column
@@ -284,12 +305,12 @@ __device__ __forceinline__ void row_pass_body(const LayerDev &L, int flags, u128
 #pragma unroll
         for (int j = 0; j < (NS > 0 ? NS : 1); j++) z0[j] = z1[j] = t0[j] = t1[j] = zero128();
         const int64_t rb = m * K;
-        for (int64_t k = lane; k < K; k += 64) {
+        for (int64_t k = k0 + lane; k < k1; k += 64) {
             const int64_t e = rb + k;
             const u128 a0 = ld(L.A[0], e), a1 = ld(L.A[1], e);
             const u128 E = add(sub(ld(L.X[0], e), a0), sub(ld(L.X[1], e), a1));
             st(L.E, e, E);
-            const bool need_ta = check || compact || (spdz && !skinny) || (spdz && skinny);
+            const bool need_ta = check || compact || spdz;
             u128 ta0 = zero128(), ta1 = zero128();
             if (need_ta) {
                 ta0 = ld(L.tA[0], e);
@@ -338,10 +359,11 @@ __device__ __forceinline__ void row_pass_body(const LayerDev &L, int flags, u128
 #pragma unroll
             for (int i = 0; i < 5; i++) cp[i] = wave_sum(cp[i]);
             if (lane == 0) {
-                st(L.cvec + o.EUc, m, cp[0]);
-                // partial compact tags; k_compact_final adds [tC^c]_p and [Delta]_p (E U^c)
-                st(L.cvec + o.tZc0, m, add(cp[1], cp[3]));
-                st(L.cvec + o.tZc1, m, add(cp[2], cp[4]));
+                // E U^c, and the partial compact tags (k_compact_final adds
+                // [tC^c]_p and [Delta]_p E U^c)
+                atomic_add128(L.cvec + o.EUc + m, cp[0]);
+                atomic_add128(L.cvec + o.tZc0 + m, add(cp[1], cp[3]));
+                atomic_add128(L.cvec + o.tZc1 + m, add(cp[2], cp[4]));
             }
         }
         if constexpr (skinny) {
@@ -355,12 +377,13 @@ __device__ __forceinline__ void row_pass_body(const LayerDev &L, int flags, u128
                         t1[j] = wave_sum(t1[j]);
                     }
                     if (lane == 0) {
+                        // onto [Z]_p = [C]_p (and [tZ]_p = [tC]_p) set by k_zero_acc
                         const int64_t mn = m * N + j;
-                        st(L.Z[0], mn, add(ld(L.C[0], mn), z0[j]));
-                        st(L.Z[1], mn, add(ld(L.C[1], mn), z1[j]));
+                        atomic_add128(L.Z[0] + mn, z0[j]);
+                        atomic_add128(L.Z[1] + mn, z1[j]);
                         if (spdz) {
-                            st(L.tZ[0], mn, add(ld(L.tC[0], mn), t0[j]));
-                            st(L.tZ[1], mn, add(ld(L.tC[1], mn), t1[j]));
+                            atomic_add128(L.tZ[0] + mn, t0[j]);
+                            atomic_add128(L.tZ[1] + mn, t1[j]);
                         }
                     }
                 }
@@ -386,8 +409,8 @@ __global__ __launch_bounds__(TPB) void k_row_pass(const LayerDev *__restrict__ L
     if (flags & F_CHECK) block_accumulate<3>(chk, sh, L.acc + 0);
 }
 
-hipError_t launch_row_pass(const LayerDev *L, int n, int flags, int64_t max_rows, int variants, hipStream_t st) {
-    const dim3 g(grid_items(max_rows), n), b(TPB);
+hipError_t launch_row_pass(const LayerDev *L, int n, int flags, int64_t max_items, int variants, hipStream_t st) {
+    const dim3 g(grid_items(max_items), n), b(TPB);
     if (variants & (1 << 0)) hipLaunchKernelGGL(k_row_pass<0>, g, b, 0, st, L, flags);
     if (variants & (1 << 1)) hipLaunchKernelGGL(k_row_pass<1>, g, b, 0, st, L, flags);
     if (variants & (1 << 2)) hipLaunchKernelGGL(k_row_pass<2>, g, b, 0, st, L, flags);

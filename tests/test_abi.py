@@ -24,13 +24,15 @@ def lib():
 
 def declared_functions():
     src = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:ct_status|const char \*)\s*(ct_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:ct_status|const char \*|double)\s*(ct_\w+)\s*\(", src, re.M)))
 
 
 def test_header_declares_the_boundary():
     names = declared_functions()
     for f in ("ct_create", "ct_destroy", "ct_gen_triple_tags", "ct_tag_linear", "ct_mac_check",
-              "ct_mac_check_device", "ct_key_shares", "ct_last_error"):
+              "ct_mac_check_device", "ct_key_shares", "ct_last_error", "ct_plan_create", "ct_plan_launch",
+              "ct_plan_destroy", "ct_server_create", "ct_server_submit", "ct_server_poll", "ct_server_drain",
+              "ct_server_layer", "ct_server_stats", "ct_server_destroy", "ct_server_now_us"):
         assert f in names
 
 
@@ -60,6 +62,10 @@ int main(void) {
   printf("%zu %zu %zu %zu\n", offsetof(ct_params, hip_stream), offsetof(ct_params, max_layers),
          offsetof(ct_layer_desc, seed), offsetof(ct_layer_desc, layer_id));
   printf("%zu %zu %zu\n", offsetof(ct_layer_bufs, E), offsetof(ct_layer_bufs, cvec), offsetof(ct_check_result, accept));
+  printf("%zu %zu %zu %zu\n", sizeof(ct_server_params), sizeof(ct_request), sizeof(ct_completion), sizeof(ct_server_counts));
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", offsetof(ct_server_params, mode), offsetof(ct_request, layer),
+         offsetof(ct_request, arrival_us), offsetof(ct_completion, done_us), offsetof(ct_completion, result),
+         offsetof(ct_server_counts, arena_bytes), offsetof(ct_server_counts, arena_used));
   return 0;
 }
 """
@@ -73,7 +79,12 @@ int main(void) {
            ctypes.sizeof(b.CtCheckResult),
            b.CtParams.hip_stream.offset, b.CtParams.max_layers.offset, b.CtLayerDesc.seed.offset,
            b.CtLayerDesc.layer_id.offset, b.CtLayerBufs.E.offset, b.CtLayerBufs.cvec.offset,
-           b.CtCheckResult.accept.offset]
+           b.CtCheckResult.accept.offset,
+           ctypes.sizeof(b.CtServerParams), ctypes.sizeof(b.CtRequest), ctypes.sizeof(b.CtCompletion),
+           ctypes.sizeof(b.CtServerCounts),
+           b.CtServerParams.mode.offset, b.CtRequest.layer.offset, b.CtRequest.arrival_us.offset,
+           b.CtCompletion.done_us.offset, b.CtCompletion.result.offset, b.CtServerCounts.arena_bytes.offset,
+           b.CtServerCounts.arena_used.offset]
     assert got == vals
 
 
@@ -90,6 +101,15 @@ def test_validation_before_device_calls(lib):
     assert lib.ct_mac_check(None, 1, None, None, 1, None) == b.CT_EINVAL
     assert lib.ct_gen_triple_tags(None, None, None, 1, 1) == b.CT_EINVAL
     assert lib.ct_last_error(None) == b"null context"
+    assert lib.ct_plan_create(None, 1, None, None, 1, None, None) == b.CT_EINVAL
+    assert lib.ct_plan_launch(None) == b.CT_EINVAL
+    assert lib.ct_plan_destroy(None) == b.CT_EINVAL
+    assert lib.ct_server_create(None, None, None) == b.CT_EINVAL
+    assert lib.ct_server_submit(None, None, 0) == b.CT_EINVAL
+    assert lib.ct_server_poll(None, None, 0, None) == b.CT_EINVAL
+    assert lib.ct_server_drain(None, 1.0) == b.CT_EINVAL
+    assert lib.ct_server_destroy(None) == b.CT_EINVAL
+    assert lib.ct_server_last_error(None) == b"null server"
 
 
 def test_product_path_has_no_oracle_dependency():
