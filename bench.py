@@ -2,16 +2,20 @@
 """Benchmark of the linear-layer hot path on one MI355X.
 
 A step is one pass of the whole hot path over one batch of layers: the online
-phase (ct_tag_linear: open E and U, output-share products, tags) and the
-verification (ct_mac_check_device: batch tag checks of E and U, check of D),
-for every layer of the workload in one call.  The dealer runs once before the
-timed region and is not timed.  Inputs are synthetic (uniform ring elements
-from the dealer's seeded generator) and resident in HBM.
+phase (open E and U, output-share products, tags) with the verification
+fused in (batch tag checks of E and U, check of D), for every layer of the
+workload, launched as one captured HIP graph (ct_plan_launch).  The dealer
+runs once before the timed region and is not timed.  Inputs are synthetic
+(uniform ring elements from the dealer's seeded generator) and resident in
+HBM.
 
 Prints one JSON line.  Default workload: the CNN layer set (four VGG-style 3x3
 convolutions as im2col products and the 25088 -> 4096 classifier layer at
-batch 1), CompactTag protocol, with the SPDZ2k protocol and per-layer
-launches measured beside it.
+batch 1), CompactTag protocol, with beside it: the same step as eager calls,
+the SPDZ2k protocol, one plain launch per layer, the check as a separate call,
+a per-kernel breakdown with the dominant kernel's roofline, a serving leg
+(open-loop Poisson arrivals of single-layer requests, p50/p99 latency) and
+the oracle on the host.  --config serving runs the full serving sweep.
 """
 from __future__ import annotations
 
@@ -36,11 +40,15 @@ DIGIT_PAIRS = 136            # int8 digit products per 128-bit ring multiply-acc
 def stage_work(stage: str, specs, mode: str):
     """Algorithmic work of one launch of a kernel stage over the layer batch:
     ("hbm", bytes) or ("mfma", int8 ops), for the fused step
-    (ct_tag_linear_check).  16 B per Z_2^128 element; per element:
+    (online phase + verification).  16 B per Z_2^128 element; per element:
       open_u     K x N: reads Y_p, B_p, tY_p, tB_p (8), writes U: 144 B
       row_pass   M x K: reads X_p, A_p, tX_p, tA_p (8), writes E: 144 B,
                  plus the folded operands written for matrix-core layers
                  (A_0 + E; SPDZ2k also tA_p + Delta_p E): 16 / 48 B
+      pack       matrix-core layers: reads each operand once and writes its
+                 digit tiles, 32 B per element: M x K: E, A_0 + E, [A]_1
+                 (SPDZ2k also the two folded tag operands): 96 / 160 B;
+                 K x N: [B]_0, [B]_1, U (SPDZ2k also [tB]_p): 96 / 160 B
       copy_base  M x N: 32 B per array (2 arrays, 4 in SPDZ2k), N > 8 layers
       ring_gemm  2 * 136 int8 ops per ring MAC; 4 M K N ring MACs per
                  layer (8 in SPDZ2k), layers with N > 8
@@ -57,6 +65,8 @@ def stage_work(stage: str, specs, mode: str):
             tot += 144 * kn
         elif stage == "row_pass":
             tot += 144 * mk + ((48 if spdz else 16) * mk if wide else 0)
+        elif stage == "pack":
+            tot += (160 if spdz else 96) * (mk + kn) if wide else 0
         elif stage == "copy_base":
             tot += (32 * mn * (4 if spdz else 2)) if wide else 0
         elif stage == "ring_gemm":
@@ -104,11 +114,15 @@ def pct(v, q):
     return v[i]
 
 
-def run_steps(ctx, mode_id, layer_groups, out_dev, steps, warmup, torch, timing=False, fused=True):
-    """Runs warmup + steps; each step enqueues every group (one call per group):
+def run_steps(ctx, mode_id, layer_groups, out_dev, steps, warmup, torch, timing=False, fused=True, plan=None):
+    """Runs warmup + steps; each step launches the captured plan (one HIP
+    graph launch) if given, else enqueues every group (one call per group):
     ct_tag_linear_check (fused) or ct_tag_linear + ct_mac_check_device.
     Returns (total seconds, per-step ms list, stage times)."""
     def step():
+        if plan is not None:
+            plan.launch()
+            return
         for g in layer_groups:
             if fused:
                 ctx.tag_linear_check(mode_id, g, out_dev)
@@ -290,7 +304,10 @@ def main():
         print("[bench] autotuning the matrix-core launch configuration ...", file=sys.stderr, flush=True)
         tuning = ctx.autotune(mode_id, layers)
     print(f"[bench] timed {args.mode}: {args.warmup} warmup + {args.steps} steps", file=sys.stderr, flush=True)
-    T, per, _ = run_steps(ctx, mode_id, [layers], out_dev, args.steps, args.warmup, torch)
+    # the timed step: one graph launch of the captured online phase + verification
+    plan = ctx.plan(mode_id, layers, out_dev)
+    T, per, _ = run_steps(ctx, mode_id, [layers], out_dev, args.steps, args.warmup, torch, plan=plan)
+    Te, pere, _ = run_steps(ctx, mode_id, [layers], out_dev, args.steps, args.warmup, torch)
     # per-kernel durations: a second pass with an event pair around every launch
     _, _, stages = run_steps(ctx, mode_id, [layers], out_dev, args.steps, 0, torch, timing=True)
     res = Context.decode_results(out_dev, len(layers))
@@ -340,6 +357,8 @@ def main():
                    "protocol": args.mode, "parties": 2, "ring": "values Z_2^64, shares and tags Z_2^128",
                    "layers_per_call": len(specs), "sum_MKN": mkn},
         "roofline": roofline,
+        "eager": {"value": round(mkn * args.steps / Te / 1e9, 3), "ms_per_step": round(Te / args.steps * 1e3, 4),
+                  "p50_ms": round(pct(pere, 50), 4), "p99_ms": round(pct(pere, 99), 4)},
         "stages": stage_rows,
         "tuning": tuning,
     }
@@ -351,7 +370,9 @@ def main():
             ctx.autotune(other, layers)
             for l in layers:
                 ctx.autotune(mode_id, [l])
-        T2, per2, _ = run_steps(ctx, other, [layers], out_dev, args.steps, args.warmup, torch)
+        plan2 = ctx.plan(other, layers, out_dev)
+        T2, per2, _ = run_steps(ctx, other, [layers], out_dev, args.steps, args.warmup, torch, plan=plan2)
+        plan2.close()
         out[oname] = {"value": round(mkn * args.steps / T2 / 1e9, 3), "ms_per_step": round(T2 / args.steps * 1e3, 4),
                       "p50_ms": round(pct(per2, 50), 4), "p99_ms": round(pct(per2, 99), 4)}
         T3, per3, _ = run_steps(ctx, mode_id, [[l] for l in layers], out_dev, args.steps, args.warmup, torch)
@@ -362,6 +383,8 @@ def main():
         out["separate_check"] = {"value": round(mkn * args.steps / T4 / 1e9, 3),
                                  "ms_per_step": round(T4 / args.steps * 1e3, 4),
                                  "p50_ms": round(pct(per4, 50), 4), "p99_ms": round(pct(per4, 99), 4)}
+    plan.close()
+    del plan
     if not args.no_serve:
         print(f"[bench] serving leg at {args.serve_rate:g} req/s ...", file=sys.stderr, flush=True)
         del layers

@@ -292,11 +292,14 @@ __device__ __forceinline__ void row_pass_body(const LayerDev &L, int flags, u128
     const uint64_t kce = L.key[K_CHI_E];
     const uint64_t d0 = L.delta[0], d1 = L.delta[1];
     u128 *AE0 = L.work, *tAE0 = L.work + M * K, *tAE1 = L.work + 2 * M * K;
-    const int64_t seg = row_seg(M, K), segs = (K + seg - 1) / seg, items = M * segs;
+    const int64_t seg = row_seg(M, K), items = M * ((K + seg - 1) / seg);
     const int64_t wave_id = (blockIdx.x * (int64_t)TPB + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * TPB) >> 6;
+    // segment-major order: the wavefronts in flight share one segment of k,
+    // so the K-long vectors they read (U^c, [tB^c]_p; U, [B]_p of skinny
+    // layers) stay in L2 while the M x K arrays stream through
     for (int64_t it = wave_id; it < items; it += nwaves) {
-        const int64_t m = it / segs, k0 = (it - m * segs) * seg;
+        const int64_t sg = it / M, m = it - sg * M, k0 = sg * seg;
         const int64_t k1 = k0 + seg < K ? k0 + seg : K;
         // compact: E U^c, E tB^c_0, E tB^c_1, tA_0 U^c, tA_1 U^c
         u128 cp[5] = {zero128(), zero128(), zero128(), zero128(), zero128()};
