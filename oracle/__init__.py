@@ -44,7 +44,7 @@ def build(force: bool = False) -> str:
 class _Desc(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int64), ("K", ctypes.c_int64), ("N", ctypes.c_int64),
                 ("seed", ctypes.c_uint64), ("layer_id", ctypes.c_uint64),
-                ("r0", ctypes.c_int64), ("r1", ctypes.c_int64)]
+                ("r0", ctypes.c_int64), ("r1", ctypes.c_int64), ("f", ctypes.c_int64), ("in_bits", ctypes.c_int64)]
 
 
 _P2 = ctypes.c_void_p * 2
@@ -54,6 +54,7 @@ _BUF_FIELDS = [
     ("C", 2), ("tC", 2), ("R", 2), ("tR", 2), ("Z", 2), ("tZ", 2), ("D", 1),
     ("Uc", 1), ("tBc", 2),
     ("Dc", 1), ("EUc", 1), ("tCc", 2), ("tRc", 2), ("tZc", 2), ("tDc", 2),
+    ("Rf", 2), ("tRf", 2), ("Zf", 2), ("tZf", 2),
 ]
 
 
@@ -163,6 +164,8 @@ class OracleLayer:
     key_seed: int
     r0: int = 0
     r1: int | None = None
+    f: int = 0
+    in_bits: int = 0
     arrays: dict = field(default_factory=dict)
     cs: np.ndarray | None = None        # [3 (E,U,D)][2 parties][2 limbs]
     tag_mults: np.ndarray | None = None
@@ -177,7 +180,7 @@ class OracleLayer:
             shapes[n] = (2, rows, K)
         for n in ("Y", "tY", "B", "tB"):
             shapes[n] = (2, K, N)
-        for n in ("C", "tC", "R", "tR", "Z", "tZ"):
+        for n in ("C", "tC", "R", "tR", "Z", "tZ", "Rf", "tRf", "Zf", "tZf"):
             shapes[n] = (2, rows, N)
         shapes.update(E=(rows, K), U=(K, N), D=(rows, N), Uc=(K,), tBc=(2, K), Dc=(rows,), EUc=(rows,),
                       tCc=(2, rows), tRc=(2, rows), tZc=(2, rows), tDc=(2, rows))
@@ -186,7 +189,8 @@ class OracleLayer:
         self.delta = key_shares(self.key_seed)
 
     def _desc(self):
-        return _Desc(self.M, self.K, self.N, self.seed & MASK64, self.layer_id & MASK64, self.r0, self.r1)
+        return _Desc(self.M, self.K, self.N, self.seed & MASK64, self.layer_id & MASK64, self.r0, self.r1,
+                     self.f, self.in_bits)
 
     def _bufs(self):
         b = _Bufs()
@@ -227,9 +231,10 @@ class OracleLayer:
 
 
 def run_layer(mode: int, M: int, K: int, N: int, seed: int, layer_id: int, key_seed: int,
-              r0: int = 0, r1: int | None = None) -> OracleLayer:
-    """Dealer, online phase and verification of one layer on rows [r0, r1)."""
-    L = OracleLayer(M, K, N, seed, layer_id, key_seed, r0, r1)
+              r0: int = 0, r1: int | None = None, f: int = 0, in_bits: int = 0) -> OracleLayer:
+    """Dealer, online phase and verification of one layer on rows [r0, r1)
+    (with f > 0 the product is truncated by f fractional bits)."""
+    L = OracleLayer(M, K, N, seed, layer_id, key_seed, r0, r1, f, in_bits)
     return L.deal().online(mode).check(mode)
 
 

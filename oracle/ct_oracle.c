@@ -163,12 +163,22 @@ static void auth_share(u128 lift, u128 dsum, uint64_t seed, uint64_t layer_id, i
     st(t1, at, tag - ts0);
 }
 
-enum { OBJ_X = 1, OBJ_Y = 2, OBJ_A = 3, OBJ_B = 4, OBJ_C = 5, OBJ_R = 6 };
+enum { OBJ_X = 1, OBJ_Y = 2, OBJ_A = 3, OBJ_B = 4, OBJ_C = 5, OBJ_R = 6, OBJ_RF = 7 };
+
+/* An input value of Z_{2^k}: a uniform draw, or with in_bits in 1..63 a signed
+ * in_bits-bit integer (the draw's top bits, sign-extended) in two's complement
+ * -- a stand-in for fixed-point encodings.  Lifted with zero upper bits. */
+static u128 input_lift(uint64_t draw, int64_t in_bits) {
+    if (in_bits <= 0 || in_bits >= 64) return (u128)draw;
+    return (u128)(uint64_t)((int64_t)draw >> (64 - in_bits));
+}
 
 /* Preprocessing of Fig. 7 (Beaver matrix triple A, B, C = A*B and the mask R),
  * plus, when with_inputs is set, authenticated shares of the inputs X and Y.
  * Inputs are values of Z_{2^k} lifted with zero upper bits; A, B, R are
- * uniform in Z_{2^{k+s}}; C~ = A~ * B~ mod 2^{k+s}. */
+ * uniform in Z_{2^{k+s}}; C~ = A~ * B~ mod 2^{k+s}.  With f > 0 also the
+ * truncated mask of Figs. 3 and 6, R^f = (R mod 2^k) / 2^f (an integer below
+ * 2^{k-f}), lifted with a uniform upper limb and authenticated like the rest. */
 void or_deal(const or_desc *d, const uint64_t delta[2], int with_inputs, or_bufs *b) {
     const int64_t M = d->M, K = d->K, N = d->N, r0 = d->r0, rows = d->r1 - d->r0;
     const uint64_t seed = d->seed, lid = d->layer_id;
@@ -187,14 +197,14 @@ void or_deal(const or_desc *d, const uint64_t delta[2], int with_inputs, or_bufs
             int64_t at = i * K + k;
             uint64_t e = (uint64_t)((r0 + i) * K + k);
             if (with_inputs) {
-                u128 x = (u128)or_draw(seed, stream_of(lid, OR_P_LIFT_X), e);
+                u128 x = input_lift(or_draw(seed, stream_of(lid, OR_P_LIFT_X), e), d->in_bits);
                 auth_share(x, dsum, seed, lid, OBJ_X, e, b->X[0], b->X[1], b->tX[0], b->tX[1], at);
             }
             auth_share(ld(At, at), dsum, seed, lid, OBJ_A, e, b->A[0], b->A[1], b->tA[0], b->tA[1], at);
         }
     for (int64_t e = 0; e < K * N; e++) {
         if (with_inputs) {
-            u128 y = (u128)or_draw(seed, stream_of(lid, OR_P_LIFT_Y), (uint64_t)e);
+            u128 y = input_lift(or_draw(seed, stream_of(lid, OR_P_LIFT_Y), (uint64_t)e), d->in_bits);
             auth_share(y, dsum, seed, lid, OBJ_Y, (uint64_t)e, b->Y[0], b->Y[1], b->tY[0], b->tY[1], e);
         }
         auth_share(ld(Bt, e), dsum, seed, lid, OBJ_B, (uint64_t)e, b->B[0], b->B[1], b->tB[0], b->tB[1], e);
@@ -206,6 +216,11 @@ void or_deal(const or_desc *d, const uint64_t delta[2], int with_inputs, or_bufs
             u128 r = draw128(seed, stream_of(lid, OR_P_LIFT_R), e);
             auth_share(ld(Ct, at), dsum, seed, lid, OBJ_C, e, b->C[0], b->C[1], b->tC[0], b->tC[1], at);
             auth_share(r, dsum, seed, lid, OBJ_R, e, b->R[0], b->R[1], b->tR[0], b->tR[1], at);
+            if (d->f > 0) {
+                u128 rf = (u128)((uint64_t)r >> d->f) |
+                          ((u128)or_draw(seed, stream_of(lid, OR_P_LIFT_RF), e) << 64);
+                auth_share(rf, dsum, seed, lid, OBJ_RF, e, b->Rf[0], b->Rf[1], b->tRf[0], b->tRf[1], at);
+            }
         }
     free(At);
     free(Bt);
@@ -258,6 +273,22 @@ void or_online(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) 
     /* Open D = R - Z (Pi_OptMAC step 2 in COMPACT mode; Pi_Truncation step 1 in
      * SPDZ2k mode), kept as the full lift D~ mod 2^{k+s}. */
     open_diff(rows * N, b->R, b->Z, b->D);
+
+    /* f > 0: truncation by the opened D (OptMAC&Trunc, Fig. 6, ExpandTrunc
+     * steps 2-4, in CompactTag mode; Pi_Truncation, Fig. 3 online step 2, after
+     * Pi_MatMul in SPDZ2k mode -- the same formulas).  D is reduced mod 2^k and
+     * divided by 2^f as an integer in [0, 2^k):
+     *   [Z^f]_p = [R^f]_p - D/2^f  (the public term by party 0 only),
+     *   [tZ^f]_p = [tR^f]_p - [Delta]_p * D/2^f. */
+    if (d->f > 0) {
+        for (int64_t e = 0; e < rows * N; e++) {
+            const uint64_t df = (uint64_t)ld(b->D, e) >> d->f;
+            for (int p = 0; p < 2; p++) {
+                st(b->Zf[p], e, ld(b->Rf[p], e) - (p == 0 ? (u128)df : (u128)0));
+                st(b->tZf[p], e, ld(b->tRf[p], e) - (u128)delta[p] * df);
+            }
+        }
+    }
 
     if (mode == OR_MODE_SPDZ2K) {
         /* Eq. (3): [tZ]_p = [tC]_p + E*[tB]_p + [tA]_p*U + [Delta]_p * (E*U);

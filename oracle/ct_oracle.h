@@ -24,8 +24,9 @@
 #define OR_P_LIFT_A 0x03
 #define OR_P_LIFT_B 0x04
 #define OR_P_LIFT_R 0x05
-#define OR_P_VSH 0x10 /* + object index 1..6 (X, Y, A, B, C, R) */
-#define OR_P_TSH 0x20 /* + object index 1..6 */
+#define OR_P_LIFT_RF 0x06 /* upper limb of the lift of the truncated mask R^f */
+#define OR_P_VSH 0x10 /* + object index 1..7 (X, Y, A, B, C, R, R^f) */
+#define OR_P_TSH 0x20 /* + object index 1..7 */
 #define OR_P_CHI 0x30
 #define OR_P_CHIHAT 0x31
 #define OR_P_CHI_E 0x32
@@ -38,6 +39,8 @@ typedef struct {
     int64_t M, K, N;          /* X is M x K, Y is K x N, Z is M x N */
     uint64_t seed, layer_id;  /* per-layer randomness */
     int64_t r0, r1;           /* rows of the M dimension that are computed */
+    int64_t f;                /* fractional bits truncated from the product (0: no truncation) */
+    int64_t in_bits;          /* 0: inputs uniform in Z_{2^k}; 1..63: signed in_bits-bit inputs */
 } or_desc;
 
 /* Every pointer is a caller-owned array of (lo, hi) uint64 pairs. */
@@ -52,6 +55,8 @@ typedef struct {
     uint64_t *Uc, *tBc[2];
     /* compact-tag vectors: rows entries */
     uint64_t *Dc, *EUc, *tCc[2], *tRc[2], *tZc[2], *tDc[2];
+    /* f > 0, rows x N: truncated mask R^f (dealt) and truncated output Z^f */
+    uint64_t *Rf[2], *tRf[2], *Zf[2], *tZf[2];
     /* check-value shares cs[W][party][limb], W in (E, U, D) */
     uint64_t cs[3][2][2];
     /* local multiplications spent on tags, per party */

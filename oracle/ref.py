@@ -33,9 +33,10 @@ def mat(M, K, N, P, Q):
     return [[sum(P[i][k] * Q[k][j] for k in range(K)) % R128 for j in range(N)] for i in range(M)]
 
 
-def online_and_check(compact: bool, M, K, N, seed, layer_id, delta, S):
+def online_and_check(compact: bool, M, K, N, seed, layer_id, delta, S, f: int = 0):
     """S: dict name -> per-party lists of Python-int matrices (X, tX, A, tA, Y, tY,
-    B, tB, C, tC, R, tR), each S[name][p][i][j].  Returns a dict of outputs."""
+    B, tB, C, tC, R, tR, and Rf, tRf when f > 0), each S[name][p][i][j].
+    Returns a dict of outputs."""
     out = {}
     E = [[(S["X"][0][i][k] - S["A"][0][i][k] + S["X"][1][i][k] - S["A"][1][i][k]) % R128
           for k in range(K)] for i in range(M)]
@@ -50,6 +51,13 @@ def online_and_check(compact: bool, M, K, N, seed, layer_id, delta, S):
                    for j in range(N)] for i in range(M)])
     D = [[(S["R"][0][i][j] - Z[0][i][j] + S["R"][1][i][j] - Z[1][i][j]) % R128 for j in range(N)]
          for i in range(M)]
+    if f > 0:
+        # truncation by the opened D: its value mod 2^64, shifted right by f
+        Df = [[(D[i][j] & MASK64) >> f for j in range(N)] for i in range(M)]
+        out["Zf"] = [[[(S["Rf"][p][i][j] - (Df[i][j] if p == 0 else 0)) % R128 for j in range(N)]
+                      for i in range(M)] for p in range(2)]
+        out["tZf"] = [[[(S["tRf"][p][i][j] - delta[p] * Df[i][j]) % R128 for j in range(N)]
+                       for i in range(M)] for p in range(2)]
     tZ = []
     if not compact:
         for p in range(2):

@@ -346,3 +346,89 @@ def test_paper_384x_example():
     ratio = O.spdz2k_tag_mults(T1, T2, T3) / O.compact_tag_mults(T1, T2, T3)
     assert round(ratio) == int(kv["printed_ratio"])
     assert abs(ratio - 384.08) < 0.01
+
+
+# ---------------------------------------------------------------- truncation (f > 0)
+
+def signed64(v):
+    v = int(v) % (1 << 64)
+    return v - (1 << 64) if v >= 1 << 63 else v
+
+
+@pytest.mark.parametrize("f", [1, 13, 40, 63])
+def test_truncation_dealer_mask(built, f):
+    """The dealt R^f is (R mod 2^k) / 2^f as an integer, authenticated (Eq. (1))."""
+    L = O.OracleLayer(5, 3, 7, 77, 4, 9, f=f).deal()
+    R_k = lift(L, "R") % (1 << 64)
+    Rf = lift(L, "Rf")
+    assert np.array_equal((Rf % (1 << 64)).astype(object), (R_k // (1 << f)).astype(object))
+    assert np.array_equal(lift(L, "tRf"), (dsum(L) * Rf) % R)
+    # the upper limb of the lift is a fresh uniform draw (not a copy of R's)
+    assert any(int(v) >> 64 != int(w) >> 64 for v, w in zip(Rf.ravel(), lift(L, "R").ravel()))
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_truncation_tag_relation_and_modes(built, shape):
+    """Both protocols output the same truncated shares and tags (Figs. 3 and 6
+    use the same formulas), whose tags satisfy Eq. (1) with Delta~."""
+    M, K, N = shape
+    outs = {}
+    for mode in (O.MODE_SPDZ2K, O.MODE_COMPACT):
+        L = O.run_layer(mode, M, K, N, seed=91, layer_id=3, key_seed=5, f=17, in_bits=20)
+        assert L.accept()
+        assert np.array_equal(lift(L, "tZf"), (dsum(L) * lift(L, "Zf")) % R)
+        outs[mode] = L
+    for n in ("Zf", "tZf"):
+        for p in range(2):
+            assert np.array_equal(outs[0][n][p], outs[1][n][p]), (n, p)
+
+
+@pytest.mark.parametrize("f", [8, 13, 24])
+def test_truncation_accuracy(built, f):
+    """With signed 16-bit inputs the product z = X Y is small, and the
+    truncated output reconstructs to floor(z / 2^f) or one more, mod 2^64,
+    for every element where R mod 2^64 - z does not leave [0, 2^64) -- the
+    correctness condition of truncation by a random mask (Sec. 3.4.2)."""
+    M, K, N = 24, 40, 9
+    for seed in (3, 4):
+        L = O.run_layer(O.MODE_COMPACT, M, K, N, seed=seed, layer_id=12, key_seed=2, f=f, in_bits=16)
+        X = [[signed64(v) for v in row] for row in lift(L, "X").tolist()]
+        Y = [[signed64(v) for v in row] for row in lift(L, "Y").tolist()]
+        assert max(abs(v) for row in X for v in row) < 1 << 15
+        R_k = lift(L, "R") % (1 << 64)
+        Zf = lift(L, "Zf") % (1 << 64)
+        wraps = 0
+        for i in range(M):
+            for j in range(N):
+                z = sum(X[i][k] * Y[k][j] for k in range(K))
+                if not 0 <= int(R_k[i, j]) - z < 1 << 64:
+                    wraps += 1
+                    continue
+                err = (int(Zf[i, j]) - (z >> f)) % (1 << 64)
+                assert err in (0, 1), (i, j, err)
+        assert wraps <= 1
+
+
+def test_truncation_mask_is_not_covered_by_the_layer_check(built):
+    """A flipped bit in a share of R^f leaves this layer's check accepting (the
+    truncated mask is only consumed by the outputs) but breaks the tag
+    relation of the output, which the next check that opens it catches."""
+    L = O.OracleLayer(4, 6, 5, 19, 2, 3, f=9).deal()
+    L["Rf"][1][2, 3, 0] ^= np.uint64(1 << 7)
+    L.online(O.MODE_COMPACT).check(O.MODE_COMPACT)
+    assert L.accept()
+    assert not np.array_equal(lift(L, "tZf"), (dsum(L) * lift(L, "Zf")) % R)
+
+
+@pytest.mark.parametrize("compact", [False, True])
+def test_truncation_bruteforce(built, compact):
+    M, K, N = 3, 4, 5
+    mode = O.MODE_COMPACT if compact else O.MODE_SPDZ2K
+    L = O.run_layer(mode, M, K, N, seed=44, layer_id=6, key_seed=8, f=11)
+    names = ("X", "tX", "A", "tA", "Y", "tY", "B", "tB", "C", "tC", "R", "tR", "Rf", "tRf")
+    S = {n: [ints(L[n][p]).reshape(L[n][p].shape[:-1]).tolist() for p in range(2)] for n in names}
+    delta = [int(L.delta[0]), int(L.delta[1])]
+    out = ref.online_and_check(compact, M, K, N, 44, 6, delta, S, f=11)
+    for p in range(2):
+        assert ints(L["Zf"][p]).reshape(M, N).tolist() == out["Zf"][p]
+        assert ints(L["tZf"][p]).reshape(M, N).tolist() == out["tZf"][p]
