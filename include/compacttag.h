@@ -22,7 +22,8 @@
  *     single-stream and not thread-safe; several contexts may coexist.
  *   - Errors are returned as ct_status; nothing is thrown across the ABI.
  *     CT_EINVAL: a null or misaligned pointer, M, K or N < 1, k or s not 64,
- *     f != 0, n < 1 or more layers than the context was sized for.
+ *     f or in_bits outside [0, 63], n < 1 or more layers than the context
+ *     was sized for.
  *     CT_EDEVICE: a HIP error (text in ct_last_error).  CT_ABORT is not a
  *     library error: it is the protocol's abort when a MAC check fails.
  */
@@ -60,8 +61,15 @@ typedef struct {
 
 typedef struct {
     int64_t M, K, N;      /* X: M x K, Y: K x N */
-    int32_t f;            /* fractional bits truncated after the product; must be 0 */
-    int32_t reserved;
+    int32_t f;            /* fractional bits truncated after the product, 0..63.  f > 0:
+                             truncation by the opened D (OptMAC&Trunc, Fig. 6, in
+                             CT_MODE_COMPACT; Pi_Truncation, Fig. 3, in CT_MODE_SPDZ2K):
+                             [Z^f]_p = [R^f]_p - (D mod 2^k) / 2^f (party 0 subtracts the
+                             public term), [tZ^f]_p = [tR^f]_p - [Delta]_p (D mod 2^k) / 2^f,
+                             written to Zf, tZf; the dealer adds the truncated mask
+                             R^f = (R mod 2^k) / 2^f (Rf, tRf).  Z, tZ, D are still written. */
+    int32_t in_bits;      /* dealer inputs: 0 = uniform in Z_{2^64}; 1..63 = signed in_bits-bit
+                             integers in two's complement (a stand-in for fixed-point data) */
     uint64_t seed;        /* per-layer seed of the dealer and of the public combiners */
     uint64_t layer_id;    /* < 2^48; names the layer's generator streams */
 } ct_layer_desc;
@@ -77,6 +85,8 @@ typedef struct {
                             written by ct_tag_linear in CT_MODE_COMPACT, unused otherwise */
     ct_u128 *work;       /* caller-owned workspace of CT_WORK_LEN(M, K, N) elements (NULL allowed
                             when that is 0); contents are undefined after a call */
+    ct_u128 *Rf[2], *tRf[2];  /* M x N, f > 0 only: truncated mask (written by the dealer) */
+    ct_u128 *Zf[2], *tZf[2];  /* M x N, f > 0 only: truncated output shares and tags */
 } ct_layer_bufs;
 
 /* Layers with N <= CT_SKINNY_N form their output products in the pass that
@@ -119,20 +129,24 @@ ct_status ct_key_shares(const ct_ctx *ctx, uint64_t out[2]);
 /* Dealer (preprocessing of Fig. 7 and F_MAC Auth, Appendix A), for n layers:
  * Beaver matrix triple A (M x K), B (K x N), C = A*B mod 2^128 (M x N) and the
  * mask R (M x N), all uniform in Z_{2^128}, and, if with_inputs != 0, inputs
- * X (M x K) and Y (K x N) uniform in Z_{2^64} (upper limb zero).  Every object
+ * X (M x K) and Y (K x N) uniform in Z_{2^64} (or signed in_bits-bit values;
+ * upper limb zero).  For f > 0 also the truncated mask of Figs. 3 and 6,
+ * R^f = (R mod 2^64) / 2^f, its upper limb a fresh uniform draw.  Every object
  * is authenticated: [v]_0 and [tv]_0 are fresh draws, [v]_1 = v~ - [v]_0 and
  * [tv]_1 = Delta~ * v~ - [tv]_0 with Delta~ = [Delta]_0 + [Delta]_1 taken as an
  * integer.  Writes X, tX, Y, tY (if with_inputs), A, tA, B, tB, C, tC, R, tR
- * of both parties.  Asynchronous. */
+ * (and Rf, tRf) of both parties.  Asynchronous. */
 ct_status ct_gen_triple_tags(ct_ctx *ctx, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
                              int with_inputs);
 
-/* Online phase of n linear layers (Fig. 7 online steps 1-7 at f = 0 for
+/* Online phase of n linear layers (Fig. 7 online steps 1-7 for
  * CT_MODE_COMPACT; Fig. 2 with Eqs. (2)-(3) plus the opening of D for
  * CT_MODE_SPDZ2K).  Reads X, tX, A, tA, Y, tY, B, tB, C, tC, R, tR; writes
  * E, U, D, Z, tZ (and cvec in CT_MODE_COMPACT).  Party 0 adds the public term
  * E*U to its value share; every party adds its key share times a public term
- * to its tag share.  Asynchronous; allocates nothing. */
+ * to its tag share.  Layers with f > 0 also read Rf, tRf and write the
+ * truncated output Zf, tZf (see ct_layer_desc.f).  Asynchronous; allocates
+ * nothing. */
 ct_status ct_tag_linear(ct_ctx *ctx, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n);
 
 /* Verification of n layers, results left in device memory: writes n
@@ -273,7 +287,7 @@ typedef struct {
     int64_t id;           /* the caller's request id (unique per server) */
     int32_t kind;         /* ct_req_kind */
     int32_t reserved;
-    ct_layer_desc layer;  /* TAG: the layer (f = 0); CHECK: only M, K, N are used */
+    ct_layer_desc layer;  /* TAG: the layer (f must be 0); CHECK: only M, K, N are used */
     double arrival_us;    /* scheduled arrival on the server clock (ct_server_now_us); the request is
                              not admitted earlier, and its latency counts from this time */
 } ct_request;

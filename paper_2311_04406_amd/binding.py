@@ -43,16 +43,18 @@ class CtParams(ctypes.Structure):
 
 class CtLayerDesc(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int64), ("K", ctypes.c_int64), ("N", ctypes.c_int64), ("f", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64), ("layer_id", ctypes.c_uint64)]
+                ("in_bits", ctypes.c_int32), ("seed", ctypes.c_uint64), ("layer_id", ctypes.c_uint64)]
 
 
 _P2 = ctypes.c_void_p * 2
 BUF_PAIRS = ["X", "tX", "A", "tA", "Y", "tY", "B", "tB", "C", "tC", "R", "tR", "Z", "tZ"]
 BUF_SINGLE = ["E", "U", "D", "cvec", "work"]
+BUF_TRUNC = ["Rf", "tRf", "Zf", "tZf"]  # f > 0 only
 
 
 class CtLayerBufs(ctypes.Structure):
-    _fields_ = [(n, _P2) for n in BUF_PAIRS] + [(n, ctypes.c_void_p) for n in BUF_SINGLE]
+    _fields_ = [(n, _P2) for n in BUF_PAIRS] + [(n, ctypes.c_void_p) for n in BUF_SINGLE] + \
+               [(n, _P2) for n in BUF_TRUNC]
 
 
 class CtStageTime(ctypes.Structure):
@@ -173,12 +175,14 @@ def _result(r: CtCheckResult) -> CheckResult:
 class Layer:
     """Device buffers of one linear layer (both parties), as torch tensors."""
 
-    def __init__(self, M: int, K: int, N: int, seed: int, layer_id: int, device="cuda:0", f: int = 0):
+    def __init__(self, M: int, K: int, N: int, seed: int, layer_id: int, device="cuda:0", f: int = 0,
+                 in_bits: int = 0):
         self.M, self.K, self.N, self.seed, self.layer_id, self.f = M, K, N, seed, layer_id, f
+        self.in_bits = in_bits
         self.t = {}
         dims = {"MK": (M, K), "KN": (K, N), "MN": (M, N)}
         groups = {"MK": ["X", "tX", "A", "tA"], "KN": ["Y", "tY", "B", "tB"],
-                  "MN": ["C", "tC", "R", "tR", "Z", "tZ"]}
+                  "MN": ["C", "tC", "R", "tR", "Z", "tZ"] + (BUF_TRUNC if f > 0 else [])}
         for g, names in groups.items():
             for n in names:
                 self.t[n] = [torch.zeros(dims[g] + (2,), dtype=torch.int64, device=device) for _ in range(2)]
@@ -193,6 +197,7 @@ class Layer:
         """A Layer over existing device tensors (no allocation)."""
         obj = cls.__new__(cls)
         obj.M, obj.K, obj.N, obj.seed, obj.layer_id, obj.f = M, K, N, seed, layer_id, 0
+        obj.in_bits = 0
         obj.t = dict(tensors)
         return obj
 
@@ -204,7 +209,7 @@ class Layer:
         return self.t[name]
 
     def desc(self) -> CtLayerDesc:
-        return CtLayerDesc(self.M, self.K, self.N, self.f, 0, self.seed & MASK64, self.layer_id & MASK64)
+        return CtLayerDesc(self.M, self.K, self.N, self.f, self.in_bits, self.seed & MASK64, self.layer_id & MASK64)
 
     def bufs(self) -> CtLayerBufs:
         b = CtLayerBufs()
@@ -212,6 +217,9 @@ class Layer:
             setattr(b, n, _P2(self.t[n][0].data_ptr(), self.t[n][1].data_ptr()))
         for n in BUF_SINGLE:
             setattr(b, n, self.t[n].data_ptr())
+        for n in BUF_TRUNC:
+            if n in self.t:
+                setattr(b, n, _P2(self.t[n][0].data_ptr(), self.t[n][1].data_ptr()))
         return b
 
     # cvec views (element offsets of compacttag.h)

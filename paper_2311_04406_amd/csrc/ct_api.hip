@@ -108,7 +108,8 @@ ct_status validate(ct_ctx *c, int max_layers, const ct_layer_desc *L, const ct_l
         if (d.M < 1 || d.K < 1 || d.N < 1) return fail(c, CT_EINVAL, at + "M, K, N must be >= 1");
         if (d.M >= (1LL << 31) || d.K >= (1LL << 31) || d.N >= (1LL << 31))
             return fail(c, CT_EINVAL, at + "M, K, N must be < 2^31");
-        if (d.f != 0) return fail(c, CT_EINVAL, at + "f must be 0 (truncation is not on this path)");
+        if (d.f < 0 || d.f > 63) return fail(c, CT_EINVAL, at + "f must be in [0, 63]");
+        if (d.in_bits < 0 || d.in_bits > 63) return fail(c, CT_EINVAL, at + "in_bits must be in [0, 63]");
         if (d.layer_id >= (1ULL << 48)) return fail(c, CT_EINVAL, at + "layer_id must be < 2^48");
         const ct_layer_bufs &b = B[l];
         auto chk = [&](const ct_u128 *p, const char *name) -> bool {
@@ -128,6 +129,10 @@ ct_status validate(ct_ctx *c, int max_layers, const ct_layer_desc *L, const ct_l
                     return CT_EINVAL;
             if (need & NEED_OUT)
                 if (!chk(b.Z[p], "Z") || !chk(b.tZ[p], "tZ")) return CT_EINVAL;
+            if (d.f > 0 && (need & NEED_TRIPLE))
+                if (!chk(b.Rf[p], "Rf") || !chk(b.tRf[p], "tRf")) return CT_EINVAL;
+            if (d.f > 0 && (need & NEED_OUT))
+                if (!chk(b.Zf[p], "Zf") || !chk(b.tZf[p], "tZf")) return CT_EINVAL;
         }
         if (need & NEED_OUT)
             if (!chk(b.E, "E") || !chk(b.U, "U") || !chk(b.D, "D")) return CT_EINVAL;
@@ -155,7 +160,8 @@ void fill_layer(const ct_ctx *c, u128 *acc, const ct_layer_desc &d, const ct_lay
     o.key[K_LIFT_A] = hkey(s, id, P_LIFT_A);
     o.key[K_LIFT_B] = hkey(s, id, P_LIFT_B);
     o.key[K_LIFT_R] = hkey(s, id, P_LIFT_R);
-    for (int obj = 1; obj <= 6; obj++) {
+    o.key[K_LIFT_RF] = hkey(s, id, P_LIFT_RF);
+    for (int obj = 1; obj <= NUM_OBJ; obj++) {
         o.key[K_VSH_X + obj - 1] = hkey(s, id, P_VSH + obj);
         o.key[K_TSH_X + obj - 1] = hkey(s, id, P_TSH + obj);
     }
@@ -172,6 +178,9 @@ void fill_layer(const ct_ctx *c, u128 *acc, const ct_layer_desc &d, const ct_lay
     cp(o.Y, b.Y); cp(o.tY, b.tY); cp(o.B, b.B); cp(o.tB, b.tB);
     cp(o.C, b.C); cp(o.tC, b.tC); cp(o.R, b.R); cp(o.tR, b.tR);
     cp(o.Z, b.Z); cp(o.tZ, b.tZ);
+    cp(o.Rf, b.Rf); cp(o.tRf, b.tRf); cp(o.Zf, b.Zf); cp(o.tZf, b.tZf);
+    o.f = d.f;
+    o.in_bits = d.in_bits;
     o.E = reinterpret_cast<u128 *>(b.E);
     o.U = reinterpret_cast<u128 *>(b.U);
     o.D = reinterpret_cast<u128 *>(b.D);
@@ -479,7 +488,7 @@ ct_status ct::run_deal(ct_ctx *c, Lane &ln, const ct_layer_desc *L, const ct_lay
         LAUNCH(c, ln, ST_DEAL_SKINNY, launch_skinny(ln.skinny_dev, nskinny, max_rows, ln.stream));
     }
     const int mask = (with_inputs ? ((1 << OBJ_X) | (1 << OBJ_Y)) : 0) | (1 << OBJ_A) | (1 << OBJ_B) |
-                     (1 << OBJ_C) | (1 << OBJ_R);
+                     (1 << OBJ_C) | (1 << OBJ_R) | (1 << OBJ_RF);
     LAUNCH(c, ln, ST_DEAL_AUTH, launch_deal_auth(ln.layers_dev, n, mask, std::max({sz.mk, sz.kn, sz.mn}), ln.stream));
     return CT_OK;
 }

@@ -17,19 +17,21 @@ struct u128 {
 // Generator stream purposes; stream = (layer_id << 16) | purpose.
 enum Purpose : uint32_t {
     P_LIFT_X = 0x01, P_LIFT_Y = 0x02, P_LIFT_A = 0x03, P_LIFT_B = 0x04, P_LIFT_R = 0x05,
-    P_VSH = 0x10,  // + object 1..6
-    P_TSH = 0x20,  // + object 1..6
+    P_LIFT_RF = 0x06,  // upper limb of the lift of the truncated mask R^f
+    P_VSH = 0x10,  // + object 1..7
+    P_TSH = 0x20,  // + object 1..7
     P_CHI = 0x30, P_CHIHAT = 0x31, P_CHI_E = 0x32, P_CHI_U = 0x33, P_CHI_D = 0x34,
     P_KEY = 0x40,  // + party, on the global layer id 0xFFFF
 };
-enum Obj : int { OBJ_X = 1, OBJ_Y = 2, OBJ_A = 3, OBJ_B = 4, OBJ_C = 5, OBJ_R = 6 };
+enum Obj : int { OBJ_X = 1, OBJ_Y = 2, OBJ_A = 3, OBJ_B = 4, OBJ_C = 5, OBJ_R = 6, OBJ_RF = 7 };
+constexpr int NUM_OBJ = 7;
 constexpr uint64_t GLOBAL_LAYER = 0xFFFF;
 
 // Index of each generator key in LayerDev::key.
 enum KeyIdx : int {
-    K_LIFT_X = 0, K_LIFT_Y, K_LIFT_A, K_LIFT_B, K_LIFT_R,
-    K_VSH_X, K_VSH_Y, K_VSH_A, K_VSH_B, K_VSH_C, K_VSH_R,
-    K_TSH_X, K_TSH_Y, K_TSH_A, K_TSH_B, K_TSH_C, K_TSH_R,
+    K_LIFT_X = 0, K_LIFT_Y, K_LIFT_A, K_LIFT_B, K_LIFT_R, K_LIFT_RF,
+    K_VSH_X, K_VSH_Y, K_VSH_A, K_VSH_B, K_VSH_C, K_VSH_R, K_VSH_RF,
+    K_TSH_X, K_TSH_Y, K_TSH_A, K_TSH_B, K_TSH_C, K_TSH_R, K_TSH_RF,
     K_CHI, K_CHIHAT, K_CHI_E, K_CHI_U, K_CHI_D,
     K_COUNT
 };
@@ -45,6 +47,8 @@ struct LayerDev {
     u128 *E, *U, *D, *cvec;
     u128 *work;                 // caller workspace: A_0 + E | tA_0 + Delta_0 E | tA_1 + Delta_1 E (M x K each)
     u128 *acc;                  // check accumulators, ACC_PER_LAYER entries (context scratch)
+    u128 *Rf[2], *tRf[2], *Zf[2], *tZf[2];  // f > 0: truncated mask and output (M x N)
+    int32_t f, in_bits;         // truncated fractional bits; dealer input width (0: uniform)
 };
 
 // Layers with N <= SKINNY_MAX_N take their output products on the VALU inside

@@ -138,11 +138,20 @@ hipError_t launch_deal_lift(const LayerDev *L, int n, int64_t max_elems, hipStre
     return hipGetLastError();
 }
 
-// y = layer * 6 + (object - 1); objects outside obj_mask are skipped.
+// An input value of Z_{2^64}: the draw itself, or with in_bits in 1..63 a
+// signed in_bits-bit integer (the draw's top bits, sign-extended) in two's
+// complement.  Lifted with a zero upper limb.
+__device__ __forceinline__ u128 input_lift(uint64_t draw, int in_bits) {
+    if (in_bits <= 0 || in_bits >= 64) return u128{draw, 0};
+    return u128{(uint64_t)((int64_t)draw >> (64 - in_bits)), 0};
+}
+
+// y = layer * NUM_OBJ + (object - 1); objects outside obj_mask, and R^f of
+// layers with f = 0, are skipped.
 __global__ void k_deal_auth(const LayerDev *__restrict__ Ls, int obj_mask) {
-    const LayerDev &L = Ls[blockIdx.y / 6];
-    const int obj = blockIdx.y % 6 + 1;
-    if (!((obj_mask >> obj) & 1)) return;
+    const LayerDev &L = Ls[blockIdx.y / NUM_OBJ];
+    const int obj = blockIdx.y % NUM_OBJ + 1;
+    if (!((obj_mask >> obj) & 1) || (obj == OBJ_RF && L.f == 0)) return;
     int64_t n;
     u128 *const *v;
     u128 *const *t;
@@ -152,16 +161,19 @@ __global__ void k_deal_auth(const LayerDev *__restrict__ Ls, int obj_mask) {
         case OBJ_A: n = L.M * L.K; v = L.A; t = L.tA; break;
         case OBJ_B: n = L.K * L.N; v = L.B; t = L.tB; break;
         case OBJ_C: n = L.M * L.N; v = L.C; t = L.tC; break;
-        default: n = L.M * L.N; v = L.R; t = L.tR; break;
+        case OBJ_R: n = L.M * L.N; v = L.R; t = L.tR; break;
+        default: n = L.M * L.N; v = L.Rf; t = L.tRf; break;
     }
     u128 *v0 = v[0], *v1 = v[1], *t0 = t[0], *t1 = t[1];
     const uint64_t kv = L.key[K_VSH_X + obj - 1], kt = L.key[K_TSH_X + obj - 1];
     const u128 dsum = key_sum(L);
     for (int64_t e = blockIdx.x * (int64_t)TPB + threadIdx.x; e < n; e += (int64_t)gridDim.x * TPB) {
         u128 lift;
-        if (obj == OBJ_X) lift = u128{sdraw(L.key[K_LIFT_X], (uint64_t)e), 0};
-        else if (obj == OBJ_Y) lift = u128{sdraw(L.key[K_LIFT_Y], (uint64_t)e), 0};
+        if (obj == OBJ_X) lift = input_lift(sdraw(L.key[K_LIFT_X], (uint64_t)e), L.in_bits);
+        else if (obj == OBJ_Y) lift = input_lift(sdraw(L.key[K_LIFT_Y], (uint64_t)e), L.in_bits);
         else if (obj == OBJ_R) lift = sdraw128(L.key[K_LIFT_R], (uint64_t)e);
+        else if (obj == OBJ_RF)  // R^f = (R mod 2^64) / 2^f, upper limb a fresh draw (Figs. 3 and 6)
+            lift = u128{sdraw128(L.key[K_LIFT_R], (uint64_t)e).lo >> L.f, sdraw(L.key[K_LIFT_RF], (uint64_t)e)};
         else lift = ld(v1, e);  // A~, B~ or C~ left in party 1's buffer
         const u128 s0 = sdraw128(kv, (uint64_t)e);
         const u128 ts0 = sdraw128(kt, (uint64_t)e);
@@ -174,7 +186,7 @@ __global__ void k_deal_auth(const LayerDev *__restrict__ Ls, int obj_mask) {
 }
 
 hipError_t launch_deal_auth(const LayerDev *L, int n, int obj_mask, int64_t max_elems, hipStream_t st) {
-    hipLaunchKernelGGL(k_deal_auth, dim3(grid_for(max_elems), 6 * n), dim3(TPB), 0, st, L, obj_mask);
+    hipLaunchKernelGGL(k_deal_auth, dim3(grid_for(max_elems), NUM_OBJ * n), dim3(TPB), 0, st, L, obj_mask);
     return hipGetLastError();
 }
 
@@ -427,6 +439,18 @@ hipError_t launch_row_pass(const LayerDev *L, int n, int flags, int64_t max_item
 // step 1).  CompactTag: [tZ]_p = [tR]_p - [Delta]_p D~ (Pi_OptMAC step 3) and
 // the compressions D~^c, [tR^c]_p, [tC^c]_p (Fig. 7 step 6).  SPDZ2k with
 // F_CHECK: the batch check sums of D with [tD]_p = [tR]_p - [tZ]_p.
+// f > 0 (both protocols): the truncated output of OptMAC&Trunc (Fig. 6
+// ExpandTrunc steps 2-4) / Pi_Truncation (Fig. 3 online step 2),
+// [Z^f]_p = [R^f]_p - (D mod 2^64) / 2^f (party 0 subtracts the public term),
+// [tZ^f]_p = [tR^f]_p - [Delta]_p (D mod 2^64) / 2^f.
+__device__ __forceinline__ void truncate_out(const LayerDev &L, int64_t e, u128 D) {
+    const uint64_t df = D.lo >> L.f;
+    st(L.Zf[0], e, sub(ld(L.Rf[0], e), u128{df, 0}));
+    st(L.Zf[1], e, ld(L.Rf[1], e));
+    st(L.tZf[0], e, sub(ld(L.tRf[0], e), mul64(u128{L.delta[0], 0}, df)));
+    st(L.tZf[1], e, sub(ld(L.tRf[1], e), mul64(u128{L.delta[1], 0}, df)));
+}
+
 __global__ __launch_bounds__(TPB) void k_post(const LayerDev *__restrict__ Ls, int flags) {
     __shared__ u128 sh[3 * WAVES];
     const LayerDev &L = Ls[blockIdx.y];
@@ -440,6 +464,7 @@ __global__ __launch_bounds__(TPB) void k_post(const LayerDev *__restrict__ Ls, i
             const int64_t e = r * N + c;
             const u128 D = add(sub(ld(L.R[0], e), ld(L.Z[0], e)), sub(ld(L.R[1], e), ld(L.Z[1], e)));
             st(L.D, e, D);
+            if (L.f > 0) truncate_out(L, e, D);
             const u128 tr0 = ld(L.tR[0], e), tr1 = ld(L.tR[1], e);
             st(L.tZ[0], e, sub(tr0, mul64(D, L.delta[0])));
             st(L.tZ[1], e, sub(tr1, mul64(D, L.delta[1])));
@@ -464,6 +489,7 @@ __global__ __launch_bounds__(TPB) void k_post(const LayerDev *__restrict__ Ls, i
             const u128 z0 = ld(L.Z[0], e), z1 = ld(L.Z[1], e);
             const u128 D = add(sub(ld(L.R[0], e), z0), sub(ld(L.R[1], e), z1));
             st(L.D, e, D);
+            if (L.f > 0) truncate_out(L, e, D);
             if (check) {
                 const uint64_t x = sdraw(kcd, (uint64_t)e);
                 chk[0] = mad64(chk[0], sub(ld(L.tR[0], e), ld(L.tZ[0], e)), x);

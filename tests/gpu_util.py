@@ -13,7 +13,7 @@ import oracle as O
 DEALT = ["X", "tX", "A", "tA", "Y", "tY", "B", "tB", "C", "tC", "R", "tR"]
 MK = {"X", "tX", "A", "tA", "E"}
 KN = {"Y", "tY", "B", "tB", "U"}
-MN = {"C", "tC", "R", "tR", "Z", "tZ", "D"}
+MN = {"C", "tC", "R", "tR", "Z", "tZ", "D", "Rf", "tRf", "Zf", "tZf"}
 
 
 def say(*a):
@@ -27,11 +27,13 @@ def to_np(t: torch.Tensor) -> np.ndarray:
 
 def gpu_layers(ctx, specs, device="cuda:0"):
     from paper_2311_04406_amd import Layer
-    return [Layer(s.M, s.K, s.N, s.seed, s.layer_id, device=device) for s in specs]
+    return [Layer(s.M, s.K, s.N, s.seed, s.layer_id, device=device, f=getattr(s, "f", 0),
+                  in_bits=getattr(s, "in_bits", 0)) for s in specs]
 
 
 def oracle_run(mode, spec, key_seed, r0=0, r1=None):
-    return O.run_layer(mode, spec.M, spec.K, spec.N, spec.seed, spec.layer_id, key_seed, r0, r1)
+    return O.run_layer(mode, spec.M, spec.K, spec.N, spec.seed, spec.layer_id, key_seed, r0, r1,
+                       getattr(spec, "f", 0), getattr(spec, "in_bits", 0))
 
 
 def _rows(name, arr, r0, r1):
@@ -46,6 +48,8 @@ def compare_layer(gl, ol, mode, r0=0, r1=None, dealt=True, what=""):
     if r1 is None:
         r1 = gl.M
     names = (DEALT if dealt else []) + ["Z", "tZ"]
+    if getattr(gl, "f", 0) > 0:
+        names += (["Rf", "tRf"] if dealt else []) + ["Zf", "tZf"]
     for n in names:
         for p in range(2):
             g = to_np(_rows(n, gl[n][p], r0, r1))

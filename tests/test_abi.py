@@ -61,7 +61,8 @@ int main(void) {
   printf("%zu %zu %zu %zu\n", sizeof(ct_params), sizeof(ct_layer_desc), sizeof(ct_layer_bufs), sizeof(ct_check_result));
   printf("%zu %zu %zu %zu\n", offsetof(ct_params, hip_stream), offsetof(ct_params, max_layers),
          offsetof(ct_layer_desc, seed), offsetof(ct_layer_desc, layer_id));
-  printf("%zu %zu %zu\n", offsetof(ct_layer_bufs, E), offsetof(ct_layer_bufs, cvec), offsetof(ct_check_result, accept));
+  printf("%zu %zu %zu %zu %zu\n", offsetof(ct_layer_bufs, E), offsetof(ct_layer_bufs, cvec), offsetof(ct_check_result, accept),
+         offsetof(ct_layer_bufs, Rf), offsetof(ct_layer_bufs, tZf));
   printf("%zu %zu %zu %zu\n", sizeof(ct_server_params), sizeof(ct_request), sizeof(ct_completion), sizeof(ct_server_counts));
   printf("%zu %zu %zu %zu %zu %zu %zu\n", offsetof(ct_server_params, mode), offsetof(ct_request, layer),
          offsetof(ct_request, arrival_us), offsetof(ct_completion, done_us), offsetof(ct_completion, result),
@@ -79,7 +80,7 @@ int main(void) {
            ctypes.sizeof(b.CtCheckResult),
            b.CtParams.hip_stream.offset, b.CtParams.max_layers.offset, b.CtLayerDesc.seed.offset,
            b.CtLayerDesc.layer_id.offset, b.CtLayerBufs.E.offset, b.CtLayerBufs.cvec.offset,
-           b.CtCheckResult.accept.offset,
+           b.CtCheckResult.accept.offset, b.CtLayerBufs.Rf.offset, b.CtLayerBufs.tZf.offset,
            ctypes.sizeof(b.CtServerParams), ctypes.sizeof(b.CtRequest), ctypes.sizeof(b.CtCompletion),
            ctypes.sizeof(b.CtServerCounts),
            b.CtServerParams.mode.offset, b.CtRequest.layer.offset, b.CtRequest.arrival_us.offset,

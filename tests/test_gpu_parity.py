@@ -14,8 +14,9 @@ MODES = [O.MODE_SPDZ2K, O.MODE_COMPACT]
 
 
 class Spec:
-    def __init__(self, M, K, N, seed=1, layer_id=1, name=""):
+    def __init__(self, M, K, N, seed=1, layer_id=1, name="", f=0, in_bits=0):
         self.M, self.K, self.N, self.seed, self.layer_id, self.name = M, K, N, seed, layer_id, name or f"{M}x{K}x{N}"
+        self.f, self.in_bits = f, in_bits
 
 
 @pytest.fixture(scope="module")
@@ -171,4 +172,42 @@ def test_flipped_share_bit_aborts(ctx, mode, target):
     ol.online(mode).check(mode)
     compare_layer(layers[0], ol, mode, what="tampered")
     compare_cs(res[0], ol, what="tampered")
+    free()
+
+
+# truncation by the opened D (f > 0): wide, skinny, ragged and split-K layers,
+# uniform and signed 16-bit inputs
+TRUNC = [Spec(70, 100, 130, 21, 21, f=13, in_bits=16), Spec(33, 70, 1, 22, 22, f=13, in_bits=16),
+         Spec(5, 300, 9, 23, 23, f=40), Spec(40, 2100, 70, 24, 24, f=1, in_bits=20),
+         Spec(17, 40, 8, 25, 25, f=63)]
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("spec", TRUNC, ids=lambda s: f"{s.name}_f{s.f}_b{s.in_bits}")
+def test_truncation_bit_exact(ctx, mode, spec):
+    say(f"[parity] truncation mode={mode} shape={spec.name} f={spec.f} in_bits={spec.in_bits}")
+    layers, status, res = run_all(ctx, mode, [spec])
+    ol = oracle_run(mode, spec, KEY)
+    compare_layer(layers[0], ol, mode, what=spec.name)
+    compare_cs(res[0], ol, what=spec.name)
+    assert status == 0 and res[0].accept and ol.accept()
+    free()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_truncation_fused_batch(ctx, mode):
+    """A batch mixing f = 0 and f > 0 layers through the fused call equals the oracle."""
+    from paper_2311_04406_amd import Context
+    specs = [Spec(64, 128, 32, 31, 31), TRUNC[0], TRUNC[1], TRUNC[3]]
+    say(f"[parity] truncation fused batch mode={mode}")
+    layers = gpu_layers(ctx, specs)
+    ctx.gen_triple_tags(layers)
+    out = torch.zeros(14 * len(specs), dtype=torch.int64, device="cuda:0")
+    ctx.tag_linear_check(mode, layers, out)
+    res = Context.decode_results(out, len(specs))
+    for l, s, r in zip(layers, specs, res):
+        ol = oracle_run(mode, s, KEY)
+        compare_layer(l, ol, mode, what=s.name)
+        compare_cs(r, ol, what=s.name)
+        assert r.accept
     free()
