@@ -164,16 +164,29 @@ __device__ __forceinline__ void combine(const v16i (&acc)[16], int r, u128 &v) {
 
 typedef __attribute__((address_space(3))) void lds_void;
 
+__device__ __forceinline__ const uint8_t *uniform_ptr(const uint8_t *p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return reinterpret_cast<const uint8_t *>(((uint64_t)hi << 32) | lo);
+}
+
 // Copies the A and B digit tiles of one K slice into an LDS stage: 64 chunks
 // of 1 KB, 16 per wavefront, each a single global_load_lds_dwordx4 (lane l
-// moves bytes [16 l, 16 l + 16) of its chunk).
+// moves bytes [16 l, 16 l + 16) of its chunk).  Wavefronts 0, 1 copy the A
+// tile, 2, 3 the B tile; the tile base is made wavefront-uniform so each copy
+// addresses memory as scalar base + 32-bit lane offset (no 64-bit address
+// registers to keep live across the products).
 __device__ __forceinline__ void issue_slice(const uint8_t *a_tile, const uint8_t *b_tile, uint8_t *stage) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint8_t *base = uniform_ptr(wave < 2 ? a_tile : b_tile);
+    const uint32_t first = (uint32_t)(wave & 1) * 16 * 1024;  // byte offset of the wave's 16 chunks in the tile
 #pragma unroll
     for (int i = 0; i < 16; i++) {
-        const int c = wave * 16 + i;  // chunk 0..63: A 0..31, B 32..63
-        const uint8_t *src = (c < 32 ? a_tile + c * 1024 : b_tile + (c - 32) * 1024) + lane * 16;
-        __builtin_amdgcn_global_load_lds((const void *)src, (lds_void *)(stage + c * 1024), 16, 0, 0);
+        const uint32_t off = first + (uint32_t)i * 1024;
+        __builtin_amdgcn_global_load_lds((const void *)(base + off + lane * 16),
+                                         (lds_void *)(stage + wave * 16 * 1024 + off - first), 16, 0, 0);
     }
 }
 
