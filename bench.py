@@ -37,7 +37,7 @@ INT8_PEAK_TOPS = 5000.0      # MI355X dense int8 MFMA, 5.0 POP/s
 DIGIT_PAIRS = 136            # int8 digit products per 128-bit ring multiply-accumulate
 
 
-def stage_work(stage: str, specs, mode: str):
+def stage_work(stage: str, specs, mode: str, f: int = 0):
     """Algorithmic work of one launch of a kernel stage over the layer batch:
     ("hbm", bytes) or ("mfma", int8 ops), for the fused step
     (online phase + verification).  16 B per Z_2^128 element; per element:
@@ -54,7 +54,8 @@ def stage_work(stage: str, specs, mode: str):
                  layer (8 in SPDZ2k), layers with N > 8
       post       M x N: CompactTag reads R_p, Z_p, tR_p, tC_p (8), writes D,
                  tZ_p (3): 176 B; SPDZ2k reads R_p, Z_p, tR_p, tZ_p (8),
-                 writes D: 144 B."""
+                 writes D: 144 B; with f > 0 also reads R^f_p, tR^f_p and
+                 writes Z^f_p, tZ^f_p: + 128 B."""
     spdz = mode == "spdz2k"
     tot = 0
     for s in specs:
@@ -72,7 +73,7 @@ def stage_work(stage: str, specs, mode: str):
         elif stage == "ring_gemm":
             tot += 2 * DIGIT_PAIRS * (8 if spdz else 4) * M * K * N if wide else 0
         elif stage == "post":
-            tot += (144 if spdz else 176) * mn
+            tot += ((144 if spdz else 176) + (128 if f > 0 else 0)) * mn
         else:
             return None
     return ("mfma" if stage == "ring_gemm" else "hbm", tot)
@@ -256,6 +257,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=1000.0,
                     help="offered rate (req/s) of the serving leg of a layer-batch run")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--f", type=int, default=0, help="truncate every product by f fractional bits (0..63)")
+    ap.add_argument("--in-bits", type=int, default=0, help="dealer inputs as signed in-bits-bit integers (0: uniform)")
     ap.add_argument("--mode", default="compact", choices=["compact", "spdz2k"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the SPDZ2k and per-layer comparison runs")
@@ -280,7 +283,8 @@ def main():
     specs = workloads.CONFIGS[args.config]()
     mode_id = MODE_COMPACT if args.mode == "compact" else MODE_SPDZ2K
     ctx = Context(device=0, key_seed=workloads.KEY_SEED, max_layers=max(256, len(specs)))
-    layers = [Layer(s.M, s.K, s.N, s.seed, s.layer_id, device="cuda:0") for s in specs]
+    layers = [Layer(s.M, s.K, s.N, s.seed, s.layer_id, device="cuda:0", f=args.f, in_bits=args.in_bits)
+              for s in specs]
     print(f"[bench] config {args.config}: {len(specs)} layers, dealer ...", file=sys.stderr, flush=True)
     ctx.gen_triple_tags(layers)
     torch.cuda.synchronize()
@@ -321,7 +325,7 @@ def main():
     stage_rows = {}
     for name, (tot_ms, n) in stages.items():
         avg = tot_ms / max(n, 1)
-        w = stage_work(name, specs, args.mode)
+        w = stage_work(name, specs, args.mode, args.f)
         row = {"ms_per_launch": round(avg, 5), "launches": n, "share_of_step": round(tot_ms / args.steps / ms, 4)}
         if w is not None and w[1] > 0:
             bound, units = w
@@ -343,7 +347,7 @@ def main():
         else:
             roofline = {"kernel": k, "bound": "mfma", "achieved": v["achieved_TOPS"], "peak": INT8_PEAK_TOPS,
                         "unit": "TOPS (int8)", "frac": v["frac"]}
-        roofline["traffic"] = measured_traffic(k, f"{args.config}/{args.mode}")
+        roofline["traffic"] = measured_traffic(k, f"{args.config}/{args.mode}" + (f"/f{args.f}" if args.f else ""))
         roofline["share_of_step"] = v["share_of_step"]
 
     out = {
@@ -355,7 +359,7 @@ def main():
         "config": {"workload": f"{args.config}: " + ", ".join(f"{s.name} ({s.M}x{s.K}x{s.N})" for s in specs)
                    if len(specs) <= 8 else f"{args.config}: {len(specs)} layers, sum MKN {mkn}",
                    "protocol": args.mode, "parties": 2, "ring": "values Z_2^64, shares and tags Z_2^128",
-                   "layers_per_call": len(specs), "sum_MKN": mkn},
+                   "layers_per_call": len(specs), "sum_MKN": mkn, "f": args.f, "in_bits": args.in_bits},
         "roofline": roofline,
         "eager": {"value": round(mkn * args.steps / Te / 1e9, 3), "ms_per_step": round(Te / args.steps * 1e3, 4),
                   "p50_ms": round(pct(pere, 50), 4), "p99_ms": round(pct(pere, 99), 4)},

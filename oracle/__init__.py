@@ -5,8 +5,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``ct_oracle.c`` through ctypes; it shares no code with the GPU library, and the
 GPU library never falls back to it.
 
-Ring elements of Z_{2^128} are numpy ``uint64`` arrays whose last axis holds
-the (lo, hi) limbs.  ``run_layer`` executes the whole two-party procedure of
+Ring elements of Z_{2^{k+s}} are numpy ``uint64`` arrays whose last axis holds
+the (lo, hi) limbs (k = s = 64 or 32; with 32 the high limb is zero).  ``run_layer`` executes the whole two-party procedure of
 one linear layer -- the dealer (preprocessing of Fig. 7), the online phase and
 the verification -- optionally restricted to a range of rows of the M
 dimension, which is how full-size layers are sampled.
@@ -44,7 +44,8 @@ def build(force: bool = False) -> str:
 class _Desc(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int64), ("K", ctypes.c_int64), ("N", ctypes.c_int64),
                 ("seed", ctypes.c_uint64), ("layer_id", ctypes.c_uint64),
-                ("r0", ctypes.c_int64), ("r1", ctypes.c_int64), ("f", ctypes.c_int64), ("in_bits", ctypes.c_int64)]
+                ("r0", ctypes.c_int64), ("r1", ctypes.c_int64), ("f", ctypes.c_int64), ("in_bits", ctypes.c_int64),
+                ("kbits", ctypes.c_int64)]
 
 
 _P2 = ctypes.c_void_p * 2
@@ -80,6 +81,8 @@ def lib():
         L.or_draw.argtypes = [u64, u64, u64]
         L.or_draw_many.argtypes = [u64, u64, u64, i64, vp]
         L.or_key_shares.argtypes = [u64, vp]
+        L.or_key_shares_k.argtypes = [u64, i64, vp]
+        L.or_set_kbits.argtypes = [i64]
         L.or_deal.argtypes = [ctypes.POINTER(_Desc), vp, ctypes.c_int, ctypes.POINTER(_Bufs)]
         L.or_online.argtypes = [ctypes.c_int, ctypes.POINTER(_Desc), vp, ctypes.POINTER(_Bufs)]
         L.or_check.argtypes = [ctypes.c_int, ctypes.POINTER(_Desc), vp, ctypes.POINTER(_Bufs)]
@@ -145,10 +148,15 @@ def stream(layer_id: int, purpose: int) -> int:
     return ((layer_id << 16) | purpose) & MASK64
 
 
-def key_shares(key_seed: int) -> np.ndarray:
+def key_shares(key_seed: int, kbits: int = 64) -> np.ndarray:
     out = np.zeros(2, dtype=np.uint64)
-    lib().or_key_shares(key_seed & MASK64, _ptr(out))
+    lib().or_key_shares_k(key_seed & MASK64, kbits, _ptr(out))
     return out
+
+
+def set_kbits(kbits: int):
+    """Ring width (k = s) of the building blocks matmul, compress, batchrec_cs, compact_cs."""
+    lib().or_set_kbits(kbits)
 
 
 # ---------------------------------------------------------------------------
@@ -166,6 +174,7 @@ class OracleLayer:
     r1: int | None = None
     f: int = 0
     in_bits: int = 0
+    kbits: int = 64
     arrays: dict = field(default_factory=dict)
     cs: np.ndarray | None = None        # [3 (E,U,D)][2 parties][2 limbs]
     tag_mults: np.ndarray | None = None
@@ -186,11 +195,11 @@ class OracleLayer:
                       tCc=(2, rows), tRc=(2, rows), tZc=(2, rows), tDc=(2, rows))
         for n, s in shapes.items():
             self.arrays[n] = np.zeros(s + (2,), dtype=np.uint64)
-        self.delta = key_shares(self.key_seed)
+        self.delta = key_shares(self.key_seed, self.kbits)
 
     def _desc(self):
         return _Desc(self.M, self.K, self.N, self.seed & MASK64, self.layer_id & MASK64, self.r0, self.r1,
-                     self.f, self.in_bits)
+                     self.f, self.in_bits, self.kbits)
 
     def _bufs(self):
         b = _Bufs()
@@ -221,7 +230,8 @@ class OracleLayer:
 
     def cs_sums(self):
         """sum over parties of each check value, mod 2^{k+s}: [E, U, D]."""
-        return [(u128(self.cs[w, 0]) + u128(self.cs[w, 1])) & MASK128 for w in range(3)]
+        mask = MASK128 if self.kbits == 64 else MASK64
+        return [(u128(self.cs[w, 0]) + u128(self.cs[w, 1])) & mask for w in range(3)]
 
     def accept(self) -> bool:
         return all(s == 0 for s in self.cs_sums())
@@ -231,10 +241,10 @@ class OracleLayer:
 
 
 def run_layer(mode: int, M: int, K: int, N: int, seed: int, layer_id: int, key_seed: int,
-              r0: int = 0, r1: int | None = None, f: int = 0, in_bits: int = 0) -> OracleLayer:
+              r0: int = 0, r1: int | None = None, f: int = 0, in_bits: int = 0, kbits: int = 64) -> OracleLayer:
     """Dealer, online phase and verification of one layer on rows [r0, r1)
-    (with f > 0 the product is truncated by f fractional bits)."""
-    L = OracleLayer(M, K, N, seed, layer_id, key_seed, r0, r1, f, in_bits)
+    (with f > 0 the product is truncated by f fractional bits; kbits = k = s)."""
+    L = OracleLayer(M, K, N, seed, layer_id, key_seed, r0, r1, f, in_bits, kbits)
     return L.deal().online(mode).check(mode)
 
 

@@ -1,15 +1,19 @@
 /*
  * ct_oracle.c -- plain, slow CPU oracle for the linear-layer hot path of
  * CompactTag (arXiv 2311.04406): two parties of SPDZ2k-style MPC over the
- * value ring Z_{2^k}, k = 64, with shares and tags in Z_{2^{k+s}} = Z_{2^128}
- * (s = 64) and key shares in Z_{2^s}.
+ * value ring Z_{2^k} with shares and tags in Z_{2^{k+s}} and key shares in
+ * Z_{2^s}, for the two parameter sets of Sec. 4.1: k = s = 64 (Z_{2^128}) and
+ * k = s = 32 (Z_{2^64}).
  *
  * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the CPU
  * baseline of the benchmark may load this file.  It shares no code with the
  * GPU library and must never be used as a fallback for it.
  *
  * Everything is naive loops over `unsigned __int128`, whose arithmetic wraps
- * modulo 2^128 exactly as the ring Z_{2^{k+s}} does.  Each step follows the
+ * modulo 2^128; with k + s = 64 every stored value is reduced mod 2^64 (a ring
+ * homomorphism, so reducing at each store equals computing in Z_{2^64}), and
+ * the operations that are not ring operations -- the key, combiner and input
+ * draws, the truncation -- reduce explicitly.  Each step follows the
  * paper in order:
  *   - authenticated sharing, Sec. 2.4 and Eq. (1);
  *   - the preprocessing functionalities F_Rand and F_MAC, Appendix A;
@@ -33,15 +37,25 @@ typedef unsigned __int128 u128;
  * read off this counter around the tag computations. */
 static uint64_t g_mults;
 
+/* k = s of the current call: 64 (ring Z_{2^128}) or 32 (ring Z_{2^64}). */
+static int64_t g_kbits = 64;
+
+void or_set_kbits(int64_t kbits) { g_kbits = kbits == 32 ? 32 : 64; }
+
+/* x mod 2^s for a draw used as a key share or a combiner (s = k) */
+static uint64_t mod_s(uint64_t x) { return g_kbits == 32 ? (x & 0xFFFFFFFFULL) : x; }
+/* v mod 2^k: the value of a lifted element */
+static uint64_t mod_k(u128 v) { return g_kbits == 32 ? (uint64_t)(uint32_t)v : (uint64_t)v; }
+
 /* ------------------------------------------------------------------ */
-/* (lo, hi) limb storage                                                */
+/* (lo, hi) limb storage; stores reduce mod 2^{k+s}                      */
 
 static inline u128 ld(const uint64_t *p, int64_t i) {
     return (u128)p[2 * i] | ((u128)p[2 * i + 1] << 64);
 }
 static inline void st(uint64_t *p, int64_t i, u128 v) {
     p[2 * i] = (uint64_t)v;
-    p[2 * i + 1] = (uint64_t)(v >> 64);
+    p[2 * i + 1] = g_kbits == 32 ? 0 : (uint64_t)(v >> 64);
 }
 static uint64_t *alloc128(int64_t n) {
     uint64_t *p = (uint64_t *)calloc((size_t)(n > 0 ? n : 1) * 2, sizeof(uint64_t));
@@ -80,14 +94,23 @@ static u128 draw128(uint64_t seed, uint64_t stream, uint64_t e) {
     return (u128)or_draw(seed, stream, 2 * e) | ((u128)or_draw(seed, stream, 2 * e + 1) << 64);
 }
 
-/* F_MAC Initialize: key shares [Delta]_p uniform in Z_{2^s}. */
-void or_key_shares(uint64_t key_seed, uint64_t delta[2]) {
-    for (int p = 0; p < 2; p++)
-        delta[p] = or_draw(key_seed, stream_of(OR_GLOBAL_LAYER, OR_P_KEY + (uint64_t)p), 0);
+/* F_MAC Initialize: key shares [Delta]_p uniform in Z_{2^s} (the draw mod 2^s). */
+void or_key_shares_k(uint64_t key_seed, int64_t kbits, uint64_t delta[2]) {
+    for (int p = 0; p < 2; p++) {
+        const uint64_t x = or_draw(key_seed, stream_of(OR_GLOBAL_LAYER, OR_P_KEY + (uint64_t)p), 0);
+        delta[p] = kbits == 32 ? (x & 0xFFFFFFFFULL) : x;
+    }
+}
+void or_key_shares(uint64_t key_seed, uint64_t delta[2]) { or_key_shares_k(key_seed, 64, delta); }
+
+/* combiner draws: uniform in Z_{2^s} */
+static void draw_chi(uint64_t seed, uint64_t stream, uint64_t first, int64_t n, uint64_t *out) {
+    or_draw_many(seed, stream, first, n, out);
+    for (int64_t i = 0; i < n; i++) out[i] = mod_s(out[i]);
 }
 
 /* The key used in every tag relation is the integer sum [Delta]_0 + [Delta]_1
- * (< 2^65), taken mod 2^{k+s}; see the reading of Sec. 2.4 in the design notes. */
+ * (< 2^{s+1}), taken mod 2^{k+s}; see the reading of Sec. 2.4 in the design notes. */
 static u128 key_sum(const uint64_t delta[2]) { return (u128)delta[0] + (u128)delta[1]; }
 
 /* ------------------------------------------------------------------ */
@@ -165,10 +188,16 @@ static void auth_share(u128 lift, u128 dsum, uint64_t seed, uint64_t layer_id, i
 
 enum { OBJ_X = 1, OBJ_Y = 2, OBJ_A = 3, OBJ_B = 4, OBJ_C = 5, OBJ_R = 6, OBJ_RF = 7 };
 
-/* An input value of Z_{2^k}: a uniform draw, or with in_bits in 1..63 a signed
- * in_bits-bit integer (the draw's top bits, sign-extended) in two's complement
- * -- a stand-in for fixed-point encodings.  Lifted with zero upper bits. */
+/* An input value of Z_{2^k}: the draw mod 2^k, or with in_bits in 1..k-1 a
+ * signed in_bits-bit integer (the top in_bits of those k bits, sign-extended)
+ * in two's complement -- a stand-in for fixed-point encodings.  Lifted with
+ * zero upper bits. */
 static u128 input_lift(uint64_t draw, int64_t in_bits) {
+    if (g_kbits == 32) {
+        const uint32_t x = (uint32_t)draw;
+        if (in_bits <= 0 || in_bits >= 32) return (u128)x;
+        return (u128)(uint32_t)((int32_t)x >> (32 - in_bits));
+    }
     if (in_bits <= 0 || in_bits >= 64) return (u128)draw;
     return (u128)(uint64_t)((int64_t)draw >> (64 - in_bits));
 }
@@ -180,6 +209,7 @@ static u128 input_lift(uint64_t draw, int64_t in_bits) {
  * truncated mask of Figs. 3 and 6, R^f = (R mod 2^k) / 2^f (an integer below
  * 2^{k-f}), lifted with a uniform upper limb and authenticated like the rest. */
 void or_deal(const or_desc *d, const uint64_t delta[2], int with_inputs, or_bufs *b) {
+    or_set_kbits(d->kbits);
     const int64_t M = d->M, K = d->K, N = d->N, r0 = d->r0, rows = d->r1 - d->r0;
     const uint64_t seed = d->seed, lid = d->layer_id;
     const u128 dsum = key_sum(delta);
@@ -217,8 +247,8 @@ void or_deal(const or_desc *d, const uint64_t delta[2], int with_inputs, or_bufs
             auth_share(ld(Ct, at), dsum, seed, lid, OBJ_C, e, b->C[0], b->C[1], b->tC[0], b->tC[1], at);
             auth_share(r, dsum, seed, lid, OBJ_R, e, b->R[0], b->R[1], b->tR[0], b->tR[1], at);
             if (d->f > 0) {
-                u128 rf = (u128)((uint64_t)r >> d->f) |
-                          ((u128)or_draw(seed, stream_of(lid, OR_P_LIFT_RF), e) << 64);
+                const uint64_t up = mod_s(or_draw(seed, stream_of(lid, OR_P_LIFT_RF), e));
+                u128 rf = (u128)(mod_k(r) >> d->f) | ((u128)up << g_kbits);
                 auth_share(rf, dsum, seed, lid, OBJ_RF, e, b->Rf[0], b->Rf[1], b->tRf[0], b->tRf[1], at);
             }
         }
@@ -246,6 +276,7 @@ static void add_into(int64_t n, uint64_t *acc, const uint64_t *x) {
 }
 
 void or_online(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) {
+    or_set_kbits(d->kbits);
     const int64_t K = d->K, N = d->N, rows = d->r1 - d->r0;
     const uint64_t seed = d->seed, lid = d->layer_id;
 
@@ -282,7 +313,7 @@ void or_online(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) 
      *   [tZ^f]_p = [tR^f]_p - [Delta]_p * D/2^f. */
     if (d->f > 0) {
         for (int64_t e = 0; e < rows * N; e++) {
-            const uint64_t df = (uint64_t)ld(b->D, e) >> d->f;
+            const uint64_t df = mod_k(ld(b->D, e)) >> d->f;
             for (int p = 0; p < 2; p++) {
                 st(b->Zf[p], e, ld(b->Rf[p], e) - (p == 0 ? (u128)df : (u128)0));
                 st(b->tZf[p], e, ld(b->tRf[p], e) - (u128)delta[p] * df);
@@ -325,7 +356,7 @@ void or_online(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) 
          * to each. */
         uint64_t *chi = (uint64_t *)malloc((size_t)(N > 0 ? N : 1) * 8);
         if (!chi) abort();
-        or_draw_many(seed, stream_of(lid, OR_P_CHI), 0, N, chi);
+        draw_chi(seed, stream_of(lid, OR_P_CHI), 0, N, chi);
         uint64_t m_pub = g_mults;
         or_compress(K, N, b->U, chi, b->Uc);
         or_compress(rows, N, b->D, chi, b->Dc);
@@ -368,6 +399,7 @@ static void tag_diff(int64_t n, const uint64_t *tP, const uint64_t *tQ, uint64_t
 }
 
 void or_check(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) {
+    or_set_kbits(d->kbits);
     const int64_t M = d->M, K = d->K, N = d->N, r0 = d->r0, rows = d->r1 - d->r0;
     const uint64_t seed = d->seed, lid = d->layer_id;
     int64_t big = rows * K > K * N ? rows * K : K * N;
@@ -379,12 +411,12 @@ void or_check(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) {
 
     /* Fig. 7 verification step 1: Pi_BatchRec tag check of E and of U, one
      * public combiner per element (Fig. 1 tag-check step 1). */
-    or_draw_many(seed, stream_of(lid, OR_P_CHI_E), (uint64_t)(r0 * K), rows * K, chi);
+    draw_chi(seed, stream_of(lid, OR_P_CHI_E), (uint64_t)(r0 * K), rows * K, chi);
     for (int p = 0; p < 2; p++) {
         tag_diff(rows * K, b->tX[p], b->tA[p], tW);
         or_batchrec_cs(rows * K, b->E, tW, chi, delta[p], b->cs[0][p]);
     }
-    or_draw_many(seed, stream_of(lid, OR_P_CHI_U), 0, K * N, chi);
+    draw_chi(seed, stream_of(lid, OR_P_CHI_U), 0, K * N, chi);
     for (int p = 0; p < 2; p++) {
         tag_diff(K * N, b->tY[p], b->tB[p], tW);
         or_batchrec_cs(K * N, b->U, tW, chi, delta[p], b->cs[1][p]);
@@ -393,14 +425,14 @@ void or_check(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) {
     if (mode == OR_MODE_SPDZ2K) {
         /* Pi_Truncation verification: Pi_BatchRec tag check of D = R - Z,
          * [tD]_p = [tR]_p - [tZ]_p. */
-        or_draw_many(seed, stream_of(lid, OR_P_CHI_D), (uint64_t)(r0 * N), rows * N, chi);
+        draw_chi(seed, stream_of(lid, OR_P_CHI_D), (uint64_t)(r0 * N), rows * N, chi);
         for (int p = 0; p < 2; p++) {
             tag_diff(rows * N, b->tR[p], b->tZ[p], tW);
             or_batchrec_cs(rows * N, b->D, tW, chi, delta[p], b->cs[2][p]);
         }
     } else {
         /* Fig. 7 verification steps 2-5: chihat in Z_{2^s}^{M x 1}. */
-        or_draw_many(seed, stream_of(lid, OR_P_CHIHAT), (uint64_t)r0, rows, chi);
+        draw_chi(seed, stream_of(lid, OR_P_CHIHAT), (uint64_t)r0, rows, chi);
         for (int p = 0; p < 2; p++) or_compact_cs(rows, b->Dc, b->tDc[p], chi, delta[p], b->cs[2][p]);
     }
     free(tW);

@@ -6,8 +6,9 @@
  * test suite, the smoke check and the CPU-baseline leg of the benchmark load
  * the oracle.
  *
- * Ring elements of Z_{2^128} are stored as two little-endian uint64 limbs
- * (lo, hi).  Matrices are row-major.  A "rows" range [r0, r1) restricts every
+ * Ring elements of Z_{2^{k+s}} are stored as two little-endian uint64 limbs
+ * (lo, hi); with k = s = 32 the high limb is always zero.  Matrices are
+ * row-major.  A "rows" range [r0, r1) restricts every
  * M-indexed quantity to those rows of the M dimension; with r0 = 0 and r1 = M
  * the oracle runs the whole procedure.  K x N quantities are always complete.
  */
@@ -40,7 +41,8 @@ typedef struct {
     uint64_t seed, layer_id;  /* per-layer randomness */
     int64_t r0, r1;           /* rows of the M dimension that are computed */
     int64_t f;                /* fractional bits truncated from the product (0: no truncation) */
-    int64_t in_bits;          /* 0: inputs uniform in Z_{2^k}; 1..63: signed in_bits-bit inputs */
+    int64_t in_bits;          /* 0: inputs uniform in Z_{2^k}; 1..k-1: signed in_bits-bit inputs */
+    int64_t kbits;            /* k = s: 64 (shares in Z_{2^128}) or 32 (shares in Z_{2^64}); 0 means 64 */
 } or_desc;
 
 /* Every pointer is a caller-owned array of (lo, hi) uint64 pairs. */
@@ -69,6 +71,10 @@ uint64_t or_draw(uint64_t seed, uint64_t stream, uint64_t i);
 void or_draw_many(uint64_t seed, uint64_t stream, uint64_t first, int64_t n, uint64_t *out);
 
 void or_key_shares(uint64_t key_seed, uint64_t delta[2]);
+void or_key_shares_k(uint64_t key_seed, int64_t kbits, uint64_t delta[2]);
+/* Ring width of the building blocks below (k = s = kbits); or_deal,
+ * or_online and or_check set it from their descriptor. */
+void or_set_kbits(int64_t kbits);
 void or_deal(const or_desc *d, const uint64_t delta[2], int with_inputs, or_bufs *b);
 void or_online(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b);
 void or_check(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b);

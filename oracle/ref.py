@@ -29,14 +29,20 @@ def stream(layer_id: int, purpose: int) -> int:
     return ((layer_id << 16) | purpose) & MASK64
 
 
-def mat(M, K, N, P, Q):
-    return [[sum(P[i][k] * Q[k][j] for k in range(K)) % R128 for j in range(N)] for i in range(M)]
+def mat(M, K, N, P, Q, ring=R128):
+    return [[sum(P[i][k] * Q[k][j] for k in range(K)) % ring for j in range(N)] for i in range(M)]
 
 
-def online_and_check(compact: bool, M, K, N, seed, layer_id, delta, S, f: int = 0):
+def online_and_check(compact: bool, M, K, N, seed, layer_id, delta, S, f: int = 0, kbits: int = 64):
     """S: dict name -> per-party lists of Python-int matrices (X, tX, A, tA, Y, tY,
     B, tB, C, tC, R, tR, and Rf, tRf when f > 0), each S[name][p][i][j].
+    Arithmetic is mod 2^{k+s} with k = s = kbits; combiners are draws mod 2^s.
     Returns a dict of outputs."""
+    R128 = 1 << (2 * kbits)          # the ring Z_{2^{k+s}} (name kept from the default k = 64)
+    smask = (1 << kbits) - 1
+
+    def mat(M_, K_, N_, P, Q):
+        return [[sum(P[i][k] * Q[k][j] for k in range(K_)) % R128 for j in range(N_)] for i in range(M_)]
     out = {}
     E = [[(S["X"][0][i][k] - S["A"][0][i][k] + S["X"][1][i][k] - S["A"][1][i][k]) % R128
           for k in range(K)] for i in range(M)]
@@ -53,7 +59,7 @@ def online_and_check(compact: bool, M, K, N, seed, layer_id, delta, S, f: int = 
          for i in range(M)]
     if f > 0:
         # truncation by the opened D: its value mod 2^64, shifted right by f
-        Df = [[(D[i][j] & MASK64) >> f for j in range(N)] for i in range(M)]
+        Df = [[(D[i][j] & smask) >> f for j in range(N)] for i in range(M)]
         out["Zf"] = [[[(S["Rf"][p][i][j] - (Df[i][j] if p == 0 else 0)) % R128 for j in range(N)]
                       for i in range(M)] for p in range(2)]
         out["tZf"] = [[[(S["tRf"][p][i][j] - delta[p] * Df[i][j]) % R128 for j in range(N)]
@@ -68,7 +74,7 @@ def online_and_check(compact: bool, M, K, N, seed, layer_id, delta, S, f: int = 
     else:
         for p in range(2):
             tZ.append([[(S["tR"][p][i][j] - delta[p] * D[i][j]) % R128 for j in range(N)] for i in range(M)])
-        chi = [draw(seed, stream(layer_id, 0x30), j) for j in range(N)]
+        chi = [draw(seed, stream(layer_id, 0x30), j) & smask for j in range(N)]
         comp = lambda Mx, rows: [sum(Mx[i][j] * chi[j] for j in range(N)) % R128 for i in range(rows)]
         Uc = comp(U, K)
         Dc = comp(D, M)
@@ -89,7 +95,7 @@ def online_and_check(compact: bool, M, K, N, seed, layer_id, delta, S, f: int = 
         cs = 0
         for i in range(rows):
             for j in range(cols):
-                c = draw(seed, stream(layer_id, purpose), i * cols + j)
+                c = draw(seed, stream(layer_id, purpose), i * cols + j) & smask
                 cs += tWp[i][j] * c - delta[p] * (W[i][j] * c)
         return cs % R128
 
@@ -105,7 +111,7 @@ def online_and_check(compact: bool, M, K, N, seed, layer_id, delta, S, f: int = 
         else:
             s = 0
             for i in range(M):
-                ch = draw(seed, stream(layer_id, 0x31), i)
+                ch = draw(seed, stream(layer_id, 0x31), i) & smask
                 s += (delta[p] * out["Dc"][i]) * ch - out["tDc"][p][i] * ch
             cs[2][p] = s % R128
     out["cs"] = cs

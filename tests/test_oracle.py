@@ -432,3 +432,113 @@ def test_truncation_bruteforce(built, compact):
     for p in range(2):
         assert ints(L["Zf"][p]).reshape(M, N).tolist() == out["Zf"][p]
         assert ints(L["tZf"][p]).reshape(M, N).tolist() == out["tZf"][p]
+
+
+# ---------------------------------------------------------------- k = s = 32 (shares in Z_{2^64})
+
+R64 = 1 << 64
+M32 = (1 << 32) - 1
+
+
+def lift64(L, name):
+    return (ints(L[name][0]) + ints(L[name][1])) % R64
+
+
+def test_k32_key_shares_and_dealer(built):
+    """Key shares are the key draws mod 2^32; every dealt object's shares sum to
+    its lift recomputed from the generator (inputs mod 2^32, masks mod 2^64)
+    and its tag shares to Delta~ times the lift, mod 2^64."""
+    d = O.key_shares(7, 32)
+    for p in range(2):
+        assert int(d[p]) == ref.draw(7, ref.stream(0xFFFF, 0x40 + p), 0) & M32
+    M, K, N, seed, lid = 3, 4, 5, 23, 6
+    L = O.OracleLayer(M, K, N, seed, lid, 7, kbits=32).deal()
+    ds = dsum(L)
+    assert ds < 1 << 33
+    d64 = lambda purpose, e: ref.draw(seed, ref.stream(lid, purpose), e)
+    X = np.array([[d64(1, i * K + k) & M32 for k in range(K)] for i in range(M)], dtype=object)
+    A = np.array([[d64(3, 2 * (i * K + k)) for k in range(K)] for i in range(M)], dtype=object)
+    Y = np.array([[d64(2, k * N + j) & M32 for j in range(N)] for k in range(K)], dtype=object)
+    B = np.array([[d64(4, 2 * (k * N + j)) for j in range(N)] for k in range(K)], dtype=object)
+    assert np.array_equal(lift64(L, "X"), X) and np.array_equal(lift64(L, "A"), A)
+    assert np.array_equal(lift64(L, "Y"), Y) and np.array_equal(lift64(L, "B"), B)
+    C = np.array([[sum(A[i, k] * B[k, j] for k in range(K)) % R64 for j in range(N)] for i in range(M)],
+                 dtype=object)
+    assert np.array_equal(lift64(L, "C"), C)
+    for n in ("X", "A", "Y", "B", "C", "R"):
+        assert np.array_equal(lift64(L, "t" + n), (ds * lift64(L, n)) % R64), n
+        assert not L[n][1][..., 1].any()   # upper limb stays zero
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("mode", [O.MODE_SPDZ2K, O.MODE_COMPACT])
+def test_k32_plain_definitions(built, shape, mode):
+    M, K, N = shape
+    L = O.run_layer(mode, M, K, N, seed=31, layer_id=4, key_seed=9, kbits=32)
+    X, Y = lift64(L, "X"), lift64(L, "Y")
+    Z = lift64(L, "Z")
+    assert np.array_equal(Z, omatmul(X, Y) % R64)
+    # Z mod 2^32 is the wrapping uint32 product of the inputs
+    z32 = (X.astype(np.uint64).astype(np.uint32).astype(np.uint64) @
+           Y.astype(np.uint64).astype(np.uint32).astype(np.uint64)) & np.uint64(M32)
+    assert np.array_equal((Z % (1 << 32)).astype(np.uint64), z32)
+    assert np.array_equal(lift64(L, "tZ"), (dsum(L) * Z) % R64)
+    assert L.accept()
+
+
+@pytest.mark.parametrize("shape", SHAPES[:5])
+def test_k32_cross_mode_identity(built, shape):
+    """Per party, the compact tag equals the SPDZ2k tag compressed by chi (mod 2^64)."""
+    M, K, N = shape
+    Ls = O.run_layer(O.MODE_SPDZ2K, M, K, N, seed=12, layer_id=2, key_seed=3, kbits=32)
+    Lc = O.run_layer(O.MODE_COMPACT, M, K, N, seed=12, layer_id=2, key_seed=3, kbits=32)
+    chi = [ref.draw(12, ref.stream(2, 0x30), j) & M32 for j in range(N)]
+    for p in range(2):
+        tz = ints(Ls["tZ"][p]).reshape(M, N)
+        want = [sum(int(tz[i, j]) * chi[j] for j in range(N)) % R64 for i in range(M)]
+        assert ints(Lc["tZc"][p]).tolist() == want
+        assert np.array_equal(Ls["Z"][p], Lc["Z"][p])
+
+
+@pytest.mark.parametrize("mode", [O.MODE_SPDZ2K, O.MODE_COMPACT])
+@pytest.mark.parametrize("target,bit", [("X", 0), ("tA", 31), ("Y", 17), ("tB", 5), ("C", 20), ("tR", 31)])
+def test_k32_single_flipped_share_bit_aborts(built, mode, target, bit):
+    L = O.OracleLayer(4, 5, 6, 61, 8, 2, kbits=32).deal()
+    L[target][1][1, 2, 0] ^= np.uint64(1 << bit)
+    L.online(mode).check(mode)
+    assert not L.accept()
+
+
+@pytest.mark.parametrize("compact", [False, True])
+def test_k32_bruteforce(built, compact):
+    M, K, N = 3, 4, 5
+    mode = O.MODE_COMPACT if compact else O.MODE_SPDZ2K
+    L = O.run_layer(mode, M, K, N, seed=45, layer_id=7, key_seed=8, f=9, kbits=32)
+    names = ("X", "tX", "A", "tA", "Y", "tY", "B", "tB", "C", "tC", "R", "tR", "Rf", "tRf")
+    S = {n: [ints(L[n][p]).reshape(L[n][p].shape[:-1]).tolist() for p in range(2)] for n in names}
+    delta = [int(L.delta[0]), int(L.delta[1])]
+    out = ref.online_and_check(compact, M, K, N, 45, 7, delta, S, f=9, kbits=32)
+    for p in range(2):
+        assert ints(L["Z"][p]).reshape(M, N).tolist() == out["Z"][p]
+        assert ints(L["tZ"][p]).reshape(M, N).tolist() == out["tZ"][p]
+        assert ints(L["Zf"][p]).reshape(M, N).tolist() == out["Zf"][p]
+    for w in range(3):
+        for p in range(2):
+            assert O.u128(L.cs[w, p]) == out["cs"][w][p], (w, p)
+
+
+@pytest.mark.parametrize("f", [4, 10])
+def test_k32_truncation_accuracy(built, f):
+    M, K, N = 12, 20, 7
+    L = O.run_layer(O.MODE_COMPACT, M, K, N, seed=5, layer_id=13, key_seed=2, f=f, in_bits=8, kbits=32)
+    sg = lambda v: (int(v) % (1 << 32)) - (1 << 32) * ((int(v) % (1 << 32)) >= 1 << 31)
+    X = [[sg(v) for v in row] for row in lift64(L, "X").tolist()]
+    Y = [[sg(v) for v in row] for row in lift64(L, "Y").tolist()]
+    R_k = lift64(L, "R") % (1 << 32)
+    Zf = lift64(L, "Zf") % (1 << 32)
+    assert np.array_equal(lift64(L, "tZf"), (dsum(L) * lift64(L, "Zf")) % R64)
+    for i in range(M):
+        for j in range(N):
+            z = sum(X[i][k] * Y[k][j] for k in range(K))
+            if 0 <= int(R_k[i, j]) - z < 1 << 32:
+                assert (int(Zf[i, j]) - (z >> f)) % (1 << 32) in (0, 1)
