@@ -37,7 +37,7 @@ INT8_PEAK_TOPS = 5000.0      # MI355X dense int8 MFMA, 5.0 POP/s
 DIGIT_PAIRS = 136            # int8 digit products per 128-bit ring multiply-accumulate
 
 
-def stage_work(stage: str, specs, mode: str, f: int = 0):
+def stage_work(stage: str, specs, mode: str, f: int = 0, kbits: int = 64):
     """Algorithmic work of one launch of a kernel stage over the layer batch:
     ("hbm", bytes) or ("mfma", int8 ops), for the fused step
     (online phase + verification).  16 B per Z_2^128 element; per element:
@@ -55,7 +55,11 @@ def stage_work(stage: str, specs, mode: str, f: int = 0):
       post       M x N: CompactTag reads R_p, Z_p, tR_p, tC_p (8), writes D,
                  tZ_p (3): 176 B; SPDZ2k reads R_p, Z_p, tR_p, tZ_p (8),
                  writes D: 144 B; with f > 0 also reads R^f_p, tR^f_p and
-                 writes Z^f_p, tZ^f_p: + 128 B."""
+                 writes Z^f_p, tZ^f_p: + 128 B.
+    With k = s = 32 elements are 8 B (every byte figure halves) and a ring
+    MAC is 36 digit products."""
+    scale = 1 if kbits == 64 else 0.5
+    pairs = DIGIT_PAIRS if kbits == 64 else 36
     spdz = mode == "spdz2k"
     tot = 0
     for s in specs:
@@ -71,12 +75,14 @@ def stage_work(stage: str, specs, mode: str, f: int = 0):
         elif stage == "copy_base":
             tot += (32 * mn * (4 if spdz else 2)) if wide else 0
         elif stage == "ring_gemm":
-            tot += 2 * DIGIT_PAIRS * (8 if spdz else 4) * M * K * N if wide else 0
+            tot += 2 * pairs * (8 if spdz else 4) * M * K * N if wide else 0
         elif stage == "post":
             tot += ((144 if spdz else 176) + (128 if f > 0 else 0)) * mn
         else:
             return None
-    return ("mfma" if stage == "ring_gemm" else "hbm", tot)
+    if stage == "ring_gemm":
+        return ("mfma", tot)
+    return ("hbm", int(tot * scale))
 
 
 # Sources that determine what the device kernels do; the hardware counters in
@@ -153,7 +159,7 @@ def run_steps(ctx, mode_id, layer_groups, out_dev, steps, warmup, torch, timing=
     return t1 - t0, per, stages
 
 
-def cpu_baseline(specs, min_seconds: float = 10.0):
+def cpu_baseline(specs, min_seconds: float = 10.0, kbits: int = 64):
     """The oracle (single-threaded C, -O2) on a bounded sample of the workload:
     every layer with M * K * N below 2^28 in full, and the first 2048 rows of
     any larger one (at most six layers); online phase + verification in the
@@ -173,7 +179,7 @@ def cpu_baseline(specs, min_seconds: float = 10.0):
     t_tot, macs, passes = 0.0, 0, 0
     while passes == 0 or t_tot < min_seconds:
         for s, r0, r1 in parts:
-            L = O.OracleLayer(s.M, s.K, s.N, s.seed, s.layer_id, KEY_SEED, r0, r1).deal()
+            L = O.OracleLayer(s.M, s.K, s.N, s.seed, s.layer_id, KEY_SEED, r0, r1, kbits=kbits).deal()
             t0 = time.perf_counter()
             L.online(O.MODE_COMPACT).check(O.MODE_COMPACT)
             t_tot += time.perf_counter() - t0
@@ -257,7 +263,9 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=1000.0,
                     help="offered rate (req/s) of the serving leg of a layer-batch run")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
-    ap.add_argument("--f", type=int, default=0, help="truncate every product by f fractional bits (0..63)")
+    ap.add_argument("--f", type=int, default=0, help="truncate every product by f fractional bits (0..k-1)")
+    ap.add_argument("--kbits", type=int, default=64, choices=[64, 32],
+                    help="parameter set k = s: 64 (shares in Z_2^128) or 32 (shares in Z_2^64)")
     ap.add_argument("--in-bits", type=int, default=0, help="dealer inputs as signed in-bits-bit integers (0: uniform)")
     ap.add_argument("--mode", default="compact", choices=["compact", "spdz2k"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -282,9 +290,8 @@ def main():
         return serving_main(args, torch)
     specs = workloads.CONFIGS[args.config]()
     mode_id = MODE_COMPACT if args.mode == "compact" else MODE_SPDZ2K
-    ctx = Context(device=0, key_seed=workloads.KEY_SEED, max_layers=max(256, len(specs)))
-    layers = [Layer(s.M, s.K, s.N, s.seed, s.layer_id, device="cuda:0", f=args.f, in_bits=args.in_bits)
-              for s in specs]
+    ctx = Context(device=0, key_seed=workloads.KEY_SEED, max_layers=max(256, len(specs)), kbits=args.kbits)
+    layers = [ctx.layer(s.M, s.K, s.N, s.seed, s.layer_id, f=args.f, in_bits=args.in_bits) for s in specs]
     print(f"[bench] config {args.config}: {len(specs)} layers, dealer ...", file=sys.stderr, flush=True)
     ctx.gen_triple_tags(layers)
     torch.cuda.synchronize()
@@ -325,7 +332,7 @@ def main():
     stage_rows = {}
     for name, (tot_ms, n) in stages.items():
         avg = tot_ms / max(n, 1)
-        w = stage_work(name, specs, args.mode, args.f)
+        w = stage_work(name, specs, args.mode, args.f, args.kbits)
         row = {"ms_per_launch": round(avg, 5), "launches": n, "share_of_step": round(tot_ms / args.steps / ms, 4)}
         if w is not None and w[1] > 0:
             bound, units = w
@@ -347,18 +354,21 @@ def main():
         else:
             roofline = {"kernel": k, "bound": "mfma", "achieved": v["achieved_TOPS"], "peak": INT8_PEAK_TOPS,
                         "unit": "TOPS (int8)", "frac": v["frac"]}
-        roofline["traffic"] = measured_traffic(k, f"{args.config}/{args.mode}" + (f"/f{args.f}" if args.f else ""))
+        roofline["traffic"] = measured_traffic(k, f"{args.config}/{args.mode}" + (f"/f{args.f}" if args.f else "")
+                                               + ("/k32" if args.kbits == 32 else ""))
         roofline["share_of_step"] = v["share_of_step"]
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "G ring-MAC/s (Z_2^64 GEMM Gops, 1 op = 1 MAC)",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
         "p50_ms": round(pct(per, 50), 4), "p99_ms": round(pct(per, 99), 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u128",
-        "data": "synthetic",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u128" if args.kbits == 64 else "u64", "data": "synthetic",
         "config": {"workload": f"{args.config}: " + ", ".join(f"{s.name} ({s.M}x{s.K}x{s.N})" for s in specs)
                    if len(specs) <= 8 else f"{args.config}: {len(specs)} layers, sum MKN {mkn}",
-                   "protocol": args.mode, "parties": 2, "ring": "values Z_2^64, shares and tags Z_2^128",
+                   "protocol": args.mode, "parties": 2,
+                   "ring": ("values Z_2^64, shares and tags Z_2^128" if args.kbits == 64 else
+                            "values Z_2^32, shares and tags Z_2^64"),
                    "layers_per_call": len(specs), "sum_MKN": mkn, "f": args.f, "in_bits": args.in_bits},
         "roofline": roofline,
         "eager": {"value": round(mkn * args.steps / Te / 1e9, 3), "ms_per_step": round(Te / args.steps * 1e3, 4),
@@ -389,7 +399,7 @@ def main():
                                  "p50_ms": round(pct(per4, 50), 4), "p99_ms": round(pct(per4, 99), 4)}
     plan.close()
     del plan
-    if not args.no_serve:
+    if not args.no_serve and args.kbits == 64:  # the server runs the k = s = 64 set
         print(f"[bench] serving leg at {args.serve_rate:g} req/s ...", file=sys.stderr, flush=True)
         del layers
         torch.cuda.empty_cache()
@@ -397,7 +407,7 @@ def main():
                                      SERVE_ARENA, SERVE_SLOTS, SERVE_BATCH)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        cb = cpu_baseline(specs)
+        cb = cpu_baseline(specs, kbits=args.kbits)
         out["cpu_baseline"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in cb.items()}
     ctx.close()
     print(json.dumps(out), flush=True)

@@ -21,7 +21,7 @@
  *     stream) and is asynchronous unless stated otherwise.  A context is
  *     single-stream and not thread-safe; several contexts may coexist.
  *   - Errors are returned as ct_status; nothing is thrown across the ABI.
- *     CT_EINVAL: a null or misaligned pointer, M, K or N < 1, k or s not 64,
+ *     CT_EINVAL: a null or misaligned pointer, M, K or N < 1, (k, s) not (64, 64) or (32, 32),
  *     f or in_bits outside [0, 63], n < 1 or more layers than the context
  *     was sized for.
  *     CT_EDEVICE: a HIP error (text in ct_last_error).  CT_ABORT is not a
@@ -54,7 +54,10 @@ typedef struct ct_ctx ct_ctx;
 typedef struct {
     int device;           /* HIP device ordinal */
     uint64_t key_seed;    /* seeds the key shares [Delta]_0, [Delta]_1 */
-    int k_bits, s_bits;   /* must both be 64 */
+    int k_bits, s_bits;   /* the parameter set of Sec. 4.1: k = s = 64 (values in Z_{2^64}, shares,
+                             tags and check values in Z_{2^128}, 16-byte elements) or k = s = 32
+                             (values in Z_{2^32}, shares and tags in Z_{2^64}, 8-byte elements
+                             uint64_t, key shares and combiners in Z_{2^32}) */
     void *hip_stream;     /* hipStream_t the context enqueues on; NULL = null stream */
     int max_layers;       /* largest n accepted by one call; <= 0 means 256 */
 } ct_params;
@@ -74,7 +77,10 @@ typedef struct {
     uint64_t layer_id;    /* < 2^48; names the layer's generator streams */
 } ct_layer_desc;
 
-/* Per-layer device buffers.  [v]_p / [t v]_p are party p's value / tag share. */
+/* Per-layer device buffers.  [v]_p / [t v]_p are party p's value / tag share.
+ * Every element is one element of Z_{2^{k+s}}: a ct_u128 for k = s = 64, a
+ * uint64_t (the pointer still typed ct_u128 *) for k = s = 32.  Element
+ * counts (CT_WORK_LEN, CT_CVEC_LEN) are the same for both. */
 typedef struct {
     ct_u128 *X[2], *tX[2], *A[2], *tA[2];                   /* M x K */
     ct_u128 *Y[2], *tY[2], *B[2], *tB[2];                   /* K x N */
@@ -198,7 +204,10 @@ ct_status ct_stage_times(ct_ctx *ctx, ct_stage_time *out, int max, int *count);
 /* Launch configuration of the matrix-core products. */
 typedef struct {
     int32_t group_m;       /* output row tiles per group of the tile order (>= 1) */
-    int32_t xcd_remap;     /* 1: each XCD gets a contiguous range of the tile list */
+    int32_t xcd_remap;     /* 0: tiles in list order (blocks go round-robin over the 8 XCDs);
+                              1: each XCD gets a contiguous range of the list; G >= 2: groups of
+                              G consecutive tiles go round-robin over the XCDs, so the tiles of a
+                              group share one XCD's L2 */
     int32_t split_target;  /* K slices of 32 per tile; 0 = as many tiles as fill the GPU twice */
     int32_t reserved;
     double gemm_ms;        /* ct_autotune: measured duration of the products per call */
@@ -206,7 +215,7 @@ typedef struct {
 
 /* Autotuner: runs the online phase of this batch of layers (outputs written
  * as by ct_tag_linear) once per candidate launch configuration (group_m in
- * 1, 2, 4, 8, 16, 64; XCD remap off and on; split_target 0, 16, 32, 64, 128),
+ * 1, 2, 4, 8, 16, 64; xcd_remap 0, 1, 4, 8, 16; split_target 0, 16, 32, 64, 128),
  * times the matrix-core products with HIP events (reps timed runs after one
  * warm-up each), and keeps the fastest for this shape class -- the protocol
  * and the rounded-up binary logarithms of M, K, N of every matrix-core

@@ -3,8 +3,9 @@
 Every step of the hot path runs in the HIP library; this module only builds
 the C structures of ``include/compacttag.h`` from torch tensors and forwards
 the calls.  Device memory and the stream come from PyTorch (ROCm build): each
-ring matrix is a ``torch.int64`` tensor of shape ``[rows, cols, 2]`` holding
-the (lo, hi) limbs of Z_{2^128} elements.
+ring matrix is a ``torch.int64`` tensor of shape ``[rows, cols, limbs]``
+holding the little-endian 64-bit limbs of its elements -- two for Z_{2^128}
+(k = s = 64), one for Z_{2^64} (k = s = 32).
 
 There is no CPU fallback: if the library is not built or no GPU is visible,
 ``load()`` raises.
@@ -173,31 +174,33 @@ def _result(r: CtCheckResult) -> CheckResult:
 
 
 class Layer:
-    """Device buffers of one linear layer (both parties), as torch tensors."""
+    """Device buffers of one linear layer (both parties), as torch tensors of
+    `limbs` 64-bit words per element (2: k = s = 64; 1: k = s = 32)."""
 
     def __init__(self, M: int, K: int, N: int, seed: int, layer_id: int, device="cuda:0", f: int = 0,
-                 in_bits: int = 0):
+                 in_bits: int = 0, limbs: int = 2):
         self.M, self.K, self.N, self.seed, self.layer_id, self.f = M, K, N, seed, layer_id, f
-        self.in_bits = in_bits
+        self.in_bits, self.limbs = in_bits, limbs
         self.t = {}
         dims = {"MK": (M, K), "KN": (K, N), "MN": (M, N)}
         groups = {"MK": ["X", "tX", "A", "tA"], "KN": ["Y", "tY", "B", "tB"],
                   "MN": ["C", "tC", "R", "tR", "Z", "tZ"] + (BUF_TRUNC if f > 0 else [])}
+        w = limbs
         for g, names in groups.items():
             for n in names:
-                self.t[n] = [torch.zeros(dims[g] + (2,), dtype=torch.int64, device=device) for _ in range(2)]
-        self.t["E"] = torch.zeros((M, K, 2), dtype=torch.int64, device=device)
-        self.t["U"] = torch.zeros((K, N, 2), dtype=torch.int64, device=device)
-        self.t["D"] = torch.zeros((M, N, 2), dtype=torch.int64, device=device)
-        self.t["cvec"] = torch.zeros((3 * K + 10 * M, 2), dtype=torch.int64, device=device)
-        self.t["work"] = torch.zeros((max(1, work_len(M, K, N)), 2), dtype=torch.int64, device=device)
+                self.t[n] = [torch.zeros(dims[g] + (w,), dtype=torch.int64, device=device) for _ in range(2)]
+        self.t["E"] = torch.zeros((M, K, w), dtype=torch.int64, device=device)
+        self.t["U"] = torch.zeros((K, N, w), dtype=torch.int64, device=device)
+        self.t["D"] = torch.zeros((M, N, w), dtype=torch.int64, device=device)
+        self.t["cvec"] = torch.zeros((3 * K + 10 * M, w), dtype=torch.int64, device=device)
+        self.t["work"] = torch.zeros((max(1, work_len(M, K, N)), w), dtype=torch.int64, device=device)
 
     @classmethod
     def wrap(cls, M: int, K: int, N: int, seed: int, layer_id: int, tensors: dict) -> "Layer":
         """A Layer over existing device tensors (no allocation)."""
         obj = cls.__new__(cls)
         obj.M, obj.K, obj.N, obj.seed, obj.layer_id, obj.f = M, K, N, seed, layer_id, 0
-        obj.in_bits = 0
+        obj.in_bits, obj.limbs = 0, 2
         obj.t = dict(tensors)
         return obj
 
@@ -242,8 +245,11 @@ def _arrays(layers):
 class Context:
     """A libcompacttag context bound to one device and one HIP stream."""
 
-    def __init__(self, device: int = 0, key_seed: int = 0, stream=None, max_layers: int = 256):
+    def __init__(self, device: int = 0, key_seed: int = 0, stream=None, max_layers: int = 256, kbits: int = 64):
+        """kbits = k = s: 64 (shares and tags in Z_{2^128}) or 32 (in Z_{2^64})."""
         self.lib = load()
+        self.kbits = kbits
+        self.limbs = 2 if kbits == 64 else 1
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: libcompacttag needs an MI355X (there is no CPU fallback)")
         self.device = device
@@ -252,7 +258,7 @@ class Context:
             stream = torch.cuda.current_stream(self.torch_device)
         self.stream = stream
         handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
-        p = CtParams(device, key_seed & MASK64, 64, 64, handle, max_layers)
+        p = CtParams(device, key_seed & MASK64, kbits, kbits, handle, max_layers)
         h = ctypes.c_void_p()
         s = self.lib.ct_create(ctypes.byref(h), ctypes.byref(p))
         if s != CT_OK:
@@ -335,6 +341,10 @@ class Context:
         cnt = ctypes.c_int()
         self._check(self.lib.ct_stage_times(self.h, buf, 32, ctypes.byref(cnt)))
         return {buf[i].name.decode(): (buf[i].total_ms, int(buf[i].launches)) for i in range(min(cnt.value, 32))}
+
+    def layer(self, M: int, K: int, N: int, seed: int, layer_id: int, f: int = 0, in_bits: int = 0) -> Layer:
+        """Buffers of one layer for this context's parameter set."""
+        return Layer(M, K, N, seed, layer_id, device=self.torch_device, f=f, in_bits=in_bits, limbs=self.limbs)
 
     def plan(self, mode: int, layers, out: torch.Tensor | None = None) -> "Plan":
         """Captures the online phase of this layer batch (with the fused

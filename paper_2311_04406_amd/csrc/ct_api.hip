@@ -339,7 +339,7 @@ int plan_gemms(std::vector<GemmProb> &probs, int num_cus, const GemmTuning &tu, 
 
 ct_status run_gemms(ct_ctx *c, Lane &ln, int nprobs, int total_tiles, const GemmTuning &tu) {
     if (nprobs > 0)
-        LAUNCH(c, ln, ST_RING_GEMM, launch_gemm(ln.gemm_dev, nprobs, total_tiles, tu.xcd_remap, ln.stream));
+        LAUNCH(c, ln, ST_RING_GEMM, launch_gemm(c->eb, ln.gemm_dev, nprobs, total_tiles, tu.xcd_remap, ln.stream));
     return CT_OK;
 }
 
@@ -400,10 +400,15 @@ extern "C" {
 ct_status ct_create(ct_ctx **out, const ct_params *p) {
     if (!out || !p) return CT_EINVAL;
     *out = nullptr;
-    if (p->k_bits != 64 || p->s_bits != 64) return CT_EINVAL;
+    if (!((p->k_bits == 64 && p->s_bits == 64) || (p->k_bits == 32 && p->s_bits == 32))) return CT_EINVAL;
     ct_ctx *c = new ct_ctx();
     c->device = p->device;
-    for (int q = 0; q < 2; q++) c->delta[q] = hdraw(hkey(p->key_seed, GLOBAL_LAYER, P_KEY + q), 0);
+    c->eb = p->k_bits == 32 ? 8 : 16;
+    // F_MAC Initialize: [Delta]_p uniform in Z_{2^s} (the key draw mod 2^s)
+    for (int q = 0; q < 2; q++) {
+        const uint64_t x = hdraw(hkey(p->key_seed, GLOBAL_LAYER, P_KEY + q), 0);
+        c->delta[q] = p->s_bits == 32 ? (x & 0xFFFFFFFFull) : x;
+    }
     hipError_t e;
     if ((e = hipSetDevice(c->device)) == hipSuccess) {
         int cus = 0;
@@ -476,20 +481,20 @@ ct_status ct::run_deal(ct_ctx *c, Lane &ln, const ct_layer_desc *L, const ct_lay
     std::copy(probs.begin(), probs.end(), ln.gemm_host);
     if ((s = upload(c, ln, n, nm, njobs, nskinny)) != CT_OK) return s;
     const Sizes sz = max_sizes(L, n);
-    LAUNCH(c, ln, ST_DEAL_LIFT, launch_deal_lift(ln.layers_dev, n, std::max(sz.mk, sz.kn), ln.stream));
-    LAUNCH(c, ln, ST_PACK, launch_pack(ln.pack_dev, njobs, pack_tiles, ln.stream));
+    LAUNCH(c, ln, ST_DEAL_LIFT, launch_deal_lift(c->eb, ln.layers_dev, n, std::max(sz.mk, sz.kn), ln.stream));
+    LAUNCH(c, ln, ST_PACK, launch_pack(c->eb, ln.pack_dev, njobs, pack_tiles, ln.stream));
     for (int i = 0; i < nm; i++)
         if (probs[i].accumulate)
-            LAUNCH(c, ln, ST_FILL_ZERO, launch_fill_zero(probs[i].out, (int64_t)probs[i].M * probs[i].N, ln.stream));
+            LAUNCH(c, ln, ST_FILL_ZERO, launch_fill_zero(c->eb, probs[i].out, (int64_t)probs[i].M * probs[i].N, ln.stream));
     if ((s = run_gemms(c, ln, nm, total_tiles, tu)) != CT_OK) return s;
     if (nskinny > 0) {
         int max_rows = 0;
         for (int i = 0; i < nskinny; i++) max_rows = std::max(max_rows, ln.skinny_host[i].M);
-        LAUNCH(c, ln, ST_DEAL_SKINNY, launch_skinny(ln.skinny_dev, nskinny, max_rows, ln.stream));
+        LAUNCH(c, ln, ST_DEAL_SKINNY, launch_skinny(c->eb, ln.skinny_dev, nskinny, max_rows, ln.stream));
     }
     const int mask = (with_inputs ? ((1 << OBJ_X) | (1 << OBJ_Y)) : 0) | (1 << OBJ_A) | (1 << OBJ_B) |
                      (1 << OBJ_C) | (1 << OBJ_R) | (1 << OBJ_RF);
-    LAUNCH(c, ln, ST_DEAL_AUTH, launch_deal_auth(ln.layers_dev, n, mask, std::max({sz.mk, sz.kn, sz.mn}), ln.stream));
+    LAUNCH(c, ln, ST_DEAL_AUTH, launch_deal_auth(c->eb, ln.layers_dev, n, mask, std::max({sz.mk, sz.kn, sz.mn}), ln.stream));
     return CT_OK;
 }
 
@@ -588,17 +593,17 @@ ct_status prepare_online(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc 
 ct_status enqueue_online(ct_ctx *c, Lane &ln, const OnlineLaunch &P) {
     const int n = P.n;
     if (P.zero_what)
-        LAUNCH(c, ln, ST_ZERO_ACC, launch_zero_acc(ln.layers_dev, n, P.zero_what, P.max_zero, ln.stream));
-    LAUNCH(c, ln, ST_OPEN_U, launch_open_u(ln.layers_dev, n, P.flags, P.max_kn_items, ln.stream));
-    LAUNCH(c, ln, ST_ROW_PASS, launch_row_pass(ln.layers_dev, n, P.flags, P.max_row_items, P.variants, ln.stream));
-    if (P.njobs > 0) LAUNCH(c, ln, ST_PACK, launch_pack(ln.pack_dev, P.njobs, P.pack_tiles, ln.stream));
+        LAUNCH(c, ln, ST_ZERO_ACC, launch_zero_acc(c->eb, ln.layers_dev, n, P.zero_what, P.max_zero, ln.stream));
+    LAUNCH(c, ln, ST_OPEN_U, launch_open_u(c->eb, ln.layers_dev, n, P.flags, P.max_kn_items, ln.stream));
+    LAUNCH(c, ln, ST_ROW_PASS, launch_row_pass(c->eb, ln.layers_dev, n, P.flags, P.max_row_items, P.variants, ln.stream));
+    if (P.njobs > 0) LAUNCH(c, ln, ST_PACK, launch_pack(c->eb, ln.pack_dev, P.njobs, P.pack_tiles, ln.stream));
     if (P.any_accum)
-        LAUNCH(c, ln, ST_COPY_BASE, launch_copy_base(ln.layers_dev, n, P.mode, P.max_mn, ln.stream));
+        LAUNCH(c, ln, ST_COPY_BASE, launch_copy_base(c->eb, ln.layers_dev, n, P.mode, P.max_mn, ln.stream));
     ct_status s = run_gemms(c, ln, P.nm, P.total_tiles, P.tu);
     if (s != CT_OK) return s;
-    LAUNCH(c, ln, ST_POST, launch_post(ln.layers_dev, n, P.flags, P.max_mn_items, ln.stream));
-    if (P.compact) LAUNCH(c, ln, ST_COMPACT_FINAL, launch_compact_final(ln.layers_dev, n, P.flags, ln.stream));
-    if (P.check) LAUNCH(c, ln, ST_FINALIZE, launch_finalize(ln.layers_dev, n, P.out_dev, ln.stream));
+    LAUNCH(c, ln, ST_POST, launch_post(c->eb, ln.layers_dev, n, P.flags, P.max_mn_items, ln.stream));
+    if (P.compact) LAUNCH(c, ln, ST_COMPACT_FINAL, launch_compact_final(c->eb, ln.layers_dev, n, P.flags, ln.stream));
+    if (P.check) LAUNCH(c, ln, ST_FINALIZE, launch_finalize(c->eb, ln.layers_dev, n, P.out_dev, ln.stream));
     return CT_OK;
 }
 
@@ -621,12 +626,12 @@ ct_status run_check(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc *L, c
     if ((s = stage_layers(c, ln, L, B, n)) != CT_OK) return s;
     if ((s = upload(c, ln, n, 0)) != CT_OK) return s;
     const Sizes sz = max_sizes(L, n);
-    LAUNCH(c, ln, ST_ZERO_ACC, launch_zero_acc(ln.layers_dev, n, 2, 0, ln.stream));
+    LAUNCH(c, ln, ST_ZERO_ACC, launch_zero_acc(c->eb, ln.layers_dev, n, 2, 0, ln.stream));
     const int mask = compact ? 0x3 : 0x7;
     LAUNCH(c, ln, ST_CHECK_BATCH,
-           launch_check_batch(ln.layers_dev, n, mask, std::max({sz.mk, sz.kn, sz.mn}), ln.stream));
-    if (compact) LAUNCH(c, ln, ST_CHECK_COMPACT, launch_check_compact(ln.layers_dev, n, ln.stream));
-    LAUNCH(c, ln, ST_FINALIZE, launch_finalize(ln.layers_dev, n, out_dev, ln.stream));
+           launch_check_batch(c->eb, ln.layers_dev, n, mask, std::max({sz.mk, sz.kn, sz.mn}), ln.stream));
+    if (compact) LAUNCH(c, ln, ST_CHECK_COMPACT, launch_check_compact(c->eb, ln.layers_dev, n, ln.stream));
+    LAUNCH(c, ln, ST_FINALIZE, launch_finalize(c->eb, ln.layers_dev, n, out_dev, ln.stream));
     return CT_OK;
 }
 
@@ -748,9 +753,10 @@ ct_status ct_set_timing(ct_ctx *c, int enable) {
 
 ct_status ct_set_tuning(ct_ctx *c, const ct_tuning *t) {
     if (!c || !t) return CT_EINVAL;
-    if (t->group_m < 1 || t->split_target < 0 || t->split_target > MAX_STEPS_PER_SPLIT)
+    if (t->group_m < 1 || t->split_target < 0 || t->split_target > MAX_STEPS_PER_SPLIT || t->xcd_remap < 0 ||
+        t->xcd_remap > 4096)
         return fail(c, CT_EINVAL, "invalid tuning");
-    c->fallback = GemmTuning{t->group_m, t->xcd_remap ? 1 : 0, t->split_target};
+    c->fallback = GemmTuning{t->group_m, t->xcd_remap, t->split_target};
     c->tuned.clear();
     return CT_OK;
 }
@@ -777,9 +783,10 @@ ct_status ct_autotune(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_
     const int64_t saved_n = c->stage_n[ST_RING_GEMM];
     static const int groups[] = {1, 2, 4, 8, 16, 64};
     static const int splits[] = {0, 16, 32, 64, 128};
+    static const int remaps[] = {0, 1, 4, 8, 16};
     GemmTuning best = c->fallback;
     double best_ms = 1e30;
-    for (int xcd = 0; xcd < 2; xcd++)
+    for (int xcd : remaps)
         for (int g : groups)
             for (int sp : splits) {
                 c->forcing = true;

@@ -92,10 +92,79 @@ __device__ __forceinline__ u128 wave_sum(u128 v) {
     return v;
 }
 
+// ---------------------------------------------------------------- Z_{2^64}
+// The same operations for the k = s = 32 parameter set, whose shares and tags
+// are elements of Z_{2^64}.
+
+__device__ __forceinline__ r64 add(r64 a, r64 b) { return r64{a.v + b.v}; }
+__device__ __forceinline__ r64 sub(r64 a, r64 b) { return r64{a.v - b.v}; }
+__device__ __forceinline__ r64 mul(r64 a, r64 b) { return r64{a.v * b.v}; }
+__device__ __forceinline__ r64 mul64(r64 a, uint64_t b) { return r64{a.v * b}; }
+__device__ __forceinline__ r64 mad64(r64 acc, r64 a, uint64_t b) { return r64{acc.v + a.v * b}; }
+__device__ __forceinline__ r64 mad(r64 acc, r64 a, r64 b) { return r64{acc.v + a.v * b.v}; }
+__device__ __forceinline__ r64 ld(const r64 *p, int64_t i) { return p[i]; }
+__device__ __forceinline__ void st(r64 *p, int64_t i, r64 v) { p[i] = v; }
+__device__ __forceinline__ void atomic_add128(r64 *p, r64 v) {
+    atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v.v);
+}
+__device__ __forceinline__ r64 shfl_xor128(r64 v, int m) { return r64{__shfl_xor(v.v, m, 64)}; }
+__device__ __forceinline__ r64 wave_sum(r64 v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = add(v, shfl_xor128(v, m));
+    return v;
+}
+
+// What depends on the parameter set, for element type R:
+//   zero(), draw(key, e)  -- element e of a uniform stream of Z_{2^{k+s}}
+//                            (for Z_{2^64}: the low half of the 128-bit element),
+//   mod_s(x)              -- a draw as a key share or combiner in Z_{2^s},
+//   mod_k(v)              -- the value v mod 2^k, as an integer,
+//   lift(lo, up)          -- lo + 2^k up (lo < 2^k, up a draw),
+//   input(draw, bits)     -- an input of Z_{2^k} (uniform, or signed bits-bit),
+//   small(x)              -- an integer x < 2^64 as an element,
+//   DIGITS                -- balanced base-256 digits per element.
+template <class R>
+struct Ring;
+
+template <>
+struct Ring<u128> {
+    static constexpr int DIGITS = 16;
+    __device__ static u128 zero() { return u128{0, 0}; }
+    __device__ static u128 draw(uint64_t key, uint64_t e) { return sdraw128(key, e); }
+    __device__ static uint64_t mod_s(uint64_t x) { return x; }
+    __device__ static uint64_t mod_k(u128 v) { return v.lo; }
+    __device__ static u128 lift(uint64_t lo, uint64_t up) { return u128{lo, up}; }
+    __device__ static u128 input(uint64_t draw, int bits) {
+        if (bits <= 0 || bits >= 64) return u128{draw, 0};
+        return u128{(uint64_t)((int64_t)draw >> (64 - bits)), 0};
+    }
+    __device__ static u128 small(uint64_t x) { return u128{x, 0}; }
+    __device__ static bool nonzero(u128 v) { return (v.lo | v.hi) != 0; }
+    __device__ static ct_u128 out(u128 v) { return ct_u128{v.lo, v.hi}; }
+};
+
+template <>
+struct Ring<r64> {
+    static constexpr int DIGITS = 8;
+    __device__ static r64 zero() { return r64{0}; }
+    __device__ static r64 draw(uint64_t key, uint64_t e) { return r64{sdraw(key, 2 * e)}; }
+    __device__ static uint64_t mod_s(uint64_t x) { return x & 0xFFFFFFFFull; }
+    __device__ static uint64_t mod_k(r64 v) { return v.v & 0xFFFFFFFFull; }
+    __device__ static r64 lift(uint64_t lo, uint64_t up) { return r64{lo | (up << 32)}; }
+    __device__ static r64 input(uint64_t draw, int bits) {
+        const uint32_t x = (uint32_t)draw;
+        if (bits <= 0 || bits >= 32) return r64{x};
+        return r64{(uint32_t)((int32_t)x >> (32 - bits))};
+    }
+    __device__ static r64 small(uint64_t x) { return r64{x}; }
+    __device__ static bool nonzero(r64 v) { return v.v != 0; }
+    __device__ static ct_u128 out(r64 v) { return ct_u128{v.v, 0}; }
+};
+
 // Sum of NV values over a block of WAVES wavefronts; the result is valid in
 // thread 0.  `sh` must hold NV * WAVES entries.
-template <int NV, int WAVES>
-__device__ __forceinline__ void block_sum(u128 (&v)[NV], u128 *sh) {
+template <int NV, int WAVES, class R>
+__device__ __forceinline__ void block_sum(R (&v)[NV], R *sh) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i < NV; i++) v[i] = wave_sum(v[i]);
@@ -107,7 +176,7 @@ __device__ __forceinline__ void block_sum(u128 (&v)[NV], u128 *sh) {
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int i = 0; i < NV; i++) {
-            u128 s = sh[i * WAVES];
+            R s = sh[i * WAVES];
 #pragma unroll
             for (int j = 1; j < WAVES; j++) s = add(s, sh[i * WAVES + j]);
             v[i] = s;

@@ -36,10 +36,25 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int BM = 64, BN = 64, BK = 32;
-constexpr int PLANE = BM * BK;       // bytes per digit plane of a 64 x 32 tile
-constexpr int OPBYTES = 16 * PLANE;  // 16 digit planes: 32 KB (= TILE_ELEMS * 16)
-constexpr int STAGE = 2 * OPBYTES;   // A and B tiles of one K slice: 64 KB
-static_assert(OPBYTES == TILE_ELEMS * 16, "tile size");
+constexpr int PLANE = BM * BK;  // bytes per digit plane of a 64 x 32 tile
+
+// Tile geometry per ring: NB digit planes per operand tile (OPB bytes, which
+// is TILE_ELEMS elements), the A and B tiles of one K slice per LDS stage.
+template <class R>
+struct Tile {
+    static constexpr int NB = Ring<R>::DIGITS;
+    static constexpr int NW = NB / 4;            // 32-bit words of digits per element
+    static constexpr int OPB = NB * PLANE;       // 32 KB (Z_{2^128}) or 16 KB (Z_{2^64})
+    static constexpr int STAGE = 2 * OPB;
+    static_assert(OPB == TILE_ELEMS * (int)sizeof(R), "tile size");
+};
+
+__device__ __forceinline__ void to_digits(r64 x, uint32_t (&w)[2]) {
+    const uint64_t K = 0x8080808080808080ull;
+    const uint64_t v = (x.v + K) ^ K;
+    w[0] = (uint32_t)v;
+    w[1] = (uint32_t)(v >> 32);
+}
 
 __device__ __forceinline__ void to_digits(u128 x, uint32_t (&w)[4]) {
     const uint64_t K = 0x8080808080808080ull;
@@ -62,11 +77,12 @@ __device__ __forceinline__ int plane_off(int j, int k) {
     return j * BK + ((chunk ^ half_swap(j)) << 4) + (k & 15);
 }
 
-// Transposes the digits of 8 consecutive-k elements into 16 planes of 8 bytes
-// and writes them at base + d * PLANE + off.
-__device__ __forceinline__ void write_planes(uint8_t *base, int off, const uint32_t (&w)[8][4]) {
+// Transposes the digits of 8 consecutive-k elements into 4 NW planes of 8
+// bytes and writes them at base + d * PLANE + off.
+template <int NW>
+__device__ __forceinline__ void write_planes(uint8_t *base, int off, const uint32_t (&w)[8][NW]) {
 #pragma unroll
-    for (int q = 0; q < 4; q++) {  // dword q holds digits 4q .. 4q+3
+    for (int q = 0; q < NW; q++) {  // dword q holds digits 4q .. 4q+3
         uint32_t y[2][4];
 #pragma unroll
         for (int h = 0; h < 2; h++) {  // elements 4h .. 4h+3
@@ -94,7 +110,9 @@ __device__ __forceinline__ void write_planes(uint8_t *base, int off, const uint3
 // each (a row segment of a left operand, a column segment of a right one),
 // write their digit planes to LDS, and the tile is stored with 16-byte
 // coalesced writes.
+template <class R>
 __global__ __launch_bounds__(256) void k_pack(const PackJob *__restrict__ jobs, int njobs, int total_tiles) {
+    constexpr int OPBYTES = Tile<R>::OPB, NW = Tile<R>::NW;
     __shared__ __attribute__((aligned(16))) uint8_t tile[OPBYTES];
     const int tid = threadIdx.x;
     for (int t = blockIdx.x; t < total_tiles; t += gridDim.x) {
@@ -110,21 +128,22 @@ __global__ __launch_bounds__(256) void k_pack(const PackJob *__restrict__ jobs, 
         if (J.side == 0) { j = tid >> 2; kk = (tid & 3) * 8; }
         else { j = tid & 63; kk = (tid >> 6) * 8; }
         const int major = tm * 64 + j;
-        uint32_t w[8][4];
+        const R *src = reinterpret_cast<const R *>(J.src);
+        uint32_t w[8][NW];
 #pragma unroll
         for (int i = 0; i < 8; i++) {
             const int k = ks * 32 + kk + i;
-            u128 v = zero128();
+            R v = Ring<R>::zero();
             if (J.side == 0) {
-                if (major < J.rows && k < J.cols) v = ld(J.src, (int64_t)major * J.cols + k);
+                if (major < J.rows && k < J.cols) v = ld(src, (int64_t)major * J.cols + k);
             } else {
-                if (k < J.rows && major < J.cols) v = ld(J.src, (int64_t)k * J.cols + major);
+                if (k < J.rows && major < J.cols) v = ld(src, (int64_t)k * J.cols + major);
             }
             to_digits(v, w[i]);
         }
-        write_planes(tile, plane_off(j, kk), w);
+        write_planes<NW>(tile, plane_off(j, kk), w);
         __syncthreads();
-        uint4 *dst = reinterpret_cast<uint4 *>(J.dst + ((int64_t)tm * J.kt + ks) * TILE_ELEMS);
+        uint4 *dst = reinterpret_cast<uint4 *>(reinterpret_cast<R *>(J.dst) + ((int64_t)tm * J.kt + ks) * TILE_ELEMS);
 #pragma unroll
         for (int i = 0; i < OPBYTES / 16 / 256; i++)
             dst[i * 256 + tid] = reinterpret_cast<const uint4 *>(tile)[i * 256 + tid];
@@ -132,10 +151,11 @@ __global__ __launch_bounds__(256) void k_pack(const PackJob *__restrict__ jobs, 
     }
 }
 
-hipError_t launch_pack(const PackJob *jobs_dev, int njobs, int total_tiles, hipStream_t st) {
+hipError_t launch_pack(int eb, const PackJob *jobs_dev, int njobs, int total_tiles, hipStream_t st) {
     if (njobs <= 0 || total_tiles <= 0) return hipSuccess;
     int grid = total_tiles < 65536 ? total_tiles : 65536;
-    hipLaunchKernelGGL(k_pack, dim3(grid), dim3(256), 0, st, jobs_dev, njobs, total_tiles);
+    if (eb == 8) hipLaunchKernelGGL(k_pack<r64>, dim3(grid), dim3(256), 0, st, jobs_dev, njobs, total_tiles);
+    else hipLaunchKernelGGL(k_pack<u128>, dim3(grid), dim3(256), 0, st, jobs_dev, njobs, total_tiles);
     return hipGetLastError();
 }
 
@@ -161,6 +181,14 @@ __device__ __forceinline__ void combine(const v16i (&acc)[16], int r, u128 &v) {
         combine<T + 1>(acc, r, v);
     }
 }
+// Z_{2^64}: sum_{t<8} 2^{8t} S_t mod 2^64
+template <int T>
+__device__ __forceinline__ void combine(const v16i (&acc)[8], int r, r64 &v) {
+    if constexpr (T < 8) {
+        v.v += (uint64_t)(int64_t)acc[T][r] << (8 * T);
+        combine<T + 1>(acc, r, v);
+    }
+}
 
 typedef __attribute__((address_space(3))) void lds_void;
 
@@ -171,39 +199,42 @@ __device__ __forceinline__ const uint8_t *uniform_ptr(const uint8_t *p) {
     return reinterpret_cast<const uint8_t *>(((uint64_t)hi << 32) | lo);
 }
 
-// Copies the A and B digit tiles of one K slice into an LDS stage: 64 chunks
-// of 1 KB, 16 per wavefront, each a single global_load_lds_dwordx4 (lane l
-// moves bytes [16 l, 16 l + 16) of its chunk).  Wavefronts 0, 1 copy the A
+// Copies the A and B digit tiles of one K slice into an LDS stage: chunks of
+// 1 KB, OPB / 2 KB per wavefront, each a single global_load_lds_dwordx4 (lane
+// l moves bytes [16 l, 16 l + 16) of its chunk).  Wavefronts 0, 1 copy the A
 // tile, 2, 3 the B tile; the tile base is made wavefront-uniform so each copy
 // addresses memory as scalar base + 32-bit lane offset (no 64-bit address
 // registers to keep live across the products).
+template <class R>
 __device__ __forceinline__ void issue_slice(const uint8_t *a_tile, const uint8_t *b_tile, uint8_t *stage) {
+    constexpr int CH = Tile<R>::OPB / 2048;  // chunks per wavefront
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint8_t *base = uniform_ptr(wave < 2 ? a_tile : b_tile);
-    const uint32_t first = (uint32_t)(wave & 1) * 16 * 1024;  // byte offset of the wave's 16 chunks in the tile
+    const uint32_t first = (uint32_t)(wave & 1) * CH * 1024;  // byte offset of the wave's chunks in the tile
 #pragma unroll
-    for (int i = 0; i < 16; i++) {
+    for (int i = 0; i < CH; i++) {
         const uint32_t off = first + (uint32_t)i * 1024;
         __builtin_amdgcn_global_load_lds((const void *)(base + off + lane * 16),
-                                         (lds_void *)(stage + wave * 16 * 1024 + off - first), 16, 0, 0);
+                                         (lds_void *)(stage + wave * CH * 1024 + off - first), 16, 0, 0);
     }
 }
 
-// The 136 digit products of one K slice from an LDS stage, fragments read in
-// triangular order.
-__device__ __forceinline__ void slice_products(const uint8_t *stage, int a_frag, int b_frag, v16i (&acc)[16]) {
-    v4i a[16], b[16];
+// The NB (NB + 1) / 2 digit products of one K slice from an LDS stage (136
+// for Z_{2^128}, 36 for Z_{2^64}), fragments read in triangular order.
+template <int NB>
+__device__ __forceinline__ void slice_products(const uint8_t *stage, int a_frag, int b_frag, v16i (&acc)[NB]) {
+    v4i a[NB], b[NB];
 #pragma unroll
-    for (int t = 0; t < 16; t++) {
+    for (int t = 0; t < NB; t++) {
         a[t] = *reinterpret_cast<const v4i *>(stage + t * PLANE + a_frag);
-        b[t] = *reinterpret_cast<const v4i *>(stage + OPBYTES + t * PLANE + b_frag);
-        // pairs (t, j) and (i, t) with i, j <= t and i + j <= 15 become available
+        b[t] = *reinterpret_cast<const v4i *>(stage + NB * PLANE + t * PLANE + b_frag);
+        // pairs (t, j) and (i, t) with i, j <= t and i + j < NB become available
 #pragma unroll
-        for (int j = 0; j <= t && t + j <= 15; j++)
+        for (int j = 0; j <= t && t + j < NB; j++)
             acc[t + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[t], b[j], acc[t + j], 0, 0, 0);
 #pragma unroll
-        for (int i = 0; i < t && i + t <= 15; i++)
+        for (int i = 0; i < t && i + t < NB; i++)
             acc[i + t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[t], acc[i + t], 0, 0, 0);
     }
 }
@@ -211,7 +242,9 @@ __device__ __forceinline__ void slice_products(const uint8_t *stage, int a_frag,
 // vmcnt(0), expcnt and lgkmcnt left unconstrained (gfx9 s_waitcnt encoding)
 #define WAIT_VMEM() __builtin_amdgcn_s_waitcnt(0x0F70)
 
+template <class R>
 __device__ __forceinline__ void gemm_tile(const GemmProb &P, int tm, int tn, int split, uint8_t *lds) {
+    constexpr int NB = Tile<R>::NB, STAGE = Tile<R>::STAGE;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int M = P.M, N = P.N;
@@ -219,18 +252,18 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &P, int tm, int tn, int
     const int s_begin = split * P.steps_per_split;
     const int s_end = min(s_begin + P.steps_per_split, P.nsteps);
 
-    v16i acc[16];
+    v16i acc[NB];
 #pragma unroll
-    for (int t = 0; t < 16; t++) acc[t] = v16i{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int t = 0; t < NB; t++) acc[t] = v16i{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 
     auto a_tile = [&](int step) {
         const int seg = step >= P.kt ? 1 : 0;
-        const u128 *Lp = seg ? P.Lp2 : P.Lp1;
+        const R *Lp = reinterpret_cast<const R *>(seg ? P.Lp2 : P.Lp1);
         return reinterpret_cast<const uint8_t *>(Lp + ((int64_t)tm * P.kt + (step - seg * P.kt)) * TILE_ELEMS);
     };
     auto b_tile = [&](int step) {
         const int seg = step >= P.kt ? 1 : 0;
-        const u128 *Rp = seg ? P.Rp2 : P.Rp1;
+        const R *Rp = reinterpret_cast<const R *>(seg ? P.Rp2 : P.Rp1);
         return reinterpret_cast<const uint8_t *>(Rp + ((int64_t)tn * P.kt + (step - seg * P.kt)) * TILE_ELEMS);
     };
 
@@ -241,13 +274,13 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &P, int tm, int tn, int
     const int a_frag = arow * BK + ((chunk ^ half_swap(arow)) << 4);
     const int b_frag = brow * BK + ((chunk ^ half_swap(brow)) << 4);
 
-    if (s_begin < s_end) issue_slice(a_tile(s_begin), b_tile(s_begin), lds);
+    if (s_begin < s_end) issue_slice<R>(a_tile(s_begin), b_tile(s_begin), lds);
     WAIT_VMEM();
     __syncthreads();
     for (int s = s_begin; s < s_end; s++) {
         const int buf = (s - s_begin) & 1;
-        if (s + 1 < s_end) issue_slice(a_tile(s + 1), b_tile(s + 1), lds + (buf ^ 1) * STAGE);
-        slice_products(lds + buf * STAGE, a_frag, b_frag, acc);
+        if (s + 1 < s_end) issue_slice<R>(a_tile(s + 1), b_tile(s + 1), lds + (buf ^ 1) * STAGE);
+        slice_products<NB>(lds + buf * STAGE, a_frag, b_frag, acc);
         WAIT_VMEM();
         __syncthreads();
     }
@@ -258,15 +291,16 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &P, int tm, int tn, int
 #pragma unroll
     for (int r = 0; r < 16; r++) {
         const int row = m0 + wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        u128 v = zero128();
+        R v = Ring<R>::zero();
         combine<0>(acc, r, v);
         if (row < M && col < N) {
             const int64_t idx = (int64_t)row * N + col;
+            R *out = reinterpret_cast<R *>(P.out);
             if (P.accumulate) {
-                atomic_add128(P.out + idx, v);
+                atomic_add128(out + idx, v);
             } else {
-                if (P.base) v = add(v, ld(P.base, idx));
-                st(P.out, idx, v);
+                if (P.base) v = add(v, ld(reinterpret_cast<const R *>(P.base), idx));
+                st(out, idx, v);
             }
         }
     }
@@ -282,17 +316,30 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &P, int tm, int tn, int
 // same right-operand tile (all row tiles and both parties' products use U)
 // and the same left-operand tiles (E is shared by all products) in the same
 // K slice at about the same time.
-__device__ __forceinline__ int xcd_tile(int b, int total) {
-    const int q = total >> 3, r = total & 7;
+// xcd_remap = 1: XCD x takes the x-th of 8 contiguous ranges of the list.
+// xcd_remap = G >= 2: the list is cut into groups of G consecutive tiles and
+// group g goes to XCD g % 8, whose blocks take their groups in order -- the
+// G tiles of a group (e.g. the row tiles and products that share one right-
+// operand tile) run on one XCD at about the same time and share its L2, and
+// every XCD still works across the whole list.  The tail that does not fill
+// 8 groups keeps the identity order.  Both are bijections on [0, total).
+__device__ __forceinline__ int xcd_tile(int b, int total, int mode) {
     const int x = b & 7, i = b >> 3;
-    return x * q + (x < r ? x : r) + i;
+    if (mode == 1) {
+        const int q = total >> 3, r = total & 7;
+        return x * q + (x < r ? x : r) + i;
+    }
+    const int full = total / (8 * mode) * (8 * mode);
+    if (b >= full) return b;
+    return ((i / mode) * 8 + x) * mode + i % mode;
 }
 
+template <class R>
 __global__ __launch_bounds__(256, 1) void k_ring_gemm(const GemmProb *__restrict__ probs, int nprobs,
                                                       int total_tiles, int xcd_remap) {
-    __shared__ __attribute__((aligned(1024))) uint8_t lds[2 * STAGE];
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[2 * Tile<R>::STAGE];
     for (int b = blockIdx.x; b < total_tiles; b += gridDim.x) {
-        const int t = xcd_remap ? xcd_tile(b, total_tiles) : b;
+        const int t = xcd_remap ? xcd_tile(b, total_tiles, xcd_remap) : b;
         int lo = 0, hi = nprobs - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -312,13 +359,19 @@ __global__ __launch_bounds__(256, 1) void k_ring_gemm(const GemmProb *__restrict
         const int pidx = r3 / gme;
         const int tm = tmg * gm + (r3 - pidx * gme);
         const GemmProb P = probs[G.gfirst + pidx];
-        gemm_tile(P, tm, tn, split, lds);
+        gemm_tile<R>(P, tm, tn, split, lds);
     }
 }
 
-hipError_t launch_gemm(const GemmProb *probs_dev, int nprobs, int total_tiles, int xcd_remap, hipStream_t st) {
+hipError_t launch_gemm(int eb, const GemmProb *probs_dev, int nprobs, int total_tiles, int xcd_remap,
+                       hipStream_t st) {
     if (nprobs <= 0 || total_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ring_gemm, dim3(total_tiles), dim3(256), 0, st, probs_dev, nprobs, total_tiles, xcd_remap);
+    if (eb == 8)
+        hipLaunchKernelGGL(k_ring_gemm<r64>, dim3(total_tiles), dim3(256), 0, st, probs_dev, nprobs, total_tiles,
+                           xcd_remap);
+    else
+        hipLaunchKernelGGL(k_ring_gemm<u128>, dim3(total_tiles), dim3(256), 0, st, probs_dev, nprobs, total_tiles,
+                           xcd_remap);
     return hipGetLastError();
 }
 
@@ -329,37 +382,41 @@ hipError_t launch_gemm(const GemmProb *probs_dev, int nprobs, int total_tiles, i
 // K with coalesced 16-byte loads, 128-bit VALU multiply-adds, a wavefront
 // reduction per column.  (The online phase forms these products inside its
 // pass over E.)
+template <class R>
 __global__ __launch_bounds__(256) void k_skinny(const SkinnyProb *__restrict__ probs, int nprobs) {
     const SkinnyProb P = probs[blockIdx.y];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int N = P.N, K = P.K;
+    const R *Lm = reinterpret_cast<const R *>(P.L), *Rm = reinterpret_cast<const R *>(P.R);
+    R *out = reinterpret_cast<R *>(P.out);
     for (int m = blockIdx.x * 4 + wave; m < P.M; m += gridDim.x * 4) {
-        u128 acc[SKINNY_MAX_N];
+        R acc[SKINNY_MAX_N];
 #pragma unroll
-        for (int n = 0; n < SKINNY_MAX_N; n++) acc[n] = zero128();
-        const u128 *row = P.L + (int64_t)m * K;
+        for (int n = 0; n < SKINNY_MAX_N; n++) acc[n] = Ring<R>::zero();
+        const R *row = Lm + (int64_t)m * K;
         for (int k = lane; k < K; k += 64) {
-            const u128 a = ld(row, k);
+            const R a = ld(row, k);
 #pragma unroll
             for (int n = 0; n < SKINNY_MAX_N; n++)
-                if (n < N) acc[n] = mad(acc[n], a, ld(P.R, (int64_t)k * N + n));
+                if (n < N) acc[n] = mad(acc[n], a, ld(Rm, (int64_t)k * N + n));
         }
 #pragma unroll
         for (int n = 0; n < SKINNY_MAX_N; n++) {
             if (n < N) {
-                const u128 v = wave_sum(acc[n]);
-                if (lane == 0) st(P.out, (int64_t)m * N + n, v);
+                const R v = wave_sum(acc[n]);
+                if (lane == 0) st(out, (int64_t)m * N + n, v);
             }
         }
     }
 }
 
-hipError_t launch_skinny(const SkinnyProb *probs_dev, int nprobs, int max_rows, hipStream_t st) {
+hipError_t launch_skinny(int eb, const SkinnyProb *probs_dev, int nprobs, int max_rows, hipStream_t st) {
     if (nprobs <= 0) return hipSuccess;
     int gx = (max_rows + 3) / 4;
     if (gx > 4096) gx = 4096;
     if (gx < 1) gx = 1;
-    hipLaunchKernelGGL(k_skinny, dim3(gx, nprobs), dim3(256), 0, st, probs_dev, nprobs);
+    if (eb == 8) hipLaunchKernelGGL(k_skinny<r64>, dim3(gx, nprobs), dim3(256), 0, st, probs_dev, nprobs);
+    else hipLaunchKernelGGL(k_skinny<u128>, dim3(gx, nprobs), dim3(256), 0, st, probs_dev, nprobs);
     return hipGetLastError();
 }
 

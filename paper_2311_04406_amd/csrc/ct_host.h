@@ -48,6 +48,7 @@ enum Stage : int {
 
 struct ct_ctx {
     int device = 0;
+    int eb = 16;  // bytes per ring element: 16 (k = s = 64, Z_{2^128}) or 8 (k = s = 32, Z_{2^64})
     uint64_t delta[2] = {0, 0};
     int num_cus = 256;
     ct::Lane main;

@@ -13,6 +13,10 @@ namespace ct {
 struct u128 {
     uint64_t lo, hi;
 };
+// An element of Z_{2^64}: shares and tags of the k = s = 32 parameter set.
+struct r64 {
+    uint64_t v;
+};
 
 // Generator stream purposes; stream = (layer_id << 16) | purpose.
 enum Purpose : uint32_t {
@@ -95,8 +99,9 @@ __host__ __device__ inline CvecOff cvec_off(int64_t M, int64_t K) {
 // tiles": for an operand with major dimension D (rows of a left operand,
 // columns of a right operand) and contraction length K, tile (t, ks) covers
 // major indices [64 t, 64 t + 64) and k in [32 ks, 32 ks + 32); it occupies
-// TILE_ELEMS elements (32 KB) at ((t * KT) + ks) * TILE_ELEMS and holds 16
-// planes of signed 8-bit digits (plane d = digit d) of 64 x 32 bytes, in the
+// TILE_ELEMS elements at ((t * KT) + ks) * TILE_ELEMS and holds one plane of
+// signed 8-bit digits per digit of an element (plane d = digit d; 16 planes,
+// 32 KB, for Z_{2^128}; 8 planes, 16 KB, for Z_{2^64}) of 64 x 32 bytes, in the
 // byte order of the GEMM's LDS stage.  Out-of-range entries are zero.
 constexpr int TILE_ELEMS = 2048;
 inline int64_t packed_elems(int64_t major, int64_t K) { return ((major + 63) / 64) * ((K + 31) / 32) * TILE_ELEMS; }
@@ -152,7 +157,7 @@ struct GemmProb {
 // Launch configuration of the matrix-core products (chosen by ct_autotune).
 struct GemmTuning {
     int32_t group_m;       // row tiles per group of the tile order (1 = row-major order)
-    int32_t xcd_remap;     // give each XCD a contiguous range of the tile list
+    int32_t xcd_remap;     // 0: identity; 1: contiguous range per XCD; G >= 2: groups of G tiles per XCD
     int32_t split_target;  // K slices per tile; 0 = enough tiles for two rounds over the CUs
 };
 
@@ -165,23 +170,24 @@ struct SkinnyProb {
 };
 
 // ---- launchers (defined in the .hip files) ----
-hipError_t launch_pack(const PackJob *jobs_dev, int njobs, int total_tiles, hipStream_t st);
-hipError_t launch_gemm(const GemmProb *probs_dev, int nprobs, int total_tiles, int xcd_remap, hipStream_t st);
-hipError_t launch_skinny(const SkinnyProb *probs_dev, int nprobs, int max_rows, hipStream_t st);
+// eb: bytes per ring element, 16 (k = s = 64) or 8 (k = s = 32).
+hipError_t launch_pack(int eb, const PackJob *jobs_dev, int njobs, int total_tiles, hipStream_t st);
+hipError_t launch_gemm(int eb, const GemmProb *probs_dev, int nprobs, int total_tiles, int xcd_remap, hipStream_t st);
+hipError_t launch_skinny(int eb, const SkinnyProb *probs_dev, int nprobs, int max_rows, hipStream_t st);
 
-hipError_t launch_fill_zero(u128 *p, int64_t n, hipStream_t st);
-hipError_t launch_deal_lift(const LayerDev *L, int n, int64_t max_elems, hipStream_t st);
-hipError_t launch_deal_auth(const LayerDev *L, int n, int obj, int64_t max_elems, hipStream_t st);
-hipError_t launch_zero_acc(const LayerDev *L, int n, int what, int64_t max_elems, hipStream_t st);
-hipError_t launch_copy_base(const LayerDev *L, int n, int mode, int64_t max_elems, hipStream_t st);
-hipError_t launch_open_u(const LayerDev *L, int n, int flags, int64_t max_items, hipStream_t st);
+hipError_t launch_fill_zero(int eb, u128 *p, int64_t n, hipStream_t st);
+hipError_t launch_deal_lift(int eb, const LayerDev *L, int n, int64_t max_elems, hipStream_t st);
+hipError_t launch_deal_auth(int eb, const LayerDev *L, int n, int obj, int64_t max_elems, hipStream_t st);
+hipError_t launch_zero_acc(int eb, const LayerDev *L, int n, int what, int64_t max_elems, hipStream_t st);
+hipError_t launch_copy_base(int eb, const LayerDev *L, int n, int mode, int64_t max_elems, hipStream_t st);
+hipError_t launch_open_u(int eb, const LayerDev *L, int n, int flags, int64_t max_items, hipStream_t st);
 // variants: bit v set if some layer takes row-pass variant v (0, 1, 2, 4, 8)
-hipError_t launch_row_pass(const LayerDev *L, int n, int flags, int64_t max_items, int variants, hipStream_t st);
-hipError_t launch_post(const LayerDev *L, int n, int flags, int64_t max_items, hipStream_t st);
-hipError_t launch_compact_final(const LayerDev *L, int n, int flags, hipStream_t st);
-hipError_t launch_check_batch(const LayerDev *L, int n, int which, int64_t max_elems, hipStream_t st);
-hipError_t launch_check_compact(const LayerDev *L, int n, hipStream_t st);
-hipError_t launch_finalize(const LayerDev *L, int n, ct_check_result *out, hipStream_t st);
+hipError_t launch_row_pass(int eb, const LayerDev *L, int n, int flags, int64_t max_items, int variants, hipStream_t st);
+hipError_t launch_post(int eb, const LayerDev *L, int n, int flags, int64_t max_items, hipStream_t st);
+hipError_t launch_compact_final(int eb, const LayerDev *L, int n, int flags, hipStream_t st);
+hipError_t launch_check_batch(int eb, const LayerDev *L, int n, int which, int64_t max_elems, hipStream_t st);
+hipError_t launch_check_compact(int eb, const LayerDev *L, int n, hipStream_t st);
+hipError_t launch_finalize(int eb, const LayerDev *L, int n, ct_check_result *out, hipStream_t st);
 
 // Number of wavefront work items of a row sweep over an R x N matrix (the
 // grid of the sweeping kernels is sized from it).

@@ -92,9 +92,10 @@ int main(void) {
 def test_validation_before_device_calls(lib):
     from paper_2311_04406_amd import binding as b
     h = ctypes.c_void_p()
-    # k, s other than 64 are rejected before the device is touched
-    p = b.CtParams(0, 1, 32, 32, None, 4)
-    assert lib.ct_create(ctypes.byref(h), ctypes.byref(p)) == b.CT_EINVAL
+    # parameter sets other than k = s = 64 and k = s = 32 are rejected before the device is touched
+    for kb, sb in ((32, 64), (64, 32), (16, 16), (48, 48)):
+        p = b.CtParams(0, 1, kb, sb, None, 4)
+        assert lib.ct_create(ctypes.byref(h), ctypes.byref(p)) == b.CT_EINVAL
     assert lib.ct_create(None, ctypes.byref(p)) == b.CT_EINVAL
     assert lib.ct_destroy(None) == b.CT_EINVAL
     assert lib.ct_key_shares(None, None) == b.CT_EINVAL

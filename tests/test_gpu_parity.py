@@ -119,7 +119,8 @@ def test_launch_configurations_give_identical_results(ctx, mode):
     ctx.gen_triple_tags(layers)
     out = torch.zeros(14 * len(specs), dtype=torch.int64, device="cuda:0")
     ref = None
-    for g, x, sp in [(1, 0, 0), (4, 1, 8), (16, 0, 32), (2, 1, 128), (8, 1, 0), (64, 1, 16)]:
+    for g, x, sp in [(1, 0, 0), (4, 1, 8), (16, 0, 32), (2, 1, 128), (8, 1, 0), (64, 1, 16), (2, 4, 16), (1, 16, 0),
+                     (8, 8, 32), (4, 3, 8)]:
         say(f"[tuning] mode={mode} group_m={g} xcd={x} split={sp}")
         ctx.set_tuning(g, x, sp)
         ctx.tag_linear_check(mode, layers, out)
