@@ -238,6 +238,22 @@ ct_status upload(ct_ctx *c, Lane &ln, int n, int nprobs, int njobs = 0, int nski
     return CT_OK;
 }
 
+// Element e of a buffer of the context's ring (eb bytes per element): the
+// tables hold u128 pointers whatever the element width, so offsets are
+// applied in bytes.
+inline u128 *elem_at(u128 *base, int64_t e, int eb) {
+    return reinterpret_cast<u128 *>(reinterpret_cast<char *>(base) + e * (int64_t)eb);
+}
+
+// Host-side bound check of a layer's workspace use: every packed operand
+// (tiles * TILE_ELEMS elements from dst) must end inside the caller's
+// CT_WORK_LEN(M, K, N) elements.
+bool job_in_work(const PackJob &j, const u128 *work, const ct_layer_desc &d, int eb) {
+    const char *b = reinterpret_cast<const char *>(work);
+    const char *e = reinterpret_cast<const char *>(j.dst) + (int64_t)j.tiles * TILE_ELEMS * eb;
+    return reinterpret_cast<const char *>(j.dst) >= b && e <= b + (int64_t)CT_WORK_LEN(d.M, d.K, d.N) * eb;
+}
+
 GemmProb make_prob(const u128 *Lp1, const u128 *Lp2, const u128 *Rp1, const u128 *Rp2, const u128 *base, u128 *out,
                    const ct_layer_desc &d) {
     GemmProb p;
@@ -469,9 +485,12 @@ ct_status ct::run_deal(ct_ctx *c, Lane &ln, const ct_layer_desc *L, const ct_lay
             continue;
         }
         const WorkOff w = work_off(d.M, d.K, d.N);
-        ln.pack_host[njobs++] = make_job(o.A[1], o.work + w.Ep, d.M, d.K, 0);
-        ln.pack_host[njobs++] = make_job(o.B[1], o.work + w.B0p, d.K, d.N, 1);
-        probs.push_back(make_prob(o.work + w.Ep, nullptr, o.work + w.B0p, nullptr, nullptr, o.C[1], d));
+        u128 *Ep = elem_at(o.work, w.Ep, c->eb), *B0p = elem_at(o.work, w.B0p, c->eb);
+        ln.pack_host[njobs++] = make_job(o.A[1], Ep, d.M, d.K, 0);
+        ln.pack_host[njobs++] = make_job(o.B[1], B0p, d.K, d.N, 1);
+        if (!job_in_work(ln.pack_host[njobs - 2], o.work, d, c->eb) || !job_in_work(ln.pack_host[njobs - 1], o.work, d, c->eb))
+            return fail(c, CT_EINVAL, "internal error: workspace layout exceeds CT_WORK_LEN");
+        probs.push_back(make_prob(Ep, nullptr, B0p, nullptr, nullptr, o.C[1], d));
     }
     const int pack_tiles = plan_jobs(ln.pack_host, njobs);
     int total_tiles = 0;
@@ -539,25 +558,30 @@ ct_status prepare_online(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc 
         const LayerDev &o = ln.layers_host[l];
         const WorkOff w = work_off(d.M, d.K, d.N);
         u128 *W = o.work;
+        auto wp = [&](int64_t e) { return elem_at(W, e, c->eb); };
+        const int first_job = njobs;
         PackJob *J = ln.pack_host;
-        J[njobs++] = make_job(o.E, W + w.Ep, d.M, d.K, 0);
-        J[njobs++] = make_job(W + w.AE0, W + w.AE0p, d.M, d.K, 0);
-        J[njobs++] = make_job(o.A[1], W + w.A1p, d.M, d.K, 0);
-        J[njobs++] = make_job(o.B[0], W + w.B0p, d.K, d.N, 1);
-        J[njobs++] = make_job(o.B[1], W + w.B1p, d.K, d.N, 1);
-        J[njobs++] = make_job(o.U, W + w.Up, d.K, d.N, 1);
+        J[njobs++] = make_job(o.E, wp(w.Ep), d.M, d.K, 0);
+        J[njobs++] = make_job(wp(w.AE0), wp(w.AE0p), d.M, d.K, 0);
+        J[njobs++] = make_job(o.A[1], wp(w.A1p), d.M, d.K, 0);
+        J[njobs++] = make_job(o.B[0], wp(w.B0p), d.K, d.N, 1);
+        J[njobs++] = make_job(o.B[1], wp(w.B1p), d.K, d.N, 1);
+        J[njobs++] = make_job(o.U, wp(w.Up), d.K, d.N, 1);
         const size_t first = probs.size();
-        probs.push_back(make_prob(W + w.Ep, W + w.AE0p, W + w.B0p, W + w.Up, o.C[0], o.Z[0], d));
-        probs.push_back(make_prob(W + w.Ep, W + w.A1p, W + w.B1p, W + w.Up, o.C[1], o.Z[1], d));
+        probs.push_back(make_prob(wp(w.Ep), wp(w.AE0p), wp(w.B0p), wp(w.Up), o.C[0], o.Z[0], d));
+        probs.push_back(make_prob(wp(w.Ep), wp(w.A1p), wp(w.B1p), wp(w.Up), o.C[1], o.Z[1], d));
         if (!compact) {
-            J[njobs++] = make_job(W + w.tAE0, W + w.tAE0p, d.M, d.K, 0);
-            J[njobs++] = make_job(W + w.tAE1, W + w.tAE1p, d.M, d.K, 0);
-            J[njobs++] = make_job(o.tB[0], W + w.tB0p, d.K, d.N, 1);
-            J[njobs++] = make_job(o.tB[1], W + w.tB1p, d.K, d.N, 1);
-            probs.push_back(make_prob(W + w.Ep, W + w.tAE0p, W + w.tB0p, W + w.Up, o.tC[0], o.tZ[0], d));
-            probs.push_back(make_prob(W + w.Ep, W + w.tAE1p, W + w.tB1p, W + w.Up, o.tC[1], o.tZ[1], d));
+            J[njobs++] = make_job(wp(w.tAE0), wp(w.tAE0p), d.M, d.K, 0);
+            J[njobs++] = make_job(wp(w.tAE1), wp(w.tAE1p), d.M, d.K, 0);
+            J[njobs++] = make_job(o.tB[0], wp(w.tB0p), d.K, d.N, 1);
+            J[njobs++] = make_job(o.tB[1], wp(w.tB1p), d.K, d.N, 1);
+            probs.push_back(make_prob(wp(w.Ep), wp(w.tAE0p), wp(w.tB0p), wp(w.Up), o.tC[0], o.tZ[0], d));
+            probs.push_back(make_prob(wp(w.Ep), wp(w.tAE1p), wp(w.tB1p), wp(w.Up), o.tC[1], o.tZ[1], d));
         }
         for (size_t j = first; j < probs.size(); j++) probs[j].gsize = (int32_t)(probs.size() - first);
+        for (int j = first_job; j < njobs; j++)  // every packed operand lies inside the workspace
+            if (!job_in_work(J[j], W, d, c->eb))
+                return fail(c, CT_EINVAL, "internal error: workspace layout exceeds CT_WORK_LEN");
     }
     P = OnlineLaunch();
     P.n = n;
