@@ -259,7 +259,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="cnn", choices=["cnn", "transformer", "batched", "fc_small", "serving"])
+    ap.add_argument("--config", default="cnn",
+                    choices=["cnn", "transformer", "batched", "training", "fc_small", "serving"])
     ap.add_argument("--serve-rate", type=float, default=1000.0,
                     help="offered rate (req/s) of the serving leg of a layer-batch run")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")

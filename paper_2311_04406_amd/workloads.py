@@ -88,6 +88,23 @@ def batched(count: int = 64, seed: int = 4000):
     return out
 
 
+def training(encoders: int = 12):
+    """The products of one encoder training step at sequence 128, hidden 768:
+    for each forward product Z = X W (M x K x N) its backward products
+    dX = dZ W^T (M x N x K) and dW = X^T dZ (K x M x N) -- the same path with
+    the operands' roles exchanged."""
+    per = [("qkv", 128, 768, 2304), ("attn_out", 128, 768, 768), ("ffn1", 128, 768, 3072),
+           ("ffn2", 128, 3072, 768)]
+    out = []
+    lid = 1
+    for e in range(encoders):
+        for n, M, K, N in per:
+            for tag, shape in (("fwd", (M, K, N)), ("dX", (M, N, K)), ("dW", (K, M, N))):
+                out.append(LayerSpec(f"enc{e}.{n}.{tag}", *shape, 1200, lid))
+                lid += 1
+    return out
+
+
 def serving_shapes():
     """The request shape set: the CNN and the encoder products."""
     return cnn() + transformer(1)
@@ -110,4 +127,5 @@ def request_choices(count: int, nshapes: int, seed: int = 5000):
     return [(_sm_draw(seed, ks, i) & 1, _sm_draw(seed, ss, i) % nshapes) for i in range(count)]
 
 
-CONFIGS = {"fc_small": fc_small, "cnn": cnn, "transformer": transformer, "batched": batched}
+CONFIGS = {"fc_small": fc_small, "cnn": cnn, "transformer": transformer, "batched": batched,
+           "training": training}

@@ -90,6 +90,22 @@ def test_transformer_config(ctx, mode):
     free()
 
 
+@pytest.mark.parametrize("mode", [O.MODE_SPDZ2K, O.MODE_COMPACT])
+def test_training_products(ctx, mode):
+    """One encoder's forward and backward products (dX = dZ W^T, dW = X^T dZ
+    shapes) in one call: sampled rows of every layer against the oracle."""
+    specs = W.training(1)
+    say(f"[fullsize] training products mode={mode} ({len(specs)} layers)")
+    layers, status, res = run_config(ctx, mode, specs)
+    assert status == 0 and all(r.accept for r in res)
+    for s, gl, r in zip(specs, layers, res):
+        rr = (s.M // 3, s.M // 3 + 2)
+        ol = oracle_run(mode, s, KEY, *rr)
+        compare_layer(gl, ol, mode, *rr, what=f"{s.name} rows {rr}")
+        compare_cs(r, ol, which=(1,), what=s.name)
+    free()
+
+
 def test_batched_config_and_alone_vs_mix(ctx):
     """64 layers of uneven shapes in one call; a layer's outputs and check
     values are the same alone as in the mix (tolerance 0: integer results)."""
