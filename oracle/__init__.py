@@ -45,7 +45,7 @@ class _Desc(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int64), ("K", ctypes.c_int64), ("N", ctypes.c_int64),
                 ("seed", ctypes.c_uint64), ("layer_id", ctypes.c_uint64),
                 ("r0", ctypes.c_int64), ("r1", ctypes.c_int64), ("f", ctypes.c_int64), ("in_bits", ctypes.c_int64),
-                ("kbits", ctypes.c_int64)]
+                ("kbits", ctypes.c_int64), ("compress", ctypes.c_int64)]
 
 
 _P2 = ctypes.c_void_p * 2
@@ -55,6 +55,7 @@ _BUF_FIELDS = [
     ("C", 2), ("tC", 2), ("R", 2), ("tR", 2), ("Z", 2), ("tZ", 2), ("D", 1),
     ("Uc", 1), ("tBc", 2),
     ("Dc", 1), ("EUc", 1), ("tCc", 2), ("tRc", 2), ("tZc", 2), ("tDc", 2),
+    ("Ec", 1), ("tAc", 2),
     ("Rf", 2), ("tRf", 2), ("Zf", 2), ("tZf", 2),
 ]
 
@@ -88,6 +89,7 @@ def lib():
         L.or_check.argtypes = [ctypes.c_int, ctypes.POINTER(_Desc), vp, ctypes.POINTER(_Bufs)]
         L.or_matmul.argtypes = [i64, i64, i64, vp, vp, vp]
         L.or_compress.argtypes = [i64, i64, vp, vp, vp]
+        L.or_compress_rows.argtypes = [i64, i64, vp, vp, vp]
         L.or_batchrec_cs.argtypes = [i64, vp, vp, vp, u64, vp]
         L.or_compact_cs.argtypes = [i64, vp, vp, vp, u64, vp]
         _lib = L
@@ -175,6 +177,7 @@ class OracleLayer:
     f: int = 0
     in_bits: int = 0
     kbits: int = 64
+    compress: int = 0                   # 0: along N (columns), 1: along M (rows; all rows)
     arrays: dict = field(default_factory=dict)
     cs: np.ndarray | None = None        # [3 (E,U,D)][2 parties][2 limbs]
     tag_mults: np.ndarray | None = None
@@ -191,15 +194,18 @@ class OracleLayer:
             shapes[n] = (2, K, N)
         for n in ("C", "tC", "R", "tR", "Z", "tZ", "Rf", "tRf", "Zf", "tZf"):
             shapes[n] = (2, rows, N)
-        shapes.update(E=(rows, K), U=(K, N), D=(rows, N), Uc=(K,), tBc=(2, K), Dc=(rows,), EUc=(rows,),
-                      tCc=(2, rows), tRc=(2, rows), tZc=(2, rows), tDc=(2, rows))
+        if self.compress not in (0, 1) or (self.compress == 1 and (self.r0, self.r1) != (0, self.M)):
+            raise ValueError("compress is 0 (along N) or 1 (along M, over all rows)")
+        L = N if self.compress == 1 else rows     # length of the compressed M x N quantities
+        shapes.update(E=(rows, K), U=(K, N), D=(rows, N), Uc=(K,), tBc=(2, K), Dc=(L,), EUc=(L,),
+                      tCc=(2, L), tRc=(2, L), tZc=(2, L), tDc=(2, L), Ec=(K,), tAc=(2, K))
         for n, s in shapes.items():
             self.arrays[n] = np.zeros(s + (2,), dtype=np.uint64)
         self.delta = key_shares(self.key_seed, self.kbits)
 
     def _desc(self):
         return _Desc(self.M, self.K, self.N, self.seed & MASK64, self.layer_id & MASK64, self.r0, self.r1,
-                     self.f, self.in_bits, self.kbits)
+                     self.f, self.in_bits, self.kbits, self.compress)
 
     def _bufs(self):
         b = _Bufs()
@@ -241,10 +247,12 @@ class OracleLayer:
 
 
 def run_layer(mode: int, M: int, K: int, N: int, seed: int, layer_id: int, key_seed: int,
-              r0: int = 0, r1: int | None = None, f: int = 0, in_bits: int = 0, kbits: int = 64) -> OracleLayer:
+              r0: int = 0, r1: int | None = None, f: int = 0, in_bits: int = 0, kbits: int = 64,
+              compress: int = 0) -> OracleLayer:
     """Dealer, online phase and verification of one layer on rows [r0, r1)
-    (with f > 0 the product is truncated by f fractional bits; kbits = k = s)."""
-    L = OracleLayer(M, K, N, seed, layer_id, key_seed, r0, r1, f, in_bits, kbits)
+    (with f > 0 the product is truncated by f fractional bits; kbits = k = s;
+    compress = 1 compresses along M, over all rows)."""
+    L = OracleLayer(M, K, N, seed, layer_id, key_seed, r0, r1, f, in_bits, kbits, compress)
     return L.deal().online(mode).check(mode)
 
 
@@ -264,6 +272,15 @@ def compress(Mx: np.ndarray, chi: np.ndarray) -> np.ndarray:
     out = np.zeros((rows, 2), dtype=np.uint64)
     lib().or_compress(rows, N, _ptr(np.ascontiguousarray(Mx)), _ptr(np.ascontiguousarray(chi, dtype=np.uint64)),
                       _ptr(out))
+    return out
+
+
+def compress_rows(Mx: np.ndarray, chi: np.ndarray) -> np.ndarray:
+    """chi^T Mx: one entry per column of Mx."""
+    rows, N = Mx.shape[:2]
+    out = np.zeros((N, 2), dtype=np.uint64)
+    lib().or_compress_rows(rows, N, _ptr(np.ascontiguousarray(Mx)),
+                           _ptr(np.ascontiguousarray(chi, dtype=np.uint64)), _ptr(out))
     return out
 
 
@@ -289,5 +306,13 @@ def spdz2k_tag_mults(M: int, K: int, N: int) -> int:
     return 3 * M * K * N + M * N
 
 
-def compact_tag_mults(M: int, K: int, N: int) -> int:
+def compact_tag_mults(M: int, K: int, N: int, compress: int = 0) -> int:
+    """compress = 1 (along M) exchanges the roles of M and N."""
+    if compress == 1:
+        return 4 * M * N + 2 * K * M + 3 * N * K + N
     return 4 * M * N + 2 * K * N + 3 * M * K + M
+
+
+def cheaper_compress(M: int, K: int, N: int) -> int:
+    """The compressed dimension with the smaller count: 1 (M) exactly when M > N."""
+    return 1 if compact_tag_mults(M, K, N, 1) < compact_tag_mults(M, K, N, 0) else 0

@@ -142,6 +142,18 @@ void or_compress(int64_t rows, int64_t N, const uint64_t *Mx, const uint64_t *ch
     }
 }
 
+/* Pi_Compress along the other dimension (Sec. 2.2 leaves the compressed
+ * dimension open): M^c = chi^T * M for M (rows x N), chi in Z_{2^s}^{rows x 1};
+ * entry j combines column j of M. */
+void or_compress_rows(int64_t rows, int64_t N, const uint64_t *Mx, const uint64_t *chi, uint64_t *out) {
+    for (int64_t j = 0; j < N; j++) {
+        u128 s = 0;
+        for (int64_t i = 0; i < rows; i++) s += (u128)chi[i] * ld(Mx, i * N + j);
+        g_mults += (uint64_t)rows;
+        st(out, j, s);
+    }
+}
+
 /* Pi_BatchRec tag check (Fig. 1, tag-check steps 2-3), one party's share:
  *   [CS] = [tag W] (.) chi - [Delta]_p * (W (.) chi),  cs_p = sum of all entries of [CS],
  * everything mod 2^{k+s}. */
@@ -275,6 +287,50 @@ static void add_into(int64_t n, uint64_t *acc, const uint64_t *x) {
     for (int64_t e = 0; e < n; e++) st(acc, e, ld(acc, e) + ld(x, e));
 }
 
+/* The compact tag with the compression taken along M instead of N (the
+ * compressed dimension is a free choice, Sec. 2.2; the cost count of
+ * Sec. 3.4.3 with the roles of M and N exchanged is 4MN + 2MK + 3KN + N
+ * multiplications, fewer than 4MN + 2KN + 3MK + M exactly when M > N).
+ * Fig. 7 steps 5-7 with every compression W^c = chi^T W, chi in Z_{2^s}^{M x 1}:
+ * Eq. (5) multiplied by chi^T from the left is
+ *   [tZ^c]_p = [tC^c]_p + E^c [tB]_p + [tA^c]_p U + [Delta]_p (E^c U),
+ *   [tD^c]_p = [tR^c]_p - [tZ^c]_p,
+ * with E^c = chi^T E and [tA^c]_p = chi^T [tA]_p of length K and every other
+ * compressed vector of length N.  The public vectors E^c, D~^c and E^c U are
+ * charged to each party. */
+static void compact_rows(const or_desc *d, const uint64_t delta[2], or_bufs *b, const uint64_t opt[2]) {
+    const int64_t M = d->M, K = d->K, N = d->N;
+    if (d->r0 != 0 || d->r1 != M) abort();
+    uint64_t *chi = (uint64_t *)malloc((size_t)(M > 0 ? M : 1) * 8);
+    uint64_t *v = alloc128(N);
+    if (!chi) abort();
+    draw_chi(d->seed, stream_of(d->layer_id, OR_P_CHI), 0, M, chi);
+    uint64_t m_pub = g_mults;
+    or_compress_rows(M, K, b->E, chi, b->Ec);
+    or_compress_rows(M, N, b->D, chi, b->Dc);
+    or_matmul(1, K, N, b->Ec, b->U, b->EUc);
+    const uint64_t pub_mults = g_mults - m_pub;
+    for (int p = 0; p < 2; p++) {
+        uint64_t m0 = g_mults;
+        or_compress_rows(M, K, b->tA[p], chi, b->tAc[p]);
+        or_compress_rows(M, N, b->tC[p], chi, b->tCc[p]);
+        or_compress_rows(M, N, b->tR[p], chi, b->tRc[p]);
+        memcpy(b->tZc[p], b->tCc[p], (size_t)N * 16);
+        or_matmul(1, K, N, b->Ec, b->tB[p], v);
+        add_into(N, b->tZc[p], v);
+        or_matmul(1, K, N, b->tAc[p], b->U, v);
+        add_into(N, b->tZc[p], v);
+        for (int64_t j = 0; j < N; j++) {
+            st(b->tZc[p], j, ld(b->tZc[p], j) + (u128)delta[p] * ld(b->EUc, j));
+            g_mults++;
+            st(b->tDc[p], j, ld(b->tRc[p], j) - ld(b->tZc[p], j));
+        }
+        b->tag_mults[p] = g_mults - m0 + pub_mults + opt[p];
+    }
+    free(chi);
+    free(v);
+}
+
 void or_online(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) {
     or_set_kbits(d->kbits);
     const int64_t K = d->K, N = d->N, rows = d->r1 - d->r0;
@@ -350,6 +406,12 @@ void or_online(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) 
             opt[p] = g_mults - m0;
         }
 
+        if (d->compress == 1) {
+            compact_rows(d, delta, b, opt);
+            free(EU);
+            free(tmp);
+            return;
+        }
         /* Fig. 7 steps 5-6: public combiners chi in Z_{2^s}^{N x 1}, compress
          * tag(B), tag(C), U, tag(R) and D~ along N.  The public vectors U^c,
          * D~^c and E*U^c are formed by every party, so their cost is charged
@@ -431,9 +493,14 @@ void or_check(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) {
             or_batchrec_cs(rows * N, b->D, tW, chi, delta[p], b->cs[2][p]);
         }
     } else {
-        /* Fig. 7 verification steps 2-5: chihat in Z_{2^s}^{M x 1}. */
-        draw_chi(seed, stream_of(lid, OR_P_CHIHAT), (uint64_t)r0, rows, chi);
-        for (int p = 0; p < 2; p++) or_compact_cs(rows, b->Dc, b->tDc[p], chi, delta[p], b->cs[2][p]);
+        /* Fig. 7 verification steps 2-5: chihat in Z_{2^s}^{L x 1}, L the
+         * length of D~^c (M when compressing along N, N when along M). */
+        const int64_t first = d->compress == 1 ? 0 : r0, len = d->compress == 1 ? N : rows;
+        uint64_t *ch = (uint64_t *)malloc((size_t)(len > 0 ? len : 1) * 8);
+        if (!ch) abort();
+        draw_chi(seed, stream_of(lid, OR_P_CHIHAT), (uint64_t)first, len, ch);
+        for (int p = 0; p < 2; p++) or_compact_cs(len, b->Dc, b->tDc[p], ch, delta[p], b->cs[2][p]);
+        free(ch);
     }
     free(tW);
     free(chi);

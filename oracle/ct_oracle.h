@@ -43,6 +43,8 @@ typedef struct {
     int64_t f;                /* fractional bits truncated from the product (0: no truncation) */
     int64_t in_bits;          /* 0: inputs uniform in Z_{2^k}; 1..k-1: signed in_bits-bit inputs */
     int64_t kbits;            /* k = s: 64 (shares in Z_{2^128}) or 32 (shares in Z_{2^64}); 0 means 64 */
+    int64_t compress;         /* dimension CompactTag compresses: 0 = N (combine the columns),
+                                 1 = M (combine the rows; needs r0 = 0, r1 = M) */
 } or_desc;
 
 /* Every pointer is a caller-owned array of (lo, hi) uint64 pairs. */
@@ -53,10 +55,13 @@ typedef struct {
     uint64_t *Y[2], *tY[2], *B[2], *tB[2], *U;
     /* rows x N */
     uint64_t *C[2], *tC[2], *R[2], *tR[2], *Z[2], *tZ[2], *D;
-    /* compact-tag vectors: K entries */
+    /* compact-tag vectors, compress = 0: K entries */
     uint64_t *Uc, *tBc[2];
-    /* compact-tag vectors: rows entries */
+    /* compact-tag vectors, compress = 0: rows entries (W^c = W chi);
+     * compress = 1: N entries (W^c = chi^T W, and EUc holds E^c U) */
     uint64_t *Dc, *EUc, *tCc[2], *tRc[2], *tZc[2], *tDc[2];
+    /* compact-tag vectors, compress = 1: K entries, E^c = chi^T E and [tA^c]_p = chi^T [tA]_p */
+    uint64_t *Ec, *tAc[2];
     /* f > 0, rows x N: truncated mask R^f (dealt) and truncated output Z^f */
     uint64_t *Rf[2], *tRf[2], *Zf[2], *tZf[2];
     /* check-value shares cs[W][party][limb], W in (E, U, D) */
@@ -82,6 +87,7 @@ void or_check(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b);
 /* building blocks, exposed so tests can feed chosen combiners */
 void or_matmul(int64_t M, int64_t K, int64_t N, const uint64_t *P, const uint64_t *Q, uint64_t *out);
 void or_compress(int64_t rows, int64_t N, const uint64_t *Mx, const uint64_t *chi, uint64_t *out);
+void or_compress_rows(int64_t rows, int64_t N, const uint64_t *Mx, const uint64_t *chi, uint64_t *out);
 void or_batchrec_cs(int64_t n, const uint64_t *W, const uint64_t *tW, const uint64_t *chi,
                     uint64_t delta_p, uint64_t out[2]);
 void or_compact_cs(int64_t rows, const uint64_t *Dc, const uint64_t *tDc, const uint64_t *chihat,

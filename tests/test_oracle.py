@@ -542,3 +542,102 @@ def test_k32_truncation_accuracy(built, f):
             z = sum(X[i][k] * Y[k][j] for k in range(K))
             if 0 <= int(R_k[i, j]) - z < 1 << 32:
                 assert (int(Zf[i, j]) - (z >> f)) % (1 << 32) in (0, 1)
+
+
+# ---------------------------------------------------------------- compression along M
+
+def transposed_layer(L, kbits=64):
+    """The product Z^T = Y^T X^T as a layer of its own (M' = N, K' = K, N' = M)
+    holding L's dealt shares transposed: X' = Y^T, A' = B^T, Y' = X^T, B' = A^T,
+    C' = C^T, R' = R^T, each with its tags, same seed, layer id and key."""
+    T = O.OracleLayer(L.N, L.K, L.M, L.seed, L.layer_id, L.key_seed, kbits=kbits, f=L.f)
+    pairs = {"X": "Y", "tX": "tY", "A": "B", "tA": "tB", "Y": "X", "tY": "tX", "B": "A", "tB": "tA",
+             "C": "C", "tC": "tC", "R": "R", "tR": "tR", "Rf": "Rf", "tRf": "tRf"}
+    for dst, src in pairs.items():
+        for p in range(2):
+            T[dst][p][...] = np.ascontiguousarray(np.swapaxes(L[src][p], 0, 1))
+    return T
+
+
+CMP_SHAPES = [(1, 1, 1), (4, 5, 3), (6, 4, 9), (9, 2, 1), (5, 7, 1), (3, 8, 2)]
+
+
+@pytest.mark.parametrize("kbits", [64, 32])
+@pytest.mark.parametrize("shape", CMP_SHAPES)
+def test_compress_along_m_is_compress_along_n_of_the_transpose(built, shape, kbits):
+    """Compressing along M is the compact tag of the transposed product
+    (Z^T = Y^T X^T, Eq. (5) multiplied from the left): the compressed vectors,
+    the compact tags and the check of D equal those of the compression along N
+    of the transposed layer, whose combiners chi (length M) and chihat (length N)
+    are the same draws."""
+    M, K, N = shape
+    L = O.OracleLayer(M, K, N, 61, 3, 9, kbits=kbits, compress=1).deal()
+    T = transposed_layer(L, kbits)
+    L.online(O.MODE_COMPACT).check(O.MODE_COMPACT)
+    T.online(O.MODE_COMPACT).check(O.MODE_COMPACT)
+    assert L.accept() and T.accept()
+    sw = lambda a: np.ascontiguousarray(np.swapaxes(a, 0, 1))
+    assert (T["E"] == sw(L["U"])).all() and (T["U"] == sw(L["E"])).all() and (T["D"] == sw(L["D"])).all()
+    for p in range(2):
+        assert (T["Z"][p] == sw(L["Z"][p])).all() and (T["tZ"][p] == sw(L["tZ"][p])).all()
+    assert (T["Uc"] == L["Ec"]).all()
+    for n in ("Dc", "EUc"):
+        assert (T[n] == L[n]).all(), n
+    for p in range(2):
+        assert (T["tBc"][p] == L["tAc"][p]).all()
+        for n in ("tCc", "tRc", "tZc", "tDc"):
+            assert (T[n][p] == L[n][p]).all(), (n, p)
+        assert (T.cs[2, p] == L.cs[2, p]).all()
+    assert list(L.tag_mults) == list(T.tag_mults) == [O.compact_tag_mults(M, K, N, 1)] * 2
+
+
+@pytest.mark.parametrize("shape", CMP_SHAPES)
+def test_compress_along_m_tag_relation(built, shape):
+    """Per the MAC relation, the compact tag shares of chi^T Z sum to
+    Delta~ chi^T Z~, those of chi^T D~ to Delta~ chi^T D~, and the value
+    shares, tags and opened matrices are those of the compression along N."""
+    M, K, N = shape
+    L = O.run_layer(O.MODE_COMPACT, M, K, N, 71, 4, 6, compress=1)
+    C = O.run_layer(O.MODE_COMPACT, M, K, N, 71, 4, 6)
+    for n in ("Z", "tZ", "E", "U", "D"):
+        assert (L[n] == C[n]).all(), n
+    chi = [ref.draw(71, ref.stream(4, 0x30), i) for i in range(M)]
+    Zt, Dt = lift(L, "Z").reshape(M, N), ints(L["D"]).reshape(M, N)
+    cZ = [sum(chi[i] * int(Zt[i, j]) for i in range(M)) % R for j in range(N)]
+    cD = [sum(chi[i] * int(Dt[i, j]) for i in range(M)) % R for j in range(N)]
+    assert ints(L["Dc"]).tolist() == cD
+    assert lift(L, "tZc").tolist() == [dsum(L) * v % R for v in cZ]
+    assert lift(L, "tDc").tolist() == [dsum(L) * v % R for v in cD]
+    Et = ints(L["E"]).reshape(M, K)
+    assert ints(L["Ec"]).tolist() == [sum(chi[i] * int(Et[i, k]) for i in range(M)) % R for k in range(K)]
+
+
+@pytest.mark.parametrize("target", [("tC", 2), ("tR", 2), ("R", 2), ("C", 2), ("tA", 0), ("tB", 1)])
+@pytest.mark.parametrize("bit", [0, 40])
+def test_compress_along_m_flipped_bit_aborts(built, target, bit):
+    name, w = target
+    M, K, N = 5, 4, 3
+    for party in (0, 1):
+        L = O.OracleLayer(M, K, N, seed=8, layer_id=6, key_seed=3, compress=1).deal()
+        flat = L[name][party].reshape(-1, 2)
+        flat[(7 * bit + 2) % flat.shape[0], 0] ^= np.uint64(1 << bit)
+        L.online(O.MODE_COMPACT).check(O.MODE_COMPACT)
+        assert L.cs_sums()[w] != 0 and not L.accept(), (name, party, bit)
+
+
+def test_compressed_dimension_choice():
+    """The count of Sec. 3.4.3 with M and N exchanged is smaller exactly when
+    M > N: the classifier at batch 1 compresses along M (1.5x fewer
+    multiplications), the encoder products along N."""
+    assert O.cheaper_compress(4096, 25088, 1) == 1
+    assert O.compact_tag_mults(4096, 25088, 1) / O.compact_tag_mults(4096, 25088, 1, 1) > 1.49
+    assert O.cheaper_compress(128, 768, 2304) == 0 and O.cheaper_compress(64, 576, 3136) == 0
+    assert O.cheaper_compress(512, 4608, 49) == 1 and O.cheaper_compress(7, 5, 7) == 0
+    for M, K, N in [(3, 9, 2), (2, 9, 3), (5, 1, 5), (1, 1, 8)]:
+        a, b = O.compact_tag_mults(M, K, N, 0), O.compact_tag_mults(M, K, N, 1)
+        assert (b < a) == (M > N) and (a == b) == (M == N)
+
+
+def test_compress_along_m_needs_all_rows(built):
+    with pytest.raises(ValueError):
+        O.OracleLayer(6, 3, 2, 1, 1, 1, r0=2, r1=4, compress=1)
