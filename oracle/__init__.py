@@ -45,7 +45,9 @@ class _Desc(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int64), ("K", ctypes.c_int64), ("N", ctypes.c_int64),
                 ("seed", ctypes.c_uint64), ("layer_id", ctypes.c_uint64),
                 ("r0", ctypes.c_int64), ("r1", ctypes.c_int64), ("f", ctypes.c_int64), ("in_bits", ctypes.c_int64),
-                ("kbits", ctypes.c_int64), ("compress", ctypes.c_int64)]
+                ("kbits", ctypes.c_int64), ("compress", ctypes.c_int64),
+                ("conv_c", ctypes.c_int64), ("conv_h", ctypes.c_int64), ("conv_w", ctypes.c_int64),
+                ("conv_k", ctypes.c_int64), ("conv_stride", ctypes.c_int64), ("conv_pad", ctypes.c_int64)]
 
 
 _P2 = ctypes.c_void_p * 2
@@ -90,6 +92,9 @@ def lib():
         L.or_matmul.argtypes = [i64, i64, i64, vp, vp, vp]
         L.or_compress.argtypes = [i64, i64, vp, vp, vp]
         L.or_compress_rows.argtypes = [i64, i64, vp, vp, vp]
+        L.or_im2col.argtypes = [ctypes.POINTER(_Desc), vp, vp]
+        L.or_right_len.restype = i64
+        L.or_right_len.argtypes = [ctypes.POINTER(_Desc)]
         L.or_batchrec_cs.argtypes = [i64, vp, vp, vp, u64, vp]
         L.or_compact_cs.argtypes = [i64, vp, vp, vp, u64, vp]
         _lib = L
@@ -178,6 +183,7 @@ class OracleLayer:
     in_bits: int = 0
     kbits: int = 64
     compress: int = 0                   # 0: along N (columns), 1: along M (rows; all rows)
+    conv: tuple | None = None           # (C, H, W, k, stride, pad): Y is the im2col of a C x H x W input
     arrays: dict = field(default_factory=dict)
     cs: np.ndarray | None = None        # [3 (E,U,D)][2 parties][2 limbs]
     tag_mults: np.ndarray | None = None
@@ -187,17 +193,23 @@ class OracleLayer:
         if self.r1 is None:
             self.r1 = self.M
         rows, K, N = self.r1 - self.r0, self.K, self.N
+        if self.conv is not None:
+            C, H, W, k, st, pd = self.conv
+            Ho, Wo = (H + 2 * pd - k) // st + 1, (W + 2 * pd - k) // st + 1
+            if min(C, H, W, k, st) < 1 or pd < 0 or Ho < 1 or Wo < 1 or K != C * k * k or N != Ho * Wo:
+                raise ValueError("convolution geometry does not give this K and N")
+        kn = (self.conv[0], self.conv[1] * self.conv[2]) if self.conv is not None else (K, N)
         shapes = {}
         for n in ("X", "tX", "A", "tA"):
             shapes[n] = (2, rows, K)
         for n in ("Y", "tY", "B", "tB"):
-            shapes[n] = (2, K, N)
+            shapes[n] = (2,) + kn
         for n in ("C", "tC", "R", "tR", "Z", "tZ", "Rf", "tRf", "Zf", "tZf"):
             shapes[n] = (2, rows, N)
         if self.compress not in (0, 1) or (self.compress == 1 and (self.r0, self.r1) != (0, self.M)):
             raise ValueError("compress is 0 (along N) or 1 (along M, over all rows)")
         L = N if self.compress == 1 else rows     # length of the compressed M x N quantities
-        shapes.update(E=(rows, K), U=(K, N), D=(rows, N), Uc=(K,), tBc=(2, K), Dc=(L,), EUc=(L,),
+        shapes.update(E=(rows, K), U=kn, D=(rows, N), Uc=(K,), tBc=(2, K), Dc=(L,), EUc=(L,),
                       tCc=(2, L), tRc=(2, L), tZc=(2, L), tDc=(2, L), Ec=(K,), tAc=(2, K))
         for n, s in shapes.items():
             self.arrays[n] = np.zeros(s + (2,), dtype=np.uint64)
@@ -205,7 +217,7 @@ class OracleLayer:
 
     def _desc(self):
         return _Desc(self.M, self.K, self.N, self.seed & MASK64, self.layer_id & MASK64, self.r0, self.r1,
-                     self.f, self.in_bits, self.kbits, self.compress)
+                     self.f, self.in_bits, self.kbits, self.compress, *(self.conv or (0, 0, 0, 0, 0, 0)))
 
     def _bufs(self):
         b = _Bufs()
@@ -248,11 +260,12 @@ class OracleLayer:
 
 def run_layer(mode: int, M: int, K: int, N: int, seed: int, layer_id: int, key_seed: int,
               r0: int = 0, r1: int | None = None, f: int = 0, in_bits: int = 0, kbits: int = 64,
-              compress: int = 0) -> OracleLayer:
+              compress: int = 0, conv: tuple | None = None) -> OracleLayer:
     """Dealer, online phase and verification of one layer on rows [r0, r1)
     (with f > 0 the product is truncated by f fractional bits; kbits = k = s;
-    compress = 1 compresses along M, over all rows)."""
-    L = OracleLayer(M, K, N, seed, layer_id, key_seed, r0, r1, f, in_bits, kbits, compress)
+    compress = 1 compresses along M, over all rows; conv = (C, H, W, k,
+    stride, pad) makes the layer a convolution of a C x H x W input)."""
+    L = OracleLayer(M, K, N, seed, layer_id, key_seed, r0, r1, f, in_bits, kbits, compress, conv)
     return L.deal().online(mode).check(mode)
 
 
@@ -272,6 +285,13 @@ def compress(Mx: np.ndarray, chi: np.ndarray) -> np.ndarray:
     out = np.zeros((rows, 2), dtype=np.uint64)
     lib().or_compress(rows, N, _ptr(np.ascontiguousarray(Mx)), _ptr(np.ascontiguousarray(chi, dtype=np.uint64)),
                       _ptr(out))
+    return out
+
+
+def im2col(L: OracleLayer, a: np.ndarray) -> np.ndarray:
+    """The K x N im2col matrix (Eq. (4)) of a C x (H W) array of a convolution layer."""
+    out = np.zeros((L.K, L.N, 2), dtype=np.uint64)
+    lib().or_im2col(ctypes.byref(L._desc()), _ptr(np.ascontiguousarray(a)), _ptr(out))
     return out
 
 

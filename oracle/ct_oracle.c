@@ -200,6 +200,48 @@ static void auth_share(u128 lift, u128 dsum, uint64_t seed, uint64_t layer_id, i
 
 enum { OBJ_X = 1, OBJ_Y = 2, OBJ_A = 3, OBJ_B = 4, OBJ_C = 5, OBJ_R = 6, OBJ_RF = 7 };
 
+/* ------------------------------------------------------------------ */
+/* convolution as a matrix product (Eq. (4))                             */
+
+static int64_t conv_out(int64_t in, const or_desc *d) {
+    return (in + 2 * d->conv_pad - d->conv_k) / d->conv_stride + 1;
+}
+
+/* A convolution layer's K and N must be those of its geometry. */
+static void conv_validate(const or_desc *d) {
+    if (d->conv_c <= 0) return;
+    if (d->conv_k < 1 || d->conv_stride < 1 || d->conv_pad < 0 || d->conv_h + 2 * d->conv_pad < d->conv_k ||
+        d->conv_w + 2 * d->conv_pad < d->conv_k || d->K != d->conv_c * d->conv_k * d->conv_k ||
+        d->N != conv_out(d->conv_h, d) * conv_out(d->conv_w, d))
+        abort();
+}
+
+int64_t or_right_len(const or_desc *d) {
+    return d->conv_c > 0 ? d->conv_c * d->conv_h * d->conv_w : d->K * d->N;
+}
+
+/* Row k = (c kh + dy) kw + dx of the im2col matrix lists, for every output
+ * position n = y Wo + x, the input element under kernel tap (dy, dx):
+ * (c, y s + dy - p, x s + dx - p), zero where that falls in the padding. */
+void or_im2col(const or_desc *d, const uint64_t *in, uint64_t *out) {
+    conv_validate(d);
+    const int64_t kk = d->conv_k, Ho = conv_out(d->conv_h, d), Wo = conv_out(d->conv_w, d);
+    for (int64_t c = 0; c < d->conv_c; c++)
+        for (int64_t dy = 0; dy < kk; dy++)
+            for (int64_t dx = 0; dx < kk; dx++) {
+                const int64_t k = (c * kk + dy) * kk + dx;
+                for (int64_t y = 0; y < Ho; y++)
+                    for (int64_t x = 0; x < Wo; x++) {
+                        const int64_t iy = y * d->conv_stride + dy - d->conv_pad;
+                        const int64_t ix = x * d->conv_stride + dx - d->conv_pad;
+                        u128 v = 0;
+                        if (iy >= 0 && iy < d->conv_h && ix >= 0 && ix < d->conv_w)
+                            v = ld(in, (c * d->conv_h + iy) * d->conv_w + ix);
+                        st(out, k * d->N + y * Wo + x, v);
+                    }
+            }
+}
+
 /* An input value of Z_{2^k}: the draw mod 2^k, or with in_bits in 1..k-1 a
  * signed in_bits-bit integer (the top in_bits of those k bits, sign-extended)
  * in two's complement -- a stand-in for fixed-point encodings.  Lifted with
@@ -226,13 +268,24 @@ void or_deal(const or_desc *d, const uint64_t delta[2], int with_inputs, or_bufs
     const uint64_t seed = d->seed, lid = d->layer_id;
     const u128 dsum = key_sum(delta);
     (void)M;
+    conv_validate(d);
+    /* the right operand's buffers: K x N, or for a convolution the input's
+     * shape, whose im2col matrix (Eq. (4)) is the product's right operand */
+    const int64_t nr = or_right_len(d);
 
-    uint64_t *At = alloc128(rows * K), *Bt = alloc128(K * N), *Ct = alloc128(rows * N);
+    uint64_t *At = alloc128(rows * K), *Bt = alloc128(nr), *Ct = alloc128(rows * N);
     for (int64_t i = 0; i < rows; i++)
         for (int64_t k = 0; k < K; k++)
             st(At, i * K + k, draw128(seed, stream_of(lid, OR_P_LIFT_A), (uint64_t)((r0 + i) * K + k)));
-    for (int64_t e = 0; e < K * N; e++) st(Bt, e, draw128(seed, stream_of(lid, OR_P_LIFT_B), (uint64_t)e));
-    or_matmul(rows, K, N, At, Bt, Ct);
+    for (int64_t e = 0; e < nr; e++) st(Bt, e, draw128(seed, stream_of(lid, OR_P_LIFT_B), (uint64_t)e));
+    if (d->conv_c > 0) {
+        uint64_t *Bx = alloc128(K * N);
+        or_im2col(d, Bt, Bx);
+        or_matmul(rows, K, N, At, Bx, Ct);
+        free(Bx);
+    } else {
+        or_matmul(rows, K, N, At, Bt, Ct);
+    }
 
     for (int64_t i = 0; i < rows; i++)
         for (int64_t k = 0; k < K; k++) {
@@ -244,7 +297,7 @@ void or_deal(const or_desc *d, const uint64_t delta[2], int with_inputs, or_bufs
             }
             auth_share(ld(At, at), dsum, seed, lid, OBJ_A, e, b->A[0], b->A[1], b->tA[0], b->tA[1], at);
         }
-    for (int64_t e = 0; e < K * N; e++) {
+    for (int64_t e = 0; e < nr; e++) {
         if (with_inputs) {
             u128 y = input_lift(or_draw(seed, stream_of(lid, OR_P_LIFT_Y), (uint64_t)e), d->in_bits);
             auth_share(y, dsum, seed, lid, OBJ_Y, (uint64_t)e, b->Y[0], b->Y[1], b->tY[0], b->tY[1], e);
@@ -331,8 +384,44 @@ static void compact_rows(const or_desc *d, const uint64_t delta[2], or_bufs *b, 
     free(v);
 }
 
+static void online_product(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b);
+
+/* The online phase.  A convolution opens U = Y - B on the input's shape (its
+ * elements are what the parties broadcast) and then runs the product on the
+ * im2col matrices of Y, B and their tags (Eq. (4)); im2col is linear, so these
+ * are authenticated shares of the im2col matrices. */
 void or_online(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) {
     or_set_kbits(d->kbits);
+    if (d->conv_c <= 0) {
+        online_product(mode, d, delta, b);
+        return;
+    }
+    conv_validate(d);
+    const int64_t KN = d->K * d->N, nr = or_right_len(d);
+    open_diff(nr, b->Y, b->B, b->U);
+    or_bufs x = *b;
+    uint64_t *tmp[9];
+    for (int i = 0; i < 9; i++) tmp[i] = alloc128(KN);
+    for (int p = 0; p < 2; p++) {
+        or_im2col(d, b->Y[p], tmp[4 * p + 0]);
+        or_im2col(d, b->tY[p], tmp[4 * p + 1]);
+        or_im2col(d, b->B[p], tmp[4 * p + 2]);
+        or_im2col(d, b->tB[p], tmp[4 * p + 3]);
+        x.Y[p] = tmp[4 * p + 0];
+        x.tY[p] = tmp[4 * p + 1];
+        x.B[p] = tmp[4 * p + 2];
+        x.tB[p] = tmp[4 * p + 3];
+    }
+    x.U = tmp[8];
+    or_desc dx = *d;
+    dx.conv_c = 0;
+    online_product(mode, &dx, delta, &x);
+    b->tag_mults[0] = x.tag_mults[0];
+    b->tag_mults[1] = x.tag_mults[1];
+    for (int i = 0; i < 9; i++) free(tmp[i]);
+}
+
+static void online_product(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) {
     const int64_t K = d->K, N = d->N, rows = d->r1 - d->r0;
     const uint64_t seed = d->seed, lid = d->layer_id;
 
@@ -464,7 +553,9 @@ void or_check(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) {
     or_set_kbits(d->kbits);
     const int64_t M = d->M, K = d->K, N = d->N, r0 = d->r0, rows = d->r1 - d->r0;
     const uint64_t seed = d->seed, lid = d->layer_id;
-    int64_t big = rows * K > K * N ? rows * K : K * N;
+    /* U is checked on the elements that were opened: K x N, or the input's shape */
+    const int64_t nr = or_right_len(d);
+    int64_t big = rows * K > nr ? rows * K : nr;
     if (rows * N > big) big = rows * N;
     uint64_t *tW = alloc128(big);
     uint64_t *chi = (uint64_t *)malloc((size_t)(big > M ? big : M) * 8);
@@ -478,10 +569,10 @@ void or_check(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) {
         tag_diff(rows * K, b->tX[p], b->tA[p], tW);
         or_batchrec_cs(rows * K, b->E, tW, chi, delta[p], b->cs[0][p]);
     }
-    draw_chi(seed, stream_of(lid, OR_P_CHI_U), 0, K * N, chi);
+    draw_chi(seed, stream_of(lid, OR_P_CHI_U), 0, nr, chi);
     for (int p = 0; p < 2; p++) {
-        tag_diff(K * N, b->tY[p], b->tB[p], tW);
-        or_batchrec_cs(K * N, b->U, tW, chi, delta[p], b->cs[1][p]);
+        tag_diff(nr, b->tY[p], b->tB[p], tW);
+        or_batchrec_cs(nr, b->U, tW, chi, delta[p], b->cs[1][p]);
     }
 
     if (mode == OR_MODE_SPDZ2K) {

@@ -45,6 +45,13 @@ typedef struct {
     int64_t kbits;            /* k = s: 64 (shares in Z_{2^128}) or 32 (shares in Z_{2^64}); 0 means 64 */
     int64_t compress;         /* dimension CompactTag compresses: 0 = N (combine the columns),
                                  1 = M (combine the rows; needs r0 = 0, r1 = M) */
+    /* Convolution (Eq. (4)): conv_c > 0 makes Y the im2col matrix of a
+     * conv_c x conv_h x conv_w input for a conv_k x conv_k kernel with stride
+     * conv_stride and zero padding conv_pad; then K = conv_c conv_k^2, N = Ho Wo
+     * (Ho = (conv_h + 2 conv_pad - conv_k) / conv_stride + 1, Wo alike), and the
+     * buffers Y, tY, B, tB, U hold conv_c x conv_h x conv_w elements: the input,
+     * its mask and the opened U of that shape.  conv_c = 0: a plain product. */
+    int64_t conv_c, conv_h, conv_w, conv_k, conv_stride, conv_pad;
 } or_desc;
 
 /* Every pointer is a caller-owned array of (lo, hi) uint64 pairs. */
@@ -83,6 +90,11 @@ void or_set_kbits(int64_t kbits);
 void or_deal(const or_desc *d, const uint64_t delta[2], int with_inputs, or_bufs *b);
 void or_online(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b);
 void or_check(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b);
+
+/* Elements of the right operand's buffers: conv_c conv_h conv_w, or K N. */
+int64_t or_right_len(const or_desc *d);
+/* Eq. (4): out (K x N) = im2col of in (conv_c x conv_h x conv_w). */
+void or_im2col(const or_desc *d, const uint64_t *in, uint64_t *out);
 
 /* building blocks, exposed so tests can feed chosen combiners */
 void or_matmul(int64_t M, int64_t K, int64_t N, const uint64_t *P, const uint64_t *Q, uint64_t *out);

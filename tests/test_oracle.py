@@ -641,3 +641,148 @@ def test_compressed_dimension_choice():
 def test_compress_along_m_needs_all_rows(built):
     with pytest.raises(ValueError):
         O.OracleLayer(6, 3, 2, 1, 1, 1, r0=2, r1=4, compress=1)
+
+
+# ---------------------------------------------------------------- convolution (Eq. (4))
+
+CONVS = [  # (C_out, (C, H, W, k, stride, pad))
+    (3, (2, 5, 5, 3, 1, 1)), (2, (3, 4, 6, 3, 2, 0)), (4, (1, 7, 5, 3, 2, 1)), (2, (2, 3, 3, 1, 1, 0)),
+    (3, (2, 6, 4, 2, 2, 1))]
+
+
+def conv_dims(cout, g):
+    C, H, W, k, s, p = g
+    Ho, Wo = (H + 2 * p - k) // s + 1, (W + 2 * p - k) // s + 1
+    return cout, C * k * k, Ho * Wo, Ho, Wo
+
+
+@pytest.mark.parametrize("cout,g", CONVS)
+@pytest.mark.parametrize("mode", [O.MODE_SPDZ2K, O.MODE_COMPACT])
+def test_conv_output_is_the_direct_convolution(built, cout, g, mode):
+    """Sum_p [Z]_p is the convolution of the lifted weights with the lifted
+    input, computed by its defining sum over channels and kernel taps (no
+    im2col), mod 2^128; the tags satisfy Eq. (1)."""
+    C, H, W, k, s, p = g
+    M, K, N, Ho, Wo = conv_dims(cout, g)
+    L = O.run_layer(mode, M, K, N, 13, 6, 5, conv=g)
+    Wt = lift(L, "X").reshape(cout, C, k, k)
+    In = lift(L, "Y").reshape(C, H, W)
+    Z = lift(L, "Z").reshape(cout, Ho, Wo)
+    for o in range(cout):
+        for y in range(Ho):
+            for x in range(Wo):
+                acc = 0
+                for c in range(C):
+                    for dy in range(k):
+                        for dx in range(k):
+                            iy, ix = y * s + dy - p, x * s + dx - p
+                            if 0 <= iy < H and 0 <= ix < W:
+                                acc += int(Wt[o, c, dy, dx]) * int(In[c, iy, ix])
+                assert int(Z[o, y, x]) == acc % R, (o, y, x)
+    assert (lift(L, "tZ") == (dsum(L) * lift(L, "Z")) % R).all()
+    assert L.accept()
+
+
+@pytest.mark.parametrize("cout,g", CONVS[:3])
+def test_conv_matches_torch_conv2d(built, cout, g):
+    """With 6-bit signed inputs the product mod 2^64 equals torch's float64
+    conv2d (exact at these magnitudes): pins the im2col ordering of Eq. (4)
+    against a library convolution."""
+    import torch
+    C, H, W, k, s, p = g
+    M, K, N, Ho, Wo = conv_dims(cout, g)
+    L = O.run_layer(O.MODE_COMPACT, M, K, N, 17, 2, 3, in_bits=6, conv=g)
+    sg = lambda v: (int(v) % 2 ** 64) - 2 ** 64 * ((int(v) % 2 ** 64) >= 2 ** 63)
+    Wt = torch.tensor([[sg(v) for v in row] for row in lift(L, "X").tolist()], dtype=torch.float64)
+    In = torch.tensor([[sg(v) for v in row] for row in lift(L, "Y").tolist()], dtype=torch.float64)
+    ref = torch.nn.functional.conv2d(In.reshape(1, C, H, W), Wt.reshape(cout, C, k, k), stride=s, padding=p)
+    got = [[sg(v) for v in row] for row in lift(L, "Z").tolist()]
+    assert torch.equal(ref.reshape(cout, Ho * Wo), torch.tensor(got, dtype=torch.float64))
+
+
+@pytest.mark.parametrize("cout,g", CONVS)
+@pytest.mark.parametrize("mode", [O.MODE_SPDZ2K, O.MODE_COMPACT])
+def test_conv_equals_the_explicit_product(built, cout, g, mode):
+    """A convolution layer is the plain product on the im2col matrices of its
+    input shares, mask shares and tags: the same output shares, tags, opened
+    E and D, compact vectors and checks of E and D; only U is opened (and
+    checked) on the input's shape, and its im2col is the product's U."""
+    M, K, N, Ho, Wo = conv_dims(cout, g)
+    Lc = O.OracleLayer(M, K, N, 23, 8, 4, conv=g).deal()
+    Lx = O.OracleLayer(M, K, N, 23, 8, 4).deal()
+    for n in ("Y", "tY", "B", "tB"):
+        for q in range(2):
+            Lx[n][q][...] = O.im2col(Lc, Lc[n][q])
+    for n in ("X", "tX", "A", "tA", "C", "tC", "R", "tR"):   # C~ = A~ im2col(B~) in both
+        assert (Lx[n] == Lc[n]).all() if n in ("X", "tX", "A", "tA", "R", "tR") else True
+        Lx[n][...] = Lc[n]
+    Lc.online(mode).check(mode)
+    Lx.online(mode).check(mode)
+    assert Lc.accept() and Lx.accept()
+    for n in ("Z", "tZ", "E", "D"):
+        assert (Lc[n] == Lx[n]).all(), n
+    assert (O.im2col(Lc, Lc["U"]) == Lx["U"]).all()
+    if mode == O.MODE_COMPACT:
+        for n in ("Uc", "tBc", "Dc", "EUc", "tCc", "tRc", "tZc", "tDc"):
+            assert (Lc[n] == Lx[n]).all(), n
+    for w in (0, 2):
+        assert (Lc.cs[w] == Lx.cs[w]).all()
+    assert list(Lc.tag_mults) == list(Lx.tag_mults)
+
+
+@pytest.mark.parametrize("cout,g", CONVS)
+def test_conv_compression_is_a_correlation(built, cout, g):
+    """Compressing the im2col matrix along N is a k x k correlation of the
+    input with the combiners laid out as an Ho x Wo image:
+    U^c[(c, dy, dx)] = sum_{y, x} chi[y Wo + x] U[c, y s + dy - p, x s + dx - p]."""
+    C, H, W, k, s, p = g
+    M, K, N, Ho, Wo = conv_dims(cout, g)
+    L = O.run_layer(O.MODE_COMPACT, M, K, N, 29, 3, 2, conv=g)
+    chi = [ref.draw(29, ref.stream(3, 0x30), j) for j in range(N)]
+    U = ints(L["U"]).reshape(C, H, W)
+    for q in range(2):
+        tB = ints(L["tB"][q]).reshape(C, H, W)
+        for c in range(C):
+            for dy in range(k):
+                for dx in range(k):
+                    su = st = 0
+                    for y in range(Ho):
+                        for x in range(Wo):
+                            iy, ix = y * s + dy - p, x * s + dx - p
+                            if 0 <= iy < H and 0 <= ix < W:
+                                su += chi[y * Wo + x] * int(U[c, iy, ix])
+                                st += chi[y * Wo + x] * int(tB[c, iy, ix])
+                    kk = (c * k + dy) * k + dx
+                    assert O.u128(L["Uc"][kk]) == su % R
+                    assert O.u128(L["tBc"][q][kk]) == st % R
+
+
+@pytest.mark.parametrize("target", ["Y", "tY", "B", "tB"])
+@pytest.mark.parametrize("mode", [O.MODE_SPDZ2K, O.MODE_COMPACT])
+def test_conv_flipped_input_bit_aborts_the_check_of_u(built, target, mode):
+    """U is opened and checked on the input's elements: one flipped bit of an
+    input or mask share (value or tag) fails the check of U."""
+    cout, g = CONVS[0]
+    M, K, N, Ho, Wo = conv_dims(cout, g)
+    for party in (0, 1):
+        L = O.OracleLayer(M, K, N, 31, 5, 6, conv=g).deal()
+        L[target][party].reshape(-1, 2)[7, 0] ^= np.uint64(1 << 21)
+        L.online(mode).check(mode)
+        assert L.cs_sums()[1] != 0 and not L.accept(), (target, party)
+
+
+@pytest.mark.parametrize("kbits", [64, 32])
+def test_conv_with_compression_along_m_and_k32(built, kbits):
+    cout, g = 12, (2, 4, 4, 3, 2, 1)     # M = 12 > N = 4: the cheaper compression is along M
+    M, K, N, Ho, Wo = conv_dims(cout, g)
+    assert O.cheaper_compress(M, K, N) == 1
+    L = O.run_layer(O.MODE_COMPACT, M, K, N, 37, 7, 8, kbits=kbits, compress=1, conv=g)
+    Ln = O.run_layer(O.MODE_COMPACT, M, K, N, 37, 7, 8, kbits=kbits, compress=0, conv=g)
+    assert L.accept() and Ln.accept()
+    for n in ("Z", "tZ", "D", "U"):
+        assert (L[n] == Ln[n]).all()
+
+
+def test_conv_geometry_is_validated(built):
+    with pytest.raises(ValueError):
+        O.OracleLayer(3, 18, 24, 1, 1, 1, conv=(2, 5, 5, 3, 1, 1))
