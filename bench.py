@@ -37,7 +37,13 @@ INT8_PEAK_TOPS = 5000.0      # MI355X dense int8 MFMA, 5.0 POP/s
 DIGIT_PAIRS = 136            # int8 digit products per 128-bit ring multiply-accumulate
 
 
-def stage_work(stage: str, specs, mode: str, f: int = 0, kbits: int = 64):
+def along_m(s, compress: str) -> bool:
+    """Whether the compact tag of layer s is compressed along M (AUTO: exactly when M > N)."""
+    return compress == "m" or (compress == "auto" and s.M > s.N)
+
+
+def stage_work(stage: str, specs, mode: str, f: int = 0, kbits: int = 64, compress: str = "n",
+               implicit: bool = False):
     """Algorithmic work of one launch of a kernel stage over the layer batch:
     ("hbm", bytes) or ("mfma", int8 ops), for the fused step
     (online phase + verification).  16 B per Z_2^128 element; per element:
@@ -56,6 +62,12 @@ def stage_work(stage: str, specs, mode: str, f: int = 0, kbits: int = 64):
                  tZ_p (3): 176 B; SPDZ2k reads R_p, Z_p, tR_p, tZ_p (8),
                  writes D: 144 B; with f > 0 also reads R^f_p, tR^f_p and
                  writes Z^f_p, tZ^f_p: + 128 B.
+      col_tag    layers compressed along M, K x N: reads U, tB_p: 48 B.
+    With implicit convolutions (im2col left implicit) the right operand's
+    arrays have the input's C H W elements: open_u moves 144 B per input
+    element, the packing of each right operand reads 16 B per input element
+    and writes 32 B per K x N entry, and conv_compress reads U, tB_p: 48 B per
+    input element.
     With k = s = 32 elements are 8 B (every byte figure halves) and a ring
     MAC is 36 digit products."""
     scale = 1 if kbits == 64 else 0.5
@@ -66,18 +78,26 @@ def stage_work(stage: str, specs, mode: str, f: int = 0, kbits: int = 64):
         M, K, N = s.M, s.K, s.N
         mk, kn, mn = M * K, K * N, M * N
         wide = N > 8
+        conv = implicit and s.conv is not None
+        nr = s.conv[0] * s.conv[1] * s.conv[2] if conv else kn
         if stage == "open_u":
-            tot += 144 * kn
+            tot += 144 * nr
         elif stage == "row_pass":
             tot += 144 * mk + ((48 if spdz else 16) * mk if wide else 0)
         elif stage == "pack":
-            tot += (160 if spdz else 96) * (mk + kn) if wide else 0
+            nright = 5 if spdz else 3
+            right = nright * (16 * nr + 32 * kn) if conv else (160 if spdz else 96) * kn
+            tot += ((160 if spdz else 96) * mk + right) if wide else 0
+        elif stage == "conv_compress":
+            tot += 48 * nr if conv and not spdz and not along_m(s, compress) else 0
         elif stage == "copy_base":
             tot += (32 * mn * (4 if spdz else 2)) if wide else 0
         elif stage == "ring_gemm":
             tot += 2 * pairs * (8 if spdz else 4) * M * K * N if wide else 0
         elif stage == "post":
             tot += ((144 if spdz else 176) + (128 if f > 0 else 0)) * mn
+        elif stage == "col_tag":
+            tot += 48 * kn if not spdz and along_m(s, compress) else 0
         else:
             return None
     if stage == "ring_gemm":
@@ -269,6 +289,11 @@ def main():
                     help="parameter set k = s: 64 (shares in Z_2^128) or 32 (shares in Z_2^64)")
     ap.add_argument("--in-bits", type=int, default=0, help="dealer inputs as signed in-bits-bit integers (0: uniform)")
     ap.add_argument("--mode", default="compact", choices=["compact", "spdz2k"])
+    ap.add_argument("--compress", default="n", choices=["n", "m", "auto"],
+                    help="dimension the compact tag compresses: N, M, or per layer the cheaper (M iff M > N)")
+    ap.add_argument("--conv", default="explicit", choices=["explicit", "implicit"],
+                    help="convolutions as products with an explicit K x N im2col operand, or with the im2col "
+                         "left implicit (input, mask and U of the input's C x H x W shape)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the SPDZ2k and per-layer comparison runs")
     ap.add_argument("--no-autotune", action="store_true", help="use the default matrix-core launch configuration")
@@ -292,7 +317,10 @@ def main():
     specs = workloads.CONFIGS[args.config]()
     mode_id = MODE_COMPACT if args.mode == "compact" else MODE_SPDZ2K
     ctx = Context(device=0, key_seed=workloads.KEY_SEED, max_layers=max(256, len(specs)), kbits=args.kbits)
-    layers = [ctx.layer(s.M, s.K, s.N, s.seed, s.layer_id, f=args.f, in_bits=args.in_bits) for s in specs]
+    cmp = {"n": 0, "m": 1, "auto": 2}[args.compress]
+    implicit = args.conv == "implicit"
+    layers = [ctx.layer(s.M, s.K, s.N, s.seed, s.layer_id, f=args.f, in_bits=args.in_bits, compress=cmp,
+                        conv=s.conv if implicit else None) for s in specs]
     print(f"[bench] config {args.config}: {len(specs)} layers, dealer ...", file=sys.stderr, flush=True)
     ctx.gen_triple_tags(layers)
     torch.cuda.synchronize()
@@ -333,7 +361,7 @@ def main():
     stage_rows = {}
     for name, (tot_ms, n) in stages.items():
         avg = tot_ms / max(n, 1)
-        w = stage_work(name, specs, args.mode, args.f, args.kbits)
+        w = stage_work(name, specs, args.mode, args.f, args.kbits, args.compress, implicit)
         row = {"ms_per_launch": round(avg, 5), "launches": n, "share_of_step": round(tot_ms / args.steps / ms, 4)}
         if w is not None and w[1] > 0:
             bound, units = w
@@ -356,7 +384,9 @@ def main():
             roofline = {"kernel": k, "bound": "mfma", "achieved": v["achieved_TOPS"], "peak": INT8_PEAK_TOPS,
                         "unit": "TOPS (int8)", "frac": v["frac"]}
         roofline["traffic"] = measured_traffic(k, f"{args.config}/{args.mode}" + (f"/f{args.f}" if args.f else "")
-                                               + ("/k32" if args.kbits == 32 else ""))
+                                               + ("/k32" if args.kbits == 32 else "")
+                                               + (f"/c{args.compress}" if args.compress != "n" else "")
+                                               + ("/implicit" if implicit else ""))
         roofline["share_of_step"] = v["share_of_step"]
 
     out = {
@@ -370,7 +400,10 @@ def main():
                    "protocol": args.mode, "parties": 2,
                    "ring": ("values Z_2^64, shares and tags Z_2^128" if args.kbits == 64 else
                             "values Z_2^32, shares and tags Z_2^64"),
-                   "layers_per_call": len(specs), "sum_MKN": mkn, "f": args.f, "in_bits": args.in_bits},
+                   "layers_per_call": len(specs), "sum_MKN": mkn, "f": args.f, "in_bits": args.in_bits,
+                   "compress": args.compress, "conv": args.conv,
+                   "compressed_along_m": [s.name for s in specs if along_m(s, args.compress)]
+                   if len(specs) <= 8 else sum(along_m(s, args.compress) for s in specs)},
         "roofline": roofline,
         "eager": {"value": round(mkn * args.steps / Te / 1e9, 3), "ms_per_step": round(Te / args.steps * 1e3, 4),
                   "p50_ms": round(pct(pere, 50), 4), "p99_ms": round(pct(pere, 99), 4)},

@@ -75,7 +75,42 @@ typedef struct {
                              integers in two's complement (a stand-in for fixed-point data) */
     uint64_t seed;        /* per-layer seed of the dealer and of the public combiners */
     uint64_t layer_id;    /* < 2^48; names the layer's generator streams */
+    int32_t compress;     /* CT_MODE_COMPACT: the dimension Pi_Compress (Fig. 4) combines,
+                             CT_COMPRESS_N, CT_COMPRESS_M or CT_COMPRESS_AUTO; ignored in
+                             CT_MODE_SPDZ2K */
+    int32_t reserved;     /* must be 0 */
+    /* Convolution (Eq. (4)) with the im2col matrix left implicit: conv_c > 0
+     * makes Y the im2col matrix of a conv_c x conv_h x conv_w input for a
+     * conv_k x conv_k kernel, stride conv_stride, zero padding conv_pad (row
+     * k = (c conv_k + dy) conv_k + dx, column n = y Wo + x holds input element
+     * (c, y stride + dy - pad, x stride + dx - pad), 0 in the padding).  Then
+     * K = conv_c conv_k^2 and N = Ho Wo with Ho = (conv_h + 2 pad - conv_k) /
+     * stride + 1 (Wo alike) are required, N > CT_SKINNY_N, and Y, tY, B, tB, U
+     * hold CT_RIGHT_LEN = conv_c conv_h conv_w elements: the input, the mask B
+     * of the input's shape (the triple is C = A im2col(B)) and the opened
+     * U = Y - B, which the parties broadcast and the check of U covers.
+     * conv_c = 0: a plain product (the other conv fields must be 0). */
+    int32_t conv_c, conv_h, conv_w, conv_k, conv_stride, conv_pad;
 } ct_layer_desc;
+
+/* Elements of Y, tY, B, tB and U of a layer. */
+#define CT_RIGHT_LEN(d) ((d).conv_c > 0 ? (int64_t)(d).conv_c * (d).conv_h * (d).conv_w : (d).K * (d).N)
+
+/* The compressed dimension of the compact tag.  The notation of Sec. 2.2
+ * leaves it open; the operation count of Sec. 3.4.3 is 4MN + 2KN + 3MK + M
+ * along N and 4MN + 2KM + 3KN + N along M, so AUTO takes M exactly when
+ * M > N (e.g. a classifier layer at batch 1).
+ *   CT_COMPRESS_N: W^c = W chi with chi of length N (the columns are combined);
+ *     the compact tag, Eq. (5), is a vector of length M, chihat has length M.
+ *   CT_COMPRESS_M: W^c = chi^T W with chi of length M; Eq. (5) multiplied by
+ *     chi^T from the left, [tZ^c]_p = [tC^c]_p + E^c [tB]_p + [tA^c]_p U +
+ *     [Delta]_p E^c U with E^c = chi^T E, [tA^c]_p = chi^T [tA]_p (length K);
+ *     the compact tag has length N, chihat has length N.
+ * chi and chihat are drawn from the same streams in both cases. */
+#define CT_COMPRESS_N 0
+#define CT_COMPRESS_M 1
+#define CT_COMPRESS_AUTO 2
+#define CT_COMPRESS_ALONG_M(M, N, c) ((c) == CT_COMPRESS_M || ((c) == CT_COMPRESS_AUTO && (M) > (N)))
 
 /* Per-layer device buffers.  [v]_p / [t v]_p are party p's value / tag share.
  * Every element is one element of Z_{2^{k+s}}: a ct_u128 for k = s = 64, a
@@ -83,11 +118,12 @@ typedef struct {
  * counts (CT_WORK_LEN, CT_CVEC_LEN) are the same for both. */
 typedef struct {
     ct_u128 *X[2], *tX[2], *A[2], *tA[2];                   /* M x K */
-    ct_u128 *Y[2], *tY[2], *B[2], *tB[2];                   /* K x N */
+    ct_u128 *Y[2], *tY[2], *B[2], *tB[2];                   /* K x N (convolution: the input's shape) */
     ct_u128 *C[2], *tC[2], *R[2], *tR[2], *Z[2], *tZ[2];    /* M x N; Z, tZ are outputs */
-    ct_u128 *E, *U, *D;  /* opened public values E = X - A (M x K), U = Y - B (K x N),
+    ct_u128 *E, *U, *D;  /* opened public values E = X - A (M x K), U = Y - B (K x N, or the input's shape),
                             D = R - Z (M x N); outputs of ct_tag_linear */
-    ct_u128 *cvec;       /* compact-tag vectors, CT_CVEC_LEN(M, K) elements, layout below;
+    ct_u128 *cvec;       /* compact-tag vectors, CT_CVEC_LEN_FOR(M, K, N, compress) elements,
+                            layout below;
                             written by ct_tag_linear in CT_MODE_COMPACT, unused otherwise */
     ct_u128 *work;       /* caller-owned workspace of CT_WORK_LEN(M, K, N) elements (NULL allowed
                             when that is 0); contents are undefined after a call */
@@ -107,9 +143,13 @@ typedef struct {
 #define CT_WORK_LEN(M, K, N) \
     ((N) > CT_SKINNY_N ? 3 * (M) * (K) + 5 * 2048 * (CT_TILES_(M, K) + CT_TILES_(N, K)) : 0)
 
-/* cvec layout (element offsets): U^c [K] | tB^c_0 [K] | tB^c_1 [K] | D^c [M] | (E U^c) [M] |
- * tC^c_0 [M] | tC^c_1 [M] | tR^c_0 [M] | tR^c_1 [M] | tZ^c_0 [M] | tZ^c_1 [M] | tD^c_0 [M] | tD^c_1 [M] */
+/* cvec layout (element offsets), compressing along N:
+ *   U^c [K] | tB^c_0 [K] | tB^c_1 [K] | D^c [M] | (E U^c) [M] | tC^c_0 [M] | tC^c_1 [M] |
+ *   tR^c_0 [M] | tR^c_1 [M] | tZ^c_0 [M] | tZ^c_1 [M] | tD^c_0 [M] | tD^c_1 [M];
+ * compressing along M, the same with U^c, tB^c_p replaced by E^c, tA^c_p and
+ * every [M] by [N] (D^c = chi^T D, (E^c U), tC^c_p = chi^T tC_p, ...). */
 #define CT_CVEC_LEN(M, K) (3 * (K) + 10 * (M))
+#define CT_CVEC_LEN_FOR(M, K, N, c) (3 * (K) + 10 * (CT_COMPRESS_ALONG_M(M, N, c) ? (N) : (M)))
 
 /* Check-value shares of one layer: cs[W][p] for W = 0 (E), 1 (U), 2 (D).
  * accept = 1 iff cs[W][0] + cs[W][1] = 0 mod 2^128 for all three W. */
@@ -323,7 +363,9 @@ ct_status ct_server_create(ct_ctx *ctx, const ct_server_params *params, ct_serve
 /* Microseconds since the server was created (the clock of arrival_us). */
 double ct_server_now_us(const ct_server *server);
 
-/* Queues n requests (validated first: on CT_EINVAL none is queued). */
+/* Queues n requests (validated first: on CT_EINVAL none is queued).  A
+ * request's layer is a plain product (conv_c = 0) with f = 0, K < 2^21 and
+ * N < 2^22; any compressed dimension. */
 ct_status ct_server_submit(ct_server *server, const ct_request *reqs, int n);
 
 /* Moves up to max completions, in completion order, into out; *count

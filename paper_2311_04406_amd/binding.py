@@ -44,7 +44,24 @@ class CtParams(ctypes.Structure):
 
 class CtLayerDesc(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int64), ("K", ctypes.c_int64), ("N", ctypes.c_int64), ("f", ctypes.c_int32),
-                ("in_bits", ctypes.c_int32), ("seed", ctypes.c_uint64), ("layer_id", ctypes.c_uint64)]
+                ("in_bits", ctypes.c_int32), ("seed", ctypes.c_uint64), ("layer_id", ctypes.c_uint64),
+                ("compress", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("conv_c", ctypes.c_int32), ("conv_h", ctypes.c_int32), ("conv_w", ctypes.c_int32),
+                ("conv_k", ctypes.c_int32), ("conv_stride", ctypes.c_int32), ("conv_pad", ctypes.c_int32)]
+
+
+# compressed dimension of the compact tag (CT_COMPRESS_*)
+COMPRESS_N, COMPRESS_M, COMPRESS_AUTO = 0, 1, 2
+
+
+def compress_along_m(M: int, N: int, compress: int) -> bool:
+    """CT_COMPRESS_ALONG_M: AUTO takes M exactly when M > N."""
+    return compress == COMPRESS_M or (compress == COMPRESS_AUTO and M > N)
+
+
+def cvec_len(M: int, K: int, N: int, compress: int = COMPRESS_N) -> int:
+    """CT_CVEC_LEN_FOR: 3 K + 10 L, L = N when compressing along M, else M."""
+    return 3 * K + 10 * (N if compress_along_m(M, N, compress) else M)
 
 
 _P2 = ctypes.c_void_p * 2
@@ -178,11 +195,16 @@ class Layer:
     `limbs` 64-bit words per element (2: k = s = 64; 1: k = s = 32)."""
 
     def __init__(self, M: int, K: int, N: int, seed: int, layer_id: int, device="cuda:0", f: int = 0,
-                 in_bits: int = 0, limbs: int = 2):
+                 in_bits: int = 0, limbs: int = 2, compress: int = COMPRESS_N, conv=None):
+        """conv = (C, H, W, k, stride, pad): a convolution whose right operand
+        is the implicit im2col matrix of a C x H x W input; Y, tY, B, tB and U
+        then have the input's shape, stored as C x (H W)."""
         self.M, self.K, self.N, self.seed, self.layer_id, self.f = M, K, N, seed, layer_id, f
-        self.in_bits, self.limbs = in_bits, limbs
+        self.in_bits, self.limbs, self.compress = in_bits, limbs, compress
+        self.conv = tuple(conv) if conv is not None else None
         self.t = {}
-        dims = {"MK": (M, K), "KN": (K, N), "MN": (M, N)}
+        kn = (self.conv[0], self.conv[1] * self.conv[2]) if self.conv else (K, N)
+        dims = {"MK": (M, K), "KN": kn, "MN": (M, N)}
         groups = {"MK": ["X", "tX", "A", "tA"], "KN": ["Y", "tY", "B", "tB"],
                   "MN": ["C", "tC", "R", "tR", "Z", "tZ"] + (BUF_TRUNC if f > 0 else [])}
         w = limbs
@@ -190,17 +212,18 @@ class Layer:
             for n in names:
                 self.t[n] = [torch.zeros(dims[g] + (w,), dtype=torch.int64, device=device) for _ in range(2)]
         self.t["E"] = torch.zeros((M, K, w), dtype=torch.int64, device=device)
-        self.t["U"] = torch.zeros((K, N, w), dtype=torch.int64, device=device)
+        self.t["U"] = torch.zeros(kn + (w,), dtype=torch.int64, device=device)
         self.t["D"] = torch.zeros((M, N, w), dtype=torch.int64, device=device)
-        self.t["cvec"] = torch.zeros((3 * K + 10 * M, w), dtype=torch.int64, device=device)
+        self.t["cvec"] = torch.zeros((cvec_len(M, K, N, compress), w), dtype=torch.int64, device=device)
         self.t["work"] = torch.zeros((max(1, work_len(M, K, N)), w), dtype=torch.int64, device=device)
 
     @classmethod
-    def wrap(cls, M: int, K: int, N: int, seed: int, layer_id: int, tensors: dict) -> "Layer":
+    def wrap(cls, M: int, K: int, N: int, seed: int, layer_id: int, tensors: dict,
+             compress: int = COMPRESS_N) -> "Layer":
         """A Layer over existing device tensors (no allocation)."""
         obj = cls.__new__(cls)
         obj.M, obj.K, obj.N, obj.seed, obj.layer_id, obj.f = M, K, N, seed, layer_id, 0
-        obj.in_bits, obj.limbs = 0, 2
+        obj.in_bits, obj.limbs, obj.compress, obj.conv = 0, 2, compress, None
         obj.t = dict(tensors)
         return obj
 
@@ -212,7 +235,12 @@ class Layer:
         return self.t[name]
 
     def desc(self) -> CtLayerDesc:
-        return CtLayerDesc(self.M, self.K, self.N, self.f, self.in_bits, self.seed & MASK64, self.layer_id & MASK64)
+        return CtLayerDesc(self.M, self.K, self.N, self.f, self.in_bits, self.seed & MASK64, self.layer_id & MASK64,
+                           self.compress, 0, *(self.conv or (0, 0, 0, 0, 0, 0)))
+
+    @property
+    def along_m(self) -> bool:
+        return compress_along_m(self.M, self.N, self.compress)
 
     def bufs(self) -> CtLayerBufs:
         b = CtLayerBufs()
@@ -225,10 +253,13 @@ class Layer:
                 setattr(b, n, _P2(self.t[n][0].data_ptr(), self.t[n][1].data_ptr()))
         return b
 
-    # cvec views (element offsets of compacttag.h)
+    # cvec views (element offsets of compacttag.h); compressed along M, the
+    # K-long parts hold E^c, [tA^c]_p (named Ec, tAc0, tAc1) and the others have N entries
     def cvec_parts(self):
-        M, K, c = self.M, self.K, self.t["cvec"]
-        o = {"Uc": (0, K), "tBc0": (K, K), "tBc1": (2 * K, K), "Dc": (3 * K, M), "EUc": (3 * K + M, M)}
+        K, c = self.K, self.t["cvec"]
+        M = self.N if self.along_m else self.M
+        k3 = ("Ec", "tAc0", "tAc1") if self.along_m else ("Uc", "tBc0", "tBc1")
+        o = {k3[0]: (0, K), k3[1]: (K, K), k3[2]: (2 * K, K), "Dc": (3 * K, M), "EUc": (3 * K + M, M)}
         base = 3 * K + 2 * M
         for i, n in enumerate(["tCc0", "tCc1", "tRc0", "tRc1", "tZc0", "tZc1", "tDc0", "tDc1"]):
             o[n] = (base + i * M, M)
@@ -342,9 +373,11 @@ class Context:
         self._check(self.lib.ct_stage_times(self.h, buf, 32, ctypes.byref(cnt)))
         return {buf[i].name.decode(): (buf[i].total_ms, int(buf[i].launches)) for i in range(min(cnt.value, 32))}
 
-    def layer(self, M: int, K: int, N: int, seed: int, layer_id: int, f: int = 0, in_bits: int = 0) -> Layer:
+    def layer(self, M: int, K: int, N: int, seed: int, layer_id: int, f: int = 0, in_bits: int = 0,
+              compress: int = COMPRESS_N, conv=None) -> Layer:
         """Buffers of one layer for this context's parameter set."""
-        return Layer(M, K, N, seed, layer_id, device=self.torch_device, f=f, in_bits=in_bits, limbs=self.limbs)
+        return Layer(M, K, N, seed, layer_id, device=self.torch_device, f=f, in_bits=in_bits, limbs=self.limbs,
+                     compress=compress, conv=conv)
 
     def plan(self, mode: int, layers, out: torch.Tensor | None = None) -> "Plan":
         """Captures the online phase of this layer batch (with the fused
@@ -417,11 +450,13 @@ class Server:
         return float(self.lib.ct_server_now_us(self.h))
 
     def submit(self, reqs):
-        """reqs: iterable of (id, kind, (M, K, N, seed, layer_id), arrival_us)."""
+        """reqs: iterable of (id, kind, (M, K, N, seed, layer_id[, compress]), arrival_us)."""
         reqs = list(reqs)
         arr = (CtRequest * max(1, len(reqs)))()
-        for i, (rid, kind, (M, K, N, seed, lid), t) in enumerate(reqs):
-            arr[i] = CtRequest(rid, kind, 0, CtLayerDesc(M, K, N, 0, 0, seed & MASK64, lid & MASK64), t)
+        for i, (rid, kind, lay, t) in enumerate(reqs):
+            M, K, N, seed, lid = lay[:5]
+            cmp = lay[5] if len(lay) > 5 else COMPRESS_N
+            arr[i] = CtRequest(rid, kind, 0, CtLayerDesc(M, K, N, 0, 0, seed & MASK64, lid & MASK64, cmp, 0), t)
         self._check(self.lib.ct_server_submit(self.h, arr, len(reqs)))
 
     def poll(self, max_items: int = 4096):
@@ -462,8 +497,9 @@ class Server:
         t["U"] = view(b.U, K, N)
         t["D"] = view(b.D, M, N)
         off = b.cvec - base
-        t["cvec"] = self.arena[off: off + (3 * K + 10 * M) * 16].view(torch.int64).view(3 * K + 10 * M, 2)
-        return Layer.wrap(M, K, N, d.seed, d.layer_id, t)
+        n = cvec_len(M, K, N, d.compress)
+        t["cvec"] = self.arena[off: off + n * 16].view(torch.int64).view(n, 2)
+        return Layer.wrap(M, K, N, d.seed, d.layer_id, t, d.compress)
 
     def stats(self) -> dict:
         c = CtServerCounts()

@@ -23,7 +23,8 @@ using namespace ct;
 
 static const char *kStageNames[ST_COUNT] = {
     "deal_lift", "fill_zero", "deal_auth", "deal_skinny", "zero_acc", "open_u", "row_pass", "pack",
-    "copy_base", "ring_gemm", "post", "compact_final", "check_batch", "check_compact", "finalize"};
+    "copy_base", "ring_gemm", "post", "compact_final", "check_batch", "check_compact", "finalize", "col_tag",
+    "conv_compress"};
 constexpr int EV_POOL = 2048;
 
 struct ct_plan {
@@ -111,6 +112,22 @@ ct_status validate(ct_ctx *c, int max_layers, const ct_layer_desc *L, const ct_l
         if (d.f < 0 || d.f > 63) return fail(c, CT_EINVAL, at + "f must be in [0, 63]");
         if (d.in_bits < 0 || d.in_bits > 63) return fail(c, CT_EINVAL, at + "in_bits must be in [0, 63]");
         if (d.layer_id >= (1ULL << 48)) return fail(c, CT_EINVAL, at + "layer_id must be < 2^48");
+        if (d.compress < CT_COMPRESS_N || d.compress > CT_COMPRESS_AUTO || d.reserved != 0)
+            return fail(c, CT_EINVAL, at + "compress must be CT_COMPRESS_N, _M or _AUTO and reserved 0");
+        if (d.conv_c < 0) return fail(c, CT_EINVAL, at + "conv_c must be >= 0");
+        if (d.conv_c == 0 && (d.conv_h | d.conv_w | d.conv_k | d.conv_stride | d.conv_pad) != 0)
+            return fail(c, CT_EINVAL, at + "convolution fields must be 0 when conv_c is 0");
+        if (d.conv_c > 0) {
+            const int64_t kk = d.conv_k, st = d.conv_stride, pd = d.conv_pad;
+            if (kk < 1 || st < 1 || pd < 0 || pd >= kk || d.conv_h < 1 || d.conv_w < 1 ||
+                d.conv_h + 2 * pd < kk || d.conv_w + 2 * pd < kk)
+                return fail(c, CT_EINVAL, at + "invalid convolution geometry");
+            const int64_t ho = (d.conv_h + 2 * pd - kk) / st + 1, wo = (d.conv_w + 2 * pd - kk) / st + 1;
+            if (d.K != (int64_t)d.conv_c * kk * kk || d.N != ho * wo)
+                return fail(c, CT_EINVAL, at + "K and N must be conv_c conv_k^2 and the output size Ho Wo");
+            if (d.N <= SKINNY_MAX_N)
+                return fail(c, CT_EINVAL, at + "convolution layers need N > CT_SKINNY_N");
+        }
         const ct_layer_bufs &b = B[l];
         auto chk = [&](const ct_u128 *p, const char *name) -> bool {
             if (!aligned16(p)) {
@@ -181,6 +198,14 @@ void fill_layer(const ct_ctx *c, u128 *acc, const ct_layer_desc &d, const ct_lay
     cp(o.Rf, b.Rf); cp(o.tRf, b.tRf); cp(o.Zf, b.Zf); cp(o.tZf, b.tZf);
     o.f = d.f;
     o.in_bits = d.in_bits;
+    o.cm = CT_COMPRESS_ALONG_M(d.M, d.N, d.compress) ? 1 : 0;
+    if (d.conv_c > 0) {
+        o.cv.on = 1;
+        o.cv.c = d.conv_c; o.cv.h = d.conv_h; o.cv.w = d.conv_w;
+        o.cv.k = d.conv_k; o.cv.s = d.conv_stride; o.cv.p = d.conv_pad;
+        o.cv.wo = (d.conv_w + 2 * d.conv_pad - d.conv_k) / d.conv_stride + 1;
+    }
+    o.nr = CT_RIGHT_LEN(d);
     o.E = reinterpret_cast<u128 *>(b.E);
     o.U = reinterpret_cast<u128 *>(b.U);
     o.D = reinterpret_cast<u128 *>(b.D);
@@ -191,8 +216,8 @@ void fill_layer(const ct_ctx *c, u128 *acc, const ct_layer_desc &d, const ct_lay
 
 struct Sizes {
     int64_t mk = 0, kn = 0, mn = 0, m = 0, k = 0, cvec = 0, kn_items = 0, mn_items = 0, row_items = 0,
-            skinny_mn = 0;
-    bool skinny = false;
+            skinny_mn = 0, col_tag = 0, nr = 0, conv_items = 0;
+    bool skinny = false, cm = false, conv_n = false;
 };
 
 Sizes max_sizes(const ct_layer_desc *L, int n) {
@@ -204,10 +229,23 @@ Sizes max_sizes(const ct_layer_desc *L, int n) {
         s.mn = std::max(s.mn, d.M * d.N);
         s.m = std::max(s.m, d.M);
         s.k = std::max(s.k, d.K);
-        s.cvec = std::max(s.cvec, (int64_t)CT_CVEC_LEN(d.M, d.K));
+        s.cvec = std::max(s.cvec, (int64_t)CT_CVEC_LEN_FOR(d.M, d.K, d.N, d.compress));
         s.kn_items = std::max(s.kn_items, sweep_items(d.K, d.N));
         s.mn_items = std::max(s.mn_items, sweep_items(d.M, d.N));
         s.row_items = std::max(s.row_items, row_items(d.M, d.K));
+        s.nr = std::max(s.nr, (int64_t)CT_RIGHT_LEN(d));
+        if (d.conv_c > 0 && !CT_COMPRESS_ALONG_M(d.M, d.N, d.compress)) {
+            // compression of the implicit im2col matrices along N
+            s.conv_n = true;
+            s.conv_items = std::max(s.conv_items, sweep_items(d.K, d.N));
+        }
+        if (CT_COMPRESS_ALONG_M(d.M, d.N, d.compress)) {
+            // column-strip row pass, column sweeps of the M x N pass and of the compact products
+            s.cm = true;
+            s.row_items = std::max(s.row_items, cm_items(d.M, d.K, d.N));
+            s.mn_items = std::max(s.mn_items, col_sweep_items(d.M, d.N));
+            s.col_tag = std::max(s.col_tag, col_sweep_items(d.K, d.N));
+        }
         if (d.N <= SKINNY_MAX_N) {
             s.skinny = true;
             s.skinny_mn = std::max(s.skinny_mn, d.M * d.N);
@@ -264,10 +302,11 @@ GemmProb make_prob(const u128 *Lp1, const u128 *Lp2, const u128 *Rp1, const u128
     return p;
 }
 
-PackJob make_job(const u128 *src, u128 *dst, int64_t rows, int64_t cols, int side) {
+PackJob make_job(const u128 *src, u128 *dst, int64_t rows, int64_t cols, int side, const ConvGeom *cv = nullptr) {
     PackJob j;
     std::memset(&j, 0, sizeof(j));
     j.src = src; j.dst = dst; j.rows = (int32_t)rows; j.cols = (int32_t)cols; j.side = side;
+    if (cv && side == 1) j.cv = *cv;
     const int64_t major = side == 0 ? rows : cols, K = side == 0 ? cols : rows;
     j.majt = (int32_t)((major + 63) / 64);
     j.kt = (int32_t)((K + 31) / 32);
@@ -487,7 +526,7 @@ ct_status ct::run_deal(ct_ctx *c, Lane &ln, const ct_layer_desc *L, const ct_lay
         const WorkOff w = work_off(d.M, d.K, d.N);
         u128 *Ep = elem_at(o.work, w.Ep, c->eb), *B0p = elem_at(o.work, w.B0p, c->eb);
         ln.pack_host[njobs++] = make_job(o.A[1], Ep, d.M, d.K, 0);
-        ln.pack_host[njobs++] = make_job(o.B[1], B0p, d.K, d.N, 1);
+        ln.pack_host[njobs++] = make_job(o.B[1], B0p, d.K, d.N, 1, &o.cv);
         if (!job_in_work(ln.pack_host[njobs - 2], o.work, d, c->eb) || !job_in_work(ln.pack_host[njobs - 1], o.work, d, c->eb))
             return fail(c, CT_EINVAL, "internal error: workspace layout exceeds CT_WORK_LEN");
         probs.push_back(make_prob(Ep, nullptr, B0p, nullptr, nullptr, o.C[1], d));
@@ -500,7 +539,7 @@ ct_status ct::run_deal(ct_ctx *c, Lane &ln, const ct_layer_desc *L, const ct_lay
     std::copy(probs.begin(), probs.end(), ln.gemm_host);
     if ((s = upload(c, ln, n, nm, njobs, nskinny)) != CT_OK) return s;
     const Sizes sz = max_sizes(L, n);
-    LAUNCH(c, ln, ST_DEAL_LIFT, launch_deal_lift(c->eb, ln.layers_dev, n, std::max(sz.mk, sz.kn), ln.stream));
+    LAUNCH(c, ln, ST_DEAL_LIFT, launch_deal_lift(c->eb, ln.layers_dev, n, std::max(sz.mk, sz.nr), ln.stream));
     LAUNCH(c, ln, ST_PACK, launch_pack(c->eb, ln.pack_dev, njobs, pack_tiles, ln.stream));
     for (int i = 0; i < nm; i++)
         if (probs[i].accumulate)
@@ -513,7 +552,7 @@ ct_status ct::run_deal(ct_ctx *c, Lane &ln, const ct_layer_desc *L, const ct_lay
     }
     const int mask = (with_inputs ? ((1 << OBJ_X) | (1 << OBJ_Y)) : 0) | (1 << OBJ_A) | (1 << OBJ_B) |
                      (1 << OBJ_C) | (1 << OBJ_R) | (1 << OBJ_RF);
-    LAUNCH(c, ln, ST_DEAL_AUTH, launch_deal_auth(c->eb, ln.layers_dev, n, mask, std::max({sz.mk, sz.kn, sz.mn}), ln.stream));
+    LAUNCH(c, ln, ST_DEAL_AUTH, launch_deal_auth(c->eb, ln.layers_dev, n, mask, std::max({sz.mk, sz.nr, sz.mn}), ln.stream));
     return CT_OK;
 }
 
@@ -564,17 +603,17 @@ ct_status prepare_online(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc 
         J[njobs++] = make_job(o.E, wp(w.Ep), d.M, d.K, 0);
         J[njobs++] = make_job(wp(w.AE0), wp(w.AE0p), d.M, d.K, 0);
         J[njobs++] = make_job(o.A[1], wp(w.A1p), d.M, d.K, 0);
-        J[njobs++] = make_job(o.B[0], wp(w.B0p), d.K, d.N, 1);
-        J[njobs++] = make_job(o.B[1], wp(w.B1p), d.K, d.N, 1);
-        J[njobs++] = make_job(o.U, wp(w.Up), d.K, d.N, 1);
+        J[njobs++] = make_job(o.B[0], wp(w.B0p), d.K, d.N, 1, &o.cv);
+        J[njobs++] = make_job(o.B[1], wp(w.B1p), d.K, d.N, 1, &o.cv);
+        J[njobs++] = make_job(o.U, wp(w.Up), d.K, d.N, 1, &o.cv);
         const size_t first = probs.size();
         probs.push_back(make_prob(wp(w.Ep), wp(w.AE0p), wp(w.B0p), wp(w.Up), o.C[0], o.Z[0], d));
         probs.push_back(make_prob(wp(w.Ep), wp(w.A1p), wp(w.B1p), wp(w.Up), o.C[1], o.Z[1], d));
         if (!compact) {
             J[njobs++] = make_job(wp(w.tAE0), wp(w.tAE0p), d.M, d.K, 0);
             J[njobs++] = make_job(wp(w.tAE1), wp(w.tAE1p), d.M, d.K, 0);
-            J[njobs++] = make_job(o.tB[0], wp(w.tB0p), d.K, d.N, 1);
-            J[njobs++] = make_job(o.tB[1], wp(w.tB1p), d.K, d.N, 1);
+            J[njobs++] = make_job(o.tB[0], wp(w.tB0p), d.K, d.N, 1, &o.cv);
+            J[njobs++] = make_job(o.tB[1], wp(w.tB1p), d.K, d.N, 1, &o.cv);
             probs.push_back(make_prob(wp(w.Ep), wp(w.tAE0p), wp(w.tB0p), wp(w.Up), o.tC[0], o.tZ[0], d));
             probs.push_back(make_prob(wp(w.Ep), wp(w.tAE1p), wp(w.tB1p), wp(w.Up), o.tC[1], o.tZ[1], d));
         }
@@ -602,13 +641,19 @@ ct_status prepare_online(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc 
     P.max_row_items = sz.row_items;
     P.max_mn = sz.mn;
     P.max_mn_items = sz.mn_items;
+    P.any_cm = compact && sz.cm;
+    P.max_col_tag = sz.col_tag;
+    P.any_conv_n = compact && sz.conv_n;
+    P.max_conv_items = sz.conv_items;
+    P.max_kn_items = std::max(P.max_kn_items, sz.nr / 64 + 1);  // elementwise opening of convolution inputs
     P.flags = (check ? F_CHECK : 0) | (compact ? F_COMPACT : F_SPDZ);
     // cvec sums, check accumulators, and [Z]_p = [C]_p ([tZ]_p = [tC]_p) of
     // skinny layers, all accumulated into atomically by the passes
     P.zero_what = (compact ? 1 : 0) | (check ? 2 : 0) | (sz.skinny ? 4 : 0) | (sz.skinny && !compact ? 8 : 0);
     for (int l = 0; l < n; l++) {
         const int64_t N = L[l].N;
-        P.variants |= 1 << (N > SKINNY_MAX_N ? 0 : (N <= 1 ? 1 : (N <= 2 ? 2 : (N <= 4 ? 4 : SKINNY_MAX_N))));
+        const int v = N > SKINNY_MAX_N ? 0 : (N <= 1 ? 1 : (N <= 2 ? 2 : (N <= 4 ? 4 : SKINNY_MAX_N)));
+        P.variants |= 1 << (compact && CT_COMPRESS_ALONG_M(L[l].M, N, L[l].compress) ? VARIANT_CM + v : v);
     }
     return CT_OK;
 }
@@ -619,7 +664,10 @@ ct_status enqueue_online(ct_ctx *c, Lane &ln, const OnlineLaunch &P) {
     if (P.zero_what)
         LAUNCH(c, ln, ST_ZERO_ACC, launch_zero_acc(c->eb, ln.layers_dev, n, P.zero_what, P.max_zero, ln.stream));
     LAUNCH(c, ln, ST_OPEN_U, launch_open_u(c->eb, ln.layers_dev, n, P.flags, P.max_kn_items, ln.stream));
+    if (P.any_conv_n)
+        LAUNCH(c, ln, ST_CONV_COMPRESS, launch_conv_compress(c->eb, ln.layers_dev, n, P.max_conv_items, ln.stream));
     LAUNCH(c, ln, ST_ROW_PASS, launch_row_pass(c->eb, ln.layers_dev, n, P.flags, P.max_row_items, P.variants, ln.stream));
+    if (P.any_cm) LAUNCH(c, ln, ST_COL_TAG, launch_col_tag(c->eb, ln.layers_dev, n, P.max_col_tag, ln.stream));
     if (P.njobs > 0) LAUNCH(c, ln, ST_PACK, launch_pack(c->eb, ln.pack_dev, P.njobs, P.pack_tiles, ln.stream));
     if (P.any_accum)
         LAUNCH(c, ln, ST_COPY_BASE, launch_copy_base(c->eb, ln.layers_dev, n, P.mode, P.max_mn, ln.stream));
@@ -653,7 +701,7 @@ ct_status run_check(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc *L, c
     LAUNCH(c, ln, ST_ZERO_ACC, launch_zero_acc(c->eb, ln.layers_dev, n, 2, 0, ln.stream));
     const int mask = compact ? 0x3 : 0x7;
     LAUNCH(c, ln, ST_CHECK_BATCH,
-           launch_check_batch(c->eb, ln.layers_dev, n, mask, std::max({sz.mk, sz.kn, sz.mn}), ln.stream));
+           launch_check_batch(c->eb, ln.layers_dev, n, mask, std::max({sz.mk, sz.nr, sz.mn}), ln.stream));
     if (compact) LAUNCH(c, ln, ST_CHECK_COMPACT, launch_check_compact(c->eb, ln.layers_dev, n, ln.stream));
     LAUNCH(c, ln, ST_FINALIZE, launch_finalize(c->eb, ln.layers_dev, n, out_dev, ln.stream));
     return CT_OK;

@@ -45,6 +45,12 @@ __device__ __forceinline__ u128 ld(const u128 *p, int64_t i) {
     const ulonglong2 v = reinterpret_cast<const ulonglong2 *>(p)[i];
     return u128{v.x, v.y};
 }
+// A load of streamed data that is not read again soon (non-temporal hint:
+// it does not displace reused lines from the caches).
+__device__ __forceinline__ u128 ld_nt(const u128 *p, int64_t i) {
+    const uint64_t *q = reinterpret_cast<const uint64_t *>(p) + 2 * i;
+    return u128{__builtin_nontemporal_load(q), __builtin_nontemporal_load(q + 1)};
+}
 __device__ __forceinline__ void st(u128 *p, int64_t i, u128 v) {
     reinterpret_cast<ulonglong2 *>(p)[i] = make_ulonglong2(v.lo, v.hi);
 }
@@ -103,6 +109,7 @@ __device__ __forceinline__ r64 mul64(r64 a, uint64_t b) { return r64{a.v * b}; }
 __device__ __forceinline__ r64 mad64(r64 acc, r64 a, uint64_t b) { return r64{acc.v + a.v * b}; }
 __device__ __forceinline__ r64 mad(r64 acc, r64 a, r64 b) { return r64{acc.v + a.v * b.v}; }
 __device__ __forceinline__ r64 ld(const r64 *p, int64_t i) { return p[i]; }
+__device__ __forceinline__ r64 ld_nt(const r64 *p, int64_t i) { return r64{__builtin_nontemporal_load(&p[i].v)}; }
 __device__ __forceinline__ void st(r64 *p, int64_t i, r64 v) { p[i] = v; }
 __device__ __forceinline__ void atomic_add128(r64 *p, r64 v) {
     atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v.v);

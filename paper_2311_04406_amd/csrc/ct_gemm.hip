@@ -136,8 +136,10 @@ __global__ __launch_bounds__(256) void k_pack(const PackJob *__restrict__ jobs, 
             R v = Ring<R>::zero();
             if (J.side == 0) {
                 if (major < J.rows && k < J.cols) v = ld(src, (int64_t)major * J.cols + k);
-            } else {
-                if (k < J.rows && major < J.cols) v = ld(src, (int64_t)k * J.cols + major);
+            } else if (k < J.rows && major < J.cols) {
+                // a convolution's right operand is the implicit im2col matrix of its input
+                const int64_t g = kn_src(J.cv, J.cols, k, major);
+                if (g >= 0) v = ld(src, g);
             }
             to_digits(v, w[i]);
         }

@@ -43,7 +43,8 @@ void lane_free(Lane &ln);
 // Kernel stages, for the optional per-launch timing (ct_set_timing).
 enum Stage : int {
     ST_DEAL_LIFT, ST_FILL_ZERO, ST_DEAL_AUTH, ST_DEAL_SKINNY, ST_ZERO_ACC, ST_OPEN_U, ST_ROW_PASS, ST_PACK,
-    ST_COPY_BASE, ST_RING_GEMM, ST_POST, ST_COMPACT_FINAL, ST_CHECK_BATCH, ST_CHECK_COMPACT, ST_FINALIZE, ST_COUNT
+    ST_COPY_BASE, ST_RING_GEMM, ST_POST, ST_COMPACT_FINAL, ST_CHECK_BATCH, ST_CHECK_COMPACT, ST_FINALIZE,
+    ST_COL_TAG, ST_CONV_COMPRESS, ST_COUNT
 };
 
 struct ct_ctx {
@@ -82,10 +83,11 @@ ct_status run_check(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc *L, c
 // tables (outside a capture), enqueue only launches kernels.
 struct OnlineLaunch {
     int n = 0, nm = 0, njobs = 0, pack_tiles = 0, total_tiles = 0, variants = 0, flags = 0, zero_what = 0;
-    bool any_accum = false, compact = false, check = false;
+    bool any_accum = false, compact = false, check = false, any_cm = false, any_conv_n = false;
     ct_mode mode = CT_MODE_COMPACT;
     GemmTuning tu;
-    int64_t max_zero = 0, max_kn_items = 0, max_row_items = 0, max_mn = 0, max_mn_items = 0;
+    int64_t max_zero = 0, max_kn_items = 0, max_row_items = 0, max_mn = 0, max_mn_items = 0, max_col_tag = 0,
+            max_conv_items = 0;
     ct_check_result *out_dev = nullptr;
 };
 ct_status prepare_online(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,

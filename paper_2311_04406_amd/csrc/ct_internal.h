@@ -40,6 +40,29 @@ enum KeyIdx : int {
     K_COUNT
 };
 
+// Geometry of a convolution layer whose right operand is the implicit im2col
+// matrix of a c x h x w input (Eq. (4)); on = 0 for a plain product.
+struct ConvGeom {
+    int32_t on, c, h, w, k, s, p, wo;
+};
+
+// Element of the input under entry (k, n) of the im2col matrix:
+// k = (c k + dy) k + dx, n = y wo + x -> (c, y s + dy - p, x s + dx - p);
+// -1 where that falls in the zero padding.  k < 2^21, n < 2^22.
+__host__ __device__ inline int64_t conv_src(const ConvGeom &g, int32_t k, int32_t n) {
+    const uint32_t kk = (uint32_t)(g.k * g.k);
+    const uint32_t c = (uint32_t)k / kk, t = (uint32_t)k - c * kk;
+    const uint32_t dy = t / (uint32_t)g.k, dx = t - dy * (uint32_t)g.k;
+    const uint32_t y = (uint32_t)n / (uint32_t)g.wo, x = (uint32_t)n - y * (uint32_t)g.wo;
+    const int32_t iy = (int32_t)(y * g.s + dy) - g.p, ix = (int32_t)(x * g.s + dx) - g.p;
+    if (iy < 0 || iy >= g.h || ix < 0 || ix >= g.w) return -1;
+    return ((int64_t)c * g.h + iy) * g.w + ix;
+}
+// Index of right-operand entry (k, n) in a layer's K x N-shaped or input-shaped buffers.
+__host__ __device__ inline int64_t kn_src(const ConvGeom &g, int64_t N, int64_t k, int64_t n) {
+    return g.on ? conv_src(g, (int32_t)k, (int32_t)n) : k * N + n;
+}
+
 // Per-layer descriptor as the kernels see it (device memory).
 struct LayerDev {
     int64_t M, K, N;
@@ -53,6 +76,10 @@ struct LayerDev {
     u128 *acc;                  // check accumulators, ACC_PER_LAYER entries (context scratch)
     u128 *Rf[2], *tRf[2], *Zf[2], *tZf[2];  // f > 0: truncated mask and output (M x N)
     int32_t f, in_bits;         // truncated fractional bits; dealer input width (0: uniform)
+    int32_t cm;                 // CompactTag compresses along M (W^c = chi^T W) instead of N
+    int32_t pad_;
+    ConvGeom cv;                // convolution geometry (cv.on = 0: plain product)
+    int64_t nr;                 // elements of Y, tY, B, tB, U: K N, or c h w of a convolution
 };
 
 // Layers with N <= SKINNY_MAX_N take their output products on the VALU inside
@@ -83,7 +110,9 @@ enum PassFlags : int {
 // Check accumulators per layer: for W in (E, U, D): [sum chi*tW_0, sum chi*tW_1, sum chi*W].
 constexpr int ACC_PER_LAYER = 9;
 
-// cvec offsets (elements), see compacttag.h
+// cvec offsets (elements), see compacttag.h.  Compressing along M the same
+// offsets are taken with M replaced by N (cvec_off(N, K)), and the three
+// K-long vectors hold E^c, [tA^c]_0, [tA^c]_1 in place of U^c, [tB^c]_p.
 struct CvecOff {
     int64_t Uc, tBc0, tBc1, Dc, EUc, tCc0, tCc1, tRc0, tRc1, tZc0, tZc1, tDc0, tDc1;
 };
@@ -93,6 +122,46 @@ __host__ __device__ inline CvecOff cvec_off(int64_t M, int64_t K) {
     o.tCc0 = 3 * K + 2 * M; o.tCc1 = 3 * K + 3 * M; o.tRc0 = 3 * K + 4 * M; o.tRc1 = 3 * K + 5 * M;
     o.tZc0 = 3 * K + 6 * M; o.tZc1 = 3 * K + 7 * M; o.tDc0 = 3 * K + 8 * M; o.tDc1 = 3 * K + 9 * M;
     return o;
+}
+
+// Length of the compressed M x N quantities (D^c, the compact tags): M when
+// compressing along N, N when compressing along M.
+__host__ __device__ inline int64_t cvec_rows(const LayerDev &L) { return L.cm ? L.N : L.M; }
+
+// Row pass of a layer compressed along M: lanes own columns; a wavefront
+// takes a strip of cm_cw(N) * 64 columns over CM_RB rows and keeps the column
+// sums chi_m E_mk, chi_m [tA]_p,mk in registers until its rows are done
+// (narrower strips for skinny layers, whose row products take registers too).
+constexpr int CM_RB = 32;
+__host__ __device__ constexpr int cm_cw_variant(int ns) { return ns == 0 || ns == 1 ? 4 : (ns == 2 ? 2 : 1); }
+__host__ __device__ inline int cm_cw(int64_t N) {
+    return cm_cw_variant(N > 8 ? 0 : (N <= 1 ? 1 : (N <= 2 ? 2 : (N <= 4 ? 4 : 8))));
+}
+// Bit of the row-pass variant set: 1 << v for k_row_pass<v>, 1 << (VARIANT_CM + v)
+// for k_row_pass_cm<v> (v = 0, 1, 2, 4, 8).
+constexpr int VARIANT_CM = 16;
+__host__ __device__ inline int64_t cm_strips(int64_t K, int cw) { return (K + 64 * cw - 1) / (64 * cw); }
+__host__ __device__ inline int64_t cm_items(int64_t M, int64_t K, int64_t N) {
+    return cm_strips(K, cm_cw(N)) * ((M + CM_RB - 1) / CM_RB);
+}
+
+// Column sweep (sums down the columns of a rows x N matrix): wavefront items
+// of rb row groups (N <= 32) or of 64 columns x rb rows, rb = col_sweep_rb(rows)
+// rows per lane: at least 4, and enough that no column receives more than
+// about 256 atomic additions (same-address atomics serialize).
+__host__ __device__ inline int64_t col_sweep_rb(int64_t rows) {
+    const int64_t rb = (rows + 255) / 256;
+    return rb < 4 ? 4 : rb;
+}
+__host__ __device__ inline int64_t col_sweep_items(int64_t rows, int64_t N) {
+    const int64_t rb = col_sweep_rb(rows);
+    if (N <= 32) {
+        int64_t g = 1;
+        while (g < N) g <<= 1;
+        const int64_t per = (64 / g) * rb;
+        return (rows + per - 1) / per;
+    }
+    return ((N + 63) / 64) * ((rows + rb - 1) / rb);
 }
 
 // Operands of the matrix-core products are converted once into "digit
@@ -133,6 +202,7 @@ struct PackJob {
     const u128 *src;
     u128 *dst;
     int32_t rows, cols, side, majt, kt, tile_begin, tiles, pad;
+    ConvGeom cv;  // right operand read as the implicit im2col matrix of src (cv.on)
 };
 
 // One ring GEMM problem over packed operands (one party's product of a layer;
@@ -181,10 +251,13 @@ hipError_t launch_deal_auth(int eb, const LayerDev *L, int n, int obj, int64_t m
 hipError_t launch_zero_acc(int eb, const LayerDev *L, int n, int what, int64_t max_elems, hipStream_t st);
 hipError_t launch_copy_base(int eb, const LayerDev *L, int n, int mode, int64_t max_elems, hipStream_t st);
 hipError_t launch_open_u(int eb, const LayerDev *L, int n, int flags, int64_t max_items, hipStream_t st);
-// variants: bit v set if some layer takes row-pass variant v (0, 1, 2, 4, 8)
+// variants: bit v (bit VARIANT_CM + v) set if some layer takes row-pass variant v (0, 1, 2, 4, 8)
+// (of the pass of layers compressed along M)
 hipError_t launch_row_pass(int eb, const LayerDev *L, int n, int flags, int64_t max_items, int variants, hipStream_t st);
 hipError_t launch_post(int eb, const LayerDev *L, int n, int flags, int64_t max_items, hipStream_t st);
 hipError_t launch_compact_final(int eb, const LayerDev *L, int n, int flags, hipStream_t st);
+hipError_t launch_col_tag(int eb, const LayerDev *L, int n, int64_t max_items, hipStream_t st);
+hipError_t launch_conv_compress(int eb, const LayerDev *L, int n, int64_t max_items, hipStream_t st);
 hipError_t launch_check_batch(int eb, const LayerDev *L, int n, int which, int64_t max_elems, hipStream_t st);
 hipError_t launch_check_compact(int eb, const LayerDev *L, int n, hipStream_t st);
 hipError_t launch_finalize(int eb, const LayerDev *L, int n, ct_check_result *out, hipStream_t st);

@@ -19,6 +19,11 @@
 // formed by the passes that read the data anyway; without it ct_mac_check
 // recomputes them with k_check_batch / k_check_compact.
 //
+// Layers compressed along M take k_row_pass_cm (column sums of E and [tA]_p),
+// a column sweep in k_post and k_col_tag (the compact-tag products over
+// K x N).  Convolution layers open U on their input's elements in k_open_u
+// and compress their implicit im2col matrices in k_conv_compress.
+//
 // Every kernel serves all layers of a call: grid dimension y indexes layers
 // (and sub-objects), dimension x strides over that layer's work.  Cross-
 // workgroup sums use exact 128-bit atomics into zeroed accumulators.
@@ -125,6 +130,54 @@ __device__ __forceinline__ void row_sweep(int64_t rows, int64_t N, Elem elem, Ro
     }
 }
 
+// Column sweep over an R x N matrix (sums down the columns), the mirror of
+// row_sweep.  N <= 32: a wavefront covers 64 / G rows of G = pow2ceil(N)
+// columns at a time (coalesced), takes rb such row groups per item and
+// reduces over the lanes of one column; wider matrices give each lane a
+// column and each item 64 columns of rb rows (rb = col_sweep_rb(rows)).
+// elem(r, c, v) accumulates into the NV column sums v; col_done(c, v)
+// receives each item's sums and must add them atomically.
+template <class R, int NV, typename Elem, typename ColDone>
+__device__ __forceinline__ void col_sweep(int64_t rows, int64_t N, Elem elem, ColDone col_done) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave_id = (blockIdx.x * (int64_t)TPB + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * TPB) >> 6;
+    const int64_t rb = col_sweep_rb(rows);
+    if (N <= 32) {
+        int G = 1;
+        while (G < N) G <<= 1;
+        const int rpw = 64 / G, c = lane % G;
+        const int64_t per = (int64_t)rpw * rb, items = (rows + per - 1) / per;
+        for (int64_t it = wave_id; it < items; it += nwaves) {
+            R v[NV];
+#pragma unroll
+            for (int i = 0; i < NV; i++) v[i] = Ring<R>::zero();
+            for (int64_t j = 0; j < rb; j++) {
+                const int64_t r = it * per + (int64_t)j * rpw + lane / G;
+                if (r < rows && c < N) elem(r, (int64_t)c, v);
+            }
+            for (int m = 32; m >= G; m >>= 1) {
+#pragma unroll
+                for (int i = 0; i < NV; i++) v[i] = add(v[i], shfl_xor128(v[i], m));
+            }
+            if (lane < G && c < N) col_done((int64_t)c, v);
+        }
+    } else {
+        const int64_t chunks = (N + 63) / 64, items = chunks * ((rows + rb - 1) / rb);
+        for (int64_t it = wave_id; it < items; it += nwaves) {
+            const int64_t b = it / chunks, c = (it - b * chunks) * 64 + lane;
+            const int64_t r0 = b * rb, r1 = r0 + rb < rows ? r0 + rb : rows;
+            R v[NV];
+#pragma unroll
+            for (int i = 0; i < NV; i++) v[i] = Ring<R>::zero();
+            if (c < N) {
+                for (int64_t r = r0; r < r1; r++) elem(r, c, v);
+                col_done(c, v);
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- fill
 
 template <class R>
@@ -148,8 +201,8 @@ hipError_t launch_fill_zero(int eb, u128 *p, int64_t n, hipStream_t st) {
 template <class R>
 __global__ void k_deal_lift(const LayerDev *__restrict__ Ls) {
     const LayerDev &L = Ls[blockIdx.y >> 1];
-    const int which = blockIdx.y & 1;  // 0: A (M x K), 1: B (K x N)
-    const int64_t n = which ? L.K * L.N : L.M * L.K;
+    const int which = blockIdx.y & 1;  // 0: A (M x K), 1: B (K x N, or a convolution input's shape)
+    const int64_t n = which ? L.nr : L.M * L.K;
     const uint64_t key = which ? L.key[K_LIFT_B] : L.key[K_LIFT_A];
     R *dst = which ? P<R>(L.B[1]) : P<R>(L.A[1]);
     for (int64_t e = blockIdx.x * (int64_t)TPB + threadIdx.x; e < n; e += (int64_t)gridDim.x * TPB)
@@ -176,9 +229,9 @@ __global__ void k_deal_auth(const LayerDev *__restrict__ Ls, int obj_mask) {
     u128 *const *t;
     switch (obj) {
         case OBJ_X: n = L.M * L.K; v = L.X; t = L.tX; break;
-        case OBJ_Y: n = L.K * L.N; v = L.Y; t = L.tY; break;
+        case OBJ_Y: n = L.nr; v = L.Y; t = L.tY; break;
         case OBJ_A: n = L.M * L.K; v = L.A; t = L.tA; break;
-        case OBJ_B: n = L.K * L.N; v = L.B; t = L.tB; break;
+        case OBJ_B: n = L.nr; v = L.B; t = L.tB; break;
         case OBJ_C: n = L.M * L.N; v = L.C; t = L.tC; break;
         case OBJ_R: n = L.M * L.N; v = L.R; t = L.tR; break;
         default: n = L.M * L.N; v = L.Rf; t = L.tRf; break;
@@ -219,7 +272,7 @@ __global__ void k_zero_acc(const LayerDev *__restrict__ Ls, int what) {
     const LayerDev &L = Ls[blockIdx.y];
     const int64_t t0 = blockIdx.x * (int64_t)TPB + threadIdx.x, stride = (int64_t)gridDim.x * TPB;
     if (what & 1) {
-        const int64_t n = 3 * L.K + 10 * L.M;
+        const int64_t n = 3 * L.K + 10 * cvec_rows(L);
         for (int64_t e = t0; e < n; e += stride) st(P<R>(L.cvec), e, Ring<R>::zero());
     }
     if ((what & 2) && blockIdx.x == 0 && threadIdx.x < ACC_PER_LAYER) st(P<R>(L.acc), threadIdx.x, Ring<R>::zero());
@@ -273,7 +326,8 @@ __global__ __launch_bounds__(TPB) void k_open_u(const LayerDev *__restrict__ Ls,
     __shared__ R sh[3 * WAVES];
     const LayerDev &L = Ls[blockIdx.y];
     const int64_t K = L.K, N = L.N;
-    const bool check = flags & F_CHECK, compact = flags & F_COMPACT;
+    // a layer compressed along M has no K-long compressions of U and [tB]_p
+    const bool check = flags & F_CHECK, compact = (flags & F_COMPACT) && !L.cm;
     const CvecOff o = cvec_off(L.M, K);
     R chk[3] = {Ring<R>::zero(), Ring<R>::zero(), Ring<R>::zero()};
     const uint64_t kchi = L.key[K_CHI], kcu = L.key[K_CHI_U];
@@ -302,8 +356,57 @@ __global__ __launch_bounds__(TPB) void k_open_u(const LayerDev *__restrict__ Ls,
             atomic_add128(P<R>(L.cvec) + o.tBc1 + r, v[2]);
         }
     };
-    row_sweep<R, 3>(K, N, elem, row_done);
+    if (L.cv.on) {
+        // a convolution opens U on the input's elements; their compression
+        // along N (an implicit im2col) is k_conv_compress
+        for (int64_t e = blockIdx.x * (int64_t)TPB + threadIdx.x; e < L.nr; e += (int64_t)gridDim.x * TPB) {
+            const R tb0 = ld(P<R>(L.tB[0]), e), tb1 = ld(P<R>(L.tB[1]), e);
+            const R u = add(sub(ld(P<R>(L.Y[0]), e), ld(P<R>(L.B[0]), e)), sub(ld(P<R>(L.Y[1]), e), ld(P<R>(L.B[1]), e)));
+            st(P<R>(L.U), e, u);
+            if (check) {
+                const uint64_t x = Ring<R>::mod_s(sdraw(kcu, (uint64_t)e));
+                chk[0] = mad64(chk[0], sub(ld(P<R>(L.tY[0]), e), tb0), x);
+                chk[1] = mad64(chk[1], sub(ld(P<R>(L.tY[1]), e), tb1), x);
+                chk[2] = mad64(chk[2], u, x);
+            }
+        }
+    } else {
+        row_sweep<R, 3>(K, N, elem, row_done);
+    }
     if (check) block_accumulate<3>(chk, sh, P<R>(L.acc) + 3);
+}
+
+// Compression along N of a convolution's implicit im2col matrices (Pi_Compress,
+// Fig. 4, with the right operand of Eq. (4)): for row k = (c, dy, dx),
+//   U^c_k = sum_n chi_n U[c, y s + dy - p, x s + dx - p]   (n = y Wo + x),
+// and [tB^c]_p alike -- a k x k correlation of the input with chi laid out as
+// an Ho x Wo image.  The gathered input elements of neighbouring n and k are
+// the same few cache lines, so the input is read from HBM about once.
+template <class R>
+__global__ __launch_bounds__(TPB) void k_conv_compress(const LayerDev *__restrict__ Ls) {
+    const LayerDev &L = Ls[blockIdx.y];
+    if (!L.cv.on || L.cm) return;
+    const CvecOff o = cvec_off(L.M, L.K);
+    const uint64_t kchi = L.key[K_CHI];
+    auto elem = [&](int64_t r, int64_t c, R (&v)[3]) {
+        const int64_t g = conv_src(L.cv, (int32_t)r, (int32_t)c);
+        if (g < 0) return;
+        const uint64_t x = Ring<R>::mod_s(sdraw(kchi, (uint64_t)c));
+        v[0] = mad64(v[0], ld(P<R>(L.U), g), x);
+        v[1] = mad64(v[1], ld(P<R>(L.tB[0]), g), x);
+        v[2] = mad64(v[2], ld(P<R>(L.tB[1]), g), x);
+    };
+    auto row_done = [&](int64_t r, R (&v)[3]) {
+        atomic_add128(P<R>(L.cvec) + o.Uc + r, v[0]);
+        atomic_add128(P<R>(L.cvec) + o.tBc0 + r, v[1]);
+        atomic_add128(P<R>(L.cvec) + o.tBc1 + r, v[2]);
+    };
+    row_sweep<R, 3>(L.K, L.N, elem, row_done);
+}
+
+hipError_t launch_conv_compress(int eb, const LayerDev *L, int n, int64_t max_items, hipStream_t st) {
+    LAUNCH_RING(eb, k_conv_compress, dim3(grid_items(max_items), n), dim3(TPB), st, L);
+    return hipGetLastError();
 }
 
 hipError_t launch_open_u(int eb, const LayerDev *L, int n, int flags, int64_t max_items, hipStream_t st) {
@@ -316,6 +419,104 @@ hipError_t launch_open_u(int eb, const LayerDev *L, int n, int flags, int64_t ma
 // lanes striding over k with coalesced loads; each item adds its row sums
 // (compact-tag products, and the output products of skinny layers) to their
 // destinations with exact 128-bit atomics.
+// The row pass of a CompactTag layer compressed along M (chi of length M):
+// besides opening E, checking it and (N <= SKINNY_MAX_N) forming the output
+// products, it compresses E and [tA]_p down the columns,
+//   E^c_k = sum_m chi_m E_mk,  [tA^c]_p,k = sum_m chi_m [tA]_p,mk  (Fig. 4 along M).
+// Work items are strips of cm_cw(N) * 64 columns over CM_RB rows, ordered
+// row-block-major so that concurrent wavefronts read neighbouring columns of
+// the same rows and add their column sums to different addresses.
+template <class R, int NS>
+__device__ __forceinline__ void row_pass_cm(const LayerDev &L, int flags, R (&chk)[3]) {
+    const int lane = threadIdx.x & 63;
+    const int64_t M = L.M, K = L.K, N = L.N;
+    const bool check = flags & F_CHECK;
+    const CvecOff o = cvec_off(N, K);
+    const uint64_t kce = L.key[K_CHI_E], kchi = L.key[K_CHI];
+    R *AE0 = P<R>(L.work);
+    constexpr int CM_CW = cm_cw_variant(NS);
+    const int64_t strips = cm_strips(K, CM_CW), items = cm_items(M, K, N);
+    const int64_t wave_id = (blockIdx.x * (int64_t)TPB + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * TPB) >> 6;
+    for (int64_t it = wave_id; it < items; it += nwaves) {
+        const int64_t rb = it / strips, sg = it - rb * strips;
+        const int64_t m0 = rb * CM_RB, m1 = m0 + CM_RB < M ? m0 + CM_RB : M;
+        const int64_t kb = sg * (64 * CM_CW) + lane;
+        R ce[CM_CW], ca0[CM_CW], ca1[CM_CW];
+#pragma unroll
+        for (int c = 0; c < CM_CW; c++) ce[c] = ca0[c] = ca1[c] = Ring<R>::zero();
+        for (int64_t m = m0; m < m1; m++) {
+            const uint64_t xm = Ring<R>::mod_s(sdraw(kchi, (uint64_t)m));
+            R z0[NS > 0 ? NS : 1], z1[NS > 0 ? NS : 1];
+#pragma unroll
+            for (int j = 0; j < (NS > 0 ? NS : 1); j++) z0[j] = z1[j] = Ring<R>::zero();
+#pragma unroll
+            for (int c = 0; c < CM_CW; c++) {
+                const int64_t k = kb + 64 * c;
+                if (k < K) {
+                    const int64_t e = m * K + k;
+                    // loads first, streamed (see row_pass_body)
+                    const R a0 = ld_nt(P<R>(L.A[0]), e);
+                    const R a1 = NS > 0 ? ld_nt(P<R>(L.A[1]), e) : ld(P<R>(L.A[1]), e);
+                    const R x0 = ld_nt(P<R>(L.X[0]), e), x1 = ld_nt(P<R>(L.X[1]), e);
+                    const R ta0 = ld_nt(P<R>(L.tA[0]), e), ta1 = ld_nt(P<R>(L.tA[1]), e);
+                    R tx0 = Ring<R>::zero(), tx1 = Ring<R>::zero();
+                    if (check) {
+                        tx0 = ld_nt(P<R>(L.tX[0]), e);
+                        tx1 = ld_nt(P<R>(L.tX[1]), e);
+                    }
+                    const R E = add(sub(x0, a0), sub(x1, a1));
+                    st(P<R>(L.E), e, E);
+                    if (check) {
+                        const uint64_t x = Ring<R>::mod_s(sdraw(kce, (uint64_t)e));
+                        chk[0] = mad64(chk[0], sub(tx0, ta0), x);
+                        chk[1] = mad64(chk[1], sub(tx1, ta1), x);
+                        chk[2] = mad64(chk[2], E, x);
+                    }
+                    ce[c] = mad64(ce[c], E, xm);
+                    ca0[c] = mad64(ca0[c], ta0, xm);
+                    ca1[c] = mad64(ca1[c], ta1, xm);
+                    if constexpr (NS == 0) {
+                        st(AE0, e, add(a0, E));  // folded left operand of party 0's product
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < NS; j++) {
+                            if (j < N) {
+                                const int64_t kn = k * N + j;
+                                const R u = ld(P<R>(L.U), kn);
+                                z0[j] = mad(mad(z0[j], E, add(ld(P<R>(L.B[0]), kn), u)), a0, u);
+                                z1[j] = mad(mad(z1[j], E, ld(P<R>(L.B[1]), kn)), a1, u);
+                            }
+                        }
+                    }
+                }
+            }
+            if constexpr (NS > 0) {
+#pragma unroll
+                for (int j = 0; j < NS; j++) {
+                    if (j < N) {
+                        z0[j] = wave_sum(z0[j]);
+                        z1[j] = wave_sum(z1[j]);
+                        if (lane == 0) {
+                            atomic_add128(P<R>(L.Z[0]) + m * N + j, z0[j]);
+                            atomic_add128(P<R>(L.Z[1]) + m * N + j, z1[j]);
+                        }
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CM_CW; c++) {
+            const int64_t k = kb + 64 * c;
+            if (k < K) {
+                atomic_add128(P<R>(L.cvec) + o.Uc + k, ce[c]);
+                atomic_add128(P<R>(L.cvec) + o.tBc0 + k, ca0[c]);
+                atomic_add128(P<R>(L.cvec) + o.tBc1 + k, ca1[c]);
+            }
+        }
+    }
+}
+
 template <class R, int NS>
 __device__ __forceinline__ void row_pass_body(const LayerDev &L, int flags, R (&chk)[3]) {
     const int lane = threadIdx.x & 63;
@@ -345,19 +546,28 @@ __device__ __forceinline__ void row_pass_body(const LayerDev &L, int flags, R (&
         const int64_t rb = m * K;
         for (int64_t k = k0 + lane; k < k1; k += 64) {
             const int64_t e = rb + k;
-            const R a0 = ld(P<R>(L.A[0]), e), a1 = ld(P<R>(L.A[1]), e);
-            const R E = add(sub(ld(P<R>(L.X[0]), e), a0), sub(ld(P<R>(L.X[1]), e), a1));
-            st(P<R>(L.E), e, E);
+            // every load of the element is issued before the store of E (which
+            // the compiler may not move them across); the arrays are streamed,
+            // except [A]_1 of a matrix-core layer, which k_pack reads next
+            const R a0 = ld_nt(P<R>(L.A[0]), e);
+            const R a1 = skinny ? ld_nt(P<R>(L.A[1]), e) : ld(P<R>(L.A[1]), e);
+            const R x0 = ld_nt(P<R>(L.X[0]), e), x1 = ld_nt(P<R>(L.X[1]), e);
             const bool need_ta = check || compact || spdz;
-            R ta0 = Ring<R>::zero(), ta1 = Ring<R>::zero();
+            R ta0 = Ring<R>::zero(), ta1 = Ring<R>::zero(), tx0 = Ring<R>::zero(), tx1 = Ring<R>::zero();
             if (need_ta) {
-                ta0 = ld(P<R>(L.tA[0]), e);
-                ta1 = ld(P<R>(L.tA[1]), e);
+                ta0 = ld_nt(P<R>(L.tA[0]), e);
+                ta1 = ld_nt(P<R>(L.tA[1]), e);
             }
             if (check) {
+                tx0 = ld_nt(P<R>(L.tX[0]), e);
+                tx1 = ld_nt(P<R>(L.tX[1]), e);
+            }
+            const R E = add(sub(x0, a0), sub(x1, a1));
+            st(P<R>(L.E), e, E);
+            if (check) {
                 const uint64_t x = Ring<R>::mod_s(sdraw(kce, (uint64_t)e));
-                chk[0] = mad64(chk[0], sub(ld(P<R>(L.tX[0]), e), ta0), x);
-                chk[1] = mad64(chk[1], sub(ld(P<R>(L.tX[1]), e), ta1), x);
+                chk[0] = mad64(chk[0], sub(tx0, ta0), x);
+                chk[1] = mad64(chk[1], sub(tx1, ta1), x);
                 chk[2] = mad64(chk[2], E, x);
             }
             if (compact) {
@@ -437,31 +647,47 @@ __host__ __device__ inline int row_variant(int64_t N) {
     return N > SKINNY_MAX_N ? 0 : (N <= 1 ? 1 : (N <= 2 ? 2 : (N <= 4 ? 4 : SKINNY_MAX_N)));
 }
 
+// Layers compressed along M (CompactTag only) take k_row_pass_cm, every
+// other layer k_row_pass; each returns at once for the layers of the other.
 template <class R, int NS>
 __global__ __launch_bounds__(TPB) void k_row_pass(const LayerDev *__restrict__ Ls, int flags) {
     __shared__ R sh[3 * WAVES];
     const LayerDev &L = Ls[blockIdx.y];
-    if (row_variant(L.N) != NS) return;
+    if (row_variant(L.N) != NS || ((flags & F_COMPACT) && L.cm)) return;
     R chk[3] = {Ring<R>::zero(), Ring<R>::zero(), Ring<R>::zero()};
     row_pass_body<R, NS>(L, flags, chk);
     if (flags & F_CHECK) block_accumulate<3>(chk, sh, P<R>(L.acc) + 0);
 }
 
+template <class R, int NS>
+__global__ __launch_bounds__(TPB) void k_row_pass_cm(const LayerDev *__restrict__ Ls, int flags) {
+    __shared__ R sh[3 * WAVES];
+    const LayerDev &L = Ls[blockIdx.y];
+    if (row_variant(L.N) != NS || !L.cm) return;
+    R chk[3] = {Ring<R>::zero(), Ring<R>::zero(), Ring<R>::zero()};
+    row_pass_cm<R, NS>(L, flags, chk);
+    if (flags & F_CHECK) block_accumulate<3>(chk, sh, P<R>(L.acc) + 0);
+}
+
+template <class R>
+void launch_row_variants(const dim3 &g, const LayerDev *L, int flags, int variants, hipStream_t st) {
+    const dim3 b(TPB);
+    if (variants & (1 << 0)) hipLaunchKernelGGL((k_row_pass<R, 0>), g, b, 0, st, L, flags);
+    if (variants & (1 << 1)) hipLaunchKernelGGL((k_row_pass<R, 1>), g, b, 0, st, L, flags);
+    if (variants & (1 << 2)) hipLaunchKernelGGL((k_row_pass<R, 2>), g, b, 0, st, L, flags);
+    if (variants & (1 << 4)) hipLaunchKernelGGL((k_row_pass<R, 4>), g, b, 0, st, L, flags);
+    if (variants & (1 << 8)) hipLaunchKernelGGL((k_row_pass<R, SKINNY_MAX_N>), g, b, 0, st, L, flags);
+    if (variants & (1 << (VARIANT_CM + 0))) hipLaunchKernelGGL((k_row_pass_cm<R, 0>), g, b, 0, st, L, flags);
+    if (variants & (1 << (VARIANT_CM + 1))) hipLaunchKernelGGL((k_row_pass_cm<R, 1>), g, b, 0, st, L, flags);
+    if (variants & (1 << (VARIANT_CM + 2))) hipLaunchKernelGGL((k_row_pass_cm<R, 2>), g, b, 0, st, L, flags);
+    if (variants & (1 << (VARIANT_CM + 4))) hipLaunchKernelGGL((k_row_pass_cm<R, 4>), g, b, 0, st, L, flags);
+    if (variants & (1 << (VARIANT_CM + 8))) hipLaunchKernelGGL((k_row_pass_cm<R, SKINNY_MAX_N>), g, b, 0, st, L, flags);
+}
+
 hipError_t launch_row_pass(int eb, const LayerDev *L, int n, int flags, int64_t max_items, int variants, hipStream_t st) {
-    const dim3 g(grid_items(max_items), n), b(TPB);
-    if (eb == 8) {
-        if (variants & (1 << 0)) hipLaunchKernelGGL((k_row_pass<r64, 0>), g, b, 0, st, L, flags);
-        if (variants & (1 << 1)) hipLaunchKernelGGL((k_row_pass<r64, 1>), g, b, 0, st, L, flags);
-        if (variants & (1 << 2)) hipLaunchKernelGGL((k_row_pass<r64, 2>), g, b, 0, st, L, flags);
-        if (variants & (1 << 4)) hipLaunchKernelGGL((k_row_pass<r64, 4>), g, b, 0, st, L, flags);
-        if (variants & (1 << 8)) hipLaunchKernelGGL((k_row_pass<r64, SKINNY_MAX_N>), g, b, 0, st, L, flags);
-    } else {
-        if (variants & (1 << 0)) hipLaunchKernelGGL((k_row_pass<u128, 0>), g, b, 0, st, L, flags);
-        if (variants & (1 << 1)) hipLaunchKernelGGL((k_row_pass<u128, 1>), g, b, 0, st, L, flags);
-        if (variants & (1 << 2)) hipLaunchKernelGGL((k_row_pass<u128, 2>), g, b, 0, st, L, flags);
-        if (variants & (1 << 4)) hipLaunchKernelGGL((k_row_pass<u128, 4>), g, b, 0, st, L, flags);
-        if (variants & (1 << 8)) hipLaunchKernelGGL((k_row_pass<u128, SKINNY_MAX_N>), g, b, 0, st, L, flags);
-    }
+    const dim3 g(grid_items(max_items), n);
+    if (eb == 8) launch_row_variants<r64>(g, L, flags, variants, st);
+    else launch_row_variants<u128>(g, L, flags, variants, st);
     return hipGetLastError();
 }
 
@@ -489,10 +715,11 @@ __global__ __launch_bounds__(TPB) void k_post(const LayerDev *__restrict__ Ls, i
     const LayerDev &L = Ls[blockIdx.y];
     const int64_t M = L.M, N = L.N;
     const bool check = flags & F_CHECK, compact = flags & F_COMPACT;
-    const CvecOff o = cvec_off(M, L.K);
     const uint64_t kchi = L.key[K_CHI], kcd = L.key[K_CHI_D];
     R chk[3] = {Ring<R>::zero(), Ring<R>::zero(), Ring<R>::zero()};
     if (compact) {
+        const bool cm = L.cm;
+        const CvecOff o = cvec_off(cvec_rows(L), L.K);
         auto elem = [&](int64_t r, int64_t c, R (&v)[5]) {
             const int64_t e = r * N + c;
             const R D = add(sub(ld(P<R>(L.R[0]), e), ld(P<R>(L.Z[0]), e)), sub(ld(P<R>(L.R[1]), e), ld(P<R>(L.Z[1]), e)));
@@ -501,21 +728,24 @@ __global__ __launch_bounds__(TPB) void k_post(const LayerDev *__restrict__ Ls, i
             const R tr0 = ld(P<R>(L.tR[0]), e), tr1 = ld(P<R>(L.tR[1]), e);
             st(P<R>(L.tZ[0]), e, sub(tr0, mul64(D, L.delta[0])));
             st(P<R>(L.tZ[1]), e, sub(tr1, mul64(D, L.delta[1])));
-            const uint64_t x = Ring<R>::mod_s(sdraw(kchi, (uint64_t)c));
+            // combiner of the compressed index: the column (along N) or the row (along M)
+            const uint64_t x = Ring<R>::mod_s(sdraw(kchi, (uint64_t)(cm ? r : c)));
             v[0] = mad64(v[0], D, x);
             v[1] = mad64(v[1], tr0, x);
             v[2] = mad64(v[2], tr1, x);
             v[3] = mad64(v[3], ld(P<R>(L.tC[0]), e), x);
             v[4] = mad64(v[4], ld(P<R>(L.tC[1]), e), x);
         };
-        auto row_done = [&](int64_t r, R (&v)[5]) {
-            atomic_add128(P<R>(L.cvec) + o.Dc + r, v[0]);
-            atomic_add128(P<R>(L.cvec) + o.tRc0 + r, v[1]);
-            atomic_add128(P<R>(L.cvec) + o.tRc1 + r, v[2]);
-            atomic_add128(P<R>(L.cvec) + o.tCc0 + r, v[3]);
-            atomic_add128(P<R>(L.cvec) + o.tCc1 + r, v[4]);
+        // each sweep hands its partial sums for entry i (a row, or a column)
+        auto done = [&](int64_t i, R (&v)[5]) {
+            atomic_add128(P<R>(L.cvec) + o.Dc + i, v[0]);
+            atomic_add128(P<R>(L.cvec) + o.tRc0 + i, v[1]);
+            atomic_add128(P<R>(L.cvec) + o.tRc1 + i, v[2]);
+            atomic_add128(P<R>(L.cvec) + o.tCc0 + i, v[3]);
+            atomic_add128(P<R>(L.cvec) + o.tCc1 + i, v[4]);
         };
-        row_sweep<R, 5>(M, N, elem, row_done);
+        if (cm) col_sweep<R, 5>(M, N, elem, done);
+        else row_sweep<R, 5>(M, N, elem, done);
     } else {
         const int64_t n = M * N;
         for (int64_t e = blockIdx.x * (int64_t)TPB + threadIdx.x; e < n; e += (int64_t)gridDim.x * TPB) {
@@ -540,7 +770,41 @@ hipError_t launch_post(int eb, const LayerDev *L, int n, int flags, int64_t max_
 }
 
 // ---------------------------------------------------------------- compact tag
-// Eq. (5) with the key on the public term, per row m:
+// Products of the compact tag of a layer compressed along M, over K x N
+// (Eq. (5) multiplied by chi^T from the left), per column n:
+//   (E^c U)_n = sum_k E^c_k U_kn,
+//   [tZ^c]_p,n partial = sum_k (E^c_k [tB]_p,kn + [tA^c]_p,k U_kn);
+// k_compact_final adds [tC^c]_p and [Delta]_p (E^c U).
+template <class R>
+__global__ __launch_bounds__(TPB) void k_col_tag(const LayerDev *__restrict__ Ls) {
+    const LayerDev &L = Ls[blockIdx.y];
+    if (!L.cm) return;
+    const int64_t N = L.N;
+    const CvecOff o = cvec_off(N, L.K);
+    R *cv = P<R>(L.cvec);
+    auto elem = [&](int64_t k, int64_t n, R (&v)[3]) {
+        const int64_t e = kn_src(L.cv, N, k, n);  // a convolution's implicit im2col entry
+        if (e < 0) return;
+        const R ec = ld(cv + o.Uc, k), u = ld(P<R>(L.U), e);
+        v[0] = mad(v[0], ec, u);
+        v[1] = mad(mad(v[1], ec, ld(P<R>(L.tB[0]), e)), ld(cv + o.tBc0, k), u);
+        v[2] = mad(mad(v[2], ec, ld(P<R>(L.tB[1]), e)), ld(cv + o.tBc1, k), u);
+    };
+    auto done = [&](int64_t n, R (&v)[3]) {
+        atomic_add128(cv + o.EUc + n, v[0]);
+        atomic_add128(cv + o.tZc0 + n, v[1]);
+        atomic_add128(cv + o.tZc1 + n, v[2]);
+    };
+    col_sweep<R, 3>(L.K, N, elem, done);
+}
+
+hipError_t launch_col_tag(int eb, const LayerDev *L, int n, int64_t max_items, hipStream_t st) {
+    LAUNCH_RING(eb, k_col_tag, dim3(grid_items(max_items), n), dim3(TPB), st, L);
+    return hipGetLastError();
+}
+
+// Eq. (5) with the key on the public term, per entry i of the compressed
+// vectors (a row m; for a layer compressed along M, a column n):
 //   [tZ^c]_p = [tC^c]_p + (E [tB^c]_p + [tA]_p U^c) + [Delta]_p (E U^c),
 //   [tD^c]_p = [tR^c]_p - [tZ^c]_p.
 // F_CHECK: the compact check of D (Fig. 7 verification steps 2-5) in the
@@ -552,7 +816,7 @@ template <class R>
 __global__ __launch_bounds__(TPB) void k_compact_final(const LayerDev *__restrict__ Ls, int flags) {
     __shared__ R sh[3 * WAVES];
     const LayerDev &L = Ls[blockIdx.y];
-    const int64_t M = L.M;
+    const int64_t M = cvec_rows(L);
     const CvecOff o = cvec_off(M, L.K);
     R *c = P<R>(L.cvec);
     R v[3] = {Ring<R>::zero(), Ring<R>::zero(), Ring<R>::zero()};
@@ -603,7 +867,7 @@ __global__ __launch_bounds__(TPB) void k_check_batch(const LayerDev *__restrict_
     if (which == 0) {
         n = L.M * L.K; tP0 = P<R>(L.tX[0]); tP1 = P<R>(L.tX[1]); tQ0 = P<R>(L.tA[0]); tQ1 = P<R>(L.tA[1]); W = P<R>(L.E); key = L.key[K_CHI_E];
     } else if (which == 1) {
-        n = L.K * L.N; tP0 = P<R>(L.tY[0]); tP1 = P<R>(L.tY[1]); tQ0 = P<R>(L.tB[0]); tQ1 = P<R>(L.tB[1]); W = P<R>(L.U); key = L.key[K_CHI_U];
+        n = L.nr; tP0 = P<R>(L.tY[0]); tP1 = P<R>(L.tY[1]); tQ0 = P<R>(L.tB[0]); tQ1 = P<R>(L.tB[1]); W = P<R>(L.U); key = L.key[K_CHI_U];
     } else {
         n = L.M * L.N; tP0 = P<R>(L.tR[0]); tP1 = P<R>(L.tR[1]); tQ0 = P<R>(L.tZ[0]); tQ1 = P<R>(L.tZ[1]); W = P<R>(L.D); key = L.key[K_CHI_D];
     }
@@ -631,7 +895,7 @@ template <class R>
 __global__ __launch_bounds__(TPB) void k_check_compact(const LayerDev *__restrict__ Ls) {
     __shared__ R sh[3 * WAVES];
     const LayerDev &L = Ls[blockIdx.y];
-    const int64_t M = L.M;
+    const int64_t M = cvec_rows(L);
     const CvecOff o = cvec_off(M, L.K);
     R v[3] = {Ring<R>::zero(), Ring<R>::zero(), Ring<R>::zero()};
     for (int64_t i = threadIdx.x; i < M; i += TPB) {

@@ -51,7 +51,8 @@ inline LayerLayout layer_layout(int64_t M, int64_t K, int64_t N) {
     o.E = off; off += bmk;
     o.U = off; off += bkn;
     o.D = off; off += bmn;
-    o.cvec = off; off += arena_round((size_t)CT_CVEC_LEN(M, K) * el);
+    // compact vectors for either compressed dimension
+    o.cvec = off; off += arena_round((size_t)(3 * K + 10 * (M > N ? M : N)) * el);
     o.total = off;
     return o;
 }

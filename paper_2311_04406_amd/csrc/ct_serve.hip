@@ -303,7 +303,8 @@ ct_status ct_server_submit(ct_server *s, const ct_request *r, int n) {
         if (r[i].kind != CT_REQ_TAG && r[i].kind != CT_REQ_CHECK)
             return sfail(s, CT_EINVAL, "request " + std::to_string(i) + ": unknown kind");
         if (d.M < 1 || d.K < 1 || d.N < 1 || d.M >= (1LL << 31) || d.K >= (1LL << 21) || d.N >= (1LL << 22) ||
-            d.f != 0 || d.in_bits < 0 || d.in_bits > 63 || d.layer_id >= (1ULL << 48))
+            d.f != 0 || d.in_bits < 0 || d.in_bits > 63 || d.layer_id >= (1ULL << 48) || d.compress < 0 ||
+            d.compress > CT_COMPRESS_AUTO || d.reserved != 0 || d.conv_c != 0)
             return sfail(s, CT_EINVAL, "request " + std::to_string(i) + ": invalid layer");
     }
     {

@@ -28,6 +28,7 @@ class LayerSpec:
     N: int
     seed: int
     layer_id: int
+    conv: tuple | None = None   # (C, H, W, k, stride, pad) of a convolution, whose Y is the im2col of its input
 
     @property
     def mkn(self) -> int:
@@ -55,10 +56,12 @@ def fc_small():
 def cnn():
     """VGG-style 3x3 convolutions (pad 1, stride 1) at batch 1 as im2col
     products, and the 25088 -> 4096 classifier layer at batch 1."""
-    shapes = [("conv64@56x56", 64, 576, 3136), ("conv128@28x28", 128, 1152, 784),
-              ("conv256@14x14", 256, 2304, 196), ("conv512@7x7", 512, 4608, 49),
-              ("fc25088x4096", 4096, 25088, 1)]
-    return [LayerSpec(n, M, K, N, 1001 + i, i + 1) for i, (n, M, K, N) in enumerate(shapes)]
+    shapes = [("conv64@56x56", 64, 576, 3136, (64, 56, 56, 3, 1, 1)),
+              ("conv128@28x28", 128, 1152, 784, (128, 28, 28, 3, 1, 1)),
+              ("conv256@14x14", 256, 2304, 196, (256, 14, 14, 3, 1, 1)),
+              ("conv512@7x7", 512, 4608, 49, (512, 7, 7, 3, 1, 1)),
+              ("fc25088x4096", 4096, 25088, 1, None)]
+    return [LayerSpec(n, M, K, N, 1001 + i, i + 1, g) for i, (n, M, K, N, g) in enumerate(shapes)]
 
 
 def transformer(encoders: int = 12):

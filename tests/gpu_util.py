@@ -28,12 +28,20 @@ def to_np(t: torch.Tensor) -> np.ndarray:
 def gpu_layers(ctx, specs, device="cuda:0"):
     from paper_2311_04406_amd import Layer
     return [Layer(s.M, s.K, s.N, s.seed, s.layer_id, device=device, f=getattr(s, "f", 0),
-                  in_bits=getattr(s, "in_bits", 0), limbs=getattr(ctx, "limbs", 2)) for s in specs]
+                  in_bits=getattr(s, "in_bits", 0), limbs=getattr(ctx, "limbs", 2),
+                  compress=getattr(s, "compress", 0), conv=getattr(s, "conv", None)) for s in specs]
+
+
+def oracle_compress(spec):
+    """The oracle's compressed dimension for a spec's compress setting (0 N, 1 M, 2 the cheaper)."""
+    c = getattr(spec, "compress", 0)
+    return O.cheaper_compress(spec.M, spec.K, spec.N) if c == 2 else c
 
 
 def oracle_run(mode, spec, key_seed, r0=0, r1=None, kbits=64):
     return O.run_layer(mode, spec.M, spec.K, spec.N, spec.seed, spec.layer_id, key_seed, r0, r1,
-                       getattr(spec, "f", 0), getattr(spec, "in_bits", 0), kbits)
+                       getattr(spec, "f", 0), getattr(spec, "in_bits", 0), kbits,
+                       oracle_compress(spec) if mode == O.MODE_COMPACT else 0, getattr(spec, "conv", None))
 
 
 def oracle_view(o, limbs):
@@ -76,7 +84,13 @@ def compare_layer(gl, ol, mode, r0=0, r1=None, dealt=True, what=""):
             raise AssertionError(f"{what}: {n} differs at {len(bad)} places, first {bad[:3].tolist()}")
     if mode == O.MODE_COMPACT:
         parts = {k: to_np(v) for k, v in gl.cvec_parts().items()}
-        pairs = [("Uc", ol["Uc"]), ("tBc0", ol["tBc"][0]), ("tBc1", ol["tBc"][1])]
+        along_m = getattr(gl, "along_m", False)
+        assert along_m == (ol.compress == 1), (what, "compressed dimension")
+        if along_m:  # vectors of length K and N: the whole layer
+            assert (r0, r1) == (0, gl.M)
+            pairs = [("Ec", ol["Ec"]), ("tAc0", ol["tAc"][0]), ("tAc1", ol["tAc"][1])]
+        else:
+            pairs = [("Uc", ol["Uc"]), ("tBc0", ol["tBc"][0]), ("tBc1", ol["tBc"][1])]
         for n, on in [("Dc", "Dc"), ("EUc", "EUc")]:
             pairs.append((n, ol[on]))
         for base in ("tCc", "tRc", "tZc", "tDc"):
@@ -84,9 +98,11 @@ def compare_layer(gl, ol, mode, r0=0, r1=None, dealt=True, what=""):
                 pairs.append((f"{base}{p}", ol[base][p]))
         for n, o in pairs:
             g = parts[n]
-            if n not in ("Uc", "tBc0", "tBc1"):
-                g = g[r0:r1]
-            assert np.array_equal(g, oracle_view(o, lw)), (what, n)
+            if not along_m and n not in ("Uc", "tBc0", "tBc1"):
+                g = g[r0:r1]  # the length-M vectors of the sampled rows
+            o = oracle_view(o, lw)
+            assert g.shape == o.shape, (what, n, g.shape, o.shape)
+            assert np.array_equal(g, o), (what, n)
 
 
 def compare_cs(gres, ol, which=(0, 1, 2), what=""):

@@ -112,7 +112,7 @@ static void sched_scenario(const char *name, uint64_t seed, size_t arena, int sl
         PendingReq r;
         r.id = i;
         r.kind = (rng() & 1) ? REQ_CHECK : REQ_TAG;
-        r.layer = ct_layer_desc{sh.M, sh.K, sh.N, 0, 0, 100 + (uint64_t)i, 1 + (uint64_t)i};
+        r.layer = ct_layer_desc{sh.M, sh.K, sh.N, 0, 0, 100 + (uint64_t)i, 1 + (uint64_t)i, 0, 0, 0, 0, 0, 0, 0, 0};
         r.arrival_us = t;
         reqs.push_back(r);
     }

@@ -67,6 +67,14 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu %zu\n", offsetof(ct_server_params, mode), offsetof(ct_request, layer),
          offsetof(ct_request, arrival_us), offsetof(ct_completion, done_us), offsetof(ct_completion, result),
          offsetof(ct_server_counts, arena_bytes), offsetof(ct_server_counts, arena_used));
+  printf("%zu %zu\n", offsetof(ct_layer_desc, compress), offsetof(ct_layer_desc, conv_pad));
+  {
+    const long long sh[4][3] = {{4096, 25088, 1}, {64, 576, 3136}, {7, 9, 7}, {3, 5, 2}};
+    for (int i = 0; i < 4; i++)
+      for (int c = 0; c < 3; c++)
+        printf("%lld ", (long long)CT_CVEC_LEN_FOR(sh[i][0], sh[i][1], sh[i][2], c));
+    printf("\n");
+  }
   return 0;
 }
 """
@@ -85,7 +93,9 @@ int main(void) {
            ctypes.sizeof(b.CtServerCounts),
            b.CtServerParams.mode.offset, b.CtRequest.layer.offset, b.CtRequest.arrival_us.offset,
            b.CtCompletion.done_us.offset, b.CtCompletion.result.offset, b.CtServerCounts.arena_bytes.offset,
-           b.CtServerCounts.arena_used.offset]
+           b.CtServerCounts.arena_used.offset, b.CtLayerDesc.compress.offset, b.CtLayerDesc.conv_pad.offset]
+    got += [b.cvec_len(M, K, N, c) for M, K, N in ((4096, 25088, 1), (64, 576, 3136), (7, 9, 7), (3, 5, 2))
+            for c in range(3)]
     assert got == vals
 
 
