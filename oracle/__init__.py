@@ -26,6 +26,7 @@ SRC = os.path.join(HERE, "ct_oracle.c")
 
 MODE_SPDZ2K = 0
 MODE_COMPACT = 1
+MAX_PARTIES = 5
 MODES = {"spdz2k": MODE_SPDZ2K, "compact": MODE_COMPACT}
 MASK64 = (1 << 64) - 1
 MASK128 = (1 << 128) - 1
@@ -47,10 +48,11 @@ class _Desc(ctypes.Structure):
                 ("r0", ctypes.c_int64), ("r1", ctypes.c_int64), ("f", ctypes.c_int64), ("in_bits", ctypes.c_int64),
                 ("kbits", ctypes.c_int64), ("compress", ctypes.c_int64),
                 ("conv_c", ctypes.c_int64), ("conv_h", ctypes.c_int64), ("conv_w", ctypes.c_int64),
-                ("conv_k", ctypes.c_int64), ("conv_stride", ctypes.c_int64), ("conv_pad", ctypes.c_int64)]
+                ("conv_k", ctypes.c_int64), ("conv_stride", ctypes.c_int64), ("conv_pad", ctypes.c_int64),
+                ("parties", ctypes.c_int64)]
 
 
-_P2 = ctypes.c_void_p * 2
+_P2 = ctypes.c_void_p * MAX_PARTIES   # one pointer per party slot
 _BUF_FIELDS = [
     ("X", 2), ("tX", 2), ("A", 2), ("tA", 2), ("E", 1),
     ("Y", 2), ("tY", 2), ("B", 2), ("tB", 2), ("U", 1),
@@ -64,7 +66,7 @@ _BUF_FIELDS = [
 
 class _Bufs(ctypes.Structure):
     _fields_ = [(n, _P2 if c == 2 else ctypes.c_void_p) for n, c in _BUF_FIELDS] + [
-        ("cs", ctypes.c_uint64 * 12), ("tag_mults", ctypes.c_uint64 * 2)]
+        ("cs", ctypes.c_uint64 * (3 * MAX_PARTIES * 2)), ("tag_mults", ctypes.c_uint64 * MAX_PARTIES)]
 
 
 _lib = None
@@ -85,6 +87,7 @@ def lib():
         L.or_draw_many.argtypes = [u64, u64, u64, i64, vp]
         L.or_key_shares.argtypes = [u64, vp]
         L.or_key_shares_k.argtypes = [u64, i64, vp]
+        L.or_key_shares_n.argtypes = [u64, i64, i64, vp]
         L.or_set_kbits.argtypes = [i64]
         L.or_deal.argtypes = [ctypes.POINTER(_Desc), vp, ctypes.c_int, ctypes.POINTER(_Bufs)]
         L.or_online.argtypes = [ctypes.c_int, ctypes.POINTER(_Desc), vp, ctypes.POINTER(_Bufs)]
@@ -155,9 +158,9 @@ def stream(layer_id: int, purpose: int) -> int:
     return ((layer_id << 16) | purpose) & MASK64
 
 
-def key_shares(key_seed: int, kbits: int = 64) -> np.ndarray:
-    out = np.zeros(2, dtype=np.uint64)
-    lib().or_key_shares_k(key_seed & MASK64, kbits, _ptr(out))
+def key_shares(key_seed: int, kbits: int = 64, parties: int = 2) -> np.ndarray:
+    out = np.zeros(parties, dtype=np.uint64)
+    lib().or_key_shares_n(key_seed & MASK64, kbits, parties, _ptr(out))
     return out
 
 
@@ -184,6 +187,7 @@ class OracleLayer:
     kbits: int = 64
     compress: int = 0                   # 0: along N (columns), 1: along M (rows; all rows)
     conv: tuple | None = None           # (C, H, W, k, stride, pad): Y is the im2col of a C x H x W input
+    parties: int = 2                    # 2..MAX_PARTIES
     arrays: dict = field(default_factory=dict)
     cs: np.ndarray | None = None        # [3 (E,U,D)][2 parties][2 limbs]
     tag_mults: np.ndarray | None = None
@@ -198,33 +202,37 @@ class OracleLayer:
             Ho, Wo = (H + 2 * pd - k) // st + 1, (W + 2 * pd - k) // st + 1
             if min(C, H, W, k, st) < 1 or pd < 0 or Ho < 1 or Wo < 1 or K != C * k * k or N != Ho * Wo:
                 raise ValueError("convolution geometry does not give this K and N")
+        if not 2 <= self.parties <= MAX_PARTIES:
+            raise ValueError(f"parties must be in [2, {MAX_PARTIES}]")
         kn = (self.conv[0], self.conv[1] * self.conv[2]) if self.conv is not None else (K, N)
+        P = self.parties
         shapes = {}
         for n in ("X", "tX", "A", "tA"):
-            shapes[n] = (2, rows, K)
+            shapes[n] = (P, rows, K)
         for n in ("Y", "tY", "B", "tB"):
-            shapes[n] = (2,) + kn
+            shapes[n] = (P,) + kn
         for n in ("C", "tC", "R", "tR", "Z", "tZ", "Rf", "tRf", "Zf", "tZf"):
-            shapes[n] = (2, rows, N)
+            shapes[n] = (P, rows, N)
         if self.compress not in (0, 1) or (self.compress == 1 and (self.r0, self.r1) != (0, self.M)):
             raise ValueError("compress is 0 (along N) or 1 (along M, over all rows)")
         L = N if self.compress == 1 else rows     # length of the compressed M x N quantities
-        shapes.update(E=(rows, K), U=kn, D=(rows, N), Uc=(K,), tBc=(2, K), Dc=(L,), EUc=(L,),
-                      tCc=(2, L), tRc=(2, L), tZc=(2, L), tDc=(2, L), Ec=(K,), tAc=(2, K))
+        shapes.update(E=(rows, K), U=kn, D=(rows, N), Uc=(K,), tBc=(P, K), Dc=(L,), EUc=(L,),
+                      tCc=(P, L), tRc=(P, L), tZc=(P, L), tDc=(P, L), Ec=(K,), tAc=(P, K))
         for n, s in shapes.items():
             self.arrays[n] = np.zeros(s + (2,), dtype=np.uint64)
-        self.delta = key_shares(self.key_seed, self.kbits)
+        self.delta = key_shares(self.key_seed, self.kbits, self.parties)
 
     def _desc(self):
         return _Desc(self.M, self.K, self.N, self.seed & MASK64, self.layer_id & MASK64, self.r0, self.r1,
-                     self.f, self.in_bits, self.kbits, self.compress, *(self.conv or (0, 0, 0, 0, 0, 0)))
+                     self.f, self.in_bits, self.kbits, self.compress, *(self.conv or (0, 0, 0, 0, 0, 0)),
+                     self.parties)
 
     def _bufs(self):
         b = _Bufs()
         for n, c in _BUF_FIELDS:
             a = self.arrays[n]
             if c == 2:
-                setattr(b, n, _P2(_ptr(a[0]), _ptr(a[1])))
+                setattr(b, n, _P2(*[_ptr(a[p]) for p in range(self.parties)]))
             else:
                 setattr(b, n, _ptr(a))
         return b
@@ -237,19 +245,19 @@ class OracleLayer:
     def online(self, mode: int):
         b = self._bufs()
         lib().or_online(mode, ctypes.byref(self._desc()), _ptr(self.delta), ctypes.byref(b))
-        self.tag_mults = np.array(b.tag_mults, dtype=np.uint64)
+        self.tag_mults = np.array(b.tag_mults, dtype=np.uint64)[:self.parties]
         return self
 
     def check(self, mode: int):
         b = self._bufs()
         lib().or_check(mode, ctypes.byref(self._desc()), _ptr(self.delta), ctypes.byref(b))
-        self.cs = np.array(b.cs, dtype=np.uint64).reshape(3, 2, 2)
+        self.cs = np.array(b.cs, dtype=np.uint64).reshape(3, MAX_PARTIES, 2)[:, :self.parties].copy()
         return self
 
     def cs_sums(self):
         """sum over parties of each check value, mod 2^{k+s}: [E, U, D]."""
         mask = MASK128 if self.kbits == 64 else MASK64
-        return [(u128(self.cs[w, 0]) + u128(self.cs[w, 1])) & mask for w in range(3)]
+        return [sum(u128(self.cs[w, p]) for p in range(self.parties)) & mask for w in range(3)]
 
     def accept(self) -> bool:
         return all(s == 0 for s in self.cs_sums())
@@ -260,12 +268,12 @@ class OracleLayer:
 
 def run_layer(mode: int, M: int, K: int, N: int, seed: int, layer_id: int, key_seed: int,
               r0: int = 0, r1: int | None = None, f: int = 0, in_bits: int = 0, kbits: int = 64,
-              compress: int = 0, conv: tuple | None = None) -> OracleLayer:
+              compress: int = 0, conv: tuple | None = None, parties: int = 2) -> OracleLayer:
     """Dealer, online phase and verification of one layer on rows [r0, r1)
     (with f > 0 the product is truncated by f fractional bits; kbits = k = s;
     compress = 1 compresses along M, over all rows; conv = (C, H, W, k,
     stride, pad) makes the layer a convolution of a C x H x W input)."""
-    L = OracleLayer(M, K, N, seed, layer_id, key_seed, r0, r1, f, in_bits, kbits, compress, conv)
+    L = OracleLayer(M, K, N, seed, layer_id, key_seed, r0, r1, f, in_bits, kbits, compress, conv, parties)
     return L.deal().online(mode).check(mode)
 
 

@@ -95,13 +95,21 @@ static u128 draw128(uint64_t seed, uint64_t stream, uint64_t e) {
 }
 
 /* F_MAC Initialize: key shares [Delta]_p uniform in Z_{2^s} (the draw mod 2^s). */
-void or_key_shares_k(uint64_t key_seed, int64_t kbits, uint64_t delta[2]) {
-    for (int p = 0; p < 2; p++) {
+void or_key_shares_n(uint64_t key_seed, int64_t kbits, int64_t parties, uint64_t *delta) {
+    for (int64_t p = 0; p < parties; p++) {
         const uint64_t x = or_draw(key_seed, stream_of(OR_GLOBAL_LAYER, OR_P_KEY + (uint64_t)p), 0);
         delta[p] = kbits == 32 ? (x & 0xFFFFFFFFULL) : x;
     }
 }
+void or_key_shares_k(uint64_t key_seed, int64_t kbits, uint64_t delta[2]) { or_key_shares_n(key_seed, kbits, 2, delta); }
 void or_key_shares(uint64_t key_seed, uint64_t delta[2]) { or_key_shares_k(key_seed, 64, delta); }
+
+/* parties of a descriptor */
+static int parties_of(const or_desc *d) {
+    if (d->parties == 0) return 2;
+    if (d->parties < 2 || d->parties > OR_MAX_PARTIES) abort();
+    return (int)d->parties;
+}
 
 /* combiner draws: uniform in Z_{2^s} */
 static void draw_chi(uint64_t seed, uint64_t stream, uint64_t first, int64_t n, uint64_t *out) {
@@ -109,9 +117,13 @@ static void draw_chi(uint64_t seed, uint64_t stream, uint64_t first, int64_t n, 
     for (int64_t i = 0; i < n; i++) out[i] = mod_s(out[i]);
 }
 
-/* The key used in every tag relation is the integer sum [Delta]_0 + [Delta]_1
- * (< 2^{s+1}), taken mod 2^{k+s}; see the reading of Sec. 2.4 in the design notes. */
-static u128 key_sum(const uint64_t delta[2]) { return (u128)delta[0] + (u128)delta[1]; }
+/* The key used in every tag relation is the integer sum of the key shares
+ * (< n 2^s), taken mod 2^{k+s}; see the reading of Sec. 2.4 in the design notes. */
+static u128 key_sum(const uint64_t *delta, int np) {
+    u128 s = 0;
+    for (int p = 0; p < np; p++) s += (u128)delta[p];
+    return s;
+}
 
 /* ------------------------------------------------------------------ */
 /* building blocks                                                      */
@@ -184,18 +196,24 @@ void or_compact_cs(int64_t rows, const uint64_t *Dc, const uint64_t *tDc, const 
 /* ------------------------------------------------------------------ */
 /* preprocessing: a trusted dealer in place of F_MAC Auth               */
 
-/* Authenticated 2-party sharing of one lifted value (Sec. 2.4): party 0's value
- * and tag shares are fresh draws, party 1's complete the sums
- *   [v]_0 + [v]_1 = v~,   [t]_0 + [t]_1 = Delta~ * v~   (mod 2^{k+s}). */
-static void auth_share(u128 lift, u128 dsum, uint64_t seed, uint64_t layer_id, int obj, uint64_t e,
-                       uint64_t *v0, uint64_t *v1, uint64_t *t0, uint64_t *t1, int64_t at) {
-    u128 s0 = draw128(seed, stream_of(layer_id, OR_P_VSH + (uint64_t)obj), e);
-    u128 tag = dsum * lift;
-    u128 ts0 = draw128(seed, stream_of(layer_id, OR_P_TSH + (uint64_t)obj), e);
-    st(v0, at, s0);
-    st(v1, at, lift - s0);
-    st(t0, at, ts0);
-    st(t1, at, tag - ts0);
+/* Authenticated n-party sharing of one lifted value (Sec. 2.4): the value and
+ * tag shares of parties 0..n-2 are fresh draws (party p from the streams of
+ * purpose VSH / TSH + object + 256 p), the last party's complete the sums
+ *   sum_p [v]_p = v~,   sum_p [t]_p = Delta~ * v~   (mod 2^{k+s}). */
+static void auth_share(int np, u128 lift, u128 dsum, uint64_t seed, uint64_t layer_id, int obj, uint64_t e,
+                       uint64_t *const v[], uint64_t *const t[], int64_t at) {
+    u128 sv = 0, stg = 0;
+    for (int p = 0; p < np - 1; p++) {
+        const uint64_t shift = (uint64_t)p << 8;
+        const u128 a = draw128(seed, stream_of(layer_id, OR_P_VSH + (uint64_t)obj + shift), e);
+        const u128 b = draw128(seed, stream_of(layer_id, OR_P_TSH + (uint64_t)obj + shift), e);
+        st(v[p], at, a);
+        st(t[p], at, b);
+        sv += a;
+        stg += b;
+    }
+    st(v[np - 1], at, lift - sv);
+    st(t[np - 1], at, dsum * lift - stg);
 }
 
 enum { OBJ_X = 1, OBJ_Y = 2, OBJ_A = 3, OBJ_B = 4, OBJ_C = 5, OBJ_R = 6, OBJ_RF = 7 };
@@ -262,11 +280,12 @@ static u128 input_lift(uint64_t draw, int64_t in_bits) {
  * uniform in Z_{2^{k+s}}; C~ = A~ * B~ mod 2^{k+s}.  With f > 0 also the
  * truncated mask of Figs. 3 and 6, R^f = (R mod 2^k) / 2^f (an integer below
  * 2^{k-f}), lifted with a uniform upper limb and authenticated like the rest. */
-void or_deal(const or_desc *d, const uint64_t delta[2], int with_inputs, or_bufs *b) {
+void or_deal(const or_desc *d, const uint64_t *delta, int with_inputs, or_bufs *b) {
     or_set_kbits(d->kbits);
     const int64_t M = d->M, K = d->K, N = d->N, r0 = d->r0, rows = d->r1 - d->r0;
     const uint64_t seed = d->seed, lid = d->layer_id;
-    const u128 dsum = key_sum(delta);
+    const int np = parties_of(d);
+    const u128 dsum = key_sum(delta, np);
     (void)M;
     conv_validate(d);
     /* the right operand's buffers: K x N, or for a convolution the input's
@@ -293,28 +312,28 @@ void or_deal(const or_desc *d, const uint64_t delta[2], int with_inputs, or_bufs
             uint64_t e = (uint64_t)((r0 + i) * K + k);
             if (with_inputs) {
                 u128 x = input_lift(or_draw(seed, stream_of(lid, OR_P_LIFT_X), e), d->in_bits);
-                auth_share(x, dsum, seed, lid, OBJ_X, e, b->X[0], b->X[1], b->tX[0], b->tX[1], at);
+                auth_share(np, x, dsum, seed, lid, OBJ_X, e, b->X, b->tX, at);
             }
-            auth_share(ld(At, at), dsum, seed, lid, OBJ_A, e, b->A[0], b->A[1], b->tA[0], b->tA[1], at);
+            auth_share(np, ld(At, at), dsum, seed, lid, OBJ_A, e, b->A, b->tA, at);
         }
     for (int64_t e = 0; e < nr; e++) {
         if (with_inputs) {
             u128 y = input_lift(or_draw(seed, stream_of(lid, OR_P_LIFT_Y), (uint64_t)e), d->in_bits);
-            auth_share(y, dsum, seed, lid, OBJ_Y, (uint64_t)e, b->Y[0], b->Y[1], b->tY[0], b->tY[1], e);
+            auth_share(np, y, dsum, seed, lid, OBJ_Y, (uint64_t)e, b->Y, b->tY, e);
         }
-        auth_share(ld(Bt, e), dsum, seed, lid, OBJ_B, (uint64_t)e, b->B[0], b->B[1], b->tB[0], b->tB[1], e);
+        auth_share(np, ld(Bt, e), dsum, seed, lid, OBJ_B, (uint64_t)e, b->B, b->tB, e);
     }
     for (int64_t i = 0; i < rows; i++)
         for (int64_t j = 0; j < N; j++) {
             int64_t at = i * N + j;
             uint64_t e = (uint64_t)((r0 + i) * N + j);
             u128 r = draw128(seed, stream_of(lid, OR_P_LIFT_R), e);
-            auth_share(ld(Ct, at), dsum, seed, lid, OBJ_C, e, b->C[0], b->C[1], b->tC[0], b->tC[1], at);
-            auth_share(r, dsum, seed, lid, OBJ_R, e, b->R[0], b->R[1], b->tR[0], b->tR[1], at);
+            auth_share(np, ld(Ct, at), dsum, seed, lid, OBJ_C, e, b->C, b->tC, at);
+            auth_share(np, r, dsum, seed, lid, OBJ_R, e, b->R, b->tR, at);
             if (d->f > 0) {
                 const uint64_t up = mod_s(or_draw(seed, stream_of(lid, OR_P_LIFT_RF), e));
                 u128 rf = (u128)(mod_k(r) >> d->f) | ((u128)up << g_kbits);
-                auth_share(rf, dsum, seed, lid, OBJ_RF, e, b->Rf[0], b->Rf[1], b->tRf[0], b->tRf[1], at);
+                auth_share(np, rf, dsum, seed, lid, OBJ_RF, e, b->Rf, b->tRf, at);
             }
         }
     free(At);
@@ -328,11 +347,13 @@ void or_deal(const or_desc *d, const uint64_t delta[2], int with_inputs, or_bufs
 /* Pi_BatchRec open (Fig. 1, steps 1-3) of W = P - Q for authenticated P, Q:
  * each party's share [W]_p = [P]_p - [Q]_p is broadcast and W = sum_p [W]_p
  * mod 2^{k+s}.  The zero mask of Fig. 1 is omitted: Q is a uniform Beaver mask. */
-static void open_diff(int64_t n, uint64_t *const P[2], uint64_t *const Q[2], uint64_t *W) {
+/* Pi_BatchRec open of W = P - Q: party p broadcasts [P]_p - [Q]_p, and W is
+ * the sum of the broadcasts. */
+static void open_diff(int np, int64_t n, uint64_t *const P[], uint64_t *const Q[], uint64_t *W) {
     for (int64_t e = 0; e < n; e++) {
-        u128 w0 = ld(P[0], e) - ld(Q[0], e);
-        u128 w1 = ld(P[1], e) - ld(Q[1], e);
-        st(W, e, w0 + w1);
+        u128 w = 0;
+        for (int p = 0; p < np; p++) w += ld(P[p], e) - ld(Q[p], e);
+        st(W, e, w);
     }
 }
 
@@ -351,8 +372,9 @@ static void add_into(int64_t n, uint64_t *acc, const uint64_t *x) {
  * with E^c = chi^T E and [tA^c]_p = chi^T [tA]_p of length K and every other
  * compressed vector of length N.  The public vectors E^c, D~^c and E^c U are
  * charged to each party. */
-static void compact_rows(const or_desc *d, const uint64_t delta[2], or_bufs *b, const uint64_t opt[2]) {
+static void compact_rows(const or_desc *d, const uint64_t *delta, or_bufs *b, const uint64_t *opt) {
     const int64_t M = d->M, K = d->K, N = d->N;
+    const int np = parties_of(d);
     if (d->r0 != 0 || d->r1 != M) abort();
     uint64_t *chi = (uint64_t *)malloc((size_t)(M > 0 ? M : 1) * 8);
     uint64_t *v = alloc128(N);
@@ -363,7 +385,7 @@ static void compact_rows(const or_desc *d, const uint64_t delta[2], or_bufs *b, 
     or_compress_rows(M, N, b->D, chi, b->Dc);
     or_matmul(1, K, N, b->Ec, b->U, b->EUc);
     const uint64_t pub_mults = g_mults - m_pub;
-    for (int p = 0; p < 2; p++) {
+    for (int p = 0; p < np; p++) {
         uint64_t m0 = g_mults;
         or_compress_rows(M, K, b->tA[p], chi, b->tAc[p]);
         or_compress_rows(M, N, b->tC[p], chi, b->tCc[p]);
@@ -384,25 +406,26 @@ static void compact_rows(const or_desc *d, const uint64_t delta[2], or_bufs *b, 
     free(v);
 }
 
-static void online_product(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b);
+static void online_product(int mode, const or_desc *d, const uint64_t *delta, or_bufs *b);
 
 /* The online phase.  A convolution opens U = Y - B on the input's shape (its
  * elements are what the parties broadcast) and then runs the product on the
  * im2col matrices of Y, B and their tags (Eq. (4)); im2col is linear, so these
  * are authenticated shares of the im2col matrices. */
-void or_online(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) {
+void or_online(int mode, const or_desc *d, const uint64_t *delta, or_bufs *b) {
     or_set_kbits(d->kbits);
     if (d->conv_c <= 0) {
         online_product(mode, d, delta, b);
         return;
     }
     conv_validate(d);
+    const int np = parties_of(d);
     const int64_t KN = d->K * d->N, nr = or_right_len(d);
-    open_diff(nr, b->Y, b->B, b->U);
+    open_diff(np, nr, b->Y, b->B, b->U);
     or_bufs x = *b;
-    uint64_t *tmp[9];
-    for (int i = 0; i < 9; i++) tmp[i] = alloc128(KN);
-    for (int p = 0; p < 2; p++) {
+    uint64_t *tmp[4 * OR_MAX_PARTIES + 1];
+    for (int i = 0; i < 4 * np + 1; i++) tmp[i] = alloc128(KN);
+    for (int p = 0; p < np; p++) {
         or_im2col(d, b->Y[p], tmp[4 * p + 0]);
         or_im2col(d, b->tY[p], tmp[4 * p + 1]);
         or_im2col(d, b->B[p], tmp[4 * p + 2]);
@@ -412,22 +435,22 @@ void or_online(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) 
         x.B[p] = tmp[4 * p + 2];
         x.tB[p] = tmp[4 * p + 3];
     }
-    x.U = tmp[8];
+    x.U = tmp[4 * np];
     or_desc dx = *d;
     dx.conv_c = 0;
     online_product(mode, &dx, delta, &x);
-    b->tag_mults[0] = x.tag_mults[0];
-    b->tag_mults[1] = x.tag_mults[1];
-    for (int i = 0; i < 9; i++) free(tmp[i]);
+    for (int p = 0; p < np; p++) b->tag_mults[p] = x.tag_mults[p];
+    for (int i = 0; i < 4 * np + 1; i++) free(tmp[i]);
 }
 
-static void online_product(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) {
+static void online_product(int mode, const or_desc *d, const uint64_t *delta, or_bufs *b) {
     const int64_t K = d->K, N = d->N, rows = d->r1 - d->r0;
     const uint64_t seed = d->seed, lid = d->layer_id;
+    const int np = parties_of(d);
 
     /* Fig. 7 online step 1: open E = X - A and U = Y - B. */
-    open_diff(rows * K, b->X, b->A, b->E);
-    open_diff(K * N, b->Y, b->B, b->U);
+    open_diff(np, rows * K, b->X, b->A, b->E);
+    open_diff(np, K * N, b->Y, b->B, b->U);
 
     /* Fig. 7 online step 2 and Eq. (2):
      *   [Z]_p = [C]_p + E*[B]_p + [A]_p*U, and the public term E*U is added by
@@ -437,7 +460,7 @@ static void online_product(int mode, const or_desc *d, const uint64_t delta[2], 
     uint64_t m_eu = g_mults;
     or_matmul(rows, K, N, b->E, b->U, EU);
     const uint64_t eu_mults = g_mults - m_eu;
-    for (int p = 0; p < 2; p++) {
+    for (int p = 0; p < np; p++) {
         memcpy(b->Z[p], b->C[p], (size_t)(rows * N) * 16);
         or_matmul(rows, K, N, b->E, b->B[p], tmp);
         add_into(rows * N, b->Z[p], tmp);
@@ -448,7 +471,7 @@ static void online_product(int mode, const or_desc *d, const uint64_t delta[2], 
 
     /* Open D = R - Z (Pi_OptMAC step 2 in COMPACT mode; Pi_Truncation step 1 in
      * SPDZ2k mode), kept as the full lift D~ mod 2^{k+s}. */
-    open_diff(rows * N, b->R, b->Z, b->D);
+    open_diff(np, rows * N, b->R, b->Z, b->D);
 
     /* f > 0: truncation by the opened D (OptMAC&Trunc, Fig. 6, ExpandTrunc
      * steps 2-4, in CompactTag mode; Pi_Truncation, Fig. 3 online step 2, after
@@ -459,7 +482,7 @@ static void online_product(int mode, const or_desc *d, const uint64_t delta[2], 
     if (d->f > 0) {
         for (int64_t e = 0; e < rows * N; e++) {
             const uint64_t df = mod_k(ld(b->D, e)) >> d->f;
-            for (int p = 0; p < 2; p++) {
+            for (int p = 0; p < np; p++) {
                 st(b->Zf[p], e, ld(b->Rf[p], e) - (p == 0 ? (u128)df : (u128)0));
                 st(b->tZf[p], e, ld(b->tRf[p], e) - (u128)delta[p] * df);
             }
@@ -470,7 +493,7 @@ static void online_product(int mode, const or_desc *d, const uint64_t delta[2], 
         /* Eq. (3): [tZ]_p = [tC]_p + E*[tB]_p + [tA]_p*U + [Delta]_p * (E*U);
          * the key term is added by every party (it is a share of Delta~ * EU).
          * Every party forms E*U itself, so its cost is charged to each. */
-        for (int p = 0; p < 2; p++) {
+        for (int p = 0; p < np; p++) {
             uint64_t m0 = g_mults;
             memcpy(b->tZ[p], b->tC[p], (size_t)(rows * N) * 16);
             or_matmul(rows, K, N, b->E, b->tB[p], tmp);
@@ -485,8 +508,8 @@ static void online_product(int mode, const or_desc *d, const uint64_t delta[2], 
         }
     } else {
         /* Pi_OptMAC step 3: [tZ]_p = [tR]_p - [Delta]_p * D~. */
-        uint64_t opt[2];
-        for (int p = 0; p < 2; p++) {
+        uint64_t opt[OR_MAX_PARTIES];
+        for (int p = 0; p < np; p++) {
             uint64_t m0 = g_mults;
             for (int64_t e = 0; e < rows * N; e++) {
                 st(b->tZ[p], e, ld(b->tR[p], e) - (u128)delta[p] * ld(b->D, e));
@@ -517,7 +540,7 @@ static void online_product(int mode, const or_desc *d, const uint64_t delta[2], 
         or_matmul(rows, K, 1, b->E, b->Uc, b->EUc);
         const uint64_t pub_mults = g_mults - m_pub;
         uint64_t *v = alloc128(rows);
-        for (int p = 0; p < 2; p++) {
+        for (int p = 0; p < np; p++) {
             uint64_t m0 = g_mults;
             or_compress(K, N, b->tB[p], chi, b->tBc[p]);
             or_compress(rows, N, b->tC[p], chi, b->tCc[p]);
@@ -549,8 +572,9 @@ static void tag_diff(int64_t n, const uint64_t *tP, const uint64_t *tQ, uint64_t
     for (int64_t e = 0; e < n; e++) st(out, e, ld(tP, e) - ld(tQ, e));
 }
 
-void or_check(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) {
+void or_check(int mode, const or_desc *d, const uint64_t *delta, or_bufs *b) {
     or_set_kbits(d->kbits);
+    const int np = parties_of(d);
     const int64_t M = d->M, K = d->K, N = d->N, r0 = d->r0, rows = d->r1 - d->r0;
     const uint64_t seed = d->seed, lid = d->layer_id;
     /* U is checked on the elements that were opened: K x N, or the input's shape */
@@ -565,12 +589,12 @@ void or_check(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) {
     /* Fig. 7 verification step 1: Pi_BatchRec tag check of E and of U, one
      * public combiner per element (Fig. 1 tag-check step 1). */
     draw_chi(seed, stream_of(lid, OR_P_CHI_E), (uint64_t)(r0 * K), rows * K, chi);
-    for (int p = 0; p < 2; p++) {
+    for (int p = 0; p < np; p++) {
         tag_diff(rows * K, b->tX[p], b->tA[p], tW);
         or_batchrec_cs(rows * K, b->E, tW, chi, delta[p], b->cs[0][p]);
     }
     draw_chi(seed, stream_of(lid, OR_P_CHI_U), 0, nr, chi);
-    for (int p = 0; p < 2; p++) {
+    for (int p = 0; p < np; p++) {
         tag_diff(nr, b->tY[p], b->tB[p], tW);
         or_batchrec_cs(nr, b->U, tW, chi, delta[p], b->cs[1][p]);
     }
@@ -579,7 +603,7 @@ void or_check(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) {
         /* Pi_Truncation verification: Pi_BatchRec tag check of D = R - Z,
          * [tD]_p = [tR]_p - [tZ]_p. */
         draw_chi(seed, stream_of(lid, OR_P_CHI_D), (uint64_t)(r0 * N), rows * N, chi);
-        for (int p = 0; p < 2; p++) {
+        for (int p = 0; p < np; p++) {
             tag_diff(rows * N, b->tR[p], b->tZ[p], tW);
             or_batchrec_cs(rows * N, b->D, tW, chi, delta[p], b->cs[2][p]);
         }
@@ -590,7 +614,7 @@ void or_check(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b) {
         uint64_t *ch = (uint64_t *)malloc((size_t)(len > 0 ? len : 1) * 8);
         if (!ch) abort();
         draw_chi(seed, stream_of(lid, OR_P_CHIHAT), (uint64_t)first, len, ch);
-        for (int p = 0; p < 2; p++) or_compact_cs(len, b->Dc, b->tDc[p], ch, delta[p], b->cs[2][p]);
+        for (int p = 0; p < np; p++) or_compact_cs(len, b->Dc, b->tDc[p], ch, delta[p], b->cs[2][p]);
         free(ch);
     }
     free(tW);

@@ -19,6 +19,11 @@
 #define OR_MODE_SPDZ2K 0
 #define OR_MODE_COMPACT 1
 
+/* Parties of one computation: 2 to OR_MAX_PARTIES (Appendix "CompactTag
+ * scales with parties"); every per-party array below has this many slots, of
+ * which the first `parties` are used. */
+#define OR_MAX_PARTIES 5
+
 /* Purposes of the counter-based generator streams; stream = (layer_id << 16) | purpose. */
 #define OR_P_LIFT_X 0x01
 #define OR_P_LIFT_Y 0x02
@@ -52,29 +57,32 @@ typedef struct {
      * buffers Y, tY, B, tB, U hold conv_c x conv_h x conv_w elements: the input,
      * its mask and the opened U of that shape.  conv_c = 0: a plain product. */
     int64_t conv_c, conv_h, conv_w, conv_k, conv_stride, conv_pad;
+    int64_t parties;          /* 2..OR_MAX_PARTIES; 0 means 2 */
 } or_desc;
 
 /* Every pointer is a caller-owned array of (lo, hi) uint64 pairs. */
 typedef struct {
     /* rows x K */
-    uint64_t *X[2], *tX[2], *A[2], *tA[2], *E;
+    uint64_t *X[OR_MAX_PARTIES], *tX[OR_MAX_PARTIES], *A[OR_MAX_PARTIES], *tA[OR_MAX_PARTIES], *E;
     /* K x N */
-    uint64_t *Y[2], *tY[2], *B[2], *tB[2], *U;
+    uint64_t *Y[OR_MAX_PARTIES], *tY[OR_MAX_PARTIES], *B[OR_MAX_PARTIES], *tB[OR_MAX_PARTIES], *U;
     /* rows x N */
-    uint64_t *C[2], *tC[2], *R[2], *tR[2], *Z[2], *tZ[2], *D;
+    uint64_t *C[OR_MAX_PARTIES], *tC[OR_MAX_PARTIES], *R[OR_MAX_PARTIES], *tR[OR_MAX_PARTIES];
+    uint64_t *Z[OR_MAX_PARTIES], *tZ[OR_MAX_PARTIES], *D;
     /* compact-tag vectors, compress = 0: K entries */
-    uint64_t *Uc, *tBc[2];
+    uint64_t *Uc, *tBc[OR_MAX_PARTIES];
     /* compact-tag vectors, compress = 0: rows entries (W^c = W chi);
      * compress = 1: N entries (W^c = chi^T W, and EUc holds E^c U) */
-    uint64_t *Dc, *EUc, *tCc[2], *tRc[2], *tZc[2], *tDc[2];
+    uint64_t *Dc, *EUc;
+    uint64_t *tCc[OR_MAX_PARTIES], *tRc[OR_MAX_PARTIES], *tZc[OR_MAX_PARTIES], *tDc[OR_MAX_PARTIES];
     /* compact-tag vectors, compress = 1: K entries, E^c = chi^T E and [tA^c]_p = chi^T [tA]_p */
-    uint64_t *Ec, *tAc[2];
+    uint64_t *Ec, *tAc[OR_MAX_PARTIES];
     /* f > 0, rows x N: truncated mask R^f (dealt) and truncated output Z^f */
-    uint64_t *Rf[2], *tRf[2], *Zf[2], *tZf[2];
+    uint64_t *Rf[OR_MAX_PARTIES], *tRf[OR_MAX_PARTIES], *Zf[OR_MAX_PARTIES], *tZf[OR_MAX_PARTIES];
     /* check-value shares cs[W][party][limb], W in (E, U, D) */
-    uint64_t cs[3][2][2];
+    uint64_t cs[3][OR_MAX_PARTIES][2];
     /* local multiplications spent on tags, per party */
-    uint64_t tag_mults[2];
+    uint64_t tag_mults[OR_MAX_PARTIES];
 } or_bufs;
 
 uint64_t or_mix64(uint64_t z);
@@ -84,12 +92,15 @@ void or_draw_many(uint64_t seed, uint64_t stream, uint64_t first, int64_t n, uin
 
 void or_key_shares(uint64_t key_seed, uint64_t delta[2]);
 void or_key_shares_k(uint64_t key_seed, int64_t kbits, uint64_t delta[2]);
+/* key shares of parties 0..parties-1 */
+void or_key_shares_n(uint64_t key_seed, int64_t kbits, int64_t parties, uint64_t *delta);
 /* Ring width of the building blocks below (k = s = kbits); or_deal,
  * or_online and or_check set it from their descriptor. */
 void or_set_kbits(int64_t kbits);
-void or_deal(const or_desc *d, const uint64_t delta[2], int with_inputs, or_bufs *b);
-void or_online(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b);
-void or_check(int mode, const or_desc *d, const uint64_t delta[2], or_bufs *b);
+/* delta holds the key shares of the descriptor's parties */
+void or_deal(const or_desc *d, const uint64_t *delta, int with_inputs, or_bufs *b);
+void or_online(int mode, const or_desc *d, const uint64_t *delta, or_bufs *b);
+void or_check(int mode, const or_desc *d, const uint64_t *delta, or_bufs *b);
 
 /* Elements of the right operand's buffers: conv_c conv_h conv_w, or K N. */
 int64_t or_right_len(const or_desc *d);

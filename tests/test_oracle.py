@@ -786,3 +786,106 @@ def test_conv_with_compression_along_m_and_k32(built, kbits):
 def test_conv_geometry_is_validated(built):
     with pytest.raises(ValueError):
         O.OracleLayer(3, 18, 24, 1, 1, 1, conv=(2, 5, 5, 3, 1, 1))
+
+
+# ---------------------------------------------------------------- n parties
+
+def nlift(L, name):
+    """sum of all parties' shares, mod 2^128"""
+    return sum(ints(L[name][p]) for p in range(L.parties)) % R
+
+
+@pytest.mark.parametrize("parties", [3, 4, 5])
+@pytest.mark.parametrize("shape", [(2, 3, 4), (5, 7, 1), (6, 4, 9)])
+@pytest.mark.parametrize("mode", [O.MODE_SPDZ2K, O.MODE_COMPACT])
+def test_parties_plain_definitions(built, parties, shape, mode):
+    """With n parties the shares of every dealt value sum to its lift (the
+    lifts do not depend on n), sum_p [Z]_p = X~ Y~, the tags of Z sum to
+    Delta~ Z~ with Delta~ the sum of the n key shares, and the check accepts."""
+    M, K, N = shape
+    L = O.run_layer(mode, M, K, N, 20 + M, 2, 77, parties=parties)
+    X, Y, A, B, Rm = lifts_from_prng(L)
+    assert (nlift(L, "X") == X).all() and (nlift(L, "Y") == Y).all() and (nlift(L, "A") == A).all()
+    assert (nlift(L, "B") == B).all() and (nlift(L, "R") == Rm).all()
+    dn = sum(int(v) for v in L.delta)
+    assert len(L.delta) == parties
+    assert list(L.delta[:2]) == list(O.key_shares(77))          # party keys do not depend on n
+    for n in ("X", "A", "C", "R"):
+        assert (nlift(L, "t" + n) == (dn * nlift(L, n)) % R).all(), n
+    XY = omatmul(X, Y)
+    assert (nlift(L, "Z") == XY).all()
+    assert (ints(L["D"]) == (Rm - XY) % R).all()
+    assert (nlift(L, "tZ") == (dn * XY) % R).all()
+    assert L.accept()
+
+
+@pytest.mark.parametrize("parties", [3, 5])
+def test_parties_dealer_streams(built, parties):
+    """Party p < n - 1 draws its value and tag shares from the streams of
+    purpose 0x10 / 0x20 + object + 256 p; the last party completes the sums
+    (with n = 2 this is the two-party dealer)."""
+    M, K, N = 2, 3, 2
+    L = O.OracleLayer(M, K, N, seed=11, layer_id=3, key_seed=9, parties=parties).deal()
+    for p in range(parties - 1):
+        for i in range(M):
+            for k in range(K):
+                e = i * K + k
+                d = lambda purpose: (ref.draw(11, ref.stream(3, purpose), 2 * e)
+                                     | (ref.draw(11, ref.stream(3, purpose), 2 * e + 1) << 64))
+                assert O.u128(L["A"][p][i, k]) == d(0x10 + 3 + 256 * p)
+                assert O.u128(L["tA"][p][i, k]) == d(0x20 + 3 + 256 * p)
+
+
+@pytest.mark.parametrize("parties", [3, 4])
+def test_parties_cross_mode_identity(built, parties):
+    """Per party, the compact tag equals the SPDZ2k tag compressed by chi."""
+    M, K, N = 4, 5, 3
+    S = O.run_layer(O.MODE_SPDZ2K, M, K, N, 31, 5, 4, parties=parties)
+    C = O.run_layer(O.MODE_COMPACT, M, K, N, 31, 5, 4, parties=parties)
+    chi = [ref.draw(31, ref.stream(5, 0x30), j) for j in range(N)]
+    for n in ("Z", "E", "U", "D"):
+        assert (S[n] == C[n]).all(), n
+    for p in range(parties):
+        tZs = ints(S["tZ"][p]).reshape(M, N)
+        expect = [sum(int(tZs[i, j]) * chi[j] for j in range(N)) % R for i in range(M)]
+        assert ints(C["tZc"][p]).tolist() == expect, p
+
+
+@pytest.mark.parametrize("parties", [2, 3, 5])
+def test_parties_tag_work_per_party_is_unchanged(built, parties):
+    """The tag multiplications of each party are the two-party closed forms of
+    Sec. 3.4.3 for any number of parties (Appendix: CompactTag scales with
+    parties)."""
+    M, K, N = 6, 4, 9
+    for mode in (O.MODE_SPDZ2K, O.MODE_COMPACT):
+        L = O.run_layer(mode, M, K, N, 3, 1, 2, parties=parties)
+        want = O.spdz2k_tag_mults(M, K, N) if mode == O.MODE_SPDZ2K else O.compact_tag_mults(M, K, N)
+        assert list(L.tag_mults) == [want] * parties
+
+
+@pytest.mark.parametrize("parties", [3, 5])
+@pytest.mark.parametrize("mode", [O.MODE_SPDZ2K, O.MODE_COMPACT])
+@pytest.mark.parametrize("target", [("X", 0), ("tA", 0), ("Y", 1), ("tB", 1), ("C", 2), ("tR", 2)])
+def test_parties_flipped_bit_aborts(built, parties, mode, target):
+    name, w = target
+    M, K, N = 3, 4, 5
+    for party in (0, parties // 2, parties - 1):
+        L = O.OracleLayer(M, K, N, seed=7, layer_id=4, key_seed=3, parties=parties).deal()
+        L[name][party].reshape(-1, 2)[5, 0] ^= np.uint64(1 << 17)
+        L.online(mode).check(mode)
+        assert L.cs_sums()[w] != 0 and not L.accept(), (name, party)
+
+
+@pytest.mark.parametrize("parties", [3, 4])
+def test_parties_with_truncation_conv_and_compression_along_m(built, parties):
+    """n parties with f > 0 (only party 0 subtracts the public term), a
+    convolution, and the compression along M."""
+    L = O.run_layer(O.MODE_COMPACT, 4, 18, 25, 5, 6, 7, f=9, parties=parties, compress=1,
+                    conv=(2, 5, 5, 3, 1, 1))
+    assert L.accept()
+    dn = sum(int(v) for v in L.delta)
+    assert (nlift(L, "tZf") == (dn * nlift(L, "Zf")) % R).all()
+    D = ints(L["D"]) % (1 << 64)
+    # R^f = (R mod 2^k) / 2^f below 2^k, and the truncated output reconstructs to R^f - (D mod 2^k) / 2^f
+    assert (nlift(L, "Rf") % (1 << 64) == (nlift(L, "R") % (1 << 64)) // 2 ** 9).all()
+    assert (nlift(L, "Zf") == (nlift(L, "Rf") - D // 2 ** 9) % R).all()
