@@ -179,11 +179,12 @@ def run_steps(ctx, mode_id, layer_groups, out_dev, steps, warmup, torch, timing=
     return t1 - t0, per, stages
 
 
-def cpu_baseline(specs, min_seconds: float = 10.0, kbits: int = 64):
+def cpu_baseline(specs, min_seconds: float = 10.0, kbits: int = 64, implicit: bool = False):
     """The oracle (single-threaded C, -O2) on a bounded sample of the workload:
     every layer with M * K * N below 2^28 in full, and the first 2048 rows of
     any larger one (at most six layers); online phase + verification in the
-    CompactTag protocol (the dealer is untimed).  The sample is repeated
+    CompactTag protocol (the dealer is untimed), convolutions as the timed
+    step runs them (implicit: on the input's shape).  The sample is repeated
     until at least min_seconds of oracle time have accumulated."""
     import oracle as O
     from paper_2311_04406_amd.workloads import KEY_SEED
@@ -199,7 +200,8 @@ def cpu_baseline(specs, min_seconds: float = 10.0, kbits: int = 64):
     t_tot, macs, passes = 0.0, 0, 0
     while passes == 0 or t_tot < min_seconds:
         for s, r0, r1 in parts:
-            L = O.OracleLayer(s.M, s.K, s.N, s.seed, s.layer_id, KEY_SEED, r0, r1, kbits=kbits).deal()
+            L = O.OracleLayer(s.M, s.K, s.N, s.seed, s.layer_id, KEY_SEED, r0, r1, kbits=kbits,
+                              conv=s.conv if implicit else None).deal()
             t0 = time.perf_counter()
             L.online(O.MODE_COMPACT).check(O.MODE_COMPACT)
             t_tot += time.perf_counter() - t0
@@ -291,7 +293,7 @@ def main():
     ap.add_argument("--mode", default="compact", choices=["compact", "spdz2k"])
     ap.add_argument("--compress", default="n", choices=["n", "m", "auto"],
                     help="dimension the compact tag compresses: N, M, or per layer the cheaper (M iff M > N)")
-    ap.add_argument("--conv", default="explicit", choices=["explicit", "implicit"],
+    ap.add_argument("--conv", default="implicit", choices=["explicit", "implicit"],
                     help="convolutions as products with an explicit K x N im2col operand, or with the im2col "
                          "left implicit (input, mask and U of the input's C x H x W shape)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -441,7 +443,7 @@ def main():
                                      SERVE_ARENA, SERVE_SLOTS, SERVE_BATCH)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        cb = cpu_baseline(specs, kbits=args.kbits)
+        cb = cpu_baseline(specs, kbits=args.kbits, implicit=implicit)
         out["cpu_baseline"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in cb.items()}
     ctx.close()
     print(json.dumps(out), flush=True)
