@@ -43,7 +43,7 @@ def along_m(s, compress: str) -> bool:
 
 
 def stage_work(stage: str, specs, mode: str, f: int = 0, kbits: int = 64, compress: str = "n",
-               implicit: bool = False):
+               implicit: bool = False, parties: int = 2):
     """Algorithmic work of one launch of a kernel stage over the layer batch:
     ("hbm", bytes) or ("mfma", int8 ops), for the fused step
     (online phase + verification).  16 B per Z_2^128 element; per element:
@@ -56,8 +56,8 @@ def stage_work(stage: str, specs, mode: str, f: int = 0, kbits: int = 64, compre
                  (SPDZ2k also the two folded tag operands): 96 / 160 B;
                  K x N: [B]_0, [B]_1, U (SPDZ2k also [tB]_p): 96 / 160 B
       copy_base  M x N: 32 B per array (2 arrays, 4 in SPDZ2k), N > 8 layers
-      ring_gemm  2 * 136 int8 ops per ring MAC; 4 M K N ring MACs per
-                 layer (8 in SPDZ2k), layers with N > 8
+      ring_gemm  2 * 136 int8 ops per ring MAC; 2 n M K N ring MACs per
+                 layer for n parties (4 n in SPDZ2k), layers with N > 8
       post       M x N: CompactTag reads R_p, Z_p, tR_p, tC_p (8), writes D,
                  tZ_p (3): 176 B; SPDZ2k reads R_p, Z_p, tR_p, tZ_p (8),
                  writes D: 144 B; with f > 0 also reads R^f_p, tR^f_p and
@@ -93,7 +93,7 @@ def stage_work(stage: str, specs, mode: str, f: int = 0, kbits: int = 64, compre
         elif stage == "copy_base":
             tot += (32 * mn * (4 if spdz else 2)) if wide else 0
         elif stage == "ring_gemm":
-            tot += 2 * pairs * (8 if spdz else 4) * M * K * N if wide else 0
+            tot += 2 * pairs * (4 if spdz else 2) * parties * M * K * N if wide else 0
         elif stage == "post":
             tot += ((144 if spdz else 176) + (128 if f > 0 else 0)) * mn
         elif stage == "col_tag":
@@ -107,7 +107,7 @@ def stage_work(stage: str, specs, mode: str, f: int = 0, kbits: int = 64, compre
 
 # Sources that determine what the device kernels do; the hardware counters in
 # profiles/traffic.json are valid only for the digest they were taken on.
-KERNEL_SOURCES = ("ct_device.h", "ct_internal.h", "ct_kernels.hip", "ct_gemm.hip")
+KERNEL_SOURCES = ("ct_device.h", "ct_internal.h", "ct_sweep.h", "ct_kernels.hip", "ct_gemm.hip", "ct_parties.hip")
 
 
 def source_digest() -> str:
@@ -179,7 +179,7 @@ def run_steps(ctx, mode_id, layer_groups, out_dev, steps, warmup, torch, timing=
     return t1 - t0, per, stages
 
 
-def cpu_baseline(specs, min_seconds: float = 10.0, kbits: int = 64, implicit: bool = False):
+def cpu_baseline(specs, min_seconds: float = 10.0, kbits: int = 64, implicit: bool = False, parties: int = 2):
     """The oracle (single-threaded C, -O2) on a bounded sample of the workload:
     every layer with M * K * N below 2^28 in full, and the first 2048 rows of
     any larger one (at most six layers); online phase + verification in the
@@ -201,7 +201,7 @@ def cpu_baseline(specs, min_seconds: float = 10.0, kbits: int = 64, implicit: bo
     while passes == 0 or t_tot < min_seconds:
         for s, r0, r1 in parts:
             L = O.OracleLayer(s.M, s.K, s.N, s.seed, s.layer_id, KEY_SEED, r0, r1, kbits=kbits,
-                              conv=s.conv if implicit else None).deal()
+                              conv=s.conv if implicit else None, parties=parties).deal()
             t0 = time.perf_counter()
             L.online(O.MODE_COMPACT).check(O.MODE_COMPACT)
             t_tot += time.perf_counter() - t0
@@ -293,6 +293,8 @@ def main():
     ap.add_argument("--mode", default="compact", choices=["compact", "spdz2k"])
     ap.add_argument("--compress", default="n", choices=["n", "m", "auto"],
                     help="dimension the compact tag compresses: N, M, or per layer the cheaper (M iff M > N)")
+    ap.add_argument("--parties", type=int, default=2,
+                    help="parties simulated in one process (2 to 5; more than 2: explicit convolutions, no server)")
     ap.add_argument("--conv", default="implicit", choices=["explicit", "implicit"],
                     help="convolutions as products with an explicit K x N im2col operand, or with the im2col "
                          "left implicit (input, mask and U of the input's C x H x W shape)")
@@ -312,21 +314,22 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2311_04406_amd import MODE_COMPACT, MODE_SPDZ2K, Context, Layer, workloads
+    from paper_2311_04406_amd import MODE_COMPACT, MODE_SPDZ2K, RESULT_WORDS, Context, Layer, workloads
 
     if args.config == "serving":
         return serving_main(args, torch)
     specs = workloads.CONFIGS[args.config]()
     mode_id = MODE_COMPACT if args.mode == "compact" else MODE_SPDZ2K
-    ctx = Context(device=0, key_seed=workloads.KEY_SEED, max_layers=max(256, len(specs)), kbits=args.kbits)
+    ctx = Context(device=0, key_seed=workloads.KEY_SEED, max_layers=max(256, len(specs)), kbits=args.kbits,
+                  parties=args.parties)
     cmp = {"n": 0, "m": 1, "auto": 2}[args.compress]
-    implicit = args.conv == "implicit"
+    implicit = args.conv == "implicit" and args.parties == 2
     layers = [ctx.layer(s.M, s.K, s.N, s.seed, s.layer_id, f=args.f, in_bits=args.in_bits, compress=cmp,
                         conv=s.conv if implicit else None) for s in specs]
     print(f"[bench] config {args.config}: {len(specs)} layers, dealer ...", file=sys.stderr, flush=True)
     ctx.gen_triple_tags(layers)
     torch.cuda.synchronize()
-    out_dev = torch.zeros(len(layers) * 14, dtype=torch.int64, device="cuda:0")
+    out_dev = torch.zeros(len(layers) * RESULT_WORDS, dtype=torch.int64, device="cuda:0")
     mkn = sum(s.mkn for s in specs)
 
     if args.copy_probe > 0:
@@ -352,7 +355,7 @@ def main():
     Te, pere, _ = run_steps(ctx, mode_id, [layers], out_dev, args.steps, args.warmup, torch)
     # per-kernel durations: a second pass with an event pair around every launch
     _, _, stages = run_steps(ctx, mode_id, [layers], out_dev, args.steps, 0, torch, timing=True)
-    res = Context.decode_results(out_dev, len(layers))
+    res = Context.decode_results(out_dev, len(layers), args.parties)
     if not all(r.accept for r in res):
         print("[bench] ERROR: an honest run was rejected", file=sys.stderr)
         sys.exit(1)
@@ -363,7 +366,7 @@ def main():
     stage_rows = {}
     for name, (tot_ms, n) in stages.items():
         avg = tot_ms / max(n, 1)
-        w = stage_work(name, specs, args.mode, args.f, args.kbits, args.compress, implicit)
+        w = stage_work(name, specs, args.mode, args.f, args.kbits, args.compress, implicit, args.parties)
         row = {"ms_per_launch": round(avg, 5), "launches": n, "share_of_step": round(tot_ms / args.steps / ms, 4)}
         if w is not None and w[1] > 0:
             bound, units = w
@@ -388,7 +391,8 @@ def main():
         roofline["traffic"] = measured_traffic(k, f"{args.config}/{args.mode}" + (f"/f{args.f}" if args.f else "")
                                                + ("/k32" if args.kbits == 32 else "")
                                                + (f"/c{args.compress}" if args.compress != "n" else "")
-                                               + ("/implicit" if implicit else ""))
+                                               + ("/implicit" if implicit else "")
+                                               + (f"/p{args.parties}" if args.parties != 2 else ""))
         roofline["share_of_step"] = v["share_of_step"]
 
     out = {
@@ -399,11 +403,11 @@ def main():
         "dtype": "u128" if args.kbits == 64 else "u64", "data": "synthetic",
         "config": {"workload": f"{args.config}: " + ", ".join(f"{s.name} ({s.M}x{s.K}x{s.N})" for s in specs)
                    if len(specs) <= 8 else f"{args.config}: {len(specs)} layers, sum MKN {mkn}",
-                   "protocol": args.mode, "parties": 2,
+                   "protocol": args.mode, "parties": args.parties,
                    "ring": ("values Z_2^64, shares and tags Z_2^128" if args.kbits == 64 else
                             "values Z_2^32, shares and tags Z_2^64"),
                    "layers_per_call": len(specs), "sum_MKN": mkn, "f": args.f, "in_bits": args.in_bits,
-                   "compress": args.compress, "conv": args.conv,
+                   "compress": args.compress, "conv": "implicit" if implicit else "explicit",
                    "compressed_along_m": [s.name for s in specs if along_m(s, args.compress)]
                    if len(specs) <= 8 else sum(along_m(s, args.compress) for s in specs)},
         "roofline": roofline,
@@ -435,7 +439,7 @@ def main():
                                  "p50_ms": round(pct(per4, 50), 4), "p99_ms": round(pct(per4, 99), 4)}
     plan.close()
     del plan
-    if not args.no_serve and args.kbits == 64:  # the server runs the k = s = 64 set
+    if not args.no_serve and args.kbits == 64 and args.parties == 2:  # the server runs two parties, k = s = 64
         print(f"[bench] serving leg at {args.serve_rate:g} req/s ...", file=sys.stderr, flush=True)
         del layers
         torch.cuda.empty_cache()
@@ -443,7 +447,7 @@ def main():
                                      SERVE_ARENA, SERVE_SLOTS, SERVE_BATCH)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        cb = cpu_baseline(specs, kbits=args.kbits, implicit=implicit)
+        cb = cpu_baseline(specs, kbits=args.kbits, implicit=implicit, parties=args.parties)
         out["cpu_baseline"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in cb.items()}
     ctx.close()
     print(json.dumps(out), flush=True)

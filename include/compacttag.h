@@ -5,9 +5,10 @@
  *
  * Setting (Sec. 2.4 of the paper): values live in Z_{2^k}, k = 64; value and
  * tag shares live in Z_{2^{k+s}} = Z_{2^128}, s = 64; the MAC key shares
- * [Delta]_p live in Z_{2^s}.  Two parties p = 0, 1 are simulated in one
- * process on one GPU; every "broadcast and reconstruct" of the paper is an
- * on-device sum of the two parties' shares.
+ * [Delta]_p live in Z_{2^s}.  The parties p = 0 .. n-1 (n = 2 by default, up
+ * to CT_MAX_PARTIES; the paper's appendix on scaling with parties) are
+ * simulated in one process on one GPU; every "broadcast and reconstruct" of
+ * the paper is an on-device sum of all parties' shares.
  *
  * Conventions shared by every entry point
  *   - Ring elements of Z_{2^128} are ct_u128 {lo, hi}: value = lo + 2^64 * hi.
@@ -51,6 +52,10 @@ typedef enum { CT_MODE_SPDZ2K = 0, CT_MODE_COMPACT = 1 } ct_mode;
 
 typedef struct ct_ctx ct_ctx;
 
+/* Most parties a context simulates; every per-party array below has this many
+ * slots, of which the first ct_params.parties are used. */
+#define CT_MAX_PARTIES 5
+
 typedef struct {
     int device;           /* HIP device ordinal */
     uint64_t key_seed;    /* seeds the key shares [Delta]_0, [Delta]_1 */
@@ -60,6 +65,9 @@ typedef struct {
                              uint64_t, key shares and combiners in Z_{2^32}) */
     void *hip_stream;     /* hipStream_t the context enqueues on; NULL = null stream */
     int max_layers;       /* largest n accepted by one call; <= 0 means 256 */
+    int parties;          /* parties simulated, 2 .. CT_MAX_PARTIES; 0 means 2.  More than two
+                             parties: plain products only (conv_c = 0), compressed along N, and
+                             no request server */
 } ct_params;
 
 typedef struct {
@@ -112,23 +120,25 @@ typedef struct {
 #define CT_COMPRESS_AUTO 2
 #define CT_COMPRESS_ALONG_M(M, N, c) ((c) == CT_COMPRESS_M || ((c) == CT_COMPRESS_AUTO && (M) > (N)))
 
-/* Per-layer device buffers.  [v]_p / [t v]_p are party p's value / tag share.
+/* Per-layer device buffers.  [v]_p / [t v]_p are party p's value / tag share
+ * (slots p < parties are used; the others are ignored).
  * Every element is one element of Z_{2^{k+s}}: a ct_u128 for k = s = 64, a
  * uint64_t (the pointer still typed ct_u128 *) for k = s = 32.  Element
  * counts (CT_WORK_LEN, CT_CVEC_LEN) are the same for both. */
 typedef struct {
-    ct_u128 *X[2], *tX[2], *A[2], *tA[2];                   /* M x K */
-    ct_u128 *Y[2], *tY[2], *B[2], *tB[2];                   /* K x N (convolution: the input's shape) */
-    ct_u128 *C[2], *tC[2], *R[2], *tR[2], *Z[2], *tZ[2];    /* M x N; Z, tZ are outputs */
+    ct_u128 *X[CT_MAX_PARTIES], *tX[CT_MAX_PARTIES], *A[CT_MAX_PARTIES], *tA[CT_MAX_PARTIES];                   /* M x K */
+    ct_u128 *Y[CT_MAX_PARTIES], *tY[CT_MAX_PARTIES], *B[CT_MAX_PARTIES], *tB[CT_MAX_PARTIES];                   /* K x N (convolution: the input's shape) */
+    ct_u128 *C[CT_MAX_PARTIES], *tC[CT_MAX_PARTIES], *R[CT_MAX_PARTIES], *tR[CT_MAX_PARTIES], *Z[CT_MAX_PARTIES], *tZ[CT_MAX_PARTIES];    /* M x N; Z, tZ are outputs */
     ct_u128 *E, *U, *D;  /* opened public values E = X - A (M x K), U = Y - B (K x N, or the input's shape),
                             D = R - Z (M x N); outputs of ct_tag_linear */
-    ct_u128 *cvec;       /* compact-tag vectors, CT_CVEC_LEN_FOR(M, K, N, compress) elements,
-                            layout below;
+    ct_u128 *cvec;       /* compact-tag vectors, CT_CVEC_LEN_FOR(M, K, N, compress) elements
+                            (n parties: CT_CVEC_LEN_NP), layout below;
                             written by ct_tag_linear in CT_MODE_COMPACT, unused otherwise */
-    ct_u128 *work;       /* caller-owned workspace of CT_WORK_LEN(M, K, N) elements (NULL allowed
-                            when that is 0); contents are undefined after a call */
-    ct_u128 *Rf[2], *tRf[2];  /* M x N, f > 0 only: truncated mask (written by the dealer) */
-    ct_u128 *Zf[2], *tZf[2];  /* M x N, f > 0 only: truncated output shares and tags */
+    ct_u128 *work;       /* caller-owned workspace of CT_WORK_LEN(M, K, N) elements (n parties:
+                            CT_WORK_LEN_NP; NULL allowed when that is 0); contents are undefined
+                            after a call */
+    ct_u128 *Rf[CT_MAX_PARTIES], *tRf[CT_MAX_PARTIES];  /* M x N, f > 0 only: truncated mask (written by the dealer) */
+    ct_u128 *Zf[CT_MAX_PARTIES], *tZf[CT_MAX_PARTIES];  /* M x N, f > 0 only: truncated output shares and tags */
 } ct_layer_bufs;
 
 /* Layers with N <= CT_SKINNY_N form their output products in the pass that
@@ -140,8 +150,11 @@ typedef struct {
  * elements per tile).  The matrix-core path needs K < 2^21 and N < 2^22. */
 #define CT_SKINNY_N 8
 #define CT_TILES_(D, K) ((((D) + 63) / 64) * (((K) + 31) / 32))
-#define CT_WORK_LEN(M, K, N) \
-    ((N) > CT_SKINNY_N ? 3 * (M) * (K) + 5 * 2048 * (CT_TILES_(M, K) + CT_TILES_(N, K)) : 0)
+#define CT_WORK_LEN(M, K, N) CT_WORK_LEN_NP(M, K, N, 2)
+/* With n parties: the folded operands A_0 + E and (SPDZ2k) [tA]_p + [Delta]_p E
+ * (n + 1 arrays of M x K) and 2n + 1 packed operands on each side. */
+#define CT_WORK_LEN_NP(M, K, N, n) \
+    ((N) > CT_SKINNY_N ? ((n) + 1) * (M) * (K) + (2 * (n) + 1) * 2048 * (CT_TILES_(M, K) + CT_TILES_(N, K)) : 0)
 
 /* cvec layout (element offsets), compressing along N:
  *   U^c [K] | tB^c_0 [K] | tB^c_1 [K] | D^c [M] | (E U^c) [M] | tC^c_0 [M] | tC^c_1 [M] |
@@ -149,12 +162,17 @@ typedef struct {
  * compressing along M, the same with U^c, tB^c_p replaced by E^c, tA^c_p and
  * every [M] by [N] (D^c = chi^T D, (E^c U), tC^c_p = chi^T tC_p, ...). */
 #define CT_CVEC_LEN(M, K) (3 * (K) + 10 * (M))
+/* n parties (compressing along N): U^c [K] | tB^c_p [K] for p < n | D^c [M] |
+ * (E U^c) [M] | tC^c_p [M] | tR^c_p [M] | tZ^c_p [M] | tD^c_p [M], each per-party
+ * group in party order; with n = 2 the layout above. */
+#define CT_CVEC_LEN_NP(M, K, n) ((1 + (n)) * (K) + (2 + 4 * (n)) * (M))
 #define CT_CVEC_LEN_FOR(M, K, N, c) (3 * (K) + 10 * (CT_COMPRESS_ALONG_M(M, N, c) ? (N) : (M)))
 
-/* Check-value shares of one layer: cs[W][p] for W = 0 (E), 1 (U), 2 (D).
- * accept = 1 iff cs[W][0] + cs[W][1] = 0 mod 2^128 for all three W. */
+/* Check-value shares of one layer: cs[W][p] for W = 0 (E), 1 (U), 2 (D) and
+ * parties p < n (the other slots are 0).  accept = 1 iff sum_p cs[W][p] = 0
+ * mod 2^{k+s} for all three W. */
 typedef struct {
-    ct_u128 cs[3][2];
+    ct_u128 cs[3][CT_MAX_PARTIES];
     int32_t accept;
     int32_t reserved;
 } ct_check_result;
@@ -169,8 +187,8 @@ ct_status ct_create(ct_ctx **out, const ct_params *params);
 /* Releases the context and its scratch after synchronizing its stream. */
 ct_status ct_destroy(ct_ctx *ctx);
 
-/* Copies the two key shares to host memory out[0], out[1]. */
-ct_status ct_key_shares(const ct_ctx *ctx, uint64_t out[2]);
+/* Copies the key shares of the context's n parties to host memory out[0 .. n-1]. */
+ct_status ct_key_shares(const ct_ctx *ctx, uint64_t out[CT_MAX_PARTIES]);
 
 /* Dealer (preprocessing of Fig. 7 and F_MAC Auth, Appendix A), for n layers:
  * Beaver matrix triple A (M x K), B (K x N), C = A*B mod 2^128 (M x N) and the

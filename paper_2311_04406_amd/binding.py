@@ -29,17 +29,21 @@ MASK64 = (1 << 64) - 1
 SKINNY_N = 8
 
 
-def work_len(M: int, K: int, N: int) -> int:
-    """CT_WORK_LEN of compacttag.h: workspace elements of one layer."""
+def work_len(M: int, K: int, N: int, parties: int = 2) -> int:
+    """CT_WORK_LEN_NP of compacttag.h: workspace elements of one layer."""
     if N <= SKINNY_N:
         return 0
     tiles = lambda d: ((d + 63) // 64) * ((K + 31) // 32)
-    return 3 * M * K + 5 * 2048 * (tiles(M) + tiles(N))
+    return (parties + 1) * M * K + (2 * parties + 1) * 2048 * (tiles(M) + tiles(N))
+
+
+MAX_PARTIES = 5   # CT_MAX_PARTIES
 
 
 class CtParams(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("key_seed", ctypes.c_uint64), ("k_bits", ctypes.c_int),
-                ("s_bits", ctypes.c_int), ("hip_stream", ctypes.c_void_p), ("max_layers", ctypes.c_int)]
+                ("s_bits", ctypes.c_int), ("hip_stream", ctypes.c_void_p), ("max_layers", ctypes.c_int),
+                ("parties", ctypes.c_int)]
 
 
 class CtLayerDesc(ctypes.Structure):
@@ -64,7 +68,7 @@ def cvec_len(M: int, K: int, N: int, compress: int = COMPRESS_N) -> int:
     return 3 * K + 10 * (N if compress_along_m(M, N, compress) else M)
 
 
-_P2 = ctypes.c_void_p * 2
+_P2 = ctypes.c_void_p * MAX_PARTIES   # one pointer per party slot
 BUF_PAIRS = ["X", "tX", "A", "tA", "Y", "tY", "B", "tB", "C", "tC", "R", "tR", "Z", "tZ"]
 BUF_SINGLE = ["E", "U", "D", "cvec", "work"]
 BUF_TRUNC = ["Rf", "tRf", "Zf", "tZf"]  # f > 0 only
@@ -85,7 +89,12 @@ class CtTuning(ctypes.Structure):
 
 
 class CtCheckResult(ctypes.Structure):
-    _fields_ = [("cs", ctypes.c_uint64 * 12), ("accept", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+    _fields_ = [("cs", ctypes.c_uint64 * (3 * MAX_PARTIES * 2)), ("accept", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+# int64 words of one ct_check_result (the device result records of the fused calls)
+RESULT_WORDS = ctypes.sizeof(CtCheckResult) // 8
 
 
 REQ_TAG, REQ_CHECK = 0, 1
@@ -177,16 +186,17 @@ class CtError(RuntimeError):
 
 @dataclass
 class CheckResult:
-    cs: list            # cs[W][p] as Python ints, W in (E, U, D)
+    cs: list            # cs[W][p] as Python ints, W in (E, U, D), p over the parties
     accept: bool
 
     def sums(self):
-        return [(self.cs[w][0] + self.cs[w][1]) % (1 << 128) for w in range(3)]
+        return [sum(self.cs[w]) % (1 << 128) for w in range(3)]
 
 
-def _result(r: CtCheckResult) -> CheckResult:
+def _result(r: CtCheckResult, parties: int = 2) -> CheckResult:
     v = list(r.cs)
-    cs = [[v[4 * w + 2 * p] | (v[4 * w + 2 * p + 1] << 64) for p in range(2)] for w in range(3)]
+    m = 2 * MAX_PARTIES
+    cs = [[v[m * w + 2 * p] | (v[m * w + 2 * p + 1] << 64) for p in range(parties)] for w in range(3)]
     return CheckResult(cs=cs, accept=bool(r.accept))
 
 
@@ -195,12 +205,13 @@ class Layer:
     `limbs` 64-bit words per element (2: k = s = 64; 1: k = s = 32)."""
 
     def __init__(self, M: int, K: int, N: int, seed: int, layer_id: int, device="cuda:0", f: int = 0,
-                 in_bits: int = 0, limbs: int = 2, compress: int = COMPRESS_N, conv=None):
+                 in_bits: int = 0, limbs: int = 2, compress: int = COMPRESS_N, conv=None, parties: int = 2):
         """conv = (C, H, W, k, stride, pad): a convolution whose right operand
         is the implicit im2col matrix of a C x H x W input; Y, tY, B, tB and U
-        then have the input's shape, stored as C x (H W)."""
+        then have the input's shape, stored as C x (H W).  parties: the share
+        arrays hold one tensor per party."""
         self.M, self.K, self.N, self.seed, self.layer_id, self.f = M, K, N, seed, layer_id, f
-        self.in_bits, self.limbs, self.compress = in_bits, limbs, compress
+        self.in_bits, self.limbs, self.compress, self.parties = in_bits, limbs, compress, parties
         self.conv = tuple(conv) if conv is not None else None
         self.t = {}
         kn = (self.conv[0], self.conv[1] * self.conv[2]) if self.conv else (K, N)
@@ -210,12 +221,13 @@ class Layer:
         w = limbs
         for g, names in groups.items():
             for n in names:
-                self.t[n] = [torch.zeros(dims[g] + (w,), dtype=torch.int64, device=device) for _ in range(2)]
+                self.t[n] = [torch.zeros(dims[g] + (w,), dtype=torch.int64, device=device) for _ in range(parties)]
         self.t["E"] = torch.zeros((M, K, w), dtype=torch.int64, device=device)
         self.t["U"] = torch.zeros(kn + (w,), dtype=torch.int64, device=device)
         self.t["D"] = torch.zeros((M, N, w), dtype=torch.int64, device=device)
-        self.t["cvec"] = torch.zeros((cvec_len(M, K, N, compress), w), dtype=torch.int64, device=device)
-        self.t["work"] = torch.zeros((max(1, work_len(M, K, N)), w), dtype=torch.int64, device=device)
+        nc = cvec_len(M, K, N, compress) if parties == 2 else (1 + parties) * K + (2 + 4 * parties) * M
+        self.t["cvec"] = torch.zeros((nc, w), dtype=torch.int64, device=device)
+        self.t["work"] = torch.zeros((max(1, work_len(M, K, N, parties)), w), dtype=torch.int64, device=device)
 
     @classmethod
     def wrap(cls, M: int, K: int, N: int, seed: int, layer_id: int, tensors: dict,
@@ -223,7 +235,7 @@ class Layer:
         """A Layer over existing device tensors (no allocation)."""
         obj = cls.__new__(cls)
         obj.M, obj.K, obj.N, obj.seed, obj.layer_id, obj.f = M, K, N, seed, layer_id, 0
-        obj.in_bits, obj.limbs, obj.compress, obj.conv = 0, 2, compress, None
+        obj.in_bits, obj.limbs, obj.compress, obj.conv, obj.parties = 0, 2, compress, None, 2
         obj.t = dict(tensors)
         return obj
 
@@ -245,18 +257,29 @@ class Layer:
     def bufs(self) -> CtLayerBufs:
         b = CtLayerBufs()
         for n in BUF_PAIRS:
-            setattr(b, n, _P2(self.t[n][0].data_ptr(), self.t[n][1].data_ptr()))
+            setattr(b, n, _P2(*[t.data_ptr() for t in self.t[n]]))
         for n in BUF_SINGLE:
             setattr(b, n, self.t[n].data_ptr())
         for n in BUF_TRUNC:
             if n in self.t:
-                setattr(b, n, _P2(self.t[n][0].data_ptr(), self.t[n][1].data_ptr()))
+                setattr(b, n, _P2(*[t.data_ptr() for t in self.t[n]]))
         return b
 
     # cvec views (element offsets of compacttag.h); compressed along M, the
     # K-long parts hold E^c, [tA^c]_p (named Ec, tAc0, tAc1) and the others have N entries
     def cvec_parts(self):
         K, c = self.K, self.t["cvec"]
+        if getattr(self, "parties", 2) > 2:  # CT_CVEC_LEN_NP layout
+            P, M = self.parties, self.M
+            o = {"Uc": (0, K)}
+            for p in range(P):
+                o[f"tBc{p}"] = ((1 + p) * K, K)
+            dc = (1 + P) * K
+            o["Dc"], o["EUc"] = (dc, M), (dc + M, M)
+            for g, name in enumerate(("tCc", "tRc", "tZc", "tDc")):
+                for p in range(P):
+                    o[f"{name}{p}"] = (dc + (2 + g * P + p) * M, M)
+            return {n: c[a:a + l] for n, (a, l) in o.items()}
         M = self.N if self.along_m else self.M
         k3 = ("Ec", "tAc0", "tAc1") if self.along_m else ("Uc", "tBc0", "tBc1")
         o = {k3[0]: (0, K), k3[1]: (K, K), k3[2]: (2 * K, K), "Dc": (3 * K, M), "EUc": (3 * K + M, M)}
@@ -276,10 +299,12 @@ def _arrays(layers):
 class Context:
     """A libcompacttag context bound to one device and one HIP stream."""
 
-    def __init__(self, device: int = 0, key_seed: int = 0, stream=None, max_layers: int = 256, kbits: int = 64):
+    def __init__(self, device: int = 0, key_seed: int = 0, stream=None, max_layers: int = 256, kbits: int = 64,
+                 parties: int = 2):
         """kbits = k = s: 64 (shares and tags in Z_{2^128}) or 32 (in Z_{2^64})."""
         self.lib = load()
         self.kbits = kbits
+        self.parties = parties
         self.limbs = 2 if kbits == 64 else 1
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: libcompacttag needs an MI355X (there is no CPU fallback)")
@@ -289,7 +314,7 @@ class Context:
             stream = torch.cuda.current_stream(self.torch_device)
         self.stream = stream
         handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
-        p = CtParams(device, key_seed & MASK64, kbits, kbits, handle, max_layers)
+        p = CtParams(device, key_seed & MASK64, kbits, kbits, handle, max_layers, parties)
         h = ctypes.c_void_p()
         s = self.lib.ct_create(ctypes.byref(h), ctypes.byref(p))
         if s != CT_OK:
@@ -313,9 +338,9 @@ class Context:
         raise CtError(s, self.lib.ct_last_error(self.h).decode())
 
     def key_shares(self):
-        out = (ctypes.c_uint64 * 2)()
+        out = (ctypes.c_uint64 * MAX_PARTIES)()
         self._check(self.lib.ct_key_shares(self.h, out))
-        return [int(out[0]), int(out[1])]
+        return [int(out[p]) for p in range(self.parties)]
 
     def gen_triple_tags(self, layers, with_inputs: bool = True):
         n, D, B = _arrays(layers)
@@ -326,7 +351,7 @@ class Context:
         self._check(self.lib.ct_tag_linear(self.h, mode, D, B, n))
 
     def mac_check_device(self, mode: int, layers, out: torch.Tensor):
-        """out: int64 device tensor of n * 14 entries (n ct_check_result records)."""
+        """out: int64 device tensor of n * RESULT_WORDS entries (n ct_check_result records)."""
         n, D, B = _arrays(layers)
         assert out.numel() * 8 >= n * ctypes.sizeof(CtCheckResult)
         self._check(self.lib.ct_mac_check_device(self.h, mode, D, B, n, ctypes.c_void_p(out.data_ptr())))
@@ -341,7 +366,7 @@ class Context:
         n, D, B = _arrays(layers)
         res = (CtCheckResult * n)()
         s = self._check(self.lib.ct_mac_check(self.h, mode, D, B, n, res), allow_abort=True)
-        out = [_result(r) for r in res]
+        out = [_result(r, self.parties) for r in res]
         return s, out
 
     def autotune(self, mode: int, layers, reps: int = 2) -> dict:
@@ -377,7 +402,7 @@ class Context:
               compress: int = COMPRESS_N, conv=None) -> Layer:
         """Buffers of one layer for this context's parameter set."""
         return Layer(M, K, N, seed, layer_id, device=self.torch_device, f=f, in_bits=in_bits, limbs=self.limbs,
-                     compress=compress, conv=conv)
+                     compress=compress, conv=conv, parties=self.parties)
 
     def plan(self, mode: int, layers, out: torch.Tensor | None = None) -> "Plan":
         """Captures the online phase of this layer batch (with the fused
@@ -392,11 +417,11 @@ class Context:
         return Plan(self, h, layers, out)
 
     @staticmethod
-    def decode_results(t: torch.Tensor, n: int):
+    def decode_results(t: torch.Tensor, n: int, parties: int = 2):
         """Decodes ct_check_result records copied back from mac_check_device."""
         raw = t.detach().cpu().contiguous().numpy().tobytes()
         arr = (CtCheckResult * n).from_buffer_copy(raw[: n * ctypes.sizeof(CtCheckResult)])
-        return [_result(r) for r in arr]
+        return [_result(r, parties) for r in arr]
 
 
 class Plan:

@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libcompacttag.so")
 BUILD_DIR = os.path.join(PKG, "_build")
-SOURCES = ["ct_api.hip", "ct_kernels.hip", "ct_gemm.hip", "ct_serve.hip"]
+SOURCES = ["ct_api.hip", "ct_kernels.hip", "ct_gemm.hip", "ct_serve.hip", "ct_parties.hip"]
 ARCH = os.environ.get("CT_OFFLOAD_ARCH", "gfx950")
 
 

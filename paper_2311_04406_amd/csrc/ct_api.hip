@@ -24,7 +24,7 @@ using namespace ct;
 static const char *kStageNames[ST_COUNT] = {
     "deal_lift", "fill_zero", "deal_auth", "deal_skinny", "zero_acc", "open_u", "row_pass", "pack",
     "copy_base", "ring_gemm", "post", "compact_final", "check_batch", "check_compact", "finalize", "col_tag",
-    "conv_compress"};
+    "conv_compress", "np_open", "np_skinny", "np_compress", "np_gemv"};
 constexpr int EV_POOL = 2048;
 
 struct ct_plan {
@@ -136,7 +136,9 @@ ct_status validate(ct_ctx *c, int max_layers, const ct_layer_desc *L, const ct_l
             }
             return true;
         };
-        for (int p = 0; p < 2; p++) {
+        if (c->np > 2 && (d.conv_c != 0 || CT_COMPRESS_ALONG_M(d.M, d.N, d.compress)))
+            return fail(c, CT_EINVAL, at + "more than two parties: plain products compressed along N only");
+        for (int p = 0; p < c->np; p++) {
             if (need & NEED_INPUTS)
                 if (!chk(b.X[p], "X") || !chk(b.tX[p], "tX") || !chk(b.Y[p], "Y") || !chk(b.tY[p], "tY"))
                     return CT_EINVAL;
@@ -169,8 +171,8 @@ void fill_layer(const ct_ctx *c, u128 *acc, const ct_layer_desc &d, const ct_lay
     o.M = d.M;
     o.K = d.K;
     o.N = d.N;
-    o.delta[0] = c->delta[0];
-    o.delta[1] = c->delta[1];
+    o.np = c->np;
+    for (int q = 0; q < c->np; q++) o.delta[q] = c->delta[q];
     const uint64_t s = d.seed, id = d.layer_id;
     o.key[K_LIFT_X] = hkey(s, id, P_LIFT_X);
     o.key[K_LIFT_Y] = hkey(s, id, P_LIFT_Y);
@@ -181,15 +183,19 @@ void fill_layer(const ct_ctx *c, u128 *acc, const ct_layer_desc &d, const ct_lay
     for (int obj = 1; obj <= NUM_OBJ; obj++) {
         o.key[K_VSH_X + obj - 1] = hkey(s, id, P_VSH + obj);
         o.key[K_TSH_X + obj - 1] = hkey(s, id, P_TSH + obj);
+        // parties 1 .. np - 2: the streams of purpose + 256 p
+        for (int q = 1; q + 1 < c->np; q++) {
+            o.vsh[q - 1][obj - 1] = hkey(s, id, P_VSH + obj + 256 * q);
+            o.tsh[q - 1][obj - 1] = hkey(s, id, P_TSH + obj + 256 * q);
+        }
     }
     o.key[K_CHI] = hkey(s, id, P_CHI);
     o.key[K_CHIHAT] = hkey(s, id, P_CHIHAT);
     o.key[K_CHI_E] = hkey(s, id, P_CHI_E);
     o.key[K_CHI_U] = hkey(s, id, P_CHI_U);
     o.key[K_CHI_D] = hkey(s, id, P_CHI_D);
-    auto cp = [](u128 *dst[2], ct_u128 *const src[2]) {
-        dst[0] = reinterpret_cast<u128 *>(src[0]);
-        dst[1] = reinterpret_cast<u128 *>(src[1]);
+    auto cp = [&](u128 *dst[MAXP], ct_u128 *const src[CT_MAX_PARTIES]) {
+        for (int q = 0; q < c->np; q++) dst[q] = reinterpret_cast<u128 *>(src[q]);
     };
     cp(o.X, b.X); cp(o.tX, b.tX); cp(o.A, b.A); cp(o.tA, b.tA);
     cp(o.Y, b.Y); cp(o.tY, b.tY); cp(o.B, b.B); cp(o.tB, b.tB);
@@ -230,7 +236,8 @@ Sizes max_sizes(const ct_layer_desc *L, int n) {
         s.m = std::max(s.m, d.M);
         s.k = std::max(s.k, d.K);
         s.cvec = std::max(s.cvec, (int64_t)CT_CVEC_LEN_FOR(d.M, d.K, d.N, d.compress));
-        s.kn_items = std::max(s.kn_items, sweep_items(d.K, d.N));
+        // a convolution's U is opened elementwise on its input (about 4 elements per lane)
+        s.kn_items = std::max(s.kn_items, d.conv_c > 0 ? (int64_t)CT_RIGHT_LEN(d) / 256 + 1 : sweep_items(d.K, d.N));
         s.mn_items = std::max(s.mn_items, sweep_items(d.M, d.N));
         s.row_items = std::max(s.row_items, row_items(d.M, d.K));
         s.nr = std::max(s.nr, (int64_t)CT_RIGHT_LEN(d));
@@ -286,10 +293,27 @@ inline u128 *elem_at(u128 *base, int64_t e, int eb) {
 // Host-side bound check of a layer's workspace use: every packed operand
 // (tiles * TILE_ELEMS elements from dst) must end inside the caller's
 // CT_WORK_LEN(M, K, N) elements.
-bool job_in_work(const PackJob &j, const u128 *work, const ct_layer_desc &d, int eb) {
+bool job_in_work(const PackJob &j, const u128 *work, const ct_layer_desc &d, int eb, int np = 2) {
     const char *b = reinterpret_cast<const char *>(work);
     const char *e = reinterpret_cast<const char *>(j.dst) + (int64_t)j.tiles * TILE_ELEMS * eb;
-    return reinterpret_cast<const char *>(j.dst) >= b && e <= b + (int64_t)CT_WORK_LEN(d.M, d.K, d.N) * eb;
+    return reinterpret_cast<const char *>(j.dst) >= b && e <= b + (int64_t)CT_WORK_LEN_NP(d.M, d.K, d.N, np) * eb;
+}
+
+// Workspace of a matrix-core layer with n parties: the folded operands
+// A_0 + E and [tA]_p + [Delta]_p E (M K each), then 2n + 1 packed left
+// operands (E, A_0 + E, [A]_1 .. [A]_{n-1}, [tA]_p + [Delta]_p E) and 2n + 1
+// packed right ones ([B]_p, U, [tB]_p).
+struct NpWork {
+    int64_t mk, pl, pr;
+    int np;
+    int64_t fold_tA(int p) const { return (1 + p) * mk; }
+    int64_t left(int i) const { return (1 + np) * mk + i * pl; }
+    int64_t right(int j) const { return (1 + np) * mk + (2 * np + 1) * pl + j * pr; }
+};
+NpWork np_work(int64_t M, int64_t K, int64_t N, int np) {
+    NpWork w;
+    w.mk = M * K; w.pl = packed_elems(M, K); w.pr = packed_elems(N, K); w.np = np;
+    return w;
 }
 
 GemmProb make_prob(const u128 *Lp1, const u128 *Lp2, const u128 *Rp1, const u128 *Rp2, const u128 *base, u128 *out,
@@ -410,8 +434,9 @@ ct_status fail(ct_ctx *c, ct_status s, const std::string &msg) {
 hipError_t lane_init(Lane &ln, hipStream_t stream, int max_layers) {
     ln.stream = stream;
     ln.max_layers = max_layers;
-    ln.max_probs = 4 * max_layers;
-    ln.max_jobs = 10 * max_layers;
+    // up to two products per party and 4 n + 2 packed operands per layer
+    ln.max_probs = 2 * CT_MAX_PARTIES * max_layers;
+    ln.max_jobs = (4 * CT_MAX_PARTIES + 2) * max_layers;
     hipError_t e;
 #define LANE_TRY(expr) \
     if ((e = (expr)) != hipSuccess) return e
@@ -459,8 +484,13 @@ ct_status ct_create(ct_ctx **out, const ct_params *p) {
     ct_ctx *c = new ct_ctx();
     c->device = p->device;
     c->eb = p->k_bits == 32 ? 8 : 16;
+    if (p->parties != 0 && (p->parties < 2 || p->parties > CT_MAX_PARTIES)) {
+        delete c;
+        return CT_EINVAL;
+    }
+    c->np = p->parties == 0 ? 2 : p->parties;
     // F_MAC Initialize: [Delta]_p uniform in Z_{2^s} (the key draw mod 2^s)
-    for (int q = 0; q < 2; q++) {
+    for (int q = 0; q < c->np; q++) {
         const uint64_t x = hdraw(hkey(p->key_seed, GLOBAL_LAYER, P_KEY + q), 0);
         c->delta[q] = p->s_bits == 32 ? (x & 0xFFFFFFFFull) : x;
     }
@@ -491,10 +521,9 @@ ct_status ct_destroy(ct_ctx *c) {
     return CT_OK;
 }
 
-ct_status ct_key_shares(const ct_ctx *c, uint64_t out[2]) {
+ct_status ct_key_shares(const ct_ctx *c, uint64_t out[CT_MAX_PARTIES]) {
     if (!c || !out) return CT_EINVAL;
-    out[0] = c->delta[0];
-    out[1] = c->delta[1];
+    for (int q = 0; q < c->np; q++) out[q] = c->delta[q];
     return CT_OK;
 }
 
@@ -512,24 +541,26 @@ ct_status ct::run_deal(ct_ctx *c, Lane &ln, const ct_layer_desc *L, const ct_lay
     // layers with N <= SKINNY_MAX_N.
     std::vector<GemmProb> probs;
     int njobs = 0, nskinny = 0;
+    const int last = c->np - 1;  // the lifts go to the last party's buffers
     for (int l = 0; l < n; l++) {
         const LayerDev &o = ln.layers_host[l];
         const ct_layer_desc &d = L[l];
         if (d.N <= SKINNY_MAX_N) {
             SkinnyProb sp;
             std::memset(&sp, 0, sizeof(sp));
-            sp.L = o.A[1]; sp.R = o.B[1]; sp.out = o.C[1];
+            sp.L = o.A[last]; sp.R = o.B[last]; sp.out = o.C[last];
             sp.M = (int32_t)d.M; sp.N = (int32_t)d.N; sp.K = (int32_t)d.K;
             ln.skinny_host[nskinny++] = sp;
             continue;
         }
         const WorkOff w = work_off(d.M, d.K, d.N);
         u128 *Ep = elem_at(o.work, w.Ep, c->eb), *B0p = elem_at(o.work, w.B0p, c->eb);
-        ln.pack_host[njobs++] = make_job(o.A[1], Ep, d.M, d.K, 0);
-        ln.pack_host[njobs++] = make_job(o.B[1], B0p, d.K, d.N, 1, &o.cv);
-        if (!job_in_work(ln.pack_host[njobs - 2], o.work, d, c->eb) || !job_in_work(ln.pack_host[njobs - 1], o.work, d, c->eb))
+        ln.pack_host[njobs++] = make_job(o.A[last], Ep, d.M, d.K, 0);
+        ln.pack_host[njobs++] = make_job(o.B[last], B0p, d.K, d.N, 1, &o.cv);
+        if (!job_in_work(ln.pack_host[njobs - 2], o.work, d, c->eb, c->np) ||
+            !job_in_work(ln.pack_host[njobs - 1], o.work, d, c->eb, c->np))
             return fail(c, CT_EINVAL, "internal error: workspace layout exceeds CT_WORK_LEN");
-        probs.push_back(make_prob(Ep, nullptr, B0p, nullptr, nullptr, o.C[1], d));
+        probs.push_back(make_prob(Ep, nullptr, B0p, nullptr, nullptr, o.C[last], d));
     }
     const int pack_tiles = plan_jobs(ln.pack_host, njobs);
     int total_tiles = 0;
@@ -539,7 +570,8 @@ ct_status ct::run_deal(ct_ctx *c, Lane &ln, const ct_layer_desc *L, const ct_lay
     std::copy(probs.begin(), probs.end(), ln.gemm_host);
     if ((s = upload(c, ln, n, nm, njobs, nskinny)) != CT_OK) return s;
     const Sizes sz = max_sizes(L, n);
-    LAUNCH(c, ln, ST_DEAL_LIFT, launch_deal_lift(c->eb, ln.layers_dev, n, std::max(sz.mk, sz.nr), ln.stream));
+    if (c->np > 2) LAUNCH(c, ln, ST_DEAL_LIFT, launch_np_lift(c->eb, ln.layers_dev, n, std::max(sz.mk, sz.nr), ln.stream));
+    else LAUNCH(c, ln, ST_DEAL_LIFT, launch_deal_lift(c->eb, ln.layers_dev, n, std::max(sz.mk, sz.nr), ln.stream));
     LAUNCH(c, ln, ST_PACK, launch_pack(c->eb, ln.pack_dev, njobs, pack_tiles, ln.stream));
     for (int i = 0; i < nm; i++)
         if (probs[i].accumulate)
@@ -552,7 +584,10 @@ ct_status ct::run_deal(ct_ctx *c, Lane &ln, const ct_layer_desc *L, const ct_lay
     }
     const int mask = (with_inputs ? ((1 << OBJ_X) | (1 << OBJ_Y)) : 0) | (1 << OBJ_A) | (1 << OBJ_B) |
                      (1 << OBJ_C) | (1 << OBJ_R) | (1 << OBJ_RF);
-    LAUNCH(c, ln, ST_DEAL_AUTH, launch_deal_auth(c->eb, ln.layers_dev, n, mask, std::max({sz.mk, sz.nr, sz.mn}), ln.stream));
+    if (c->np > 2)
+        LAUNCH(c, ln, ST_DEAL_AUTH, launch_np_auth(c->eb, ln.layers_dev, n, mask, std::max({sz.mk, sz.nr, sz.mn}), ln.stream));
+    else
+        LAUNCH(c, ln, ST_DEAL_AUTH, launch_deal_auth(c->eb, ln.layers_dev, n, mask, std::max({sz.mk, sz.nr, sz.mn}), ln.stream));
     return CT_OK;
 }
 
@@ -568,6 +603,97 @@ ct_status ct_gen_triple_tags(ct_ctx *c, const ct_layer_desc *L, const ct_layer_b
 
 namespace ct {
 
+// ---- n parties (np > 2): the plain per-step passes of ct_parties.hip and one
+// matrix-core product per party (two in SPDZ2k mode):
+//   [Z]_p = [C]_p + E [B]_p + L_p U,  L_0 = A_0 + E, L_p = [A]_p;
+//   [tZ]_p = [tC]_p + E [tB]_p + ([tA]_p + [Delta]_p E) U.
+ct_status prepare_online_np(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc *L, int n,
+                            ct_check_result *out_dev, OnlineLaunch &P) {
+    const bool compact = mode == CT_MODE_COMPACT, check = out_dev != nullptr;
+    const int np = c->np;
+    std::vector<GemmProb> probs;
+    int njobs = 0;
+    PackJob *J = ln.pack_host;
+    for (int l = 0; l < n; l++) {
+        const ct_layer_desc &d = L[l];
+        if (d.N <= SKINNY_MAX_N) continue;
+        const LayerDev &o = ln.layers_host[l];
+        const NpWork w = np_work(d.M, d.K, d.N, np);
+        if (njobs + 4 * np + 2 > ln.max_jobs || (int)probs.size() + 2 * np > ln.max_probs)
+            return fail(c, CT_EINVAL, "internal error: layer tables too small");
+        auto wp = [&](int64_t e) { return elem_at(o.work, e, c->eb); };
+        const int first_job = njobs;
+        J[njobs++] = make_job(o.E, wp(w.left(0)), d.M, d.K, 0);
+        J[njobs++] = make_job(wp(0), wp(w.left(1)), d.M, d.K, 0);  // A_0 + E
+        for (int p = 1; p < np; p++) J[njobs++] = make_job(o.A[p], wp(w.left(1 + p)), d.M, d.K, 0);
+        for (int p = 0; p < np; p++) J[njobs++] = make_job(o.B[p], wp(w.right(p)), d.K, d.N, 1);
+        J[njobs++] = make_job(o.U, wp(w.right(np)), d.K, d.N, 1);
+        const size_t first = probs.size();
+        for (int p = 0; p < np; p++)
+            probs.push_back(make_prob(wp(w.left(0)), wp(w.left(1 + p)), wp(w.right(p)), wp(w.right(np)), o.C[p], o.Z[p], d));
+        if (!compact) {
+            for (int p = 0; p < np; p++) {
+                J[njobs++] = make_job(wp(w.fold_tA(p)), wp(w.left(np + 1 + p)), d.M, d.K, 0);
+                J[njobs++] = make_job(o.tB[p], wp(w.right(np + 1 + p)), d.K, d.N, 1);
+                probs.push_back(make_prob(wp(w.left(0)), wp(w.left(np + 1 + p)), wp(w.right(np + 1 + p)),
+                                          wp(w.right(np)), o.tC[p], o.tZ[p], d));
+            }
+        }
+        for (size_t j = first; j < probs.size(); j++) probs[j].gsize = (int32_t)(probs.size() - first);
+        for (int j = first_job; j < njobs; j++)
+            if (!job_in_work(J[j], o.work, d, c->eb, np))
+                return fail(c, CT_EINVAL, "internal error: workspace layout exceeds CT_WORK_LEN_NP");
+    }
+    P = OnlineLaunch();
+    P.n = n;
+    P.mode = mode;
+    P.compact = compact;
+    P.check = check;
+    P.out_dev = out_dev;
+    P.njobs = njobs;
+    P.pack_tiles = plan_jobs(ln.pack_host, njobs);
+    P.tu = tuning_for(c, shape_class(mode, L, n));
+    P.nm = plan_gemms(probs, c->num_cus, P.tu, &P.total_tiles, &P.any_accum);
+    std::copy(probs.begin(), probs.end(), ln.gemm_host);
+    ct_status s = upload(c, ln, n, P.nm, njobs);
+    if (s != CT_OK) return s;
+    P.flags = (check ? F_CHECK : 0) | (compact ? F_COMPACT : F_SPDZ);
+    for (int l = 0; l < n; l++) {
+        const ct_layer_desc &d = L[l];
+        P.max_open = std::max({P.max_open, d.M * d.K, d.K * d.N});
+        P.max_mn = std::max(P.max_mn, d.M * d.N);
+        P.max_compress_items = std::max({P.max_compress_items, sweep_items(d.K, d.N), sweep_items(d.M, d.N)});
+        P.max_gemv_items = std::max(P.max_gemv_items, sweep_items(d.M, d.K));
+        P.max_cvec_np = std::max(P.max_cvec_np, (int64_t)CT_CVEC_LEN_NP(d.M, d.K, np));
+        if (d.N <= SKINNY_MAX_N) {
+            P.any_skinny = true;
+            P.max_skinny_items = std::max(P.max_skinny_items, d.M * np);
+        }
+    }
+    return CT_OK;
+}
+
+ct_status enqueue_online_np(ct_ctx *c, Lane &ln, const OnlineLaunch &P) {
+    const int n = P.n;
+    const int zero = (P.compact ? 1 : 0) | (P.check ? 2 : 0);
+    if (zero) LAUNCH(c, ln, ST_ZERO_ACC, launch_np_zero(c->eb, ln.layers_dev, n, zero, P.max_cvec_np, ln.stream));
+    LAUNCH(c, ln, ST_NP_OPEN, launch_np_open(c->eb, ln.layers_dev, n, P.flags, P.max_open, ln.stream));
+    if (P.njobs > 0) LAUNCH(c, ln, ST_PACK, launch_pack(c->eb, ln.pack_dev, P.njobs, P.pack_tiles, ln.stream));
+    if (P.any_accum) LAUNCH(c, ln, ST_COPY_BASE, launch_prob_base(c->eb, ln.gemm_dev, P.nm, P.max_mn, ln.stream));
+    ct_status s = run_gemms(c, ln, P.nm, P.total_tiles, P.tu);
+    if (s != CT_OK) return s;
+    if (P.any_skinny)
+        LAUNCH(c, ln, ST_NP_SKINNY, launch_np_skinny(c->eb, ln.layers_dev, n, P.flags, P.max_skinny_items, ln.stream));
+    LAUNCH(c, ln, ST_POST, launch_np_post(c->eb, ln.layers_dev, n, P.flags, P.max_mn, ln.stream));
+    if (P.compact) {
+        LAUNCH(c, ln, ST_NP_COMPRESS, launch_np_compress(c->eb, ln.layers_dev, n, P.max_compress_items, ln.stream));
+        LAUNCH(c, ln, ST_NP_GEMV, launch_np_gemv(c->eb, ln.layers_dev, n, P.max_gemv_items, ln.stream));
+        LAUNCH(c, ln, ST_COMPACT_FINAL, launch_np_compact_final(c->eb, ln.layers_dev, n, P.flags, ln.stream));
+    }
+    if (P.check) LAUNCH(c, ln, ST_FINALIZE, launch_np_finalize(c->eb, ln.layers_dev, n, P.out_dev, ln.stream));
+    return CT_OK;
+}
+
 // The online phase, optionally with the verification fused into its passes
 // (out_dev != nullptr): validation, tables and their upload.
 ct_status prepare_online(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
@@ -582,6 +708,7 @@ ct_status prepare_online(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc 
     if (check && !aligned16(out_dev)) return fail(c, CT_EINVAL, "out_dev is null or misaligned");
     HIPCHK(c, hipSetDevice(c->device));
     if ((s = stage_layers(c, ln, L, B, n)) != CT_OK) return s;
+    if (c->np > 2) return prepare_online_np(c, ln, mode, L, n, out_dev, P);
 
     // Matrix-core products (layers with N > SKINNY_MAX_N), both parties,
     // Eq. (2) with E U folded into party 0's left operand by the row pass:
@@ -645,7 +772,6 @@ ct_status prepare_online(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc 
     P.max_col_tag = sz.col_tag;
     P.any_conv_n = compact && sz.conv_n;
     P.max_conv_items = sz.conv_items;
-    P.max_kn_items = std::max(P.max_kn_items, sz.nr / 64 + 1);  // elementwise opening of convolution inputs
     P.flags = (check ? F_CHECK : 0) | (compact ? F_COMPACT : F_SPDZ);
     // cvec sums, check accumulators, and [Z]_p = [C]_p ([tZ]_p = [tC]_p) of
     // skinny layers, all accumulated into atomically by the passes
@@ -660,6 +786,7 @@ ct_status prepare_online(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc 
 
 // The kernels of the online phase, in order, on the lane's stream.
 ct_status enqueue_online(ct_ctx *c, Lane &ln, const OnlineLaunch &P) {
+    if (c->np > 2) return enqueue_online_np(c, ln, P);
     const int n = P.n;
     if (P.zero_what)
         LAUNCH(c, ln, ST_ZERO_ACC, launch_zero_acc(c->eb, ln.layers_dev, n, P.zero_what, P.max_zero, ln.stream));
@@ -698,8 +825,16 @@ ct_status run_check(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc *L, c
     if ((s = stage_layers(c, ln, L, B, n)) != CT_OK) return s;
     if ((s = upload(c, ln, n, 0)) != CT_OK) return s;
     const Sizes sz = max_sizes(L, n);
-    LAUNCH(c, ln, ST_ZERO_ACC, launch_zero_acc(c->eb, ln.layers_dev, n, 2, 0, ln.stream));
     const int mask = compact ? 0x3 : 0x7;
+    if (c->np > 2) {
+        LAUNCH(c, ln, ST_ZERO_ACC, launch_np_zero(c->eb, ln.layers_dev, n, 2, 0, ln.stream));
+        LAUNCH(c, ln, ST_CHECK_BATCH,
+               launch_np_check_batch(c->eb, ln.layers_dev, n, mask, std::max({sz.mk, sz.nr, sz.mn}), ln.stream));
+        if (compact) LAUNCH(c, ln, ST_CHECK_COMPACT, launch_np_check_compact(c->eb, ln.layers_dev, n, ln.stream));
+        LAUNCH(c, ln, ST_FINALIZE, launch_np_finalize(c->eb, ln.layers_dev, n, out_dev, ln.stream));
+        return CT_OK;
+    }
+    LAUNCH(c, ln, ST_ZERO_ACC, launch_zero_acc(c->eb, ln.layers_dev, n, 2, 0, ln.stream));
     LAUNCH(c, ln, ST_CHECK_BATCH,
            launch_check_batch(c->eb, ln.layers_dev, n, mask, std::max({sz.mk, sz.nr, sz.mn}), ln.stream));
     if (compact) LAUNCH(c, ln, ST_CHECK_COMPACT, launch_check_compact(c->eb, ln.layers_dev, n, ln.stream));

@@ -44,13 +44,14 @@ void lane_free(Lane &ln);
 enum Stage : int {
     ST_DEAL_LIFT, ST_FILL_ZERO, ST_DEAL_AUTH, ST_DEAL_SKINNY, ST_ZERO_ACC, ST_OPEN_U, ST_ROW_PASS, ST_PACK,
     ST_COPY_BASE, ST_RING_GEMM, ST_POST, ST_COMPACT_FINAL, ST_CHECK_BATCH, ST_CHECK_COMPACT, ST_FINALIZE,
-    ST_COL_TAG, ST_CONV_COMPRESS, ST_COUNT
+    ST_COL_TAG, ST_CONV_COMPRESS, ST_NP_OPEN, ST_NP_SKINNY, ST_NP_COMPRESS, ST_NP_GEMV, ST_COUNT
 };
 
 struct ct_ctx {
     int device = 0;
     int eb = 16;  // bytes per ring element: 16 (k = s = 64, Z_{2^128}) or 8 (k = s = 32, Z_{2^64})
-    uint64_t delta[2] = {0, 0};
+    int np = 2;   // parties simulated
+    uint64_t delta[CT_MAX_PARTIES] = {};  // key shares [Delta]_p, p < np
     int num_cus = 256;
     ct::Lane main;
     std::string err;
@@ -88,6 +89,9 @@ struct OnlineLaunch {
     GemmTuning tu;
     int64_t max_zero = 0, max_kn_items = 0, max_row_items = 0, max_mn = 0, max_mn_items = 0, max_col_tag = 0,
             max_conv_items = 0;
+    // n-party path
+    int64_t max_open = 0, max_skinny_items = 0, max_compress_items = 0, max_gemv_items = 0, max_cvec_np = 0;
+    bool any_skinny = false;
     ct_check_result *out_dev = nullptr;
 };
 ct_status prepare_online(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,

@@ -64,23 +64,48 @@ __host__ __device__ inline int64_t kn_src(const ConvGeom &g, int64_t N, int64_t 
 }
 
 // Per-layer descriptor as the kernels see it (device memory).
+// The two-party kernels use slots 0 and 1 of the per-party arrays; the
+// n-party kernels (np > 2) slots 0 .. np - 1.
+constexpr int MAXP = CT_MAX_PARTIES;
 struct LayerDev {
     int64_t M, K, N;
-    uint64_t delta[2];          // key shares
+    uint64_t delta[MAXP];       // key shares
     uint64_t key[K_COUNT];      // SplitMix64 stream keys
-    u128 *X[2], *tX[2], *A[2], *tA[2];
-    u128 *Y[2], *tY[2], *B[2], *tB[2];
-    u128 *C[2], *tC[2], *R[2], *tR[2], *Z[2], *tZ[2];
+    u128 *X[MAXP], *tX[MAXP], *A[MAXP], *tA[MAXP];
+    u128 *Y[MAXP], *tY[MAXP], *B[MAXP], *tB[MAXP];
+    u128 *C[MAXP], *tC[MAXP], *R[MAXP], *tR[MAXP], *Z[MAXP], *tZ[MAXP];
     u128 *E, *U, *D, *cvec;
-    u128 *work;                 // caller workspace: A_0 + E | tA_0 + Delta_0 E | tA_1 + Delta_1 E (M x K each)
+    u128 *work;                 // caller workspace: A_0 + E | tA_p + Delta_p E for p < np (M x K each), then
+                                // the packed operands
     u128 *acc;                  // check accumulators, ACC_PER_LAYER entries (context scratch)
-    u128 *Rf[2], *tRf[2], *Zf[2], *tZf[2];  // f > 0: truncated mask and output (M x N)
+    u128 *Rf[MAXP], *tRf[MAXP], *Zf[MAXP], *tZf[MAXP];  // f > 0: truncated mask and output (M x N)
     int32_t f, in_bits;         // truncated fractional bits; dealer input width (0: uniform)
     int32_t cm;                 // CompactTag compresses along M (W^c = chi^T W) instead of N
-    int32_t pad_;
+    int32_t np;                 // parties
     ConvGeom cv;                // convolution geometry (cv.on = 0: plain product)
     int64_t nr;                 // elements of Y, tY, B, tB, U: K N, or c h w of a convolution
+    // share streams of parties 1 .. np - 2 (party 0 uses key[K_VSH_X + obj - 1] and
+    // key[K_TSH_X + obj - 1]; the last party completes the sums)
+    uint64_t vsh[MAXP - 2][NUM_OBJ], tsh[MAXP - 2][NUM_OBJ];
 };
+
+// cvec offsets of n parties, compressing along N (see compacttag.h): U^c,
+// tB^c_p (K each), then D^c, E U^c, tC^c_p, tR^c_p, tZ^c_p, tD^c_p (M each).
+struct NpCvec {
+    int64_t Uc, tBc, Dc, EUc, tCc, tRc, tZc, tDc, K, M;
+    __host__ __device__ int64_t tb(int p) const { return tBc + p * K; }
+    __host__ __device__ int64_t tc(int p) const { return tCc + p * M; }
+    __host__ __device__ int64_t tr(int p) const { return tRc + p * M; }
+    __host__ __device__ int64_t tz(int p) const { return tZc + p * M; }
+    __host__ __device__ int64_t td(int p) const { return tDc + p * M; }
+};
+__host__ __device__ inline NpCvec np_cvec(int64_t M, int64_t K, int np) {
+    NpCvec o;
+    o.K = K; o.M = M;
+    o.Uc = 0; o.tBc = K; o.Dc = (1 + np) * K; o.EUc = o.Dc + M;
+    o.tCc = o.Dc + 2 * M; o.tRc = o.tCc + np * M; o.tZc = o.tRc + np * M; o.tDc = o.tZc + np * M;
+    return o;
+}
 
 // Layers with N <= SKINNY_MAX_N take their output products on the VALU inside
 // the pass that opens E (no MFMA tiles, no workspace).
@@ -107,8 +132,11 @@ enum PassFlags : int {
     F_SPDZ = 4,     // SPDZ2k protocol (per-element tags by products)
 };
 
-// Check accumulators per layer: for W in (E, U, D): [sum chi*tW_0, sum chi*tW_1, sum chi*W].
-constexpr int ACC_PER_LAYER = 9;
+// Check accumulators per layer.  Two parties: for W in (E, U, D) at 3 W:
+// [sum chi*tW_0, sum chi*tW_1, sum chi*W].  n parties: at W (CT_MAX_PARTIES + 1):
+// [sum chi*tW_p for p < n ..., sum chi*W at slot CT_MAX_PARTIES].
+constexpr int ACC_W = CT_MAX_PARTIES + 1;
+constexpr int ACC_PER_LAYER = 3 * ACC_W;
 
 // cvec offsets (elements), see compacttag.h.  Compressing along M the same
 // offsets are taken with M replaced by N (cvec_off(N, K)), and the three
@@ -146,19 +174,27 @@ __host__ __device__ inline int64_t cm_items(int64_t M, int64_t K, int64_t N) {
 }
 
 // Column sweep (sums down the columns of a rows x N matrix): wavefront items
-// of rb row groups (N <= 32) or of 64 columns x rb rows, rb = col_sweep_rb(rows)
-// rows per lane: at least 4, and enough that no column receives more than
-// about 256 atomic additions (same-address atomics serialize).
-__host__ __device__ inline int64_t col_sweep_rb(int64_t rows) {
+// of rb groups of 64 / G rows (N <= 32, G = pow2ceil(N); one atomic per column
+// per item) or of 64 columns x rb rows (one per lane).  rb = col_sweep_rb keeps
+// the atomic additions per column near 256 at most (same-address atomics
+// serialize) without starving the sweep of wavefronts.
+__host__ __device__ inline int64_t col_sweep_group(int64_t N) {
+    int64_t g = 1;
+    while (g < N) g <<= 1;
+    return g;
+}
+__host__ __device__ inline int64_t col_sweep_rb(int64_t rows, int64_t N) {
+    if (N <= 32) {
+        const int64_t per = (64 / col_sweep_group(N)) * 256, rb = (rows + per - 1) / per;
+        return rb < 1 ? 1 : rb;
+    }
     const int64_t rb = (rows + 255) / 256;
     return rb < 4 ? 4 : rb;
 }
 __host__ __device__ inline int64_t col_sweep_items(int64_t rows, int64_t N) {
-    const int64_t rb = col_sweep_rb(rows);
+    const int64_t rb = col_sweep_rb(rows, N);
     if (N <= 32) {
-        int64_t g = 1;
-        while (g < N) g <<= 1;
-        const int64_t per = (64 / g) * rb;
+        const int64_t per = (64 / col_sweep_group(N)) * rb;
         return (rows + per - 1) / per;
     }
     return ((N + 63) / 64) * ((rows + rb - 1) / rb);
@@ -258,6 +294,21 @@ hipError_t launch_post(int eb, const LayerDev *L, int n, int flags, int64_t max_
 hipError_t launch_compact_final(int eb, const LayerDev *L, int n, int flags, hipStream_t st);
 hipError_t launch_col_tag(int eb, const LayerDev *L, int n, int64_t max_items, hipStream_t st);
 hipError_t launch_conv_compress(int eb, const LayerDev *L, int n, int64_t max_items, hipStream_t st);
+
+// n-party path (ct_parties.hip)
+hipError_t launch_np_lift(int eb, const LayerDev *L, int n, int64_t max_elems, hipStream_t st);
+hipError_t launch_np_auth(int eb, const LayerDev *L, int n, int obj_mask, int64_t max_elems, hipStream_t st);
+hipError_t launch_np_zero(int eb, const LayerDev *L, int n, int what, int64_t max_elems, hipStream_t st);
+hipError_t launch_np_open(int eb, const LayerDev *L, int n, int flags, int64_t max_elems, hipStream_t st);
+hipError_t launch_prob_base(int eb, const GemmProb *probs, int nprobs, int64_t max_mn, hipStream_t st);
+hipError_t launch_np_skinny(int eb, const LayerDev *L, int n, int flags, int64_t max_items, hipStream_t st);
+hipError_t launch_np_post(int eb, const LayerDev *L, int n, int flags, int64_t max_elems, hipStream_t st);
+hipError_t launch_np_compress(int eb, const LayerDev *L, int n, int64_t max_items, hipStream_t st);
+hipError_t launch_np_gemv(int eb, const LayerDev *L, int n, int64_t max_items, hipStream_t st);
+hipError_t launch_np_compact_final(int eb, const LayerDev *L, int n, int flags, hipStream_t st);
+hipError_t launch_np_check_batch(int eb, const LayerDev *L, int n, int which_mask, int64_t max_elems, hipStream_t st);
+hipError_t launch_np_check_compact(int eb, const LayerDev *L, int n, hipStream_t st);
+hipError_t launch_np_finalize(int eb, const LayerDev *L, int n, ct_check_result *out, hipStream_t st);
 hipError_t launch_check_batch(int eb, const LayerDev *L, int n, int which, int64_t max_elems, hipStream_t st);
 hipError_t launch_check_compact(int eb, const LayerDev *L, int n, hipStream_t st);
 hipError_t launch_finalize(int eb, const LayerDev *L, int n, ct_check_result *out, hipStream_t st);

@@ -269,6 +269,7 @@ ct_status ct_server_create(ct_ctx *ctx, const ct_server_params *p, ct_server **o
     if (p->max_batch < 1 || p->max_batch > MAX_BATCH) return fail(ctx, CT_EINVAL, "max_batch must be in [1, 256]");
     if (p->mode != CT_MODE_SPDZ2K && p->mode != CT_MODE_COMPACT) return fail(ctx, CT_EINVAL, "unknown mode");
     if (ctx->eb != 16) return fail(ctx, CT_EINVAL, "the server runs the k = s = 64 parameter set");
+    if (ctx->np != 2) return fail(ctx, CT_EINVAL, "the server runs two parties");
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, CT_EDEVICE, "hipSetDevice failed");
     ct_server *s = new ct_server();
     s->ctx = ctx;

@@ -29,7 +29,8 @@ def gpu_layers(ctx, specs, device="cuda:0"):
     from paper_2311_04406_amd import Layer
     return [Layer(s.M, s.K, s.N, s.seed, s.layer_id, device=device, f=getattr(s, "f", 0),
                   in_bits=getattr(s, "in_bits", 0), limbs=getattr(ctx, "limbs", 2),
-                  compress=getattr(s, "compress", 0), conv=getattr(s, "conv", None)) for s in specs]
+                  compress=getattr(s, "compress", 0), conv=getattr(s, "conv", None),
+                  parties=getattr(ctx, "parties", 2)) for s in specs]
 
 
 def oracle_compress(spec):
@@ -38,10 +39,11 @@ def oracle_compress(spec):
     return O.cheaper_compress(spec.M, spec.K, spec.N) if c == 2 else c
 
 
-def oracle_run(mode, spec, key_seed, r0=0, r1=None, kbits=64):
+def oracle_run(mode, spec, key_seed, r0=0, r1=None, kbits=64, parties=2):
     return O.run_layer(mode, spec.M, spec.K, spec.N, spec.seed, spec.layer_id, key_seed, r0, r1,
                        getattr(spec, "f", 0), getattr(spec, "in_bits", 0), kbits,
-                       oracle_compress(spec) if mode == O.MODE_COMPACT else 0, getattr(spec, "conv", None))
+                       oracle_compress(spec) if mode == O.MODE_COMPACT else 0, getattr(spec, "conv", None),
+                       parties)
 
 
 def oracle_view(o, limbs):
@@ -65,11 +67,13 @@ def compare_layer(gl, ol, mode, r0=0, r1=None, dealt=True, what=""):
     if r1 is None:
         r1 = gl.M
     lw = gl.limbs if hasattr(gl, "limbs") else 2
+    np_ = getattr(gl, "parties", 2)
+    assert np_ == ol.parties, (what, "parties")
     names = (DEALT if dealt else []) + ["Z", "tZ"]
     if getattr(gl, "f", 0) > 0:
         names += (["Rf", "tRf"] if dealt else []) + ["Zf", "tZf"]
     for n in names:
-        for p in range(2):
+        for p in range(np_):
             g = to_np(_rows(n, gl[n][p], r0, r1))
             o = oracle_view(ol[n][p], lw)
             assert g.shape == o.shape, (what, n, g.shape, o.shape)
@@ -90,15 +94,15 @@ def compare_layer(gl, ol, mode, r0=0, r1=None, dealt=True, what=""):
             assert (r0, r1) == (0, gl.M)
             pairs = [("Ec", ol["Ec"]), ("tAc0", ol["tAc"][0]), ("tAc1", ol["tAc"][1])]
         else:
-            pairs = [("Uc", ol["Uc"]), ("tBc0", ol["tBc"][0]), ("tBc1", ol["tBc"][1])]
+            pairs = [("Uc", ol["Uc"])] + [(f"tBc{p}", ol["tBc"][p]) for p in range(np_)]
         for n, on in [("Dc", "Dc"), ("EUc", "EUc")]:
             pairs.append((n, ol[on]))
         for base in ("tCc", "tRc", "tZc", "tDc"):
-            for p in range(2):
+            for p in range(np_):
                 pairs.append((f"{base}{p}", ol[base][p]))
         for n, o in pairs:
             g = parts[n]
-            if not along_m and n not in ("Uc", "tBc0", "tBc1"):
+            if not along_m and not (n == "Uc" or n.startswith("tBc")):
                 g = g[r0:r1]  # the length-M vectors of the sampled rows
             o = oracle_view(o, lw)
             assert g.shape == o.shape, (what, n, g.shape, o.shape)
@@ -107,7 +111,8 @@ def compare_layer(gl, ol, mode, r0=0, r1=None, dealt=True, what=""):
 
 def compare_cs(gres, ol, which=(0, 1, 2), what=""):
     for w in which:
-        for p in range(2):
+        assert len(gres.cs[w]) == ol.parties, (what, "parties")
+        for p in range(ol.parties):
             assert gres.cs[w][p] == O.u128(ol.cs[w, p]), (what, w, p)
 
 

@@ -67,7 +67,16 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu %zu\n", offsetof(ct_server_params, mode), offsetof(ct_request, layer),
          offsetof(ct_request, arrival_us), offsetof(ct_completion, done_us), offsetof(ct_completion, result),
          offsetof(ct_server_counts, arena_bytes), offsetof(ct_server_counts, arena_used));
-  printf("%zu %zu\n", offsetof(ct_layer_desc, compress), offsetof(ct_layer_desc, conv_pad));
+  printf("%zu %zu %zu %d\n", offsetof(ct_layer_desc, compress), offsetof(ct_layer_desc, conv_pad),
+         offsetof(ct_params, parties), CT_MAX_PARTIES);
+  {
+    const long long sh[3][3] = {{64, 576, 3136}, {7, 9, 7}, {4096, 25088, 1}};
+    for (int i = 0; i < 3; i++)
+      for (int n = 2; n <= CT_MAX_PARTIES; n++)
+        printf("%lld %lld ", (long long)CT_WORK_LEN_NP(sh[i][0], sh[i][1], sh[i][2], n),
+               (long long)CT_CVEC_LEN_NP(sh[i][0], sh[i][1], n));
+    printf("\n");
+  }
   {
     const long long sh[4][3] = {{4096, 25088, 1}, {64, 576, 3136}, {7, 9, 7}, {3, 5, 2}};
     for (int i = 0; i < 4; i++)
@@ -93,7 +102,11 @@ int main(void) {
            ctypes.sizeof(b.CtServerCounts),
            b.CtServerParams.mode.offset, b.CtRequest.layer.offset, b.CtRequest.arrival_us.offset,
            b.CtCompletion.done_us.offset, b.CtCompletion.result.offset, b.CtServerCounts.arena_bytes.offset,
-           b.CtServerCounts.arena_used.offset, b.CtLayerDesc.compress.offset, b.CtLayerDesc.conv_pad.offset]
+           b.CtServerCounts.arena_used.offset, b.CtLayerDesc.compress.offset, b.CtLayerDesc.conv_pad.offset,
+           b.CtParams.parties.offset, b.MAX_PARTIES]
+    for M, K, N in ((64, 576, 3136), (7, 9, 7), (4096, 25088, 1)):
+        for n in range(2, b.MAX_PARTIES + 1):
+            got += [b.work_len(M, K, N, n), (1 + n) * K + (2 + 4 * n) * M]
     got += [b.cvec_len(M, K, N, c) for M, K, N in ((4096, 25088, 1), (64, 576, 3136), (7, 9, 7), (3, 5, 2))
             for c in range(3)]
     assert got == vals
@@ -105,6 +118,10 @@ def test_validation_before_device_calls(lib):
     # parameter sets other than k = s = 64 and k = s = 32 are rejected before the device is touched
     for kb, sb in ((32, 64), (64, 32), (16, 16), (48, 48)):
         p = b.CtParams(0, 1, kb, sb, None, 4)
+        assert lib.ct_create(ctypes.byref(h), ctypes.byref(p)) == b.CT_EINVAL
+    # party counts outside 2 .. CT_MAX_PARTIES
+    for parties in (1, -1, b.MAX_PARTIES + 1):
+        p = b.CtParams(0, 1, 64, 64, None, 4, parties)
         assert lib.ct_create(ctypes.byref(h), ctypes.byref(p)) == b.CT_EINVAL
     assert lib.ct_create(None, ctypes.byref(p)) == b.CT_EINVAL
     assert lib.ct_destroy(None) == b.CT_EINVAL

@@ -8,6 +8,7 @@ import torch
 
 import oracle as O
 from gpu_util import compare_cs, compare_layer, free, gpu_layers, oracle_run, say, to_np
+from paper_2311_04406_amd.binding import RESULT_WORDS
 
 pytestmark = pytest.mark.gpu
 
@@ -55,7 +56,7 @@ def run_one(c, spec, kbits, fused):
                                  else spec.compress == ALONG_M)
     c.gen_triple_tags(layers)
     if fused:
-        out = torch.zeros(14, dtype=torch.int64, device="cuda:0")
+        out = torch.zeros(RESULT_WORDS, dtype=torch.int64, device="cuda:0")
         c.tag_linear_check(O.MODE_COMPACT, layers, out)
         from paper_2311_04406_amd import Context
         res = Context.decode_results(out, 1)[0]
@@ -93,7 +94,7 @@ def test_auto_mixed_batch_and_graph(ctx):
     layers = gpu_layers(ctx, specs)
     assert [l.along_m for l in layers] == [True, False, True, False, False, True]
     ctx.gen_triple_tags(layers)
-    out = torch.zeros(14 * len(specs), dtype=torch.int64, device="cuda:0")
+    out = torch.zeros(RESULT_WORDS * len(specs), dtype=torch.int64, device="cuda:0")
     ctx.tag_linear_check(O.MODE_COMPACT, layers, out)
     res = Context.decode_results(out, len(specs))
     refs = []

@@ -9,6 +9,7 @@ import torch
 
 import oracle as O
 from gpu_util import compare_cs, compare_layer, free, gpu_layers, oracle_run, say, to_np
+from paper_2311_04406_amd.binding import RESULT_WORDS
 
 pytestmark = pytest.mark.gpu
 
@@ -47,7 +48,7 @@ def run_one(c, spec, mode, fused, kbits=64):
     layers = gpu_layers(c, [spec])
     c.gen_triple_tags(layers)
     if fused:
-        out = torch.zeros(14, dtype=torch.int64, device="cuda:0")
+        out = torch.zeros(RESULT_WORDS, dtype=torch.int64, device="cuda:0")
         c.tag_linear_check(mode, layers, out)
         res = Context.decode_results(out, 1)[0]
         status = 0 if res.accept else 4
@@ -100,7 +101,7 @@ def test_conv_and_plain_layers_in_one_plan(ctx):
     mode = O.MODE_COMPACT
     layers = gpu_layers(ctx, specs)
     ctx.gen_triple_tags(layers)
-    out = torch.zeros(14 * len(specs), dtype=torch.int64, device="cuda:0")
+    out = torch.zeros(RESULT_WORDS * len(specs), dtype=torch.int64, device="cuda:0")
     ctx.tag_linear_check(mode, layers, out)
     res = Context.decode_results(out, len(specs))
     refs = []

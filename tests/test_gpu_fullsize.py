@@ -11,6 +11,7 @@ import torch
 import oracle as O
 from gpu_util import compare_cs, compare_layer, free, gpu_layers, oracle_run, say, to_np
 from paper_2311_04406_amd import workloads as W
+from paper_2311_04406_amd.binding import RESULT_WORDS
 
 pytestmark = pytest.mark.gpu
 KEY = W.KEY_SEED
@@ -31,7 +32,7 @@ def run_config(ctx, mode, specs):
     from paper_2311_04406_amd import Context
     layers = gpu_layers(ctx, specs)
     ctx.gen_triple_tags(layers)
-    out = torch.zeros(14 * len(specs), dtype=torch.int64, device="cuda:0")
+    out = torch.zeros(RESULT_WORDS * len(specs), dtype=torch.int64, device="cuda:0")
     ctx.tag_linear_check(mode, layers, out)
     fused = Context.decode_results(out, len(specs))
     status, res = ctx.mac_check(mode, layers)

@@ -8,6 +8,7 @@ import torch
 
 import oracle as O
 from gpu_util import compare_cs, compare_layer, free, gpu_layers, oracle_run, say, to_np
+from paper_2311_04406_amd.binding import RESULT_WORDS
 
 pytestmark = pytest.mark.gpu
 
@@ -76,7 +77,7 @@ def test_plan_replays_match_eager(ctx, mode):
     from paper_2311_04406_amd import Context
     say(f"[graph] mode={mode} batch of {len(BATCH)}")
     layers = gpu_layers(ctx, BATCH)
-    out = torch.zeros(14 * len(BATCH), dtype=torch.int64, device="cuda:0")
+    out = torch.zeros(RESULT_WORDS * len(BATCH), dtype=torch.int64, device="cuda:0")
     ctx.gen_triple_tags(layers)
     ctx.tag_linear_check(mode, layers, out)
     torch.cuda.synchronize()
@@ -108,7 +109,7 @@ def test_plan_recomputes_from_current_inputs(ctx, mode):
     say(f"[graph] new inputs mode={mode}")
     specs = BATCH[:3]
     layers = gpu_layers(ctx, specs)
-    out = torch.zeros(14 * len(specs), dtype=torch.int64, device="cuda:0")
+    out = torch.zeros(RESULT_WORDS * len(specs), dtype=torch.int64, device="cuda:0")
     ctx.gen_triple_tags(layers)
     plan = ctx.plan(mode, layers, None)
     plan_chk = ctx.plan(mode, layers, out)

@@ -6,6 +6,7 @@ import torch
 
 import oracle as O
 from gpu_util import compare_cs, compare_layer, free, gpu_layers, oracle_run, say, to_np
+from paper_2311_04406_amd.binding import RESULT_WORDS
 
 pytestmark = pytest.mark.gpu
 
@@ -62,7 +63,7 @@ def test_k32_fused_batch_and_graph(ctx, mode):
     specs = [SMALL[2], SMALL[3], SMALL[5], SMALL[9]]
     layers = gpu_layers(ctx, specs)
     ctx.gen_triple_tags(layers)
-    out = torch.zeros(14 * len(specs), dtype=torch.int64, device="cuda:0")
+    out = torch.zeros(RESULT_WORDS * len(specs), dtype=torch.int64, device="cuda:0")
     ctx.tag_linear_check(mode, layers, out)
     res = Context.decode_results(out, len(specs))
     for l, s, r in zip(layers, specs, res):
@@ -106,7 +107,7 @@ def test_k32_sampled_encoder_layer(ctx, mode):
     spec = Spec(128, 3072, 768, 1100, 4)
     layers = gpu_layers(ctx, [spec])
     ctx.gen_triple_tags(layers)
-    out = torch.zeros(14, dtype=torch.int64, device="cuda:0")
+    out = torch.zeros(RESULT_WORDS, dtype=torch.int64, device="cuda:0")
     ctx.tag_linear_check(mode, layers, out)
     torch.cuda.synchronize()
     ol = oracle_run(mode, spec, KEY, 40, 64, kbits=32)

@@ -6,6 +6,7 @@ import torch
 
 import oracle as O
 from gpu_util import compare_cs, compare_layer, free, gpu_layers, oracle_run, say, to_np
+from paper_2311_04406_amd.binding import RESULT_WORDS
 
 pytestmark = pytest.mark.gpu
 
@@ -96,7 +97,7 @@ def test_fused_verification_matches(ctx, mode, spec):
     say(f"[fused] mode={mode} shape={spec.name}")
     layers = gpu_layers(ctx, [spec])
     ctx.gen_triple_tags(layers)
-    out = torch.zeros(14, dtype=torch.int64, device="cuda:0")
+    out = torch.zeros(RESULT_WORDS, dtype=torch.int64, device="cuda:0")
     ctx.tag_linear_check(mode, layers, out)
     torch.cuda.synchronize()
     fused = Context.decode_results(out, 1)[0]
@@ -117,7 +118,7 @@ def test_launch_configurations_give_identical_results(ctx, mode):
     specs = [Spec(200, 700, 300, 31, 5), Spec(70, 100, 130, 3, 3), Spec(33, 70, 1, 7, 7)]
     layers = gpu_layers(ctx, specs)
     ctx.gen_triple_tags(layers)
-    out = torch.zeros(14 * len(specs), dtype=torch.int64, device="cuda:0")
+    out = torch.zeros(RESULT_WORDS * len(specs), dtype=torch.int64, device="cuda:0")
     ref = None
     for g, x, sp in [(1, 0, 0), (4, 1, 8), (16, 0, 32), (2, 1, 128), (8, 1, 0), (64, 1, 16), (2, 4, 16), (1, 16, 0),
                      (8, 8, 32), (4, 3, 8)]:
@@ -160,7 +161,7 @@ def test_flipped_share_bit_aborts(ctx, mode, target):
     idx = 37 % flat.shape[0]
     limb = 0 if bit < 64 else 1
     flat[idx, limb] ^= (1 << (bit % 64)) if bit % 64 < 63 else -(1 << 63)
-    out = torch.zeros(14, dtype=torch.int64, device="cuda:0")
+    out = torch.zeros(RESULT_WORDS, dtype=torch.int64, device="cuda:0")
     ctx.tag_linear_check(mode, layers, out)
     from paper_2311_04406_amd import Context
     fused = Context.decode_results(out, 1)[0]
@@ -203,7 +204,7 @@ def test_truncation_fused_batch(ctx, mode):
     say(f"[parity] truncation fused batch mode={mode}")
     layers = gpu_layers(ctx, specs)
     ctx.gen_triple_tags(layers)
-    out = torch.zeros(14 * len(specs), dtype=torch.int64, device="cuda:0")
+    out = torch.zeros(RESULT_WORDS * len(specs), dtype=torch.int64, device="cuda:0")
     ctx.tag_linear_check(mode, layers, out)
     res = Context.decode_results(out, len(specs))
     for l, s, r in zip(layers, specs, res):
