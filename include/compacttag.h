@@ -1,6 +1,7 @@
 /*
  * compacttag.h -- C ABI of libcompacttag, the MI355X (gfx950) library for the
- * linear-layer hot path of actively secure two-party MPC over Z_{2^64}
+ * linear-layer hot path of actively secure MPC over Z_{2^64} (two parties by
+ * default)
  * (CompactTag, arXiv 2311.04406).
  *
  * Setting (Sec. 2.4 of the paper): values live in Z_{2^k}, k = 64; value and

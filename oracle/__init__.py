@@ -6,8 +6,9 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 GPU library never falls back to it.
 
 Ring elements of Z_{2^{k+s}} are numpy ``uint64`` arrays whose last axis holds
-the (lo, hi) limbs (k = s = 64 or 32; with 32 the high limb is zero).  ``run_layer`` executes the whole two-party procedure of
-one linear layer -- the dealer (preprocessing of Fig. 7), the online phase and
+the (lo, hi) limbs (k = s = 64 or 32; with 32 the high limb is zero).
+``run_layer`` executes the whole procedure (two parties by default) of one
+linear layer -- the dealer (preprocessing of Fig. 7), the online phase and
 the verification -- optionally restricted to a range of rows of the M
 dimension, which is how full-size layers are sampled.
 """

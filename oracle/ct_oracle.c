@@ -1,7 +1,7 @@
 /*
  * ct_oracle.c -- plain, slow CPU oracle for the linear-layer hot path of
- * CompactTag (arXiv 2311.04406): two parties of SPDZ2k-style MPC over the
- * value ring Z_{2^k} with shares and tags in Z_{2^{k+s}} and key shares in
+ * CompactTag (arXiv 2311.04406): two to five parties of SPDZ2k-style MPC over
+ * the value ring Z_{2^k} with shares and tags in Z_{2^{k+s}} and key shares in
  * Z_{2^s}, for the two parameter sets of Sec. 4.1: k = s = 64 (Z_{2^128}) and
  * k = s = 32 (Z_{2^64}).
  *
@@ -20,7 +20,10 @@
  *   - Pi_BatchRec (Fig. 1): open and tag check;
  *   - Pi_MatMul (Fig. 2, Eqs. (2)-(3)): the SPDZ2k baseline;
  *   - Pi_Compress (Fig. 4), Pi_OptMAC (Fig. 5), the compact tag of
- *     Eq. (5) and Pi_CompactMatMul (Fig. 7) at f = 0.
+ *     Eq. (5) and Pi_CompactMatMul (Fig. 7), along N or along M;
+ *   - truncation for f > 0: OptMAC&Trunc (Fig. 6) / Pi_Truncation (Fig. 3);
+ *   - convolutions as im2col products (Eq. (4)) opened on the input's shape;
+ *   - n parties (the appendix on scaling with parties).
  * Readings where the paper is ambiguous (integer key sum, the party that adds
  * public value terms, D opened mod 2^{k+s}, E*U inside the compact tag, check
  * modulus 2^{k+s}) are the ones listed in the design notes and in the file

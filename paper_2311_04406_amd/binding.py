@@ -201,7 +201,7 @@ def _result(r: CtCheckResult, parties: int = 2) -> CheckResult:
 
 
 class Layer:
-    """Device buffers of one linear layer (both parties), as torch tensors of
+    """Device buffers of one linear layer (every party), as torch tensors of
     `limbs` 64-bit words per element (2: k = s = 64; 1: k = s = 32)."""
 
     def __init__(self, M: int, K: int, N: int, seed: int, layer_id: int, device="cuda:0", f: int = 0,

@@ -658,36 +658,55 @@ ct_status prepare_online_np(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_de
     ct_status s = upload(c, ln, n, P.nm, njobs);
     if (s != CT_OK) return s;
     P.flags = (check ? F_CHECK : 0) | (compact ? F_COMPACT : F_SPDZ);
+    bool fused_skinny = false;
     for (int l = 0; l < n; l++) {
         const ct_layer_desc &d = L[l];
         P.max_open = std::max({P.max_open, d.M * d.K, d.K * d.N});
         P.max_mn = std::max(P.max_mn, d.M * d.N);
         P.max_compress_items = std::max({P.max_compress_items, sweep_items(d.K, d.N), sweep_items(d.M, d.N)});
-        P.max_gemv_items = std::max(P.max_gemv_items, sweep_items(d.M, d.K));
         P.max_cvec_np = std::max(P.max_cvec_np, (int64_t)CT_CVEC_LEN_NP(d.M, d.K, np));
-        if (d.N <= SKINNY_MAX_N) {
-            P.any_skinny = true;
+        if (np_fused_row(d.N)) {
+            // the fused row pass (variants 0, 1, 2)
+            P.variants |= 1 << row_variant(d.N);
+            P.max_row_items = std::max(P.max_row_items, row_items(d.M, d.K));
+            if (d.N <= SKINNY_MAX_N) {
+                fused_skinny = true;
+                P.max_zero = std::max(P.max_zero, d.M * d.N);
+            }
+        } else {
+            P.any_unfused = true;
+            P.max_gemv_items = std::max(P.max_gemv_items, sweep_items(d.M, d.K));
             P.max_skinny_items = std::max(P.max_skinny_items, d.M * np);
         }
     }
+    P.max_zero = std::max(P.max_zero, compact ? P.max_cvec_np : 0);
+    P.zero_what = (compact ? 1 : 0) | (check ? 2 : 0) | (fused_skinny ? 4 : 0) | (fused_skinny && !compact ? 8 : 0);
     return CT_OK;
 }
 
 ct_status enqueue_online_np(ct_ctx *c, Lane &ln, const OnlineLaunch &P) {
     const int n = P.n;
-    const int zero = (P.compact ? 1 : 0) | (P.check ? 2 : 0);
-    if (zero) LAUNCH(c, ln, ST_ZERO_ACC, launch_np_zero(c->eb, ln.layers_dev, n, zero, P.max_cvec_np, ln.stream));
-    LAUNCH(c, ln, ST_NP_OPEN, launch_np_open(c->eb, ln.layers_dev, n, P.flags, P.max_open, ln.stream));
+    if (P.zero_what)
+        LAUNCH(c, ln, ST_ZERO_ACC, launch_np_zero(c->eb, ln.layers_dev, n, P.zero_what, P.max_zero, ln.stream));
+    // U and its compression first: the fused row pass reads U^c, [tB^c]_p and, for N <= 2, U
+    LAUNCH(c, ln, ST_OPEN_U, launch_np_open(c->eb, ln.layers_dev, n, 2, P.flags, P.max_open, ln.stream));
+    if (P.compact)
+        LAUNCH(c, ln, ST_NP_COMPRESS, launch_np_compress(c->eb, ln.layers_dev, n, 1, P.max_compress_items, ln.stream));
+    if (P.variants)
+        LAUNCH(c, ln, ST_ROW_PASS,
+               launch_np_row_pass(c->eb, c->np, ln.layers_dev, n, P.flags, P.max_row_items, P.variants, ln.stream));
+    if (P.any_unfused) LAUNCH(c, ln, ST_NP_OPEN, launch_np_open(c->eb, ln.layers_dev, n, 1, P.flags, P.max_open, ln.stream));
     if (P.njobs > 0) LAUNCH(c, ln, ST_PACK, launch_pack(c->eb, ln.pack_dev, P.njobs, P.pack_tiles, ln.stream));
     if (P.any_accum) LAUNCH(c, ln, ST_COPY_BASE, launch_prob_base(c->eb, ln.gemm_dev, P.nm, P.max_mn, ln.stream));
     ct_status s = run_gemms(c, ln, P.nm, P.total_tiles, P.tu);
     if (s != CT_OK) return s;
-    if (P.any_skinny)
+    if (P.any_unfused)
         LAUNCH(c, ln, ST_NP_SKINNY, launch_np_skinny(c->eb, ln.layers_dev, n, P.flags, P.max_skinny_items, ln.stream));
     LAUNCH(c, ln, ST_POST, launch_np_post(c->eb, ln.layers_dev, n, P.flags, P.max_mn, ln.stream));
     if (P.compact) {
-        LAUNCH(c, ln, ST_NP_COMPRESS, launch_np_compress(c->eb, ln.layers_dev, n, P.max_compress_items, ln.stream));
-        LAUNCH(c, ln, ST_NP_GEMV, launch_np_gemv(c->eb, ln.layers_dev, n, P.max_gemv_items, ln.stream));
+        LAUNCH(c, ln, ST_NP_COMPRESS, launch_np_compress(c->eb, ln.layers_dev, n, 2, P.max_compress_items, ln.stream));
+        if (P.any_unfused)
+            LAUNCH(c, ln, ST_NP_GEMV, launch_np_gemv(c->eb, ln.layers_dev, n, P.max_gemv_items, ln.stream));
         LAUNCH(c, ln, ST_COMPACT_FINAL, launch_np_compact_final(c->eb, ln.layers_dev, n, P.flags, ln.stream));
     }
     if (P.check) LAUNCH(c, ln, ST_FINALIZE, launch_np_finalize(c->eb, ln.layers_dev, n, P.out_dev, ln.stream));

@@ -91,7 +91,7 @@ struct OnlineLaunch {
             max_conv_items = 0;
     // n-party path
     int64_t max_open = 0, max_skinny_items = 0, max_compress_items = 0, max_gemv_items = 0, max_cvec_np = 0;
-    bool any_skinny = false;
+    bool any_skinny = false, any_unfused = false;  // layers with 2 < N <= SKINNY_MAX_N
     ct_check_result *out_dev = nullptr;
 };
 ct_status prepare_online(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,

@@ -156,6 +156,19 @@ __host__ __device__ inline CvecOff cvec_off(int64_t M, int64_t K) {
 // compressing along N, N when compressing along M.
 __host__ __device__ inline int64_t cvec_rows(const LayerDev &L) { return L.cm ? L.N : L.M; }
 
+// Variant of the row pass a layer takes: 0 for matrix-core layers, else the
+// smallest of 1, 2, 4, 8 that holds N.  Each variant is its own kernel so the
+// register budget (and occupancy) of one does not limit the others.
+__host__ __device__ inline int row_variant(int64_t N) {
+    return N > SKINNY_MAX_N ? 0 : (N <= 1 ? 1 : (N <= 2 ? 2 : (N <= 4 ? 4 : SKINNY_MAX_N)));
+}
+
+// With more than two parties, the fused row pass serves matrix-core layers and
+// layers with N <= 2 (its per-party row products fit in registers); layers
+// with 2 < N <= SKINNY_MAX_N take the separate opening, product and compact
+// passes.
+__host__ __device__ inline bool np_fused_row(int64_t N) { return N > SKINNY_MAX_N || N <= 2; }
+
 // Row pass of a layer compressed along M: lanes own columns; a wavefront
 // takes a strip of cm_cw(N) * 64 columns over CM_RB rows and keeps the column
 // sums chi_m E_mk, chi_m [tA]_p,mk in registers until its rows are done
@@ -299,11 +312,14 @@ hipError_t launch_conv_compress(int eb, const LayerDev *L, int n, int64_t max_it
 hipError_t launch_np_lift(int eb, const LayerDev *L, int n, int64_t max_elems, hipStream_t st);
 hipError_t launch_np_auth(int eb, const LayerDev *L, int n, int obj_mask, int64_t max_elems, hipStream_t st);
 hipError_t launch_np_zero(int eb, const LayerDev *L, int n, int what, int64_t max_elems, hipStream_t st);
-hipError_t launch_np_open(int eb, const LayerDev *L, int n, int flags, int64_t max_elems, hipStream_t st);
+hipError_t launch_np_open(int eb, const LayerDev *L, int n, int which, int flags, int64_t max_elems, hipStream_t st);
 hipError_t launch_prob_base(int eb, const GemmProb *probs, int nprobs, int64_t max_mn, hipStream_t st);
 hipError_t launch_np_skinny(int eb, const LayerDev *L, int n, int flags, int64_t max_items, hipStream_t st);
 hipError_t launch_np_post(int eb, const LayerDev *L, int n, int flags, int64_t max_elems, hipStream_t st);
-hipError_t launch_np_compress(int eb, const LayerDev *L, int n, int64_t max_items, hipStream_t st);
+hipError_t launch_np_compress(int eb, const LayerDev *L, int n, int which_mask, int64_t max_items, hipStream_t st);
+// variants: bit v set if some fused layer takes row-pass variant v (0, 1, 2)
+hipError_t launch_np_row_pass(int eb, int np, const LayerDev *L, int n, int flags, int64_t max_items, int variants,
+                              hipStream_t st);
 hipError_t launch_np_gemv(int eb, const LayerDev *L, int n, int64_t max_items, hipStream_t st);
 hipError_t launch_np_compact_final(int eb, const LayerDev *L, int n, int flags, hipStream_t st);
 hipError_t launch_np_check_batch(int eb, const LayerDev *L, int n, int which_mask, int64_t max_elems, hipStream_t st);

@@ -493,12 +493,6 @@ __device__ __forceinline__ void row_pass_body(const LayerDev &L, int flags, R (&
     }
 }
 
-// Variant of the row pass a layer takes: 0 for matrix-core layers, else the
-// smallest of 1, 2, 4, 8 that holds N.  Each variant is its own kernel so the
-// register budget (and occupancy) of one does not limit the others.
-__host__ __device__ inline int row_variant(int64_t N) {
-    return N > SKINNY_MAX_N ? 0 : (N <= 1 ? 1 : (N <= 2 ? 2 : (N <= 4 ? 4 : SKINNY_MAX_N)));
-}
 
 // Layers compressed along M (CompactTag only) take k_row_pass_cm, every
 // other layer k_row_pass; each returns at once for the layers of the other.

@@ -16,6 +16,8 @@
 //            k_np_check_compact, then k_np_finalize.
 // Check accumulators of a layer: acc[W ACC_W + p] = sum chi [tW]_p for p < n,
 // acc[W ACC_W + MAXP] = sum chi W, W in (E, U, D).
+#include <algorithm>
+
 #include "ct_sweep.h"
 
 namespace ct {
@@ -101,20 +103,30 @@ hipError_t launch_np_auth(int eb, const LayerDev *L, int n, int obj_mask, int64_
 
 // ---------------------------------------------------------------- zeroing
 // what bit 0: the compact vectors ((1 + n) K + (2 + 4 n) M elements); bit 1:
-// the check accumulators.
+// the check accumulators; bit 2: for layers with N <= 2, [Z]_p = [C]_p (the
+// fused row pass adds their row products atomically); bit 3: also
+// [tZ]_p = [tC]_p.
 template <class R>
 __global__ void k_np_zero(const LayerDev *__restrict__ Ls, int what) {
     const LayerDev &L = Ls[blockIdx.y];
+    const int64_t t0 = blockIdx.x * (int64_t)TPB + threadIdx.x, stride = (int64_t)gridDim.x * TPB;
     if (what & 1) {
         const int64_t n = (1 + L.np) * L.K + (2 + 4 * L.np) * L.M;
-        for (int64_t e = blockIdx.x * (int64_t)TPB + threadIdx.x; e < n; e += (int64_t)gridDim.x * TPB)
-            st(P<R>(L.cvec), e, Ring<R>::zero());
+        for (int64_t e = t0; e < n; e += stride) st(P<R>(L.cvec), e, Ring<R>::zero());
     }
     if ((what & 2) && blockIdx.x == 0 && threadIdx.x < ACC_PER_LAYER) st(P<R>(L.acc), threadIdx.x, Ring<R>::zero());
+    if ((what & 4) && L.N <= 2) {
+        const int64_t n = L.M * L.N;
+        for (int64_t e = t0; e < n; e += stride)
+            for (int p = 0; p < L.np; p++) {
+                st(P<R>(L.Z[p]), e, ld(P<R>(L.C[p]), e));
+                if (what & 8) st(P<R>(L.tZ[p]), e, ld(P<R>(L.tC[p]), e));
+            }
+    }
 }
 
 hipError_t launch_np_zero(int eb, const LayerDev *L, int n, int what, int64_t max_elems, hipStream_t st) {
-    LAUNCH_RING(eb, k_np_zero, dim3((what & 1) ? grid_for(max_elems) : 1, n), dim3(TPB), st, L, what);
+    LAUNCH_RING(eb, k_np_zero, dim3((what & 5) ? grid_for(max_elems) : 1, n), dim3(TPB), st, L, what);
     return hipGetLastError();
 }
 
@@ -126,6 +138,7 @@ template <class R>
 __global__ __launch_bounds__(TPB) void k_np_open_e(const LayerDev *__restrict__ Ls, int flags) {
     __shared__ R sh[ACC_W * WAVES];
     const LayerDev &L = Ls[blockIdx.y];
+    if (np_fused_row(L.N)) return;  // opened by k_np_row_pass
     const int np = L.np;
     const bool check = flags & F_CHECK, spdz = flags & F_SPDZ, wide = L.N > SKINNY_MAX_N;
     const int64_t n = L.M * L.K;
@@ -186,9 +199,164 @@ __global__ __launch_bounds__(TPB) void k_np_open_u(const LayerDev *__restrict__ 
     if (check) block_accumulate<ACC_W>(chk, sh, P<R>(L.acc) + 1 * ACC_W);
 }
 
-hipError_t launch_np_open(int eb, const LayerDev *L, int n, int flags, int64_t max_elems, hipStream_t st) {
-    LAUNCH_RING(eb, k_np_open_e, dim3(grid_for(max_elems), n), dim3(TPB), st, L, flags);
-    LAUNCH_RING(eb, k_np_open_u, dim3(grid_for(max_elems), n), dim3(TPB), st, L, flags);
+// which: bit 0 opens E (layers the fused row pass does not serve), bit 1 opens U.
+// The elementwise passes that accumulate check sums run at most 1024
+// workgroups per layer: each adds its sums with one atomic per accumulator,
+// and same-address atomics serialize.
+inline int grid_acc(int64_t n) { return std::min(grid_for(n), 1024); }
+
+hipError_t launch_np_open(int eb, const LayerDev *L, int n, int which, int flags, int64_t max_elems, hipStream_t st) {
+    if (which & 1) LAUNCH_RING(eb, k_np_open_e, dim3(grid_acc(max_elems), n), dim3(TPB), st, L, flags);
+    if (which & 2) LAUNCH_RING(eb, k_np_open_u, dim3(grid_acc(max_elems), n), dim3(TPB), st, L, flags);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- fused row pass
+// One pass over M x K for matrix-core layers and layers with N <= 2 (the
+// n-party form of the two-party row pass): opens E = sum_p ([X]_p - [A]_p),
+// accumulates its batch check sums, writes the folded left operands
+// (A_0 + E; SPDZ2k [tA]_p + [Delta]_p E), adds the row products of the compact
+// tag (E U^c and per party E [tB^c]_p + [tA]_p U^c, onto zeroed vectors) and,
+// for N <= 2, forms every party's output row products
+//   [Z]_p = [C]_p + E [B]_p + L_p U (L_0 = A_0 + E, L_p = [A]_p),
+//   [tZ]_p = [tC]_p + E [tB]_p + ([tA]_p + [Delta]_p E) U (SPDZ2k),
+// added onto [Z]_p = [C]_p ([tZ]_p = [tC]_p) set by k_np_zero.  Items are row
+// segments of row_seg(M, K) elements taken segment-major, one wavefront each.
+// NP: the party count, a compile-time constant so that only NP parties'
+// accumulators take registers.
+template <class R, int NS, int NP>
+__global__ __launch_bounds__(TPB) void k_np_row_pass(const LayerDev *__restrict__ Ls, int flags) {
+    __shared__ R sh[ACC_W * WAVES];
+    const LayerDev &L = Ls[blockIdx.y];
+    if (!np_fused_row(L.N) || row_variant(L.N) != NS || L.np != NP) return;
+    constexpr int NZ = NS > 0 ? NS : 1;
+    constexpr int np = NP;
+    const int lane = threadIdx.x & 63;
+    const int64_t M = L.M, K = L.K, N = L.N, mk = M * K;
+    const bool check = flags & F_CHECK, compact = flags & F_COMPACT, spdz = flags & F_SPDZ;
+    const NpCvec o = np_cvec(M, K, np);
+    R *cv = P<R>(L.cvec);
+    R *W = P<R>(L.work);
+    const uint64_t kce = L.key[K_CHI_E];
+    R chk[ACC_W];
+#pragma unroll
+    for (int i = 0; i < ACC_W; i++) chk[i] = Ring<R>::zero();
+    const int64_t seg = row_seg(M, K), items = M * ((K + seg - 1) / seg);
+    const int64_t wave_id = (blockIdx.x * (int64_t)TPB + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * TPB) >> 6;
+    for (int64_t it = wave_id; it < items; it += nwaves) {
+        const int64_t sg = it / M, m = it - sg * M, k0 = sg * seg;
+        const int64_t k1 = k0 + seg < K ? k0 + seg : K;
+        R cp[1 + MAXP];  // E U^c, then per party E [tB^c]_p + [tA]_p U^c
+#pragma unroll
+        for (int i = 0; i < 1 + MAXP; i++) cp[i] = Ring<R>::zero();
+        R z[MAXP][NZ], t[MAXP][NZ];
+#pragma unroll
+        for (int p = 0; p < MAXP; p++)
+#pragma unroll
+            for (int j = 0; j < NZ; j++) z[p][j] = t[p][j] = Ring<R>::zero();
+        for (int64_t k = k0 + lane; k < k1; k += 64) {
+            const int64_t e = m * K + k;
+            R E = Ring<R>::zero(), a[MAXP];
+#pragma unroll
+            for (int p = 0; p < MAXP; p++) {
+                a[p] = Ring<R>::zero();
+                if (p < np) {
+                    a[p] = ld(P<R>(L.A[p]), e);
+                    E = add(E, sub(ld_nt(P<R>(L.X[p]), e), a[p]));
+                }
+            }
+            st(P<R>(L.E), e, E);
+            if constexpr (NS == 0) {
+                st(W, e, add(a[0], E));
+            }
+            uint64_t x = 0;
+            if (check) {
+                x = Ring<R>::mod_s(sdraw(kce, (uint64_t)e));
+                chk[MAXP] = mad64(chk[MAXP], E, x);
+            }
+            const R uc = compact ? ld(cv + o.Uc, k) : Ring<R>::zero();
+            if (compact) cp[0] = mad(cp[0], E, uc);
+#pragma unroll
+            for (int p = 0; p < MAXP; p++) {
+                if (p < np) {
+                    const R ta = ld_nt(P<R>(L.tA[p]), e);
+                    if (check) chk[p] = mad64(chk[p], sub(ld_nt(P<R>(L.tX[p]), e), ta), x);
+                    if (compact) cp[1 + p] = mad(mad(cp[1 + p], E, ld(cv + o.tb(p), k)), ta, uc);
+                    const R tae = spdz ? add(ta, mul64(E, L.delta[p])) : Ring<R>::zero();
+                    if constexpr (NS == 0) {
+                        if (spdz) st(W + (1 + p) * mk, e, tae);  // folded tag operand of party p
+                    } else {
+                        const R ap = p == 0 ? add(a[0], E) : a[p];
+#pragma unroll
+                        for (int j = 0; j < NS; j++) {
+                            if (j < N) {
+                                const int64_t kn = k * N + j;
+                                const R u = ld(P<R>(L.U), kn);
+                                z[p][j] = mad(mad(z[p][j], E, ld(P<R>(L.B[p]), kn)), ap, u);
+                                if (spdz) t[p][j] = mad(mad(t[p][j], E, ld(P<R>(L.tB[p]), kn)), tae, u);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        if (compact) {
+#pragma unroll
+            for (int i = 0; i < 1 + MAXP; i++)
+                if (i < 1 + np) cp[i] = wave_sum(cp[i]);
+            if (lane == 0) {
+                atomic_add128(cv + o.EUc + m, cp[0]);
+#pragma unroll
+                for (int p = 0; p < MAXP; p++)
+                    if (p < np) atomic_add128(cv + o.tz(p) + m, cp[1 + p]);
+            }
+        }
+        if constexpr (NS > 0) {
+#pragma unroll
+            for (int p = 0; p < MAXP; p++) {
+                if (p < np) {
+#pragma unroll
+                    for (int j = 0; j < NS; j++) {
+                        if (j < N) {
+                            z[p][j] = wave_sum(z[p][j]);
+                            if (spdz) t[p][j] = wave_sum(t[p][j]);
+                            if (lane == 0) {
+                                atomic_add128(P<R>(L.Z[p]) + m * N + j, z[p][j]);
+                                if (spdz) atomic_add128(P<R>(L.tZ[p]) + m * N + j, t[p][j]);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (check) block_accumulate<ACC_W>(chk, sh, P<R>(L.acc) + 0 * ACC_W);
+}
+
+template <class R, int NP>
+void launch_np_row_variants(const dim3 &g, const LayerDev *L, int flags, int variants, hipStream_t st) {
+    const dim3 b(TPB);
+    if (variants & (1 << 0)) hipLaunchKernelGGL((k_np_row_pass<R, 0, NP>), g, b, 0, st, L, flags);
+    if (variants & (1 << 1)) hipLaunchKernelGGL((k_np_row_pass<R, 1, NP>), g, b, 0, st, L, flags);
+    if (variants & (1 << 2)) hipLaunchKernelGGL((k_np_row_pass<R, 2, NP>), g, b, 0, st, L, flags);
+}
+
+template <class R>
+void launch_np_row_parties(int np, const dim3 &g, const LayerDev *L, int flags, int variants, hipStream_t st) {
+    static_assert(MAXP == 5, "one instantiation per party count");
+    if (np == 3) launch_np_row_variants<R, 3>(g, L, flags, variants, st);
+    else if (np == 4) launch_np_row_variants<R, 4>(g, L, flags, variants, st);
+    else launch_np_row_variants<R, 5>(g, L, flags, variants, st);
+}
+
+hipError_t launch_np_row_pass(int eb, int np, const LayerDev *L, int n, int flags, int64_t max_items, int variants,
+                              hipStream_t st) {
+    // at most 2048 workgroups: each adds its check sums with one atomic per
+    // accumulator, and same-address atomics serialize
+    const dim3 g(std::min(grid_items(max_items), 2048), n);
+    if (eb == 8) launch_np_row_parties<r64>(np, g, L, flags, variants, st);
+    else launch_np_row_parties<u128>(np, g, L, flags, variants, st);
     return hipGetLastError();
 }
 
@@ -215,7 +383,7 @@ template <class R>
 __global__ __launch_bounds__(TPB) void k_np_skinny(const LayerDev *__restrict__ Ls, int flags) {
     const LayerDev &L = Ls[blockIdx.y];
     const int64_t M = L.M, K = L.K, N = L.N;
-    if (N > SKINNY_MAX_N) return;
+    if (np_fused_row(N)) return;
     const int np = L.np, lane = threadIdx.x & 63;
     const bool spdz = flags & F_SPDZ;
     const int64_t items = M * np;
@@ -309,7 +477,7 @@ __global__ __launch_bounds__(TPB) void k_np_post(const LayerDev *__restrict__ Ls
 }
 
 hipError_t launch_np_post(int eb, const LayerDev *L, int n, int flags, int64_t max_elems, hipStream_t st) {
-    LAUNCH_RING(eb, k_np_post, dim3(grid_for(max_elems), n), dim3(TPB), st, L, flags);
+    LAUNCH_RING(eb, k_np_post, dim3(grid_acc(max_elems), n), dim3(TPB), st, L, flags);
     return hipGetLastError();
 }
 
@@ -318,9 +486,10 @@ hipError_t launch_np_post(int eb, const LayerDev *L, int n, int flags, int64_t m
 // the rows of K x N (U^c, [tB^c]_p), y = 2 l + 1 over the rows of M x N
 // (D^c, [tR^c]_p, [tC^c]_p).
 template <class R>
-__global__ __launch_bounds__(TPB) void k_np_compress(const LayerDev *__restrict__ Ls) {
+__global__ __launch_bounds__(TPB) void k_np_compress(const LayerDev *__restrict__ Ls, int which_mask) {
     const LayerDev &L = Ls[blockIdx.y >> 1];
     const int which = blockIdx.y & 1, np = L.np;
+    if (!((which_mask >> which) & 1)) return;
     const NpCvec o = np_cvec(L.M, L.K, np);
     R *cv = P<R>(L.cvec);
     const uint64_t kchi = L.key[K_CHI];
@@ -362,8 +531,8 @@ __global__ __launch_bounds__(TPB) void k_np_compress(const LayerDev *__restrict_
     }
 }
 
-hipError_t launch_np_compress(int eb, const LayerDev *L, int n, int64_t max_items, hipStream_t st) {
-    LAUNCH_RING(eb, k_np_compress, dim3(grid_items(max_items), 2 * n), dim3(TPB), st, L);
+hipError_t launch_np_compress(int eb, const LayerDev *L, int n, int which_mask, int64_t max_items, hipStream_t st) {
+    LAUNCH_RING(eb, k_np_compress, dim3(grid_items(max_items), 2 * n), dim3(TPB), st, L, which_mask);
     return hipGetLastError();
 }
 
@@ -372,6 +541,7 @@ hipError_t launch_np_compress(int eb, const LayerDev *L, int n, int64_t max_item
 template <class R>
 __global__ __launch_bounds__(TPB) void k_np_gemv(const LayerDev *__restrict__ Ls) {
     const LayerDev &L = Ls[blockIdx.y];
+    if (np_fused_row(L.N)) return;  // formed by k_np_row_pass
     const int np = L.np;
     const NpCvec o = np_cvec(L.M, L.K, np);
     R *cv = P<R>(L.cvec);
