@@ -46,28 +46,32 @@ def stage_work(stage: str, specs, mode: str, f: int = 0, kbits: int = 64, compre
                implicit: bool = False, parties: int = 2):
     """Algorithmic work of one launch of a kernel stage over the layer batch:
     ("hbm", bytes) or ("mfma", int8 ops), for the fused step
-    (online phase + verification).  16 B per Z_2^128 element; per element:
-      open_u     K x N: reads Y_p, B_p, tY_p, tB_p (8), writes U: 144 B
-      row_pass   M x K: reads X_p, A_p, tX_p, tA_p (8), writes E: 144 B,
-                 plus the folded operands written for matrix-core layers
-                 (A_0 + E; SPDZ2k also tA_p + Delta_p E): 16 / 48 B
+    (online phase + verification).  16 B per Z_2^128 element; per element,
+    with n parties (two: the figures in brackets):
+      open_u     K x N: reads Y_p, B_p, tY_p, tB_p (4 n), writes U:
+                 64 n + 16 B [144]
+      row_pass   M x K: reads X_p, A_p, tX_p, tA_p (4 n), writes E:
+                 64 n + 16 B [144], plus the folded operands written for
+                 matrix-core layers (A_0 + E; SPDZ2k also tA_p + Delta_p E):
+                 16 [16] / 16 + 16 n [48] B
       pack       matrix-core layers: reads each operand once and writes its
-                 digit tiles, 32 B per element: M x K: E, A_0 + E, [A]_1
-                 (SPDZ2k also the two folded tag operands): 96 / 160 B;
-                 K x N: [B]_0, [B]_1, U (SPDZ2k also [tB]_p): 96 / 160 B
-      copy_base  M x N: 32 B per array (2 arrays, 4 in SPDZ2k), N > 8 layers
+                 digit tiles, 32 B per element: M x K: E, A_0 + E, [A]_p
+                 (p > 0; SPDZ2k also the n folded tag operands):
+                 32 (n + 1) [96] / 32 (2 n + 1) [160] B; K x N: [B]_p, U
+                 (SPDZ2k also [tB]_p): the same counts
+      copy_base  M x N: 32 B per array (n arrays, 2 n in SPDZ2k), N > 8 layers
       ring_gemm  2 * 136 int8 ops per ring MAC; 2 n M K N ring MACs per
-                 layer for n parties (4 n in SPDZ2k), layers with N > 8
-      post       M x N: CompactTag reads R_p, Z_p, tR_p, tC_p (8), writes D,
-                 tZ_p (3): 176 B; SPDZ2k reads R_p, Z_p, tR_p, tZ_p (8),
-                 writes D: 144 B; with f > 0 also reads R^f_p, tR^f_p and
-                 writes Z^f_p, tZ^f_p: + 128 B.
-      col_tag    layers compressed along M, K x N: reads U, tB_p: 48 B.
+                 layer (4 n in SPDZ2k), layers with N > 8
+      post       M x N: CompactTag reads R_p, Z_p, tR_p, tC_p (4 n), writes
+                 D, tZ_p (n + 1): 80 n + 16 B [176]; SPDZ2k reads R_p, Z_p,
+                 tR_p, tZ_p (4 n), writes D: 64 n + 16 B [144]; with f > 0
+                 also reads R^f_p, tR^f_p and writes Z^f_p, tZ^f_p: + 64 n B.
+      col_tag    layers compressed along M, K x N: reads U, tB_p: 16 n + 16 B.
     With implicit convolutions (im2col left implicit) the right operand's
-    arrays have the input's C H W elements: open_u moves 144 B per input
+    arrays have the input's C H W elements: open_u moves its bytes per input
     element, the packing of each right operand reads 16 B per input element
-    and writes 32 B per K x N entry, and conv_compress reads U, tB_p: 48 B per
-    input element.
+    and writes 32 B per K x N entry, and conv_compress reads U, tB_p:
+    16 n + 16 B per input element.
     With k = s = 32 elements are 8 B (every byte figure halves) and a ring
     MAC is 36 digit products."""
     scale = 1 if kbits == 64 else 0.5
@@ -80,24 +84,26 @@ def stage_work(stage: str, specs, mode: str, f: int = 0, kbits: int = 64, compre
         wide = N > 8
         conv = implicit and s.conv is not None
         nr = s.conv[0] * s.conv[1] * s.conv[2] if conv else kn
+        n = parties
+        elem = 64 * n + 16                  # 4 n share arrays read, one opened value written
+        nops = (2 * n + 1) if spdz else (n + 1)  # packed operands per side
         if stage == "open_u":
-            tot += 144 * nr
+            tot += elem * nr
         elif stage == "row_pass":
-            tot += 144 * mk + ((48 if spdz else 16) * mk if wide else 0)
+            tot += elem * mk + ((16 + 16 * n if spdz else 16) * mk if wide else 0)
         elif stage == "pack":
-            nright = 5 if spdz else 3
-            right = nright * (16 * nr + 32 * kn) if conv else (160 if spdz else 96) * kn
-            tot += ((160 if spdz else 96) * mk + right) if wide else 0
+            right = nops * (16 * nr + 32 * kn) if conv else 32 * nops * kn
+            tot += (32 * nops * mk + right) if wide else 0
         elif stage == "conv_compress":
-            tot += 48 * nr if conv and not spdz and not along_m(s, compress) else 0
+            tot += (16 * n + 16) * nr if conv and not spdz and not along_m(s, compress) else 0
         elif stage == "copy_base":
-            tot += (32 * mn * (4 if spdz else 2)) if wide else 0
+            tot += (32 * mn * (2 * n if spdz else n)) if wide else 0
         elif stage == "ring_gemm":
             tot += 2 * pairs * (4 if spdz else 2) * parties * M * K * N if wide else 0
         elif stage == "post":
-            tot += ((144 if spdz else 176) + (128 if f > 0 else 0)) * mn
+            tot += ((64 * n + 16 if spdz else 80 * n + 16) + (64 * n if f > 0 else 0)) * mn
         elif stage == "col_tag":
-            tot += 48 * kn if not spdz and along_m(s, compress) else 0
+            tot += (16 * n + 16) * kn if not spdz and along_m(s, compress) else 0
         else:
             return None
     if stage == "ring_gemm":

@@ -54,6 +54,12 @@ __device__ __forceinline__ u128 ld_nt(const u128 *p, int64_t i) {
 __device__ __forceinline__ void st(u128 *p, int64_t i, u128 v) {
     reinterpret_cast<ulonglong2 *>(p)[i] = make_ulonglong2(v.lo, v.hi);
 }
+// A store of streamed output that is not read again soon (non-temporal hint);
+// one 16-byte store.
+typedef unsigned long long ct_u64x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void st_nt(u128 *p, int64_t i, u128 v) {
+    __builtin_nontemporal_store(ct_u64x2{v.lo, v.hi}, reinterpret_cast<ct_u64x2 *>(p) + i);
+}
 
 // Exact accumulation into a Z_{2^128} cell from many threads: the low limb is
 // added atomically, and its wrap-around (old + v.lo >= 2^64) is carried into
@@ -111,6 +117,7 @@ __device__ __forceinline__ r64 mad(r64 acc, r64 a, r64 b) { return r64{acc.v + a
 __device__ __forceinline__ r64 ld(const r64 *p, int64_t i) { return p[i]; }
 __device__ __forceinline__ r64 ld_nt(const r64 *p, int64_t i) { return r64{__builtin_nontemporal_load(&p[i].v)}; }
 __device__ __forceinline__ void st(r64 *p, int64_t i, r64 v) { p[i] = v; }
+__device__ __forceinline__ void st_nt(r64 *p, int64_t i, r64 v) { __builtin_nontemporal_store(v.v, &p[i].v); }
 __device__ __forceinline__ void atomic_add128(r64 *p, r64 v) {
     atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v.v);
 }

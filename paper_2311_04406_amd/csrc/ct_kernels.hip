@@ -397,30 +397,39 @@ __device__ __forceinline__ void row_pass_body(const LayerDev &L, int flags, R (&
 #pragma unroll
         for (int j = 0; j < (NS > 0 ? NS : 1); j++) z0[j] = z1[j] = t0[j] = t1[j] = Ring<R>::zero();
         const int64_t rb = m * K;
-        for (int64_t k = k0 + lane; k < k1; k += 64) {
-            const int64_t e = rb + k;
-            // every load of the element is issued before the store of E (which
-            // the compiler may not move them across); the arrays are streamed,
-            // except [A]_1 of a matrix-core layer, which k_pack reads next
-            const R a0 = ld_nt(P<R>(L.A[0]), e);
-            const R a1 = skinny ? ld_nt(P<R>(L.A[1]), e) : ld(P<R>(L.A[1]), e);
-            const R x0 = ld_nt(P<R>(L.X[0]), e), x1 = ld_nt(P<R>(L.X[1]), e);
-            const bool need_ta = check || compact || spdz;
-            R ta0 = Ring<R>::zero(), ta1 = Ring<R>::zero(), tx0 = Ring<R>::zero(), tx1 = Ring<R>::zero();
+        // the elements of one M x K position: shares of X, A and their tags
+        struct In {
+            R a0, a1, x0, x1, ta0, ta1, tx0, tx1;
+        };
+        const bool need_ta = check || compact || spdz;
+        auto load = [&](int64_t e, In &v) {
+            // the arrays are streamed, except [A]_1 of a matrix-core layer,
+            // which k_pack reads next
+            v.a0 = ld_nt(P<R>(L.A[0]), e);
+            v.a1 = skinny ? ld_nt(P<R>(L.A[1]), e) : ld(P<R>(L.A[1]), e);
+            v.x0 = ld_nt(P<R>(L.X[0]), e);
+            v.x1 = ld_nt(P<R>(L.X[1]), e);
+            v.ta0 = v.ta1 = v.tx0 = v.tx1 = Ring<R>::zero();
             if (need_ta) {
-                ta0 = ld_nt(P<R>(L.tA[0]), e);
-                ta1 = ld_nt(P<R>(L.tA[1]), e);
+                v.ta0 = ld_nt(P<R>(L.tA[0]), e);
+                v.ta1 = ld_nt(P<R>(L.tA[1]), e);
             }
             if (check) {
-                tx0 = ld_nt(P<R>(L.tX[0]), e);
-                tx1 = ld_nt(P<R>(L.tX[1]), e);
+                v.tx0 = ld_nt(P<R>(L.tX[0]), e);
+                v.tx1 = ld_nt(P<R>(L.tX[1]), e);
             }
-            const R E = add(sub(x0, a0), sub(x1, a1));
-            st(P<R>(L.E), e, E);
+        };
+        auto use = [&](int64_t k, const In &v) {
+            const int64_t e = rb + k;
+            const R E = add(sub(v.x0, v.a0), sub(v.x1, v.a1));
+            // E of a layer whose products are formed here is not read again
+            // in the step; a matrix-core layer's is packed next
+            if (skinny) st_nt(P<R>(L.E), e, E);
+            else st(P<R>(L.E), e, E);
             if (check) {
                 const uint64_t x = Ring<R>::mod_s(sdraw(kce, (uint64_t)e));
-                chk[0] = mad64(chk[0], sub(tx0, ta0), x);
-                chk[1] = mad64(chk[1], sub(tx1, ta1), x);
+                chk[0] = mad64(chk[0], sub(v.tx0, v.ta0), x);
+                chk[1] = mad64(chk[1], sub(v.tx1, v.ta1), x);
                 chk[2] = mad64(chk[2], E, x);
             }
             if (compact) {
@@ -428,17 +437,17 @@ __device__ __forceinline__ void row_pass_body(const LayerDev &L, int flags, R (&
                 cp[0] = mad(cp[0], E, uc);
                 cp[1] = mad(cp[1], E, ld(tBc0, k));
                 cp[2] = mad(cp[2], E, ld(tBc1, k));
-                cp[3] = mad(cp[3], ta0, uc);
-                cp[4] = mad(cp[4], ta1, uc);
+                cp[3] = mad(cp[3], v.ta0, uc);
+                cp[4] = mad(cp[4], v.ta1, uc);
             }
             if constexpr (!skinny) {
                 // folded left operands of the matrix-core products:
                 //   [Z]_0 = [C]_0 + E [B]_0 + (A_0 + E) U,
                 //   [tZ]_p = [tC]_p + E [tB]_p + ([tA]_p + [Delta]_p E) U
-                st(AE0, e, add(a0, E));
+                st(AE0, e, add(v.a0, E));
                 if (spdz) {
-                    st(tAE0, e, add(ta0, mul64(E, d0)));
-                    st(tAE1, e, add(ta1, mul64(E, d1)));
+                    st(tAE0, e, add(v.ta0, mul64(E, d0)));
+                    st(tAE1, e, add(v.ta1, mul64(E, d1)));
                 }
             } else {
 #pragma unroll
@@ -446,15 +455,25 @@ __device__ __forceinline__ void row_pass_body(const LayerDev &L, int flags, R (&
                     if (j < N) {
                         const int64_t kn = k * N + j;
                         const R u = ld(P<R>(L.U), kn);
-                        z0[j] = mad(mad(z0[j], E, add(ld(P<R>(L.B[0]), kn), u)), a0, u);
-                        z1[j] = mad(mad(z1[j], E, ld(P<R>(L.B[1]), kn)), a1, u);
+                        z0[j] = mad(mad(z0[j], E, add(ld(P<R>(L.B[0]), kn), u)), v.a0, u);
+                        z1[j] = mad(mad(z1[j], E, ld(P<R>(L.B[1]), kn)), v.a1, u);
                         if (spdz) {
-                            t0[j] = mad(mad(t0[j], E, add(ld(P<R>(L.tB[0]), kn), mul64(u, d0))), ta0, u);
-                            t1[j] = mad(mad(t1[j], E, add(ld(P<R>(L.tB[1]), kn), mul64(u, d1))), ta1, u);
+                            t0[j] = mad(mad(t0[j], E, add(ld(P<R>(L.tB[0]), kn), mul64(u, d0))), v.ta0, u);
+                            t1[j] = mad(mad(t1[j], E, add(ld(P<R>(L.tB[1]), kn), mul64(u, d1))), v.ta1, u);
                         }
                     }
                 }
             }
+        };
+        // every load of the element is issued before the store of E (which
+        // the compiler may not move loads across).  Two elements per lane at
+        // a time would double the loads in flight but costs registers: the
+        // skinny pass then runs 3 wavefronts per SIMD instead of 4, and is
+        // slower.
+        for (int64_t k = k0 + lane; k < k1; k += 64) {
+            In v;
+            load(rb + k, v);
+            use(k, v);
         }
         if (compact) {
 #pragma unroll
@@ -532,7 +551,11 @@ void launch_row_variants(const dim3 &g, const LayerDev *L, int flags, int varian
 }
 
 hipError_t launch_row_pass(int eb, const LayerDev *L, int n, int flags, int64_t max_items, int variants, hipStream_t st) {
-    const dim3 g(grid_items(max_items), n);
+    // at most 2048 workgroups (8 per compute unit), each sweeping many items:
+    // every workgroup adds its check sums with one atomic per accumulator, and
+    // same-address atomics serialize (1024 leaves the memory system underfed)
+    const int gx = grid_items(max_items);
+    const dim3 g(gx > 2048 ? 2048 : gx, n);
     if (eb == 8) launch_row_variants<r64>(g, L, flags, variants, st);
     else launch_row_variants<u128>(g, L, flags, variants, st);
     return hipGetLastError();

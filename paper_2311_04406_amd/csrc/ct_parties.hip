@@ -255,35 +255,48 @@ __global__ __launch_bounds__(TPB) void k_np_row_pass(const LayerDev *__restrict_
         for (int p = 0; p < MAXP; p++)
 #pragma unroll
             for (int j = 0; j < NZ; j++) z[p][j] = t[p][j] = Ring<R>::zero();
+        const bool need_ta = check || compact || spdz;
         for (int64_t k = k0 + lane; k < k1; k += 64) {
             const int64_t e = m * K + k;
-            R E = Ring<R>::zero(), a[MAXP];
+            // every load of the element is issued before the store of E (which
+            // the compiler may not move loads across); the arrays are
+            // streamed, except [A]_p (p > 0) of a matrix-core layer, which
+            // k_pack reads next
+            R a[MAXP], x[MAXP], ta[MAXP], tx[MAXP];
 #pragma unroll
             for (int p = 0; p < MAXP; p++) {
-                a[p] = Ring<R>::zero();
+                a[p] = x[p] = ta[p] = tx[p] = Ring<R>::zero();
                 if (p < np) {
-                    a[p] = ld(P<R>(L.A[p]), e);
-                    E = add(E, sub(ld_nt(P<R>(L.X[p]), e), a[p]));
+                    a[p] = (NS > 0 || p == 0) ? ld_nt(P<R>(L.A[p]), e) : ld(P<R>(L.A[p]), e);
+                    x[p] = ld_nt(P<R>(L.X[p]), e);
+                    if (need_ta) ta[p] = ld_nt(P<R>(L.tA[p]), e);
+                    if (check) tx[p] = ld_nt(P<R>(L.tX[p]), e);
                 }
             }
-            st(P<R>(L.E), e, E);
+            R E = Ring<R>::zero();
+#pragma unroll
+            for (int p = 0; p < MAXP; p++)
+                if (p < np) E = add(E, sub(x[p], a[p]));
+            // E of a layer whose products are formed here is not read again
+            // in the step; a matrix-core layer's is packed next
+            if constexpr (NS > 0) st_nt(P<R>(L.E), e, E);
+            else st(P<R>(L.E), e, E);
             if constexpr (NS == 0) {
                 st(W, e, add(a[0], E));
             }
-            uint64_t x = 0;
+            uint64_t xe = 0;
             if (check) {
-                x = Ring<R>::mod_s(sdraw(kce, (uint64_t)e));
-                chk[MAXP] = mad64(chk[MAXP], E, x);
+                xe = Ring<R>::mod_s(sdraw(kce, (uint64_t)e));
+                chk[MAXP] = mad64(chk[MAXP], E, xe);
             }
             const R uc = compact ? ld(cv + o.Uc, k) : Ring<R>::zero();
             if (compact) cp[0] = mad(cp[0], E, uc);
 #pragma unroll
             for (int p = 0; p < MAXP; p++) {
                 if (p < np) {
-                    const R ta = ld_nt(P<R>(L.tA[p]), e);
-                    if (check) chk[p] = mad64(chk[p], sub(ld_nt(P<R>(L.tX[p]), e), ta), x);
-                    if (compact) cp[1 + p] = mad(mad(cp[1 + p], E, ld(cv + o.tb(p), k)), ta, uc);
-                    const R tae = spdz ? add(ta, mul64(E, L.delta[p])) : Ring<R>::zero();
+                    if (check) chk[p] = mad64(chk[p], sub(tx[p], ta[p]), xe);
+                    if (compact) cp[1 + p] = mad(mad(cp[1 + p], E, ld(cv + o.tb(p), k)), ta[p], uc);
+                    const R tae = spdz ? add(ta[p], mul64(E, L.delta[p])) : Ring<R>::zero();
                     if constexpr (NS == 0) {
                         if (spdz) st(W + (1 + p) * mk, e, tae);  // folded tag operand of party p
                     } else {
