@@ -241,6 +241,25 @@ __device__ __forceinline__ void slice_products(const uint8_t *stage, int a_frag,
     }
 }
 
+// Fragment t of the A (side 0) or B (side 1) tile in an LDS stage.
+template <int NB>
+__device__ __forceinline__ v4i frag(const uint8_t *stage, int side, int t, int off) {
+    return *reinterpret_cast<const v4i *>(stage + (side * NB + t) * PLANE + off);
+}
+
+// Product group T of a K slice: the digit pairs (T, j), j <= T, and (i, T),
+// i < T, with digit sum below NB -- the products that fragment pair T
+// completes.  Group sizes 1, 3, 5, ... up to NB / 2, then 2 (NB - T).
+template <int NB>
+__device__ __forceinline__ void group_products(int T, const v4i (&a)[NB], const v4i (&b)[NB], v16i (&acc)[NB]) {
+#pragma unroll
+    for (int j = 0; j < NB; j++)
+        if (j <= T && T + j < NB) acc[T + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[T], b[j], acc[T + j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < NB; i++)
+        if (i < T && i + T < NB) acc[i + T] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[T], acc[i + T], 0, 0, 0);
+}
+
 // vmcnt(0), expcnt and lgkmcnt left unconstrained (gfx9 s_waitcnt encoding)
 #define WAIT_VMEM() __builtin_amdgcn_s_waitcnt(0x0F70)
 
@@ -276,15 +295,54 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &P, int tm, int tn, int
     const int a_frag = arow * BK + ((chunk ^ half_swap(arow)) << 4);
     const int b_frag = brow * BK + ((chunk ^ half_swap(brow)) << 4);
 
+    // Software pipeline over K slices (LDS stages alternate):
+    //   top of slice s: copy slice s+1 global -> LDS (the other stage);
+    //   product group t reads fragment pair t+2 (two groups of products
+    //   cover the LDS latency);
+    //   after group NB-3 every fragment of slice s is in registers: wait for
+    //   this wavefront's copies, barrier (slice s+1 has landed and no
+    //   wavefront reads stage s any more), read fragment pairs 0 and 1 of
+    //   slice s+1, then the last two groups of slice s hide their latency.
+    // Scheduling barriers keep the compiler from regrouping the reads.
+    v4i a[NB], b[NB], a0n, b0n, a1n, b1n;
     if (s_begin < s_end) issue_slice<R>(a_tile(s_begin), b_tile(s_begin), lds);
     WAIT_VMEM();
     __syncthreads();
+    a[0] = frag<NB>(lds, 0, 0, a_frag);
+    b[0] = frag<NB>(lds, 1, 0, b_frag);
+    a[1] = frag<NB>(lds, 0, 1, a_frag);
+    b[1] = frag<NB>(lds, 1, 1, b_frag);
     for (int s = s_begin; s < s_end; s++) {
         const int buf = (s - s_begin) & 1;
-        if (s + 1 < s_end) issue_slice<R>(a_tile(s + 1), b_tile(s + 1), lds + (buf ^ 1) * STAGE);
-        slice_products<NB>(lds + buf * STAGE, a_frag, b_frag, acc);
-        WAIT_VMEM();
-        __syncthreads();
+        const uint8_t *stage = lds + buf * STAGE;
+        uint8_t *next = lds + (buf ^ 1) * STAGE;
+        const bool more = s + 1 < s_end;
+        if (more) issue_slice<R>(a_tile(s + 1), b_tile(s + 1), next);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int t = 0; t < NB; t++) {
+            if (t + 2 < NB) {
+                a[t + 2] = frag<NB>(stage, 0, t + 2, a_frag);
+                b[t + 2] = frag<NB>(stage, 1, t + 2, b_frag);
+            }
+            group_products<NB>(t, a, b, acc);
+            __builtin_amdgcn_sched_barrier(0);
+            if (t == NB - 3) {
+                WAIT_VMEM();
+                __syncthreads();
+                if (more) {
+                    a0n = frag<NB>(next, 0, 0, a_frag);
+                    b0n = frag<NB>(next, 1, 0, b_frag);
+                    a1n = frag<NB>(next, 0, 1, a_frag);
+                    b1n = frag<NB>(next, 1, 1, b_frag);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        a[0] = a0n;
+        b[0] = b0n;
+        a[1] = a1n;
+        b[1] = b1n;
     }
 
     // epilogue: 32x32 accumulator layout -- lane l, register r holds
