@@ -49,7 +49,10 @@ def stage_work(stage: str, specs, mode: str, f: int = 0, kbits: int = 64, compre
     (online phase + verification).  16 B per Z_2^128 element; per element,
     with n parties (two: the figures in brackets):
       open_u     K x N: reads Y_p, B_p, tY_p, tB_p (4 n), writes U:
-                 64 n + 16 B [144]
+                 64 n + 16 B [144]; two-party matrix-core layers that are
+                 not convolutions take open_pack instead
+      open_pack  those layers, K x N: the same, and writes the digit tiles
+                 of [B]_0, [B]_1, U (16 B each per element): 192 B
       row_pass   M x K: reads X_p, A_p, tX_p, tA_p (4 n), writes E:
                  64 n + 16 B [144], plus the folded operands written for
                  matrix-core layers (A_0 + E; SPDZ2k also tA_p + Delta_p E):
@@ -58,12 +61,16 @@ def stage_work(stage: str, specs, mode: str, f: int = 0, kbits: int = 64, compre
                  digit tiles, 32 B per element: M x K: E, A_0 + E, [A]_p
                  (p > 0; SPDZ2k also the n folded tag operands):
                  32 (n + 1) [96] / 32 (2 n + 1) [160] B; K x N: [B]_p, U
-                 (SPDZ2k also [tB]_p): the same counts
-      copy_base  M x N: 32 B per array (n arrays, 2 n in SPDZ2k), N > 8 layers
+                 (SPDZ2k also [tB]_p): the same counts, less the three
+                 operands open_pack writes
+      copy_base  M x N base copies of the products whose K range is split
+                 (32 B per element); which products split depends on the
+                 tile plan, so no byte figure is given
       ring_gemm  2 * 136 int8 ops per ring MAC; 2 n M K N ring MACs per
                  layer (4 n in SPDZ2k), layers with N > 8
       post       M x N: CompactTag reads R_p, Z_p, tR_p, tC_p (4 n), writes
-                 D, tZ_p (n + 1): 80 n + 16 B [176]; SPDZ2k reads R_p, Z_p,
+                 D, tZ_p (n + 1): 80 n + 16 B [176] (beyond two parties tC_p
+                 is compressed in a pass of its own: 64 n + 16 B); SPDZ2k reads R_p, Z_p,
                  tR_p, tZ_p (4 n), writes D: 64 n + 16 B [144]; with f > 0
                  also reads R^f_p, tR^f_p and writes Z^f_p, tZ^f_p: + 64 n B.
       col_tag    layers compressed along M, K x N: reads U, tB_p: 16 n + 16 B.
@@ -87,21 +94,24 @@ def stage_work(stage: str, specs, mode: str, f: int = 0, kbits: int = 64, compre
         n = parties
         elem = 64 * n + 16                  # 4 n share arrays read, one opened value written
         nops = (2 * n + 1) if spdz else (n + 1)  # packed operands per side
+        fused = n == 2 and wide and not conv     # U opened and right operands packed in one pass
         if stage == "open_u":
-            tot += elem * nr
+            tot += 0 if fused else elem * nr
+        elif stage == "open_pack":
+            tot += (elem + 48) * kn if fused else 0
         elif stage == "row_pass":
             tot += elem * mk + ((16 + 16 * n if spdz else 16) * mk if wide else 0)
         elif stage == "pack":
-            right = nops * (16 * nr + 32 * kn) if conv else 32 * nops * kn
+            right = nops * (16 * nr + 32 * kn) if conv else 32 * (nops - (3 if fused else 0)) * kn
             tot += (32 * nops * mk + right) if wide else 0
         elif stage == "conv_compress":
             tot += (16 * n + 16) * nr if conv and not spdz and not along_m(s, compress) else 0
         elif stage == "copy_base":
-            tot += (32 * mn * (2 * n if spdz else n)) if wide else 0
+            return None
         elif stage == "ring_gemm":
             tot += 2 * pairs * (4 if spdz else 2) * parties * M * K * N if wide else 0
         elif stage == "post":
-            tot += ((64 * n + 16 if spdz else 80 * n + 16) + (64 * n if f > 0 else 0)) * mn
+            tot += ((64 * n + 16 if spdz or n > 2 else 80 * n + 16) + (64 * n if f > 0 else 0)) * mn
         elif stage == "col_tag":
             tot += (16 * n + 16) * kn if not spdz and along_m(s, compress) else 0
         else:

@@ -24,7 +24,7 @@ using namespace ct;
 static const char *kStageNames[ST_COUNT] = {
     "deal_lift", "fill_zero", "deal_auth", "deal_skinny", "zero_acc", "open_u", "row_pass", "pack",
     "copy_base", "ring_gemm", "post", "compact_final", "check_batch", "check_compact", "finalize", "col_tag",
-    "conv_compress", "np_open", "np_skinny", "np_compress", "np_gemv"};
+    "conv_compress", "np_open", "np_skinny", "np_compress", "np_gemv", "open_pack"};
 constexpr int EV_POOL = 2048;
 
 struct ct_plan {
@@ -737,6 +737,7 @@ ct_status prepare_online(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc 
     std::vector<GemmProb> probs;
     probs.reserve(4 * n);
     int njobs = 0;
+    int64_t open_tiles = 0;
     for (int l = 0; l < n; l++) {
         const ct_layer_desc &d = L[l];
         if (d.N <= SKINNY_MAX_N) continue;
@@ -749,9 +750,24 @@ ct_status prepare_online(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc 
         J[njobs++] = make_job(o.E, wp(w.Ep), d.M, d.K, 0);
         J[njobs++] = make_job(wp(w.AE0), wp(w.AE0p), d.M, d.K, 0);
         J[njobs++] = make_job(o.A[1], wp(w.A1p), d.M, d.K, 0);
-        J[njobs++] = make_job(o.B[0], wp(w.B0p), d.K, d.N, 1, &o.cv);
-        J[njobs++] = make_job(o.B[1], wp(w.B1p), d.K, d.N, 1, &o.cv);
-        J[njobs++] = make_job(o.U, wp(w.Up), d.K, d.N, 1, &o.cv);
+        if (!o.cv.on) {
+            // k_open_pack opens U and writes the right operands' digit tiles
+            const PackJob rj[3] = {make_job(o.B[0], wp(w.B0p), d.K, d.N, 1), make_job(o.B[1], wp(w.B1p), d.K, d.N, 1),
+                                   make_job(o.U, wp(w.Up), d.K, d.N, 1)};
+            for (const PackJob &j : rj)
+                if (!job_in_work(j, W, d, c->eb))
+                    return fail(c, CT_EINVAL, "internal error: workspace layout exceeds CT_WORK_LEN");
+            LayerDev &lh = ln.layers_host[l];
+            lh.fo = 1;
+            lh.rp[0] = wp(w.B0p);
+            lh.rp[1] = wp(w.B1p);
+            lh.rp[2] = wp(w.Up);
+            open_tiles = std::max<int64_t>(open_tiles, rj[0].tiles);
+        } else {
+            J[njobs++] = make_job(o.B[0], wp(w.B0p), d.K, d.N, 1, &o.cv);
+            J[njobs++] = make_job(o.B[1], wp(w.B1p), d.K, d.N, 1, &o.cv);
+            J[njobs++] = make_job(o.U, wp(w.Up), d.K, d.N, 1, &o.cv);
+        }
         const size_t first = probs.size();
         probs.push_back(make_prob(wp(w.Ep), wp(w.AE0p), wp(w.B0p), wp(w.Up), o.C[0], o.Z[0], d));
         probs.push_back(make_prob(wp(w.Ep), wp(w.A1p), wp(w.B1p), wp(w.Up), o.C[1], o.Z[1], d));
@@ -775,6 +791,8 @@ ct_status prepare_online(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc 
     P.check = check;
     P.out_dev = out_dev;
     P.njobs = njobs;
+    P.open_tiles = (int)open_tiles;
+    for (int l = 0; l < n; l++) P.any_open_u |= !ln.layers_host[l].fo;
     P.pack_tiles = plan_jobs(ln.pack_host, njobs);
     P.tu = tuning_for(c, shape_class(mode, L, n));
     P.nm = plan_gemms(probs, c->num_cus, P.tu, &P.total_tiles, &P.any_accum);
@@ -809,14 +827,17 @@ ct_status enqueue_online(ct_ctx *c, Lane &ln, const OnlineLaunch &P) {
     const int n = P.n;
     if (P.zero_what)
         LAUNCH(c, ln, ST_ZERO_ACC, launch_zero_acc(c->eb, ln.layers_dev, n, P.zero_what, P.max_zero, ln.stream));
-    LAUNCH(c, ln, ST_OPEN_U, launch_open_u(c->eb, ln.layers_dev, n, P.flags, P.max_kn_items, ln.stream));
+    if (P.any_open_u)
+        LAUNCH(c, ln, ST_OPEN_U, launch_open_u(c->eb, ln.layers_dev, n, P.flags, P.max_kn_items, ln.stream));
+    if (P.open_tiles > 0)
+        LAUNCH(c, ln, ST_OPEN_PACK, launch_open_pack(c->eb, ln.layers_dev, n, P.flags, P.open_tiles, ln.stream));
     if (P.any_conv_n)
         LAUNCH(c, ln, ST_CONV_COMPRESS, launch_conv_compress(c->eb, ln.layers_dev, n, P.max_conv_items, ln.stream));
     LAUNCH(c, ln, ST_ROW_PASS, launch_row_pass(c->eb, ln.layers_dev, n, P.flags, P.max_row_items, P.variants, ln.stream));
     if (P.any_cm) LAUNCH(c, ln, ST_COL_TAG, launch_col_tag(c->eb, ln.layers_dev, n, P.max_col_tag, ln.stream));
     if (P.njobs > 0) LAUNCH(c, ln, ST_PACK, launch_pack(c->eb, ln.pack_dev, P.njobs, P.pack_tiles, ln.stream));
     if (P.any_accum)
-        LAUNCH(c, ln, ST_COPY_BASE, launch_copy_base(c->eb, ln.layers_dev, n, P.mode, P.max_mn, ln.stream));
+        LAUNCH(c, ln, ST_COPY_BASE, launch_prob_base(c->eb, ln.gemm_dev, P.nm, P.max_mn, ln.stream));
     ct_status s = run_gemms(c, ln, P.nm, P.total_tiles, P.tu);
     if (s != CT_OK) return s;
     LAUNCH(c, ln, ST_POST, launch_post(c->eb, ln.layers_dev, n, P.flags, P.max_mn_items, ln.stream));

@@ -28,7 +28,7 @@
 // while the matrix cores work on the other, and reads 16-byte digit fragments
 // in a triangular order (fragment pair t unlocks 2t+1 or 2(16-t) products) so
 // the first products issue after a single fragment pair.
-#include "ct_device.h"
+#include "ct_sweep.h"
 
 namespace ct {
 
@@ -158,6 +158,105 @@ hipError_t launch_pack(int eb, const PackJob *jobs_dev, int njobs, int total_til
     int grid = total_tiles < 65536 ? total_tiles : 65536;
     if (eb == 8) hipLaunchKernelGGL(k_pack<r64>, dim3(grid), dim3(256), 0, st, jobs_dev, njobs, total_tiles);
     else hipLaunchKernelGGL(k_pack<u128>, dim3(grid), dim3(256), 0, st, jobs_dev, njobs, total_tiles);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- open U and pack
+// Two-party matrix-core layers that are not convolutions: one pass over
+// K x N opens U = ([Y]_0 - [B]_0) + ([Y]_1 - [B]_1) (Fig. 7 online step 1),
+// accumulates its batch check sums (Pi_BatchRec, Fig. 1), forms U^c and
+// [tB^c]_p (compression along N, Pi_Compress) and writes the digit tiles of
+// the right operands [B]_0, [B]_1 and U of the products -- the work of
+// k_open_u and of k_pack's right-operand jobs, without reading [B]_p and U a
+// second time.  One workgroup per 64 (n) x 32 (k) tile, laid out as k_pack
+// lays out a right operand's tile: lane j takes column n = 64 tn + j,
+// wavefront w the 8 rows k = 32 ks + 8 w + i; the rows' compressions are
+// summed over the wavefront and added atomically, one per row and tile.
+template <class R>
+__device__ __forceinline__ void store_tile(uint8_t *tile, int off, const uint32_t (&w)[8][Tile<R>::NW], u128 *dst) {
+    constexpr int OPB = Tile<R>::OPB;
+    write_planes<Tile<R>::NW>(tile, off, w);
+    __syncthreads();
+    uint4 *d = reinterpret_cast<uint4 *>(dst);
+#pragma unroll
+    for (int i = 0; i < OPB / 16 / 256; i++) d[i * 256 + threadIdx.x] = reinterpret_cast<const uint4 *>(tile)[i * 256 + threadIdx.x];
+    __syncthreads();
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_open_pack(const LayerDev *__restrict__ Ls, int flags) {
+    constexpr int NW = Tile<R>::NW;
+    __shared__ __attribute__((aligned(16))) uint8_t tile[Tile<R>::OPB];
+    __shared__ R sh[3 * WAVES];
+    const LayerDev &L = Ls[blockIdx.y];
+    if (!L.fo) return;
+    const int64_t K = L.K, N = L.N;
+    const int kt = (int)((K + 31) / 32), tiles = (int)((N + 63) / 64) * kt;
+    if ((int)blockIdx.x >= tiles) return;
+    const int tn = blockIdx.x / kt, ks = blockIdx.x - tn * kt;
+    const int lane = threadIdx.x & 63, kk = (threadIdx.x >> 6) * 8;
+    const int64_t n = (int64_t)tn * 64 + lane;
+    const bool check = flags & F_CHECK, compact = (flags & F_COMPACT) && !L.cm;
+    const bool need_tb = check || compact;
+    const CvecOff o = cvec_off(L.M, K);
+    const uint64_t kcu = L.key[K_CHI_U];
+    const uint64_t xn = compact && n < N ? Ring<R>::mod_s(sdraw(L.key[K_CHI], (uint64_t)n)) : 0;
+    R chk[3] = {Ring<R>::zero(), Ring<R>::zero(), Ring<R>::zero()};
+    uint32_t wb0[8][NW], wb1[8][NW], wu[8][NW];
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        const int64_t k = (int64_t)ks * 32 + kk + i;
+        R b0 = Ring<R>::zero(), b1 = Ring<R>::zero(), u = Ring<R>::zero();
+        R tb0 = Ring<R>::zero(), tb1 = Ring<R>::zero();
+        if (k < K && n < N) {
+            const int64_t e = k * N + n;
+            // all loads of the element before the store of U
+            const R y0 = ld_nt(P<R>(L.Y[0]), e), y1 = ld_nt(P<R>(L.Y[1]), e);
+            b0 = ld_nt(P<R>(L.B[0]), e);
+            b1 = ld_nt(P<R>(L.B[1]), e);
+            R ty0 = Ring<R>::zero(), ty1 = Ring<R>::zero();
+            if (need_tb) {
+                tb0 = ld_nt(P<R>(L.tB[0]), e);
+                tb1 = ld_nt(P<R>(L.tB[1]), e);
+            }
+            if (check) {
+                ty0 = ld_nt(P<R>(L.tY[0]), e);
+                ty1 = ld_nt(P<R>(L.tY[1]), e);
+            }
+            u = add(sub(y0, b0), sub(y1, b1));
+            // U is read again only by the column tags of a layer compressed along M
+            if (L.cm) st(P<R>(L.U), e, u);
+            else st_nt(P<R>(L.U), e, u);
+            if (check) {
+                const uint64_t x = Ring<R>::mod_s(sdraw(kcu, (uint64_t)e));
+                chk[0] = mad64(chk[0], sub(ty0, tb0), x);
+                chk[1] = mad64(chk[1], sub(ty1, tb1), x);
+                chk[2] = mad64(chk[2], u, x);
+            }
+        }
+        if (compact && k < K) {  // k is the same for the whole wavefront
+            const R v0 = wave_sum(mul64(u, xn)), v1 = wave_sum(mul64(tb0, xn)), v2 = wave_sum(mul64(tb1, xn));
+            if (lane == 0) {
+                atomic_add128(P<R>(L.cvec) + o.Uc + k, v0);
+                atomic_add128(P<R>(L.cvec) + o.tBc0 + k, v1);
+                atomic_add128(P<R>(L.cvec) + o.tBc1 + k, v2);
+            }
+        }
+        to_digits(b0, wb0[i]);
+        to_digits(b1, wb1[i]);
+        to_digits(u, wu[i]);
+    }
+    const int64_t toff = ((int64_t)tn * kt + ks) * TILE_ELEMS;
+    const int off = plane_off(lane, kk);
+    store_tile<R>(tile, off, wb0, reinterpret_cast<u128 *>(P<R>(L.rp[0]) + toff));
+    store_tile<R>(tile, off, wb1, reinterpret_cast<u128 *>(P<R>(L.rp[1]) + toff));
+    store_tile<R>(tile, off, wu, reinterpret_cast<u128 *>(P<R>(L.rp[2]) + toff));
+    if (check) block_accumulate<3>(chk, sh, P<R>(L.acc) + 3);
+}
+
+hipError_t launch_open_pack(int eb, const LayerDev *L, int n, int flags, int max_tiles, hipStream_t st) {
+    if (n <= 0 || max_tiles <= 0) return hipSuccess;
+    LAUNCH_RING(eb, k_open_pack, dim3(max_tiles, n), dim3(256), st, L, flags);
     return hipGetLastError();
 }
 

@@ -44,7 +44,7 @@ void lane_free(Lane &ln);
 enum Stage : int {
     ST_DEAL_LIFT, ST_FILL_ZERO, ST_DEAL_AUTH, ST_DEAL_SKINNY, ST_ZERO_ACC, ST_OPEN_U, ST_ROW_PASS, ST_PACK,
     ST_COPY_BASE, ST_RING_GEMM, ST_POST, ST_COMPACT_FINAL, ST_CHECK_BATCH, ST_CHECK_COMPACT, ST_FINALIZE,
-    ST_COL_TAG, ST_CONV_COMPRESS, ST_NP_OPEN, ST_NP_SKINNY, ST_NP_COMPRESS, ST_NP_GEMV, ST_COUNT
+    ST_COL_TAG, ST_CONV_COMPRESS, ST_NP_OPEN, ST_NP_SKINNY, ST_NP_COMPRESS, ST_NP_GEMV, ST_OPEN_PACK, ST_COUNT
 };
 
 struct ct_ctx {
@@ -84,6 +84,8 @@ ct_status run_check(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc *L, c
 // tables (outside a capture), enqueue only launches kernels.
 struct OnlineLaunch {
     int n = 0, nm = 0, njobs = 0, pack_tiles = 0, total_tiles = 0, variants = 0, flags = 0, zero_what = 0;
+    int open_tiles = 0;       // k_open_pack tiles of the largest fused layer
+    bool any_open_u = false;  // a layer that k_open_u opens (not fused)
     bool any_accum = false, compact = false, check = false, any_cm = false, any_conv_n = false;
     ct_mode mode = CT_MODE_COMPACT;
     GemmTuning tu;

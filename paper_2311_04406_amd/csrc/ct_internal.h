@@ -87,6 +87,11 @@ struct LayerDev {
     // share streams of parties 1 .. np - 2 (party 0 uses key[K_VSH_X + obj - 1] and
     // key[K_TSH_X + obj - 1]; the last party completes the sums)
     uint64_t vsh[MAXP - 2][NUM_OBJ], tsh[MAXP - 2][NUM_OBJ];
+    // two-party matrix-core layers that are not convolutions: U is opened by
+    // k_open_pack, which also writes the digit tiles of [B]_0, [B]_1 and U
+    // (rp[0..2], in the workspace); k_open_u skips them
+    int32_t fo, pad_fo;
+    u128 *rp[3];
 };
 
 // cvec offsets of n parties, compressing along N (see compacttag.h): U^c,
@@ -298,8 +303,8 @@ hipError_t launch_fill_zero(int eb, u128 *p, int64_t n, hipStream_t st);
 hipError_t launch_deal_lift(int eb, const LayerDev *L, int n, int64_t max_elems, hipStream_t st);
 hipError_t launch_deal_auth(int eb, const LayerDev *L, int n, int obj, int64_t max_elems, hipStream_t st);
 hipError_t launch_zero_acc(int eb, const LayerDev *L, int n, int what, int64_t max_elems, hipStream_t st);
-hipError_t launch_copy_base(int eb, const LayerDev *L, int n, int mode, int64_t max_elems, hipStream_t st);
 hipError_t launch_open_u(int eb, const LayerDev *L, int n, int flags, int64_t max_items, hipStream_t st);
+hipError_t launch_open_pack(int eb, const LayerDev *L, int n, int flags, int max_tiles, hipStream_t st);
 // variants: bit v (bit VARIANT_CM + v) set if some layer takes row-pass variant v (0, 1, 2, 4, 8)
 // (of the pass of layers compressed along M)
 hipError_t launch_row_pass(int eb, const LayerDev *L, int n, int flags, int64_t max_items, int variants, hipStream_t st);

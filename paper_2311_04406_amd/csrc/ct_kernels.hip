@@ -22,7 +22,9 @@
 // Layers compressed along M take k_row_pass_cm (column sums of E and [tA]_p),
 // a column sweep in k_post and k_col_tag (the compact-tag products over
 // K x N).  Convolution layers open U on their input's elements in k_open_u
-// and compress their implicit im2col matrices in k_conv_compress.
+// and compress their implicit im2col matrices in k_conv_compress.  Two-party
+// matrix-core layers that are not convolutions open U in k_open_pack
+// (ct_gemm.hip), which also writes their right operands' digit tiles.
 //
 // Every kernel serves all layers of a call: grid dimension y indexes layers
 // (and sub-objects), dimension x strides over that layer's work.  Cross-
@@ -147,25 +149,22 @@ hipError_t launch_zero_acc(int eb, const LayerDev *L, int n, int what, int64_t m
     return hipGetLastError();
 }
 
-// Output arrays that receive split-K partial products start from their
-// constant term: [Z]_p = [C]_p, and in SPDZ2k mode [tZ]_p = [tC]_p.  Layers
-// whose products are formed in the row pass (N <= SKINNY_MAX_N) are skipped.
+// Products whose K range is split add their partial results atomically onto
+// the output, which first receives the product's constant term: [Z]_p = [C]_p
+// (SPDZ2k also [tZ]_p = [tC]_p).  Only the split products are copied; the
+// others add the constant term in the product's epilogue.
 template <class R>
-__global__ void k_copy_base(const LayerDev *__restrict__ Ls, int spdz) {
-    const LayerDev &L = Ls[blockIdx.y >> 2];
-    const int which = blockIdx.y & 3;  // 0,1: Z_p ; 2,3: tZ_p
-    if ((which >= 2 && !spdz) || L.N <= SKINNY_MAX_N) return;
-    const int p = which & 1;
-    const R *src = which >= 2 ? P<R>(L.tC[p]) : P<R>(L.C[p]);
-    R *dst = which >= 2 ? P<R>(L.tZ[p]) : P<R>(L.Z[p]);
-    const int64_t n = L.M * L.N;
+__global__ void k_prob_base(const GemmProb *__restrict__ probs) {
+    const GemmProb &p = probs[blockIdx.y];
+    if (!p.accumulate || !p.base) return;
+    const int64_t n = (int64_t)p.M * p.N;
     for (int64_t e = blockIdx.x * (int64_t)TPB + threadIdx.x; e < n; e += (int64_t)gridDim.x * TPB)
-        st(dst, e, ld(src, e));
+        st(P<R>(p.out), e, ld(reinterpret_cast<const R *>(p.base), e));
 }
 
-hipError_t launch_copy_base(int eb, const LayerDev *L, int n, int mode, int64_t max_elems, hipStream_t st) {
-    LAUNCH_RING(eb, k_copy_base, dim3(grid_for(max_elems), 4 * n), dim3(TPB), st, L,
-                       mode == CT_MODE_SPDZ2K ? 1 : 0);
+hipError_t launch_prob_base(int eb, const GemmProb *probs, int nprobs, int64_t max_mn, hipStream_t st) {
+    if (nprobs <= 0) return hipSuccess;
+    LAUNCH_RING(eb, k_prob_base, dim3(grid_for(max_mn), nprobs), dim3(TPB), st, probs);
     return hipGetLastError();
 }
 
@@ -178,6 +177,7 @@ template <class R>
 __global__ __launch_bounds__(TPB) void k_open_u(const LayerDev *__restrict__ Ls, int flags) {
     __shared__ R sh[3 * WAVES];
     const LayerDev &L = Ls[blockIdx.y];
+    if (L.fo) return;  // opened by k_open_pack
     const int64_t K = L.K, N = L.N;
     // a layer compressed along M has no K-long compressions of U and [tB]_p
     const bool check = flags & F_CHECK, compact = (flags & F_COMPACT) && !L.cm;

@@ -373,22 +373,6 @@ hipError_t launch_np_row_pass(int eb, int np, const LayerDev *L, int n, int flag
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- products
-// Split-K products add into out, which starts from base.
-template <class R>
-__global__ void k_prob_base(const GemmProb *__restrict__ probs) {
-    const GemmProb &p = probs[blockIdx.y];
-    if (!p.accumulate || !p.base) return;
-    const int64_t n = (int64_t)p.M * p.N;
-    for (int64_t e = blockIdx.x * (int64_t)TPB + threadIdx.x; e < n; e += (int64_t)gridDim.x * TPB)
-        st(P<R>(p.out), e, ld(reinterpret_cast<const R *>(p.base), e));
-}
-
-hipError_t launch_prob_base(int eb, const GemmProb *probs, int nprobs, int64_t max_mn, hipStream_t st) {
-    LAUNCH_RING(eb, k_prob_base, dim3(grid_for(max_mn), nprobs), dim3(TPB), st, probs);
-    return hipGetLastError();
-}
-
 // Layers with N <= SKINNY_MAX_N: one wavefront per (row m, party p) forms
 //   [Z]_p = [C]_p + E [B]_p + L_p U,  L_0 = A_0 + E, L_p = [A]_p   (Eq. (2)),
 // and in SPDZ2k mode [tZ]_p = [tC]_p + E [tB]_p + ([tA]_p + [Delta]_p E) U (Eq. (3)).
