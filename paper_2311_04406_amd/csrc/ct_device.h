@@ -61,6 +61,23 @@ __device__ __forceinline__ void st_nt(u128 *p, int64_t i, u128 v) {
     __builtin_nontemporal_store(ct_u64x2{v.lo, v.hi}, reinterpret_cast<ct_u64x2 *>(p) + i);
 }
 
+// Exact accumulation of many values into four 64-bit cells with atomics
+// whose results are not waited for: cell j receives the j-th 32-bit limb of
+// each value, so no cell can wrap before 2^32 additions, and from_limbs
+// recombines sum_j cell_j 2^{32 j} mod 2^128.  (atomic_add128 below needs the
+// returned old low limb to carry, which makes the adding thread wait.)
+__device__ __forceinline__ void atomic_add_limbs(unsigned long long *cell, u128 v) {
+    const unsigned long long l[4] = {v.lo & 0xffffffffull, v.lo >> 32, v.hi & 0xffffffffull, v.hi >> 32};
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+        if (l[j]) atomicAdd(cell + j, l[j]);
+}
+__device__ __forceinline__ void from_limbs(const unsigned long long *cell, u128 &v) {
+    const unsigned long long l0 = cell[0], l1 = cell[1], l2 = cell[2], l3 = cell[3];
+    const unsigned long long lo = l0 + (l1 << 32);
+    v = u128{lo, (l1 >> 32) + l2 + (l3 << 32) + (lo < l0 ? 1ull : 0ull)};
+}
+
 // Exact accumulation into a Z_{2^128} cell from many threads: the low limb is
 // added atomically, and its wrap-around (old + v.lo >= 2^64) is carried into
 // the high limb by a second atomic add.  Every wrap of the low word is counted
@@ -118,6 +135,12 @@ __device__ __forceinline__ r64 ld(const r64 *p, int64_t i) { return p[i]; }
 __device__ __forceinline__ r64 ld_nt(const r64 *p, int64_t i) { return r64{__builtin_nontemporal_load(&p[i].v)}; }
 __device__ __forceinline__ void st(r64 *p, int64_t i, r64 v) { p[i] = v; }
 __device__ __forceinline__ void st_nt(r64 *p, int64_t i, r64 v) { __builtin_nontemporal_store(v.v, &p[i].v); }
+__device__ __forceinline__ void atomic_add_limbs(unsigned long long *cell, r64 v) {
+    const unsigned long long l0 = v.v & 0xffffffffull, l1 = v.v >> 32;
+    if (l0) atomicAdd(cell, l0);
+    if (l1) atomicAdd(cell + 1, l1);
+}
+__device__ __forceinline__ void from_limbs(const unsigned long long *cell, r64 &v) { v = r64{cell[0] + (cell[1] << 32)}; }
 __device__ __forceinline__ void atomic_add128(r64 *p, r64 v) {
     atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v.v);
 }

@@ -141,7 +141,18 @@ enum PassFlags : int {
 // [sum chi*tW_0, sum chi*tW_1, sum chi*W].  n parties: at W (CT_MAX_PARTIES + 1):
 // [sum chi*tW_p for p < n ..., sum chi*W at slot CT_MAX_PARTIES].
 constexpr int ACC_W = CT_MAX_PARTIES + 1;
-constexpr int ACC_PER_LAYER = 3 * ACC_W;
+// The row passes add their check sums of E into copies of their
+// accumulators held as 32-bit limbs in 64-bit cells (atomic_add_limbs), from
+// element ACC_RP of the layer's accumulators on: workgroup b adds into copy
+// b % RP_COPIES (two parties: 3 sums, 12 cells a copy) or b % NP_RP_COPIES
+// (n parties: ACC_W sums, 4 ACC_W cells), so that concurrent workgroups add
+// to different cells without waiting; k_finalize / k_np_finalize add the
+// copies to the E sums.
+constexpr int ACC_RP = 3 * ACC_W;
+constexpr int RP_CELLS = 1536;  // 64-bit cells (768 elements of 16 bytes)
+constexpr int RP_COPIES = RP_CELLS / 12;
+constexpr int NP_RP_COPIES = RP_CELLS / (4 * ACC_W);
+constexpr int ACC_PER_LAYER = 3 * ACC_W + RP_CELLS / 2;
 
 // cvec offsets (elements), see compacttag.h.  Compressing along M the same
 // offsets are taken with M replaced by N (cvec_off(N, K)), and the three

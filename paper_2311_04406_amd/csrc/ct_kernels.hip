@@ -130,7 +130,8 @@ __global__ void k_zero_acc(const LayerDev *__restrict__ Ls, int what) {
         const int64_t n = 3 * L.K + 10 * cvec_rows(L);
         for (int64_t e = t0; e < n; e += stride) st(P<R>(L.cvec), e, Ring<R>::zero());
     }
-    if ((what & 2) && blockIdx.x == 0 && threadIdx.x < ACC_PER_LAYER) st(P<R>(L.acc), threadIdx.x, Ring<R>::zero());
+    if ((what & 2) && blockIdx.x == 0)  // ACC_PER_LAYER 16-byte elements whatever the ring
+        for (int i = threadIdx.x; i < ACC_PER_LAYER; i += TPB) st(L.acc, i, u128{0, 0});
     if ((what & 4) && L.N <= SKINNY_MAX_N) {
         const int64_t n = L.M * L.N;
         for (int64_t e = t0; e < n; e += stride) {
@@ -517,22 +518,22 @@ __device__ __forceinline__ void row_pass_body(const LayerDev &L, int flags, R (&
 // other layer k_row_pass; each returns at once for the layers of the other.
 template <class R, int NS>
 __global__ __launch_bounds__(TPB) void k_row_pass(const LayerDev *__restrict__ Ls, int flags) {
-    __shared__ R sh[3 * WAVES];
     const LayerDev &L = Ls[blockIdx.y];
     if (row_variant(L.N) != NS || ((flags & F_COMPACT) && L.cm)) return;
     R chk[3] = {Ring<R>::zero(), Ring<R>::zero(), Ring<R>::zero()};
     row_pass_body<R, NS>(L, flags, chk);
-    if (flags & F_CHECK) block_accumulate<3>(chk, sh, P<R>(L.acc) + 0);
+    if (flags & F_CHECK)
+        wave_accumulate_limbs<3>(chk, rp_cells<R>(L) + 12 * (((blockIdx.x * TPB + threadIdx.x) >> 6) % RP_COPIES));
 }
 
 template <class R, int NS>
 __global__ __launch_bounds__(TPB) void k_row_pass_cm(const LayerDev *__restrict__ Ls, int flags) {
-    __shared__ R sh[3 * WAVES];
     const LayerDev &L = Ls[blockIdx.y];
     if (row_variant(L.N) != NS || !L.cm) return;
     R chk[3] = {Ring<R>::zero(), Ring<R>::zero(), Ring<R>::zero()};
     row_pass_cm<R, NS>(L, flags, chk);
-    if (flags & F_CHECK) block_accumulate<3>(chk, sh, P<R>(L.acc) + 0);
+    if (flags & F_CHECK)
+        wave_accumulate_limbs<3>(chk, rp_cells<R>(L) + 12 * (((blockIdx.x * TPB + threadIdx.x) >> 6) % RP_COPIES));
 }
 
 template <class R>
@@ -551,11 +552,10 @@ void launch_row_variants(const dim3 &g, const LayerDev *L, int flags, int varian
 }
 
 hipError_t launch_row_pass(int eb, const LayerDev *L, int n, int flags, int64_t max_items, int variants, hipStream_t st) {
-    // at most 2048 workgroups (8 per compute unit), each sweeping many items:
-    // every workgroup adds its check sums with one atomic per accumulator, and
-    // same-address atomics serialize (1024 leaves the memory system underfed)
+    // at most 8192 workgroups, each sweeping many items: every workgroup adds
+    // its check sums into one of RP_COPIES copies without waiting
     const int gx = grid_items(max_items);
-    const dim3 g(gx > 2048 ? 2048 : gx, n);
+    const dim3 g(gx > 8192 ? 8192 : gx, n);
     if (eb == 8) launch_row_variants<r64>(g, L, flags, variants, st);
     else launch_row_variants<u128>(g, L, flags, variants, st);
     return hipGetLastError();
@@ -789,19 +789,35 @@ hipError_t launch_check_compact(int eb, const LayerDev *L, int n, hipStream_t st
 
 // cs[W][p] = acc[3W + p] - [Delta]_p acc[3W + 2]; accept iff every cs sum is 0.
 template <class R>
-__global__ void k_finalize(const LayerDev *__restrict__ Ls, int n, ct_check_result *out) {
-    const int l = blockIdx.x * TPB + threadIdx.x;
+__global__ __launch_bounds__(64) void k_finalize(const LayerDev *__restrict__ Ls, int n, ct_check_result *out) {
+    const int l = blockIdx.x, lane = threadIdx.x;
     if (l >= n) return;
     const LayerDev &L = Ls[l];
+    // the row pass's copies of the E sums, over the wavefront (zero where
+    // another kernel accumulated them)
+    const unsigned long long *cells = rp_cells<R>(L);
+    R e[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        e[i] = Ring<R>::zero();
+        for (int s = lane; s < RP_COPIES; s += 64) {
+            R v;
+            from_limbs(cells + 12 * s + 4 * i, v);
+            e[i] = add(e[i], v);
+        }
+        e[i] = wave_sum(e[i]);
+    }
+    if (lane != 0) return;
+    for (int i = 0; i < 3; i++) e[i] = add(e[i], ld(P<R>(L.acc), i));
     int ok = 1;
     ct_check_result r;
     for (int w = 0; w < 3; w++)
         for (int p = 0; p < CT_MAX_PARTIES; p++) r.cs[w][p] = ct_u128{0, 0};
     for (int w = 0; w < 3; w++) {
-        const R aw = ld(P<R>(L.acc), 3 * w + 2);
+        const R aw = w == 0 ? e[2] : ld(P<R>(L.acc), 3 * w + 2);
         R c[2];
         for (int p = 0; p < 2; p++) {
-            c[p] = sub(ld(P<R>(L.acc), 3 * w + p), mul64(aw, L.delta[p]));
+            c[p] = sub(w == 0 ? e[p] : ld(P<R>(L.acc), 3 * w + p), mul64(aw, L.delta[p]));
             r.cs[w][p] = Ring<R>::out(c[p]);
         }
         if (Ring<R>::nonzero(add(c[0], c[1]))) ok = 0;
@@ -812,7 +828,7 @@ __global__ void k_finalize(const LayerDev *__restrict__ Ls, int n, ct_check_resu
 }
 
 hipError_t launch_finalize(int eb, const LayerDev *L, int n, ct_check_result *out, hipStream_t st) {
-    LAUNCH_RING(eb, k_finalize, dim3((n + TPB - 1) / TPB), dim3(TPB), st, L, n, out);
+    LAUNCH_RING(eb, k_finalize, dim3(n), dim3(64), st, L, n, out);
     return hipGetLastError();
 }
 

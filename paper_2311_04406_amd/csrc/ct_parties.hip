@@ -114,7 +114,8 @@ __global__ void k_np_zero(const LayerDev *__restrict__ Ls, int what) {
         const int64_t n = (1 + L.np) * L.K + (2 + 4 * L.np) * L.M;
         for (int64_t e = t0; e < n; e += stride) st(P<R>(L.cvec), e, Ring<R>::zero());
     }
-    if ((what & 2) && blockIdx.x == 0 && threadIdx.x < ACC_PER_LAYER) st(P<R>(L.acc), threadIdx.x, Ring<R>::zero());
+    if ((what & 2) && blockIdx.x == 0)  // ACC_PER_LAYER 16-byte elements whatever the ring
+        for (int i = threadIdx.x; i < ACC_PER_LAYER; i += TPB) st(L.acc, i, u128{0, 0});
     if ((what & 4) && L.N <= 2) {
         const int64_t n = L.M * L.N;
         for (int64_t e = t0; e < n; e += stride)
@@ -226,7 +227,6 @@ hipError_t launch_np_open(int eb, const LayerDev *L, int n, int which, int flags
 // accumulators take registers.
 template <class R, int NS, int NP>
 __global__ __launch_bounds__(TPB) void k_np_row_pass(const LayerDev *__restrict__ Ls, int flags) {
-    __shared__ R sh[ACC_W * WAVES];
     const LayerDev &L = Ls[blockIdx.y];
     if (!np_fused_row(L.N) || row_variant(L.N) != NS || L.np != NP) return;
     constexpr int NZ = NS > 0 ? NS : 1;
@@ -344,7 +344,8 @@ __global__ __launch_bounds__(TPB) void k_np_row_pass(const LayerDev *__restrict_
             }
         }
     }
-    if (check) block_accumulate<ACC_W>(chk, sh, P<R>(L.acc) + 0 * ACC_W);
+    if (check)
+        wave_accumulate_limbs<ACC_W>(chk, rp_cells<R>(L) + 4 * ACC_W * (((blockIdx.x * TPB + threadIdx.x) >> 6) % NP_RP_COPIES));
 }
 
 template <class R, int NP>
@@ -365,9 +366,9 @@ void launch_np_row_parties(int np, const dim3 &g, const LayerDev *L, int flags, 
 
 hipError_t launch_np_row_pass(int eb, int np, const LayerDev *L, int n, int flags, int64_t max_items, int variants,
                               hipStream_t st) {
-    // at most 2048 workgroups: each adds its check sums with one atomic per
-    // accumulator, and same-address atomics serialize
-    const dim3 g(std::min(grid_items(max_items), 2048), n);
+    // at most 8192 workgroups: each adds its check sums into one of
+    // NP_RP_COPIES copies without waiting
+    const dim3 g(std::min(grid_items(max_items), 8192), n);
     if (eb == 8) launch_np_row_parties<r64>(np, g, L, flags, variants, st);
     else launch_np_row_parties<u128>(np, g, L, flags, variants, st);
     return hipGetLastError();
@@ -674,20 +675,38 @@ hipError_t launch_np_check_compact(int eb, const LayerDev *L, int n, hipStream_t
 // cs[W][p] = acc[W ACC_W + p] - [Delta]_p acc[W ACC_W + MAXP]; accept iff
 // sum_p cs[W][p] = 0 for every W.
 template <class R>
-__global__ void k_np_finalize(const LayerDev *__restrict__ Ls, int n, ct_check_result *out) {
-    const int l = blockIdx.x * TPB + threadIdx.x;
+__global__ __launch_bounds__(64) void k_np_finalize(const LayerDev *__restrict__ Ls, int n, ct_check_result *out) {
+    const int l = blockIdx.x, lane = threadIdx.x;
     if (l >= n) return;
     const LayerDev &L = Ls[l];
+    // the fused row pass's copies of the E sums, over the wavefront
+    const unsigned long long *cells = rp_cells<R>(L);
+    R e[ACC_W];
+#pragma unroll
+    for (int i = 0; i < ACC_W; i++) {
+        e[i] = Ring<R>::zero();
+        for (int s = lane; s < NP_RP_COPIES; s += 64) {
+            R v;
+            from_limbs(cells + 4 * ACC_W * s + 4 * i, v);
+            e[i] = add(e[i], v);
+        }
+        e[i] = wave_sum(e[i]);
+    }
+    if (lane != 0) return;
+    auto acc = [&](int w, int i) {
+        const R v = ld(P<R>(L.acc), w * ACC_W + i);
+        return w == 0 ? add(v, e[i]) : v;
+    };
     ct_check_result r;
     for (int w = 0; w < 3; w++)
         for (int p = 0; p < CT_MAX_PARTIES; p++) r.cs[w][p] = ct_u128{0, 0};
     int ok = 1;
     for (int w = 0; w < 3; w++) {
-        const R aw = ld(P<R>(L.acc), w * ACC_W + MAXP);
+        const R aw = acc(w, MAXP);
         R sum = Ring<R>::zero();
 #pragma unroll
         for (int p = 0; p < MAXP; p++) if (p < L.np) {
-            const R c = sub(ld(P<R>(L.acc), w * ACC_W + p), mul64(aw, L.delta[p]));
+            const R c = sub(acc(w, p), mul64(aw, L.delta[p]));
             r.cs[w][p] = Ring<R>::out(c);
             sum = add(sum, c);
         }
@@ -699,7 +718,7 @@ __global__ void k_np_finalize(const LayerDev *__restrict__ Ls, int n, ct_check_r
 }
 
 hipError_t launch_np_finalize(int eb, const LayerDev *L, int n, ct_check_result *out, hipStream_t st) {
-    LAUNCH_RING(eb, k_np_finalize, dim3((n + TPB - 1) / TPB), dim3(TPB), st, L, n, out);
+    LAUNCH_RING(eb, k_np_finalize, dim3(n), dim3(64), st, L, n, out);
     return hipGetLastError();
 }
 

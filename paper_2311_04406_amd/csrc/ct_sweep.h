@@ -65,6 +65,36 @@ inline int grid_items(int64_t items) {  // one wavefront per item
     return (int)g;
 }
 
+// The limb cells of a layer's row-pass copies (after its ACC_RP accumulators
+// of the ring's element size).
+template <class R>
+__device__ __forceinline__ unsigned long long *rp_cells(const LayerDev &L) {
+    return reinterpret_cast<unsigned long long *>(P<R>(L.acc) + ACC_RP);
+}
+
+// Adds each wavefront's NV sums (wave-reduced) into copy `copy` of the 4 NV
+// limb cells at `cells`, without a workgroup barrier or waiting for the
+// atomics: a wavefront that finishes early leaves at once.
+template <int NV, class R>
+__device__ __forceinline__ void wave_accumulate_limbs(R (&v)[NV], unsigned long long *cells) {
+#pragma unroll
+    for (int i = 0; i < NV; i++) {
+        const R s = wave_sum(v[i]);
+        if ((threadIdx.x & 63) == 0) atomic_add_limbs(cells + 4 * i, s);
+    }
+}
+
+// Adds each workgroup's NV sums (block-reduced) into the 4 NV limb cells of
+// `cells` (atomic_add_limbs), without waiting for the atomics.
+template <int NV, class R>
+__device__ __forceinline__ void block_accumulate_limbs(R (&v)[NV], R *sh, unsigned long long *cells) {
+    block_sum<NV, WAVES>(v, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; i++) atomic_add_limbs(cells + 4 * i, v[i]);
+    }
+}
+
 // Adds each workgroup's NV sums (block-reduced) atomically into dst[0..NV).
 template <int NV, class R>
 __device__ __forceinline__ void block_accumulate(R (&v)[NV], R *sh, R *dst) {
