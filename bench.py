@@ -4,7 +4,11 @@
 A step is one pass of the whole hot path over one batch of layers: the online
 phase (open E and U, output-share products, tags) with the verification
 fused in (batch tag checks of E and U, check of D), for every layer of the
-workload, launched as one captured HIP graph (ct_plan_launch).  The dealer
+workload, launched as one captured HIP graph (ct_plan_launch; a batch that
+mixes matrix-core layers with row-pass-only layers runs the two groups on two
+streams forked and joined inside the graph).  The per-kernel breakdown comes
+from a second, untimed pass with per-launch timing, which runs every stage
+once over the whole batch on one stream.  The dealer
 runs once before the timed region and is not timed.  Inputs are synthetic
 (uniform ring elements from the dealer's seeded generator) and resident in
 HBM.

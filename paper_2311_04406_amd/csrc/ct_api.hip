@@ -29,7 +29,8 @@ constexpr int EV_POOL = 2048;
 
 struct ct_plan {
     ct_ctx *ctx = nullptr;
-    Lane lane;
+    Lane lane, side;  // side: the matrix-core layers of a mixed batch (forked in the graph)
+    hipEvent_t fork = nullptr, join = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -262,9 +263,15 @@ Sizes max_sizes(const ct_layer_desc *L, int n) {
 }
 
 // Waits for the lane's previous upload, then stages the layer records.
-ct_status stage_layers(ct_ctx *c, Lane &ln, const ct_layer_desc *L, const ct_layer_bufs *B, int n) {
+// out_index: position of each layer's check record in the caller's result
+// array (null: the layer's own position).
+ct_status stage_layers(ct_ctx *c, Lane &ln, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
+                       const int *out_index = nullptr) {
     HIPCHK(c, hipEventSynchronize(ln.upload_done));
-    for (int l = 0; l < n; l++) fill_layer(c, ln.acc_dev, L[l], B[l], l, ln.layers_host[l]);
+    for (int l = 0; l < n; l++) {
+        fill_layer(c, ln.acc_dev, L[l], B[l], l, ln.layers_host[l]);
+        ln.layers_host[l].out_index = out_index ? out_index[l] : l;
+    }
     return CT_OK;
 }
 
@@ -499,7 +506,14 @@ ct_status ct_create(ct_ctx **out, const ct_params *p) {
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cus > 0)
             c->num_cus = cus;
-        e = lane_init(c->main, reinterpret_cast<hipStream_t>(p->hip_stream), p->max_layers > 0 ? p->max_layers : 256);
+        const int ml = p->max_layers > 0 ? p->max_layers : 256;
+        e = lane_init(c->main, reinterpret_cast<hipStream_t>(p->hip_stream), ml);
+        hipStream_t side = nullptr;
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = lane_init(c->side, side, ml);
+        else c->side.stream = side;
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join, hipEventDisableTiming);
     }
     if (e != hipSuccess) {
         std::fprintf(stderr, "ct_create: %s\n", hipGetErrorString(e));
@@ -514,9 +528,15 @@ ct_status ct_create(ct_ctx **out, const ct_params *p) {
 ct_status ct_destroy(ct_ctx *c) {
     if (!c) return CT_EINVAL;
     if (c->main.layers_dev) (void)hipStreamSynchronize(c->main.stream);
+    if (c->side.stream) (void)hipStreamSynchronize(c->side.stream);
     for (auto e : c->ev_start) (void)hipEventDestroy(e);
     for (auto e : c->ev_end) (void)hipEventDestroy(e);
+    if (c->fork) (void)hipEventDestroy(c->fork);
+    if (c->join) (void)hipEventDestroy(c->join);
     lane_free(c->main);
+    hipStream_t side = c->side.stream;
+    lane_free(c->side);
+    if (side) (void)hipStreamDestroy(side);
     delete c;
     return CT_OK;
 }
@@ -716,7 +736,7 @@ ct_status enqueue_online_np(ct_ctx *c, Lane &ln, const OnlineLaunch &P) {
 // The online phase, optionally with the verification fused into its passes
 // (out_dev != nullptr): validation, tables and their upload.
 ct_status prepare_online(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
-                         ct_check_result *out_dev, OnlineLaunch &P) {
+                         ct_check_result *out_dev, OnlineLaunch &P, const int *out_index) {
     if (!c) return CT_EINVAL;
     if (mode != CT_MODE_SPDZ2K && mode != CT_MODE_COMPACT) return fail(c, CT_EINVAL, "unknown mode");
     const bool compact = mode == CT_MODE_COMPACT;
@@ -726,7 +746,7 @@ ct_status prepare_online(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc 
     if (s != CT_OK) return s;
     if (check && !aligned16(out_dev)) return fail(c, CT_EINVAL, "out_dev is null or misaligned");
     HIPCHK(c, hipSetDevice(c->device));
-    if ((s = stage_layers(c, ln, L, B, n)) != CT_OK) return s;
+    if ((s = stage_layers(c, ln, L, B, n, out_index)) != CT_OK) return s;
     if (c->np > 2) return prepare_online_np(c, ln, mode, L, n, out_dev, P);
 
     // Matrix-core products (layers with N > SKINNY_MAX_N), both parties,
@@ -853,6 +873,40 @@ ct_status run_online(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc *L, 
     return s != CT_OK ? s : enqueue_online(c, ln, P);
 }
 
+ct_status prepare_online_split(ct_ctx *c, Lane &a, Lane &b, ct_mode mode, const ct_layer_desc *L,
+                               const ct_layer_bufs *B, int n, ct_check_result *out_dev, OnlineLaunch &Pa,
+                               OnlineLaunch &Pb, bool &split) {
+    split = false;
+    if (!c) return CT_EINVAL;
+    if (n <= 0 || !L || !B || !b.layers_dev) return prepare_online(c, a, mode, L, B, n, out_dev, Pa);
+    std::vector<int> ia, ib;
+    for (int l = 0; l < n; l++) (L[l].N > SKINNY_MAX_N ? ib : ia).push_back(l);
+    if (ia.empty() || ib.empty()) return prepare_online(c, a, mode, L, B, n, out_dev, Pa);
+    std::vector<ct_layer_desc> La, Lb;
+    std::vector<ct_layer_bufs> Ba, Bb;
+    for (int l : ia) { La.push_back(L[l]); Ba.push_back(B[l]); }
+    for (int l : ib) { Lb.push_back(L[l]); Bb.push_back(B[l]); }
+    ct_status s = prepare_online(c, b, mode, Lb.data(), Bb.data(), (int)ib.size(), out_dev, Pb, ib.data());
+    if (s == CT_OK) s = prepare_online(c, a, mode, La.data(), Ba.data(), (int)ia.size(), out_dev, Pa, ia.data());
+    split = s == CT_OK;
+    return s;
+}
+
+ct_status enqueue_online_split(ct_ctx *c, Lane &a, Lane &b, hipEvent_t fork, hipEvent_t join, const OnlineLaunch &Pa,
+                               const OnlineLaunch &Pb, bool split) {
+    if (!split) return enqueue_online(c, a, Pa);
+    // lane b starts after what the caller enqueued on lane a so far
+    HIPCHK(c, hipEventRecord(fork, a.stream));
+    HIPCHK(c, hipStreamWaitEvent(b.stream, fork, 0));
+    ct_status s = enqueue_online(c, b, Pb);
+    if (s == CT_OK) s = enqueue_online(c, a, Pa);
+    // and lane a's later work after lane b's (also on failure, so that the
+    // streams stay joined)
+    HIPCHK(c, hipEventRecord(join, b.stream));
+    HIPCHK(c, hipStreamWaitEvent(a.stream, join, 0));
+    return s;
+}
+
 ct_status run_check(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
                     ct_check_result *out_dev) {
     if (!c) return CT_EINVAL;
@@ -895,7 +949,13 @@ ct_status ct_tag_linear_check(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, c
                               ct_check_result *out_dev) {
     if (!c) return CT_EINVAL;
     if (!out_dev) return fail(c, CT_EINVAL, "null result array");
-    return run_online(c, c->main, mode, L, B, n, out_dev);
+    // with per-launch timing on, every stage runs once over the whole batch
+    // on the main lane, so that each stage's time covers all layers
+    if (c->timing) return run_online(c, c->main, mode, L, B, n, out_dev);
+    OnlineLaunch Pa, Pb;
+    bool split = false;
+    ct_status s = prepare_online_split(c, c->main, c->side, mode, L, B, n, out_dev, Pa, Pb, split);
+    return s != CT_OK ? s : enqueue_online_split(c, c->main, c->side, c->fork, c->join, Pa, Pb, split);
 }
 
 ct_status ct_mac_check_device(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
@@ -928,22 +988,30 @@ ct_status ct_plan_create(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const 
     HIPCHK(c, hipSetDevice(c->device));
     ct_plan *pl = new ct_plan();
     pl->ctx = c;
-    hipStream_t st = nullptr;
+    hipStream_t st = nullptr, side = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
     if (e == hipSuccess) e = lane_init(pl->lane, st, std::max(n, 1));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = lane_init(pl->side, side, std::max(n, 1));
+    else pl->side.stream = side;
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->join, hipEventDisableTiming);
     if (e != hipSuccess) {
         ct_plan_destroy(pl);
         return hip_fail(c, e, "ct_plan_create");
     }
-    OnlineLaunch P;
-    ct_status s = prepare_online(c, pl->lane, mode, L, B, n, out_dev, P);
+    OnlineLaunch Pa, Pb;
+    bool split = false;
+    ct_status s = prepare_online_split(c, pl->lane, pl->side, mode, L, B, n, out_dev, Pa, Pb, split);
     if (s == CT_OK) {
         // the tables are uploaded before the capture starts, so the graph
-        // holds kernel nodes only
+        // holds kernel nodes only; the side stream joins the capture through
+        // the fork event and is joined back before it ends
         e = hipStreamSynchronize(st);
+        if (e == hipSuccess) e = hipStreamSynchronize(side);
         if (e == hipSuccess) e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            s = enqueue_online(c, pl->lane, P);
+            s = enqueue_online_split(c, pl->lane, pl->side, pl->fork, pl->join, Pa, Pb, split);
             const hipError_t e2 = hipStreamEndCapture(st, &pl->graph);
             if (s == CT_OK && e2 != hipSuccess) e = e2;
         }
@@ -972,11 +1040,16 @@ ct_status ct_plan_destroy(ct_plan *pl) {
     if (pl->lane.stream) (void)hipStreamSynchronize(pl->lane.stream);
     // a replay may still be running on the context stream
     (void)hipStreamSynchronize(pl->ctx->main.stream);
+    if (pl->side.stream) (void)hipStreamSynchronize(pl->side.stream);
     if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
     if (pl->graph) (void)hipGraphDestroy(pl->graph);
-    hipStream_t st = pl->lane.stream;
+    if (pl->fork) (void)hipEventDestroy(pl->fork);
+    if (pl->join) (void)hipEventDestroy(pl->join);
+    hipStream_t st = pl->lane.stream, side = pl->side.stream;
     lane_free(pl->lane);
+    lane_free(pl->side);
     if (st) (void)hipStreamDestroy(st);
+    if (side) (void)hipStreamDestroy(side);
     delete pl;
     return CT_OK;
 }

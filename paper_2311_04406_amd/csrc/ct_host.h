@@ -54,6 +54,10 @@ struct ct_ctx {
     uint64_t delta[CT_MAX_PARTIES] = {};  // key shares [Delta]_p, p < np
     int num_cus = 256;
     ct::Lane main;
+    // second lane for the matrix-core layers of a mixed online call, and the
+    // events that fork it from and join it to the main stream
+    ct::Lane side;
+    hipEvent_t fork = nullptr, join = nullptr;
     std::string err;
     // per-launch timing: event pairs recorded around each kernel of the main lane
     bool timing = false;
@@ -97,8 +101,19 @@ struct OnlineLaunch {
     ct_check_result *out_dev = nullptr;
 };
 ct_status prepare_online(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
-                         ct_check_result *out_dev, OnlineLaunch &P);
+                         ct_check_result *out_dev, OnlineLaunch &P, const int *out_index = nullptr);
 ct_status enqueue_online(ct_ctx *c, Lane &ln, const OnlineLaunch &P);
+// The online phase of a batch that mixes matrix-core layers (N > 8) with
+// layers whose products the row pass forms: the matrix-core layers run on
+// lane b, forked from lane a's stream, and the others on lane a, joined back
+// before anything later on lane a's stream.  The two groups share no data, so
+// their kernels overlap (the row pass of a wide classifier is bandwidth-bound,
+// the products of convolutions are not).  A batch of one kind runs on lane a.
+ct_status prepare_online_split(ct_ctx *c, Lane &a, Lane &b, ct_mode mode, const ct_layer_desc *L,
+                               const ct_layer_bufs *B, int n, ct_check_result *out_dev, OnlineLaunch &Pa,
+                               OnlineLaunch &Pb, bool &split);
+ct_status enqueue_online_split(ct_ctx *c, Lane &a, Lane &b, hipEvent_t fork, hipEvent_t join, const OnlineLaunch &Pa,
+                               const OnlineLaunch &Pb, bool split);
 
 ct_status fail(ct_ctx *c, ct_status s, const std::string &msg);
 

@@ -90,7 +90,8 @@ struct LayerDev {
     // two-party matrix-core layers that are not convolutions: U is opened by
     // k_open_pack, which also writes the digit tiles of [B]_0, [B]_1 and U
     // (rp[0..2], in the workspace); k_open_u skips them
-    int32_t fo, pad_fo;
+    int32_t fo;
+    int32_t out_index;          // position of the layer's check record in the caller's result array
     u128 *rp[3];
 };
 

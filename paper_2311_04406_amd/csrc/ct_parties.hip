@@ -714,7 +714,7 @@ __global__ __launch_bounds__(64) void k_np_finalize(const LayerDev *__restrict__
     }
     r.accept = ok;
     r.reserved = 0;
-    out[l] = r;
+    out[L.out_index] = r;
 }
 
 hipError_t launch_np_finalize(int eb, const LayerDev *L, int n, ct_check_result *out, hipStream_t st) {
