@@ -879,6 +879,12 @@ ct_status prepare_online_split(ct_ctx *c, Lane &a, Lane &b, ct_mode mode, const 
     split = false;
     if (!c) return CT_EINVAL;
     if (n <= 0 || !L || !B || !b.layers_dev) return prepare_online(c, a, mode, L, B, n, out_dev, Pa);
+    // the whole batch first, so that an error names the caller's layer index
+    if (mode != CT_MODE_SPDZ2K && mode != CT_MODE_COMPACT) return fail(c, CT_EINVAL, "unknown mode");
+    ct_status v = validate(c, a.max_layers, L, B, n,
+                           NEED_INPUTS | NEED_TRIPLE | NEED_OUT | NEED_WORK |
+                               (mode == CT_MODE_COMPACT ? NEED_CVEC : 0));
+    if (v != CT_OK) return v;
     std::vector<int> ia, ib;
     for (int l = 0; l < n; l++) (L[l].N > SKINNY_MAX_N ? ib : ia).push_back(l);
     if (ia.empty() || ib.empty()) return prepare_online(c, a, mode, L, B, n, out_dev, Pa);
