@@ -380,10 +380,18 @@ GemmTuning tuning_for(const ct_ctx *c, uint64_t key) {
 // Plans the products: probs holds consecutive groups (the products of one
 // layer); gsize of each problem must be set.  Fills tiles, K splits and the
 // group tile ranges.
-int plan_gemms(std::vector<GemmProb> &probs, int num_cus, const GemmTuning &tu, int *total_tiles, bool *any_accum) {
+int plan_gemms(std::vector<GemmProb> &probs, int num_cus, const GemmTuning &tu, int *total_tiles, bool *any_accum,
+               int eb) {
+    // Z_{2^64}: two 32 x 32 output tiles per wavefront (128-row workgroup
+    // tiles, half the operand copies and barriers per product) when the
+    // launch still has two such tiles per compute unit before any K split
+    int64_t tiles128 = 0;
+    for (const auto &p : probs) tiles128 += (int64_t)((p.M + 127) / 128) * ((p.N + 63) / 64);
+    const int mt = eb == 8 && tiles128 >= 2LL * num_cus ? 2 : 1;
     int64_t total_steps = 0;
     for (auto &p : probs) {
-        p.tiles_m = (p.M + 63) / 64;
+        p.mt = mt;
+        p.tiles_m = (p.M + 64 * mt - 1) / (64 * mt);
         p.tiles_n = (p.N + 63) / 64;
         p.kt = (p.K + 31) / 32;
         p.nsteps = p.kt * (p.Lp2 ? 2 : 1);
@@ -425,7 +433,8 @@ int plan_gemms(std::vector<GemmProb> &probs, int num_cus, const GemmTuning &tu, 
 
 ct_status run_gemms(ct_ctx *c, Lane &ln, int nprobs, int total_tiles, const GemmTuning &tu) {
     if (nprobs > 0)
-        LAUNCH(c, ln, ST_RING_GEMM, launch_gemm(c->eb, ln.gemm_dev, nprobs, total_tiles, tu.xcd_remap, ln.stream));
+        LAUNCH(c, ln, ST_RING_GEMM, launch_gemm(c->eb, ln.gemm_dev, nprobs, total_tiles, tu.xcd_remap,
+                                                ln.gemm_host[0].mt, ln.stream));
     return CT_OK;
 }
 
@@ -586,7 +595,7 @@ ct_status ct::run_deal(ct_ctx *c, Lane &ln, const ct_layer_desc *L, const ct_lay
     int total_tiles = 0;
     bool any_accum = false;
     const GemmTuning tu = c->fallback;
-    const int nm = plan_gemms(probs, c->num_cus, tu, &total_tiles, &any_accum);
+    const int nm = plan_gemms(probs, c->num_cus, tu, &total_tiles, &any_accum, c->eb);
     std::copy(probs.begin(), probs.end(), ln.gemm_host);
     if ((s = upload(c, ln, n, nm, njobs, nskinny)) != CT_OK) return s;
     const Sizes sz = max_sizes(L, n);
@@ -673,7 +682,7 @@ ct_status prepare_online_np(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_de
     P.njobs = njobs;
     P.pack_tiles = plan_jobs(ln.pack_host, njobs);
     P.tu = tuning_for(c, shape_class(mode, L, n));
-    P.nm = plan_gemms(probs, c->num_cus, P.tu, &P.total_tiles, &P.any_accum);
+    P.nm = plan_gemms(probs, c->num_cus, P.tu, &P.total_tiles, &P.any_accum, c->eb);
     std::copy(probs.begin(), probs.end(), ln.gemm_host);
     ct_status s = upload(c, ln, n, P.nm, njobs);
     if (s != CT_OK) return s;
@@ -815,7 +824,7 @@ ct_status prepare_online(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc 
     for (int l = 0; l < n; l++) P.any_open_u |= !ln.layers_host[l].fo;
     P.pack_tiles = plan_jobs(ln.pack_host, njobs);
     P.tu = tuning_for(c, shape_class(mode, L, n));
-    P.nm = plan_gemms(probs, c->num_cus, P.tu, &P.total_tiles, &P.any_accum);
+    P.nm = plan_gemms(probs, c->num_cus, P.tu, &P.total_tiles, &P.any_accum, c->eb);
     std::copy(probs.begin(), probs.end(), ln.gemm_host);
     if ((s = upload(c, ln, n, P.nm, njobs)) != CT_OK) return s;
 

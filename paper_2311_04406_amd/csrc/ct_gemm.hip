@@ -39,15 +39,21 @@ constexpr int BM = 64, BN = 64, BK = 32;
 constexpr int PLANE = BM * BK;  // bytes per digit plane of a 64 x 32 tile
 
 // Tile geometry per ring: NB digit planes per operand tile (OPB bytes, which
-// is TILE_ELEMS elements), the A and B tiles of one K slice per LDS stage.
+// is TILE_ELEMS elements).  A wavefront holds NB diagonal accumulators of 16
+// registers per 32 x 32 output tile; with 8 digits (Z_{2^64}) that is half
+// its 256 AGPRs, so it can take MT = 2 output tiles stacked in M (a workgroup
+// then owns 64 MT x 64 outputs).  An LDS stage (Stage<R, MT>) holds the MT
+// left-operand digit tiles and the right-operand digit tile of one K slice.
 template <class R>
 struct Tile {
     static constexpr int NB = Ring<R>::DIGITS;
     static constexpr int NW = NB / 4;            // 32-bit words of digits per element
     static constexpr int OPB = NB * PLANE;       // 32 KB (Z_{2^128}) or 16 KB (Z_{2^64})
-    static constexpr int STAGE = 2 * OPB;
+    static constexpr int MT_MAX = NB == 8 ? 2 : 1;
     static_assert(OPB == TILE_ELEMS * (int)sizeof(R), "tile size");
 };
+template <class R, int MT>
+constexpr int stage_bytes() { return (MT + 1) * Tile<R>::OPB; }
 
 __device__ __forceinline__ void to_digits(r64 x, uint32_t (&w)[2]) {
     const uint64_t K = 0x8080808080808080ull;
@@ -300,99 +306,103 @@ __device__ __forceinline__ const uint8_t *uniform_ptr(const uint8_t *p) {
     return reinterpret_cast<const uint8_t *>(((uint64_t)hi << 32) | lo);
 }
 
-// Copies the A and B digit tiles of one K slice into an LDS stage: chunks of
-// 1 KB, OPB / 2 KB per wavefront, each a single global_load_lds_dwordx4 (lane
-// l moves bytes [16 l, 16 l + 16) of its chunk).  Wavefronts 0, 1 copy the A
-// tile, 2, 3 the B tile; the tile base is made wavefront-uniform so each copy
-// addresses memory as scalar base + 32-bit lane offset (no 64-bit address
-// registers to keep live across the products).
-template <class R>
-__device__ __forceinline__ void issue_slice(const uint8_t *a_tile, const uint8_t *b_tile, uint8_t *stage) {
-    constexpr int CH = Tile<R>::OPB / 2048;  // chunks per wavefront
+// Copies the MT left and the right digit tiles of one K slice into an LDS
+// stage (left tiles first): chunks of 1 KB, (MT + 1) OPB / 4 KB per
+// wavefront, each a single global_load_lds_dwordx4 (lane l moves bytes
+// [16 l, 16 l + 16) of its chunk).  Every chunk's tile base is made
+// wavefront-uniform so each copy addresses memory as scalar base + 32-bit
+// lane offset (no 64-bit address registers to keep live across the
+// products).  A left tile past the operand's last row tile (null) is not
+// copied: its rows are not stored.
+template <class R, int MT>
+__device__ __forceinline__ void issue_slice(const uint8_t *const (&a_tiles)[MT], const uint8_t *b_tile,
+                                            uint8_t *stage) {
+    constexpr int TCH = Tile<R>::OPB / 1024;  // chunks per tile
+    constexpr int CH = (MT + 1) * TCH / 4;                       // chunks per wavefront
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint8_t *base = uniform_ptr(wave < 2 ? a_tile : b_tile);
-    const uint32_t first = (uint32_t)(wave & 1) * CH * 1024;  // byte offset of the wave's chunks in the tile
 #pragma unroll
     for (int i = 0; i < CH; i++) {
-        const uint32_t off = first + (uint32_t)i * 1024;
-        __builtin_amdgcn_global_load_lds((const void *)(base + off + lane * 16),
-                                         (lds_void *)(stage + wave * CH * 1024 + off - first), 16, 0, 0);
+        const int c = wave * CH + i, q = c / TCH;
+        const uint8_t *src = q < MT ? a_tiles[q < MT ? q : 0] : b_tile;
+        if (!src) continue;
+        const uint8_t *base = uniform_ptr(src);
+        __builtin_amdgcn_global_load_lds((const void *)(base + (uint32_t)(c - q * TCH) * 1024 + lane * 16),
+                                         (lds_void *)(stage + c * 1024), 16, 0, 0);
     }
 }
 
-// The NB (NB + 1) / 2 digit products of one K slice from an LDS stage (136
-// for Z_{2^128}, 36 for Z_{2^64}), fragments read in triangular order.
-template <int NB>
-__device__ __forceinline__ void slice_products(const uint8_t *stage, int a_frag, int b_frag, v16i (&acc)[NB]) {
-    v4i a[NB], b[NB];
-#pragma unroll
-    for (int t = 0; t < NB; t++) {
-        a[t] = *reinterpret_cast<const v4i *>(stage + t * PLANE + a_frag);
-        b[t] = *reinterpret_cast<const v4i *>(stage + NB * PLANE + t * PLANE + b_frag);
-        // pairs (t, j) and (i, t) with i, j <= t and i + j < NB become available
-#pragma unroll
-        for (int j = 0; j <= t && t + j < NB; j++)
-            acc[t + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[t], b[j], acc[t + j], 0, 0, 0);
-#pragma unroll
-        for (int i = 0; i < t && i + t < NB; i++)
-            acc[i + t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[t], acc[i + t], 0, 0, 0);
-    }
-}
-
-// Fragment t of the A (side 0) or B (side 1) tile in an LDS stage.
-template <int NB>
-__device__ __forceinline__ v4i frag(const uint8_t *stage, int side, int t, int off) {
-    return *reinterpret_cast<const v4i *>(stage + (side * NB + t) * PLANE + off);
+// Digit plane t of a fragment whose plane-0 byte offset in an LDS stage is off.
+__device__ __forceinline__ v4i frag(const uint8_t *stage, int off, int t) {
+    return *reinterpret_cast<const v4i *>(stage + off + t * PLANE);
 }
 
 // Product group T of a K slice: the digit pairs (T, j), j <= T, and (i, T),
 // i < T, with digit sum below NB -- the products that fragment pair T
-// completes.  Group sizes 1, 3, 5, ... up to NB / 2, then 2 (NB - T).
-template <int NB>
-__device__ __forceinline__ void group_products(int T, const v4i (&a)[NB], const v4i (&b)[NB], v16i (&acc)[NB]) {
+// completes -- for each of the MT output tiles (which share the right
+// fragments).  Group sizes 1, 3, 5, ... up to NB / 2, then 2 (NB - T), times MT.
+template <int NB, int MT>
+__device__ __forceinline__ void group_products(int T, const v4i (&a)[MT][NB], const v4i (&b)[NB],
+                                               v16i (&acc)[MT][NB]) {
 #pragma unroll
     for (int j = 0; j < NB; j++)
-        if (j <= T && T + j < NB) acc[T + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[T], b[j], acc[T + j], 0, 0, 0);
+#pragma unroll
+        for (int h = 0; h < MT; h++)
+            if (j <= T && T + j < NB)
+                acc[h][T + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[h][T], b[j], acc[h][T + j], 0, 0, 0);
 #pragma unroll
     for (int i = 0; i < NB; i++)
-        if (i < T && i + T < NB) acc[i + T] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[T], acc[i + T], 0, 0, 0);
+#pragma unroll
+        for (int h = 0; h < MT; h++)
+            if (i < T && i + T < NB)
+                acc[h][i + T] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[h][i], b[T], acc[h][i + T], 0, 0, 0);
 }
 
 // vmcnt(0), expcnt and lgkmcnt left unconstrained (gfx9 s_waitcnt encoding)
 #define WAIT_VMEM() __builtin_amdgcn_s_waitcnt(0x0F70)
 
-template <class R>
+template <class R, int MT>
 __device__ __forceinline__ void gemm_tile(const GemmProb &P, int tm, int tn, int split, uint8_t *lds) {
-    constexpr int NB = Tile<R>::NB, STAGE = Tile<R>::STAGE;
+    constexpr int NB = Tile<R>::NB, OPB = Tile<R>::OPB, STAGE = stage_bytes<R, MT>();
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int M = P.M, N = P.N;
-    const int m0 = tm * BM, n0 = tn * BN;
+    const int m0 = tm * 64 * MT, n0 = tn * BN;
     const int s_begin = split * P.steps_per_split;
     const int s_end = min(s_begin + P.steps_per_split, P.nsteps);
+    const int mtiles = (M + 63) / 64;  // row tiles of the packed left operand
 
-    v16i acc[NB];
+    v16i acc[MT][NB];
 #pragma unroll
-    for (int t = 0; t < NB; t++) acc[t] = v16i{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int h = 0; h < MT; h++)
+#pragma unroll
+        for (int t = 0; t < NB; t++) acc[h][t] = v16i{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 
-    auto a_tile = [&](int step) {
-        const int seg = step >= P.kt ? 1 : 0;
+    auto copy_slice = [&](int step, uint8_t *stage) {
+        const int seg = step >= P.kt ? 1 : 0, ks = step - seg * P.kt;
         const R *Lp = reinterpret_cast<const R *>(seg ? P.Lp2 : P.Lp1);
-        return reinterpret_cast<const uint8_t *>(Lp + ((int64_t)tm * P.kt + (step - seg * P.kt)) * TILE_ELEMS);
-    };
-    auto b_tile = [&](int step) {
-        const int seg = step >= P.kt ? 1 : 0;
         const R *Rp = reinterpret_cast<const R *>(seg ? P.Rp2 : P.Rp1);
-        return reinterpret_cast<const uint8_t *>(Rp + ((int64_t)tn * P.kt + (step - seg * P.kt)) * TILE_ELEMS);
+        const uint8_t *at[MT];
+#pragma unroll
+        for (int q = 0; q < MT; q++) {
+            const int t = tm * MT + q;
+            at[q] = t < mtiles ? reinterpret_cast<const uint8_t *>(Lp + ((int64_t)t * P.kt + ks) * TILE_ELEMS) : nullptr;
+        }
+        issue_slice<R, MT>(at, reinterpret_cast<const uint8_t *>(Rp + ((int64_t)tn * P.kt + ks) * TILE_ELEMS), stage);
     };
 
-    // MFMA-side fragment offsets: lane -> row/column lane % 32, k half lane / 32
+    // MFMA-side fragment offsets: lane -> row/column lane % 32, k half lane / 32.
+    // Output tile h of the wavefront has rows 32 (MT wm + h) + lane % 32 of the
+    // workgroup's 64 MT, i.e. rows of left tile (MT wm + h) / 2.
     const int chunk = lane >> 5;
-    const int arow = wm * 32 + (lane & 31);
+    int a_off[MT];
+#pragma unroll
+    for (int h = 0; h < MT; h++) {
+        const int r = 32 * (MT * wm + h) + (lane & 31), q = r >> 6, lr = r & 63;
+        a_off[h] = q * OPB + lr * BK + ((chunk ^ half_swap(lr)) << 4);
+    }
     const int brow = wn * 32 + (lane & 31);
-    const int a_frag = arow * BK + ((chunk ^ half_swap(arow)) << 4);
-    const int b_frag = brow * BK + ((chunk ^ half_swap(brow)) << 4);
+    const int b_off = MT * OPB + brow * BK + ((chunk ^ half_swap(brow)) << 4);
 
     // Software pipeline over K slices (LDS stages alternate):
     //   top of slice s: copy slice s+1 global -> LDS (the other stage);
@@ -403,63 +413,76 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &P, int tm, int tn, int
     //   wavefront reads stage s any more), read fragment pairs 0 and 1 of
     //   slice s+1, then the last two groups of slice s hide their latency.
     // Scheduling barriers keep the compiler from regrouping the reads.
-    v4i a[NB], b[NB], a0n, b0n, a1n, b1n;
-    if (s_begin < s_end) issue_slice<R>(a_tile(s_begin), b_tile(s_begin), lds);
+    v4i a[MT][NB], b[NB], a0n[MT], a1n[MT], b0n, b1n;
+    if (s_begin < s_end) copy_slice(s_begin, lds);
     WAIT_VMEM();
     __syncthreads();
-    a[0] = frag<NB>(lds, 0, 0, a_frag);
-    b[0] = frag<NB>(lds, 1, 0, b_frag);
-    a[1] = frag<NB>(lds, 0, 1, a_frag);
-    b[1] = frag<NB>(lds, 1, 1, b_frag);
+#pragma unroll
+    for (int h = 0; h < MT; h++) {
+        a[h][0] = frag(lds, a_off[h], 0);
+        a[h][1] = frag(lds, a_off[h], 1);
+    }
+    b[0] = frag(lds, b_off, 0);
+    b[1] = frag(lds, b_off, 1);
     for (int s = s_begin; s < s_end; s++) {
         const int buf = (s - s_begin) & 1;
         const uint8_t *stage = lds + buf * STAGE;
         uint8_t *next = lds + (buf ^ 1) * STAGE;
         const bool more = s + 1 < s_end;
-        if (more) issue_slice<R>(a_tile(s + 1), b_tile(s + 1), next);
+        if (more) copy_slice(s + 1, next);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int t = 0; t < NB; t++) {
             if (t + 2 < NB) {
-                a[t + 2] = frag<NB>(stage, 0, t + 2, a_frag);
-                b[t + 2] = frag<NB>(stage, 1, t + 2, b_frag);
+#pragma unroll
+                for (int h = 0; h < MT; h++) a[h][t + 2] = frag(stage, a_off[h], t + 2);
+                b[t + 2] = frag(stage, b_off, t + 2);
             }
-            group_products<NB>(t, a, b, acc);
+            group_products<NB, MT>(t, a, b, acc);
             __builtin_amdgcn_sched_barrier(0);
             if (t == NB - 3) {
                 WAIT_VMEM();
                 __syncthreads();
                 if (more) {
-                    a0n = frag<NB>(next, 0, 0, a_frag);
-                    b0n = frag<NB>(next, 1, 0, b_frag);
-                    a1n = frag<NB>(next, 0, 1, a_frag);
-                    b1n = frag<NB>(next, 1, 1, b_frag);
+#pragma unroll
+                    for (int h = 0; h < MT; h++) {
+                        a0n[h] = frag(next, a_off[h], 0);
+                        a1n[h] = frag(next, a_off[h], 1);
+                    }
+                    b0n = frag(next, b_off, 0);
+                    b1n = frag(next, b_off, 1);
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
-        a[0] = a0n;
+#pragma unroll
+        for (int h = 0; h < MT; h++) {
+            a[h][0] = a0n[h];
+            a[h][1] = a1n[h];
+        }
         b[0] = b0n;
-        a[1] = a1n;
         b[1] = b1n;
     }
 
     // epilogue: 32x32 accumulator layout -- lane l, register r holds
-    // row 8*(r/4) + 4*(l/32) + r%4, column l%32 of the wavefront's tile.
+    // row 8*(r/4) + 4*(l/32) + r%4, column l%32 of the output tile.
     const int col = n0 + wn * 32 + (lane & 31);
+    R *out = reinterpret_cast<R *>(P.out);
 #pragma unroll
-    for (int r = 0; r < 16; r++) {
-        const int row = m0 + wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        R v = Ring<R>::zero();
-        combine<0>(acc, r, v);
-        if (row < M && col < N) {
-            const int64_t idx = (int64_t)row * N + col;
-            R *out = reinterpret_cast<R *>(P.out);
-            if (P.accumulate) {
-                atomic_add128(out + idx, v);
-            } else {
-                if (P.base) v = add(v, ld(reinterpret_cast<const R *>(P.base), idx));
-                st(out, idx, v);
+    for (int h = 0; h < MT; h++) {
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            const int row = m0 + 32 * (MT * wm + h) + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            R v = Ring<R>::zero();
+            combine<0>(acc[h], r, v);
+            if (row < M && col < N) {
+                const int64_t idx = (int64_t)row * N + col;
+                if (P.accumulate) {
+                    atomic_add128(out + idx, v);
+                } else {
+                    if (P.base) v = add(v, ld(reinterpret_cast<const R *>(P.base), idx));
+                    st(out, idx, v);
+                }
             }
         }
     }
@@ -493,10 +516,10 @@ __device__ __forceinline__ int xcd_tile(int b, int total, int mode) {
     return ((i / mode) * 8 + x) * mode + i % mode;
 }
 
-template <class R>
+template <class R, int MT>
 __global__ __launch_bounds__(256, 1) void k_ring_gemm(const GemmProb *__restrict__ probs, int nprobs,
                                                       int total_tiles, int xcd_remap) {
-    __shared__ __attribute__((aligned(1024))) uint8_t lds[2 * Tile<R>::STAGE];
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[2 * stage_bytes<R, MT>()];
     for (int b = blockIdx.x; b < total_tiles; b += gridDim.x) {
         const int t = xcd_remap ? xcd_tile(b, total_tiles, xcd_remap) : b;
         int lo = 0, hi = nprobs - 1;
@@ -518,19 +541,22 @@ __global__ __launch_bounds__(256, 1) void k_ring_gemm(const GemmProb *__restrict
         const int pidx = r3 / gme;
         const int tm = tmg * gm + (r3 - pidx * gme);
         const GemmProb P = probs[G.gfirst + pidx];
-        gemm_tile<R>(P, tm, tn, split, lds);
+        gemm_tile<R, MT>(P, tm, tn, split, lds);
     }
 }
 
-hipError_t launch_gemm(int eb, const GemmProb *probs_dev, int nprobs, int total_tiles, int xcd_remap,
+hipError_t launch_gemm(int eb, const GemmProb *probs_dev, int nprobs, int total_tiles, int xcd_remap, int mt,
                        hipStream_t st) {
     if (nprobs <= 0 || total_tiles <= 0) return hipSuccess;
-    if (eb == 8)
-        hipLaunchKernelGGL(k_ring_gemm<r64>, dim3(total_tiles), dim3(256), 0, st, probs_dev, nprobs, total_tiles,
+    if (eb == 8 && mt == 2)
+        hipLaunchKernelGGL((k_ring_gemm<r64, 2>), dim3(total_tiles), dim3(256), 0, st, probs_dev, nprobs, total_tiles,
+                           xcd_remap);
+    else if (eb == 8)
+        hipLaunchKernelGGL((k_ring_gemm<r64, 1>), dim3(total_tiles), dim3(256), 0, st, probs_dev, nprobs, total_tiles,
                            xcd_remap);
     else
-        hipLaunchKernelGGL(k_ring_gemm<u128>, dim3(total_tiles), dim3(256), 0, st, probs_dev, nprobs, total_tiles,
-                           xcd_remap);
+        hipLaunchKernelGGL((k_ring_gemm<u128, 1>), dim3(total_tiles), dim3(256), 0, st, probs_dev, nprobs,
+                           total_tiles, xcd_remap);
     return hipGetLastError();
 }
 

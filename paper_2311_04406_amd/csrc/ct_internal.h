@@ -239,6 +239,7 @@ __host__ __device__ inline int64_t col_sweep_items(int64_t rows, int64_t N) {
 // 32 KB, for Z_{2^128}; 8 planes, 16 KB, for Z_{2^64}) of 64 x 32 bytes, in the
 // byte order of the GEMM's LDS stage.  Out-of-range entries are zero.
 constexpr int TILE_ELEMS = 2048;
+
 inline int64_t packed_elems(int64_t major, int64_t K) { return ((major + 63) / 64) * ((K + 31) / 32) * TILE_ELEMS; }
 
 // Workspace of a layer with N > SKINNY_MAX_N (element offsets): the folded
@@ -287,7 +288,8 @@ struct GemmProb {
     int32_t group_m;  // tile order: column sweeps over groups of group_m row tiles
     int32_t gfirst;   // index of the first problem of the layer group (problems of one layer
     int32_t gsize;    //   share M, N, K and splits and are interleaved in the tile order)
-    int32_t pad;
+    int32_t mt;       // 32 x 32 output tiles per wavefront, stacked in M (the same for every
+                      // problem of a launch): workgroup tiles of 64 mt x 64 outputs
 };
 
 // Launch configuration of the matrix-core products (chosen by ct_autotune).
@@ -308,7 +310,8 @@ struct SkinnyProb {
 // ---- launchers (defined in the .hip files) ----
 // eb: bytes per ring element, 16 (k = s = 64) or 8 (k = s = 32).
 hipError_t launch_pack(int eb, const PackJob *jobs_dev, int njobs, int total_tiles, hipStream_t st);
-hipError_t launch_gemm(int eb, const GemmProb *probs_dev, int nprobs, int total_tiles, int xcd_remap, hipStream_t st);
+hipError_t launch_gemm(int eb, const GemmProb *probs_dev, int nprobs, int total_tiles, int xcd_remap, int mt,
+                       hipStream_t st);
 hipError_t launch_skinny(int eb, const SkinnyProb *probs_dev, int nprobs, int max_rows, hipStream_t st);
 
 hipError_t launch_fill_zero(int eb, u128 *p, int64_t n, hipStream_t st);
