@@ -232,7 +232,12 @@ ct_status ct_mac_check_device(ct_ctx *ctx, ct_mode mode, const ct_layer_desc *L,
  * the kernel that opens the checked value (E and U from the input shares, D
  * after the products), so no share array is read twice.  This is the
  * amortised verification of many products in one shot.  Asynchronous;
- * allocates nothing. */
+ * allocates nothing.  A batch that mixes layers with N > CT_SKINNY_N and
+ * layers with N <= CT_SKINNY_N runs the former on a second stream of the
+ * context, forked from the context stream after its earlier work and joined
+ * back before its later work, so the two groups overlap; every check record
+ * still lands at its layer's position in out_dev.  With per-kernel timing
+ * enabled (ct_set_timing) the whole batch runs on the context stream. */
 ct_status ct_tag_linear_check(ct_ctx *ctx, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
                               ct_check_result *out_dev);
 
@@ -300,7 +305,9 @@ ct_status ct_set_tuning(ct_ctx *ctx, const ct_tuning *t);
  * layer buffers, out_dev and the launch configuration (ct_autotune's choice
  * for the batch at creation time) are bound at creation; every launch
  * recomputes all outputs from the current contents of the input buffers.
- * Creating a plan allocates; launching one does not. */
+ * A mixed batch is captured as two branches of the graph, as
+ * ct_tag_linear_check runs it on two streams.  Creating a plan allocates;
+ * launching one does not. */
 typedef struct ct_plan ct_plan;
 
 /* Validates as ct_tag_linear_check does (out_dev may be NULL: no
