@@ -325,6 +325,8 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="copy this many MiB once with a plain device copy before the steps (calibrates "
                          "hardware byte counters against a kernel of known traffic)")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="run mixed batches on one stream (every kernel alone, as a per-kernel profile needs)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -342,6 +344,8 @@ def main():
     mode_id = MODE_COMPACT if args.mode == "compact" else MODE_SPDZ2K
     ctx = Context(device=0, key_seed=workloads.KEY_SEED, max_layers=max(256, len(specs)), kbits=args.kbits,
                   parties=args.parties)
+    if args.no_overlap:
+        ctx.set_overlap(False)
     cmp = {"n": 0, "m": 1, "auto": 2}[args.compress]
     implicit = args.conv == "implicit" and args.parties == 2
     layers = [ctx.layer(s.M, s.K, s.N, s.seed, s.layer_id, f=args.f, in_bits=args.in_bits, compress=cmp,

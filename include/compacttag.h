@@ -254,6 +254,12 @@ ct_status ct_mac_check(ct_ctx *ctx, ct_mode mode, const ct_layer_desc *L, const 
  * folded into per-stage totals.  Not for use under graph capture. */
 ct_status ct_set_timing(ct_ctx *ctx, int enable);
 
+/* Whether ct_tag_linear_check and plans created afterwards run the two
+ * layer groups of a mixed batch on two streams (enable != 0, the default) or
+ * the whole batch on the context stream (0: every kernel then runs alone,
+ * as a per-kernel profile needs).  Results are the same either way. */
+ct_status ct_set_overlap(ct_ctx *ctx, int enable);
+
 typedef struct {
     char name[24];        /* kernel stage, e.g. "ring_gemm", "check_batch" */
     double total_ms;      /* summed event-measured duration */

@@ -146,6 +146,7 @@ def load() -> ctypes.CDLL:
     L.ct_mac_check.argtypes = [vp, i, ctypes.POINTER(CtLayerDesc), ctypes.POINTER(CtLayerBufs), i,
                                ctypes.POINTER(CtCheckResult)]
     L.ct_set_timing.argtypes = [vp, i]
+    L.ct_set_overlap.argtypes = [vp, i]
     L.ct_stage_times.argtypes = [vp, ctypes.POINTER(CtStageTime), i, ctypes.POINTER(ctypes.c_int)]
     L.ct_autotune.argtypes = [vp, i, ctypes.POINTER(CtLayerDesc), ctypes.POINTER(CtLayerBufs), i, i,
                               ctypes.POINTER(CtTuning)]
@@ -169,7 +170,7 @@ def load() -> ctypes.CDLL:
     L.ct_last_error.argtypes = [vp]
     L.ct_last_error.restype = ctypes.c_char_p
     for f in ("ct_create", "ct_destroy", "ct_key_shares", "ct_gen_triple_tags", "ct_tag_linear",
-              "ct_mac_check_device", "ct_mac_check", "ct_set_timing", "ct_stage_times", "ct_tag_linear_check",
+              "ct_mac_check_device", "ct_mac_check", "ct_set_timing", "ct_set_overlap", "ct_stage_times", "ct_tag_linear_check",
               "ct_autotune", "ct_get_tuning", "ct_set_tuning", "ct_plan_create", "ct_plan_launch",
               "ct_plan_destroy", "ct_server_create", "ct_server_submit", "ct_server_poll", "ct_server_drain",
               "ct_server_layer", "ct_server_stats", "ct_server_destroy"):
@@ -390,6 +391,10 @@ class Context:
 
     def set_timing(self, enable: bool):
         self._check(self.lib.ct_set_timing(self.h, int(enable)))
+
+    def set_overlap(self, enable: bool):
+        """Mixed batches on two streams (default) or all on the context stream."""
+        self._check(self.lib.ct_set_overlap(self.h, int(enable)))
 
     def stage_times(self):
         """{stage: (total_ms, launches)} since the previous call (synchronizes)."""

@@ -887,7 +887,7 @@ ct_status prepare_online_split(ct_ctx *c, Lane &a, Lane &b, ct_mode mode, const 
                                OnlineLaunch &Pb, bool &split) {
     split = false;
     if (!c) return CT_EINVAL;
-    if (n <= 0 || !L || !B || !b.layers_dev) return prepare_online(c, a, mode, L, B, n, out_dev, Pa);
+    if (n <= 0 || !L || !B || !b.layers_dev || !c->overlap) return prepare_online(c, a, mode, L, B, n, out_dev, Pa);
     // the whole batch first, so that an error names the caller's layer index
     if (mode != CT_MODE_SPDZ2K && mode != CT_MODE_COMPACT) return fail(c, CT_EINVAL, "unknown mode");
     ct_status v = validate(c, a.max_layers, L, B, n,
@@ -1066,6 +1066,12 @@ ct_status ct_plan_destroy(ct_plan *pl) {
     if (st) (void)hipStreamDestroy(st);
     if (side) (void)hipStreamDestroy(side);
     delete pl;
+    return CT_OK;
+}
+
+ct_status ct_set_overlap(ct_ctx *c, int enable) {
+    if (!c) return CT_EINVAL;
+    c->overlap = enable != 0;
     return CT_OK;
 }
 

@@ -58,6 +58,7 @@ struct ct_ctx {
     // events that fork it from and join it to the main stream
     ct::Lane side;
     hipEvent_t fork = nullptr, join = nullptr;
+    bool overlap = true;  // mixed batches on two streams (ct_set_overlap)
     std::string err;
     // per-launch timing: event pairs recorded around each kernel of the main lane
     bool timing = false;

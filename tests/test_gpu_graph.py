@@ -140,6 +140,38 @@ def test_plan_recomputes_from_current_inputs(ctx, mode):
     free()
 
 
+@pytest.mark.parametrize("mode", MODES)
+def test_one_stream_matches_two(ctx, mode):
+    """A mixed batch (skinny layer amid matrix-core ones) run with its two
+    layer groups on two streams (the default) and all on the context stream
+    (ct_set_overlap(0)), eagerly and as a plan: the same outputs and the same
+    check records at the same positions."""
+    say(f"[graph] overlap on/off mode={mode}")
+    layers = gpu_layers(ctx, BATCH)
+    out = torch.zeros(RESULT_WORDS * len(BATCH), dtype=torch.int64, device="cuda:0")
+    ctx.gen_triple_tags(layers)
+    ctx.tag_linear_check(mode, layers, out)
+    torch.cuda.synchronize()
+    ref = snapshot(layers, out)
+    try:
+        ctx.set_overlap(False)
+        clear(layers, out)
+        ctx.tag_linear_check(mode, layers, out)
+        torch.cuda.synchronize()
+        same(layers, out, ref, "one stream, eager")
+        plan = ctx.plan(mode, layers, out)
+        for rep in range(2):
+            clear(layers, out)
+            torch.cuda.synchronize()
+            plan.launch()
+            torch.cuda.synchronize()
+            same(layers, out, ref, f"one stream, replay {rep}")
+        plan.close()
+    finally:
+        ctx.set_overlap(True)
+    free()
+
+
 def test_plan_rejects_invalid(ctx):
     from paper_2311_04406_amd import CtError, Layer
     l = Layer(4, 4, 4, 1, 1)
