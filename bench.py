@@ -25,6 +25,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import math
 import os
@@ -130,10 +131,19 @@ def stage_work(stage: str, specs, mode: str, f: int = 0, kbits: int = 64, compre
 KERNEL_SOURCES = ("ct_device.h", "ct_internal.h", "ct_sweep.h", "ct_kernels.hip", "ct_gemm.hip", "ct_parties.hip")
 
 
+def strip_comments(src: str) -> str:
+    """C/C++ source without its comments and trailing blanks: what the counters
+    depend on (string literals in these files hold no comment markers)."""
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return "\n".join(line.rstrip() for line in src.splitlines() if line.strip())
+
+
 def source_digest() -> str:
+    """Digest of the kernel sources' code (comments ignored)."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, "paper_2311_04406_amd", "csrc", f), "rb").read())
+        h.update(strip_comments(open(os.path.join(ROOT, "paper_2311_04406_amd", "csrc", f)).read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -3,19 +3,23 @@
 // simulated in one process, every per-party step of the two-party path done
 // for each party, every opening a sum over all parties' broadcasts.
 //
-// The kernels are the plain form of the protocol -- one pass per step -- and
-// share only the matrix-core products (k_pack, k_ring_gemm: one product per
-// party) with the fused two-party passes:
+// They share the matrix-core products (k_pack, k_ring_gemm: one product per
+// party) with the two-party path:
 //   dealer   k_np_lift, k_np_auth: n-way authenticated sharing (Sec. 2.4);
-//   online   k_np_open_e, k_np_open_u (Fig. 7 step 1), the products (Eq. (2),
-//            and Eq. (3) in SPDZ2k mode) on the matrix cores or, for
-//            N <= SKINNY_MAX_N, in k_np_skinny, k_np_post (D, Pi_OptMAC,
+//   online   k_np_row_pass, the fused pass over M x K of matrix-core layers
+//            and layers with N <= 2 (E, its check sums, the folded operands,
+//            the compact-tag row products and, for N <= 2, the output
+//            products of every party); k_np_open_e for the other layers and
+//            k_np_open_u (Fig. 7 step 1); the products (Eq. (2), and Eq. (3)
+//            in SPDZ2k mode) on the matrix cores or, for 2 < N <=
+//            SKINNY_MAX_N, in k_np_skinny; k_np_post (D, Pi_OptMAC,
 //            truncation), k_np_compress, k_np_gemv, k_np_compact_final
 //            (Fig. 7 steps 5-7, Eq. (5));
 //   checks   accumulated by the passes (F_CHECK) or by k_np_check_batch /
 //            k_np_check_compact, then k_np_finalize.
 // Check accumulators of a layer: acc[W ACC_W + p] = sum chi [tW]_p for p < n,
-// acc[W ACC_W + MAXP] = sum chi W, W in (E, U, D).
+// acc[W ACC_W + MAXP] = sum chi W, W in (E, U, D); the fused row pass adds
+// its E sums into NP_RP_COPIES limb-celled copies instead (ct_internal.h).
 #include <algorithm>
 
 #include "ct_sweep.h"
