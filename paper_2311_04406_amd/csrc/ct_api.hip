@@ -692,7 +692,7 @@ ct_status prepare_online_np(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_de
         const ct_layer_desc &d = L[l];
         P.max_open = std::max({P.max_open, d.M * d.K, d.K * d.N});
         P.max_mn = std::max(P.max_mn, d.M * d.N);
-        P.max_compress_items = std::max({P.max_compress_items, sweep_items(d.K, d.N), sweep_items(d.M, d.N)});
+        P.max_compress_items = std::max(P.max_compress_items, sweep_items(d.M, d.N));
         P.max_cvec_np = std::max(P.max_cvec_np, (int64_t)CT_CVEC_LEN_NP(d.M, d.K, np));
         if (np_fused_row(d.N)) {
             // the fused row pass (variants 0, 1, 2)
@@ -717,10 +717,9 @@ ct_status enqueue_online_np(ct_ctx *c, Lane &ln, const OnlineLaunch &P) {
     const int n = P.n;
     if (P.zero_what)
         LAUNCH(c, ln, ST_ZERO_ACC, launch_np_zero(c->eb, ln.layers_dev, n, P.zero_what, P.max_zero, ln.stream));
-    // U and its compression first: the fused row pass reads U^c, [tB^c]_p and, for N <= 2, U
+    // U and its compression (formed by the same pass) first: the fused row
+    // pass reads U^c, [tB^c]_p and, for N <= 2, U
     LAUNCH(c, ln, ST_OPEN_U, launch_np_open(c->eb, ln.layers_dev, n, 2, P.flags, P.max_open, ln.stream));
-    if (P.compact)
-        LAUNCH(c, ln, ST_NP_COMPRESS, launch_np_compress(c->eb, ln.layers_dev, n, 1, P.max_compress_items, ln.stream));
     if (P.variants)
         LAUNCH(c, ln, ST_ROW_PASS,
                launch_np_row_pass(c->eb, c->np, ln.layers_dev, n, P.flags, P.max_row_items, P.variants, ln.stream));
@@ -733,7 +732,7 @@ ct_status enqueue_online_np(ct_ctx *c, Lane &ln, const OnlineLaunch &P) {
         LAUNCH(c, ln, ST_NP_SKINNY, launch_np_skinny(c->eb, ln.layers_dev, n, P.flags, P.max_skinny_items, ln.stream));
     LAUNCH(c, ln, ST_POST, launch_np_post(c->eb, ln.layers_dev, n, P.flags, P.max_mn, ln.stream));
     if (P.compact) {
-        LAUNCH(c, ln, ST_NP_COMPRESS, launch_np_compress(c->eb, ln.layers_dev, n, 2, P.max_compress_items, ln.stream));
+        LAUNCH(c, ln, ST_NP_COMPRESS, launch_np_compress(c->eb, ln.layers_dev, n, P.max_compress_items, ln.stream));
         if (P.any_unfused)
             LAUNCH(c, ln, ST_NP_GEMV, launch_np_gemv(c->eb, ln.layers_dev, n, P.max_gemv_items, ln.stream));
         LAUNCH(c, ln, ST_COMPACT_FINAL, launch_np_compact_final(c->eb, ln.layers_dev, n, P.flags, ln.stream));

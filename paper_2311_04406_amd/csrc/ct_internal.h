@@ -336,7 +336,7 @@ hipError_t launch_np_open(int eb, const LayerDev *L, int n, int which, int flags
 hipError_t launch_prob_base(int eb, const GemmProb *probs, int nprobs, int64_t max_mn, hipStream_t st);
 hipError_t launch_np_skinny(int eb, const LayerDev *L, int n, int flags, int64_t max_items, hipStream_t st);
 hipError_t launch_np_post(int eb, const LayerDev *L, int n, int flags, int64_t max_elems, hipStream_t st);
-hipError_t launch_np_compress(int eb, const LayerDev *L, int n, int which_mask, int64_t max_items, hipStream_t st);
+hipError_t launch_np_compress(int eb, const LayerDev *L, int n, int64_t max_items, hipStream_t st);
 // variants: bit v set if some fused layer takes row-pass variant v (0, 1, 2)
 hipError_t launch_np_row_pass(int eb, int np, const LayerDev *L, int n, int flags, int64_t max_items, int variants,
                               hipStream_t st);

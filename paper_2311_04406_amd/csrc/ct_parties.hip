@@ -182,25 +182,50 @@ __global__ __launch_bounds__(TPB) void k_np_open_u(const LayerDev *__restrict__ 
     __shared__ R sh[ACC_W * WAVES];
     const LayerDev &L = Ls[blockIdx.y];
     const int np = L.np;
-    const bool check = flags & F_CHECK;
-    const int64_t n = L.K * L.N;
+    const bool check = flags & F_CHECK, compact = flags & F_COMPACT;
+    const int64_t N = L.N;
     R chk[ACC_W];
 #pragma unroll
     for (int i = 0; i < ACC_W; i++) chk[i] = Ring<R>::zero();
-    const uint64_t kcu = L.key[K_CHI_U];
-    for (int64_t e = blockIdx.x * (int64_t)TPB + threadIdx.x; e < n; e += (int64_t)gridDim.x * TPB) {
-        R U = Ring<R>::zero();
+    const uint64_t kcu = L.key[K_CHI_U], kchi = L.key[K_CHI];
+    const NpCvec o = np_cvec(L.M, L.K, np);
+    R *cv = P<R>(L.cvec);
+    // a sweep over the rows of K x N, so that CompactTag's compressions along
+    // N, U^c = U chi and [tB^c]_p = [tB]_p chi, are formed from the values
+    // this pass has in registers (no second read of U and [tB]_p)
+    auto elem = [&](int64_t r, int64_t c, R (&v)[1 + MAXP]) {
+        const int64_t e = r * N + c;
+        R U = Ring<R>::zero(), tb[MAXP];
 #pragma unroll
-        for (int p = 0; p < MAXP; p++) if (p < np) U = add(U, sub(ld(P<R>(L.Y[p]), e), ld(P<R>(L.B[p]), e)));
+        for (int p = 0; p < MAXP; p++) {
+            tb[p] = Ring<R>::zero();
+            if (p < np) {
+                U = add(U, sub(ld_nt(P<R>(L.Y[p]), e), ld(P<R>(L.B[p]), e)));
+                if (check || compact) tb[p] = ld_nt(P<R>(L.tB[p]), e);
+            }
+        }
         st(P<R>(L.U), e, U);
         if (check) {
             const uint64_t x = Ring<R>::mod_s(sdraw(kcu, (uint64_t)e));
 #pragma unroll
             for (int p = 0; p < MAXP; p++)
-                if (p < np) chk[p] = mad64(chk[p], sub(ld(P<R>(L.tY[p]), e), ld(P<R>(L.tB[p]), e)), x);
+                if (p < np) chk[p] = mad64(chk[p], sub(ld_nt(P<R>(L.tY[p]), e), tb[p]), x);
             chk[MAXP] = mad64(chk[MAXP], U, x);
         }
-    }
+        if (compact) {
+            const uint64_t x = Ring<R>::mod_s(sdraw(kchi, (uint64_t)c));
+            v[0] = mad64(v[0], U, x);
+#pragma unroll
+            for (int p = 0; p < MAXP; p++) if (p < np) v[1 + p] = mad64(v[1 + p], tb[p], x);
+        }
+    };
+    auto done = [&](int64_t r, R (&v)[1 + MAXP]) {
+        if (!compact) return;
+        atomic_add128(cv + o.Uc + r, v[0]);
+#pragma unroll
+        for (int p = 0; p < MAXP; p++) if (p < np) atomic_add128(cv + o.tb(p) + r, v[1 + p]);
+    };
+    row_sweep<R, 1 + MAXP>(L.K, N, elem, done);
     if (check) block_accumulate<ACC_W>(chk, sh, P<R>(L.acc) + 1 * ACC_W);
 }
 
@@ -484,57 +509,40 @@ hipError_t launch_np_post(int eb, const LayerDev *L, int n, int flags, int64_t m
 }
 
 // ---------------------------------------------------------------- compact tag
-// Pi_Compress along N (Fig. 7 steps 5-6), chi_c per column: y = 2 l + 0 over
-// the rows of K x N (U^c, [tB^c]_p), y = 2 l + 1 over the rows of M x N
-// (D^c, [tR^c]_p, [tC^c]_p).
+// Pi_Compress along N (Fig. 7 steps 5-6) of the M x N quantities, chi_c per
+// column: D^c, [tR^c]_p, [tC^c]_p (U^c and [tB^c]_p are formed by
+// k_np_open_u).
 template <class R>
-__global__ __launch_bounds__(TPB) void k_np_compress(const LayerDev *__restrict__ Ls, int which_mask) {
-    const LayerDev &L = Ls[blockIdx.y >> 1];
-    const int which = blockIdx.y & 1, np = L.np;
-    if (!((which_mask >> which) & 1)) return;
+__global__ __launch_bounds__(TPB) void k_np_compress(const LayerDev *__restrict__ Ls) {
+    const LayerDev &L = Ls[blockIdx.y];
+    const int np = L.np;
     const NpCvec o = np_cvec(L.M, L.K, np);
     R *cv = P<R>(L.cvec);
     const uint64_t kchi = L.key[K_CHI];
     const int64_t N = L.N;
-    if (which == 0) {
-        auto elem = [&](int64_t r, int64_t c, R (&v)[1 + MAXP]) {
-            const int64_t e = r * N + c;
-            const uint64_t x = Ring<R>::mod_s(sdraw(kchi, (uint64_t)c));
-            v[0] = mad64(v[0], ld(P<R>(L.U), e), x);
+    auto elem = [&](int64_t r, int64_t c, R (&v)[1 + 2 * MAXP]) {
+        const int64_t e = r * N + c;
+        const uint64_t x = Ring<R>::mod_s(sdraw(kchi, (uint64_t)c));
+        v[0] = mad64(v[0], ld(P<R>(L.D), e), x);
 #pragma unroll
-            for (int p = 0; p < MAXP; p++) if (p < np) v[1 + p] = mad64(v[1 + p], ld(P<R>(L.tB[p]), e), x);
-        };
-        auto done = [&](int64_t r, R (&v)[1 + MAXP]) {
-            atomic_add128(cv + o.Uc + r, v[0]);
+        for (int p = 0; p < MAXP; p++) if (p < np) {
+            v[1 + p] = mad64(v[1 + p], ld(P<R>(L.tR[p]), e), x);
+            v[1 + MAXP + p] = mad64(v[1 + MAXP + p], ld(P<R>(L.tC[p]), e), x);
+        }
+    };
+    auto done = [&](int64_t r, R (&v)[1 + 2 * MAXP]) {
+        atomic_add128(cv + o.Dc + r, v[0]);
 #pragma unroll
-            for (int p = 0; p < MAXP; p++) if (p < np) atomic_add128(cv + o.tb(p) + r, v[1 + p]);
-        };
-        row_sweep<R, 1 + MAXP>(L.K, N, elem, done);
-    } else {
-        auto elem = [&](int64_t r, int64_t c, R (&v)[1 + 2 * MAXP]) {
-            const int64_t e = r * N + c;
-            const uint64_t x = Ring<R>::mod_s(sdraw(kchi, (uint64_t)c));
-            v[0] = mad64(v[0], ld(P<R>(L.D), e), x);
-#pragma unroll
-            for (int p = 0; p < MAXP; p++) if (p < np) {
-                v[1 + p] = mad64(v[1 + p], ld(P<R>(L.tR[p]), e), x);
-                v[1 + MAXP + p] = mad64(v[1 + MAXP + p], ld(P<R>(L.tC[p]), e), x);
-            }
-        };
-        auto done = [&](int64_t r, R (&v)[1 + 2 * MAXP]) {
-            atomic_add128(cv + o.Dc + r, v[0]);
-#pragma unroll
-            for (int p = 0; p < MAXP; p++) if (p < np) {
-                atomic_add128(cv + o.tr(p) + r, v[1 + p]);
-                atomic_add128(cv + o.tc(p) + r, v[1 + MAXP + p]);
-            }
-        };
-        row_sweep<R, 1 + 2 * MAXP>(L.M, N, elem, done);
-    }
+        for (int p = 0; p < MAXP; p++) if (p < np) {
+            atomic_add128(cv + o.tr(p) + r, v[1 + p]);
+            atomic_add128(cv + o.tc(p) + r, v[1 + MAXP + p]);
+        }
+    };
+    row_sweep<R, 1 + 2 * MAXP>(L.M, N, elem, done);
 }
 
-hipError_t launch_np_compress(int eb, const LayerDev *L, int n, int which_mask, int64_t max_items, hipStream_t st) {
-    LAUNCH_RING(eb, k_np_compress, dim3(grid_items(max_items), 2 * n), dim3(TPB), st, L, which_mask);
+hipError_t launch_np_compress(int eb, const LayerDev *L, int n, int64_t max_items, hipStream_t st) {
+    LAUNCH_RING(eb, k_np_compress, dim3(grid_items(max_items), n), dim3(TPB), st, L);
     return hipGetLastError();
 }
 
