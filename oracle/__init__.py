@@ -17,13 +17,17 @@ from __future__ import annotations
 import ctypes
 import os
 import subprocess
+import sys
 from dataclasses import dataclass, field
 
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libct_oracle.so")
 SRC = os.path.join(HERE, "ct_oracle.c")
+# CT_ORACLE_LIB names a library built from ct_oracle.c elsewhere (e.g. with
+# sanitizers); it is then used as it is and never rebuilt here.
+_LIB_OVERRIDE = os.environ.get("CT_ORACLE_LIB") or None
+LIB_PATH = _LIB_OVERRIDE or os.path.join(HERE, "libct_oracle.so")
 
 MODE_SPDZ2K = 0
 MODE_COMPACT = 1
@@ -33,9 +37,32 @@ MASK64 = (1 << 64) - 1
 MASK128 = (1 << 128) - 1
 
 
+def _gpu_initialised() -> bool:
+    """Whether this process has initialised the GPU through torch."""
+    t = sys.modules.get("torch")
+    try:
+        return bool(t is not None and t.cuda.is_initialized())
+    except Exception:
+        return False
+
+
+def stale() -> bool:
+    """Whether libct_oracle.so is missing or older than its source."""
+    return not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC)
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (-O2, no intrinsics, single-threaded)."""
-    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC):
+    """Compile the oracle with gcc (-O2, no intrinsics; each call runs on its
+    calling thread).  A process that has initialised the GPU never compiles
+    (that would fork a compiler from it): there a missing or stale library
+    raises, so build it before the first GPU call."""
+    if _LIB_OVERRIDE:
+        return LIB_PATH
+    if force or stale():
+        if _gpu_initialised():
+            raise RuntimeError(f"{LIB_PATH} is missing or older than {SRC}, and this process has initialised "
+                               "the GPU: build the oracle before any GPU call (python3 -c 'import oracle; "
+                               "oracle.build()')")
         tmp = LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-Wall", "-Wextra",
                                "-o", tmp, SRC])

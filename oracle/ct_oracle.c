@@ -36,12 +36,14 @@
 
 typedef unsigned __int128 u128;
 
-/* Ring multiplications performed so far; the tag accounting of Sec. 3.4.3 is
- * read off this counter around the tag computations. */
-static uint64_t g_mults;
+/* Ring multiplications performed so far by this thread; the tag accounting of
+ * Sec. 3.4.3 is read off this counter around the tag computations.  Both this
+ * counter and the ring width below are per thread, so row ranges of a layer
+ * (or different layers) can run on several threads at once. */
+static _Thread_local uint64_t g_mults;
 
-/* k = s of the current call: 64 (ring Z_{2^128}) or 32 (ring Z_{2^64}). */
-static int64_t g_kbits = 64;
+/* k = s of the current call on this thread: 64 (ring Z_{2^128}) or 32 (ring Z_{2^64}). */
+static _Thread_local int64_t g_kbits = 64;
 
 void or_set_kbits(int64_t kbits) { g_kbits = kbits == 32 ? 32 : 64; }
 
