@@ -365,7 +365,9 @@ typedef struct {
 } ct_server_params;
 
 typedef struct {
-    int64_t id;           /* the caller's request id (unique per server) */
+    int64_t id;           /* the caller's request id, unique per server: a request whose id is that of
+                             a layer still resident (a TAG not yet evicted, or a CHECK that ran as
+                             one) completes with CT_EINVAL and does not run */
     int32_t kind;         /* ct_req_kind */
     int32_t reserved;
     ct_layer_desc layer;  /* TAG: the layer (f must be 0); CHECK: only M, K, N are used */
@@ -377,7 +379,8 @@ typedef struct {
     int64_t id;
     int32_t kind;         /* as executed */
     int32_t status;       /* CT_OK; CT_ABORT: the check rejected; CT_ENOMEM: the layer does not fit in
-                             the arena at all; CT_EDEVICE: a HIP error (ct_server_last_error) */
+                             the arena at all; CT_EINVAL: the id names a resident layer (not run);
+                             CT_EDEVICE: a HIP error (ct_server_last_error) */
     int64_t layer;        /* id of the TAG request whose layer this request wrote or checked (-1 if none) */
     double arrival_us, admit_us, done_us;  /* server clock; done_us: completion seen by the worker */
     int32_t batch_size, slot;
@@ -387,6 +390,7 @@ typedef struct {
 typedef struct {
     int64_t submitted, completed, rejected, converted, evictions, batches, max_batch, resident_layers;
     uint64_t arena_bytes, arena_peak, arena_used;
+    int64_t duplicates;   /* requests refused (CT_EINVAL) because their id named a resident layer */
 } ct_server_counts;
 
 /* Creates the server's slots and starts its worker thread. */

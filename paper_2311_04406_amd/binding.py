@@ -120,7 +120,8 @@ class CtCompletion(ctypes.Structure):
 class CtServerCounts(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "rejected", "converted", "evictions",
                                               "batches", "max_batch", "resident_layers")] + \
-               [(n, ctypes.c_uint64) for n in ("arena_bytes", "arena_peak", "arena_used")]
+               [(n, ctypes.c_uint64) for n in ("arena_bytes", "arena_peak", "arena_used")] + \
+               [("duplicates", ctypes.c_int64)]
 
 
 _lib = None
@@ -189,9 +190,6 @@ class CtError(RuntimeError):
 class CheckResult:
     cs: list            # cs[W][p] as Python ints, W in (E, U, D), p over the parties
     accept: bool
-
-    def sums(self):
-        return [sum(self.cs[w]) % (1 << 128) for w in range(3)]
 
 
 def _result(r: CtCheckResult, parties: int = 2) -> CheckResult:

@@ -146,7 +146,8 @@ struct BatchItem {
     int64_t req_id = 0;
     int32_t requested = REQ_TAG;  // kind as submitted
     int32_t kind = REQ_TAG;       // kind as executed
-    int32_t status = CT_OK;       // CT_ENOMEM: larger than the arena (not executed)
+    int32_t status = CT_OK;       // CT_ENOMEM: larger than the arena; CT_EINVAL: the id of a resident
+                                  // layer (neither is executed)
     int64_t resident = -1;        // id of the resident layer it writes (TAG) or verifies (CHECK)
     double arrival_us = 0;
 };
@@ -159,6 +160,7 @@ struct Batch {
 
 struct SchedStats {
     int64_t submitted = 0, admitted = 0, finished = 0, rejected = 0, converted = 0, evictions = 0, batches = 0;
+    int64_t duplicates = 0;  // requests refused because their id named a resident layer
     int64_t max_batch = 0;
     size_t arena_peak = 0;
 };
@@ -198,7 +200,8 @@ class Scheduler {
     // Forms the next batch from the requests that have arrived by now_us, for
     // a free slot.  Returns false (and forms nothing) if no slot is free or
     // no arrived request can be admitted.  Requests larger than the whole
-    // arena are returned in the batch with status CT_ENOMEM and not executed.
+    // arena are returned in the batch with status CT_ENOMEM, requests whose id
+    // is that of a resident layer with CT_EINVAL; neither is executed.
     bool next_batch(double now_us, Batch &b) {
         const int slot = free_slot();
         b = Batch();
@@ -210,6 +213,15 @@ class Scheduler {
             it.req_id = r.id;
             it.requested = it.kind = r.kind;
             it.arrival_us = r.arrival_us;
+            if (residents_.count(r.id)) {
+                // the id of a layer still resident (maybe in flight): refused,
+                // so that layer and its workspace are never taken over
+                it.status = CT_EINVAL;
+                b.items.push_back(it);
+                queue_.pop_front();
+                stats_.duplicates++;
+                continue;
+            }
             if (r.kind == REQ_CHECK) {
                 Resident *t = newest_ready(r.layer);
                 if (t) {

@@ -371,6 +371,7 @@ ct_status ct_server_stats(ct_server *s, ct_server_counts *out) {
     out->arena_peak = st.arena_peak;
     out->arena_used = s->sched.arena().used();
     out->resident_layers = (int64_t)s->sched.residents().size();
+    out->duplicates = st.duplicates;
     return CT_OK;
 }
 

@@ -3,13 +3,19 @@ import sys
 
 import pytest
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ROOT = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(ROOT)
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    # The oracle is compiled here, before any test touches the GPU: a process
+    # that has initialised the GPU must not fork a compiler (oracle.build
+    # refuses to then).
+    import oracle
+    oracle.build()
 
 
 @pytest.fixture(scope="session")

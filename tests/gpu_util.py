@@ -116,6 +116,13 @@ def compare_cs(gres, ol, which=(0, 1, 2), what=""):
             assert gres.cs[w][p] == O.u128(ol.cs[w, p]), (what, w, p)
 
 
+def cs_sums(res, kbits: int = 64):
+    """Sum over the parties of each check value (E, U, D) of a check record,
+    mod 2^{k+s}: 2^128 for k = s = 64, 2^64 for k = s = 32."""
+    mod = 1 << (2 * kbits)
+    return [sum(res.cs[w]) % mod for w in range(3)]
+
+
 def free():
     torch.cuda.synchronize()
     torch.cuda.empty_cache()

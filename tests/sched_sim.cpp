@@ -234,7 +234,51 @@ static void sched_scenario(const char *name, uint64_t seed, size_t arena, int sl
                 (long long)st.converted, (long long)st.evictions, (long long)st.rejected, st.arena_peak);
 }
 
+// Request ids name resident layers: a request whose id is that of a layer
+// still resident (in flight or complete) is refused with CT_EINVAL and
+// changes nothing; an id becomes free again once its layer is evicted.
+static void dup_scenario() {
+    Scheduler s(size_t(1) << 30, 2, 8);
+    auto req = [](int64_t id, int kind, int64_t M, int64_t K, int64_t N, double t) {
+        PendingReq r;
+        r.id = id;
+        r.kind = kind;
+        r.layer = ct_layer_desc{M, K, N, 0, 0, 100 + (uint64_t)id, 1 + (uint64_t)id, 0, 0, 0, 0, 0, 0, 0, 0};
+        r.arrival_us = t;
+        return r;
+    };
+    s.submit(req(5, REQ_TAG, 64, 576, 300, 0.0));
+    s.submit(req(5, REQ_TAG, 40, 2100, 70, 1.0));    // same id while 5 is in flight
+    s.submit(req(7, REQ_CHECK, 70, 100, 130, 2.0));  // nothing of its shape: runs as a TAG, resident as 7
+    s.submit(req(7, REQ_TAG, 33, 70, 1, 3.0));       // same id as the converted check
+    Batch b;
+    CHECK(s.next_batch(10.0, b));
+    CHECK(b.items.size() == 4);
+    CHECK(b.items[0].status == CT_OK && b.items[0].resident == 5);
+    CHECK(b.items[1].status == CT_EINVAL);
+    CHECK(b.items[2].status == CT_OK && b.items[2].kind == REQ_TAG && b.items[2].resident == 7);
+    CHECK(b.items[3].status == CT_EINVAL);
+    const size_t used = s.arena().used();
+    CHECK(s.resident(5) && s.resident(5)->layer.M == 64 && s.resident(5)->layer.N == 300);
+    CHECK(s.resident(7) && s.resident(7)->layer.M == 70);
+    s.finish(b);
+    CHECK(s.resident(5)->ready && s.resident(5)->pins == 0 && s.resident(7)->ready);
+    // a complete resident layer keeps its id too
+    s.submit(req(5, REQ_TAG, 40, 2100, 70, 11.0));
+    CHECK(s.next_batch(12.0, b));
+    CHECK(b.items.size() == 1 && b.items[0].status == CT_EINVAL);
+    s.finish(b);
+    CHECK(s.arena().used() == used - [&] {
+        size_t w = 0;
+        for (const auto &kv : s.residents()) w += kv.second.work_bytes;
+        return w;
+    }() - layer_work_bytes(64, 576, 300) - layer_work_bytes(70, 100, 130));
+    CHECK(s.stats().duplicates == 3 && s.stats().finished == 5);
+    std::printf("ok sched dupes refused=%lld resident=%zu\n", (long long)s.stats().duplicates, s.residents().size());
+}
+
 int main() {
+    dup_scenario();
     for (uint64_t seed : {1, 2, 3}) arena_scenario(seed);
     // roomy arena, overload: batches fill up, several slots busy at once, no eviction
     sched_scenario("roomy", 11, size_t(1) << 40, 3, 8, 3000, 0.05, 2000.0, 0, 0);

@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import oracle as O
-from gpu_util import compare_cs, compare_layer, free, gpu_layers, oracle_run, say, to_np
+from gpu_util import compare_cs, compare_layer, cs_sums, free, gpu_layers, oracle_run, say, to_np
 from paper_2311_04406_amd.binding import RESULT_WORDS
 
 pytestmark = pytest.mark.gpu
@@ -133,7 +133,7 @@ def test_along_m_flipped_bit_aborts(ctx, target, bit, w):
     ctx.tag_linear(O.MODE_COMPACT, layers)
     status, res = ctx.mac_check(O.MODE_COMPACT, layers)
     assert status == CT_ABORT and not res[0].accept
-    sums = res[0].sums()
+    sums = cs_sums(res[0])
     assert sums[w] != 0, sums
     free()
 
@@ -183,6 +183,6 @@ def test_classifier_compressed_along_m(ctx):
     L["tC"][0].view(-1)[2000] ^= 1 << 7
     ctx.tag_linear(O.MODE_COMPACT, layers)
     status, res = ctx.mac_check(O.MODE_COMPACT, layers)
-    assert status == CT_ABORT and res[0].sums()[2] != 0 and res[0].sums()[0] == 0
+    assert status == CT_ABORT and cs_sums(res[0])[2] != 0 and cs_sums(res[0])[0] == 0
     del layers, L
     free()

@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import oracle as O
-from gpu_util import compare_cs, compare_layer, free, gpu_layers, oracle_run, say, to_np
+from gpu_util import compare_cs, compare_layer, cs_sums, free, gpu_layers, oracle_run, say, to_np
 from paper_2311_04406_amd.binding import RESULT_WORDS
 
 pytestmark = pytest.mark.gpu
@@ -138,7 +138,7 @@ def test_conv_flipped_input_bit_aborts(ctx, mode, target):
     t.view(-1, t.shape[-1])[11, 0] ^= 1 << 33
     ctx.tag_linear(mode, layers)
     status, res = ctx.mac_check(mode, layers)
-    assert status == CT_ABORT and res[0].sums()[1] != 0
+    assert status == CT_ABORT and cs_sums(res[0])[1] != 0
     free()
 
 

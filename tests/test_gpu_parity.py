@@ -5,7 +5,7 @@ import pytest
 import torch
 
 import oracle as O
-from gpu_util import compare_cs, compare_layer, free, gpu_layers, oracle_run, say, to_np
+from gpu_util import compare_cs, compare_layer, cs_sums, free, gpu_layers, oracle_run, say, to_np
 from paper_2311_04406_amd.binding import RESULT_WORDS
 
 pytestmark = pytest.mark.gpu
@@ -167,7 +167,7 @@ def test_flipped_share_bit_aborts(ctx, mode, target):
     fused = Context.decode_results(out, 1)[0]
     status, res = ctx.mac_check(mode, layers)
     assert status == CT_ABORT and not res[0].accept and not fused.accept
-    assert res[0].sums()[w] != 0
+    assert cs_sums(res[0])[w] != 0
     assert fused.cs == res[0].cs
     ol = O.OracleLayer(s.M, s.K, s.N, s.seed, s.layer_id, KEY).deal()
     ol[name][party].reshape(-1, 2)[idx, limb] ^= np.uint64(1 << (bit % 64))

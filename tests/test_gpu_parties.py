@@ -6,7 +6,7 @@ import pytest
 import torch
 
 import oracle as O
-from gpu_util import compare_cs, compare_layer, free, gpu_layers, oracle_run, say, to_np
+from gpu_util import compare_cs, compare_layer, cs_sums, free, gpu_layers, oracle_run, say, to_np
 from paper_2311_04406_amd.binding import RESULT_WORDS
 
 pytestmark = pytest.mark.gpu
@@ -126,7 +126,7 @@ def test_parties_flipped_bit_aborts(contexts, mode, target, w):
         t.view(-1, t.shape[-1])[17, 0] ^= 1 << 29
         c.tag_linear(mode, layers)
         status, res = c.mac_check(mode, layers)
-        assert status == CT_ABORT and res[0].sums()[w] != 0, (target, party)
+        assert status == CT_ABORT and cs_sums(res[0])[w] != 0, (target, party)
         free()
 
 

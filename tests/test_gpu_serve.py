@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import oracle as O
-from gpu_util import compare_cs, compare_layer, free, oracle_run, say, to_np
+from gpu_util import compare_cs, compare_layer, cs_sums, free, oracle_run, say, to_np
 from paper_2311_04406_amd.workloads import poisson_arrivals, request_choices
 
 pytestmark = pytest.mark.gpu
@@ -174,7 +174,7 @@ def test_eviction_rejection_and_tamper(alone_ctx):
     c = srv.poll()[0]
     assert c["kind"] == REQ_CHECK and c["layer"] == 2000 and c["status"] == CT_ABORT
     assert not c["result"].accept
-    sums = c["result"].sums()
+    sums = cs_sums(c["result"])
     assert sums[0] != 0 and sums[1] == 0 and sums[2] == 0   # only the check of E fails
     srv.close()
     ctx.close()
