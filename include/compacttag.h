@@ -241,6 +241,27 @@ ct_status ct_mac_check_device(ct_ctx *ctx, ct_mode mode, const ct_layer_desc *L,
 ct_status ct_tag_linear_check(ct_ctx *ctx, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,
                               ct_check_result *out_dev);
 
+/* Bytes of the static workspace of ct_tag_linear_check_static: 256 MiB per GPU. */
+#define CT_STATIC_WORK_BYTES (256LL << 20)
+
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: exactly
+ * ct_tag_linear_check (same outputs, same check records in out_dev), except
+ * that the workspace of the layers with N > CT_SKINNY_N comes from a static
+ * array of CT_STATIC_WORK_BYTES that the library holds on each GPU for the
+ * life of the process; B[l].work is ignored.  The layers' workspaces
+ * (CT_WORK_LEN_NP(M, K, N, parties) elements each, at 256-byte boundaries)
+ * must fit in it together: otherwise CT_EINVAL with the sizes in
+ * ct_last_error, and nothing runs.  Allocates no device memory (no hipMalloc,
+ * hipFree or other allocating call); the caller still passes every input and
+ * output buffer.  Every call on one GPU
+ * uses the same array and leaves undefined contents in it (every byte a call
+ * reads there it has written first), so calls that overlap on one GPU --
+ * from contexts on different streams, or from several threads -- race and
+ * must be serialized by the caller.  Asynchronous. */
+ct_status ct_tag_linear_check_static(ct_ctx *ctx, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B,
+                                     int n, ct_check_result *out_dev);
+
 /* As ct_mac_check_device, then waits for the stream and copies the n results
  * to host memory out.  Returns CT_ABORT if any layer fails its check (out is
  * still filled, so the caller can see which check value failed). */

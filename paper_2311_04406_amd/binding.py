@@ -25,6 +25,7 @@ MODE_SPDZ2K = 0
 MODE_COMPACT = 1
 CT_OK, CT_EINVAL, CT_ENOMEM, CT_EDEVICE, CT_ABORT = 0, 1, 2, 3, 4
 STATUS = {0: "CT_OK", 1: "CT_EINVAL", 2: "CT_ENOMEM", 3: "CT_EDEVICE", 4: "CT_ABORT"}
+STATIC_WORK_BYTES = 256 << 20   # CT_STATIC_WORK_BYTES
 MASK64 = (1 << 64) - 1
 SKINNY_N = 8
 
@@ -144,6 +145,8 @@ def load() -> ctypes.CDLL:
     L.ct_tag_linear.argtypes = [vp, i, ctypes.POINTER(CtLayerDesc), ctypes.POINTER(CtLayerBufs), i]
     L.ct_mac_check_device.argtypes = [vp, i, ctypes.POINTER(CtLayerDesc), ctypes.POINTER(CtLayerBufs), i, vp]
     L.ct_tag_linear_check.argtypes = [vp, i, ctypes.POINTER(CtLayerDesc), ctypes.POINTER(CtLayerBufs), i, vp]
+    L.ct_tag_linear_check_static.argtypes = [vp, i, ctypes.POINTER(CtLayerDesc), ctypes.POINTER(CtLayerBufs), i,
+                                             vp]
     L.ct_mac_check.argtypes = [vp, i, ctypes.POINTER(CtLayerDesc), ctypes.POINTER(CtLayerBufs), i,
                                ctypes.POINTER(CtCheckResult)]
     L.ct_set_timing.argtypes = [vp, i]
@@ -171,7 +174,7 @@ def load() -> ctypes.CDLL:
     L.ct_last_error.argtypes = [vp]
     L.ct_last_error.restype = ctypes.c_char_p
     for f in ("ct_create", "ct_destroy", "ct_key_shares", "ct_gen_triple_tags", "ct_tag_linear",
-              "ct_mac_check_device", "ct_mac_check", "ct_set_timing", "ct_set_overlap", "ct_stage_times", "ct_tag_linear_check",
+              "ct_mac_check_device", "ct_mac_check", "ct_tag_linear_check_static", "ct_set_timing", "ct_set_overlap", "ct_stage_times", "ct_tag_linear_check",
               "ct_autotune", "ct_get_tuning", "ct_set_tuning", "ct_plan_create", "ct_plan_launch",
               "ct_plan_destroy", "ct_server_create", "ct_server_submit", "ct_server_poll", "ct_server_drain",
               "ct_server_layer", "ct_server_stats", "ct_server_destroy"):
@@ -360,6 +363,13 @@ class Context:
         n, D, B = _arrays(layers)
         assert out.numel() * 8 >= n * ctypes.sizeof(CtCheckResult)
         self._check(self.lib.ct_tag_linear_check(self.h, mode, D, B, n, ctypes.c_void_p(out.data_ptr())))
+
+    def tag_linear_check_static(self, mode: int, layers, out: torch.Tensor):
+        """As tag_linear_check, with the workspace taken from the library's
+        static per-GPU array (the layers' own work tensors are not used)."""
+        n, D, B = _arrays(layers)
+        assert out.numel() * 8 >= n * ctypes.sizeof(CtCheckResult)
+        self._check(self.lib.ct_tag_linear_check_static(self.h, mode, D, B, n, ctypes.c_void_p(out.data_ptr())))
 
     def mac_check(self, mode: int, layers):
         n, D, B = _arrays(layers)

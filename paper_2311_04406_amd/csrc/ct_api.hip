@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -35,7 +36,34 @@ struct ct_plan {
     hipGraphExec_t exec = nullptr;
 };
 
+// The workspace of ct_tag_linear_check_static: one file-scope array that each
+// GPU holds for the life of the process.  Host code never passes the name
+// itself to a kernel (on the host it is only a stand-in): ct_create takes the
+// device address with hipGetSymbolAddress once per device, with that device
+// current, and every use goes through that address.
+static __device__ __align__(256) uint8_t scratch[CT_STATIC_WORK_BYTES];
+
 namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[MAX_DEVICES] = {};  // device address of `scratch` per device
+
+// Device address of this device's `scratch` (the device must be current).
+hipError_t scratch_address(int device, void **out) {
+    *out = nullptr;
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_dev[device] = p;
+    }
+    *out = g_scratch_dev[device];
+    return hipSuccess;
+}
 
 // ---- SplitMix64 (Steele, Lea, Flood 2014), host side ----
 uint64_t hmix(uint64_t z) {
@@ -523,6 +551,8 @@ ct_status ct_create(ct_ctx **out, const ct_params *p) {
         else c->side.stream = side;
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join, hipEventDisableTiming);
+        if (e == hipSuccess) e = scratch_address(c->device, &c->static_work);
+        if (e == hipSuccess) c->static_bufs.resize(ml);
     }
     if (e != hipSuccess) {
         std::fprintf(stderr, "ct_create: %s\n", hipGetErrorString(e));
@@ -970,6 +1000,37 @@ ct_status ct_tag_linear_check(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, c
     bool split = false;
     ct_status s = prepare_online_split(c, c->main, c->side, mode, L, B, n, out_dev, Pa, Pb, split);
     return s != CT_OK ? s : enqueue_online_split(c, c->main, c->side, c->fork, c->join, Pa, Pb, split);
+}
+
+ct_status ct_tag_linear_check_static(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B,
+                                     int n, ct_check_result *out_dev) {
+    if (!c) return CT_EINVAL;
+    if (!L || !B) return fail(c, CT_EINVAL, "null layer or buffer array");
+    if (n < 1 || n > (int)c->static_bufs.size())
+        return fail(c, CT_EINVAL, "n must be in [1, max_layers] (" + std::to_string(c->static_bufs.size()) + ")");
+    if (!c->static_work) return fail(c, CT_EDEVICE, "no static workspace on this device");
+    // the layers' workspaces, one after another at 256-byte boundaries
+    const int64_t cap = CT_STATIC_WORK_BYTES;
+    int64_t off = 0;
+    for (int l = 0; l < n; l++) {
+        const ct_layer_desc &d = L[l];
+        ct_layer_bufs &b = c->static_bufs[l];
+        b = B[l];
+        b.work = nullptr;
+        if (d.N <= SKINNY_MAX_N) continue;  // no workspace
+        // M, K, N of any size are rejected before their products could overflow
+        if (d.M < 1 || d.K < 1 || d.N < 1 || d.M * d.K > cap || d.N * d.K > cap)
+            return fail(c, CT_EINVAL, "layer " + std::to_string(l) + ": needs more workspace than the static "
+                                      "workspace holds (" + std::to_string(cap) + " bytes)");
+        const int64_t bytes = (int64_t)CT_WORK_LEN_NP(d.M, d.K, d.N, (int64_t)c->np) * c->eb;
+        off = (off + 255) & ~(int64_t)255;
+        if (bytes > cap - off)
+            return fail(c, CT_EINVAL, "layers 0.." + std::to_string(l) + " need more than the " + std::to_string(cap) +
+                                      " bytes of the static workspace (CT_STATIC_WORK_BYTES)");
+        b.work = reinterpret_cast<ct_u128 *>(static_cast<uint8_t *>(c->static_work) + off);
+        off += bytes;
+    }
+    return ct_tag_linear_check(c, mode, L, c->static_bufs.data(), n, out_dev);
 }
 
 ct_status ct_mac_check_device(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n,

@@ -72,6 +72,12 @@ struct ct_ctx {
     ct::GemmTuning fallback = {1, 0, 0};
     bool forcing = false;
     ct::GemmTuning forced = {1, 0, 0};
+    // ct_tag_linear_check_static: this device's static workspace (its device
+    // address, from hipGetSymbolAddress at ct_create) and the host copy of a
+    // call's buffer records with their workspace pointers redirected into it
+    // (max_layers records, allocated at ct_create)
+    void *static_work = nullptr;
+    std::vector<ct_layer_bufs> static_bufs;
 };
 
 namespace ct {
