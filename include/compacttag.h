@@ -292,6 +292,23 @@ typedef struct {
  * *count receives the number of stages), then resets the totals. */
 ct_status ct_stage_times(ct_ctx *ctx, ct_stage_time *out, int max, int *count);
 
+/* Product kernel and workgroup tile shape (ct_tuning.tile).  Both kernels
+ * compute the same exact products (identical results); a workgroup of four
+ * wavefronts owns 64 x 64 outputs, or 128 x 64 with two 32 x 32 tiles per
+ * wavefront, which only the k = s = 32 set has registers for (with
+ * k = s = 64 the 128 x 64 shapes run as 64 x 64).
+ *   CT_TILE_AUTO: LDS-staged; 128 x 64 for k = s = 32 when the launch has at
+ *     least two such tiles per compute unit, else 64 x 64.
+ *   CT_TILE_LDS_*: operand digit tiles copied global -> LDS, one K slice
+ *     ahead, fragments read from LDS (a workgroup barrier per K slice).
+ *   CT_TILE_REGS_*: every wavefront loads its digit fragments from global
+ *     memory into registers one K slice ahead; no LDS, no barriers. */
+#define CT_TILE_AUTO 0
+#define CT_TILE_LDS_64x64 1
+#define CT_TILE_LDS_128x64 2
+#define CT_TILE_REGS_64x64 3
+#define CT_TILE_REGS_128x64 4
+
 /* Launch configuration of the matrix-core products. */
 typedef struct {
     int32_t group_m;       /* output row tiles per group of the tile order (>= 1) */
@@ -300,19 +317,22 @@ typedef struct {
                               G consecutive tiles go round-robin over the XCDs, so the tiles of a
                               group share one XCD's L2 */
     int32_t split_target;  /* K slices of 32 per tile; 0 = as many tiles as fill the GPU twice */
-    int32_t reserved;
+    int32_t tile;          /* CT_TILE_*: product kernel and workgroup tile shape */
     double gemm_ms;        /* ct_autotune: measured duration of the products per call */
 } ct_tuning;
 
 /* Autotuner: runs the online phase of this batch of layers (outputs written
- * as by ct_tag_linear) once per candidate launch configuration (group_m in
- * 1, 2, 4, 8, 16, 64; xcd_remap 0, 1, 4, 8, 16; split_target 0, 16, 32, 64, 128),
- * times the matrix-core products with HIP events (reps timed runs after one
- * warm-up each), and keeps the fastest for this shape class -- the protocol
- * and the rounded-up binary logarithms of M, K, N of every matrix-core
- * layer.  Later calls of the same class use it.  Synchronizes; allocates the
- * timing event pool if timing was never enabled.  best (may be NULL)
- * receives the choice. */
+ * as by ct_tag_linear) once per candidate launch configuration, times the
+ * matrix-core products with HIP events (reps timed runs after one warm-up
+ * each), and keeps the fastest for this shape class -- the protocol and the
+ * rounded-up binary logarithms of M, K, N of every matrix-core layer.  The
+ * candidates are a coordinate descent from the current configuration: the
+ * tile shape and kernel (CT_TILE_LDS_64x64, CT_TILE_REGS_64x64, and for
+ * k = s = 32 also the 128 x 64 shapes), then split_target in 0, 16, 32, 64,
+ * 128, xcd_remap in 0, 1, 4, 8, 16 and group_m in 1, 2, 4, 8, 16, 64, each
+ * under the best so far, then the tile shape again.  Later calls of the same
+ * class use the choice.  Synchronizes; allocates the timing event pool if
+ * timing was never enabled.  best (may be NULL) receives the choice. */
 ct_status ct_autotune(ct_ctx *ctx, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n, int reps,
                       ct_tuning *best);
 

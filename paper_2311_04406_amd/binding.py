@@ -86,7 +86,12 @@ class CtStageTime(ctypes.Structure):
 
 class CtTuning(ctypes.Structure):
     _fields_ = [("group_m", ctypes.c_int32), ("xcd_remap", ctypes.c_int32), ("split_target", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("gemm_ms", ctypes.c_double)]
+                ("tile", ctypes.c_int32), ("gemm_ms", ctypes.c_double)]
+
+
+# product kernel and workgroup tile shape (CT_TILE_*)
+TILE_AUTO, TILE_LDS_64x64, TILE_LDS_128x64, TILE_REGS_64x64, TILE_REGS_128x64 = 0, 1, 2, 3, 4
+TILE_NAMES = {0: "auto", 1: "lds_64x64", 2: "lds_128x64", 3: "regs_64x64", 4: "regs_128x64"}
 
 
 class CtCheckResult(ctypes.Structure):
@@ -385,16 +390,18 @@ class Context:
         t = CtTuning()
         self._check(self.lib.ct_autotune(self.h, mode, D, B, n, reps, ctypes.byref(t)))
         return {"group_m": t.group_m, "xcd_remap": t.xcd_remap, "split_target": t.split_target,
-                "gemm_ms": t.gemm_ms}
+                "tile": TILE_NAMES.get(t.tile, t.tile), "gemm_ms": t.gemm_ms}
 
     def get_tuning(self, mode: int, layers) -> dict:
         n, D, B = _arrays(layers)
         t = CtTuning()
         self._check(self.lib.ct_get_tuning(self.h, mode, D, n, ctypes.byref(t)))
-        return {"group_m": t.group_m, "xcd_remap": t.xcd_remap, "split_target": t.split_target}
+        return {"group_m": t.group_m, "xcd_remap": t.xcd_remap, "split_target": t.split_target,
+                "tile": TILE_NAMES.get(t.tile, t.tile)}
 
-    def set_tuning(self, group_m: int = 1, xcd_remap: int = 0, split_target: int = 0):
-        t = CtTuning(group_m, xcd_remap, split_target, 0, 0.0)
+    def set_tuning(self, group_m: int = 1, xcd_remap: int = 0, split_target: int = 0, tile: int = TILE_AUTO):
+        """Launch configuration of shape classes never tuned (tile: TILE_*)."""
+        t = CtTuning(group_m, xcd_remap, split_target, tile, 0.0)
         self._check(self.lib.ct_set_tuning(self.h, ctypes.byref(t)))
 
     def set_timing(self, enable: bool):

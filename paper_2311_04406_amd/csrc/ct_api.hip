@@ -408,14 +408,25 @@ GemmTuning tuning_for(const ct_ctx *c, uint64_t key) {
 // Plans the products: probs holds consecutive groups (the products of one
 // layer); gsize of each problem must be set.  Fills tiles, K splits and the
 // group tile ranges.
-int plan_gemms(std::vector<GemmProb> &probs, int num_cus, const GemmTuning &tu, int *total_tiles, bool *any_accum,
-               int eb) {
-    // Z_{2^64}: two 32 x 32 output tiles per wavefront (128-row workgroup
-    // tiles, half the operand copies and barriers per product) when the
-    // launch still has two such tiles per compute unit before any K split
+// Output tiles per wavefront (stacked in M) a launch takes: tuning tile
+// shapes 128 x 64 exist for Z_{2^64} only (8 diagonal accumulators per tile
+// leave room for two); CT_TILE_AUTO takes them when the launch still has two
+// such workgroup tiles per compute unit before any K split.
+int gemm_mt(const std::vector<GemmProb> &probs, int num_cus, const GemmTuning &tu, int eb) {
+    if (eb != 8) return 1;
+    if (tu.tile == CT_TILE_LDS_128x64 || tu.tile == CT_TILE_REGS_128x64) return 2;
+    if (tu.tile != CT_TILE_AUTO) return 1;
     int64_t tiles128 = 0;
     for (const auto &p : probs) tiles128 += (int64_t)((p.M + 127) / 128) * ((p.N + 63) / 64);
-    const int mt = eb == 8 && tiles128 >= 2LL * num_cus ? 2 : 1;
+    return tiles128 >= 2LL * num_cus ? 2 : 1;
+}
+int gemm_kernel(const GemmTuning &tu) {
+    return tu.tile == CT_TILE_REGS_64x64 || tu.tile == CT_TILE_REGS_128x64 ? GEMM_REGS : GEMM_LDS;
+}
+
+int plan_gemms(std::vector<GemmProb> &probs, int num_cus, const GemmTuning &tu, int *total_tiles, bool *any_accum,
+               int eb) {
+    const int mt = gemm_mt(probs, num_cus, tu, eb);
     int64_t total_steps = 0;
     for (auto &p : probs) {
         p.mt = mt;
@@ -462,7 +473,7 @@ int plan_gemms(std::vector<GemmProb> &probs, int num_cus, const GemmTuning &tu, 
 ct_status run_gemms(ct_ctx *c, Lane &ln, int nprobs, int total_tiles, const GemmTuning &tu) {
     if (nprobs > 0)
         LAUNCH(c, ln, ST_RING_GEMM, launch_gemm(c->eb, ln.gemm_dev, nprobs, total_tiles, tu.xcd_remap,
-                                                ln.gemm_host[0].mt, ln.stream));
+                                                ln.gemm_host[0].mt, gemm_kernel(tu), ln.stream));
     return CT_OK;
 }
 
@@ -1155,9 +1166,9 @@ ct_status ct_set_timing(ct_ctx *c, int enable) {
 ct_status ct_set_tuning(ct_ctx *c, const ct_tuning *t) {
     if (!c || !t) return CT_EINVAL;
     if (t->group_m < 1 || t->split_target < 0 || t->split_target > MAX_STEPS_PER_SPLIT || t->xcd_remap < 0 ||
-        t->xcd_remap > 4096)
+        t->xcd_remap > 4096 || t->tile < CT_TILE_AUTO || t->tile > CT_TILE_REGS_128x64)
         return fail(c, CT_EINVAL, "invalid tuning");
-    c->fallback = GemmTuning{t->group_m, t->xcd_remap, t->split_target};
+    c->fallback = GemmTuning{t->group_m, t->xcd_remap, t->split_target, t->tile};
     c->tuned.clear();
     return CT_OK;
 }
@@ -1168,6 +1179,7 @@ ct_status ct_get_tuning(const ct_ctx *c, ct_mode mode, const ct_layer_desc *L, i
     out->group_m = t.group_m;
     out->xcd_remap = t.xcd_remap;
     out->split_target = t.split_target;
+    out->tile = t.tile;
     out->gemm_ms = -1.0;
     return CT_OK;
 }
@@ -1185,31 +1197,51 @@ ct_status ct_autotune(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_
     static const int groups[] = {1, 2, 4, 8, 16, 64};
     static const int splits[] = {0, 16, 32, 64, 128};
     static const int remaps[] = {0, 1, 4, 8, 16};
+    static const int tiles64[] = {CT_TILE_LDS_64x64, CT_TILE_REGS_64x64};
+    static const int tiles32[] = {CT_TILE_LDS_64x64, CT_TILE_REGS_64x64, CT_TILE_LDS_128x64, CT_TILE_REGS_128x64};
     GemmTuning best = c->fallback;
+    if (best.tile == CT_TILE_AUTO) best.tile = CT_TILE_LDS_64x64;
     double best_ms = 1e30;
-    for (int xcd : remaps)
-        for (int g : groups)
-            for (int sp : splits) {
-                c->forcing = true;
-                c->forced = GemmTuning{g, xcd, sp};
-                s = run_online(c, c->main, mode, L, B, n, nullptr);  // warm-up
-                if (s == CT_OK) {
-                    HIPCHK(c, fold_timing(c));
-                    c->stage_ms[ST_RING_GEMM] = 0;
-                    c->stage_n[ST_RING_GEMM] = 0;
-                    for (int r = 0; r < reps && s == CT_OK; r++) s = run_online(c, c->main, mode, L, B, n, nullptr);
-                }
-                if (s == CT_OK) {
-                    HIPCHK(c, fold_timing(c));
-                    const double ms = c->stage_ms[ST_RING_GEMM] / reps;
-                    if (c->stage_n[ST_RING_GEMM] > 0 && ms < best_ms) {
-                        best_ms = ms;
-                        best = c->forced;
-                    }
-                }
-                c->forcing = false;
-                if (s != CT_OK) return s;
+    // times the products under one candidate; keeps it if it is the fastest
+    auto trial = [&](const GemmTuning &cand) -> ct_status {
+        c->forcing = true;
+        c->forced = cand;
+        ct_status st = run_online(c, c->main, mode, L, B, n, nullptr);  // warm-up
+        if (st == CT_OK) {
+            HIPCHK(c, fold_timing(c));
+            c->stage_ms[ST_RING_GEMM] = 0;
+            c->stage_n[ST_RING_GEMM] = 0;
+            for (int r = 0; r < reps && st == CT_OK; r++) st = run_online(c, c->main, mode, L, B, n, nullptr);
+        }
+        if (st == CT_OK) {
+            HIPCHK(c, fold_timing(c));
+            const double ms = c->stage_ms[ST_RING_GEMM] / reps;
+            if (c->stage_n[ST_RING_GEMM] > 0 && ms < best_ms) {
+                best_ms = ms;
+                best = cand;
             }
+        }
+        c->forcing = false;
+        return st;
+    };
+    // coordinate descent from the current configuration: the kernel and
+    // workgroup tile shape, the K split, the XCD mapping, the tile order;
+    // then the tile shape once more under the chosen rest
+    const int *tl = c->eb == 8 ? tiles32 : tiles64;
+    const int ntl = c->eb == 8 ? 4 : 2;
+    s = trial(best);
+    for (int pass = 0; pass < 2 && s == CT_OK; pass++) {
+        for (int i = 0; i < ntl && s == CT_OK; i++)
+            if (tl[i] != best.tile) { GemmTuning t = best; t.tile = tl[i]; s = trial(t); }
+        if (pass == 1) break;
+        for (int sp : splits)
+            if (s == CT_OK && sp != best.split_target) { GemmTuning t = best; t.split_target = sp; s = trial(t); }
+        for (int xcd : remaps)
+            if (s == CT_OK && xcd != best.xcd_remap) { GemmTuning t = best; t.xcd_remap = xcd; s = trial(t); }
+        for (int g : groups)
+            if (s == CT_OK && g != best.group_m) { GemmTuning t = best; t.group_m = g; s = trial(t); }
+    }
+    if (s != CT_OK) return s;
     c->stage_ms[ST_RING_GEMM] = saved_ms;
     c->stage_n[ST_RING_GEMM] = saved_n;
     if (!was_timing) {
@@ -1220,6 +1252,7 @@ ct_status ct_autotune(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_
         best_out->group_m = best.group_m;
         best_out->xcd_remap = best.xcd_remap;
         best_out->split_target = best.split_target;
+        best_out->tile = best.tile;
         best_out->gemm_ms = best_ms < 1e29 ? best_ms : -1.0;
     }
     return CT_OK;

@@ -358,6 +358,36 @@ __device__ __forceinline__ void group_products(int T, const v4i (&a)[MT][NB], co
                 acc[h][i + T] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[h][i], b[T], acc[h][i + T], 0, 0, 0);
 }
 
+// Epilogue of a wavefront's MT output tiles: the 32x32 accumulator layout
+// gives lane l, register r row 8*(r/4) + 4*(l/32) + r%4 and column l%32 of
+// an output tile; each output is sum_t 2^{8t} S_t plus the base (or added
+// atomically to the output when the product's K range is split).
+template <class R, int MT>
+__device__ __forceinline__ void store_tile_out(const GemmProb &P, const v16i (&acc)[MT][Tile<R>::NB], int m0, int n0,
+                                               int wm, int wn, int lane) {
+    const int M = P.M, N = P.N;
+    const int col = n0 + wn * 32 + (lane & 31);
+    R *out = reinterpret_cast<R *>(P.out);
+#pragma unroll
+    for (int h = 0; h < MT; h++) {
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            const int row = m0 + 32 * (MT * wm + h) + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            R v = Ring<R>::zero();
+            combine<0>(acc[h], r, v);
+            if (row < M && col < N) {
+                const int64_t idx = (int64_t)row * N + col;
+                if (P.accumulate) {
+                    atomic_add128(out + idx, v);
+                } else {
+                    if (P.base) v = add(v, ld(reinterpret_cast<const R *>(P.base), idx));
+                    st(out, idx, v);
+                }
+            }
+        }
+    }
+}
+
 // vmcnt(0), expcnt and lgkmcnt left unconstrained (gfx9 s_waitcnt encoding)
 #define WAIT_VMEM() __builtin_amdgcn_s_waitcnt(0x0F70)
 
@@ -366,7 +396,7 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &P, int tm, int tn, int
     constexpr int NB = Tile<R>::NB, OPB = Tile<R>::OPB, STAGE = stage_bytes<R, MT>();
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    const int M = P.M, N = P.N;
+    const int M = P.M;
     const int m0 = tm * 64 * MT, n0 = tn * BN;
     const int s_begin = split * P.steps_per_split;
     const int s_end = min(s_begin + P.steps_per_split, P.nsteps);
@@ -464,28 +494,7 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &P, int tm, int tn, int
         b[1] = b1n;
     }
 
-    // epilogue: 32x32 accumulator layout -- lane l, register r holds
-    // row 8*(r/4) + 4*(l/32) + r%4, column l%32 of the output tile.
-    const int col = n0 + wn * 32 + (lane & 31);
-    R *out = reinterpret_cast<R *>(P.out);
-#pragma unroll
-    for (int h = 0; h < MT; h++) {
-#pragma unroll
-        for (int r = 0; r < 16; r++) {
-            const int row = m0 + 32 * (MT * wm + h) + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            R v = Ring<R>::zero();
-            combine<0>(acc[h], r, v);
-            if (row < M && col < N) {
-                const int64_t idx = (int64_t)row * N + col;
-                if (P.accumulate) {
-                    atomic_add128(out + idx, v);
-                } else {
-                    if (P.base) v = add(v, ld(reinterpret_cast<const R *>(P.base), idx));
-                    st(out, idx, v);
-                }
-            }
-        }
-    }
+    store_tile_out<R, MT>(P, acc, m0, n0, wm, wn, lane);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
@@ -516,38 +525,206 @@ __device__ __forceinline__ int xcd_tile(int b, int total, int mode) {
     return ((i / mode) * 8 + x) * mode + i % mode;
 }
 
+// Tile t of a launch -> (problem, output row tile, column tile, K split),
+// in the order described above.
+struct TileRef {
+    int prob, tm, tn, split;
+};
+__device__ __forceinline__ TileRef decode_tile(const GemmProb *__restrict__ probs, int nprobs, int t) {
+    int lo = 0, hi = nprobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (probs[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+    }
+    const GemmProb &G = probs[lo];
+    const int tiles_m = G.tiles_m, tiles_n = G.tiles_n, gsize = G.gsize, gm = G.group_m;
+    const int local = t - G.tile_begin;
+    const int per_split = tiles_m * tiles_n * gsize;
+    const int split = local / per_split;
+    const int rem = local - split * per_split;
+    const int tmg = rem / (gm * tiles_n * gsize);
+    const int gme = min(gm, tiles_m - tmg * gm);
+    const int r2 = rem - tmg * gm * tiles_n * gsize;
+    const int tn = r2 / (gme * gsize);
+    const int r3 = r2 - tn * gme * gsize;
+    const int pidx = r3 / gme;
+    return TileRef{G.gfirst + pidx, tmg * gm + (r3 - pidx * gme), tn, split};
+}
+
 template <class R, int MT>
 __global__ __launch_bounds__(256, 1) void k_ring_gemm(const GemmProb *__restrict__ probs, int nprobs,
                                                       int total_tiles, int xcd_remap) {
     __shared__ __attribute__((aligned(1024))) uint8_t lds[2 * stage_bytes<R, MT>()];
     for (int b = blockIdx.x; b < total_tiles; b += gridDim.x) {
         const int t = xcd_remap ? xcd_tile(b, total_tiles, xcd_remap) : b;
-        int lo = 0, hi = nprobs - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (probs[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
-        }
-        const GemmProb &G = probs[lo];
-        const int tiles_m = G.tiles_m, tiles_n = G.tiles_n, gsize = G.gsize, gm = G.group_m;
-        const int local = t - G.tile_begin;
-        const int per_split = tiles_m * tiles_n * gsize;
-        const int split = local / per_split;
-        const int rem = local - split * per_split;
-        const int tmg = rem / (gm * tiles_n * gsize);
-        const int gme = min(gm, tiles_m - tmg * gm);
-        const int r2 = rem - tmg * gm * tiles_n * gsize;
-        const int tn = r2 / (gme * gsize);
-        const int r3 = r2 - tn * gme * gsize;
-        const int pidx = r3 / gme;
-        const int tm = tmg * gm + (r3 - pidx * gme);
-        const GemmProb P = probs[G.gfirst + pidx];
-        gemm_tile<R, MT>(P, tm, tn, split, lds);
+        const TileRef tr = decode_tile(probs, nprobs, t);
+        const GemmProb P = probs[tr.prob];
+        gemm_tile<R, MT>(P, tr.tm, tr.tn, tr.split, lds);
     }
 }
 
+// ---------------------------------------------------------------- products, register-streamed
+// The same products without LDS: every wavefront loads its own digit
+// fragments straight from the packed tiles in global memory into registers
+// (16 bytes per lane, 1 KB per fragment and wavefront, coalesced), one K
+// slice ahead: while product group T of slice s runs, fragment pair T of
+// slice s + 1 is loaded, so each load has a whole slice of products to land
+// and the wavefront never waits at a barrier.  The two wavefronts of a
+// workgroup that share a row (or column) tile read the same fragment at about
+// the same time, so the second read is served by the compute unit's cache.
+// Registers: the NB diagonal accumulators of MT output tiles in AGPRs; the
+// current and the next slice's fragments in VGPRs (live ranges overlap by
+// about half a slice in the triangular order).
+
+// A digit tile of one K slice as a buffer resource: wavefront-uniform base
+// (scalar registers), OPB bytes; a fragment load adds the lane's 32-bit
+// offset and the plane's scalar offset, and anything past the tile would
+// read as zero instead of leaving it.
+typedef __amdgpu_buffer_rsrc_t tile_rsrc;
+#ifndef RS_PREFETCH
+#define RS_PREFETCH 16
+#endif
+constexpr int RSRC_FLAGS = 0x00020000;  // gfx9 buffer resource word 3: 32-bit data format
+
+template <class R>
+__device__ __forceinline__ tile_rsrc tile_buffer(const uint8_t *tile) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(tile), 0, Tile<R>::OPB, RSRC_FLAGS);
+}
+
+__device__ __forceinline__ v4i load_frag(tile_rsrc t, int lane_off, int plane_off) {
+    return __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(t, lane_off, plane_off, 0));
+}
+
+// Loads fragment pair T (MT left fragments, one right fragment) of a slice.
+template <class R, int MT>
+__device__ __forceinline__ void load_pair(int T, const tile_rsrc (&at)[MT], tile_rsrc bt, const int (&a_off)[MT],
+                                          int b_off, v4i (&a)[MT][Tile<R>::NB], v4i (&b)[Tile<R>::NB]) {
+#pragma unroll
+    for (int h = 0; h < MT; h++) a[h][T] = load_frag(at[h], a_off[h], T * PLANE);
+    b[T] = load_frag(bt, b_off, T * PLANE);
+}
+
+// One K slice with a prefetch distance of D <= NB product groups: before group T
+// the wavefront loads fragment pair T + D -- of this slice (tiles ct, cbt,
+// into ca, cb) while T + D < NB, else pair T + D - NB of the next slice
+// (tiles na, nbt, into xa, xb).  Pairs 0 .. D - 1 of a slice are therefore
+// loaded during the previous one.
+template <class R, int MT, int D>
+__device__ __forceinline__ void rs_slice(v4i (&ca)[MT][Tile<R>::NB], v4i (&cb)[Tile<R>::NB],
+                                         v4i (&xa)[MT][Tile<R>::NB], v4i (&xb)[Tile<R>::NB],
+                                         const tile_rsrc (&ct)[MT], tile_rsrc cbt, const tile_rsrc (&na)[MT],
+                                         tile_rsrc nbt, const int (&a_off)[MT], int b_off,
+                                         v16i (&acc)[MT][Tile<R>::NB]) {
+    constexpr int NB = Tile<R>::NB;
+    static_assert(D >= 1 && D <= NB, "prefetch distance");
+#pragma unroll
+    for (int T = 0; T < NB; T++) {
+        if (T + D < NB) load_pair<R, MT>(T + D, ct, cbt, a_off, b_off, ca, cb);
+        else load_pair<R, MT>(T + D - NB, na, nbt, a_off, b_off, xa, xb);
+        group_products<NB, MT>(T, ca, cb, acc);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+template <class R, int MT>
+__device__ __forceinline__ void gemm_tile_rs(const GemmProb &P, int tm, int tn, int split) {
+    constexpr int NB = Tile<R>::NB, OPB = Tile<R>::OPB;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int s_begin = split * P.steps_per_split;
+    const int s_end = min(s_begin + P.steps_per_split, P.nsteps);
+    const int mtiles = (P.M + 63) / 64;  // row tiles of the packed left operand
+
+    v16i acc[MT][NB];
+#pragma unroll
+    for (int h = 0; h < MT; h++)
+#pragma unroll
+        for (int t = 0; t < NB; t++) acc[h][t] = v16i{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+
+    // Lane -> row (column) lane % 32 of the wavefront's 32, 16-byte k half
+    // lane / 32 (rows swap their halves as k_pack lays them out).  Output
+    // tile h has rows 32 (MT wm + h) + lane % 32 of the workgroup's 64 MT,
+    // i.e. rows of left tile q = (MT wm + h) / 2; a missing last left tile
+    // (M past its rows) is read from the first one, whose products are
+    // then not stored.
+    const int chunk = lane >> 5;
+    int a_off[MT], a_q[MT];
+#pragma unroll
+    for (int h = 0; h < MT; h++) {
+        const int r = 32 * (MT * wm + h) + (lane & 31), lr = r & 63;
+        a_q[h] = tm * MT + (r >> 6) < mtiles ? (r >> 6) : 0;
+        a_off[h] = lr * BK + ((chunk ^ half_swap(lr)) << 4);
+    }
+    const int brow = wn * 32 + (lane & 31);
+    const int b_off = brow * BK + ((chunk ^ half_swap(brow)) << 4);
+
+    // digit tiles of step st (a K slice of the first or second segment)
+    auto tiles = [&](int st, tile_rsrc (&at)[MT], tile_rsrc &bt) {
+        const int seg = st >= P.kt ? 1 : 0, ks = st - seg * P.kt;
+        const uint8_t *Lp = reinterpret_cast<const uint8_t *>(seg ? P.Lp2 : P.Lp1);
+        const uint8_t *Rp = reinterpret_cast<const uint8_t *>(seg ? P.Rp2 : P.Rp1);
+#pragma unroll
+        for (int h = 0; h < MT; h++)
+            at[h] = tile_buffer<R>(uniform_ptr(Lp + ((int64_t)(tm * MT + a_q[h]) * P.kt + ks) * OPB));
+        bt = tile_buffer<R>(uniform_ptr(Rp + ((int64_t)tn * P.kt + ks) * OPB));
+    };
+
+    // fragments of two consecutive slices: fa[c], fb[c] hold slice s while
+    // the first pairs of slice s + 1 arrive in fa[1 - c], fb[1 - c] (c
+    // alternates; both indices are compile-time constants)
+    constexpr int D = RS_PREFETCH < NB ? RS_PREFETCH : NB;  // at most a whole slice ahead
+    v4i fa[2][MT][NB], fb[2][NB];
+    tile_rsrc t0[MT], b0t, t1[MT], b1t;
+    if (s_begin < s_end) {
+        tiles(s_begin, t0, b0t);
+#pragma unroll
+        for (int T = 0; T < D; T++) load_pair<R, MT>(T, t0, b0t, a_off, b_off, fa[0], fb[0]);
+    }
+    // slices in pairs (the fragment sets alternate), then an odd last one;
+    // the last slice of the range loads the first pairs of its own tiles
+    // again (unused), so that no load is conditional
+    const int nsl = s_end - s_begin;
+    for (int s = s_begin; s + 1 < s_end; s += 2) {
+        tiles(s + 1, t1, b1t);
+        rs_slice<R, MT, D>(fa[0], fb[0], fa[1], fb[1], t0, b0t, t1, b1t, a_off, b_off, acc);
+        tiles(min(s + 2, s_end - 1), t0, b0t);
+        rs_slice<R, MT, D>(fa[1], fb[1], fa[0], fb[0], t1, b1t, t0, b0t, a_off, b_off, acc);
+    }
+    if (nsl > 0 && (nsl & 1))
+        rs_slice<R, MT, D>(fa[0], fb[0], fa[1], fb[1], t0, b0t, t0, b0t, a_off, b_off, acc);
+    store_tile_out<R, MT>(P, acc, tm * 64 * MT, tn * BN, wm, wn, lane);
+}
+
+// One workgroup per output tile (grid = total_tiles): a loop over tiles
+// around the K loop would make the compiler wait for every outstanding load
+// at the top of each K iteration (the epilogue's stores meet the prefetched
+// loads at the loop header), which the prefetch is there to avoid.
+template <class R, int MT>
+__global__ __launch_bounds__(256, 1) void k_ring_gemm_rs(const GemmProb *__restrict__ probs, int nprobs,
+                                                         int total_tiles, int xcd_remap) {
+    const int b = blockIdx.x;
+    if (b >= total_tiles) return;
+    const int t = xcd_remap ? xcd_tile(b, total_tiles, xcd_remap) : b;
+    const TileRef tr = decode_tile(probs, nprobs, t);
+    const GemmProb P = probs[tr.prob];
+    gemm_tile_rs<R, MT>(P, tr.tm, tr.tn, tr.split);
+}
+
 hipError_t launch_gemm(int eb, const GemmProb *probs_dev, int nprobs, int total_tiles, int xcd_remap, int mt,
-                       hipStream_t st) {
+                       int kernel, hipStream_t st) {
     if (nprobs <= 0 || total_tiles <= 0) return hipSuccess;
+    if (kernel == GEMM_REGS) {
+        if (eb == 8 && mt == 2)
+            hipLaunchKernelGGL((k_ring_gemm_rs<r64, 2>), dim3(total_tiles), dim3(256), 0, st, probs_dev, nprobs,
+                               total_tiles, xcd_remap);
+        else if (eb == 8)
+            hipLaunchKernelGGL((k_ring_gemm_rs<r64, 1>), dim3(total_tiles), dim3(256), 0, st, probs_dev, nprobs,
+                               total_tiles, xcd_remap);
+        else
+            hipLaunchKernelGGL((k_ring_gemm_rs<u128, 1>), dim3(total_tiles), dim3(256), 0, st, probs_dev, nprobs,
+                               total_tiles, xcd_remap);
+        return hipGetLastError();
+    }
     if (eb == 8 && mt == 2)
         hipLaunchKernelGGL((k_ring_gemm<r64, 2>), dim3(total_tiles), dim3(256), 0, st, probs_dev, nprobs, total_tiles,
                            xcd_remap);

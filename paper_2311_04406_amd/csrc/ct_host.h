@@ -69,9 +69,9 @@ struct ct_ctx {
     int64_t stage_n[ST_COUNT] = {};
     // launch configuration of the matrix-core products per shape class
     std::unordered_map<uint64_t, ct::GemmTuning> tuned;
-    ct::GemmTuning fallback = {1, 0, 0};
+    ct::GemmTuning fallback = {1, 0, 0, CT_TILE_AUTO};
     bool forcing = false;
-    ct::GemmTuning forced = {1, 0, 0};
+    ct::GemmTuning forced = {1, 0, 0, CT_TILE_AUTO};
     // ct_tag_linear_check_static: this device's static workspace (its device
     // address, from hipGetSymbolAddress at ct_create) and the host copy of a
     // call's buffer records with their workspace pointers redirected into it

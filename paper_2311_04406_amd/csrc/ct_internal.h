@@ -292,11 +292,16 @@ struct GemmProb {
                       // problem of a launch): workgroup tiles of 64 mt x 64 outputs
 };
 
+// Product kernels: operand tiles staged through LDS, or fragments streamed
+// from global memory into registers.
+enum GemmKernel : int { GEMM_LDS = 0, GEMM_REGS = 1 };
+
 // Launch configuration of the matrix-core products (chosen by ct_autotune).
 struct GemmTuning {
     int32_t group_m;       // row tiles per group of the tile order (1 = row-major order)
     int32_t xcd_remap;     // 0: identity; 1: contiguous range per XCD; G >= 2: groups of G tiles per XCD
     int32_t split_target;  // K slices per tile; 0 = enough tiles for two rounds over the CUs
+    int32_t tile;          // CT_TILE_*: kernel and workgroup tile (0 = by the launch's size)
 };
 
 // Unpacked product for the dealer's layers with N <= SKINNY_MAX_N:
@@ -310,8 +315,10 @@ struct SkinnyProb {
 // ---- launchers (defined in the .hip files) ----
 // eb: bytes per ring element, 16 (k = s = 64) or 8 (k = s = 32).
 hipError_t launch_pack(int eb, const PackJob *jobs_dev, int njobs, int total_tiles, hipStream_t st);
+// kernel: GEMM_LDS (operand tiles staged through LDS, k_ring_gemm) or
+// GEMM_REGS (fragments streamed into registers, k_ring_gemm_rs)
 hipError_t launch_gemm(int eb, const GemmProb *probs_dev, int nprobs, int total_tiles, int xcd_remap, int mt,
-                       hipStream_t st);
+                       int kernel, hipStream_t st);
 hipError_t launch_skinny(int eb, const SkinnyProb *probs_dev, int nprobs, int max_rows, hipStream_t st);
 
 hipError_t launch_fill_zero(int eb, u128 *p, int64_t n, hipStream_t st);
