@@ -13,13 +13,15 @@ runs once before the timed region and is not timed.  Inputs are synthetic
 (uniform ring elements from the dealer's seeded generator) and resident in
 HBM.
 
-Prints one JSON line.  Default workload: the CNN layer set (four VGG-style 3x3
-convolutions as im2col products and the 25088 -> 4096 classifier layer at
-batch 1), CompactTag protocol, with beside it: the same step as eager calls,
-the SPDZ2k protocol, one plain launch per layer, the check as a separate call,
-a per-kernel breakdown with the dominant kernel's roofline, a serving leg
-(open-loop Poisson arrivals of single-layer requests, p50/p99 latency) and
-the oracle on the host.  --config serving runs the full serving sweep.
+Prints one JSON line.  Default workload: the batched layer set (64 linear
+layers with M, K, N log-uniform in [32, 4096], seeded; the largest
+configuration by sum M K N), CompactTag protocol, with beside it: the same
+step as eager calls, the SPDZ2k protocol, one plain launch per layer, the
+check as a separate call, a per-kernel breakdown with the dominant kernel's
+roofline, the captured steps of the CNN and encoder layer sets (--extra), a
+serving leg (open-loop Poisson arrivals of single-layer requests, p50/p99
+latency) and the oracle on the host (all host threads up to 16, and one).
+--config serving runs the full serving sweep.
 """
 from __future__ import annotations
 
@@ -163,6 +165,22 @@ def measured_traffic(kernel: str, workload: str):
     return None
 
 
+def measured_counters(kernel: str, workload: str):
+    """MFMA busy fraction and clock of a product kernel from the committed
+    rocprofv3 counter summary (profiles/counters.json), if it was taken on
+    the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        e = json.load(open(path)).get(workload, {}).get(kernel)
+        if e and e.get("source_digest") == source_digest():
+            return {"mfma_busy": e["mfma_busy"], "clock_ghz": e.get("clock_ghz")}
+    except Exception:
+        return None
+    return None
+
+
 def pct(v, q):
     v = sorted(v)
     if not v:
@@ -209,43 +227,106 @@ def run_steps(ctx, mode_id, layer_groups, out_dev, steps, warmup, torch, timing=
     return t1 - t0, per, stages
 
 
-def cpu_baseline(specs, min_seconds: float = 10.0, kbits: int = 64, implicit: bool = False, parties: int = 2):
-    """The oracle (single-threaded C, -O2) on a bounded sample of the workload:
-    every layer with M * K * N below 2^28 in full, and the first 2048 rows of
-    any larger one (at most six layers); online phase + verification in the
-    CompactTag protocol (the dealer is untimed), convolutions as the timed
-    step runs them (implicit: on the input's shape).  The sample is repeated
-    until at least min_seconds of oracle time have accumulated."""
+def cpu_threads() -> int:
+    """Host threads for the oracle: the cores this process may run on, at most
+    16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_sample(specs, budget_mkn: int = 1 << 30):
+    """A bounded sample of the workload for the oracle: up to 16 layers spread
+    over the batch, each on its first rows, at most budget / (number of
+    layers) M K N per layer.  Returns [(spec, rows)]."""
+    step = max(1, len(specs) // 16)
+    pick = specs[::step][:16]
+    per = budget_mkn // len(pick)
+    out = []
+    for s in pick:
+        rows = max(1, min(s.M, per // max(1, s.K * s.N)))
+        out.append((s, rows))
+    return out
+
+
+def cpu_baseline(specs, min_seconds: float = 10.0, kbits: int = 64, implicit: bool = False, parties: int = 2,
+                 threads: int = 1, mode: int = 1):
+    """The oracle (plain C, -O2) on a bounded sample of the workload (see
+    cpu_sample): online phase + verification of the timed step's protocol,
+    convolutions as the timed step runs them; the dealer is untimed.  With
+    threads > 1 every sampled layer's rows are cut into ranges (about four
+    per layer on large layers) that run concurrently on a thread pool (the
+    oracle releases the interpreter lock; each range opens U and compresses
+    the K x N operands itself, as a separate party computation would).  The
+    sample is repeated until at least min_seconds of wall time have
+    accumulated."""
+    import concurrent.futures as cf
+
     import oracle as O
     from paper_2311_04406_amd.workloads import KEY_SEED
-    O.build()
-    parts = []
-    for s in specs:
-        if s.mkn < (1 << 28):
-            parts.append((s, 0, None))
-        else:
-            parts.append((s, 0, min(s.M, 2048)))
-        if len(parts) >= 6:
-            break
+    parts = cpu_sample(specs)
+    tasks = []
+    for s, rows in parts:
+        pieces = 1 if threads == 1 else max(1, min(4, rows // 8, (rows * s.K * s.N) // (1 << 24)))
+        step = -(-rows // pieces)
+        for r0 in range(0, rows, step):
+            tasks.append((s, r0, min(rows, r0 + step)))
+    tasks.sort(key=lambda t: -(t[2] - t[1]) * t[0].K * t[0].N)
+
+    def deal(t):
+        s, r0, r1 = t
+        return O.OracleLayer(s.M, s.K, s.N, s.seed, s.layer_id, KEY_SEED, r0, r1, kbits=kbits,
+                             conv=s.conv if implicit else None, parties=parties).deal()
+
+    def run(L):
+        L.online(mode).check(mode)
+        return L
     t_tot, macs, passes = 0.0, 0, 0
-    while passes == 0 or t_tot < min_seconds:
-        for s, r0, r1 in parts:
-            L = O.OracleLayer(s.M, s.K, s.N, s.seed, s.layer_id, KEY_SEED, r0, r1, kbits=kbits,
-                              conv=s.conv if implicit else None, parties=parties).deal()
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        dealt = list(ex.map(deal, tasks))   # untimed
+        while passes == 0 or t_tot < min_seconds:
             t0 = time.perf_counter()
-            L.online(O.MODE_COMPACT).check(O.MODE_COMPACT)
+            if threads == 1:
+                for L in dealt:
+                    run(L)
+            else:
+                list(ex.map(run, dealt))
             t_tot += time.perf_counter() - t0
-            rows = (r1 if r1 is not None else s.M) - r0
-            macs += rows * s.K * s.N
-            if r1 is None:
-                assert L.accept()
-            del L
-        passes += 1
-    desc = " + ".join(f"{s.name} rows [{r0},{r1 if r1 is not None else s.M})" for s, r0, r1 in parts)
-    return {"value": macs / t_tot / 1e9, "unit": "G ring-MAC/s", "cores": 1, "kind": "oracle",
-            "sample": f"{desc}, {passes} passes; CompactTag online phase + verification, single-threaded C "
-                      f"oracle; {t_tot:.1f} s",
+            macs += sum((r1 - r0) * s.K * s.N for s, r0, r1 in tasks)
+            passes += 1
+    full = [L for L, (s, r0, r1) in zip(dealt, tasks) if (r0, r1) == (0, s.M)]
+    assert all(L.accept() for L in full)
+    desc = ", ".join(f"{s.name} rows [0,{rows})" for s, rows in parts)
+    return {"value": macs / t_tot / 1e9, "unit": "G ring-MAC/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(parts)} layers: {desc}; {len(tasks)} row ranges, {passes} passes; "
+                      f"{'CompactTag' if mode == 1 else 'SPDZ2k'} online phase + verification, plain C oracle on "
+                      f"{threads} host thread{'s' if threads > 1 else ''}; {t_tot:.1f} s",
             "seconds": t_tot, "ring_macs": macs}
+
+
+def extra_run(torch, ctx, name: str, mode_id: int, args, implicit: bool, cmp: int) -> dict:
+    """The captured step of another workload (same protocol and parameters):
+    dealer untimed, the launch configuration autotuned unless disabled,
+    warm-up, then the timed graph launches; honest acceptance checked."""
+    from paper_2311_04406_amd import RESULT_WORDS, Context, workloads
+    specs = workloads.CONFIGS[name]()
+    layers = [ctx.layer(s.M, s.K, s.N, s.seed, s.layer_id, f=args.f, in_bits=args.in_bits, compress=cmp,
+                        conv=s.conv if implicit else None) for s in specs]
+    ctx.gen_triple_tags(layers)
+    out_dev = torch.zeros(len(layers) * RESULT_WORDS, dtype=torch.int64, device="cuda:0")
+    if not args.no_autotune and not args.tuning:
+        ctx.autotune(mode_id, layers)
+    plan = ctx.plan(mode_id, layers, out_dev)
+    T, per, _ = run_steps(ctx, mode_id, [layers], out_dev, args.steps, args.warmup, torch, plan=plan)
+    plan.close()
+    res = Context.decode_results(out_dev, len(layers), args.parties)
+    mkn = sum(s.mkn for s in specs)
+    del layers
+    return {"value": round(mkn * args.steps / T / 1e9, 3), "ms_per_step": round(T / args.steps * 1e3, 4),
+            "p50_ms": round(pct(per, 50), 4), "p99_ms": round(pct(per, 99), 4), "layers": len(specs),
+            "sum_MKN": mkn, "accept": all(r.accept for r in res)}
 
 
 def serving_run(torch, ctx, mode_id, rate: float, count: int, arena_bytes: int, slots: int, max_batch: int,
@@ -311,7 +392,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="cnn",
+    ap.add_argument("--config", default="batched",
                     choices=["cnn", "transformer", "batched", "training", "fc_small", "serving"])
     ap.add_argument("--serve-rate", type=float, default=1000.0,
                     help="offered rate (req/s) of the serving leg of a layer-batch run")
@@ -331,10 +412,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the SPDZ2k and per-layer comparison runs")
     ap.add_argument("--no-autotune", action="store_true", help="use the default matrix-core launch configuration")
-    ap.add_argument("--tuning", default=None, help="fixed launch configuration group_m,xcd_remap,split_target")
+    ap.add_argument("--tuning", default=None,
+                    help="fixed launch configuration group_m,xcd_remap,split_target[,tile] (tile: CT_TILE_* number)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="copy this many MiB once with a plain device copy before the steps (calibrates "
                          "hardware byte counters against a kernel of known traffic)")
+    ap.add_argument("--extra", default="cnn,transformer",
+                    help="further workloads whose captured step is timed beside the main one (comma list; "
+                         "'' for none)")
     ap.add_argument("--no-overlap", action="store_true",
                     help="run mixed batches on one stream (every kernel alone, as a per-kernel profile needs)")
     args = ap.parse_args()
@@ -344,6 +429,12 @@ def main():
               "the layers shard across GPUs by layer or by output columns, which is not built here",
               file=sys.stderr)
         sys.exit(2)
+
+    if not args.no_cpu_baseline and args.config != "serving":
+        # compiled before any GPU call: a process that has initialised the GPU
+        # must not fork a compiler
+        import oracle
+        oracle.build()
 
     import torch
     from paper_2311_04406_amd import MODE_COMPACT, MODE_SPDZ2K, RESULT_WORDS, Context, Layer, workloads
@@ -376,8 +467,8 @@ def main():
         del src, dst
     tuning = None
     if args.tuning:
-        g, x, sp = (int(v) for v in args.tuning.split(","))
-        ctx.set_tuning(g, x, sp)
+        v = [int(x) for x in args.tuning.split(",")]
+        ctx.set_tuning(*v)
         tuning = ctx.get_tuning(mode_id, layers)
     elif not args.no_autotune:
         print("[bench] autotuning the matrix-core launch configuration ...", file=sys.stderr, flush=True)
@@ -422,11 +513,12 @@ def main():
         else:
             roofline = {"kernel": k, "bound": "mfma", "achieved": v["achieved_TOPS"], "peak": INT8_PEAK_TOPS,
                         "unit": "TOPS (int8)", "frac": v["frac"]}
-        roofline["traffic"] = measured_traffic(k, f"{args.config}/{args.mode}" + (f"/f{args.f}" if args.f else "")
-                                               + ("/k32" if args.kbits == 32 else "")
-                                               + (f"/c{args.compress}" if args.compress != "n" else "")
-                                               + ("/implicit" if implicit else "")
-                                               + (f"/p{args.parties}" if args.parties != 2 else ""))
+        wl_key = (f"{args.config}/{args.mode}" + (f"/f{args.f}" if args.f else "") + ("/k32" if args.kbits == 32 else "")
+                  + (f"/c{args.compress}" if args.compress != "n" else "") + ("/implicit" if implicit else "")
+                  + (f"/p{args.parties}" if args.parties != 2 else ""))
+        roofline["traffic"] = measured_traffic(k, wl_key)
+        if v["bound"] == "mfma":
+            roofline["counters"] = measured_counters(k, wl_key)
         roofline["share_of_step"] = v["share_of_step"]
 
     out = {
@@ -475,14 +567,28 @@ def main():
     del plan
     if not args.no_serve and args.kbits == 64 and args.parties == 2:  # the server runs two parties, k = s = 64
         print(f"[bench] serving leg at {args.serve_rate:g} req/s ...", file=sys.stderr, flush=True)
-        del layers
+        layers = None
         torch.cuda.empty_cache()
         out["serving"] = serving_run(torch, ctx, mode_id, args.serve_rate, serve_count(args.serve_rate),
                                      SERVE_ARENA, SERVE_SLOTS, SERVE_BATCH)
+    if args.extra:
+        del layers
+        torch.cuda.empty_cache()
+        out["extra"] = {}
+        for name in [x for x in args.extra.split(",") if x and x != args.config]:
+            print(f"[bench] extra workload {name} ...", file=sys.stderr, flush=True)
+            out["extra"][name] = extra_run(torch, ctx, name, mode_id, args, implicit, cmp)
+            torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        cb = cpu_baseline(specs, kbits=args.kbits, implicit=implicit, parties=args.parties)
+        nt = cpu_threads()
+        print(f"[bench] cpu baseline (oracle, {nt} threads and 1) ...", file=sys.stderr, flush=True)
+        cb = cpu_baseline(specs, kbits=args.kbits, implicit=implicit, parties=args.parties, threads=nt,
+                          mode=mode_id)
+        c1 = cpu_baseline(specs, kbits=args.kbits, implicit=implicit, parties=args.parties, threads=1,
+                          mode=mode_id)
         out["cpu_baseline"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in cb.items()}
+        out["cpu_baseline"]["single_core"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in c1.items()
+                                              if k in ("value", "seconds", "ring_macs", "cores")}
     ctx.close()
     print(json.dumps(out), flush=True)
 
