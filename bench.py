@@ -330,31 +330,37 @@ def extra_run(torch, ctx, name: str, mode_id: int, args, implicit: bool, cmp: in
 
 
 def serving_run(torch, ctx, mode_id, rate: float, count: int, arena_bytes: int, slots: int, max_batch: int,
-                seed: int = 5000, warm: float = 0.1):
+                seed: int = 5000, warm: float = 0.1, prep_lead_ms: float | None = None):
     """One open-loop serving run: `count` requests of a seeded Poisson stream
     at `rate` req/s, each one layer of the CNN or encoder shape set, tag
     generation or check with probability 1/2, submitted with their scheduled
-    arrival times to a fresh server.  The first `warm` fraction is excluded
-    from the statistics.  Latency = completion - scheduled arrival."""
-    from paper_2311_04406_amd import REQ_TAG, Server, workloads
+    arrival times to a fresh server.  With prep_lead_ms, every tag-generation
+    request is preceded, prep_lead_ms earlier, by a preprocessing request for
+    its layer (the offline phase: the dealer), so that the request itself
+    runs the online phase only.  The first `warm` fraction is excluded from
+    the statistics.  Latency = completion - scheduled arrival."""
+    from paper_2311_04406_amd import REQ_PREP, REQ_TAG, Server, workloads
     shapes = workloads.serving_shapes()
     arr = workloads.poisson_arrivals(rate, count, seed)
     ch = workloads.request_choices(count, len(shapes), seed)
     srv = Server(ctx, arena_bytes, slots=slots, max_batch=max_batch, mode=mode_id)
-    t0 = srv.now_us() + 5000.0
-    reqs = []
+    t0 = srv.now_us() + 5000.0 + (prep_lead_ms or 0.0) * 1e3
+    reqs, preps = [], []
     for i in range(count):
         s = shapes[ch[i][1]]
-        reqs.append((i, ch[i][0], (s.M, s.K, s.N, 50000 + i, 10000 + i), t0 + arr[i] * 1e6))
-    srv.submit(reqs)
+        lay = (s.M, s.K, s.N, 50000 + i, 10000 + i)
+        reqs.append((i, ch[i][0], lay, t0 + arr[i] * 1e6))
+        if prep_lead_ms is not None and ch[i][0] == REQ_TAG:
+            preps.append((count + i, REQ_PREP, lay, t0 + arr[i] * 1e6 - prep_lead_ms * 1e3))
+    srv.submit(preps + reqs)
     srv.drain(600)
-    comps = srv.poll(count + 16)
+    comps = [c for c in srv.poll(count + len(preps) + 16) if c["kind"] != REQ_PREP]
     st = srv.stats()
     srv.close()
     torch.cuda.synchronize()
     by_id = {r[0]: r for r in reqs}
     nwarm = int(count * warm)
-    live = [c for c in comps if c["id"] >= nwarm]
+    live = [c for c in comps if nwarm <= c["id"] < count]
     bad = [c for c in comps if c["status"] != 0]
     lat = sorted((c["done_us"] - c["arrival_us"]) / 1e3 for c in live)
     lat_tag = sorted((c["done_us"] - c["arrival_us"]) / 1e3 for c in live if c["kind"] == REQ_TAG)
@@ -373,7 +379,8 @@ def serving_run(torch, ctx, mode_id, rate: float, count: int, arena_bytes: int, 
             "check_p99_ms": round(pct(lat_chk, 99), 3) if lat_chk else None,
             "batches": st["batches"], "mean_batch": round(st["completed"] / max(st["batches"], 1), 2),
             "max_batch": st["max_batch"], "converted_checks": st["converted"], "evictions": st["evictions"],
-            "arena_peak_GB": round(st["arena_peak"] / 1e9, 2)}
+            "arena_peak_GB": round(st["arena_peak"] / 1e9, 2),
+            "prep_lead_ms": prep_lead_ms, "prepared": st["prepared"], "online_only": st["online_only"]}
 
 
 SERVE_RATES = (100, 200, 500, 1000, 2000, 5000)
@@ -397,6 +404,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=1000.0,
                     help="offered rate (req/s) of the serving leg of a layer-batch run")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-prep-ms", type=float, default=20.0,
+                    help="lead (ms) of the preprocessing requests in the online-phase serving runs")
     ap.add_argument("--f", type=int, default=0, help="truncate every product by f fractional bits (0..k-1)")
     ap.add_argument("--kbits", type=int, default=64, choices=[64, 32],
                     help="parameter set k = s: 64 (shares in Z_2^128) or 32 (shares in Z_2^64)")
@@ -571,6 +580,8 @@ def main():
         torch.cuda.empty_cache()
         out["serving"] = serving_run(torch, ctx, mode_id, args.serve_rate, serve_count(args.serve_rate),
                                      SERVE_ARENA, SERVE_SLOTS, SERVE_BATCH)
+        out["serving_online"] = serving_run(torch, ctx, mode_id, args.serve_rate, serve_count(args.serve_rate),
+                                            SERVE_ARENA, SERVE_SLOTS, SERVE_BATCH, prep_lead_ms=args.serve_prep_ms)
     if args.extra:
         del layers
         torch.cuda.empty_cache()
@@ -600,11 +611,15 @@ def serving_main(args, torch):
     mode_id = MODE_COMPACT if args.mode == "compact" else MODE_SPDZ2K
     ctx = Context(device=0, key_seed=workloads.KEY_SEED)
     rows = []
+    online = []
     for rate in SERVE_RATES:
         print(f"[bench] serving {rate} req/s ...", file=sys.stderr, flush=True)
         rows.append(serving_run(torch, ctx, mode_id, rate, serve_count(rate), SERVE_ARENA, SERVE_SLOTS,
                                 SERVE_BATCH))
         print(f"[bench]   {rows[-1]}", file=sys.stderr, flush=True)
+        online.append(serving_run(torch, ctx, mode_id, rate, serve_count(rate), SERVE_ARENA, SERVE_SLOTS,
+                                  SERVE_BATCH, prep_lead_ms=args.serve_prep_ms))
+        print(f"[bench]   online phase only: {online[-1]}", file=sys.stderr, flush=True)
     ctx.close()
     top = rows[-1]
     ref = next((r for r in rows if r["rate_rps"] == args.serve_rate), rows[0])
@@ -622,6 +637,7 @@ def serving_main(args, torch):
                    "arena_GB": SERVE_ARENA / 2**30, "slots": SERVE_SLOTS, "max_batch": SERVE_BATCH,
                    "latency_rate_rps": ref["rate_rps"]},
         "serving": rows,
+        "serving_online": online,
     }
     print(json.dumps(out), flush=True)
 

@@ -393,7 +393,16 @@ ct_status ct_plan_destroy(ct_plan *plan);
  * afterwards; all layer memory comes from the caller's arena. */
 typedef struct ct_server ct_server;
 
-typedef enum { CT_REQ_TAG = 0, CT_REQ_CHECK = 1 } ct_req_kind;
+/* CT_REQ_PREP: the preprocessing of a layer ahead of its TAG request (the
+ * offline phase, Sec. 3.5; inputs and triple are input-independent material
+ * here, drawn by the dealer): admitted by footprint like a TAG, it runs only
+ * the dealer and leaves the layer resident as prepared.  A later TAG request
+ * for the same layer (M, K, N, seed, layer_id) then runs only the online
+ * phase on it -- waiting, first come first served, if the preparation is
+ * still on the device.  The TAG's results are the same as without the PREP.
+ * A prepared layer no TAG has taken may be evicted (after every complete
+ * layer), and its TAG then deals the layer itself. */
+typedef enum { CT_REQ_TAG = 0, CT_REQ_CHECK = 1, CT_REQ_PREP = 2 } ct_req_kind;
 
 typedef struct {
     void *arena;          /* device memory for resident layers and workspaces (caller-owned,
@@ -432,6 +441,8 @@ typedef struct {
     int64_t submitted, completed, rejected, converted, evictions, batches, max_batch, resident_layers;
     uint64_t arena_bytes, arena_peak, arena_used;
     int64_t duplicates;   /* requests refused (CT_EINVAL) because their id named a resident layer */
+    int64_t prepared;     /* PREP requests admitted */
+    int64_t online_only;  /* TAG requests that ran the online phase only, on a prepared layer */
 } ct_server_counts;
 
 /* Creates the server's slots and starts its worker thread. */

@@ -7,5 +7,5 @@ compact tags, and batch MAC verification, behind the C ABI of
 ``include/compacttag.h``.  ``binding`` is the thin ctypes layer over it.
 """
 from .binding import (COMPRESS_AUTO, COMPRESS_M, COMPRESS_N, CT_ABORT, CT_OK, MAX_PARTIES, MODE_COMPACT,  # noqa
-                      MODE_SPDZ2K, RESULT_WORDS, CheckResult, Context, CtError, Layer, Plan, REQ_CHECK, REQ_TAG,
+                      MODE_SPDZ2K, RESULT_WORDS, CheckResult, Context, CtError, Layer, Plan, REQ_CHECK, REQ_PREP, REQ_TAG,
                       Server, load)

@@ -103,7 +103,7 @@ class CtCheckResult(ctypes.Structure):
 RESULT_WORDS = ctypes.sizeof(CtCheckResult) // 8
 
 
-REQ_TAG, REQ_CHECK = 0, 1
+REQ_TAG, REQ_CHECK, REQ_PREP = 0, 1, 2
 
 
 class CtServerParams(ctypes.Structure):
@@ -127,7 +127,7 @@ class CtServerCounts(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "rejected", "converted", "evictions",
                                               "batches", "max_batch", "resident_layers")] + \
                [(n, ctypes.c_uint64) for n in ("arena_bytes", "arena_peak", "arena_used")] + \
-               [("duplicates", ctypes.c_int64)]
+               [("duplicates", ctypes.c_int64), ("prepared", ctypes.c_int64), ("online_only", ctypes.c_int64)]
 
 
 _lib = None

@@ -4,9 +4,11 @@
 //
 // Requests are tag generation (TAG: the dealer draws the layer's inputs and
 // triple into freshly admitted memory, then the online phase computes its
-// outputs and tags) and verification (CHECK: the MAC checks of a resident
+// outputs and tags), verification (CHECK: the MAC checks of a resident
 // layer of the requested shape whose tags are complete; with none resident
-// it runs as a TAG).  Admission is by footprint in one device arena: a TAG
+// it runs as a TAG) and preprocessing (PREP: only the dealer, ahead of the
+// TAG request of the same layer -- the offline phase; that TAG then runs
+// only the online phase on the prepared layer).  Admission is by footprint in one device arena: a TAG
 // needs the layer's resident bytes plus its transient workspace; completed
 // layers stay resident (shares, tags, public values) for later CHECKs and
 // are evicted least recently used first when a TAG does not fit.  Batches
@@ -122,7 +124,7 @@ class Arena {
     std::map<size_t, size_t> free_;  // offset -> length
 };
 
-enum ReqKind : int32_t { REQ_TAG = 0, REQ_CHECK = 1 };
+enum ReqKind : int32_t { REQ_TAG = 0, REQ_CHECK = 1, REQ_PREP = 2 };
 
 struct PendingReq {
     int64_t id;
@@ -139,6 +141,8 @@ struct Resident {
     size_t work_off = 0, work_bytes = 0;  // workspace, held while its TAG is in flight
     int pins = 0;                    // batches in flight that use it
     bool ready = false;              // its tags are complete
+    bool prepared = false;           // written by a PREP: dealt for a later TAG, online phase not run
+    bool dealt = false;              // (prepared) the dealer has completed
     uint64_t last_use = 0;
 };
 
@@ -148,7 +152,8 @@ struct BatchItem {
     int32_t kind = REQ_TAG;       // kind as executed
     int32_t status = CT_OK;       // CT_ENOMEM: larger than the arena; CT_EINVAL: the id of a resident
                                   // layer (neither is executed)
-    int64_t resident = -1;        // id of the resident layer it writes (TAG) or verifies (CHECK)
+    int64_t resident = -1;        // id of the resident layer it writes (TAG, PREP) or verifies (CHECK)
+    int32_t online_only = 0;      // a TAG on a prepared layer: the online phase only
     double arrival_us = 0;
 };
 
@@ -161,6 +166,8 @@ struct Batch {
 struct SchedStats {
     int64_t submitted = 0, admitted = 0, finished = 0, rejected = 0, converted = 0, evictions = 0, batches = 0;
     int64_t duplicates = 0;  // requests refused because their id named a resident layer
+    int64_t prepared = 0;    // PREP requests admitted
+    int64_t online_only = 0; // TAG requests that found their layer prepared
     int64_t max_batch = 0;
     size_t arena_peak = 0;
 };
@@ -234,6 +241,36 @@ class Scheduler {
                 }
                 it.kind = REQ_TAG;  // nothing of this shape to verify: run it as a TAG
             }
+            if (r.kind == REQ_TAG) {
+                Resident *pr = prepared_for(r.layer);
+                if (pr) {
+                    if (!pr->dealt) break;  // its preparation is still in flight; nothing overtakes
+                    // the online phase needs the workspace again; the
+                    // prepared layer is pinned so that no eviction takes it
+                    const size_t work = layer_work_bytes(r.layer.M, r.layer.K, r.layer.N);
+                    pr->pins++;
+                    size_t woff = work ? Arena::NONE : 0;
+                    while (work && (woff = arena_.alloc(work)) == Arena::NONE)
+                        if (!evict_one()) break;
+                    pr->pins--;
+                    if (woff == Arena::NONE) break;  // waits for memory
+                    Resident res = *pr;
+                    residents_.erase(pr->id);
+                    res.id = r.id;
+                    res.prepared = false;
+                    res.work_off = woff;
+                    res.work_bytes = work;
+                    res.pins = 1;
+                    res.last_use = ++clock_;
+                    residents_[r.id] = res;
+                    it.resident = r.id;
+                    it.online_only = 1;
+                    stats_.online_only++;
+                    b.items.push_back(it);
+                    queue_.pop_front();
+                    continue;
+                }
+            }
             const LayerLayout lay = layer_layout(r.layer.M, r.layer.K, r.layer.N);
             const size_t work = layer_work_bytes(r.layer.M, r.layer.K, r.layer.N);
             if (lay.total + work > arena_.size()) {
@@ -264,8 +301,10 @@ class Scheduler {
             res.work_bytes = work;
             res.pins = 1;
             res.last_use = ++clock_;
+            res.prepared = r.kind == REQ_PREP;
             residents_[r.id] = res;
             if (it.kind != it.requested) stats_.converted++;
+            if (r.kind == REQ_PREP) stats_.prepared++;
             it.resident = r.id;
             b.items.push_back(it);
             queue_.pop_front();
@@ -282,8 +321,9 @@ class Scheduler {
     }
 
     // The batch has completed on the device: TAG layers become ready (their
-    // workspace is released), CHECK pins are dropped, the slot is free.  A
-    // TAG that failed (ok == false) releases its layer.
+    // workspace is released), PREP layers dealt (likewise), CHECK pins are
+    // dropped, the slot is free.  A TAG or PREP that failed (ok == false)
+    // releases its layer.
     void finish(const Batch &b, bool ok = true) {
         for (const BatchItem &it : b.items) {
             stats_.finished++;
@@ -293,11 +333,12 @@ class Scheduler {
             Resident &res = r->second;
             res.pins--;
             res.last_use = ++clock_;
-            if (it.kind == REQ_TAG) {
+            if (it.kind == REQ_TAG || it.kind == REQ_PREP) {
                 if (res.work_bytes) arena_.release(res.work_off, res.work_bytes);
                 res.work_bytes = 0;
                 if (ok) {
-                    res.ready = true;
+                    if (it.kind == REQ_TAG) res.ready = true;
+                    else res.dealt = true;
                 } else {
                     arena_.release(res.off, res.bytes);
                     residents_.erase(r);
@@ -327,15 +368,30 @@ class Scheduler {
         return best;
     }
 
-    // Evicts the least recently used ready layer that no batch in flight
-    // uses; false if there is none.
+    // The dealt or in-flight prepared layer of a TAG's layer (same shape,
+    // seed and layer id), if any.
+    Resident *prepared_for(const ct_layer_desc &d) {
+        for (auto &kv : residents_) {
+            Resident &r = kv.second;
+            if (r.prepared && r.layer.M == d.M && r.layer.K == d.K && r.layer.N == d.N && r.layer.seed == d.seed &&
+                r.layer.layer_id == d.layer_id)
+                return &r;
+        }
+        return nullptr;
+    }
+
+    // Evicts the least recently used complete layer that no batch in flight
+    // uses -- a ready one if there is any, else a dealt prepared one (whose
+    // TAG then deals its layer again); false if there is none.
     bool evict_one() {
         auto victim = residents_.end();
-        for (auto it = residents_.begin(); it != residents_.end(); ++it) {
-            const Resident &r = it->second;
-            if (!r.ready || r.pins > 0) continue;
-            if (victim == residents_.end() || r.last_use < victim->second.last_use) victim = it;
-        }
+        for (int pass = 0; pass < 2 && victim == residents_.end(); pass++)
+            for (auto it = residents_.begin(); it != residents_.end(); ++it) {
+                const Resident &r = it->second;
+                const bool done = pass == 0 ? r.ready : (r.prepared && r.dealt);
+                if (!done || r.pins > 0) continue;
+                if (victim == residents_.end() || r.last_use < victim->second.last_use) victim = it;
+            }
         if (victim == residents_.end()) return false;
         arena_.release(victim->second.off, victim->second.bytes);
         residents_.erase(victim);

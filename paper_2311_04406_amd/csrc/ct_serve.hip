@@ -3,9 +3,10 @@
 // A worker thread owns the context while the server lives.  It takes
 // submitted requests in order of their scheduled arrival, forms batches with
 // the policy of ct_sched.h whenever one of its slots is free, and runs each
-// batch on that slot's stream: the dealer and the online phase for the TAG
-// requests of the batch, then the MAC checks of its CHECK requests, then a
-// copy of the check results to pinned host memory and an event.  Slots run
+// batch on that slot's stream: the dealer for the TAG and PREP requests of
+// the batch (not for a TAG whose layer a PREP has dealt already), the online
+// phase for its TAG requests, then the MAC checks of its CHECK requests, then
+// a copy of the check results to pinned host memory and an event.  Slots run
 // concurrently, so batches admitted while others are on the device overlap
 // with them.  Completions carry the scheduled arrival, admission and
 // completion times on one host clock.
@@ -95,19 +96,20 @@ ct_layer_bufs layer_bufs(char *base, const Resident &r) {
 }
 
 // Enqueues a batch on its slot.  Runs on the worker thread, outside the lock;
-// tagL/tagB and chkL/chkB were read from the scheduler under the lock.
-void launch_batch(ct_server *s, Slot &sl, std::vector<ct_layer_desc> &tagL, std::vector<ct_layer_bufs> &tagB,
+// the layer lists were read from the scheduler under the lock: dealL/dealB
+// the layers the dealer writes (TAG and PREP), onL/onB those whose online
+// phase runs (TAG), chkL/chkB those checked (CHECK).
+void launch_batch(ct_server *s, Slot &sl, std::vector<ct_layer_desc> &dealL, std::vector<ct_layer_bufs> &dealB,
+                  std::vector<ct_layer_desc> &onL, std::vector<ct_layer_bufs> &onB,
                   std::vector<ct_layer_desc> &chkL, std::vector<ct_layer_bufs> &chkB) {
     ct_ctx *c = s->ctx;
     const ct_mode mode = (ct_mode)s->p.mode;
     sl.failed = false;
     sl.error.clear();
     ct_status st = CT_OK;
-    const int nt = (int)tagL.size(), nc = (int)chkL.size();
-    if (nt > 0) {
-        st = run_deal(c, sl.deal, tagL.data(), tagB.data(), nt, 1);
-        if (st == CT_OK) st = run_online(c, sl.online, mode, tagL.data(), tagB.data(), nt, nullptr);
-    }
+    const int nd = (int)dealL.size(), nt = (int)onL.size(), nc = (int)chkL.size();
+    if (nd > 0) st = run_deal(c, sl.deal, dealL.data(), dealB.data(), nd, 1);
+    if (st == CT_OK && nt > 0) st = run_online(c, sl.online, mode, onL.data(), onB.data(), nt, nullptr);
     if (st == CT_OK && nc > 0) {
         st = run_check(c, sl.check, mode, chkL.data(), chkB.data(), nc, sl.check.res_dev);
         if (st == CT_OK &&
@@ -167,8 +169,8 @@ void finish_batch(ct_server *s, Slot &sl, bool device_ok, double now) {
 
 void worker_main(ct_server *s) {
     (void)hipSetDevice(s->ctx->device);
-    std::vector<ct_layer_desc> tagL, chkL;
-    std::vector<ct_layer_bufs> tagB, chkB;
+    std::vector<ct_layer_desc> dealL, onL, chkL;
+    std::vector<ct_layer_bufs> dealB, onB, chkB;
     while (true) {
         bool stopping;
         {
@@ -196,7 +198,7 @@ void worker_main(ct_server *s) {
         }
         while (true) {
             Batch b;
-            tagL.clear(); tagB.clear(); chkL.clear(); chkB.clear();
+            dealL.clear(); dealB.clear(); onL.clear(); onB.clear(); chkL.clear(); chkB.clear();
             Slot *sl = nullptr;
             {
                 std::lock_guard<std::mutex> lk(s->mu);
@@ -207,9 +209,15 @@ void worker_main(ct_server *s) {
                     const BatchItem &it = b.items[i];
                     if (it.status != CT_OK) continue;
                     const Resident *r = s->sched.resident(it.resident);
-                    if (it.kind == REQ_TAG) {
-                        tagL.push_back(r->layer);
-                        tagB.push_back(layer_bufs(s->base, *r));
+                    if (it.kind == REQ_TAG || it.kind == REQ_PREP) {
+                        if (!it.online_only) {
+                            dealL.push_back(r->layer);
+                            dealB.push_back(layer_bufs(s->base, *r));
+                        }
+                        if (it.kind == REQ_TAG) {
+                            onL.push_back(r->layer);
+                            onB.push_back(layer_bufs(s->base, *r));
+                        }
                     } else {
                         chkL.push_back(r->layer);
                         chkB.push_back(layer_bufs(s->base, *r));
@@ -218,7 +226,7 @@ void worker_main(ct_server *s) {
                 }
                 sl->batch = b;
             }
-            launch_batch(s, *sl, tagL, tagB, chkL, chkB);
+            launch_batch(s, *sl, dealL, dealB, onL, onB, chkL, chkB);
             progressed = true;
             busy++;
         }
@@ -301,7 +309,7 @@ ct_status ct_server_submit(ct_server *s, const ct_request *r, int n) {
     if (!s || (n > 0 && !r) || n < 0) return CT_EINVAL;
     for (int i = 0; i < n; i++) {
         const ct_layer_desc &d = r[i].layer;
-        if (r[i].kind != CT_REQ_TAG && r[i].kind != CT_REQ_CHECK)
+        if (r[i].kind != CT_REQ_TAG && r[i].kind != CT_REQ_CHECK && r[i].kind != CT_REQ_PREP)
             return sfail(s, CT_EINVAL, "request " + std::to_string(i) + ": unknown kind");
         if (d.M < 1 || d.K < 1 || d.N < 1 || d.M >= (1LL << 31) || d.K >= (1LL << 21) || d.N >= (1LL << 22) ||
             d.f != 0 || d.in_bits < 0 || d.in_bits > 63 || d.layer_id >= (1ULL << 48) || d.compress < 0 ||
@@ -372,6 +380,8 @@ ct_status ct_server_stats(ct_server *s, ct_server_counts *out) {
     out->arena_used = s->sched.arena().used();
     out->resident_layers = (int64_t)s->sched.residents().size();
     out->duplicates = st.duplicates;
+    out->prepared = st.prepared;
+    out->online_only = st.online_only;
     return CT_OK;
 }
 

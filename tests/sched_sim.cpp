@@ -277,8 +277,73 @@ static void dup_scenario() {
     std::printf("ok sched dupes refused=%lld resident=%zu\n", (long long)s.stats().duplicates, s.residents().size());
 }
 
+// PREP requests: the dealer runs ahead of the TAG of the same layer, which
+// then runs the online phase only (and waits while the PREP is in flight);
+// CHECKs never see prepared layers; a dealt prepared layer is evicted only
+// after every complete one.
+static void prep_scenario() {
+    auto req = [](int64_t id, int kind, int64_t M, int64_t K, int64_t N, uint64_t seed, uint64_t lid, double t) {
+        PendingReq r;
+        r.id = id;
+        r.kind = kind;
+        r.layer = ct_layer_desc{M, K, N, 0, 0, seed, lid, 0, 0, 0, 0, 0, 0, 0, 0};
+        r.arrival_us = t;
+        return r;
+    };
+    Scheduler s(size_t(1) << 30, 2, 8);
+    Batch b, b2;
+    s.submit(req(100, REQ_PREP, 64, 576, 300, 11, 21, 0.0));
+    CHECK(s.next_batch(1.0, b));
+    CHECK(b.items.size() == 1 && b.items[0].kind == REQ_PREP && b.items[0].resident == 100 && !b.items[0].online_only);
+    const size_t work = layer_work_bytes(64, 576, 300), lay = layer_layout(64, 576, 300).total;
+    CHECK(s.resident(100)->prepared && !s.resident(100)->dealt && s.arena().used() == arena_round(lay) + work);
+    s.finish(b);
+    CHECK(s.resident(100)->dealt && !s.resident(100)->ready && s.arena().used() == arena_round(lay));
+    // its TAG takes the prepared layer over: online phase only, workspace again
+    s.submit(req(1, REQ_TAG, 64, 576, 300, 11, 21, 2.0));
+    CHECK(s.next_batch(3.0, b));
+    CHECK(b.items.size() == 1 && b.items[0].kind == REQ_TAG && b.items[0].online_only && b.items[0].resident == 1);
+    CHECK(s.resident(100) == nullptr && s.resident(1) && !s.resident(1)->prepared && s.resident(1)->work_bytes == work);
+    s.finish(b);
+    CHECK(s.resident(1)->ready && s.arena().used() == arena_round(lay));
+    // a TAG whose PREP is still on the device waits for it
+    s.submit(req(101, REQ_PREP, 70, 100, 130, 12, 22, 4.0));
+    s.submit(req(2, REQ_TAG, 70, 100, 130, 12, 22, 5.0));
+    CHECK(s.next_batch(6.0, b));
+    CHECK(b.items.size() == 1 && b.items[0].kind == REQ_PREP);
+    CHECK(!s.next_batch(6.0, b2) && s.queued() == 1);
+    s.finish(b);
+    CHECK(s.next_batch(7.0, b));
+    CHECK(b.items.size() == 1 && b.items[0].online_only && b.items[0].resident == 2);
+    s.finish(b);
+    // without a PREP a TAG deals as before; a CHECK of a prepared shape does not see it
+    s.submit(req(102, REQ_PREP, 40, 2100, 70, 13, 23, 8.0));
+    s.submit(req(3, REQ_TAG, 33, 70, 1, 14, 24, 8.5));
+    s.submit(req(4, REQ_CHECK, 40, 2100, 70, 15, 25, 9.0));
+    CHECK(s.next_batch(10.0, b));
+    CHECK(b.items.size() == 3 && !b.items[1].online_only && b.items[2].kind == REQ_TAG && b.items[2].resident == 4);
+    s.finish(b);
+    CHECK(s.resident(102)->dealt && s.resident(4)->ready);
+    const SchedStats &st = s.stats();
+    CHECK(st.prepared == 3 && st.online_only == 2 && st.converted == 1 && st.finished == 7);
+    // eviction order: complete layers first, then the dealt prepared one
+    Scheduler t(arena_round(layer_layout(64, 64, 64).total) * 2 + layer_work_bytes(64, 64, 64), 1, 1);
+    t.submit(req(200, REQ_PREP, 64, 64, 64, 31, 41, 0.0));
+    CHECK(t.next_batch(1.0, b)); t.finish(b);
+    t.submit(req(5, REQ_TAG, 64, 64, 64, 32, 42, 2.0));
+    CHECK(t.next_batch(3.0, b)); t.finish(b);
+    t.submit(req(6, REQ_TAG, 64, 64, 64, 33, 43, 4.0));
+    CHECK(t.next_batch(5.0, b)); t.finish(b);
+    CHECK(t.resident(200) && t.resident(5) == nullptr && t.resident(6) && t.stats().evictions == 1);
+    t.submit(req(7, REQ_TAG, 64, 64, 64, 34, 44, 6.0));
+    CHECK(t.next_batch(7.0, b)); t.finish(b);
+    CHECK(t.stats().evictions == 2 && (t.resident(200) == nullptr) != (t.resident(6) == nullptr));
+    std::printf("ok sched prep prepared=%lld online_only=%lld\n", (long long)st.prepared, (long long)st.online_only);
+}
+
 int main() {
     dup_scenario();
+    prep_scenario();
     for (uint64_t seed : {1, 2, 3}) arena_scenario(seed);
     // roomy arena, overload: batches fill up, several slots busy at once, no eviction
     sched_scenario("roomy", 11, size_t(1) << 40, 3, 8, 3000, 0.05, 2000.0, 0, 0);

@@ -181,6 +181,46 @@ def test_eviction_rejection_and_tamper(alone_ctx):
     free()
 
 
+@pytest.mark.parametrize("mode", [O.MODE_COMPACT, O.MODE_SPDZ2K])
+def test_prepared_layers_equal_alone(alone_ctx, mode):
+    """PREP requests deal layers ahead of their TAG requests (the offline
+    phase); those TAGs run the online phase only, and every served layer --
+    prepared or not -- equals the same layer computed alone, bit for bit.
+    A repeated id of a resident layer is refused without running."""
+    from paper_2311_04406_amd import REQ_PREP, REQ_TAG, Context, Server
+    from paper_2311_04406_amd.binding import CT_EINVAL
+    say(f"[serve] prepared layers mode={mode}")
+    ctx = Context(device=0, key_seed=KEY)
+    srv = Server(ctx, 4 << 30, slots=3, max_batch=8, mode=mode)
+    t0 = srv.now_us() + 3000.0
+    tags = requests(24, 20000.0, 5200 + mode, SHAPES, t0 + 2000.0)
+    tags = [(i, REQ_TAG, lay, t) for i, _, lay, t in tags]
+    preps = [(1000 + i, REQ_PREP, lay, t0 + 50.0 * i) for i, _, lay, t in tags if i % 3 != 2]
+    srv.submit(preps + tags)
+    srv.drain(120)
+    comps = srv.poll()
+    st = srv.stats()
+    say(f"[serve] stats {st}")
+    assert len(comps) == len(preps) + len(tags) and all(c["status"] == 0 for c in comps)
+    assert st["prepared"] == len(preps) and 0 < st["online_only"] <= len(preps)
+    by_id = {r[0]: r for r in tags}
+    for c in comps:
+        if c["kind"] != REQ_TAG:
+            continue
+        assert c["layer"] == c["id"]
+        M, K, N, seed, lid = by_id[c["id"]][2]
+        ref, ref_st, ref_res = alone(alone_ctx, mode, M, K, N, seed, lid)
+        same_layer(srv.layer(c["id"]), ref, f"request {c['id']} {M}x{K}x{N}", mode)
+        del ref
+    srv.submit([(0, REQ_TAG, by_id[0][2], srv.now_us())])   # id 0 is resident
+    srv.drain(60)
+    c = srv.poll()[0]
+    assert c["id"] == 0 and c["status"] == CT_EINVAL and srv.stats()["duplicates"] == 1
+    srv.close()
+    ctx.close()
+    free()
+
+
 def test_server_rejects_invalid_parameters():
     from paper_2311_04406_amd import Context, CtError, Server
     ctx = Context(device=0, key_seed=KEY)

@@ -37,4 +37,4 @@ def test_scheduler_simulation_under_asan_and_ubsan(tmp_path):
                            "-o", exe, os.path.join(ROOT, "tests", "sched_sim.cpp")])
     r = subprocess.run([exe], capture_output=True, text=True, timeout=600, env=dict(os.environ, **ENV_SAN))
     assert r.returncode == 0, (r.stdout + r.stderr)[-3000:]
-    assert r.stdout.count("ok sched") == 5 and r.stdout.count("ok arena") == 3
+    assert r.stdout.count("ok sched") == 6 and r.stdout.count("ok arena") == 3

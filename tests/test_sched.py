@@ -31,7 +31,9 @@ def run_sim(tmp_path):
 def test_scheduler_simulation(tmp_path):
     text, s = run_sim(tmp_path)
     assert text.count("ok arena") == 3
-    assert set(s) == {"roomy", "tight", "small", "serial", "dupes"}
+    assert set(s) == {"roomy", "tight", "small", "serial", "dupes", "prep"}
+    # preprocessing ahead of a TAG: the TAG runs the online phase only
+    assert s["prep"] == {"prepared": 3, "online_only": 2}
     # ids of resident layers are refused, never taken over
     assert s["dupes"] == {"refused": 3, "resident": 2}
     # overload with room to spare: batches fill to the limit, every slot in use, nothing evicted
