@@ -302,12 +302,16 @@ ct_status ct_stage_times(ct_ctx *ctx, ct_stage_time *out, int max, int *count);
  *   CT_TILE_LDS_*: operand digit tiles copied global -> LDS, one K slice
  *     ahead, fragments read from LDS (a workgroup barrier per K slice).
  *   CT_TILE_REGS_*: every wavefront loads its digit fragments from global
- *     memory into registers one K slice ahead; no LDS, no barriers. */
+ *     memory into registers one K slice ahead; no LDS, no barriers.
+ *   CT_TILE_REGS_FIT: register-streamed, one 32 x 32 tile per wavefront, the
+ *     workgroup tile chosen per layer from 64 x 64, 32 x 128 and 128 x 32 as
+ *     the one with the fewest padded outputs (64 x 64 on ties). */
 #define CT_TILE_AUTO 0
 #define CT_TILE_LDS_64x64 1
 #define CT_TILE_LDS_128x64 2
 #define CT_TILE_REGS_64x64 3
 #define CT_TILE_REGS_128x64 4
+#define CT_TILE_REGS_FIT 5
 
 /* Launch configuration of the matrix-core products. */
 typedef struct {
@@ -327,8 +331,8 @@ typedef struct {
  * each), and keeps the fastest for this shape class -- the protocol and the
  * rounded-up binary logarithms of M, K, N of every matrix-core layer.  The
  * candidates are a coordinate descent from the current configuration: the
- * tile shape and kernel (CT_TILE_LDS_64x64, CT_TILE_REGS_64x64, and for
- * k = s = 32 also the 128 x 64 shapes), then split_target in 0, 16, 32, 64,
+ * tile shape and kernel (CT_TILE_LDS_64x64, CT_TILE_REGS_64x64,
+ * CT_TILE_REGS_FIT, and for k = s = 32 also the 128 x 64 shapes), then split_target in 0, 16, 32, 64,
  * 128, xcd_remap in 0, 1, 4, 8, 16 and group_m in 1, 2, 4, 8, 16, 64, each
  * under the best so far, then the tile shape again.  Later calls of the same
  * class use the choice.  Synchronizes; allocates the timing event pool if

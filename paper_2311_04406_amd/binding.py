@@ -90,8 +90,8 @@ class CtTuning(ctypes.Structure):
 
 
 # product kernel and workgroup tile shape (CT_TILE_*)
-TILE_AUTO, TILE_LDS_64x64, TILE_LDS_128x64, TILE_REGS_64x64, TILE_REGS_128x64 = 0, 1, 2, 3, 4
-TILE_NAMES = {0: "auto", 1: "lds_64x64", 2: "lds_128x64", 3: "regs_64x64", 4: "regs_128x64"}
+TILE_AUTO, TILE_LDS_64x64, TILE_LDS_128x64, TILE_REGS_64x64, TILE_REGS_128x64, TILE_REGS_FIT = 0, 1, 2, 3, 4, 5
+TILE_NAMES = {0: "auto", 1: "lds_64x64", 2: "lds_128x64", 3: "regs_64x64", 4: "regs_128x64", 5: "regs_fit"}
 
 
 class CtCheckResult(ctypes.Structure):

@@ -421,7 +421,20 @@ int gemm_mt(const std::vector<GemmProb> &probs, int num_cus, const GemmTuning &t
     return tiles128 >= 2LL * num_cus ? 2 : 1;
 }
 int gemm_kernel(const GemmTuning &tu) {
-    return tu.tile == CT_TILE_REGS_64x64 || tu.tile == CT_TILE_REGS_128x64 ? GEMM_REGS : GEMM_LDS;
+    return tu.tile == CT_TILE_REGS_64x64 || tu.tile == CT_TILE_REGS_128x64 || tu.tile == CT_TILE_REGS_FIT
+               ? GEMM_REGS
+               : GEMM_LDS;
+}
+
+// CT_TILE_REGS_FIT: the workgroup tile of a product with the fewest padded
+// outputs, 64 x 64 on ties (its four wavefronts share two left and two right
+// fragments; the narrow shapes read five).
+int fit_wshape(int M, int N) {
+    auto padded = [&](int wm, int wn) { return (int64_t)((M + wm - 1) / wm * wm) * ((N + wn - 1) / wn * wn); };
+    const int64_t sq = padded(64, 64), wide = padded(32, 128), tall = padded(128, 32);
+    if (wide < sq && wide <= tall) return WS_32x128;
+    if (tall < sq) return WS_128x32;
+    return WS_64x64;
 }
 
 int plan_gemms(std::vector<GemmProb> &probs, int num_cus, const GemmTuning &tu, int *total_tiles, bool *any_accum,
@@ -430,8 +443,11 @@ int plan_gemms(std::vector<GemmProb> &probs, int num_cus, const GemmTuning &tu, 
     int64_t total_steps = 0;
     for (auto &p : probs) {
         p.mt = mt;
-        p.tiles_m = (p.M + 64 * mt - 1) / (64 * mt);
-        p.tiles_n = (p.N + 63) / 64;
+        p.wshape = tu.tile == CT_TILE_REGS_FIT ? fit_wshape(p.M, p.N) : WS_64x64;
+        const int wgm = p.wshape == WS_32x128 ? 32 : p.wshape == WS_128x32 ? 128 : 64 * mt;
+        const int wgn = p.wshape == WS_32x128 ? 128 : p.wshape == WS_128x32 ? 32 : 64;
+        p.tiles_m = (p.M + wgm - 1) / wgm;
+        p.tiles_n = (p.N + wgn - 1) / wgn;
         p.kt = (p.K + 31) / 32;
         p.nsteps = p.kt * (p.Lp2 ? 2 : 1);
         p.group_m = std::max(1, std::min(tu.group_m, p.tiles_m));
@@ -1166,7 +1182,7 @@ ct_status ct_set_timing(ct_ctx *c, int enable) {
 ct_status ct_set_tuning(ct_ctx *c, const ct_tuning *t) {
     if (!c || !t) return CT_EINVAL;
     if (t->group_m < 1 || t->split_target < 0 || t->split_target > MAX_STEPS_PER_SPLIT || t->xcd_remap < 0 ||
-        t->xcd_remap > 4096 || t->tile < CT_TILE_AUTO || t->tile > CT_TILE_REGS_128x64)
+        t->xcd_remap > 4096 || t->tile < CT_TILE_AUTO || t->tile > CT_TILE_REGS_FIT)
         return fail(c, CT_EINVAL, "invalid tuning");
     c->fallback = GemmTuning{t->group_m, t->xcd_remap, t->split_target, t->tile};
     c->tuned.clear();
@@ -1197,8 +1213,9 @@ ct_status ct_autotune(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_
     static const int groups[] = {1, 2, 4, 8, 16, 64};
     static const int splits[] = {0, 16, 32, 64, 128};
     static const int remaps[] = {0, 1, 4, 8, 16};
-    static const int tiles64[] = {CT_TILE_LDS_64x64, CT_TILE_REGS_64x64};
-    static const int tiles32[] = {CT_TILE_LDS_64x64, CT_TILE_REGS_64x64, CT_TILE_LDS_128x64, CT_TILE_REGS_128x64};
+    static const int tiles64[] = {CT_TILE_LDS_64x64, CT_TILE_REGS_64x64, CT_TILE_REGS_FIT};
+    static const int tiles32[] = {CT_TILE_LDS_64x64, CT_TILE_REGS_64x64, CT_TILE_REGS_FIT, CT_TILE_LDS_128x64,
+                                  CT_TILE_REGS_128x64};
     GemmTuning best = c->fallback;
     if (best.tile == CT_TILE_AUTO) best.tile = CT_TILE_LDS_64x64;
     double best_ms = 1e30;
@@ -1228,7 +1245,7 @@ ct_status ct_autotune(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_
     // workgroup tile shape, the K split, the XCD mapping, the tile order;
     // then the tile shape once more under the chosen rest
     const int *tl = c->eb == 8 ? tiles32 : tiles64;
-    const int ntl = c->eb == 8 ? 4 : 2;
+    const int ntl = c->eb == 8 ? 5 : 3;
     s = trial(best);
     for (int pass = 0; pass < 2 && s == CT_OK; pass++) {
         for (int i = 0; i < ntl && s == CT_OK; i++)

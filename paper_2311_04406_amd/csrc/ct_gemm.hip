@@ -630,10 +630,26 @@ template <class R, int MT>
 __device__ __forceinline__ void gemm_tile_rs(const GemmProb &P, int tm, int tn, int split) {
     constexpr int NB = Tile<R>::NB, OPB = Tile<R>::OPB;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
     const int s_begin = split * P.steps_per_split;
     const int s_end = min(s_begin + P.steps_per_split, P.nsteps);
     const int mtiles = (P.M + 63) / 64;  // row tiles of the packed left operand
+
+    // The wavefront's place in the workgroup tile (WaveShape; MT stacked
+    // tiles only as 2 x 2) and its first output row r0 and column c0.  A
+    // wavefront whose outputs all lie past M or N has nothing to store and
+    // leaves (this kernel has no barriers).
+    int r0, c0;
+    if (MT == 1 && P.wshape == WS_32x128) {
+        r0 = tm * 32;
+        c0 = tn * 128 + 32 * wave;
+    } else if (MT == 1 && P.wshape == WS_128x32) {
+        r0 = tm * 128 + 32 * wave;
+        c0 = tn * 32;
+    } else {
+        r0 = tm * 64 * MT + 32 * MT * (wave >> 1);
+        c0 = tn * 64 + 32 * (wave & 1);
+    }
+    if (r0 >= P.M || c0 >= P.N) return;
 
     v16i acc[MT][NB];
 #pragma unroll
@@ -643,20 +659,20 @@ __device__ __forceinline__ void gemm_tile_rs(const GemmProb &P, int tm, int tn, 
 
     // Lane -> row (column) lane % 32 of the wavefront's 32, 16-byte k half
     // lane / 32 (rows swap their halves as k_pack lays them out).  Output
-    // tile h has rows 32 (MT wm + h) + lane % 32 of the workgroup's 64 MT,
-    // i.e. rows of left tile q = (MT wm + h) / 2; a missing last left tile
-    // (M past its rows) is read from the first one, whose products are
-    // then not stored.
+    // tile h has rows r0 + 32 h + lane % 32, i.e. rows of packed left tile
+    // a_q[h]; a missing last left tile (M past its rows) is read from the
+    // first one, whose products are then not stored.  Columns c0 + lane % 32
+    // lie in packed right tile c0 / 64.
     const int chunk = lane >> 5;
     int a_off[MT], a_q[MT];
 #pragma unroll
     for (int h = 0; h < MT; h++) {
-        const int r = 32 * (MT * wm + h) + (lane & 31), lr = r & 63;
-        a_q[h] = tm * MT + (r >> 6) < mtiles ? (r >> 6) : 0;
+        const int r = r0 + 32 * h, lr = (r & 63) + (lane & 31);
+        a_q[h] = (r >> 6) < mtiles ? (r >> 6) : 0;
         a_off[h] = lr * BK + ((chunk ^ half_swap(lr)) << 4);
     }
-    const int brow = wn * 32 + (lane & 31);
-    const int b_off = brow * BK + ((chunk ^ half_swap(brow)) << 4);
+    const int b_q = c0 >> 6, lc = (c0 & 63) + (lane & 31);
+    const int b_off = lc * BK + ((chunk ^ half_swap(lc)) << 4);
 
     // digit tiles of step st (a K slice of the first or second segment)
     auto tiles = [&](int st, tile_rsrc (&at)[MT], tile_rsrc &bt) {
@@ -665,8 +681,8 @@ __device__ __forceinline__ void gemm_tile_rs(const GemmProb &P, int tm, int tn, 
         const uint8_t *Rp = reinterpret_cast<const uint8_t *>(seg ? P.Rp2 : P.Rp1);
 #pragma unroll
         for (int h = 0; h < MT; h++)
-            at[h] = tile_buffer<R>(uniform_ptr(Lp + ((int64_t)(tm * MT + a_q[h]) * P.kt + ks) * OPB));
-        bt = tile_buffer<R>(uniform_ptr(Rp + ((int64_t)tn * P.kt + ks) * OPB));
+            at[h] = tile_buffer<R>(uniform_ptr(Lp + ((int64_t)a_q[h] * P.kt + ks) * OPB));
+        bt = tile_buffer<R>(uniform_ptr(Rp + ((int64_t)b_q * P.kt + ks) * OPB));
     };
 
     // fragments of two consecutive slices: fa[c], fb[c] hold slice s while
@@ -692,7 +708,7 @@ __device__ __forceinline__ void gemm_tile_rs(const GemmProb &P, int tm, int tn, 
     }
     if (nsl > 0 && (nsl & 1))
         rs_slice<R, MT, D>(fa[0], fb[0], fa[1], fb[1], t0, b0t, t0, b0t, a_off, b_off, acc);
-    store_tile_out<R, MT>(P, acc, tm * 64 * MT, tn * BN, wm, wn, lane);
+    store_tile_out<R, MT>(P, acc, r0, c0, 0, 0, lane);
 }
 
 // One workgroup per output tile (grid = total_tiles): a loop over tiles

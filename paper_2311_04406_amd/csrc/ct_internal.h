@@ -293,7 +293,15 @@ struct GemmProb {
     int32_t gsize;    //   share M, N, K and splits and are interleaved in the tile order)
     int32_t mt;       // 32 x 32 output tiles per wavefront, stacked in M (the same for every
                       // problem of a launch): workgroup tiles of 64 mt x 64 outputs
+    int32_t wshape;   // WaveShape of the workgroup tile (register-streamed kernel, mt = 1)
 };
+
+// Arrangement of the four wavefronts of a register-streamed workgroup at one
+// 32 x 32 output tile each: 2 x 2 (64 x 64 outputs), 1 x 4 (32 x 128) or
+// 4 x 1 (128 x 32).  The wavefronts load their fragments independently, so
+// any arrangement reads the same packed operand tiles; the narrow ones pad a
+// product's M (or N) to 32 instead of 64.
+enum WaveShape : int { WS_64x64 = 0, WS_32x128 = 1, WS_128x32 = 2 };
 
 // Product kernels: operand tiles staged through LDS, or fragments streamed
 // from global memory into registers.

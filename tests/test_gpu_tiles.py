@@ -11,7 +11,7 @@ import torch
 import oracle as O
 from gpu_util import compare_cs, compare_layer, free, gpu_layers, oracle_run, say
 from paper_2311_04406_amd.binding import (RESULT_WORDS, TILE_LDS_128x64, TILE_LDS_64x64, TILE_REGS_128x64,
-                                          TILE_REGS_64x64)
+                                          TILE_REGS_64x64, TILE_REGS_FIT)
 
 pytestmark = pytest.mark.gpu
 KEY = 7
@@ -24,14 +24,17 @@ class Spec:
         self.name = f"{M}x{K}x{N}"
 
 
-# (spec, split_target): 0 = no forced split; 8 slices of 32 force K splits
-SHAPES = [(Spec(200, 300, 150, 31, 1), 0),     # ragged M (128-row: 128 + 72), N and K
-          (Spec(192, 96, 70, 32, 2), 0),       # 128-row tiles: one full, one lone 64-row tail
-          (Spec(130, 1000, 65, 33, 3), 8),     # 2 rows past a 128 tile; K = 1000 in 4 splits
-          (Spec(64, 2048, 128, 34, 4), 8),     # one 64-row tile; 8 splits
-          (Spec(33, 257, 9, 35, 5), 0)]        # smallest matrix-core N
-TILES = {64: [TILE_LDS_64x64, TILE_REGS_64x64, TILE_LDS_128x64, TILE_REGS_128x64],
-         32: [TILE_LDS_64x64, TILE_REGS_64x64, TILE_LDS_128x64, TILE_REGS_128x64]}
+# (spec, split_target): 0 = no forced split; 8 slices of 32 force K splits.
+# The fitted workgroup tile (TILE_REGS_FIT) of each shape is noted.
+SHAPES = [(Spec(200, 300, 150, 31, 1), 0),     # ragged M (128-row: 128 + 72), N and K; fit 128 x 32
+          (Spec(192, 96, 70, 32, 2), 0),       # 128-row tiles: one full, one lone 64-row tail; fit 64 x 64
+          (Spec(130, 1000, 65, 33, 3), 8),     # 2 rows past a 128 tile; K = 1000 in 4 splits; fit 32 x 128
+          (Spec(64, 2048, 128, 34, 4), 8),     # one 64-row tile; 8 splits; fit 64 x 64
+          (Spec(33, 257, 9, 35, 5), 0),        # smallest matrix-core N; fit 64 x 64
+          (Spec(90, 200, 250, 38, 8), 0),      # fit 32 x 128: ragged 32-row and 128-column tiles
+          (Spec(250, 70, 90, 39, 9), 8)]       # fit 128 x 32, K in 3 slices (no split)
+ALL = [TILE_LDS_64x64, TILE_REGS_64x64, TILE_REGS_FIT, TILE_LDS_128x64, TILE_REGS_128x64]
+TILES = {64: ALL, 32: ALL}
 
 
 @pytest.fixture(scope="module", params=[64, 32])
@@ -69,7 +72,7 @@ def test_autotune_names_a_tile_shape(ctx):
     layers = gpu_layers(ctx, [spec])
     ctx.gen_triple_tags(layers)
     t = ctx.autotune(O.MODE_COMPACT, layers, reps=1)
-    assert t["tile"] in ("lds_64x64", "regs_64x64", "lds_128x64", "regs_128x64"), t
+    assert t["tile"] in ("lds_64x64", "regs_64x64", "regs_fit", "lds_128x64", "regs_128x64"), t
     assert t["gemm_ms"] > 0
     assert ctx.get_tuning(O.MODE_COMPACT, layers)["tile"] == t["tile"]
     ol = oracle_run(O.MODE_COMPACT, spec, KEY, kbits=ctx.kbits)
