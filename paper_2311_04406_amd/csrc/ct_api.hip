@@ -273,7 +273,7 @@ Sizes max_sizes(const ct_layer_desc *L, int n) {
         if (d.conv_c > 0 && !CT_COMPRESS_ALONG_M(d.M, d.N, d.compress)) {
             // compression of the implicit im2col matrices along N
             s.conv_n = true;
-            s.conv_items = std::max(s.conv_items, sweep_items(d.K, d.N));
+            s.conv_items = std::max(s.conv_items, conv_compress_items(d.conv_c, d.N));
         }
         if (CT_COMPRESS_ALONG_M(d.M, d.N, d.compress)) {
             // column-strip row pass, column sweeps of the M x N pass and of the compact products

@@ -90,6 +90,26 @@ __device__ __forceinline__ void atomic_add128(u128 *p, u128 v) {
     if (hi) atomicAdd(q + 1, hi);
 }
 
+// atomic_add128 of NV values into the cells p[i] with ok[i] set, the NV
+// low-limb atomics in flight together before the first carry is formed (the
+// empty asm keeps the compiler from merging each cell's two conditional
+// blocks, which would wait for every atomic in turn).
+template <int NV>
+__device__ __forceinline__ void atomic_add128_n(u128 *const (&p)[NV], const u128 (&v)[NV], const bool (&ok)[NV]) {
+    unsigned long long old[NV];
+#pragma unroll
+    for (int i = 0; i < NV; i++) {
+        old[i] = 0;
+        if (ok[i]) old[i] = atomicAdd(reinterpret_cast<unsigned long long *>(p[i]), (unsigned long long)v[i].lo);
+    }
+    __asm__ volatile("" ::: "memory");
+#pragma unroll
+    for (int i = 0; i < NV; i++) {
+        const unsigned long long hi = v[i].hi + (old[i] + v[i].lo < old[i] ? 1ull : 0ull);
+        if (ok[i] && hi) atomicAdd(reinterpret_cast<unsigned long long *>(p[i]) + 1, hi);
+    }
+}
+
 // ---------------------------------------------------------------- generator
 // SplitMix64 (Steele, Lea, Flood, OOPSLA 2014), counter form: the i-th draw of
 // a stream with key `key` is mix(key + (i + 1) * golden gamma).
@@ -143,6 +163,12 @@ __device__ __forceinline__ void atomic_add_limbs(unsigned long long *cell, r64 v
 __device__ __forceinline__ void from_limbs(const unsigned long long *cell, r64 &v) { v = r64{cell[0] + (cell[1] << 32)}; }
 __device__ __forceinline__ void atomic_add128(r64 *p, r64 v) {
     atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v.v);
+}
+template <int NV>
+__device__ __forceinline__ void atomic_add128_n(r64 *const (&p)[NV], const r64 (&v)[NV], const bool (&ok)[NV]) {
+#pragma unroll
+    for (int i = 0; i < NV; i++)
+        if (ok[i]) atomicAdd(reinterpret_cast<unsigned long long *>(p[i]), (unsigned long long)v[i].v);
 }
 __device__ __forceinline__ r64 shfl_xor128(r64 v, int m) { return r64{__shfl_xor(v.v, m, 64)}; }
 __device__ __forceinline__ r64 wave_sum(r64 v) {

@@ -358,32 +358,58 @@ __device__ __forceinline__ void group_products(int T, const v4i (&a)[MT][NB], co
                 acc[h][i + T] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[h][i], b[T], acc[h][i + T], 0, 0, 0);
 }
 
+// Adds v into out[idx] exactly mod 2^{k+s} for the outputs with ok set, all
+// 16 atomics of a lane in flight together (an output out of range issues
+// nothing).
+template <class R>
+__device__ __forceinline__ void add_outputs(R *out, const int64_t (&idx)[16], const bool (&ok)[16], const R (&v)[16]) {
+    R *cell[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) cell[r] = out + idx[r];
+    atomic_add128_n<16>(cell, v, ok);
+}
+
 // Epilogue of a wavefront's MT output tiles: the 32x32 accumulator layout
 // gives lane l, register r row 8*(r/4) + 4*(l/32) + r%4 and column l%32 of
 // an output tile; each output is sum_t 2^{8t} S_t plus the base (or added
-// atomically to the output when the product's K range is split).
+// atomically to the output when the product's K range is split).  A lane's
+// 16 outputs of a tile are formed first and their base loads (or atomics)
+// issued together, so the wavefront waits for memory once per tile rather
+// than once per output.
 template <class R, int MT>
 __device__ __forceinline__ void store_tile_out(const GemmProb &P, const v16i (&acc)[MT][Tile<R>::NB], int m0, int n0,
                                                int wm, int wn, int lane) {
     const int M = P.M, N = P.N;
     const int col = n0 + wn * 32 + (lane & 31);
     R *out = reinterpret_cast<R *>(P.out);
+    const R *base = reinterpret_cast<const R *>(P.base);
 #pragma unroll
     for (int h = 0; h < MT; h++) {
+        const int row0 = m0 + 32 * (MT * wm + h) + 4 * (lane >> 5);
+        R v[16];
+        int64_t idx[16];
+        bool ok[16];
 #pragma unroll
         for (int r = 0; r < 16; r++) {
-            const int row = m0 + 32 * (MT * wm + h) + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            R v = Ring<R>::zero();
-            combine<0>(acc[h], r, v);
-            if (row < M && col < N) {
-                const int64_t idx = (int64_t)row * N + col;
-                if (P.accumulate) {
-                    atomic_add128(out + idx, v);
-                } else {
-                    if (P.base) v = add(v, ld(reinterpret_cast<const R *>(P.base), idx));
-                    st(out, idx, v);
-                }
+            const int row = row0 + 8 * (r >> 2) + (r & 3);
+            ok[r] = row < M && col < N;
+            idx[r] = (int64_t)row * N + col;
+            v[r] = Ring<R>::zero();
+            combine<0>(acc[h], r, v[r]);
+        }
+        if (P.accumulate) {
+            add_outputs(out, idx, ok, v);
+        } else {
+            if (base) {
+                R b[16];
+#pragma unroll
+                for (int r = 0; r < 16; r++) b[r] = ok[r] ? ld(base, idx[r]) : Ring<R>::zero();
+#pragma unroll
+                for (int r = 0; r < 16; r++) v[r] = add(v[r], b[r]);
             }
+#pragma unroll
+            for (int r = 0; r < 16; r++)
+                if (ok[r]) st(out, idx[r], v[r]);
         }
     }
 }

@@ -379,4 +379,8 @@ inline int64_t sweep_items(int64_t rows, int64_t N) {
     return rows * ((N + 511) / 512);
 }
 
+// Workgroup items of k_conv_compress: (input channel, segment of 512 output
+// positions) of a convolution with c input channels and N output positions.
+inline int64_t conv_compress_items(int64_t c, int64_t N) { return c * ((N + 511) / 512); }
+
 }  // namespace ct

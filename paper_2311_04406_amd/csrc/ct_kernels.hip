@@ -234,32 +234,63 @@ __global__ __launch_bounds__(TPB) void k_open_u(const LayerDev *__restrict__ Ls,
 // Fig. 4, with the right operand of Eq. (4)): for row k = (c, dy, dx),
 //   U^c_k = sum_n chi_n U[c, y s + dy - p, x s + dx - p]   (n = y Wo + x),
 // and [tB^c]_p alike -- a k x k correlation of the input with chi laid out as
-// an Ho x Wo image.  The gathered input elements of neighbouring n and k are
-// the same few cache lines, so the input is read from HBM about once.
+// an Ho x Wo image.  Work items are (channel c, segment of CONV_SEG positions
+// n), one workgroup of CONV_WAVES wavefronts each; the wavefronts share out
+// the k x k rows (c, dy, dx) of the channel (three each for a 3 x 3 window),
+// so the input rows under the segment and the window's halo are fetched once
+// into the compute unit's caches and read there by all k^2 rows.  (Rows
+// taken as independent wavefront items went round-robin over the XCDs, each
+// of whose L2s fetched the same input lines: 6.5x the input's bytes.)
+constexpr int CONV_SEG = 512;
+constexpr int CONV_WAVES = 3;
 template <class R>
 __global__ __launch_bounds__(TPB) void k_conv_compress(const LayerDev *__restrict__ Ls) {
     const LayerDev &L = Ls[blockIdx.y];
     if (!L.cv.on || L.cm) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const CvecOff o = cvec_off(L.M, L.K);
     const uint64_t kchi = L.key[K_CHI];
-    auto elem = [&](int64_t r, int64_t c, R (&v)[3]) {
-        const int64_t g = conv_src(L.cv, (int32_t)r, (int32_t)c);
-        if (g < 0) return;
-        const uint64_t x = Ring<R>::mod_s(sdraw(kchi, (uint64_t)c));
-        v[0] = mad64(v[0], ld(P<R>(L.U), g), x);
-        v[1] = mad64(v[1], ld(P<R>(L.tB[0]), g), x);
-        v[2] = mad64(v[2], ld(P<R>(L.tB[1]), g), x);
-    };
-    auto row_done = [&](int64_t r, R (&v)[3]) {
-        atomic_add128(P<R>(L.cvec) + o.Uc + r, v[0]);
-        atomic_add128(P<R>(L.cvec) + o.tBc0 + r, v[1]);
-        atomic_add128(P<R>(L.cvec) + o.tBc1 + r, v[2]);
-    };
-    row_sweep<R, 3>(L.K, L.N, elem, row_done);
+    const int N = (int)L.N, kk = L.cv.k * L.cv.k;
+    const int segs = (N + CONV_SEG - 1) / CONV_SEG;
+    const int64_t items = (int64_t)L.cv.c * segs;
+    constexpr int J = CONV_SEG / 64;  // positions per lane and segment
+    R *cv = P<R>(L.cvec);
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const int ch = (int)(it / segs), n0 = (int)(it - (int64_t)ch * segs) * CONV_SEG;
+        uint64_t chi[J];
+#pragma unroll
+        for (int j = 0; j < J; j++) {
+            const int n = n0 + 64 * j + lane;
+            chi[j] = n < N ? Ring<R>::mod_s(sdraw(kchi, (uint64_t)n)) : 0;
+        }
+        for (int t = wave; t < kk; t += CONV_WAVES) {
+            const int32_t k = ch * kk + t;
+            R v[3] = {Ring<R>::zero(), Ring<R>::zero(), Ring<R>::zero()};
+#pragma unroll
+            for (int j = 0; j < J; j++) {
+                const int n = n0 + 64 * j + lane;
+                const int64_t g = n < N ? conv_src(L.cv, k, n) : -1;
+                if (g >= 0) {
+                    v[0] = mad64(v[0], ld(P<R>(L.U), g), chi[j]);
+                    v[1] = mad64(v[1], ld(P<R>(L.tB[0]), g), chi[j]);
+                    v[2] = mad64(v[2], ld(P<R>(L.tB[1]), g), chi[j]);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 3; i++) v[i] = wave_sum(v[i]);
+            if (lane == 0) {
+                R *const cell[3] = {cv + o.Uc + k, cv + o.tBc0 + k, cv + o.tBc1 + k};
+                const bool ok[3] = {true, true, true};
+                atomic_add128_n<3>(cell, v, ok);
+            }
+        }
+    }
 }
 
 hipError_t launch_conv_compress(int eb, const LayerDev *L, int n, int64_t max_items, hipStream_t st) {
-    LAUNCH_RING(eb, k_conv_compress, dim3(grid_items(max_items), n), dim3(TPB), st, L);
+    // one workgroup per (channel, segment) item
+    const int gx = (int)std::min<int64_t>(std::max<int64_t>(max_items, 1), 16384);
+    LAUNCH_RING(eb, k_conv_compress, dim3(gx, n), dim3(64 * CONV_WAVES), st, L);
     return hipGetLastError();
 }
 
