@@ -321,6 +321,12 @@ __device__ __forceinline__ void row_pass_cm(const LayerDev &L, int flags, R (&ch
     R *AE0 = P<R>(L.work);
     constexpr int CM_CW = cm_cw_variant(NS);
     const int64_t strips = cm_strips(K, CM_CW), items = cm_items(M, K, N);
+    // output products of the item's rows (N <= SKINNY_MAX_N), per wavefront:
+    // added at the end of the item, all rows' atomics in flight together
+    constexpr int NSX = NS > 0 ? NS : 1;
+    static_assert(CM_RB <= 64, "one lane per row of an item");
+    __shared__ R zsh[WAVES * CM_RB * 2 * NSX];
+    R *zrow = zsh + (threadIdx.x >> 6) * (CM_RB * 2 * NSX);
     const int64_t wave_id = (blockIdx.x * (int64_t)TPB + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * TPB) >> 6;
     for (int64_t it = wave_id; it < items; it += nwaves) {
@@ -383,11 +389,30 @@ __device__ __forceinline__ void row_pass_cm(const LayerDev &L, int flags, R (&ch
                         z0[j] = wave_sum(z0[j]);
                         z1[j] = wave_sum(z1[j]);
                         if (lane == 0) {
-                            atomic_add128(P<R>(L.Z[0]) + m * N + j, z0[j]);
-                            atomic_add128(P<R>(L.Z[1]) + m * N + j, z1[j]);
+                            zrow[(m - m0) * 2 * NSX + 2 * j] = z0[j];
+                            zrow[(m - m0) * 2 * NSX + 2 * j + 1] = z1[j];
                         }
                     }
                 }
+            }
+        }
+        if constexpr (NS > 0) {
+            // lane r adds row m0 + r's products (written to LDS by lane 0 of
+            // this wavefront, earlier in its own instruction order)
+            const int64_t m = m0 + lane;
+            if (m < m1) {
+                R *cell[2 * NS];
+                R val[2 * NS];
+                bool ok[2 * NS];
+#pragma unroll
+                for (int j = 0; j < NS; j++) {
+                    cell[2 * j] = P<R>(L.Z[0]) + m * N + j;
+                    cell[2 * j + 1] = P<R>(L.Z[1]) + m * N + j;
+                    val[2 * j] = zrow[lane * 2 * NSX + 2 * j];
+                    val[2 * j + 1] = zrow[lane * 2 * NSX + 2 * j + 1];
+                    ok[2 * j] = ok[2 * j + 1] = j < N;
+                }
+                atomic_add128_n<2 * NS>(cell, val, ok);
             }
         }
 #pragma unroll
@@ -557,8 +582,12 @@ __global__ __launch_bounds__(TPB) void k_row_pass(const LayerDev *__restrict__ L
         wave_accumulate_limbs<3>(chk, rp_cells<R>(L) + 12 * (((blockIdx.x * TPB + threadIdx.x) >> 6) % RP_COPIES));
 }
 
+// Three workgroups per compute unit (at most 168 registers) for the 128-bit
+// single-output variant, the classifier's: the pass is bound by HBM and a
+// third wavefront per SIMD keeps more loads in flight.
 template <class R, int NS>
-__global__ __launch_bounds__(TPB) void k_row_pass_cm(const LayerDev *__restrict__ Ls, int flags) {
+__global__ __launch_bounds__(TPB, (sizeof(R) == 16 && NS == 1) ? 3 : 1) void k_row_pass_cm(
+    const LayerDev *__restrict__ Ls, int flags) {
     const LayerDev &L = Ls[blockIdx.y];
     if (row_variant(L.N) != NS || !L.cm) return;
     R chk[3] = {Ring<R>::zero(), Ring<R>::zero(), Ring<R>::zero()};
