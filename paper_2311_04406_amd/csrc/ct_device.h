@@ -90,6 +90,14 @@ __device__ __forceinline__ void atomic_add128(u128 *p, u128 v) {
     if (hi) atomicAdd(q + 1, hi);
 }
 
+// Orders a wavefront's LDS writes before its later LDS reads by other lanes
+// of the same wavefront (a compiler and memory fence at wavefront scope).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // atomic_add128 of NV values into the cells p[i] with ok[i] set, the NV
 // low-limb atomics in flight together before the first carry is formed (the
 // empty asm keeps the compiler from merging each cell's two conditional
@@ -108,6 +116,20 @@ __device__ __forceinline__ void atomic_add128_n(u128 *const (&p)[NV], const u128
         const unsigned long long hi = v[i].hi + (old[i] + v[i].lo < old[i] ? 1ull : 0ull);
         if (ok[i] && hi) atomicAdd(reinterpret_cast<unsigned long long *>(p[i]) + 1, hi);
     }
+}
+
+// atomic_add128 of v[i] into cell base[off[i] + at] for every i < NV, in
+// flight together.
+template <int NV, class R>
+__device__ __forceinline__ void add_cells(R *base, const int64_t (&off)[NV], int64_t at, const R (&v)[NV]) {
+    R *cell[NV];
+    bool ok[NV];
+#pragma unroll
+    for (int i = 0; i < NV; i++) {
+        cell[i] = base + off[i] + at;
+        ok[i] = true;
+    }
+    atomic_add128_n<NV>(cell, v, ok);
 }
 
 // ---------------------------------------------------------------- generator

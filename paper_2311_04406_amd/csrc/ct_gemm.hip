@@ -177,7 +177,7 @@ hipError_t launch_pack(int eb, const PackJob *jobs_dev, int njobs, int total_til
 // second time.  One workgroup per 64 (n) x 32 (k) tile, laid out as k_pack
 // lays out a right operand's tile: lane j takes column n = 64 tn + j,
 // wavefront w the 8 rows k = 32 ks + 8 w + i; the rows' compressions are
-// summed over the wavefront and added atomically, one per row and tile.
+// summed over the wavefront and added atomically, once per row and tile.
 template <class R>
 __device__ __forceinline__ void store_tile(uint8_t *tile, int off, const uint32_t (&w)[8][Tile<R>::NW], u128 *dst) {
     constexpr int OPB = Tile<R>::OPB;
@@ -242,11 +242,7 @@ __global__ __launch_bounds__(256) void k_open_pack(const LayerDev *__restrict__ 
         }
         if (compact && k < K) {  // k is the same for the whole wavefront
             const R v0 = wave_sum(mul64(u, xn)), v1 = wave_sum(mul64(tb0, xn)), v2 = wave_sum(mul64(tb1, xn));
-            if (lane == 0) {
-                atomic_add128(P<R>(L.cvec) + o.Uc + k, v0);
-                atomic_add128(P<R>(L.cvec) + o.tBc0 + k, v1);
-                atomic_add128(P<R>(L.cvec) + o.tBc1 + k, v2);
-            }
+            if (lane == 0) add_cells<3>(P<R>(L.cvec), {o.Uc, o.tBc0, o.tBc1}, k, {v0, v1, v2});
         }
         to_digits(b0, wb0[i]);
         to_digits(b1, wb1[i]);

@@ -204,11 +204,7 @@ __global__ __launch_bounds__(TPB) void k_open_u(const LayerDev *__restrict__ Ls,
         }
     };
     auto row_done = [&](int64_t r, R (&v)[3]) {
-        if (compact) {
-            atomic_add128(P<R>(L.cvec) + o.Uc + r, v[0]);
-            atomic_add128(P<R>(L.cvec) + o.tBc0 + r, v[1]);
-            atomic_add128(P<R>(L.cvec) + o.tBc1 + r, v[2]);
-        }
+        if (compact) add_cells<3>(P<R>(L.cvec), {o.Uc, o.tBc0, o.tBc1}, r, v);
     };
     if (L.cv.on) {
         // a convolution opens U on the input's elements; their compression
@@ -398,7 +394,8 @@ __device__ __forceinline__ void row_pass_cm(const LayerDev &L, int flags, R (&ch
         }
         if constexpr (NS > 0) {
             // lane r adds row m0 + r's products (written to LDS by lane 0 of
-            // this wavefront, earlier in its own instruction order)
+            // this wavefront)
+            wave_sync();
             const int64_t m = m0 + lane;
             if (m < m1) {
                 R *cell[2 * NS];
@@ -418,11 +415,7 @@ __device__ __forceinline__ void row_pass_cm(const LayerDev &L, int flags, R (&ch
 #pragma unroll
         for (int c = 0; c < CM_CW; c++) {
             const int64_t k = kb + 64 * c;
-            if (k < K) {
-                atomic_add128(P<R>(L.cvec) + o.Uc + k, ce[c]);
-                atomic_add128(P<R>(L.cvec) + o.tBc0 + k, ca0[c]);
-                atomic_add128(P<R>(L.cvec) + o.tBc1 + k, ca1[c]);
-            }
+            if (k < K) add_cells<3>(P<R>(L.cvec), {o.Uc, o.tBc0, o.tBc1}, k, {ce[c], ca0[c], ca1[c]});
         }
     }
 }
@@ -537,10 +530,11 @@ __device__ __forceinline__ void row_pass_body(const LayerDev &L, int flags, R (&
             for (int i = 0; i < 5; i++) cp[i] = wave_sum(cp[i]);
             if (lane == 0) {
                 // E U^c, and the partial compact tags (k_compact_final adds
-                // [tC^c]_p and [Delta]_p E U^c)
-                atomic_add128(P<R>(L.cvec) + o.EUc + m, cp[0]);
-                atomic_add128(P<R>(L.cvec) + o.tZc0 + m, add(cp[1], cp[3]));
-                atomic_add128(P<R>(L.cvec) + o.tZc1 + m, add(cp[2], cp[4]));
+                // [tC^c]_p and [Delta]_p E U^c); the three atomics in flight together
+                R *const cell[3] = {P<R>(L.cvec) + o.EUc + m, P<R>(L.cvec) + o.tZc0 + m, P<R>(L.cvec) + o.tZc1 + m};
+                const R val[3] = {cp[0], add(cp[1], cp[3]), add(cp[2], cp[4])};
+                const bool ok[3] = {true, true, true};
+                atomic_add128_n<3>(cell, val, ok);
             }
         }
         if constexpr (skinny) {
@@ -556,12 +550,11 @@ __device__ __forceinline__ void row_pass_body(const LayerDev &L, int flags, R (&
                     if (lane == 0) {
                         // onto [Z]_p = [C]_p (and [tZ]_p = [tC]_p) set by k_zero_acc
                         const int64_t mn = m * N + j;
-                        atomic_add128(P<R>(L.Z[0]) + mn, z0[j]);
-                        atomic_add128(P<R>(L.Z[1]) + mn, z1[j]);
-                        if (spdz) {
-                            atomic_add128(P<R>(L.tZ[0]) + mn, t0[j]);
-                            atomic_add128(P<R>(L.tZ[1]) + mn, t1[j]);
-                        }
+                        R *const cell[4] = {P<R>(L.Z[0]) + mn, P<R>(L.Z[1]) + mn, P<R>(L.tZ[0]) + mn,
+                                            P<R>(L.tZ[1]) + mn};
+                        const R val[4] = {z0[j], z1[j], t0[j], t1[j]};
+                        const bool ok[4] = {true, true, spdz, spdz};
+                        atomic_add128_n<4>(cell, val, ok);
                     }
                 }
             }
@@ -668,11 +661,7 @@ __global__ __launch_bounds__(TPB) void k_post(const LayerDev *__restrict__ Ls, i
         };
         // each sweep hands its partial sums for entry i (a row, or a column)
         auto done = [&](int64_t i, R (&v)[5]) {
-            atomic_add128(P<R>(L.cvec) + o.Dc + i, v[0]);
-            atomic_add128(P<R>(L.cvec) + o.tRc0 + i, v[1]);
-            atomic_add128(P<R>(L.cvec) + o.tRc1 + i, v[2]);
-            atomic_add128(P<R>(L.cvec) + o.tCc0 + i, v[3]);
-            atomic_add128(P<R>(L.cvec) + o.tCc1 + i, v[4]);
+            add_cells<5>(P<R>(L.cvec), {o.Dc, o.tRc0, o.tRc1, o.tCc0, o.tCc1}, i, v);
         };
         if (cm) col_sweep<R, 5>(M, N, elem, done);
         else row_sweep<R, 5>(M, N, elem, done);
@@ -720,11 +709,7 @@ __global__ __launch_bounds__(TPB) void k_col_tag(const LayerDev *__restrict__ Ls
         v[1] = mad(mad(v[1], ec, ld(P<R>(L.tB[0]), e)), ld(cv + o.tBc0, k), u);
         v[2] = mad(mad(v[2], ec, ld(P<R>(L.tB[1]), e)), ld(cv + o.tBc1, k), u);
     };
-    auto done = [&](int64_t n, R (&v)[3]) {
-        atomic_add128(cv + o.EUc + n, v[0]);
-        atomic_add128(cv + o.tZc0 + n, v[1]);
-        atomic_add128(cv + o.tZc1 + n, v[2]);
-    };
+    auto done = [&](int64_t n, R (&v)[3]) { add_cells<3>(cv, {o.EUc, o.tZc0, o.tZc1}, n, v); };
     col_sweep<R, 3>(L.K, N, elem, done);
 }
 
