@@ -322,21 +322,25 @@ typedef struct {
                               group share one XCD's L2 */
     int32_t split_target;  /* K slices of 32 per tile; 0 = as many tiles as fill the GPU twice */
     int32_t tile;          /* CT_TILE_*: product kernel and workgroup tile shape */
-    double gemm_ms;        /* ct_autotune: measured duration of the products per call */
+    double gemm_ms;        /* ct_autotune: measured duration of the products per call, with the copy
+                              of the constant terms into the outputs of K-split products */
 } ct_tuning;
 
 /* Autotuner: runs the online phase of this batch of layers (outputs written
  * as by ct_tag_linear) once per candidate launch configuration, times the
- * matrix-core products with HIP events (reps timed runs after one warm-up
+ * matrix-core products and the copy of the constant terms that K-split
+ * products need first, with HIP events (reps timed runs after one warm-up
  * each), and keeps the fastest for this shape class -- the protocol and the
  * rounded-up binary logarithms of M, K, N of every matrix-core layer.  The
  * candidates are a coordinate descent from the current configuration: the
  * tile shape and kernel (CT_TILE_LDS_64x64, CT_TILE_REGS_64x64,
- * CT_TILE_REGS_FIT, and for k = s = 32 also the 128 x 64 shapes), then split_target in 0, 16, 32, 64,
- * 128, xcd_remap in 0, 1, 4, 8, 16 and group_m in 1, 2, 4, 8, 16, 64, each
- * under the best so far, then the tile shape again.  Later calls of the same
- * class use the choice.  Synchronizes; allocates the timing event pool if
- * timing was never enabled.  best (may be NULL) receives the choice. */
+ * CT_TILE_REGS_FIT, and for k = s = 32 also the 128 x 64 shapes), then
+ * split_target in 0, 16, 32, 64, 128, xcd_remap in 0, 1, 4, 8, 16 and
+ * group_m in 1, 2, 4, 8, 16, 64, each under the best so far, then the tile
+ * shape again.  Later calls of the same class use the choice.  Synchronizes;
+ * allocates the timing event pool if timing was never enabled; the stage
+ * times of ct_stage_times are left as they were.  best (may be NULL)
+ * receives the choice. */
 ct_status ct_autotune(ct_ctx *ctx, ct_mode mode, const ct_layer_desc *L, const ct_layer_bufs *B, int n, int reps,
                       ct_tuning *best);
 

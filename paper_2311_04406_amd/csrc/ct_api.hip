@@ -1208,8 +1208,11 @@ ct_status ct_autotune(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_
     ct_status s = ct_set_timing(c, 1);
     if (s != CT_OK) return s;
     HIPCHK(c, fold_timing(c));
-    const double saved_ms = c->stage_ms[ST_RING_GEMM];
-    const int64_t saved_n = c->stage_n[ST_RING_GEMM];
+    // the trials' stage times are not the caller's: restored afterwards
+    double saved_ms[ST_COUNT];
+    int64_t saved_n[ST_COUNT];
+    std::copy(c->stage_ms, c->stage_ms + ST_COUNT, saved_ms);
+    std::copy(c->stage_n, c->stage_n + ST_COUNT, saved_n);
     static const int groups[] = {1, 2, 4, 8, 16, 64};
     static const int splits[] = {0, 16, 32, 64, 128};
     static const int remaps[] = {0, 1, 4, 8, 16};
@@ -1219,20 +1222,20 @@ ct_status ct_autotune(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_
     GemmTuning best = c->fallback;
     if (best.tile == CT_TILE_AUTO) best.tile = CT_TILE_LDS_64x64;
     double best_ms = 1e30;
-    // times the products under one candidate; keeps it if it is the fastest
+    // times the products under one candidate (with the copy of the constant
+    // terms that split products need first); keeps it if it is the fastest
     auto trial = [&](const GemmTuning &cand) -> ct_status {
         c->forcing = true;
         c->forced = cand;
         ct_status st = run_online(c, c->main, mode, L, B, n, nullptr);  // warm-up
         if (st == CT_OK) {
             HIPCHK(c, fold_timing(c));
-            c->stage_ms[ST_RING_GEMM] = 0;
-            c->stage_n[ST_RING_GEMM] = 0;
+            for (int k : {ST_RING_GEMM, ST_COPY_BASE}) c->stage_ms[k] = 0, c->stage_n[k] = 0;
             for (int r = 0; r < reps && st == CT_OK; r++) st = run_online(c, c->main, mode, L, B, n, nullptr);
         }
         if (st == CT_OK) {
             HIPCHK(c, fold_timing(c));
-            const double ms = c->stage_ms[ST_RING_GEMM] / reps;
+            const double ms = (c->stage_ms[ST_RING_GEMM] + c->stage_ms[ST_COPY_BASE]) / reps;
             if (c->stage_n[ST_RING_GEMM] > 0 && ms < best_ms) {
                 best_ms = ms;
                 best = cand;
@@ -1258,9 +1261,9 @@ ct_status ct_autotune(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_
         for (int g : groups)
             if (s == CT_OK && g != best.group_m) { GemmTuning t = best; t.group_m = g; s = trial(t); }
     }
+    std::copy(saved_ms, saved_ms + ST_COUNT, c->stage_ms);
+    std::copy(saved_n, saved_n + ST_COUNT, c->stage_n);
     if (s != CT_OK) return s;
-    c->stage_ms[ST_RING_GEMM] = saved_ms;
-    c->stage_n[ST_RING_GEMM] = saved_n;
     if (!was_timing) {
         c->timing = false;
     }
