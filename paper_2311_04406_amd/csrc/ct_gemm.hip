@@ -588,10 +588,12 @@ __global__ __launch_bounds__(256, 1) void k_ring_gemm(const GemmProb *__restrict
 // ---------------------------------------------------------------- products, register-streamed
 // The same products without LDS: every wavefront loads its own digit
 // fragments straight from the packed tiles in global memory into registers
-// (16 bytes per lane, 1 KB per fragment and wavefront, coalesced), one K
-// slice ahead: while product group T of slice s runs, fragment pair T of
-// slice s + 1 is loaded, so each load has a whole slice of products to land
-// and the wavefront never waits at a barrier.  The two wavefronts of a
+// (16 bytes per lane, 1 KB per fragment and wavefront, coalesced), half a
+// K slice ahead: before product group T of a slice runs, fragment pair
+// T + RS_PREFETCH is loaded (of this slice, or of the next once past its
+// end), so each load has half a slice of products to land and the wavefront
+// never waits at a barrier (a whole slice ahead kept more registers live
+// and measured 2-4% slower).  The two wavefronts of a
 // workgroup that share a row (or column) tile read the same fragment at about
 // the same time, so the second read is served by the compute unit's cache.
 // Registers: the NB diagonal accumulators of MT output tiles in AGPRs; the
@@ -604,7 +606,7 @@ __global__ __launch_bounds__(256, 1) void k_ring_gemm(const GemmProb *__restrict
 // read as zero instead of leaving it.
 typedef __amdgpu_buffer_rsrc_t tile_rsrc;
 #ifndef RS_PREFETCH
-#define RS_PREFETCH 16
+#define RS_PREFETCH 8
 #endif
 constexpr int RSRC_FLAGS = 0x00020000;  // gfx9 buffer resource word 3: 32-bit data format
 
