@@ -297,8 +297,8 @@ ct_status ct_stage_times(ct_ctx *ctx, ct_stage_time *out, int max, int *count);
  * wavefronts owns 64 x 64 outputs, or 128 x 64 with two 32 x 32 tiles per
  * wavefront, which only the k = s = 32 set has registers for (with
  * k = s = 64 the 128 x 64 shapes run as 64 x 64).
- *   CT_TILE_AUTO: LDS-staged; 128 x 64 for k = s = 32 when the launch has at
- *     least two such tiles per compute unit, else 64 x 64.
+ *   CT_TILE_AUTO: register-streamed; 128 x 64 for k = s = 32 when the launch
+ *     has at least two such tiles per compute unit, else 64 x 64.
  *   CT_TILE_LDS_*: operand digit tiles copied global -> LDS, one K slice
  *     ahead, fragments read from LDS (a workgroup barrier per K slice).
  *   CT_TILE_REGS_*: every wavefront loads its digit fragments from global

@@ -421,9 +421,7 @@ int gemm_mt(const std::vector<GemmProb> &probs, int num_cus, const GemmTuning &t
     return tiles128 >= 2LL * num_cus ? 2 : 1;
 }
 int gemm_kernel(const GemmTuning &tu) {
-    return tu.tile == CT_TILE_REGS_64x64 || tu.tile == CT_TILE_REGS_128x64 || tu.tile == CT_TILE_REGS_FIT
-               ? GEMM_REGS
-               : GEMM_LDS;
+    return tu.tile == CT_TILE_LDS_64x64 || tu.tile == CT_TILE_LDS_128x64 ? GEMM_LDS : GEMM_REGS;
 }
 
 // CT_TILE_REGS_FIT: the workgroup tile of a product with the fewest padded
@@ -1220,7 +1218,7 @@ ct_status ct_autotune(ct_ctx *c, ct_mode mode, const ct_layer_desc *L, const ct_
     static const int tiles32[] = {CT_TILE_LDS_64x64, CT_TILE_REGS_64x64, CT_TILE_REGS_FIT, CT_TILE_LDS_128x64,
                                   CT_TILE_REGS_128x64};
     GemmTuning best = c->fallback;
-    if (best.tile == CT_TILE_AUTO) best.tile = CT_TILE_LDS_64x64;
+    if (best.tile == CT_TILE_AUTO) best.tile = CT_TILE_REGS_64x64;
     double best_ms = 1e30;
     // times the products under one candidate (with the copy of the constant
     // terms that split products need first); keeps it if it is the fastest
