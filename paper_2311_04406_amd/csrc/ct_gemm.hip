@@ -398,7 +398,8 @@ __device__ __forceinline__ void add_outputs(R *out, const int64_t (&idx)[16], co
 // atomically to the output when the product's K range is split).  A lane's
 // 16 outputs of a tile are formed first and their base loads (or atomics)
 // issued together, so the wavefront waits for memory once per tile rather
-// than once per output.
+// than once per output.  Both streams are non-temporal: read and written
+// once here, they would only displace operand tiles from L2.
 template <class R, int MT>
 __device__ __forceinline__ void store_tile_out(const GemmProb &P, const v16i (&acc)[MT][Tile<R>::NB], int m0, int n0,
                                                int wm, int wn, int lane) {
@@ -426,13 +427,13 @@ __device__ __forceinline__ void store_tile_out(const GemmProb &P, const v16i (&a
             if (base) {
                 R b[16];
 #pragma unroll
-                for (int r = 0; r < 16; r++) b[r] = ok[r] ? ld(base, idx[r]) : Ring<R>::zero();
+                for (int r = 0; r < 16; r++) b[r] = ok[r] ? ld_nt(base, idx[r]) : Ring<R>::zero();
 #pragma unroll
                 for (int r = 0; r < 16; r++) v[r] = add(v[r], b[r]);
             }
 #pragma unroll
             for (int r = 0; r < 16; r++)
-                if (ok[r]) st(out, idx[r], v[r]);
+                if (ok[r]) st_nt(out, idx[r], v[r]);
         }
     }
 }
