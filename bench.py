@@ -384,7 +384,7 @@ def serving_run(torch, ctx, mode_id, rate: float, count: int, arena_bytes: int, 
 
 
 SERVE_RATES = (100, 200, 500, 1000, 2000, 5000)
-SERVE_ARENA = 96 << 30
+SERVE_ARENA = 192 << 30  # of the 288 GB: the request stream's layers (the classifier's are 14.8 GB)
 SERVE_SLOTS = 3
 SERVE_BATCH = 32
 
