@@ -171,7 +171,8 @@ typedef struct {
 
 /* Check-value shares of one layer: cs[W][p] for W = 0 (E), 1 (U), 2 (D) and
  * parties p < n (the other slots are 0).  accept = 1 iff sum_p cs[W][p] = 0
- * mod 2^{k+s} for all three W. */
+ * mod 2^{k+s} for all three W.  reserved is 0, except 1 when a persistent
+ * launch's barrier wait ran out (accept is then 0; see ct_set_launch). */
 typedef struct {
     ct_u128 cs[3][CT_MAX_PARTIES];
     int32_t accept;
@@ -280,6 +281,27 @@ ct_status ct_set_timing(ct_ctx *ctx, int enable);
  * the whole batch on the context stream (0: every kernel then runs alone,
  * as a per-kernel profile needs).  Results are the same either way. */
 ct_status ct_set_overlap(ct_ctx *ctx, int enable);
+
+/* How ct_tag_linear_check (and ct_tag_linear_check_static, and plans created
+ * afterwards) launch the online phase of a batch of two parties (Sec. 3.3:
+ * the layers of a batch are tagged and verified together).
+ *   CT_LAUNCH_STAGED (the default): one multi-layer kernel per stage, each
+ *     at the occupancy its registers allow.
+ *   CT_LAUNCH_PERSISTENT: the whole online phase and its fused check in one
+ *     launch of one 256-thread workgroup per compute unit, which walks the
+ *     stages over all layers and meets at a grid barrier between stages;
+ *     every stage then runs at the product kernel's occupancy (four
+ *     wavefronts per compute unit).  It applies to calls whose layers are
+ *     all matrix-core layers (N > CT_SKINNY_N) that are not convolutions and
+ *     not compressed along M; other calls take the staged kernels.  The
+ *     results are the same bit for bit.  A barrier wait is bounded (about
+ *     2 s); if one runs out, every layer's check record reports accept = 0
+ *     and reserved = 1.  The launch needs every workgroup resident at once:
+ *     do not run other work on the device beside it.
+ * Returns CT_EINVAL for another mode. */
+#define CT_LAUNCH_STAGED 0
+#define CT_LAUNCH_PERSISTENT 1
+ct_status ct_set_launch(ct_ctx *ctx, int mode);
 
 typedef struct {
     char name[24];        /* kernel stage, e.g. "ring_gemm", "check_batch" */

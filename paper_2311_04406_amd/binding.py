@@ -91,6 +91,8 @@ class CtTuning(ctypes.Structure):
 
 # product kernel and workgroup tile shape (CT_TILE_*)
 TILE_AUTO, TILE_LDS_64x64, TILE_LDS_128x64, TILE_REGS_64x64, TILE_REGS_128x64, TILE_REGS_FIT = 0, 1, 2, 3, 4, 5
+# launch of the online phase (CT_LAUNCH_*)
+LAUNCH_STAGED, LAUNCH_PERSISTENT = 0, 1
 TILE_NAMES = {0: "auto", 1: "lds_64x64", 2: "lds_128x64", 3: "regs_64x64", 4: "regs_128x64", 5: "regs_fit"}
 
 
@@ -156,6 +158,7 @@ def load() -> ctypes.CDLL:
                                ctypes.POINTER(CtCheckResult)]
     L.ct_set_timing.argtypes = [vp, i]
     L.ct_set_overlap.argtypes = [vp, i]
+    L.ct_set_launch.argtypes = [vp, i]
     L.ct_stage_times.argtypes = [vp, ctypes.POINTER(CtStageTime), i, ctypes.POINTER(ctypes.c_int)]
     L.ct_autotune.argtypes = [vp, i, ctypes.POINTER(CtLayerDesc), ctypes.POINTER(CtLayerBufs), i, i,
                               ctypes.POINTER(CtTuning)]
@@ -179,7 +182,7 @@ def load() -> ctypes.CDLL:
     L.ct_last_error.argtypes = [vp]
     L.ct_last_error.restype = ctypes.c_char_p
     for f in ("ct_create", "ct_destroy", "ct_key_shares", "ct_gen_triple_tags", "ct_tag_linear",
-              "ct_mac_check_device", "ct_mac_check", "ct_tag_linear_check_static", "ct_set_timing", "ct_set_overlap", "ct_stage_times", "ct_tag_linear_check",
+              "ct_mac_check_device", "ct_mac_check", "ct_tag_linear_check_static", "ct_set_timing", "ct_set_overlap", "ct_set_launch", "ct_stage_times", "ct_tag_linear_check",
               "ct_autotune", "ct_get_tuning", "ct_set_tuning", "ct_plan_create", "ct_plan_launch",
               "ct_plan_destroy", "ct_server_create", "ct_server_submit", "ct_server_poll", "ct_server_drain",
               "ct_server_layer", "ct_server_stats", "ct_server_destroy"):
@@ -198,13 +201,14 @@ class CtError(RuntimeError):
 class CheckResult:
     cs: list            # cs[W][p] as Python ints, W in (E, U, D), p over the parties
     accept: bool
+    reserved: int = 0   # 1: a persistent launch's barrier wait ran out
 
 
 def _result(r: CtCheckResult, parties: int = 2) -> CheckResult:
     v = list(r.cs)
     m = 2 * MAX_PARTIES
     cs = [[v[m * w + 2 * p] | (v[m * w + 2 * p + 1] << 64) for p in range(parties)] for w in range(3)]
-    return CheckResult(cs=cs, accept=bool(r.accept))
+    return CheckResult(cs=cs, accept=bool(r.accept), reserved=int(r.reserved))
 
 
 class Layer:
@@ -410,6 +414,10 @@ class Context:
     def set_overlap(self, enable: bool):
         """Mixed batches on two streams (default) or all on the context stream."""
         self._check(self.lib.ct_set_overlap(self.h, int(enable)))
+
+    def set_launch(self, mode: int):
+        """LAUNCH_STAGED (one kernel per stage) or LAUNCH_PERSISTENT (one launch)."""
+        self._check(self.lib.ct_set_launch(self.h, int(mode)))
 
     def stage_times(self):
         """{stage: (total_ms, launches)} since the previous call (synchronizes)."""

@@ -25,7 +25,7 @@ using namespace ct;
 static const char *kStageNames[ST_COUNT] = {
     "deal_lift", "fill_zero", "deal_auth", "deal_skinny", "zero_acc", "open_u", "row_pass", "pack",
     "copy_base", "ring_gemm", "post", "compact_final", "check_batch", "check_compact", "finalize", "col_tag",
-    "conv_compress", "np_open", "np_skinny", "np_compress", "np_gemv", "open_pack"};
+    "conv_compress", "np_open", "np_skinny", "np_compress", "np_gemv", "open_pack", "persistent"};
 constexpr int EV_POOL = 2048;
 
 struct ct_plan {
@@ -515,6 +515,7 @@ hipError_t lane_init(Lane &ln, hipStream_t stream, int max_layers) {
     LANE_TRY(hipMalloc(&ln.skinny_dev, sizeof(SkinnyProb) * ln.max_layers));
     LANE_TRY(hipMalloc(&ln.acc_dev, sizeof(u128) * ACC_PER_LAYER * ln.max_layers));
     LANE_TRY(hipMalloc(&ln.res_dev, sizeof(ct_check_result) * ln.max_layers));
+    LANE_TRY(hipMalloc(&ln.sync_dev, 16));
     LANE_TRY(hipHostMalloc(&ln.layers_host, sizeof(LayerDev) * ln.max_layers, hipHostMallocDefault));
     LANE_TRY(hipHostMalloc(&ln.gemm_host, sizeof(GemmProb) * ln.max_probs, hipHostMallocDefault));
     LANE_TRY(hipHostMalloc(&ln.pack_host, sizeof(PackJob) * ln.max_jobs, hipHostMallocDefault));
@@ -528,6 +529,7 @@ hipError_t lane_init(Lane &ln, hipStream_t stream, int max_layers) {
 
 void lane_free(Lane &ln) {
     if (ln.upload_done) (void)hipEventDestroy(ln.upload_done);
+    if (ln.sync_dev) (void)hipFree(ln.sync_dev);
     if (ln.layers_dev) (void)hipFree(ln.layers_dev);
     if (ln.gemm_dev) (void)hipFree(ln.gemm_dev);
     if (ln.pack_dev) (void)hipFree(ln.pack_dev);
@@ -904,10 +906,42 @@ ct_status prepare_online(ct_ctx *c, Lane &ln, ct_mode mode, const ct_layer_desc 
     return CT_OK;
 }
 
-// The kernels of the online phase, in order, on the lane's stream.
+// Whether a prepared two-party online call can run as the persistent launch:
+// it carries the fused check and all its layers are matrix-core layers (N >
+// SKINNY_MAX_N) that are neither convolutions nor compressed along M.
+bool persist_ok(const OnlineLaunch &P) {
+    return P.check && P.variants == 1 && !P.any_open_u && !P.any_conv_n && !P.any_cm && P.nm > 0;
+}
+
+// The kernels of the online phase, in order, on the lane's stream (or, in
+// the persistent launch mode, the one persistent launch when the call
+// qualifies).
 ct_status enqueue_online(ct_ctx *c, Lane &ln, const OnlineLaunch &P) {
     if (c->np > 2) return enqueue_online_np(c, ln, P);
     const int n = P.n;
+    if (c->launch_mode == CT_LAUNCH_PERSISTENT && persist_ok(P)) {
+        PersistArgs a;
+        a.Ls = ln.layers_dev;
+        a.jobs = ln.pack_dev;
+        a.probs = ln.gemm_dev;
+        a.out = P.out_dev;
+        a.sync = ln.sync_dev;
+        a.n = n;
+        a.flags = P.flags;
+        a.zero_what = P.zero_what;
+        a.njobs = P.njobs;
+        a.pack_tiles = P.pack_tiles;
+        a.nprobs = P.nm;
+        a.total_tiles = P.total_tiles;
+        a.xcd_remap = P.tu.xcd_remap;
+        a.any_accum = P.any_accum ? 1 : 0;
+        a.mt = ln.gemm_host[0].mt;
+        // the barrier counter starts at zero (a fill kernel, not a memset,
+        // so that the launch can be captured into a graph)
+        LAUNCH(c, ln, ST_FILL_ZERO, launch_fill_zero(16, reinterpret_cast<u128 *>(ln.sync_dev), 1, ln.stream));
+        LAUNCH(c, ln, ST_PERSIST, launch_online_persist(c->eb, a, c->num_cus, ln.stream));
+        return CT_OK;
+    }
     if (P.zero_what)
         LAUNCH(c, ln, ST_ZERO_ACC, launch_zero_acc(c->eb, ln.layers_dev, n, P.zero_what, P.max_zero, ln.stream));
     if (P.any_open_u)
@@ -1157,6 +1191,13 @@ ct_status ct_plan_destroy(ct_plan *pl) {
 ct_status ct_set_overlap(ct_ctx *c, int enable) {
     if (!c) return CT_EINVAL;
     c->overlap = enable != 0;
+    return CT_OK;
+}
+
+ct_status ct_set_launch(ct_ctx *c, int mode) {
+    if (!c) return CT_EINVAL;
+    if (mode != CT_LAUNCH_STAGED && mode != CT_LAUNCH_PERSISTENT) return fail(c, CT_EINVAL, "unknown launch mode");
+    c->launch_mode = mode;
     return CT_OK;
 }
 

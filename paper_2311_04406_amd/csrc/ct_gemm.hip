@@ -28,7 +28,7 @@
 // while the matrix cores work on the other, and reads 16-byte digit fragments
 // in a triangular order (fragment pair t unlocks 2t+1 or 2(16-t) products) so
 // the first products issue after a single fragment pair.
-#include "ct_sweep.h"
+#include "ct_passes.h"
 
 namespace ct {
 
@@ -117,11 +117,11 @@ __device__ __forceinline__ void write_planes(uint8_t *base, int off, const uint3
 // segment of a right one, loaded directly), write their digit planes to
 // LDS, and the tile is stored with 16-byte coalesced writes.
 template <class R>
-__global__ __launch_bounds__(256) void k_pack(const PackJob *__restrict__ jobs, int njobs, int total_tiles) {
+__device__ __forceinline__ void pack_body(const PackJob *__restrict__ jobs, int njobs, int total_tiles, const Grid &g) {
     constexpr int OPBYTES = Tile<R>::OPB, NW = Tile<R>::NW;
     __shared__ __attribute__((aligned(16))) uint8_t tile[OPBYTES];
     const int tid = threadIdx.x;
-    for (int t = blockIdx.x; t < total_tiles; t += gridDim.x) {
+    for (int t = (int)g.x; t < total_tiles; t += (int)g.nx) {
         int lo = 0, hi = njobs - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -186,6 +186,11 @@ __global__ __launch_bounds__(256) void k_pack(const PackJob *__restrict__ jobs, 
     }
 }
 
+template <class R>
+__global__ __launch_bounds__(256) void k_pack(const PackJob *__restrict__ jobs, int njobs, int total_tiles) {
+    pack_body<R>(jobs, njobs, total_tiles, hw_grid());
+}
+
 hipError_t launch_pack(int eb, const PackJob *jobs_dev, int njobs, int total_tiles, hipStream_t st) {
     if (njobs <= 0 || total_tiles <= 0) return hipSuccess;
     int grid = total_tiles < 65536 ? total_tiles : 65536;
@@ -217,16 +222,16 @@ __device__ __forceinline__ void store_tile(uint8_t *tile, int off, const uint32_
 }
 
 template <class R>
-__global__ __launch_bounds__(256) void k_open_pack(const LayerDev *__restrict__ Ls, int flags) {
+__device__ __forceinline__ void open_pack_body(const LayerDev *__restrict__ Ls, int flags, const Grid &g) {
     constexpr int NW = Tile<R>::NW;
     __shared__ __attribute__((aligned(16))) uint8_t tile[Tile<R>::OPB];
     __shared__ R sh[3 * WAVES];
-    const LayerDev &L = Ls[blockIdx.y];
+    const LayerDev &L = Ls[g.y];
     if (!L.fo) return;
     const int64_t K = L.K, N = L.N;
     const int kt = (int)((K + 31) / 32), tiles = (int)((N + 63) / 64) * kt;
-    if ((int)blockIdx.x >= tiles) return;
-    const int tn = blockIdx.x / kt, ks = blockIdx.x - tn * kt;
+    if ((int)g.x >= tiles) return;
+    const int tn = (int)g.x / kt, ks = (int)g.x - tn * kt;
     const int lane = threadIdx.x & 63, kk = (threadIdx.x >> 6) * 8;
     const int64_t n = (int64_t)tn * 64 + lane;
     const bool check = flags & F_CHECK, compact = (flags & F_COMPACT) && !L.cm;
@@ -281,6 +286,11 @@ __global__ __launch_bounds__(256) void k_open_pack(const LayerDev *__restrict__ 
     store_tile<R>(tile, off, wb1, reinterpret_cast<u128 *>(P<R>(L.rp[1]) + toff));
     store_tile<R>(tile, off, wu, reinterpret_cast<u128 *>(P<R>(L.rp[2]) + toff));
     if (check) block_accumulate<3>(chk, sh, P<R>(L.acc) + 3);
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_open_pack(const LayerDev *__restrict__ Ls, int flags) {
+    open_pack_body<R>(Ls, flags, hw_grid());
 }
 
 hipError_t launch_open_pack(int eb, const LayerDev *L, int n, int flags, int max_tiles, hipStream_t st) {
@@ -776,6 +786,102 @@ __global__ __launch_bounds__(256, 1) void k_ring_gemm_rs(const GemmProb *__restr
     const TileRef tr = decode_tile(probs, nprobs, t);
     const GemmProb P = probs[tr.prob];
     gemm_tile_rs<R, MT>(P, tr.tm, tr.tn, tr.split);
+}
+
+// ---------------------------------------------------------------- persistent launch
+// The two-party online phase of a batch of matrix-core layers in one launch:
+// one workgroup per compute unit walks the stages of the staged kernels, in
+// their order, over every layer of the batch -- zeroing; opening U with the
+// right operands' digit tiles; the pass over M x K; packing the left
+// operands (and the constant terms of split products); the products; the
+// pass over M x N; the compact tag's final step; the check verdicts -- as
+// workgroups of grids of its own, running the same stage bodies.  A stage
+// starts when every workgroup has finished the previous one (grid barrier).
+// The register-streamed products need all 512 registers of a lane, so every
+// stage runs at one workgroup (four wavefronts) per compute unit.
+
+// Grid barrier: workgroup arrivals counted in sync[0] (phase p is complete
+// at p * gridDim.x arrivals).  The release fence before the arrival and the
+// acquire fence after the wait make the workgroups' writes of the earlier
+// stages visible to the later ones on every XCD.  The wait is bounded: past
+// about 2 s (wall clock, 100 MHz) it sets sync[1] and goes on, and a
+// workgroup that sees sync[1] set stops waiting at once.
+__device__ __forceinline__ void grid_barrier(uint32_t *sync, uint32_t phase) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        atomicAdd(sync, 1u);
+        const uint32_t target = phase * gridDim.x;
+        const uint64_t t0 = wall_clock64();
+        while (__hip_atomic_load(sync, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(sync + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+            if (wall_clock64() - t0 > 200000000ull) {
+                atomicOr(sync + 1, 1u);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(4);
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+template <class R, int MT>
+__global__ __launch_bounds__(256, 1) void k_online_persist(PersistArgs a) {
+    const uint32_t W = gridDim.x, w = blockIdx.x;
+    uint32_t phase = 0;
+    if (a.zero_what)
+        for (int l = 0; l < a.n; l++) zero_acc_body<R>(a.Ls, a.zero_what, Grid{w, (uint32_t)l, W});
+    grid_barrier(a.sync, ++phase);
+    // the right operands' tiles of all layers as one list, dealt round-robin
+    uint32_t first = 0;
+    for (int l = 0; l < a.n; l++) {
+        const LayerDev &L = a.Ls[l];
+        const uint32_t tiles = L.fo ? (uint32_t)(((L.N + 63) / 64) * ((L.K + 31) / 32)) : 0;
+        for (uint32_t t = (w + W - first % W) % W; t < tiles; t += W) open_pack_body<R>(a.Ls, a.flags, Grid{t, (uint32_t)l, tiles});
+        first += tiles;
+    }
+    grid_barrier(a.sync, ++phase);  // the row pass reads U^c and [tB^c]_p
+    for (int l = 0; l < a.n; l++) row_pass_layer<R, 0>(a.Ls, a.flags, Grid{w, (uint32_t)l, W});
+    grid_barrier(a.sync, ++phase);
+    pack_body<R>(a.jobs, a.njobs, a.pack_tiles, Grid{w, 0, W});
+    if (a.any_accum)
+        for (int p = 0; p < a.nprobs; p++) prob_base_body<R>(a.probs, Grid{w, (uint32_t)p, W});
+    grid_barrier(a.sync, ++phase);
+    for (int b = (int)w; b < a.total_tiles; b += (int)W) {
+        const int t = a.xcd_remap ? xcd_tile(b, a.total_tiles, a.xcd_remap) : b;
+        const TileRef tr = decode_tile(a.probs, a.nprobs, t);
+        const GemmProb P = a.probs[tr.prob];
+        gemm_tile_rs<R, MT>(P, tr.tm, tr.tn, tr.split);
+    }
+    grid_barrier(a.sync, ++phase);
+    for (int l = 0; l < a.n; l++) post_body<R>(a.Ls, a.flags, Grid{w, (uint32_t)l, W});
+    grid_barrier(a.sync, ++phase);
+    if (a.flags & F_COMPACT)
+        for (int l = 0; l < a.n; l++) compact_final_body<R>(a.Ls, a.flags, Grid{w, (uint32_t)l, W});
+    grid_barrier(a.sync, ++phase);
+    // one wavefront per layer; a run-out barrier rejects every layer
+    const bool ran_out = __hip_atomic_load(a.sync + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    const int lane = threadIdx.x & 63;
+    for (int l = (int)(w * WAVES + (threadIdx.x >> 6)); l < a.n; l += (int)(W * WAVES)) {
+        finalize_body<R>(a.Ls, a.n, a.out, l);
+        if (ran_out && lane == 0) {
+            ct_check_result *r = a.out + a.Ls[l].out_index;
+            r->accept = 0;
+            r->reserved = 1;
+        }
+    }
+}
+
+hipError_t launch_online_persist(int eb, const PersistArgs &a, int wgs, hipStream_t st) {
+    if (a.n <= 0 || wgs <= 0) return hipSuccess;
+    if (eb == 8 && a.mt == 2)
+        hipLaunchKernelGGL((k_online_persist<r64, 2>), dim3(wgs), dim3(256), 0, st, a);
+    else if (eb == 8)
+        hipLaunchKernelGGL((k_online_persist<r64, 1>), dim3(wgs), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_online_persist<u128, 1>), dim3(wgs), dim3(256), 0, st, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_gemm(int eb, const GemmProb *probs_dev, int nprobs, int total_tiles, int xcd_remap, int mt,

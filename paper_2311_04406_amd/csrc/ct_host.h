@@ -29,6 +29,7 @@ struct Lane {
     SkinnyProb *skinny_dev = nullptr, *skinny_host = nullptr;
     u128 *acc_dev = nullptr;
     ct_check_result *res_dev = nullptr, *res_host = nullptr;
+    uint32_t *sync_dev = nullptr;      // grid barrier of the persistent launch (16 bytes)
     hipEvent_t upload_done = nullptr;  // the staging copies may be rewritten once this has completed
     bool timed = false;                // per-launch event timing (the context's own lane only)
 };
@@ -44,7 +45,8 @@ void lane_free(Lane &ln);
 enum Stage : int {
     ST_DEAL_LIFT, ST_FILL_ZERO, ST_DEAL_AUTH, ST_DEAL_SKINNY, ST_ZERO_ACC, ST_OPEN_U, ST_ROW_PASS, ST_PACK,
     ST_COPY_BASE, ST_RING_GEMM, ST_POST, ST_COMPACT_FINAL, ST_CHECK_BATCH, ST_CHECK_COMPACT, ST_FINALIZE,
-    ST_COL_TAG, ST_CONV_COMPRESS, ST_NP_OPEN, ST_NP_SKINNY, ST_NP_COMPRESS, ST_NP_GEMV, ST_OPEN_PACK, ST_COUNT
+    ST_COL_TAG, ST_CONV_COMPRESS, ST_NP_OPEN, ST_NP_SKINNY, ST_NP_COMPRESS, ST_NP_GEMV, ST_OPEN_PACK, ST_PERSIST,
+    ST_COUNT
 };
 
 struct ct_ctx {
@@ -59,6 +61,7 @@ struct ct_ctx {
     ct::Lane side;
     hipEvent_t fork = nullptr, join = nullptr;
     bool overlap = true;  // mixed batches on two streams (ct_set_overlap)
+    int launch_mode = CT_LAUNCH_STAGED;  // ct_set_launch
     std::string err;
     // per-launch timing: event pairs recorded around each kernel of the main lane
     bool timing = false;

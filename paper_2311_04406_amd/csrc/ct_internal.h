@@ -323,6 +323,19 @@ struct SkinnyProb {
     int32_t M, N, K, pad;
 };
 
+// The two-party online phase of a batch as one persistent launch
+// (k_online_persist): the stages' tables as the staged kernels take them, and
+// the launch's grid barrier.  sync[0] counts workgroup arrivals and must be 0
+// at the launch; sync[1] is set when a barrier wait ran out (about 2 s).
+struct PersistArgs {
+    const LayerDev *Ls;
+    const PackJob *jobs;
+    const GemmProb *probs;
+    ct_check_result *out;
+    uint32_t *sync;
+    int32_t n, flags, zero_what, njobs, pack_tiles, nprobs, total_tiles, xcd_remap, any_accum, mt;
+};
+
 // ---- launchers (defined in the .hip files) ----
 // eb: bytes per ring element, 16 (k = s = 64) or 8 (k = s = 32).
 hipError_t launch_pack(int eb, const PackJob *jobs_dev, int njobs, int total_tiles, hipStream_t st);
@@ -330,6 +343,9 @@ hipError_t launch_pack(int eb, const PackJob *jobs_dev, int njobs, int total_til
 // GEMM_REGS (fragments streamed into registers, k_ring_gemm_rs)
 hipError_t launch_gemm(int eb, const GemmProb *probs_dev, int nprobs, int total_tiles, int xcd_remap, int mt,
                        int kernel, hipStream_t st);
+// The persistent launch: `wgs` workgroups of 256 threads, one per compute
+// unit (all must be resident at once: the stages meet at grid barriers).
+hipError_t launch_online_persist(int eb, const PersistArgs &a, int wgs, hipStream_t st);
 hipError_t launch_skinny(int eb, const SkinnyProb *probs_dev, int nprobs, int max_rows, hipStream_t st);
 
 hipError_t launch_fill_zero(int eb, u128 *p, int64_t n, hipStream_t st);

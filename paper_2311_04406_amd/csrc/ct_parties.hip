@@ -225,7 +225,7 @@ __global__ __launch_bounds__(TPB) void k_np_open_u(const LayerDev *__restrict__ 
 #pragma unroll
         for (int p = 0; p < MAXP; p++) if (p < np) atomic_add128(cv + o.tb(p) + r, v[1 + p]);
     };
-    row_sweep<R, 1 + MAXP>(L.K, N, elem, done);
+    row_sweep<R, 1 + MAXP>(hw_grid(), L.K, N, elem, done);
     if (check) block_accumulate<ACC_W>(chk, sh, P<R>(L.acc) + 1 * ACC_W);
 }
 
@@ -538,7 +538,7 @@ __global__ __launch_bounds__(TPB) void k_np_compress(const LayerDev *__restrict_
             atomic_add128(cv + o.tc(p) + r, v[1 + MAXP + p]);
         }
     };
-    row_sweep<R, 1 + 2 * MAXP>(L.M, N, elem, done);
+    row_sweep<R, 1 + 2 * MAXP>(hw_grid(), L.M, N, elem, done);
 }
 
 hipError_t launch_np_compress(int eb, const LayerDev *L, int n, int64_t max_items, hipStream_t st) {
@@ -569,7 +569,7 @@ __global__ __launch_bounds__(TPB) void k_np_gemv(const LayerDev *__restrict__ Ls
 #pragma unroll
         for (int p = 0; p < MAXP; p++) if (p < np) atomic_add128(cv + o.tz(p) + m, v[1 + p]);
     };
-    row_sweep<R, 1 + MAXP>(L.M, K, elem, done);
+    row_sweep<R, 1 + MAXP>(hw_grid(), L.M, K, elem, done);
 }
 
 hipError_t launch_np_gemv(int eb, const LayerDev *L, int n, int64_t max_items, hipStream_t st) {

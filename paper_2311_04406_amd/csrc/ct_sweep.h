@@ -12,6 +12,15 @@ constexpr int TPB = 256;
 constexpr int WAVES = TPB / 64;
 constexpr int SEGW = 512;  // elements per wavefront item of a long row
 
+// The workgroup a stage body runs as: workgroup (x, y) of a grid with nx
+// workgroups along x.  A stage kernel passes its own blockIdx and gridDim
+// (hw_grid); the persistent launch runs the same bodies as workgroups of a
+// grid of its choosing.
+struct Grid {
+    uint32_t x, y, nx;
+};
+__device__ __forceinline__ Grid hw_grid() { return Grid{blockIdx.x, blockIdx.y, gridDim.x}; }
+
 // Buffers of a layer as elements of the context's ring (u128 for k = s = 64,
 // r64 for k = s = 32).
 template <class R>
@@ -106,16 +115,16 @@ __device__ __forceinline__ void block_accumulate(R (&v)[NV], R *sh, R *dst) {
     }
 }
 
-// Row sweep over an R x N matrix.  Rows of N <= 64 elements are reduced by
+// Row sweep over an R x N matrix by the workgroups of grid g.  Rows of N <= 64 elements are reduced by
 // groups of G = pow2ceil(N) lanes (64 / G rows per wavefront); longer rows
 // are cut into items of SEGW elements, one wavefront each.  elem(r, c, v)
 // accumulates into the NV row sums v; row_done(r, v) receives each item's sums
 // (in the group leader lane) and must add them atomically.
 template <class R, int NV, typename Elem, typename RowDone>
-__device__ __forceinline__ void row_sweep(int64_t rows, int64_t N, Elem elem, RowDone row_done) {
+__device__ __forceinline__ void row_sweep(const Grid &g, int64_t rows, int64_t N, Elem elem, RowDone row_done) {
     const int lane = threadIdx.x & 63;
-    const int64_t wave_id = (blockIdx.x * (int64_t)TPB + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * TPB) >> 6;
+    const int64_t wave_id = ((int64_t)g.x * TPB + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)g.nx * TPB) >> 6;
     if (N <= 64) {
         int G = 1;
         while (G < N) G <<= 1;
@@ -158,10 +167,10 @@ __device__ __forceinline__ void row_sweep(int64_t rows, int64_t N, Elem elem, Ro
 // elem(r, c, v) accumulates into the NV column sums v; col_done(c, v)
 // receives each item's sums and must add them atomically.
 template <class R, int NV, typename Elem, typename ColDone>
-__device__ __forceinline__ void col_sweep(int64_t rows, int64_t N, Elem elem, ColDone col_done) {
+__device__ __forceinline__ void col_sweep(const Grid &g, int64_t rows, int64_t N, Elem elem, ColDone col_done) {
     const int lane = threadIdx.x & 63;
-    const int64_t wave_id = (blockIdx.x * (int64_t)TPB + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * TPB) >> 6;
+    const int64_t wave_id = ((int64_t)g.x * TPB + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)g.nx * TPB) >> 6;
     const int64_t rb = col_sweep_rb(rows, N);
     if (N <= 32) {
         const int G = (int)col_sweep_group(N);
