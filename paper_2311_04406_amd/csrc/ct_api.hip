@@ -515,7 +515,7 @@ hipError_t lane_init(Lane &ln, hipStream_t stream, int max_layers) {
     LANE_TRY(hipMalloc(&ln.skinny_dev, sizeof(SkinnyProb) * ln.max_layers));
     LANE_TRY(hipMalloc(&ln.acc_dev, sizeof(u128) * ACC_PER_LAYER * ln.max_layers));
     LANE_TRY(hipMalloc(&ln.res_dev, sizeof(ct_check_result) * ln.max_layers));
-    LANE_TRY(hipMalloc(&ln.sync_dev, 16));
+    LANE_TRY(hipMalloc(&ln.sync_dev, 64));
     LANE_TRY(hipHostMalloc(&ln.layers_host, sizeof(LayerDev) * ln.max_layers, hipHostMallocDefault));
     LANE_TRY(hipHostMalloc(&ln.gemm_host, sizeof(GemmProb) * ln.max_probs, hipHostMallocDefault));
     LANE_TRY(hipHostMalloc(&ln.pack_host, sizeof(PackJob) * ln.max_jobs, hipHostMallocDefault));
@@ -936,9 +936,9 @@ ct_status enqueue_online(ct_ctx *c, Lane &ln, const OnlineLaunch &P) {
         a.xcd_remap = P.tu.xcd_remap;
         a.any_accum = P.any_accum ? 1 : 0;
         a.mt = ln.gemm_host[0].mt;
-        // the barrier counter starts at zero (a fill kernel, not a memset,
+        // the launch's counters start at zero (a fill kernel, not a memset,
         // so that the launch can be captured into a graph)
-        LAUNCH(c, ln, ST_FILL_ZERO, launch_fill_zero(16, reinterpret_cast<u128 *>(ln.sync_dev), 1, ln.stream));
+        LAUNCH(c, ln, ST_FILL_ZERO, launch_fill_zero(16, reinterpret_cast<u128 *>(ln.sync_dev), 3, ln.stream));
         LAUNCH(c, ln, ST_PERSIST, launch_online_persist(c->eb, a, c->num_cus, ln.stream));
         return CT_OK;
     }

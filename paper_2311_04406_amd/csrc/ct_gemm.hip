@@ -848,17 +848,31 @@ __global__ __launch_bounds__(256, 1) void k_online_persist(PersistArgs a) {
     if (a.any_accum)
         for (int p = 0; p < a.nprobs; p++) prob_base_body<R>(a.probs, Grid{w, (uint32_t)p, W});
     grid_barrier(a.sync, ++phase);
-    for (int b = (int)w; b < a.total_tiles; b += (int)W) {
-        const int t = a.xcd_remap ? xcd_tile(b, a.total_tiles, a.xcd_remap) : b;
-        const TileRef tr = decode_tile(a.probs, a.nprobs, t);
-        const GemmProb P = a.probs[tr.prob];
-        gemm_tile_rs<R, MT>(P, tr.tm, tr.tn, tr.split);
+    // the product tiles are taken in list order as workgroups free up (tiles
+    // differ in length), from one counter per XCD so that tile b still runs on
+    // XCD b % 8 as in the staged kernel: counter x hands out b = 8 i + x (one
+    // counter for all if the grid has fewer than 8 workgroups)
+    {
+        __shared__ int next_tile;
+        const uint32_t q = W >= 8 ? 8 : 1, x = w % q;
+        for (;;) {
+            if (threadIdx.x == 0) next_tile = (int)(q * atomicAdd(a.sync + 4 + x, 1u) + x);
+            __syncthreads();
+            const int b = next_tile;
+            __syncthreads();
+            if (b >= a.total_tiles) break;
+            const int t = a.xcd_remap ? xcd_tile(b, a.total_tiles, a.xcd_remap) : b;
+            const TileRef tr = decode_tile(a.probs, a.nprobs, t);
+            const GemmProb P = a.probs[tr.prob];
+            gemm_tile_rs<R, MT>(P, tr.tm, tr.tn, tr.split);
+        }
     }
     grid_barrier(a.sync, ++phase);
     for (int l = 0; l < a.n; l++) post_body<R>(a.Ls, a.flags, Grid{w, (uint32_t)l, W});
     grid_barrier(a.sync, ++phase);
+    // four workgroups per layer, as the staged kernel
     if (a.flags & F_COMPACT)
-        for (int l = 0; l < a.n; l++) compact_final_body<R>(a.Ls, a.flags, Grid{w, (uint32_t)l, W});
+        for (uint32_t v = w; v < 4u * (uint32_t)a.n; v += W) compact_final_body<R>(a.Ls, a.flags, Grid{v & 3, v >> 2, 4});
     grid_barrier(a.sync, ++phase);
     // one wavefront per layer; a run-out barrier rejects every layer
     const bool ran_out = __hip_atomic_load(a.sync + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;

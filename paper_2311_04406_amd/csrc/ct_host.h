@@ -29,7 +29,7 @@ struct Lane {
     SkinnyProb *skinny_dev = nullptr, *skinny_host = nullptr;
     u128 *acc_dev = nullptr;
     ct_check_result *res_dev = nullptr, *res_host = nullptr;
-    uint32_t *sync_dev = nullptr;      // grid barrier of the persistent launch (16 bytes)
+    uint32_t *sync_dev = nullptr;      // counters of the persistent launch (64 bytes)
     hipEvent_t upload_done = nullptr;  // the staging copies may be rewritten once this has completed
     bool timed = false;                // per-launch event timing (the context's own lane only)
 };

@@ -325,8 +325,9 @@ struct SkinnyProb {
 
 // The two-party online phase of a batch as one persistent launch
 // (k_online_persist): the stages' tables as the staged kernels take them, and
-// the launch's grid barrier.  sync[0] counts workgroup arrivals and must be 0
-// at the launch; sync[1] is set when a barrier wait ran out (about 2 s).
+// the launch's counters, sync[0 .. 12), all 0 at the launch: sync[0] counts
+// workgroup arrivals at the grid barriers, sync[1] is set when a barrier wait
+// ran out (about 2 s), sync[4 + x] hands out the product tiles of XCD x.
 struct PersistArgs {
     const LayerDev *Ls;
     const PackJob *jobs;
