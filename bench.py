@@ -17,7 +17,7 @@ Prints one JSON line.  Default workload: the batched layer set (64 linear
 layers with M, K, N log-uniform in [32, 4096], seeded; the largest
 configuration by sum M K N), CompactTag protocol, with beside it: the same
 step as eager calls, the SPDZ2k protocol, one plain launch per layer, the
-check as a separate call, a per-kernel breakdown with the dominant kernel's
+check as a separate call, the step as one persistent launch, a per-kernel breakdown with the dominant kernel's
 roofline, the captured steps of the CNN and encoder layer sets (--extra), a
 serving leg (open-loop Poisson arrivals of single-layer requests, p50/p99
 latency) and the oracle on the host (all host threads up to 16, and one).
@@ -47,6 +47,15 @@ DIGIT_PAIRS = 136            # int8 digit products per 128-bit ring multiply-acc
 def along_m(s, compress: str) -> bool:
     """Whether the compact tag of layer s is compressed along M (AUTO: exactly when M > N)."""
     return compress == "m" or (compress == "auto" and s.M > s.N)
+
+
+def persistent_applies(specs, compress: str, parties: int, implicit: bool) -> bool:
+    """Whether ct_set_launch(CT_LAUNCH_PERSISTENT) runs a batch as the one
+    persistent launch (two parties; every layer a matrix-core layer that is
+    not an implicit-im2col convolution and not compressed along M) or as the
+    staged kernels."""
+    return parties == 2 and all(s.N > 8 and not (implicit and s.conv is not None) and not along_m(s, compress)
+                                for s in specs)
 
 
 def stage_work(stage: str, specs, mode: str, f: int = 0, kbits: int = 64, compress: str = "n",
@@ -447,6 +456,7 @@ def main():
 
     import torch
     from paper_2311_04406_amd import MODE_COMPACT, MODE_SPDZ2K, RESULT_WORDS, Context, Layer, workloads
+    from paper_2311_04406_amd.binding import LAUNCH_PERSISTENT, LAUNCH_STAGED
 
     if args.config == "serving":
         return serving_main(args, torch)
@@ -572,6 +582,19 @@ def main():
         out["separate_check"] = {"value": round(mkn * args.steps / T4 / 1e9, 3),
                                  "ms_per_step": round(T4 / args.steps * 1e3, 4),
                                  "p50_ms": round(pct(per4, 50), 4), "p99_ms": round(pct(per4, 99), 4)}
+        if persistent_applies(specs, args.compress, args.parties, implicit):
+            # the same captured step as one persistent launch (every stage at
+            # the products' occupancy, grid barriers between stages)
+            ctx.set_launch(LAUNCH_PERSISTENT)
+            plan5 = ctx.plan(mode_id, layers, out_dev)
+            ctx.set_launch(LAUNCH_STAGED)
+            T5, per5, _ = run_steps(ctx, mode_id, [layers], out_dev, args.steps, args.warmup, torch, plan=plan5)
+            plan5.close()
+            ok5 = all(r.accept and r.reserved == 0 for r in Context.decode_results(out_dev, len(layers), args.parties))
+            out["persistent_launch"] = {"value": round(mkn * args.steps / T5 / 1e9, 3),
+                                        "ms_per_step": round(T5 / args.steps * 1e3, 4),
+                                        "p50_ms": round(pct(per5, 50), 4), "p99_ms": round(pct(per5, 99), 4),
+                                        "accept": ok5}
     plan.close()
     del plan
     if not args.no_serve and args.kbits == 64 and args.parties == 2:  # the server runs two parties, k = s = 64

@@ -86,3 +86,15 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_persistent_launch_scope():
+    """The bench's rule for when the persistent launch applies follows the
+    library's: two parties, matrix-core layers only, no implicit convolution,
+    nothing compressed along M."""
+    from paper_2311_04406_amd import workloads as W
+    assert bench.persistent_applies(W.batched(), "n", 2, True)
+    assert not bench.persistent_applies(W.batched(), "n", 3, True)
+    assert not bench.persistent_applies(W.cnn(), "n", 2, True)     # classifier N = 1, convolutions
+    assert bench.persistent_applies(W.transformer(1), "n", 2, True)
+    assert not bench.persistent_applies(W.transformer(1), "m", 2, True)
