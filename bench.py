@@ -139,7 +139,8 @@ def stage_work(stage: str, specs, mode: str, f: int = 0, kbits: int = 64, compre
 
 # Sources that determine what the device kernels do; the hardware counters in
 # profiles/traffic.json are valid only for the digest they were taken on.
-KERNEL_SOURCES = ("ct_device.h", "ct_internal.h", "ct_sweep.h", "ct_kernels.hip", "ct_gemm.hip", "ct_parties.hip")
+KERNEL_SOURCES = ("ct_device.h", "ct_internal.h", "ct_sweep.h", "ct_passes.h", "ct_kernels.hip", "ct_gemm.hip",
+                  "ct_parties.hip")
 
 
 def strip_comments(src: str) -> str:
