@@ -291,13 +291,15 @@ ct_status ct_set_overlap(ct_ctx *ctx, int enable);
  *     launch of one 256-thread workgroup per compute unit, which walks the
  *     stages over all layers and meets at a grid barrier between stages;
  *     every stage then runs at the product kernel's occupancy (four
- *     wavefronts per compute unit).  It applies to calls whose layers are
- *     all matrix-core layers (N > CT_SKINNY_N) that are not convolutions and
- *     not compressed along M; other calls take the staged kernels.  The
- *     results are the same bit for bit.  A barrier wait is bounded (about
- *     2 s); if one runs out, every layer's check record reports accept = 0
- *     and reserved = 1.  The launch needs every workgroup resident at once:
- *     do not run other work on the device beside it.
+ *     wavefronts per compute unit).  It applies to calls (and plans) that
+ *     carry the fused check and whose layers are all matrix-core layers
+ *     (N > CT_SKINNY_N) that are neither convolutions nor compressed along
+ *     M; other calls, and the request server's batches, take the staged
+ *     kernels.  The results are the same bit for bit.  A barrier wait is
+ *     bounded (about 2 s); if one runs out, every layer's check record
+ *     reports accept = 0 and reserved = 1.  The launch needs every
+ *     workgroup resident at once: do not run other work on the device
+ *     beside it.
  * Returns CT_EINVAL for another mode. */
 #define CT_LAUNCH_STAGED 0
 #define CT_LAUNCH_PERSISTENT 1
