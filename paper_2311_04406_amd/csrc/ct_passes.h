@@ -158,13 +158,13 @@ __device__ __forceinline__ void row_pass_body(const LayerDev &L, int flags, R (&
             use(k, v);
         }
         if (compact) {
-#pragma unroll
-            for (int i = 0; i < 5; i++) cp[i] = wave_sum(cp[i]);
+            // the partial compact tags E tB^c_p + tA_p U^c summed per lane
+            // first: three wavefront reductions for the five row products
+            const R val[3] = {wave_sum(cp[0]), wave_sum(add(cp[1], cp[3])), wave_sum(add(cp[2], cp[4]))};
             if (lane == 0) {
                 // E U^c, and the partial compact tags (k_compact_final adds
                 // [tC^c]_p and [Delta]_p E U^c); the three atomics in flight together
                 R *const cell[3] = {P<R>(L.cvec) + o.EUc + m, P<R>(L.cvec) + o.tZc0 + m, P<R>(L.cvec) + o.tZc1 + m};
-                const R val[3] = {cp[0], add(cp[1], cp[3]), add(cp[2], cp[4])};
                 const bool ok[3] = {true, true, true};
                 atomic_add128_n<3>(cell, val, ok);
             }
