@@ -174,6 +174,24 @@ def test_persistent_plan_replays(ctx, mode):
 
 
 @pytest.mark.parametrize("mode", MODES)
+def test_persistent_static_workspace(ctx, mode):
+    """The entry point with the static per-GPU workspace, as one persistent
+    launch: the staged result."""
+    say(f"[persist] static workspace mode={mode}")
+    layers, out, ref, _ = staged_then_persistent(ctx, mode, BATCH[:3], "static, eager")
+    clear(layers, out)
+    torch.cuda.synchronize()
+    try:
+        ctx.set_launch(LAUNCH_PERSISTENT)
+        ctx.tag_linear_check_static(mode, layers, out)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_launch(LAUNCH_STAGED)
+    same(layers, out, ref, "static workspace")
+    free()
+
+
+@pytest.mark.parametrize("mode", MODES)
 def test_mixed_batch_takes_staged_kernels(ctx, mode):
     say(f"[persist] mixed batch mode={mode}")
     _, _, _, stages = staged_then_persistent(ctx, mode, MIXED, "mixed")
