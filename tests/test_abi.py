@@ -139,6 +139,8 @@ def test_validation_before_device_calls(lib):
     assert lib.ct_server_drain(None, 1.0) == b.CT_EINVAL
     assert lib.ct_server_destroy(None) == b.CT_EINVAL
     assert lib.ct_server_last_error(None) == b"null server"
+    assert lib.ct_set_launch(None, b.LAUNCH_STAGED) == b.CT_EINVAL
+    assert lib.ct_set_overlap(None, 1) == b.CT_EINVAL
 
 
 def test_product_path_has_no_oracle_dependency():
