@@ -27,7 +27,11 @@
 // global_load_lds_dwordx4 into one of two statically distinct LDS stages
 // while the matrix cores work on the other, and reads 16-byte digit fragments
 // in a triangular order (fragment pair t unlocks 2t+1 or 2(16-t) products) so
-// the first products issue after a single fragment pair.
+// the first products issue after a single fragment pair.  k_ring_gemm_rs
+// (the default) streams each wavefront's fragments straight into registers
+// instead.  k_open_pack opens U and writes the right operands' tiles in one
+// pass, and k_online_persist runs a whole two-party online phase as one
+// persistent launch over the stage bodies.
 #include "ct_passes.h"
 
 namespace ct {
