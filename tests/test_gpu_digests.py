@@ -27,6 +27,9 @@ pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "digests")
 CASES = sorted(f[:-5] for f in os.listdir(GOLD) if f.endswith(".json")) if os.path.isdir(GOLD) else []
 MODE_IDS = {"spdz2k": 0, "compact": 1}
+# configurations also run as one persistent launch (two parties, matrix-core
+# layers only, nothing compressed along M)
+PERSISTENT_CASES = ("batched", "transformer")
 _POOL = cf.ThreadPoolExecutor(max_workers=16)
 
 
@@ -108,6 +111,28 @@ def test_config_digests(case):
                 compare(digests(online_tensors(gl, mname, f, along_m)), l["online"][mname],
                         f"{case} {l['name']} {mname}")
                 check_records(r, l["cs"][mname], parties, f"{case} {l['name']} {mname} fused")
+            if case in PERSISTENT_CASES:
+                # the same step as one persistent launch, into cleared outputs
+                from paper_2311_04406_amd.binding import LAUNCH_PERSISTENT, LAUNCH_STAGED
+                for gl in layers:
+                    for n, t in online_tensors(gl, mname, f, False):
+                        t.zero_()
+                    gl["cvec"].zero_()
+                out.zero_()
+                ctx.set_launch(LAUNCH_PERSISTENT)
+                try:
+                    plan = ctx.plan(mode, layers, out)
+                finally:
+                    ctx.set_launch(LAUNCH_STAGED)
+                plan.launch()
+                torch.cuda.synchronize()
+                plan.close()
+                fused = Context.decode_results(out, len(layers), parties)
+                for gl, l, r in zip(layers, lays, fused):
+                    compare(digests(online_tensors(gl, mname, f, False)), l["online"][mname],
+                            f"{case} {l['name']} {mname} persistent")
+                    check_records(r, l["cs"][mname], parties, f"{case} {l['name']} {mname} persistent")
+                say(f"  {mname}: the persistent launch matches too")
             st, res = ctx.mac_check(mode, layers)
             assert st == 0, (case, mname, "standalone check rejected")
             for l, r in zip(lays, res):
