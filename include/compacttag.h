@@ -296,14 +296,24 @@ ct_status ct_set_overlap(ct_ctx *ctx, int enable);
  *     (N > CT_SKINNY_N) that are neither convolutions nor compressed along
  *     M; other calls, and the request server's batches, take the staged
  *     kernels.  The results are the same bit for bit.  A barrier wait is
- *     bounded (about 2 s); if one runs out, every layer's check record
- *     reports accept = 0 and reserved = 1.  The launch needs every
- *     workgroup resident at once: do not run other work on the device
- *     beside it.
+ *     bounded (ct_set_launch_wait, 2 s by default); if one runs out, every
+ *     layer's check record reports accept = 0 and reserved = 1.  The launch
+ *     needs every workgroup resident at once: do not run other work on the
+ *     device beside it.
  * Returns CT_EINVAL for another mode. */
 #define CT_LAUNCH_STAGED 0
 #define CT_LAUNCH_PERSISTENT 1
 ct_status ct_set_launch(ct_ctx *ctx, int mode);
+
+/* Bound of each grid-barrier wait of the persistent launch, in ticks of the
+ * device's 100 MHz wall clock (CT_LAUNCH_WAIT_DEFAULT: 2 s).  A wait that
+ * runs out sets the launch's run-out flag, every later wait of the launch
+ * ends at once, and every layer's check record reports accept = 0 and
+ * reserved = 1 (the outputs are then not to be used).  A tiny bound lets a
+ * caller exercise that report.  Applies to launches enqueued afterwards
+ * (a plan keeps the bound it was captured with). */
+#define CT_LAUNCH_WAIT_DEFAULT 200000000ull
+ct_status ct_set_launch_wait(ct_ctx *ctx, uint64_t ticks);
 
 typedef struct {
     char name[24];        /* kernel stage, e.g. "ring_gemm", "check_batch" */

@@ -93,6 +93,7 @@ class CtTuning(ctypes.Structure):
 TILE_AUTO, TILE_LDS_64x64, TILE_LDS_128x64, TILE_REGS_64x64, TILE_REGS_128x64, TILE_REGS_FIT = 0, 1, 2, 3, 4, 5
 # launch of the online phase (CT_LAUNCH_*)
 LAUNCH_STAGED, LAUNCH_PERSISTENT = 0, 1
+LAUNCH_WAIT_DEFAULT = 200000000  # 2 s of the device's 100 MHz wall clock
 TILE_NAMES = {0: "auto", 1: "lds_64x64", 2: "lds_128x64", 3: "regs_64x64", 4: "regs_128x64", 5: "regs_fit"}
 
 
@@ -159,6 +160,7 @@ def load() -> ctypes.CDLL:
     L.ct_set_timing.argtypes = [vp, i]
     L.ct_set_overlap.argtypes = [vp, i]
     L.ct_set_launch.argtypes = [vp, i]
+    L.ct_set_launch_wait.argtypes = [vp, ctypes.c_uint64]
     L.ct_stage_times.argtypes = [vp, ctypes.POINTER(CtStageTime), i, ctypes.POINTER(ctypes.c_int)]
     L.ct_autotune.argtypes = [vp, i, ctypes.POINTER(CtLayerDesc), ctypes.POINTER(CtLayerBufs), i, i,
                               ctypes.POINTER(CtTuning)]
@@ -182,7 +184,7 @@ def load() -> ctypes.CDLL:
     L.ct_last_error.argtypes = [vp]
     L.ct_last_error.restype = ctypes.c_char_p
     for f in ("ct_create", "ct_destroy", "ct_key_shares", "ct_gen_triple_tags", "ct_tag_linear",
-              "ct_mac_check_device", "ct_mac_check", "ct_tag_linear_check_static", "ct_set_timing", "ct_set_overlap", "ct_set_launch", "ct_stage_times", "ct_tag_linear_check",
+              "ct_mac_check_device", "ct_mac_check", "ct_tag_linear_check_static", "ct_set_timing", "ct_set_overlap", "ct_set_launch", "ct_set_launch_wait", "ct_stage_times", "ct_tag_linear_check",
               "ct_autotune", "ct_get_tuning", "ct_set_tuning", "ct_plan_create", "ct_plan_launch",
               "ct_plan_destroy", "ct_server_create", "ct_server_submit", "ct_server_poll", "ct_server_drain",
               "ct_server_layer", "ct_server_stats", "ct_server_destroy"):
@@ -418,6 +420,10 @@ class Context:
     def set_launch(self, mode: int):
         """LAUNCH_STAGED (one kernel per stage) or LAUNCH_PERSISTENT (one launch)."""
         self._check(self.lib.ct_set_launch(self.h, int(mode)))
+
+    def set_launch_wait(self, ticks: int = LAUNCH_WAIT_DEFAULT):
+        """Bound of the persistent launch's barrier waits (100 MHz ticks)."""
+        self._check(self.lib.ct_set_launch_wait(self.h, int(ticks)))
 
     def stage_times(self):
         """{stage: (total_ms, launches)} since the previous call (synchronizes)."""

@@ -926,6 +926,7 @@ ct_status enqueue_online(ct_ctx *c, Lane &ln, const OnlineLaunch &P) {
         a.probs = ln.gemm_dev;
         a.out = P.out_dev;
         a.sync = ln.sync_dev;
+        a.wait_ticks = c->launch_wait;
         a.n = n;
         a.flags = P.flags;
         a.zero_what = P.zero_what;
@@ -1198,6 +1199,12 @@ ct_status ct_set_launch(ct_ctx *c, int mode) {
     if (!c) return CT_EINVAL;
     if (mode != CT_LAUNCH_STAGED && mode != CT_LAUNCH_PERSISTENT) return fail(c, CT_EINVAL, "unknown launch mode");
     c->launch_mode = mode;
+    return CT_OK;
+}
+
+ct_status ct_set_launch_wait(ct_ctx *c, uint64_t ticks) {
+    if (!c) return CT_EINVAL;
+    c->launch_wait = ticks;
     return CT_OK;
 }
 

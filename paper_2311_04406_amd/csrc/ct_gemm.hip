@@ -808,9 +808,9 @@ __global__ __launch_bounds__(256, 1) void k_ring_gemm_rs(const GemmProb *__restr
 // at p * gridDim.x arrivals).  The release fence before the arrival and the
 // acquire fence after the wait make the workgroups' writes of the earlier
 // stages visible to the later ones on every XCD.  The wait is bounded: past
-// about 2 s (wall clock, 100 MHz) it sets sync[1] and goes on, and a
-// workgroup that sees sync[1] set stops waiting at once.
-__device__ __forceinline__ void grid_barrier(uint32_t *sync, uint32_t phase) {
+// `ticks` of the 100 MHz wall clock (2 s by default) it sets sync[1] and goes
+// on, and a workgroup that sees sync[1] set stops waiting at once.
+__device__ __forceinline__ void grid_barrier(uint32_t *sync, uint32_t phase, uint64_t ticks) {
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
@@ -819,7 +819,7 @@ __device__ __forceinline__ void grid_barrier(uint32_t *sync, uint32_t phase) {
         const uint64_t t0 = wall_clock64();
         while (__hip_atomic_load(sync, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (__hip_atomic_load(sync + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-            if (wall_clock64() - t0 > 200000000ull) {
+            if (wall_clock64() - t0 > ticks) {
                 atomicOr(sync + 1, 1u);
                 break;
             }
@@ -836,7 +836,7 @@ __global__ __launch_bounds__(256, 1) void k_online_persist(PersistArgs a) {
     uint32_t phase = 0;
     if (a.zero_what)
         for (int l = 0; l < a.n; l++) zero_acc_body<R>(a.Ls, a.zero_what, Grid{w, (uint32_t)l, W});
-    grid_barrier(a.sync, ++phase);
+    grid_barrier(a.sync, ++phase, a.wait_ticks);
     // the right operands' tiles of all layers as one list, dealt round-robin
     uint32_t first = 0;
     for (int l = 0; l < a.n; l++) {
@@ -845,13 +845,13 @@ __global__ __launch_bounds__(256, 1) void k_online_persist(PersistArgs a) {
         for (uint32_t t = (w + W - first % W) % W; t < tiles; t += W) open_pack_body<R>(a.Ls, a.flags, Grid{t, (uint32_t)l, tiles});
         first += tiles;
     }
-    grid_barrier(a.sync, ++phase);  // the row pass reads U^c and [tB^c]_p
+    grid_barrier(a.sync, ++phase, a.wait_ticks);  // the row pass reads U^c and [tB^c]_p
     for (int l = 0; l < a.n; l++) row_pass_layer<R, 0>(a.Ls, a.flags, Grid{w, (uint32_t)l, W});
-    grid_barrier(a.sync, ++phase);
+    grid_barrier(a.sync, ++phase, a.wait_ticks);
     pack_body<R>(a.jobs, a.njobs, a.pack_tiles, Grid{w, 0, W});
     if (a.any_accum)
         for (int p = 0; p < a.nprobs; p++) prob_base_body<R>(a.probs, Grid{w, (uint32_t)p, W});
-    grid_barrier(a.sync, ++phase);
+    grid_barrier(a.sync, ++phase, a.wait_ticks);
     // the product tiles are taken in list order as workgroups free up (tiles
     // differ in length), from one counter per XCD so that tile b still runs on
     // XCD b % 8 as in the staged kernel: counter x hands out b = 8 i + x (one
@@ -871,13 +871,13 @@ __global__ __launch_bounds__(256, 1) void k_online_persist(PersistArgs a) {
             gemm_tile_rs<R, MT>(P, tr.tm, tr.tn, tr.split);
         }
     }
-    grid_barrier(a.sync, ++phase);
+    grid_barrier(a.sync, ++phase, a.wait_ticks);
     for (int l = 0; l < a.n; l++) post_body<R>(a.Ls, a.flags, Grid{w, (uint32_t)l, W});
-    grid_barrier(a.sync, ++phase);
+    grid_barrier(a.sync, ++phase, a.wait_ticks);
     // four workgroups per layer, as the staged kernel
     if (a.flags & F_COMPACT)
         for (uint32_t v = w; v < 4u * (uint32_t)a.n; v += W) compact_final_body<R>(a.Ls, a.flags, Grid{v & 3, v >> 2, 4});
-    grid_barrier(a.sync, ++phase);
+    grid_barrier(a.sync, ++phase, a.wait_ticks);
     // one wavefront per layer; a run-out barrier rejects every layer
     const bool ran_out = __hip_atomic_load(a.sync + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
     const int lane = threadIdx.x & 63;

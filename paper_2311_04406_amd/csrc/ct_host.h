@@ -62,6 +62,7 @@ struct ct_ctx {
     hipEvent_t fork = nullptr, join = nullptr;
     bool overlap = true;  // mixed batches on two streams (ct_set_overlap)
     int launch_mode = CT_LAUNCH_STAGED;  // ct_set_launch
+    uint64_t launch_wait = CT_LAUNCH_WAIT_DEFAULT;  // ct_set_launch_wait
     std::string err;
     // per-launch timing: event pairs recorded around each kernel of the main lane
     bool timing = false;

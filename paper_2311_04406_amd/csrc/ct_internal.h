@@ -327,13 +327,15 @@ struct SkinnyProb {
 // (k_online_persist): the stages' tables as the staged kernels take them, and
 // the launch's counters, sync[0 .. 12), all 0 at the launch: sync[0] counts
 // workgroup arrivals at the grid barriers, sync[1] is set when a barrier wait
-// ran out (about 2 s), sync[4 + x] hands out the product tiles of XCD x.
+// ran out (after wait_ticks of the 100 MHz wall clock), sync[4 + x] hands
+// out the product tiles of XCD x.
 struct PersistArgs {
     const LayerDev *Ls;
     const PackJob *jobs;
     const GemmProb *probs;
     ct_check_result *out;
     uint32_t *sync;
+    uint64_t wait_ticks;
     int32_t n, flags, zero_what, njobs, pack_tiles, nprobs, total_tiles, xcd_remap, any_accum, mt;
 };
 

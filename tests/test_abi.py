@@ -140,6 +140,7 @@ def test_validation_before_device_calls(lib):
     assert lib.ct_server_destroy(None) == b.CT_EINVAL
     assert lib.ct_server_last_error(None) == b"null server"
     assert lib.ct_set_launch(None, b.LAUNCH_STAGED) == b.CT_EINVAL
+    assert lib.ct_set_launch_wait(None, b.LAUNCH_WAIT_DEFAULT) == b.CT_EINVAL
     assert lib.ct_set_overlap(None, 1) == b.CT_EINVAL
 
 

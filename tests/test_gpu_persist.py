@@ -219,6 +219,40 @@ def test_persistent_k32(mode, tile):
     free()
 
 
+def test_run_out_barrier_is_reported(ctx):
+    """A barrier bound of zero ticks, set from the host: the first waits run
+    out at once, every later one ends at once, every kernel finishes, and
+    every layer's check record reports the run-out (accept 0, reserved 1).
+    With the default bound the same context runs the batch correctly again."""
+    from paper_2311_04406_amd import Context
+    mode = O.MODE_COMPACT
+    say("[persist] run-out barrier")
+    specs = BATCH[:3]
+    layers = gpu_layers(ctx, specs)
+    out = torch.zeros(RESULT_WORDS * len(specs), dtype=torch.int64, device="cuda:0")
+    ctx.gen_triple_tags(layers)
+    try:
+        ctx.set_launch(LAUNCH_PERSISTENT)
+        ctx.set_launch_wait(0)
+        ctx.tag_linear_check(mode, layers, out)
+        torch.cuda.synchronize()
+        res = Context.decode_results(out, len(specs))
+        assert all(not r.accept and r.reserved == 1 for r in res), [(r.accept, r.reserved) for r in res]
+        ctx.set_launch_wait()
+        clear(layers, out)
+        ctx.tag_linear_check(mode, layers, out)
+        torch.cuda.synchronize()
+        res = Context.decode_results(out, len(specs))
+        assert all(r.accept and r.reserved == 0 for r in res)
+    finally:
+        ctx.set_launch(LAUNCH_STAGED)
+        ctx.set_launch_wait()
+    ol = oracle_run(mode, specs[0], KEY)
+    compare_layer(layers[0], ol, mode, what="after a run-out launch")
+    compare_cs(res[0], ol, what="after a run-out launch")
+    free()
+
+
 def test_set_launch_rejects_unknown_mode(ctx):
     from paper_2311_04406_amd import CtError
     with pytest.raises(CtError):
